@@ -1,0 +1,250 @@
+"""Pins of the CPU oracle against facts fixed outside it: hand-written code
+tables and bitstreams, dense brute force, closed forms, invariants, and the
+paper's own sequential algorithm.  All CPU-only."""
+import math
+
+import numpy as np
+import pytest
+
+import bvinputs as B
+from oracle import bvdecode, pagerank, product
+from tests.golden_io import pack_stream, read_codes, read_tiny_stream
+
+
+# ------------------------------------------------------------------ codes
+def test_codes_golden():
+    for kind, k, x, bits in read_codes():
+        data = np.frombuffer(int(bits + "0" * ((-len(bits)) % 8), 2).to_bytes((len(bits) + 7) // 8, "big"),
+                             dtype=np.uint8)
+        br = bvdecode.BitReader(data.tobytes(), len(bits))
+        got = {"unary": br.unary, "gamma": br.gamma, "zeta": lambda: br.zeta(k)}[kind]()
+        assert got == x, (kind, k, bits)
+        assert br.pos == len(bits), (kind, k, bits)
+
+
+def test_nu_inverse():
+    for z in range(-50, 51):
+        u = 2 * z if z >= 0 else 2 * (-z) - 1
+        assert bvdecode.nu_inv(u) == z
+
+
+# ------------------------------------------------------------- bitstream
+def test_tiny_stream_golden():
+    data, lists, refs = read_tiny_stream()
+    rowptr, col, got_refs, hdr = bvdecode.decode(data)
+    assert hdr["n"] == 6 and hdr["m"] == 16
+    for i, L in enumerate(lists):
+        assert col[int(rowptr[i]):int(rowptr[i + 1])].tolist() == L
+    assert got_refs.tolist() == refs
+
+
+def _roundtrip(g, **kw):
+    enc = B.encode(g, **kw)
+    rowptr, col, refs, hdr = bvdecode.decode(enc.data)
+    assert np.array_equal(rowptr, g.rowptr)
+    assert np.array_equal(col, g.col)
+    assert np.array_equal(refs, enc.refs)
+    assert hdr["m"] == g.m
+    return refs
+
+
+def test_roundtrip_web():
+    g = B.web_graph(3000, 15.0, 11)
+    refs = _roundtrip(g)
+    assert (refs > 0).mean() > 0.5          # the copying model is referenced heavily
+
+
+def test_roundtrip_social():
+    _roundtrip(B.social_graph(3000, 12.0, 400, 2.1, 12))
+
+
+@pytest.mark.parametrize("W,R,Lmin,zk", [(7, 3, 4, 3), (1, 1, 2, 1), (0, 0, 3, 2), (15, 15, 8, 5)])
+def test_roundtrip_params(W, R, Lmin, zk):
+    _roundtrip(B.web_graph(1500, 12.0, 5), W=W, R=R, Lmin=Lmin, zeta_k=zk, stride=0 if W * R == 0 else W * R + 1)
+
+
+def test_roundtrip_crafted():
+    n = 200
+    lists = [[] for _ in range(n)]
+    lists[1] = list(range(0, 10))                 # interval touching 0
+    lists[2] = list(range(0, 10))                 # identical to its reference
+    lists[3] = [150]                              # reference fully skipped
+    lists[4] = [3, 4, 150, 199]                   # self-loop at 4, id n-1
+    lists[5] = list(range(190, 200))              # interval touching n-1
+    lists[6] = list(range(0, 200, 2))             # long strided row
+    lists[7] = list(range(0, 200))                # complete row incl. self
+    for i in range(8, 40):                        # a deep chain of near-identical rows
+        lists[i] = sorted(set(lists[i - 1] if i > 8 else range(20, 60)) ^ {60 + i, 20 + (i % 7)})
+    g = B.from_lists(lists)
+    for W, R in [(7, 3), (3, 1), (7, 15)]:
+        _roundtrip(g, W=W, R=R, stride=W * R + 1)
+
+
+def test_roundtrip_long_row():
+    n = 60000
+    rng = np.random.default_rng(3)
+    lists = [[] for _ in range(n)]
+    lists[10] = sorted(rng.choice(n, 50000, replace=False).tolist())
+    lists[11] = sorted(set(lists[10][:40000]) | {5, 6, 7, 8})
+    g = B.from_lists(lists)
+    _roundtrip(g)
+
+
+def test_corrupt_streams():
+    g = B.web_graph(500, 10.0, 7)
+    data = B.encode(g).data
+    bad = data.copy(); bad[0] = ord("X")
+    with pytest.raises(bvdecode.FormatError):
+        bvdecode.decode(bad)
+    with pytest.raises(bvdecode.FormatError):
+        bvdecode.decode(data[: len(data) // 2])
+    bad = data.copy(); bad[16] ^= 1               # edge count in the header
+    with pytest.raises(bvdecode.FormatError):
+        bvdecode.decode(bad)
+    # a reference outside the window: node 1 claiming g=2
+    bits = "010" + "1" + "110" + "010" + "001"   # node0 [..]; node1 d=1 g=2
+    with pytest.raises(bvdecode.FormatError):
+        bvdecode.decode(pack_stream(2, 2, 7, 3, 4, 3, bits))
+
+
+# --------------------------------------------------------------- product
+def _csr(g):
+    return g.rowptr, g.col
+
+
+def test_product_dense_bruteforce():
+    for seed in range(3):
+        g = B.web_graph(800, 12.0, 100 + seed)
+        x = B.uniform_x(g.n, seed)
+        y = product.matvec_exact(*_csr(g), x)
+        yd = product.matvec_dense(*_csr(g), x)
+        assert np.allclose(y, yd, rtol=1e-14, atol=0)
+        assert np.allclose(product.matvec(*_csr(g), x), y, rtol=1e-14, atol=0)
+
+
+def test_product_closed_forms():
+    n = 37
+    x = B.uniform_x(n, 9)
+    y = product.matvec_exact(*_csr(B.complete_graph(n)), x)
+    assert np.allclose(y, x.sum() - x, rtol=1e-14)
+    y = product.matvec_exact(*_csr(B.path_graph(n)), x)
+    assert np.array_equal(y[:-1], x[1:]) and y[-1] == 0.0
+    y = product.matvec_exact(*_csr(B.star_graph(n, 3, "out")), x)
+    assert math.isclose(y[3], x.sum() - x[3], rel_tol=1e-14) and np.all(np.delete(y, 3) == 0)
+    y = product.matvec_exact(*_csr(B.star_graph(n, 3, "in")), x)
+    assert y[3] == 0 and np.all(np.delete(y, 3) == x[3])
+
+
+def test_product_indicator_and_ones():
+    g = B.web_graph(2000, 15.0, 21)
+    deg = np.diff(g.rowptr).astype(np.float64)
+    assert np.array_equal(product.matvec(*_csr(g), np.ones(g.n)), deg)
+    for j in (0, 777, g.n - 1):
+        e = np.zeros(g.n); e[j] = 1.0
+        colj = np.zeros(g.n)
+        for i in range(g.n):
+            if j in set(g.row(i).tolist()):
+                colj[i] = 1.0
+        assert np.array_equal(product.matvec(*_csr(g), e), colj)
+
+
+def test_product_integer_exact_and_invariants():
+    g = B.web_graph(3000, 15.0, 22)
+    x = B.integer_x(g.n, 5, 1000)
+    y = product.matvec(*_csr(g), x)
+    assert np.array_equal(y, product.matvec_exact(*_csr(g), x))
+    indeg = np.bincount(g.col, minlength=g.n).astype(np.float64)
+    assert y.sum() == float(np.dot(indeg, x))
+    x2 = B.integer_x(g.n, 6, 1000)
+    assert np.array_equal(product.matvec(*_csr(g), x + x2), y + product.matvec(*_csr(g), x2))
+
+
+def test_proposition_reuse_equals_plain():
+    """A x = A' x + w, computed by the paper's sequential algorithm."""
+    g = B.web_graph(3000, 15.0, 23)
+    enc = B.encode(g)
+    r, plus, minus, m_prime = product.difference_form(g.rowptr, g.col, enc.refs)
+    assert m_prime < g.m                           # the copying model compresses
+    xi = B.integer_x(g.n, 1, 1000)
+    assert np.array_equal(product.reuse_product(r, plus, minus, xi), product.matvec(*_csr(g), xi))
+    x = B.uniform_x(g.n, 2)
+    y0 = product.matvec_exact(*_csr(g), x)
+    y1 = product.reuse_product(r, plus, minus, x)
+    assert np.max(np.abs(y1 - y0) / np.maximum(np.abs(y0), 1e-300)) < 1e-12
+
+
+def test_difference_form_rule():
+    """Rows whose difference is not smaller than themselves keep v_i."""
+    g = B.from_lists([[1, 2, 3, 4], [9], [1, 2, 3, 5]])
+    r, plus, minus, mp = product.difference_form(g.rowptr, g.col, np.array([0, 1, 2], dtype=np.uint8))
+    assert r.tolist() == [-1, -1, 0]              # row 1 vs row 0: |diff| = 5 >= 1 -> keep
+    assert plus[2] == [5] and minus[2] == [4] and mp == 4 + 1 + 2
+
+
+# -------------------------------------------------------------- pagerank
+def _in_links(g):
+    return g.transpose()
+
+
+def _dense(g):
+    A = np.zeros((g.n, g.n))
+    for i in range(g.n):
+        A[i, g.row(i)] = 1.0
+    return A
+
+
+@pytest.mark.parametrize("seed", [0, 1, 2])
+def test_pagerank_dense_solve(seed):
+    rng = np.random.default_rng(seed)
+    n = 60
+    lists = [sorted(set(rng.choice(n, rng.integers(0, 6), replace=False).tolist()) - {i}) for i in range(n)]
+    lists[5] = []                                  # make sure dangling nodes exist
+    g = B.from_lists(lists)
+    bt = _in_links(g)
+    for tele in (None, rng.dirichlet(np.ones(n))):
+        pstar = pagerank.pagerank_dense(_dense(g), 0.85, tele)
+        p, t, r, ok = pagerank.pagerank(bt.rowptr, bt.col, 0.85, iters=300, teleport=tele)
+        assert np.max(np.abs(p - pstar)) < 1e-13
+        p, t, r, ok = pagerank.pagerank(bt.rowptr, bt.col, 0.85, tol=1e-6, teleport=tele)
+        assert ok and r < 1e-6
+        assert np.abs(p - pstar).sum() <= 0.85 / 0.15 * r * (1 + 1e-9)
+
+
+def test_pagerank_closed_forms():
+    beta = 0.85
+    for n in (2, 5, 17):
+        for g in (B.complete_graph(n), B.cycle_graph(n)):
+            bt = _in_links(g)
+            p = pagerank.pagerank(bt.rowptr, bt.col, beta, iters=400)[0]
+            assert np.allclose(p, 1.0 / n, rtol=0, atol=1e-14)
+        c = 0
+        cases = {
+            "both": ((1 - beta) / n + beta) / (1 + beta),
+            "in": (1 + (n - 1) * beta) / (n + (n - 1) * beta),
+            "out": 1.0 / (n + beta),
+        }
+        for kind, pc in cases.items():
+            g = B.star_graph(n, c, kind)
+            bt = _in_links(g)
+            p = pagerank.pagerank(bt.rowptr, bt.col, beta, iters=400)[0]
+            assert abs(p[c] - pc) < 1e-13, kind
+            assert np.allclose(np.delete(p, c), (1 - pc) / (n - 1), atol=1e-13)
+            assert abs(pagerank.pagerank_dense(_dense(g), beta)[c] - pc) < 1e-13
+
+
+def test_pagerank_degenerate():
+    g = B.empty_graph(10)
+    bt = _in_links(g)
+    p, t, r, ok = pagerank.pagerank(bt.rowptr, bt.col, 0.85)
+    assert ok and t == 1 and np.allclose(p, 0.1, atol=1e-16)
+    h = B.web_graph(300, 8.0, 3).transpose()
+    v = np.random.default_rng(0).dirichlet(np.ones(300))
+    p, t, r, ok = pagerank.pagerank(h.rowptr, h.col, 0.0, teleport=v)
+    assert np.allclose(p, v, atol=1e-16)
+
+
+def test_pagerank_mass_conserved():
+    g = B.web_graph(2000, 10.0, 8).transpose()
+    for it in (1, 5, 30):
+        p = pagerank.pagerank(g.rowptr, g.col, 0.85, iters=it)[0]
+        assert abs(p.sum() - 1.0) < 1e-12
