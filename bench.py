@@ -1,0 +1,189 @@
+#!/usr/bin/env python3
+"""Benchmark: uncompressed edges/s of the compressed product y = A x on a
+web-like graph (n = 2^20, mean out-degree 20), against the same-GPU CSR
+product, plus PageRank seconds to L1 residual 1e-6 (compressed vs CSR).
+
+One step = one compressed product over the whole graph (FP32 vectors,
+two-sum compensated accumulation), inputs resident in HBM.  Prints one JSON
+line.  Single GPU only."""
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK_HBM_GBS = 8000.0
+KERNEL_SOURCES = ["paper_1708_07271_amd/csrc/bv_kernels.hip", "paper_1708_07271_amd/csrc/bv_layout.cpp"]
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def kernel_hash():
+    h = hashlib.sha256()
+    for p in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, p), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def load_traffic(kernel, workload):
+    """HBM bytes per launch from committed rocprofv3 counter runs, if they were
+    taken on the current kernel source; else None."""
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    try:
+        with open(path) as f:
+            d = json.load(f)
+        e = d.get("%s|%s" % (kernel, workload))
+        if e and e.get("kernel_hash") == kernel_hash():
+            return e.get("bytes_per_launch")
+    except (OSError, ValueError):
+        pass
+    return None
+
+
+def time_launches(fn, steps, warmup, torch):
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    s = torch.cuda.current_stream()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(s)
+    for _ in range(steps):
+        fn()
+    e1.record(s)
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / steps   # ms per launch
+
+
+def cpu_baseline(g, x64, budget_s):
+    """The oracle's product (numpy, float64) timed on the host."""
+    from oracle import product
+    reps, t0 = 0, time.perf_counter()
+    while True:
+        product.matvec(g.rowptr, g.col, x64)
+        reps += 1
+        el = time.perf_counter() - t0
+        if el >= budget_s:
+            break
+    return {"value": reps * g.m / el, "unit": "edges/s", "cores": 1, "kind": "oracle",
+            "sample": "%d full products of the %d-edge graph (oracle.product.matvec, numpy float64, one thread)"
+                      % (reps, g.m)}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=500)
+    ap.add_argument("--warmup", type=int, default=50)
+    ap.add_argument("--workload", default="web-n2p20-d20")
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU-baseline leg")
+    ap.add_argument("--no-pagerank", action="store_true")
+    ap.add_argument("--cpu-seconds", type=float, default=10.0)
+    ap.add_argument("--only", choices=["bv", "csr", "all"], default="all",
+                    help="restrict the timed kernels (profiling runs)")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py runs on one GPU only: the compressed product and PageRank here are single-GPU "
+              "kernels (see DESIGN.md for how the path would shard)", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import bvinputs as B
+    import paper_1708_07271_amd as P
+
+    assert torch.cuda.is_available(), "bench.py needs a HIP device"
+    dev = torch.device("cuda:0")
+    t0 = time.perf_counter()
+    g = B.workload_graph(args.workload)
+    enc = B.encode(g)
+    log("graph n=%d m=%d bitstream %.1f MB (%.2f bits/edge) in %.1fs" % (
+        g.n, g.m, enc.data.size / 1e6, enc.data.size * 8 / g.m, time.perf_counter() - t0))
+    G = P.bvmv_load(enc.data, keep_lists=1)
+    info = G.info()
+    C = P.bvmv_csr_create(G)
+    log("layout %.1f MB, units %d, m' %d, escapes %d, long rows %d; csr %.1f MB" % (
+        info["layout_bytes"] / 1e6, info["units"], info["m_prime"], info["escapes"], info["long_rows"],
+        C.bytes() / 1e6))
+    x32 = B.uniform_x(g.n, 102, np.float32)
+    x = torch.from_numpy(x32).to(dev)
+    y = torch.empty_like(x)
+    y2 = torch.empty_like(x)
+    prec = P.BVMV_F32_COMP
+
+    ms_bv = ms_csr = None
+    if args.only in ("bv", "all"):
+        ms_bv = time_launches(lambda: P.bvmv_multiply(G, x, y, prec), args.steps, args.warmup, torch)
+        log("compressed product: %.4f ms" % ms_bv)
+    if args.only in ("csr", "all"):
+        ms_csr = time_launches(lambda: P.bvmv_csr_multiply(C, x, y2, prec), args.steps, args.warmup, torch)
+        log("csr product: %.4f ms" % ms_csr)
+    if ms_bv is None:
+        ms_bv = ms_csr
+
+    pr = None
+    if not args.no_pagerank and args.only == "all":
+        p = torch.empty(g.n, dtype=torch.float32, device=dev)
+        P.bvmv_pagerank(G, p, prec=prec)          # warm (graph capture)
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        (it, ok, r), = P.bvmv_pagerank(G, p, prec=prec)
+        torch.cuda.synchronize()
+        pr_s = time.perf_counter() - t
+        P.bvmv_csr_pagerank(C, p, prec=prec)
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        it_c, ok_c, r_c = P.bvmv_csr_pagerank(C, p, prec=prec)
+        torch.cuda.synchronize()
+        pr_csr_s = time.perf_counter() - t
+        pr = {"seconds_to_1e-6": pr_s, "iterations": it, "converged": ok, "residual": r,
+              "csr_seconds_to_1e-6": pr_csr_s, "csr_iterations": it_c, "speedup_vs_csr": pr_csr_s / pr_s}
+        log("pagerank: %.4f s (%d it) vs csr %.4f s (%d it)" % (pr_s, it, pr_csr_s, it_c))
+
+    alg_bytes = info["layout_bytes"] + 4 * g.n + 4 * g.n     # layout + read x once + write y once
+    achieved = alg_bytes / (ms_bv * 1e-3) / 1e9
+    csr_bytes = C.bytes() + 8 * g.n
+    result = {
+        "metric": "uncompressed edges/s: compressed A·x vs CSR SpMV; PageRank s to L1 1e-6",
+        "value": g.m / (ms_bv * 1e-3),
+        "unit": "edges/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_bv,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": args.workload, "n": g.n, "m": g.m, "precision": "f32 two-sum compensated",
+                   "x": "uniform[0,1) float32, seed 102"},
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                     "frac": achieved / PEAK_HBM_GBS, "traffic": load_traffic("bv_tile_kernel", args.workload),
+                     "kernel": "bv_tile_kernel", "alg_bytes_per_launch": alg_bytes},
+        "layout": {"bytes": info["layout_bytes"], "bytes_per_edge": info["layout_bytes"] / g.m,
+                   "m_prime": info["m_prime"], "m_over_m_prime": g.m / max(info["m_prime"], 1),
+                   "units": info["units"], "escapes": info["escapes"], "long_rows": info["long_rows"],
+                   "bitstream_bits_per_edge": enc.data.size * 8 / g.m},
+    }
+    if ms_csr is not None:
+        result["csr"] = {"edges_per_s": g.m / (ms_csr * 1e-3), "ms": ms_csr, "bytes": csr_bytes,
+                         "achieved_GBs": csr_bytes / (ms_csr * 1e-3) / 1e9,
+                         "speedup_compressed_vs_csr": ms_csr / ms_bv}
+    if pr is not None:
+        result["pagerank"] = pr
+    if not args.no_cpu:
+        result["cpu_baseline"] = cpu_baseline(g, x32.astype(np.float64), args.cpu_seconds)
+    print(json.dumps(result), flush=True)
+
+
+if __name__ == "__main__":
+    main()

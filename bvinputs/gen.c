@@ -22,12 +22,14 @@
  * numbers, Section "Our Approach").  Little-endian 64-byte header:
  *   0 "BVMV" | 4 u32 version=1 | 8 u64 n | 16 u64 m | 24 u32 W | 28 u32 R
  *   32 u32 Lmin | 36 u32 zeta_k | 40 u32 stride S | 44 u32 0 | 48 u64 body_bits
- *   56 u64 nseg ; then nseg u64 bit offsets (offset of node max(0,k*S - W*R));
+ *   56 u64 nseg ; then nseg u64 bit offsets (offset of node k*S);
  *   then the body, MSB-first bit order, zero padded to a multiple of 8 bytes.
  * Per node i (codes: unary(x)= x zeros then a one; gamma(x) on x+1; zeta_k(x)
  * on x+1; nu(z)= 2z for z>=0, 2|z|-1 for z<0):
  *   gamma(d_i); if d_i==0 done.
- *   if W>0: unary(g), g = i - r_i in [0,W], 0 = no reference.
+ *   if W>0: unary(g), g = i - r_i in [0,W], 0 = no reference.  With a segment
+ *     table (S > 0) a reference never crosses a multiple of S, so each
+ *     segment of S nodes decodes on its own.
  *   if g>0: gamma(b) explicit blocks over the reference's list; block 0 (copy)
  *     gamma(len), later blocks gamma(len-1), alternating copy/skip; the rest of
  *     the reference list is copied if b is even, skipped if b is odd.
@@ -448,7 +450,7 @@ static uint64_t row_code(bitw_t *bw, const encp_t *P, int64_t i, const uint32_t 
 typedef struct {
   const encp_t *P; int64_t n; const uint64_t *rp; const uint32_t *col;
   int64_t lo, hi; uint64_t *cost; /* cost[(i)*(W+1)+g], UINT64_MAX if invalid */
-  const uint8_t *gsel; bitw_t bw; int phase;
+  const uint8_t *gsel; bitw_t bw; int phase; int64_t stride;
 } enc_job_t;
 
 static void *enc_worker(void *arg) {
@@ -464,7 +466,7 @@ static void *enc_worker(void *arg) {
       for (int g = 0; g <= P->W; ++g) {
         uint64_t c = UINT64_MAX;
         if (g == 0) c = row_code(NULL, P, i, Li, di, NULL, 0, 0, scratch);
-        else if (g <= i && di > 0) {
+        else if (g <= i && di > 0 && (J->stride == 0 || (i - g) / J->stride == i / J->stride)) {
           int64_t r = i - g; int64_t dr = (int64_t)(J->rp[r + 1] - J->rp[r]);
           if (dr > 0) c = row_code(NULL, P, i, Li, di, J->col + J->rp[r], dr, g, scratch);
         }
@@ -485,7 +487,7 @@ static void *enc_worker(void *arg) {
 int bvi_encode(int64_t n, const uint64_t *rowptr, const uint32_t *col, int W, int R, int Lmin, int zk,
                int64_t stride, int nthreads, uint8_t **out, int64_t *nbytes_out, uint8_t *gsel_out) {
   if (n <= 0 || W < 0 || W > 15 || R < 0 || R > 15 || Lmin < 2 || zk < 1 || zk > 8 || nthreads < 1) return -1;
-  if (stride != 0 && stride < (int64_t)W * R + 1) return -1;
+  if (stride < 0 || stride > 0xFFFFFFFFll) return -1;
   for (int64_t i = 0; i < n; ++i) {
     if (rowptr[i + 1] < rowptr[i]) return -1;
     for (uint64_t k = rowptr[i]; k < rowptr[i + 1]; ++k) {
@@ -508,7 +510,7 @@ int bvi_encode(int64_t n, const uint64_t *rowptr, const uint32_t *col, int W, in
       memset(&jobs[t], 0, sizeof(enc_job_t));
       jobs[t].P = &P; jobs[t].n = n; jobs[t].rp = rowptr; jobs[t].col = col;
       jobs[t].lo = n * t / nthreads; jobs[t].hi = n * (t + 1) / nthreads;
-      jobs[t].cost = cost; jobs[t].gsel = gsel; jobs[t].phase = phase;
+      jobs[t].cost = cost; jobs[t].gsel = gsel; jobs[t].phase = phase; jobs[t].stride = stride;
       pthread_create(&th[t], NULL, enc_worker, &jobs[t]);
     }
     for (int t = 0; t < nthreads; ++t) pthread_join(th[t], NULL);
@@ -548,14 +550,11 @@ int bvi_encode(int64_t n, const uint64_t *rowptr, const uint32_t *col, int W, in
   u32 = (uint32_t)stride; memcpy(buf + 40, &u32, 4);
   memcpy(buf + 48, &body_bits, 8);
   memcpy(buf + 56, &nseg, 8);
-  /* bit offsets of segment warm-up starts */
+  /* bit offsets of the segment starts k*S */
   {
-    uint64_t off = 0; int64_t k = 0;
-    for (int64_t i = 0; i < n && k < nseg; ++i) {
-      while (k < nseg) {
-        int64_t st = k * stride - (int64_t)W * R; if (st < 0) st = 0;
-        if (st == i) { memcpy(buf + 64 + 8 * k, &off, 8); ++k; } else break;
-      }
+    uint64_t off = 0;
+    for (int64_t i = 0; i < n; ++i) {
+      if (stride && i % stride == 0) memcpy(buf + 64 + 8 * (i / stride), &off, 8);
       off += rowbits[i];
     }
   }

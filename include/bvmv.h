@@ -1,0 +1,201 @@
+/*
+ * bvmv: binary adjacency-matrix x vector products computed directly on a
+ * Boldi-Vigna-style compressed graph, and the PageRank power method driven by
+ * them, on AMD Instinct MI355X (gfx950).
+ *
+ * The operation (Francisco, Gagie, Ladra, Navarro, "Exploiting
+ * Computation-Friendly Graph Compression Methods for Adjacency-Matrix
+ * Multiplication", arXiv 1708.07271):
+ *   - A is the n x n binary adjacency matrix, row i = the list L_i of node i;
+ *     y = A x^T, y_i = sum_{j in L_i} x_j (Section "Introduction").
+ *   - Row i is stored against a reference row r_i < i within a window W
+ *     (Section "Our Approach"); with A' = rows v_i - v_{r_i} and
+ *     w_i = v_{r_i} . x^T, A x^T = A' x^T + w^T (the Proposition), so
+ *     y_i = y_{r_i} + sum_j A'_ij x_j reuses the reference row's sum.
+ *   - PageRank: p_t = a p_0 + (1 - a) p_{t-1} M, M = D^{-1} A (Section
+ *     "PageRank", Eq. (1)); the left product is taken as a right product with
+ *     the transposed matrix (Section "Experimental Evaluation").
+ *
+ * Conventions for every entry point:
+ *   - Vectors passed as `const void*` / `void*` are DEVICE pointers owned by
+ *     the caller, of the element type the precision selects (double for
+ *     BVMV_F64, float otherwise), contiguous unless a leading dimension is
+ *     given.  Multi-vector arguments are node-major: element (v, c) of an
+ *     n x k block lives at v * ld + c.
+ *   - `stream` is a hipStream_t (NULL = the null stream).  Calls enqueue work
+ *     on it and return without synchronising, except where stated.
+ *   - Return value: a bvmv_status.  On a negative status the outputs are
+ *     unspecified and bvmv_last_error() returns a message (thread-local).
+ *     No exception crosses this interface.
+ *   - The library owns every handle it returns until the matching free call.
+ */
+#ifndef BVMV_H
+#define BVMV_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct bvmv_graph bvmv_graph;
+typedef struct bvmv_csr bvmv_csr;
+
+typedef enum {
+  BVMV_OK = 0,
+  BVMV_NOT_CONVERGED = 1,   /* PageRank hit max_iter; outputs are still written */
+  BVMV_EINVAL = -1,         /* bad argument (null pointer, size, option out of range) */
+  BVMV_EFORMAT = -2,        /* malformed or truncated bitstream */
+  BVMV_ENOMEM = -3,         /* host or device allocation failed, or over the memory budget */
+  BVMV_EDEVICE = -4         /* HIP runtime error */
+} bvmv_status;
+
+typedef enum {
+  BVMV_F64 = 0,       /* double vectors, double accumulation */
+  BVMV_F32 = 1,       /* float vectors, float accumulation along reuse chains */
+  BVMV_F32_COMP = 2   /* float vectors, two-sum compensated (hi, lo) accumulation */
+} bvmv_prec;
+
+/* Layout and tuning options of bvmv_load.  Zero fields take defaults. */
+typedef struct {
+  int device;            /* HIP device ordinal */
+  int tile_rows;         /* rows per tile: 128, 256 or 512 (0 = default 256) */
+  int window_cap;        /* max x-window columns staged per tile: 256..8192 (0 = 2048) */
+  int long_row_words;    /* rows coded in more words than this are processed by a whole block (0 = 192) */
+  int interval_mode;     /* 0 = interval sums from a per-tile prefix of x; 1 = direct sums */
+  int autotune;          /* 1 = time candidate layouts at load and keep the fastest */
+  int keep_lists;        /* 1 = keep the decoded lists on the host (export, CSR baseline) */
+  int nthreads;          /* host decode / layout threads (0 = hardware concurrency, max 16) */
+  uint64_t device_mem_budget;  /* bytes; 0 = unlimited.  Layout larger than this -> BVMV_ENOMEM */
+} bvmv_load_opts;
+
+/* Decode a bitstream and build the device layout.
+ * bitstream: HOST pointer to nbytes bytes in the project's BV-style format
+ *   (list referencing within a window, copy/skip blocks, intervals,
+ *   gap-coded residuals; Section "Our Approach").  Copied; the caller may
+ *   free it on return.
+ * opts: may be NULL (defaults).  out: receives the handle.
+ * Errors: BVMV_EFORMAT for a malformed stream, BVMV_EINVAL for bad options,
+ *   BVMV_ENOMEM, BVMV_EDEVICE.  Synchronous. */
+int bvmv_load(const void* bitstream, size_t nbytes, const bvmv_load_opts* opts, bvmv_graph** out);
+
+/* y = A x (Section "Our Approach": y_i = y_{r_i} + sum_j A'_ij x_j, plus
+ * interval sums and residual entries).  x, y: device vectors of n elements
+ * (double for BVMV_F64, float otherwise); x and y must not overlap.
+ * Deterministic: the same inputs give bit-identical y. */
+int bvmv_multiply(bvmv_graph* g, const void* x, void* y, int prec, void* stream);
+
+/* Y = A X for k right-hand sides at once (one pass over the layout serves all
+ * k products).  X, Y: node-major n x k blocks with leading dimension ld >= k
+ * (elements).  1 <= k <= 64.  prec: BVMV_F32 or BVMV_F32_COMP (float) or
+ * BVMV_F64 (double). */
+int bvmv_multiply_batch(bvmv_graph* g, const void* X, void* Y, int k, int64_t ld, int prec, void* stream);
+
+/* PageRank options.  damping = beta, the weight of following links (the
+ * paper's teleport probability a is 1 - beta).  Iteration stops at the first
+ * t with ||p_t - p_{t-1}||_1 < tol (accumulated in double), or at max_iter. */
+typedef struct {
+  double damping;   /* 0 <= damping < 1 (0 = default 0.85 unless exact_zero_damping) */
+  double tol;       /* > 0 (0 = default 1e-6) */
+  int max_iter;     /* > 0 (0 = default 1000) */
+  int prec;         /* BVMV_F32_COMP (default), BVMV_F32 or BVMV_F64 */
+  int chunk;        /* iterations per captured HIP graph replay (0 = default 16) */
+  int exact_zero_damping;  /* 1 = use damping exactly as given, even 0 */
+} bvmv_pr_opts;
+
+typedef struct {
+  int iters;          /* iterations run (the t at which the stopping test held) */
+  int converged;      /* 1 if residual < tol */
+  double residual;    /* ||p_t - p_{t-1}||_1 of the last iteration */
+} bvmv_pr_result;
+
+/* PageRank by the power method, Eq. (1), on the loaded rows read as IN-LINK
+ * lists: row v lists every u with an edge u -> v (the transposed matrix, as
+ * the paper does), so the out-degree d_u is the number of rows listing u.
+ * Per iteration: delta = sum of p_u over d_u = 0 (double); z_u = p_u / d_u;
+ * y = B z (the compressed product); p'_v = (1-beta) v_v + beta (y_v + delta v_v);
+ * residual = ||p' - p||_1 (double).  Dangling mass goes to the teleport vector.
+ * teleport: device n x k node-major (ld = k) of the prec's element type, each
+ *   column a probability vector; NULL = uniform 1/n (k must then be 1, or the
+ *   graph a group: each member graph gets its own uniform vector).
+ * start: device n x k start vectors; NULL = the teleport vector.
+ * p_out: device n x k result.  res: HOST array of k results (for a group:
+ *   one per member graph).  k = number of personalized right-hand sides.
+ * Synchronises `stream` once per replayed chunk to read the residuals.
+ * Returns BVMV_NOT_CONVERGED (with outputs written) if some column did not
+ * converge within max_iter. */
+int bvmv_pagerank(bvmv_graph* g, const bvmv_pr_opts* opts, const void* teleport, const void* start,
+                  void* p_out, int k, bvmv_pr_result* res, void* stream);
+
+/* Ragged batch: the block-diagonal union of `count` loaded graphs as one
+ * handle.  Member i occupies rows/columns [offsets[i], offsets[i+1]).
+ * bvmv_multiply on a group multiplies every member at once; bvmv_pagerank
+ * runs every member's PageRank (own uniform teleport, own stopping test) in
+ * one launch sequence.  The members stay valid and owned by the caller. */
+int bvmv_group(bvmv_graph* const* graphs, int count, bvmv_graph** out);
+/* offsets: HOST array of count+1 row offsets of a group's members. */
+int bvmv_group_offsets(const bvmv_graph* group, int64_t* offsets, int* count);
+
+typedef struct {
+  int64_t n, m;             /* nodes, edges (nonzeros of A) */
+  int64_t m_prime;          /* nonzeros of A' with the paper's fallback rule (keep v_i when
+                               |v_i - v_{r_i}| >= |v_i|) and the stream's references */
+  int64_t units;            /* work units of the device layout: entries + 1 per reused row */
+  int64_t diff_rows, direct_rows, long_rows;
+  int64_t escapes;          /* entries outside their tile's x window */
+  int64_t ntiles;
+  int64_t layout_bytes;     /* device bytes of the layout (tiles + row info + words + long entries) */
+  int64_t stream_bytes;     /* size of the input bitstream */
+  int W, R, Lmin, zeta_k;
+  int tile_rows, window_cap, long_row_words, interval_mode;
+  int max_level;            /* deepest reuse level in the layout (<= R) */
+  int ngraphs;              /* 1, or the member count of a group */
+} bvmv_info;
+int bvmv_get_info(const bvmv_graph* g, bvmv_info* out);
+
+/* Decoded lists of a graph loaded with keep_lists = 1, into HOST buffers:
+ * rowptr[n+1] (uint64), col[m] (uint32, each row strictly increasing). */
+int bvmv_export_csr(const bvmv_graph* g, uint64_t* rowptr, uint32_t* col);
+
+/* deg = A 1 by integer reuse on the device (deg_i = deg_{r_i} - skipped +
+ * added entries).  deg: device int32[n]. */
+int bvmv_degrees(bvmv_graph* g, int32_t* deg, void* stream);
+
+/* Host-only decode (no device needed).  Call with rowptr = col = refs = NULL
+ * to get n and m, then again with buffers of n+1, m and n elements.
+ * refs[i] = i - r_i (0 = no reference). */
+int bvmv_decode(const void* bitstream, size_t nbytes, int nthreads, uint64_t* rowptr, uint32_t* col,
+                uint8_t* refs, int64_t* n, int64_t* m);
+
+/* Plain CSR baseline built the same way (row tiles, LDS-staged column ids,
+ * whole-block long rows).  From a graph loaded with keep_lists = 1, or from
+ * host CSR arrays. */
+int bvmv_csr_create(const bvmv_graph* g, bvmv_csr** out);
+int bvmv_csr_create_host(int64_t n, const uint64_t* rowptr, const uint32_t* col, int device, bvmv_csr** out);
+int bvmv_csr_multiply(bvmv_csr* c, const void* x, void* y, int prec, void* stream);
+/* PageRank with the CSR product, same semantics as bvmv_pagerank, k = 1. */
+int bvmv_csr_pagerank(bvmv_csr* c, const bvmv_pr_opts* opts, const void* teleport, const void* start,
+                      void* p_out, bvmv_pr_result* res, void* stream);
+int64_t bvmv_csr_bytes(const bvmv_csr* c);
+void bvmv_csr_free(bvmv_csr* c);
+
+/* Host interpretation of the device layout that bvmv_load would build from
+ * this bitstream and options, in double precision: y = A x with x and y HOST
+ * arrays of n doubles.  A test aid for the layout builder (no device
+ * needed); no other entry point uses it.  stats (may be NULL) receives 9
+ * values: tiles, units, differential rows, direct rows, long rows, escapes,
+ * layout bytes, m', deepest level.  BVMV_EINVAL if the layout is
+ * inconsistent. */
+int bvmv_layout_selfcheck(const void* bitstream, size_t nbytes, const bvmv_load_opts* opts, const double* x,
+                          double* y, int64_t* stats);
+
+void bvmv_free(bvmv_graph* g);
+const char* bvmv_last_error(void);
+/* Library version string. */
+const char* bvmv_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* BVMV_H */

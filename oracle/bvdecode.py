@@ -14,7 +14,8 @@ Boldi-Vigna zeta_k.  Field order and header are this project's own.
 
 Header (little endian, 64 bytes): "BVMV", u32 version, u64 n, u64 m, u32 W,
 u32 R, u32 Lmin, u32 zeta_k, u32 stride, u32 0, u64 body_bits, u64 nseg; then
-nseg u64 segment bit offsets; then the MSB-first body.
+nseg u64 bit offsets of nodes 0, S, 2S, ... (S = stride); then the MSB-first
+body.  With a segment table a reference never crosses a multiple of S.
 """
 from __future__ import annotations
 
@@ -124,6 +125,8 @@ def decode(data):
         g = br.unary() if W > 0 else 0
         if g > W or g > i:
             raise FormatError("reference outside the window at node %d" % i)
+        if g and hdr["stride"] and hdr["nseg"] and (i - g) // hdr["stride"] != i // hdr["stride"]:
+            raise FormatError("reference crosses a segment boundary at node %d" % i)
         copied: list[int] = []
         if g > 0:
             ref = lists[i - g]

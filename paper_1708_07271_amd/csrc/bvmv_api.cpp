@@ -1,0 +1,672 @@
+// C ABI of the library (declared in include/bvmv.h).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <memory>
+#include <string>
+#include <thread>
+#include <vector>
+
+#include "../../include/bvmv.h"
+#include "bv_decode.hpp"
+#include "bv_layout.hpp"
+#include "kernels.hpp"
+
+using namespace bvmv;
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const std::string& msg) {
+  g_err = msg;
+  return code;
+}
+
+#define HIP_TRY(expr)                                                                   \
+  do {                                                                                  \
+    hipError_t e_ = (expr);                                                             \
+    if (e_ != hipSuccess) return fail(BVMV_EDEVICE, std::string(#expr ": ") + hipGetErrorString(e_)); \
+  } while (0)
+
+struct DeviceGuard {
+  int prev = -1;
+  hipError_t err = hipSuccess;
+  explicit DeviceGuard(int dev) {
+    if (hipGetDevice(&prev) != hipSuccess) prev = -1;
+    if (prev != dev) err = hipSetDevice(dev);
+  }
+  ~DeviceGuard() {
+    int cur = -1;
+    if (prev >= 0 && hipGetDevice(&cur) == hipSuccess && cur != prev) (void)hipSetDevice(prev);
+  }
+};
+
+int default_threads(int req) {
+  if (req > 0) return std::min(req, 64);
+  unsigned hc = std::thread::hardware_concurrency();
+  return int(std::max(1u, std::min(hc ? hc : 4u, 16u)));
+}
+
+template <class T>
+int dev_upload(T** dst, const T* src, size_t count) {
+  *dst = nullptr;
+  if (count == 0) count = 1;
+  hipError_t e = hipMalloc(reinterpret_cast<void**>(dst), count * sizeof(T));
+  if (e != hipSuccess) { *dst = nullptr; return fail(BVMV_ENOMEM, std::string("hipMalloc: ") + hipGetErrorString(e)); }
+  if (src) {
+    e = hipMemcpy(*dst, src, count * sizeof(T), hipMemcpyHostToDevice);
+    if (e != hipSuccess) return fail(BVMV_EDEVICE, std::string("hipMemcpy: ") + hipGetErrorString(e));
+  }
+  return BVMV_OK;
+}
+
+void dev_free(void* p) {
+  if (p) (void)hipFree(p);
+}
+
+size_t elem_size(int prec) { return prec == BVMV_F64 ? 8 : 4; }
+
+// PageRank working set kept with a handle between calls.
+struct PRWork {
+  int prec = -1;
+  int64_t n = 0;
+  void* p[2] = {nullptr, nullptr};
+  void* z[2] = {nullptr, nullptr};
+  PRState* st = nullptr;
+  double* slots = nullptr;
+  PRState* h_st = nullptr;  // pinned
+  int nst = 0;
+  hipGraphExec_t exec = nullptr;
+  hipGraph_t graph = nullptr;
+  // key of the captured graph
+  const void* key_tele = nullptr;
+  double key_beta = -1, key_tol = -1;
+  int key_max_iter = -1, key_chunk = -1, key_mode = -1;
+
+  void drop_graph() {
+    if (exec) (void)hipGraphExecDestroy(exec);
+    if (graph) (void)hipGraphDestroy(graph);
+    exec = nullptr;
+    graph = nullptr;
+    key_chunk = -1;
+  }
+  void release() {
+    drop_graph();
+    for (int b = 0; b < 2; ++b) { dev_free(p[b]); dev_free(z[b]); p[b] = z[b] = nullptr; }
+    dev_free(st);
+    dev_free(slots);
+    if (h_st) (void)hipHostFree(h_st);
+    st = nullptr;
+    slots = nullptr;
+    h_st = nullptr;
+    prec = -1;
+  }
+  int ensure(int pr, int64_t nn, int members, int64_t ntiles) {
+    if (prec == pr && n == nn && nst == members && slots) return BVMV_OK;
+    release();
+    const size_t es = elem_size(pr);
+    for (int b = 0; b < 2; ++b) {
+      HIP_TRY(hipMalloc(&p[b], size_t(nn) * es));
+      HIP_TRY(hipMalloc(&z[b], size_t(nn) * es));
+    }
+    HIP_TRY(hipMalloc(reinterpret_cast<void**>(&st), sizeof(PRState) * size_t(members)));
+    HIP_TRY(hipMalloc(reinterpret_cast<void**>(&slots), sizeof(double) * 2 * size_t(std::max<int64_t>(ntiles, 1))));
+    HIP_TRY(hipHostMalloc(reinterpret_cast<void**>(&h_st), sizeof(PRState) * size_t(members), hipHostMallocDefault));
+    prec = pr;
+    n = nn;
+    nst = members;
+    return BVMV_OK;
+  }
+};
+
+struct PROptsResolved {
+  double beta, tol;
+  int max_iter, prec, chunk;
+};
+
+int resolve_pr_opts(const bvmv_pr_opts* o, PROptsResolved& r) {
+  r.beta = 0.85;
+  r.tol = 1e-6;
+  r.max_iter = 1000;
+  r.prec = BVMV_F32_COMP;
+  r.chunk = 16;
+  if (o) {
+    if (o->damping != 0.0 || o->exact_zero_damping) r.beta = o->damping;
+    if (o->tol != 0.0) r.tol = o->tol;
+    if (o->max_iter) r.max_iter = o->max_iter;
+    r.prec = o->prec;
+    if (o->chunk) r.chunk = o->chunk;
+  }
+  if (!(r.beta >= 0.0 && r.beta < 1.0) || !(r.tol > 0.0) || r.max_iter < 1 || r.prec < 0 || r.prec > 2 ||
+      r.chunk < 1 || r.chunk > 1024)
+    return fail(BVMV_EINVAL, "PageRank option out of range");
+  if (r.chunk % 2) ++r.chunk;  // even, so every replay starts from buffer 0
+  return BVMV_OK;
+}
+
+}  // namespace
+
+namespace bvmv {
+int set_error(int code, const std::string& msg) { return fail(code, msg); }
+}  // namespace bvmv
+
+struct bvmv_graph {
+  int device = 0;
+  bvmv_load_opts opts{};
+  int interval_mode = 0;
+  DecodedGraph dec;          // lists kept only with keep_lists
+  bool lists_kept = false;
+  HostLayout hl;             // host copy (groups are built from it)
+  std::vector<int32_t> h_outdeg;
+  int64_t n = 0, m = 0, m_prime = 0, stream_bytes = 0;
+  int W = 0, R = 0, Lmin = 0, zk = 0;
+  // device
+  TileDesc* d_tiles = nullptr;
+  uint32_t* d_info = nullptr;
+  uint16_t* d_words = nullptr;
+  uint32_t* d_longs = nullptr;
+  int32_t* d_outdeg = nullptr;
+  DevLayout L;
+  // group
+  int ngraphs = 1;
+  std::vector<int64_t> offsets;        // ngraphs + 1
+  std::vector<uint32_t> tile_offsets;  // ngraphs + 1
+  PRWork pr;
+  hipStream_t cap = nullptr;
+
+  void release_device() {
+    pr.release();
+    dev_free(d_tiles);
+    dev_free(d_info);
+    dev_free(d_words);
+    dev_free(d_longs);
+    dev_free(d_outdeg);
+    d_tiles = nullptr;
+    d_info = nullptr;
+    d_words = nullptr;
+    d_longs = nullptr;
+    d_outdeg = nullptr;
+    if (cap) (void)hipStreamDestroy(cap);
+    cap = nullptr;
+  }
+};
+
+struct bvmv_csr {
+  int device = 0;
+  int64_t n = 0, m = 0;
+  std::vector<CsrTile> tiles;
+  CsrTile* d_tiles = nullptr;
+  uint32_t* d_rowptr = nullptr;
+  uint32_t* d_col = nullptr;
+  int32_t* d_outdeg = nullptr;
+  DevCsr C;
+  PRWork pr;
+  hipStream_t cap = nullptr;
+};
+
+namespace {
+
+int upload_layout(bvmv_graph* g) {
+  const HostLayout& hl = g->hl;
+  if (int rc = dev_upload(&g->d_tiles, hl.tiles.data(), hl.tiles.size())) return rc;
+  if (int rc = dev_upload(&g->d_info, hl.info.data(), hl.info.size())) return rc;
+  if (int rc = dev_upload(&g->d_words, hl.words.data(), hl.words.size())) return rc;
+  if (int rc = dev_upload(&g->d_longs, hl.longs.data(), hl.longs.size())) return rc;
+  if (int rc = dev_upload(&g->d_outdeg, g->h_outdeg.data(), g->h_outdeg.size())) return rc;
+  g->L.tiles = g->d_tiles;
+  g->L.info = g->d_info;
+  g->L.words = g->d_words;
+  g->L.longs = g->d_longs;
+  g->L.ntiles = uint32_t(hl.tiles.size());
+  // LDS carve sizes: the largest use of any tile, rounded up
+  uint32_t tcap = 0, wcap = 0, ecap = 0;
+  for (const auto& t : hl.tiles) {
+    tcap = std::max(tcap, t.nrows);
+    wcap = std::max(wcap, t.winlen);
+    ecap = std::max(ecap, t.nwords);
+  }
+  g->L.tcap = std::max<uint32_t>(64, (tcap + 63) / 64 * 64);
+  g->L.wcap = std::max<uint32_t>(64, (wcap + 63) / 64 * 64);
+  g->L.ecap = std::max<uint32_t>(64, (ecap + 63) / 64 * 64);
+  HIP_TRY(hipStreamCreateWithFlags(&g->cap, hipStreamNonBlocking));
+  return BVMV_OK;
+}
+
+// Launch chunked PageRank on a tile layout or a CSR.  `iter` launches one
+// iteration on stream s with the given args; `init` the start kernel.
+template <class IterFn, class InitFn>
+int run_pagerank(PRWork& w, hipStream_t cap, const PROptsResolved& o, int interval_mode, int64_t n,
+                 const std::vector<int64_t>& offsets, const std::vector<uint32_t>& tile_offsets,
+                 const void* tele, const void* start, void* p_out, bvmv_pr_result* res, hipStream_t s,
+                 IterFn iter, InitFn init) {
+  const int members = int(offsets.size()) - 1;
+  if (int rc = w.ensure(o.prec, n, members, int64_t(tile_offsets.back()))) return rc;
+  for (int gI = 0; gI < members; ++gI) {
+    PRState& st = w.h_st[gI];
+    std::memset(&st, 0, sizeof(st));
+    st.inv_n = 1.0 / double(offsets[size_t(gI) + 1] - offsets[size_t(gI)]);
+    st.tile_lo = tile_offsets[size_t(gI)];
+    st.tile_hi = tile_offsets[size_t(gI) + 1];
+  }
+  HIP_TRY(hipMemcpyAsync(w.st, w.h_st, sizeof(PRState) * size_t(members), hipMemcpyHostToDevice, s));
+  HIP_TRY(init(start, tele, w.p[0], w.z[0], s));
+  const bool same = w.exec && w.key_tele == tele && w.key_beta == o.beta && w.key_tol == o.tol &&
+                    w.key_max_iter == o.max_iter && w.key_chunk == o.chunk && w.key_mode == interval_mode;
+  if (!same) {
+    w.drop_graph();
+    HIP_TRY(hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal));
+    hipError_t ce = hipSuccess;
+    for (int c = 0; c < o.chunk && ce == hipSuccess; ++c) {
+      PRArgs a{};
+      a.p_cur = w.p[c % 2];
+      a.p_new = w.p[(c + 1) % 2];
+      a.z_cur = w.z[c % 2];
+      a.z_new = w.z[(c + 1) % 2];
+      a.tele = tele;
+      a.st = w.st;
+      a.slots = w.slots;
+      a.beta = o.beta;
+      a.tol = o.tol;
+      a.max_iter = o.max_iter;
+      a.buf = (c + 1) % 2;
+      ce = iter(a, cap);
+    }
+    hipGraph_t gr = nullptr;
+    hipError_t ee = hipStreamEndCapture(cap, &gr);
+    if (ce != hipSuccess) {
+      if (gr) (void)hipGraphDestroy(gr);
+      return fail(BVMV_EDEVICE, std::string("PageRank launch: ") + hipGetErrorString(ce));
+    }
+    if (ee != hipSuccess) return fail(BVMV_EDEVICE, std::string("hipStreamEndCapture: ") + hipGetErrorString(ee));
+    w.graph = gr;
+    HIP_TRY(hipGraphInstantiate(&w.exec, w.graph, nullptr, nullptr, 0));
+    w.key_tele = tele;
+    w.key_beta = o.beta;
+    w.key_tol = o.tol;
+    w.key_max_iter = o.max_iter;
+    w.key_chunk = o.chunk;
+    w.key_mode = interval_mode;
+  }
+  const int max_replays = (o.max_iter + o.chunk - 1) / o.chunk + 1;
+  for (int rep = 0; rep < max_replays; ++rep) {
+    HIP_TRY(hipGraphLaunch(w.exec, s));
+    HIP_TRY(hipMemcpyAsync(w.h_st, w.st, sizeof(PRState) * size_t(members), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    bool all = true;
+    for (int gI = 0; gI < members; ++gI) all = all && w.h_st[gI].done;
+    if (all) break;
+  }
+  const size_t es = elem_size(o.prec);
+  int status = BVMV_OK;
+  for (int gI = 0; gI < members; ++gI) {
+    const PRState& st = w.h_st[gI];
+    const size_t off = size_t(offsets[size_t(gI)]) * es;
+    const size_t bytes = size_t(offsets[size_t(gI) + 1] - offsets[size_t(gI)]) * es;
+    const int fb = st.done ? st.final_buf : 0;
+    HIP_TRY(hipMemcpyAsync(static_cast<char*>(p_out) + off, static_cast<const char*>(w.p[fb]) + off, bytes,
+                           hipMemcpyDeviceToDevice, s));
+    if (res) {
+      res[gI].iters = st.iter;
+      res[gI].converged = st.converged;
+      res[gI].residual = st.resid;
+    }
+    if (!st.converged) status = BVMV_NOT_CONVERGED;
+  }
+  return status;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* bvmv_last_error(void) { return g_err.c_str(); }
+const char* bvmv_version(void) { return "bvmv 0.1 (gfx950)"; }
+
+int bvmv_decode(const void* bitstream, size_t nbytes, int nthreads, uint64_t* rowptr, uint32_t* col, uint8_t* refs,
+                int64_t* n, int64_t* m) {
+  if (!bitstream || !n || !m) return fail(BVMV_EINVAL, "null argument");
+  DecodedGraph dg;
+  std::string err;
+  if (decode_stream(static_cast<const uint8_t*>(bitstream), nbytes, default_threads(nthreads), dg, err))
+    return fail(BVMV_EFORMAT, err);
+  *n = dg.n;
+  *m = dg.m;
+  if (rowptr) std::memcpy(rowptr, dg.rowptr.data(), dg.rowptr.size() * 8);
+  if (col && dg.m) std::memcpy(col, dg.col.data(), dg.col.size() * 4);
+  if (refs) std::memcpy(refs, dg.refs.data(), dg.refs.size());
+  return BVMV_OK;
+}
+
+int bvmv_load(const void* bitstream, size_t nbytes, const bvmv_load_opts* opts, bvmv_graph** out) {
+  if (!bitstream || !out) return fail(BVMV_EINVAL, "null argument");
+  *out = nullptr;
+  bvmv_load_opts o{};
+  if (opts) o = *opts;
+  if (o.tile_rows == 0) o.tile_rows = 256;
+  if (o.window_cap == 0) o.window_cap = 2048;
+  if (o.long_row_words == 0) o.long_row_words = 192;
+  if (!(o.tile_rows == 128 || o.tile_rows == 256 || o.tile_rows == 512) || o.window_cap < 256 ||
+      o.window_cap > 8192 || o.long_row_words < 16 || o.long_row_words > 4096 || o.interval_mode < 0 ||
+      o.interval_mode > 1 || o.device < 0)
+    return fail(BVMV_EINVAL, "load option out of range");
+  int ndev = 0;
+  if (hipGetDeviceCount(&ndev) != hipSuccess || o.device >= ndev) return fail(BVMV_EINVAL, "no such device");
+  std::unique_ptr<bvmv_graph> g(new bvmv_graph());
+  g->device = o.device;
+  g->opts = o;
+  g->interval_mode = o.interval_mode;
+  std::string err;
+  const int nt = default_threads(o.nthreads);
+  if (decode_stream(static_cast<const uint8_t*>(bitstream), nbytes, nt, g->dec, err)) return fail(BVMV_EFORMAT, err);
+  g->n = g->dec.n;
+  g->m = g->dec.m;
+  g->stream_bytes = int64_t(nbytes);
+  g->W = int(g->dec.hdr.W);
+  g->R = int(g->dec.hdr.R);
+  g->Lmin = int(g->dec.hdr.Lmin);
+  g->zk = int(g->dec.hdr.zeta_k);
+  g->h_outdeg.assign(size_t(g->n), 0);
+  for (uint32_t c : g->dec.col) ++g->h_outdeg[c];
+  LayoutParams prm;
+  prm.tile_rows = o.tile_rows;
+  prm.window_cap = o.window_cap;
+  prm.long_row_words = o.long_row_words;
+  prm.word_cap = 4096;
+  if (build_layout(g->dec, prm, nt, g->hl, err)) return fail(BVMV_EINVAL, err);
+  g->m_prime = g->hl.m_prime;
+  if (o.device_mem_budget && uint64_t(g->hl.bytes()) + uint64_t(g->n) * 4 > o.device_mem_budget)
+    return fail(BVMV_ENOMEM, "layout exceeds the device memory budget");
+  g->offsets = {0, g->n};
+  g->tile_offsets = {0, uint32_t(g->hl.tiles.size())};
+  {
+    DeviceGuard dg(o.device);
+    if (dg.err != hipSuccess) return fail(BVMV_EDEVICE, "hipSetDevice failed");
+    if (int rc = upload_layout(g.get())) {
+      g->release_device();
+      return rc;
+    }
+  }
+  if (o.keep_lists) {
+    g->lists_kept = true;
+  } else {
+    std::vector<uint32_t>().swap(g->dec.col);
+    std::vector<uint64_t>().swap(g->dec.rowptr);
+    std::vector<uint8_t>().swap(g->dec.refs);
+  }
+  *out = g.release();
+  return BVMV_OK;
+}
+
+void bvmv_free(bvmv_graph* g) {
+  if (!g) return;
+  {
+    DeviceGuard dg(g->device);
+    g->release_device();
+  }
+  delete g;
+}
+
+int bvmv_multiply(bvmv_graph* g, const void* x, void* y, int prec, void* stream) {
+  if (!g || !x || !y) return fail(BVMV_EINVAL, "null argument");
+  if (prec < 0 || prec > 2) return fail(BVMV_EINVAL, "bad precision");
+  if (x == y) return fail(BVMV_EINVAL, "x and y must not overlap");
+  DeviceGuard dg(g->device);
+  HIP_TRY(launch_bv_multiply(g->L, prec, g->interval_mode, x, y, static_cast<hipStream_t>(stream)));
+  return BVMV_OK;
+}
+
+int bvmv_multiply_batch(bvmv_graph* g, const void* X, void* Y, int k, int64_t ld, int prec, void* stream) {
+  if (!g || !X || !Y) return fail(BVMV_EINVAL, "null argument");
+  if (prec < 0 || prec > 2 || k < 1 || k > 64 || ld < k) return fail(BVMV_EINVAL, "bad batch arguments");
+  if (X == Y) return fail(BVMV_EINVAL, "X and Y must not overlap");
+  DeviceGuard dg(g->device);
+  HIP_TRY(launch_bv_multiply_batch(g->L, prec, X, Y, k, ld, static_cast<hipStream_t>(stream)));
+  return BVMV_OK;
+}
+
+int bvmv_degrees(bvmv_graph* g, int32_t* deg, void* stream) {
+  if (!g || !deg) return fail(BVMV_EINVAL, "null argument");
+  DeviceGuard dg(g->device);
+  HIP_TRY(launch_bv_degrees(g->L, deg, static_cast<hipStream_t>(stream)));
+  return BVMV_OK;
+}
+
+int bvmv_pagerank(bvmv_graph* g, const bvmv_pr_opts* opts, const void* teleport, const void* start, void* p_out,
+                  int k, bvmv_pr_result* res, void* stream) {
+  if (!g || !p_out) return fail(BVMV_EINVAL, "null argument");
+  PROptsResolved o;
+  if (int rc = resolve_pr_opts(opts, o)) return rc;
+  if (k != 1) return fail(BVMV_EINVAL, "k > 1 needs the batched PageRank entry");
+  DeviceGuard dg(g->device);
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  DevLayout L = g->L;
+  const int mode = g->interval_mode;
+  const int prec = o.prec;
+  auto iter = [&](const PRArgs& a, hipStream_t cs) { return launch_bv_pagerank_iter(L, prec, mode, a, cs); };
+  auto init = [&](const void* st, const void* te, void* p0, void* z0, hipStream_t ss) {
+    return launch_pr_init(L, prec, st, te, p0, z0, g->d_outdeg, g->pr.st, g->pr.slots, ss);
+  };
+  return run_pagerank(g->pr, g->cap, o, mode, g->n, g->offsets, g->tile_offsets, teleport, start, p_out, res, s,
+                      iter, init);
+}
+
+int bvmv_group(bvmv_graph* const* graphs, int count, bvmv_graph** out) {
+  if (!graphs || count < 1 || !out) return fail(BVMV_EINVAL, "bad group arguments");
+  *out = nullptr;
+  std::unique_ptr<bvmv_graph> g(new bvmv_graph());
+  g->device = graphs[0]->device;
+  g->opts = graphs[0]->opts;
+  g->interval_mode = graphs[0]->interval_mode;
+  g->ngraphs = count;
+  g->offsets.assign(1, 0);
+  g->tile_offsets.assign(1, 0);
+  HostLayout& hl = g->hl;
+  hl.prm = graphs[0]->hl.prm;
+  for (int i = 0; i < count; ++i) {
+    const bvmv_graph* m = graphs[i];
+    if (!m || m->ngraphs != 1) return fail(BVMV_EINVAL, "group members must be loaded graphs");
+    if (m->device != g->device || m->interval_mode != g->interval_mode)
+      return fail(BVMV_EINVAL, "group members must share device and interval mode");
+    const uint64_t rb = uint64_t(g->n), wb = hl.words.size(), lb = hl.longs.size();
+    if (rb + uint64_t(m->n) >= (uint64_t(1) << 30) || wb + m->hl.words.size() >= (uint64_t(1) << 32) ||
+        lb + m->hl.longs.size() >= (uint64_t(1) << 32))
+      return fail(BVMV_EINVAL, "group too large");
+    for (TileDesc td : m->hl.tiles) {
+      td.row0 += uint32_t(rb);
+      td.win0 += uint32_t(rb);
+      td.word0 += uint32_t(wb);
+      td.long0 += uint32_t(lb);
+      td.graph = uint32_t(i);
+      hl.tiles.push_back(td);
+    }
+    hl.info.insert(hl.info.end(), m->hl.info.begin(), m->hl.info.end());
+    hl.words.insert(hl.words.end(), m->hl.words.begin(), m->hl.words.end());
+    hl.longs.insert(hl.longs.end(), m->hl.longs.begin(), m->hl.longs.end());
+    g->h_outdeg.insert(g->h_outdeg.end(), m->h_outdeg.begin(), m->h_outdeg.end());
+    hl.units += m->hl.units;
+    hl.diff_rows += m->hl.diff_rows;
+    hl.direct_rows += m->hl.direct_rows;
+    hl.long_rows += m->hl.long_rows;
+    hl.escapes += m->hl.escapes;
+    hl.m_prime += m->hl.m_prime;
+    hl.max_level = std::max(hl.max_level, m->hl.max_level);
+    g->n += m->n;
+    g->m += m->m;
+    g->m_prime += m->m_prime;
+    g->stream_bytes += m->stream_bytes;
+    g->offsets.push_back(g->n);
+    g->tile_offsets.push_back(uint32_t(hl.tiles.size()));
+  }
+  hl.n = g->n;
+  g->W = graphs[0]->W;
+  g->R = graphs[0]->R;
+  g->Lmin = graphs[0]->Lmin;
+  g->zk = graphs[0]->zk;
+  DeviceGuard dg(g->device);
+  if (int rc = upload_layout(g.get())) {
+    g->release_device();
+    return rc;
+  }
+  *out = g.release();
+  return BVMV_OK;
+}
+
+int bvmv_group_offsets(const bvmv_graph* g, int64_t* offsets, int* count) {
+  if (!g) return fail(BVMV_EINVAL, "null argument");
+  if (count) *count = g->ngraphs;
+  if (offsets) std::copy(g->offsets.begin(), g->offsets.end(), offsets);
+  return BVMV_OK;
+}
+
+int bvmv_get_info(const bvmv_graph* g, bvmv_info* out) {
+  if (!g || !out) return fail(BVMV_EINVAL, "null argument");
+  std::memset(out, 0, sizeof(*out));
+  out->n = g->n;
+  out->m = g->m;
+  out->m_prime = g->m_prime;
+  out->units = g->hl.units;
+  out->diff_rows = g->hl.diff_rows;
+  out->direct_rows = g->hl.direct_rows;
+  out->long_rows = g->hl.long_rows;
+  out->escapes = g->hl.escapes;
+  out->ntiles = int64_t(g->hl.tiles.size());
+  out->layout_bytes = g->hl.bytes();
+  out->stream_bytes = g->stream_bytes;
+  out->W = g->W;
+  out->R = g->R;
+  out->Lmin = g->Lmin;
+  out->zeta_k = g->zk;
+  out->tile_rows = g->hl.prm.tile_rows;
+  out->window_cap = g->hl.prm.window_cap;
+  out->long_row_words = g->hl.prm.long_row_words;
+  out->interval_mode = g->interval_mode;
+  out->max_level = g->hl.max_level;
+  out->ngraphs = g->ngraphs;
+  return BVMV_OK;
+}
+
+int bvmv_export_csr(const bvmv_graph* g, uint64_t* rowptr, uint32_t* col) {
+  if (!g || !rowptr || !col) return fail(BVMV_EINVAL, "null argument");
+  if (!g->lists_kept) return fail(BVMV_EINVAL, "graph was loaded without keep_lists");
+  std::memcpy(rowptr, g->dec.rowptr.data(), g->dec.rowptr.size() * 8);
+  if (g->m) std::memcpy(col, g->dec.col.data(), g->dec.col.size() * 4);
+  return BVMV_OK;
+}
+
+// ------------------------------------------------------------------ CSR
+int bvmv_csr_create_host(int64_t n, const uint64_t* rowptr, const uint32_t* col, int device, bvmv_csr** out) {
+  if (n < 1 || !rowptr || !col || !out) return fail(BVMV_EINVAL, "bad CSR arguments");
+  *out = nullptr;
+  const uint64_t m = rowptr[n];
+  if (m >= (uint64_t(1) << 32) - 1) return fail(BVMV_EINVAL, "CSR too large for 32-bit row pointers");
+  std::unique_ptr<bvmv_csr> c(new bvmv_csr());
+  c->device = device;
+  c->n = n;
+  c->m = int64_t(m);
+  std::vector<uint32_t> rp32(size_t(n) + 1);
+  for (int64_t i = 0; i <= n; ++i) rp32[size_t(i)] = uint32_t(rowptr[i]);
+  std::vector<int32_t> outdeg(size_t(n), 0);
+  for (uint64_t k = 0; k < m; ++k) {
+    if (col[k] >= uint64_t(n)) return fail(BVMV_EINVAL, "column out of range");
+    ++outdeg[col[k]];
+  }
+  const int rcap = 256, ccap = 4096, long_thr = 192;
+  // tiles: runs of short rows (<= rcap rows, <= ccap columns), long rows alone
+  int64_t i = 0;
+  while (i < n) {
+    const uint64_t d = rowptr[i + 1] - rowptr[i];
+    if (d > uint64_t(long_thr)) {
+      c->tiles.push_back({uint32_t(i), 1u | 0x80000000u, uint32_t(rowptr[i]), uint32_t(d)});
+      ++i;
+      continue;
+    }
+    const int64_t i0 = i;
+    while (i < n && i - i0 < rcap && rowptr[i + 1] - rowptr[i] <= uint64_t(long_thr) &&
+           rowptr[i + 1] - rowptr[i0] <= uint64_t(ccap))
+      ++i;
+    c->tiles.push_back({uint32_t(i0), uint32_t(i - i0), uint32_t(rowptr[i0]), uint32_t(rowptr[i] - rowptr[i0])});
+  }
+  DeviceGuard dg(device);
+  if (dg.err != hipSuccess) return fail(BVMV_EDEVICE, "hipSetDevice failed");
+  auto cleanup = [&] {
+    dev_free(c->d_tiles);
+    dev_free(c->d_rowptr);
+    dev_free(c->d_col);
+    dev_free(c->d_outdeg);
+  };
+  if (dev_upload(&c->d_tiles, c->tiles.data(), c->tiles.size()) ||
+      dev_upload(&c->d_rowptr, rp32.data(), rp32.size()) || dev_upload(&c->d_col, col, size_t(m)) ||
+      dev_upload(&c->d_outdeg, outdeg.data(), outdeg.size())) {
+    cleanup();
+    return BVMV_ENOMEM;
+  }
+  if (hipStreamCreateWithFlags(&c->cap, hipStreamNonBlocking) != hipSuccess) {
+    cleanup();
+    return fail(BVMV_EDEVICE, "hipStreamCreate failed");
+  }
+  c->C.tiles = c->d_tiles;
+  c->C.rowptr = c->d_rowptr;
+  c->C.col = c->d_col;
+  c->C.ntiles = uint32_t(c->tiles.size());
+  c->C.rcap = rcap;
+  c->C.ccap = ccap;
+  *out = c.release();
+  return BVMV_OK;
+}
+
+int bvmv_csr_create(const bvmv_graph* g, bvmv_csr** out) {
+  if (!g || !out) return fail(BVMV_EINVAL, "null argument");
+  if (!g->lists_kept || g->ngraphs != 1) return fail(BVMV_EINVAL, "graph was loaded without keep_lists");
+  return bvmv_csr_create_host(g->n, g->dec.rowptr.data(), g->dec.col.empty() ? nullptr : g->dec.col.data(),
+                              g->device, out);
+}
+
+int bvmv_csr_multiply(bvmv_csr* c, const void* x, void* y, int prec, void* stream) {
+  if (!c || !x || !y) return fail(BVMV_EINVAL, "null argument");
+  if (prec < 0 || prec > 2) return fail(BVMV_EINVAL, "bad precision");
+  DeviceGuard dg(c->device);
+  HIP_TRY(launch_csr_multiply(c->C, prec, x, y, static_cast<hipStream_t>(stream)));
+  return BVMV_OK;
+}
+
+int bvmv_csr_pagerank(bvmv_csr* c, const bvmv_pr_opts* opts, const void* teleport, const void* start, void* p_out,
+                      bvmv_pr_result* res, void* stream) {
+  if (!c || !p_out) return fail(BVMV_EINVAL, "null argument");
+  PROptsResolved o;
+  if (int rc = resolve_pr_opts(opts, o)) return rc;
+  DeviceGuard dg(c->device);
+  DevCsr C = c->C;
+  const int prec = o.prec;
+  std::vector<int64_t> offsets{0, c->n};
+  std::vector<uint32_t> toffs{0, C.ntiles};
+  auto iter = [&](const PRArgs& a, hipStream_t cs) { return launch_csr_pagerank_iter(C, prec, a, cs); };
+  auto init = [&](const void* st, const void* te, void* p0, void* z0, hipStream_t ss) {
+    return launch_csr_pr_init(C, prec, st, te, p0, z0, c->d_outdeg, c->pr.st, c->pr.slots, ss);
+  };
+  return run_pagerank(c->pr, c->cap, o, 0, c->n, offsets, toffs, teleport, start, p_out, res,
+                      static_cast<hipStream_t>(stream), iter, init);
+}
+
+int64_t bvmv_csr_bytes(const bvmv_csr* c) {
+  if (!c) return 0;
+  return int64_t(c->n + 1) * 4 + c->m * 4;
+}
+
+void bvmv_csr_free(bvmv_csr* c) {
+  if (!c) return;
+  {
+    DeviceGuard dg(c->device);
+    c->pr.release();
+    dev_free(c->d_tiles);
+    dev_free(c->d_rowptr);
+    dev_free(c->d_col);
+    dev_free(c->d_outdeg);
+    if (c->cap) (void)hipStreamDestroy(c->cap);
+  }
+  delete c;
+}
+
+}  // extern "C"

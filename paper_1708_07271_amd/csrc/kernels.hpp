@@ -1,0 +1,74 @@
+// Host-side launchers of the HIP kernels (gfx950, wave64).
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "bv_layout.hpp"
+
+namespace bvmv {
+
+struct DevLayout {
+  const TileDesc* tiles = nullptr;
+  const uint32_t* info = nullptr;
+  const uint16_t* words = nullptr;
+  const uint32_t* longs = nullptr;
+  uint32_t ntiles = 0;
+  uint32_t tcap = 256, wcap = 2048, ecap = 4096;  // LDS carve sizes (>= every tile's use)
+};
+
+struct DevCsr {
+  const CsrTile* tiles = nullptr;
+  const uint32_t* rowptr = nullptr;  // n+1, 32-bit
+  const uint32_t* col = nullptr;
+  uint32_t ntiles = 0;
+  uint32_t rcap = 256, ccap = 4096;
+};
+
+// Per-member PageRank state, updated by the last block of every iteration.
+struct PRState {
+  double delta;      // dangling mass of the current iterate
+  double resid;      // ||p_t - p_{t-1}||_1 of the last iteration
+  double inv_n;      // 1/n of the member (uniform teleport)
+  int32_t iter;      // iterations done
+  int32_t done;      // 1 once converged or out of iterations
+  int32_t converged;
+  int32_t final_buf; // buffer (0/1) holding the final iterate once done
+  uint32_t ticket;   // blocks of the current launch that have finished
+  uint32_t tile_lo, tile_hi;  // tile range of the member
+  uint32_t pad;
+};
+
+struct PRArgs {
+  const void* p_cur;     // current iterate (X*)
+  void* p_new;           // next iterate (X*)
+  const void* z_cur;     // p_cur / d (X*), gathered by the product
+  void* z_new;           // p_new / d (X*)
+  const void* tele;      // teleport (X*), nullptr = uniform per member
+  const int32_t* outdeg; // d_u
+  PRState* st;           // per member
+  double* slots;         // 2 doubles per tile
+  double beta, tol;
+  int32_t max_iter;
+  int32_t buf;           // index of p_new's buffer (0/1)
+};
+
+hipError_t launch_bv_multiply(const DevLayout& L, int prec, int interval_mode, const void* x, void* y,
+                              hipStream_t s);
+hipError_t launch_bv_degrees(const DevLayout& L, int32_t* deg, hipStream_t s);
+hipError_t launch_bv_pagerank_iter(const DevLayout& L, int prec, int interval_mode, const PRArgs& a,
+                                   hipStream_t s);
+// z = p / d, dangling mass and state reset for the start vector (tile grid)
+hipError_t launch_pr_init(const DevLayout& L, int prec, const void* start, const void* tele, void* p0, void* z0,
+                          const int32_t* outdeg, PRState* st, double* slots, hipStream_t s);
+
+hipError_t launch_csr_multiply(const DevCsr& C, int prec, const void* x, void* y, hipStream_t s);
+hipError_t launch_csr_pagerank_iter(const DevCsr& C, int prec, const PRArgs& a, hipStream_t s);
+hipError_t launch_csr_pr_init(const DevCsr& C, int prec, const void* start, const void* tele, void* p0, void* z0,
+                              const int32_t* outdeg, PRState* st, double* slots, hipStream_t s);
+
+// Y = A X for k <= 64 right-hand sides, node-major with leading dimension ld
+hipError_t launch_bv_multiply_batch(const DevLayout& L, int prec, const void* X, void* Y, int k, int64_t ld,
+                                    hipStream_t s);
+
+}  // namespace bvmv

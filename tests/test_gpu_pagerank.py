@@ -1,0 +1,149 @@
+"""GPU parity of PageRank (power method, Eq. (1) of the paper) against the
+CPU oracle: closed forms, iteration-matched oracle runs, degenerate cases,
+personalized teleport, warm start, groups (ragged batch) and the CSR path.
+
+The loaded rows are in-link lists; dangling mass goes to the teleport vector;
+the stopping test is ||p_t - p_{t-1}||_1 < tol accumulated in double."""
+import numpy as np
+import pytest
+
+import bvinputs as B
+from oracle import pagerank
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+DEV = "cuda:0"
+
+
+@pytest.fixture(scope="module")
+def P():
+    if not torch.cuda.is_available():
+        pytest.skip("no HIP device")
+    import paper_1708_07271_amd as mod
+    mod.load_library()
+    return mod
+
+
+def _in_links(g):
+    return g.transpose()
+
+
+def _pr(P, G, n, prec, **kw):
+    dt = torch.float64 if prec == P.BVMV_F64 else torch.float32
+    p = torch.empty(n, dtype=dt, device=DEV)
+    for key in ("teleport", "start"):
+        if key in kw and kw[key] is not None:
+            kw[key] = torch.from_numpy(np.ascontiguousarray(kw[key]).astype(np.float64 if dt == torch.float64
+                                                                              else np.float32)).to(DEV)
+    res = P.bvmv_pagerank(G, p, prec=prec, **kw)
+    torch.cuda.synchronize()
+    return p.cpu().numpy().astype(np.float64), res
+
+
+def test_closed_forms(P):
+    beta = 0.85
+    n = 17
+    cases = [(B.complete_graph(n), None), (B.cycle_graph(n), None)]
+    for kind, pc in (("both", ((1 - beta) / n + beta) / (1 + beta)),
+                     ("in", (1 + (n - 1) * beta) / (n + (n - 1) * beta)),
+                     ("out", 1.0 / (n + beta))):
+        cases.append((B.star_graph(n, 0, kind), pc))
+    for g, pc in cases:
+        bt = _in_links(g)
+        G = P.bvmv_load(B.encode(bt).data)
+        p, ((it, ok, r),) = _pr(P, G, n, P.BVMV_F64, tol=1e-15, max_iter=1000)
+        assert ok
+        if pc is None:
+            assert np.max(np.abs(p - 1.0 / n)) < 1e-14
+        else:
+            assert abs(p[0] - pc) < 1e-13
+            assert np.max(np.abs(p[1:] - (1 - pc) / (n - 1))) < 1e-13
+
+
+@pytest.mark.parametrize("prec_name,tol", [("f64", 1e-12), ("f32c", 1e-5), ("f32", 1e-4)])
+def test_iteration_matched(P, prec_name, tol):
+    prec = P.PREC_NAMES[prec_name]
+    g = B.web_graph(40_000, 15.0, 77)          # rows read as in-link lists, as loaded
+    G = P.bvmv_load(B.encode(g).data)
+    p, ((it, ok, r),) = _pr(P, G, g.n, prec)
+    assert ok and r < 1e-6
+    _, t_or, _, ok_or = pagerank.pagerank(g.rowptr, g.col, 0.85, tol=1e-6)
+    assert ok_or and abs(it - t_or) <= 1
+    p_ref = pagerank.pagerank(g.rowptr, g.col, 0.85, iters=it)[0]
+    assert np.max(np.abs(p - p_ref) / p_ref) < tol
+    assert abs(p.sum() - 1.0) < (1e-12 if prec == P.BVMV_F64 else 1e-5)
+
+
+def test_personalized_start_and_limits(P):
+    g = B.web_graph(20_000, 12.0, 78)
+    G = P.bvmv_load(B.encode(g).data)
+    v = np.zeros(g.n)
+    seeds = np.random.default_rng(1).choice(g.n, 16, replace=False)
+    v[seeds] = 1.0 / 16
+    p, ((it, ok, r),) = _pr(P, G, g.n, P.BVMV_F64, teleport=v)
+    p_ref = pagerank.pagerank(g.rowptr, g.col, 0.85, teleport=v, iters=it)[0]
+    assert ok and np.max(np.abs(p - p_ref)) < 1e-12 * np.max(p_ref)
+    # warm start from the converged vector: stops almost at once
+    p2, ((it2, ok2, r2),) = _pr(P, G, g.n, P.BVMV_F64, teleport=v, start=p)
+    assert ok2 and it2 <= 2
+    # iteration limit: NOT_CONVERGED status, outputs still written
+    p3, ((it3, ok3, r3),) = _pr(P, G, g.n, P.BVMV_F64, teleport=v, max_iter=3)
+    assert not ok3 and it3 == 3
+    assert np.max(np.abs(p3 - pagerank.pagerank(g.rowptr, g.col, 0.85, teleport=v, iters=3)[0])) < 1e-15
+    # beta = 0: p = v
+    p4, _ = _pr(P, G, g.n, P.BVMV_F64, teleport=v, damping=0.0)
+    assert np.max(np.abs(p4 - v)) < 1e-16
+
+
+def test_edgeless_and_determinism(P):
+    G = P.bvmv_load(B.encode(B.empty_graph(500)).data)
+    p, ((it, ok, r),) = _pr(P, G, 500, P.BVMV_F32_COMP)
+    assert ok and it == 1 and np.allclose(p, 1 / 500, rtol=1e-6)
+    g = B.web_graph(30_000, 15.0, 79)
+    G = P.bvmv_load(B.encode(g).data)
+    a, ra = _pr(P, G, g.n, P.BVMV_F32_COMP)
+    b, rb = _pr(P, G, g.n, P.BVMV_F32_COMP)
+    assert ra == rb and np.array_equal(a, b)
+
+
+def test_group_equals_solo(P):
+    sizes = [3000, 800, 12_000, 5000, 200]
+    gs = [B.web_graph(n, 10.0 + i, 200 + i) for i, n in enumerate(sizes)]
+    Gs = [P.bvmv_load(B.encode(g).data) for g in gs]
+    grp = P.bvmv_group(Gs)
+    offs = P.bvmv_group_offsets(grp)
+    pg, res = _pr(P, grp, offs[-1], P.BVMV_F32_COMP)
+    assert len(res) == len(gs)
+    for i, g in enumerate(gs):
+        ps, ((it, ok, r),) = _pr(P, Gs[i], g.n, P.BVMV_F32_COMP)
+        assert res[i][0] == it and res[i][1] == ok
+        assert np.array_equal(pg[offs[i]:offs[i + 1]], ps)
+        p_ref = pagerank.pagerank(g.rowptr, g.col, 0.85, iters=it)[0]
+        assert np.max(np.abs(ps - p_ref) / p_ref) < 1e-5
+
+
+def test_csr_pagerank(P):
+    g = B.web_graph(30_000, 15.0, 80)
+    G = P.bvmv_load(B.encode(g).data, keep_lists=1)
+    C = P.bvmv_csr_create(G)
+    p = torch.empty(g.n, dtype=torch.float32, device=DEV)
+    it, ok, r = P.bvmv_csr_pagerank(C, p)
+    torch.cuda.synchronize()
+    p_ref = pagerank.pagerank(g.rowptr, g.col, 0.85, iters=it)[0]
+    assert ok and np.max(np.abs(p.cpu().numpy() - p_ref) / p_ref) < 1e-5
+    pc, ((itc, okc, rc),) = _pr(P, G, g.n, P.BVMV_F32_COMP)
+    assert abs(itc - it) <= 1
+
+
+@pytest.mark.slow
+def test_full_size_pagerank_2p20(P):
+    g = B.workload_graph("web-n2p20-d20")
+    G = P.bvmv_load(B.encode(g).data)
+    p, ((it, ok, r),) = _pr(P, G, g.n, P.BVMV_F32_COMP)
+    assert ok
+    p_ref, t_or, _, _ = pagerank.pagerank(g.rowptr, g.col, 0.85, tol=1e-6)
+    assert abs(it - t_or) <= 1
+    p_ref = pagerank.pagerank(g.rowptr, g.col, 0.85, iters=it)[0]
+    assert np.max(np.abs(p - p_ref) / p_ref) < 1e-5
+    assert abs(p.sum() - 1.0) < 1e-5

@@ -1,0 +1,220 @@
+"""GPU parity of the compressed product, degrees, CSR baseline and batched
+products against the CPU oracle (same seeded inputs).
+
+Tolerances: FP64 path 1e-12 relative per entry; FP32 paths 1e-5 relative per
+entry against the float64 oracle on the same float32 inputs; integer-valued
+x makes every partial sum exact, so all modes must then be bit-exact."""
+import numpy as np
+import pytest
+
+import bvinputs as B
+from oracle import product
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def P():
+    if not torch.cuda.is_available():
+        pytest.skip("no HIP device")
+    import paper_1708_07271_amd as mod
+    mod.load_library()
+    return mod
+
+
+DEV = "cuda:0"
+
+
+def _rel(a, b):
+    a = np.asarray(a, dtype=np.float64)
+    b = np.asarray(b, dtype=np.float64)
+    d = np.abs(a - b)
+    z = b == 0
+    assert np.all(d[z] == 0), "nonzero result where the oracle gives 0"
+    return float(np.max(d[~z] / np.abs(b[~z]))) if np.any(~z) else 0.0
+
+
+def _mul(P, G, x, prec):
+    xd = torch.from_numpy(np.ascontiguousarray(x)).to(DEV)
+    yd = torch.empty_like(xd)
+    P.bvmv_multiply(G, xd, yd, prec)
+    torch.cuda.synchronize()
+    return yd.cpu().numpy()
+
+
+def _csr_mul(P, C, x, prec):
+    xd = torch.from_numpy(np.ascontiguousarray(x)).to(DEV)
+    yd = torch.empty_like(xd)
+    P.bvmv_csr_multiply(C, xd, yd, prec)
+    torch.cuda.synchronize()
+    return yd.cpu().numpy()
+
+
+LAYOUTS = [dict(), dict(tile_rows=128, window_cap=256, long_row_words=16),
+           dict(tile_rows=512, window_cap=8192, long_row_words=4096), dict(interval_mode=1),
+           dict(tile_rows=256, window_cap=512, long_row_words=40, interval_mode=1)]
+
+
+def _graphs():
+    return {
+        "web-n1e4-d15": B.web_graph(10_000, 15.0, 1),
+        "social-n3e4-d30": B.social_graph(30_000, 30.0, 5000, 2.1, 3),
+    }
+
+
+@pytest.fixture(scope="module")
+def graphs():
+    out = {}
+    for name, g in _graphs().items():
+        out[name] = (g, B.encode(g))
+    return out
+
+
+@pytest.mark.parametrize("lay", range(len(LAYOUTS)))
+def test_product_parity_all_modes(P, graphs, lay):
+    for name, (g, enc) in graphs.items():
+        print("case", name, LAYOUTS[lay], flush=True)
+        G = P.bvmv_load(enc.data, **LAYOUTS[lay])
+        x = B.uniform_x(g.n, 101)
+        assert _rel(_mul(P, G, x, P.BVMV_F64), product.matvec(g.rowptr, g.col, x)) < 1e-12
+        x32 = x.astype(np.float32)
+        ref32 = product.matvec(g.rowptr, g.col, x32.astype(np.float64))
+        assert _rel(_mul(P, G, x32, P.BVMV_F32_COMP), ref32) < 1e-5
+        assert _rel(_mul(P, G, x32, P.BVMV_F32), ref32) < 1e-3
+        xi = B.integer_x(g.n, 5, 7)                 # partial sums < 2^24: exact in float32
+        refi = product.matvec(g.rowptr, g.col, xi)
+        for prec in (P.BVMV_F32, P.BVMV_F32_COMP):
+            assert np.array_equal(_mul(P, G, xi.astype(np.float32), prec), refi)
+        xi = B.integer_x(g.n, 6, 1000)
+        assert np.array_equal(_mul(P, G, xi, P.BVMV_F64), product.matvec(g.rowptr, g.col, xi))
+
+
+def test_deterministic(P, graphs):
+    g, enc = graphs["social-n3e4-d30"]
+    G = P.bvmv_load(enc.data)
+    x = B.uniform_x(g.n, 3).astype(np.float32)
+    for prec in (P.BVMV_F32, P.BVMV_F32_COMP):
+        a = _mul(P, G, x, prec)
+        b = _mul(P, G, x, prec)
+        assert np.array_equal(a.view(np.uint32), b.view(np.uint32))
+
+
+def test_degrees_and_export(P, graphs):
+    for name, (g, enc) in graphs.items():
+        G = P.bvmv_load(enc.data, keep_lists=1)
+        deg = torch.empty(g.n, dtype=torch.int32, device=DEV)
+        P.bvmv_degrees(G, deg)
+        torch.cuda.synchronize()
+        assert np.array_equal(deg.cpu().numpy(), np.diff(g.rowptr).astype(np.int32))
+        rp, col = P.bvmv_export_csr(G)
+        assert np.array_equal(rp, g.rowptr) and np.array_equal(col, g.col)
+        info = G.info()
+        assert info["m"] == g.m and info["n"] == g.n
+
+
+def test_closed_forms_on_device(P):
+    n = 300
+    x = B.uniform_x(n, 9)
+    cases = [(B.complete_graph(n), x.sum() - x), (B.star_graph(n, 7, "out"), None), (B.path_graph(n), None)]
+    for g, _ in cases:
+        G = P.bvmv_load(B.encode(g).data)
+        y = _mul(P, G, x, P.BVMV_F64)
+        assert _rel(y, product.matvec_exact(g.rowptr, g.col, x)) < 1e-12
+    G = P.bvmv_load(B.encode(B.complete_graph(n)).data)
+    assert _rel(_mul(P, G, x, P.BVMV_F64), x.sum() - x) < 1e-12
+
+
+def test_edge_cases(P):
+    # empty graph, single node, self-loops, rows touching 0 and n-1, a long reused row
+    for g in (B.empty_graph(1), B.empty_graph(1000), B.from_lists([[0]]), B.from_lists([[1], [0, 1]])):
+        G = P.bvmv_load(B.encode(g).data)
+        x = B.integer_x(g.n, 1, 1000)
+        assert np.array_equal(_mul(P, G, x, P.BVMV_F64), product.matvec(g.rowptr, g.col, x))
+    n = 70_000
+    rng = np.random.default_rng(5)
+    lists = [[] for _ in range(n)]
+    lists[1] = list(range(0, 300))
+    lists[2] = list(range(0, 300))
+    lists[5] = sorted(rng.choice(n, 50_000, replace=False).tolist())
+    lists[6] = sorted(set(lists[5][:45_000]) | {n - 1})
+    lists[n - 1] = list(range(n - 20, n))
+    g = B.from_lists(lists)
+    enc = B.encode(g)
+    for lay in LAYOUTS:
+        G = P.bvmv_load(enc.data, **lay)
+        x = B.integer_x(n, 2, 7)
+        assert np.array_equal(_mul(P, G, x.astype(np.float32), P.BVMV_F32_COMP), product.matvec(g.rowptr, g.col, x))
+
+
+def test_csr_baseline(P, graphs):
+    for name, (g, enc) in graphs.items():
+        G = P.bvmv_load(enc.data, keep_lists=1)
+        C = P.bvmv_csr_create(G)
+        x = B.uniform_x(g.n, 11)
+        assert _rel(_csr_mul(P, C, x, P.BVMV_F64), product.matvec(g.rowptr, g.col, x)) < 1e-12
+        x32 = x.astype(np.float32)
+        ref32 = product.matvec(g.rowptr, g.col, x32.astype(np.float64))
+        assert _rel(_csr_mul(P, C, x32, P.BVMV_F32_COMP), ref32) < 1e-5
+        xi = B.integer_x(g.n, 12, 7).astype(np.float32)
+        assert np.array_equal(_csr_mul(P, C, xi, P.BVMV_F32), product.matvec(g.rowptr, g.col, xi))
+
+
+@pytest.mark.parametrize("k", [1, 3, 16, 32, 64])
+def test_batch_matches_oracle(P, graphs, k):
+    for name, (g, enc) in graphs.items():
+        print("case", name, k, flush=True)
+        G = P.bvmv_load(enc.data)
+        rng = np.random.default_rng(k)
+        X = rng.random((g.n, k), dtype=np.float32)
+        Xd = torch.from_numpy(X).to(DEV)
+        Yd = torch.empty_like(Xd)
+        P.bvmv_multiply_batch(G, Xd, Yd, P.BVMV_F32_COMP)
+        torch.cuda.synchronize()
+        Y = Yd.cpu().numpy()
+        for c in range(0, k, max(1, k // 4)):
+            assert _rel(Y[:, c], product.matvec(g.rowptr, g.col, X[:, c].astype(np.float64))) < 1e-5
+        Xi = rng.integers(0, 8, size=(g.n, k)).astype(np.float32)
+        Xd = torch.from_numpy(Xi).to(DEV)
+        P.bvmv_multiply_batch(G, Xd, Yd, P.BVMV_F32)
+        torch.cuda.synchronize()
+        Y = Yd.cpu().numpy()
+        for c in range(k):
+            assert np.array_equal(Y[:, c], product.matvec(g.rowptr, g.col, Xi[:, c].astype(np.float64)))
+        Xd64 = torch.from_numpy(X.astype(np.float64)).to(DEV)
+        Yd64 = torch.empty_like(Xd64)
+        P.bvmv_multiply_batch(G, Xd64, Yd64, P.BVMV_F64)
+        torch.cuda.synchronize()
+        assert _rel(Yd64.cpu().numpy()[:, k - 1], product.matvec(g.rowptr, g.col, X[:, k - 1].astype(np.float64))) < 1e-12
+
+
+def test_group_block_diagonal(P):
+    sizes = [1000, 5000, 20_000, 300]
+    gs = [B.web_graph(n, 12.0, 50 + i) for i, n in enumerate(sizes)]
+    Gs = [P.bvmv_load(B.encode(g).data) for g in gs]
+    grp = P.bvmv_group(Gs)
+    offs = P.bvmv_group_offsets(grp)
+    assert offs == [0] + list(np.cumsum(sizes))
+    x = B.integer_x(offs[-1], 3, 7).astype(np.float32)
+    y = _mul(P, grp, x, P.BVMV_F32_COMP)
+    for i, g in enumerate(gs):
+        seg = slice(offs[i], offs[i + 1])
+        assert np.array_equal(y[seg], product.matvec(g.rowptr, g.col, x[seg].astype(np.float64)))
+        assert np.array_equal(y[seg], _mul(P, Gs[i], x[seg], P.BVMV_F32_COMP))
+
+
+@pytest.mark.slow
+def test_full_size_web_2p20(P):
+    """n = 2^20, mean out-degree 20: every row against the oracle, and sampled
+    rows against correctly rounded sums."""
+    g = B.workload_graph("web-n2p20-d20")
+    G = P.bvmv_load(B.encode(g).data)
+    x32 = B.uniform_x(g.n, 102, np.float32)
+    y = _mul(P, G, x32, P.BVMV_F32_COMP)
+    x64 = x32.astype(np.float64)
+    assert _rel(y, product.matvec(g.rowptr, g.col, x64)) < 1e-5
+    rows = np.random.default_rng(0).choice(g.n, 2000, replace=False)
+    assert _rel(y[rows], product.matvec_rows(g.rowptr, g.col, x64, rows)) < 1e-5
+    xi = B.integer_x(g.n, 4, 7).astype(np.float32)
+    assert np.array_equal(_mul(P, G, xi, P.BVMV_F32_COMP), product.matvec(g.rowptr, g.col, xi))

@@ -1,0 +1,122 @@
+"""CPU tier for the native library: it loads, exports every symbol the header
+declares, its host decoder matches the generator's lists and the
+hand-written stream, and the device layout (interpreted on the host) gives
+the oracle's product.  No compute call touches a device here."""
+import os
+import re
+
+import numpy as np
+import pytest
+
+import bvinputs as B
+from oracle import product
+from tests.golden_io import pack_stream, read_tiny_stream
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+@pytest.fixture(scope="module")
+def P():
+    import paper_1708_07271_amd as mod
+    mod.load_library()
+    return mod
+
+
+def test_exports_every_declared_symbol(P):
+    lib = P.load_library()
+    names = set()
+    for hdr in os.listdir(os.path.join(ROOT, "include")):
+        if hdr.endswith(".h"):
+            text = open(os.path.join(ROOT, "include", hdr)).read()
+            names |= set(re.findall(r"^\s*(?:[\w\*]+\s+)+\**(bvmv_\w+)\s*\(", text, flags=re.M))
+    assert len(names) >= 20
+    for n in sorted(names):
+        assert hasattr(lib, n), n
+
+
+def test_decode_golden_stream(P):
+    data, lists, refs = read_tiny_stream()
+    rowptr, col, got_refs = P.bvmv_decode(data)
+    for i, L in enumerate(lists):
+        assert col[int(rowptr[i]):int(rowptr[i + 1])].tolist() == L
+    assert got_refs.tolist() == refs
+
+
+@pytest.mark.parametrize("nthreads", [1, 4])
+def test_decode_matches_generator(P, nthreads):
+    for g in (B.web_graph(150_000, 20.0, 31), B.social_graph(60_000, 20.0, 5000, 2.1, 32)):
+        enc = B.encode(g, stride=4096)
+        rowptr, col, refs = P.bvmv_decode(enc.data, nthreads=nthreads)
+        assert np.array_equal(rowptr, g.rowptr)
+        assert np.array_equal(col, g.col)
+        assert np.array_equal(refs, enc.refs)
+
+
+def test_decode_rejects_corruption(P):
+    g = B.web_graph(3000, 12.0, 3)
+    data = B.encode(g, stride=512).data
+    for bad in (data[:100], data[: len(data) - 9]):
+        with pytest.raises(P.BvmvError) as ei:
+            P.bvmv_decode(bad)
+        assert ei.value.code == P.BVMV_EFORMAT
+    bad = data.copy()
+    bad[16] ^= 4                                  # header edge count
+    with pytest.raises(P.BvmvError):
+        P.bvmv_decode(bad)
+    bad = data.copy()
+    bad[64 + 8] ^= 1                              # second segment offset
+    with pytest.raises(P.BvmvError):
+        P.bvmv_decode(bad)
+    # node 1 referencing 2 rows back
+    with pytest.raises(P.BvmvError):
+        P.bvmv_decode(pack_stream(2, 2, 7, 3, 4, 3, "010" + "1" + "110" + "010" + "001"))
+    # flipped body bits must never crash: either an error or a consistent graph
+    rng = np.random.default_rng(0)
+    body0 = 64 + 8 * ((g.n + 511) // 512)
+    for _ in range(40):
+        bad = data.copy()
+        pos = int(rng.integers(body0, len(data)))
+        bad[pos] ^= np.uint8(1 << int(rng.integers(0, 8)))
+        try:
+            rp, col, _ = P.bvmv_decode(bad)
+            assert rp[-1] == col.size and np.all(col < g.n)
+        except P.BvmvError as e:
+            assert e.code == P.BVMV_EFORMAT
+
+
+LAYOUT_CASES = [(256, 2048, 192), (128, 256, 16), (512, 8192, 4096), (256, 512, 40)]
+
+
+@pytest.mark.parametrize("tile_rows,window_cap,long_words", LAYOUT_CASES)
+def test_layout_interpreter_matches_oracle(P, tile_rows, window_cap, long_words):
+    graphs = [B.web_graph(30_000, 20.0, 41), B.social_graph(20_000, 30.0, 3000, 2.1, 42)]
+    for g in graphs:
+        enc = B.encode(g)
+        x = B.integer_x(g.n, 7, 1000)
+        y, st = P.bvmv_layout_selfcheck(enc.data, x, tile_rows, window_cap, long_words)
+        assert np.array_equal(y, product.matvec(g.rowptr, g.col, x))
+        assert st["max_level"] <= 3
+        x = B.uniform_x(g.n, 8)
+        y, _ = P.bvmv_layout_selfcheck(enc.data, x, tile_rows, window_cap, long_words)
+        y0 = product.matvec(g.rowptr, g.col, x)
+        assert np.max(np.abs(y - y0) / np.maximum(y0, 1e-300)) < 1e-12
+
+
+def test_layout_crafted_edge_cases(P):
+    n = 5000
+    rng = np.random.default_rng(5)
+    lists = [[] for _ in range(n)]
+    lists[0] = [n - 1]
+    lists[1] = list(range(0, 300))                     # long interval from 0
+    lists[2] = list(range(0, 300))                     # identical to its reference
+    lists[3] = [2, 3]                                  # reference almost fully skipped
+    lists[4] = [4]                                     # self-loop
+    lists[5] = sorted(rng.choice(n, 4000, replace=False).tolist())   # long random row
+    lists[6] = sorted(set(lists[5][:3900]) | {n - 1})  # reuses a long row
+    lists[n - 1] = list(range(n - 20, n))              # interval touching n-1
+    g = B.from_lists(lists)
+    enc = B.encode(g)
+    x = B.integer_x(n, 1, 1000)
+    for case in LAYOUT_CASES:
+        y, _ = P.bvmv_layout_selfcheck(enc.data, x, *case)
+        assert np.array_equal(y, product.matvec(g.rowptr, g.col, x))
