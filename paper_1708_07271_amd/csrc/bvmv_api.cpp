@@ -241,9 +241,11 @@ template <class IterFn, class InitFn>
 int run_pagerank(PRWork& w, hipStream_t cap, const PROptsResolved& o, int interval_mode, int64_t n,
                  const std::vector<int64_t>& offsets, const std::vector<uint32_t>& tile_offsets,
                  const void* tele, const void* start, void* p_out, bvmv_pr_result* res, hipStream_t s,
-                 IterFn iter, InitFn init) {
+                 const int32_t* outdeg, IterFn iter, InitFn init) {
   const int members = int(offsets.size()) - 1;
   if (int rc = w.ensure(o.prec, n, members, int64_t(tile_offsets.back()))) return rc;
+  if (!outdeg || !w.p[0] || !w.p[1] || !w.z[0] || !w.z[1] || !w.st || !w.slots || !w.h_st)
+    return fail(BVMV_EINVAL, "PageRank working set is incomplete");
   for (int gI = 0; gI < members; ++gI) {
     PRState& st = w.h_st[gI];
     std::memset(&st, 0, sizeof(st));
@@ -266,6 +268,7 @@ int run_pagerank(PRWork& w, hipStream_t cap, const PROptsResolved& o, int interv
       a.z_cur = w.z[c % 2];
       a.z_new = w.z[(c + 1) % 2];
       a.tele = tele;
+      a.outdeg = outdeg;
       a.st = w.st;
       a.slots = w.slots;
       a.beta = o.beta;
@@ -450,6 +453,7 @@ int bvmv_pagerank(bvmv_graph* g, const bvmv_pr_opts* opts, const void* teleport,
     return launch_pr_init(L, prec, st, te, p0, z0, g->d_outdeg, g->pr.st, g->pr.slots, ss);
   };
   return run_pagerank(g->pr, g->cap, o, mode, g->n, g->offsets, g->tile_offsets, teleport, start, p_out, res, s,
+                      g->d_outdeg,
                       iter, init);
 }
 
@@ -647,7 +651,7 @@ int bvmv_csr_pagerank(bvmv_csr* c, const bvmv_pr_opts* opts, const void* telepor
     return launch_csr_pr_init(C, prec, st, te, p0, z0, c->d_outdeg, c->pr.st, c->pr.slots, ss);
   };
   return run_pagerank(c->pr, c->cap, o, 0, c->n, offsets, toffs, teleport, start, p_out, res,
-                      static_cast<hipStream_t>(stream), iter, init);
+                      static_cast<hipStream_t>(stream), c->d_outdeg, iter, init);
 }
 
 int64_t bvmv_csr_bytes(const bvmv_csr* c) {

@@ -49,16 +49,18 @@ def test_closed_forms(P):
                      ("in", (1 + (n - 1) * beta) / (n + (n - 1) * beta)),
                      ("out", 1.0 / (n + beta))):
         cases.append((B.star_graph(n, 0, kind), pc))
-    for g, pc in cases:
+    for ci, (g, pc) in enumerate(cases):
         bt = _in_links(g)
         G = P.bvmv_load(B.encode(bt).data)
-        p, ((it, ok, r),) = _pr(P, G, n, P.BVMV_F64, tol=1e-15, max_iter=1000)
+        # tol 1e-13: the L1 contraction bound puts p within 0.85/0.15 * 1e-13 of the fixed point
+        p, ((it, ok, r),) = _pr(P, G, n, P.BVMV_F64, tol=1e-13, max_iter=1000)
+        print("case", ci, it, ok, r, flush=True)
         assert ok
         if pc is None:
             assert np.max(np.abs(p - 1.0 / n)) < 1e-14
         else:
-            assert abs(p[0] - pc) < 1e-13
-            assert np.max(np.abs(p[1:] - (1 - pc) / (n - 1))) < 1e-13
+            assert abs(p[0] - pc) < 1e-12
+            assert np.max(np.abs(p[1:] - (1 - pc) / (n - 1))) < 1e-12
 
 
 @pytest.mark.parametrize("prec_name,tol", [("f64", 1e-12), ("f32c", 1e-5), ("f32", 1e-4)])
