@@ -60,10 +60,12 @@ typedef enum {
 /* Layout and tuning options of bvmv_load.  Zero fields take defaults. */
 typedef struct {
   int device;            /* HIP device ordinal */
-  int tile_rows;         /* rows per tile: 128, 256 or 512 (0 = default 256) */
-  int window_cap;        /* max x-window columns staged per tile: 256..8192 (0 = 2048) */
-  int long_row_words;    /* rows coded in more words than this are processed by a whole block (0 = 192) */
-  int interval_mode;     /* 0 = interval sums from a per-tile prefix of x; 1 = direct sums */
+  int tile_rows;         /* rows per tile (one wavefront each): 8..64 (0 = 64) */
+  int window_cap;        /* max x-window columns staged per tile: 64..8192 (0 = 512) */
+  int stage_bytes;       /* max entry-stream bytes staged in LDS per tile: 512..16384 (0 = 4096) */
+  int long_row_bytes;    /* rows staging more than this are summed by the whole wave (0 = stage_bytes/2) */
+  int interval_mode;     /* 0 = intervals summed entry by entry from the LDS window (default);
+                            1 = interval sums from a per-tile prefix of x, P[s+len] - P[s] */
   int autotune;          /* 1 = time candidate layouts at load and keep the fastest */
   int keep_lists;        /* 1 = keep the decoded lists on the host (export, CSR baseline) */
   int nthreads;          /* host decode / layout threads (0 = hardware concurrency, max 16) */
@@ -145,10 +147,11 @@ typedef struct {
   int64_t diff_rows, direct_rows, long_rows;
   int64_t escapes;          /* entries outside their tile's x window */
   int64_t ntiles;
-  int64_t layout_bytes;     /* device bytes of the layout (tiles + row info + words + long entries) */
+  int64_t layout_bytes;     /* device bytes of the layout (tiles, row info, entry streams, long rows) */
   int64_t stream_bytes;     /* size of the input bitstream */
+  int64_t n_singles, n_wide, n_intervals;  /* entries of the three per-tile streams */
   int W, R, Lmin, zeta_k;
-  int tile_rows, window_cap, long_row_words, interval_mode;
+  int tile_rows, window_cap, stage_bytes, long_row_bytes, interval_mode;
   int max_level;            /* deepest reuse level in the layout (<= R) */
   int ngraphs;              /* 1, or the member count of a group */
 } bvmv_info;

@@ -32,7 +32,8 @@ class BvmvError(RuntimeError):
 
 class LoadOpts(ctypes.Structure):
     _fields_ = [("device", ctypes.c_int), ("tile_rows", ctypes.c_int), ("window_cap", ctypes.c_int),
-                ("long_row_words", ctypes.c_int), ("interval_mode", ctypes.c_int), ("autotune", ctypes.c_int),
+                ("stage_bytes", ctypes.c_int), ("long_row_bytes", ctypes.c_int), ("interval_mode", ctypes.c_int),
+                ("autotune", ctypes.c_int),
                 ("keep_lists", ctypes.c_int), ("nthreads", ctypes.c_int), ("device_mem_budget", ctypes.c_uint64)]
 
 
@@ -48,9 +49,10 @@ class PRResult(ctypes.Structure):
 class Info(ctypes.Structure):
     _fields_ = [(f, ctypes.c_int64) for f in ("n", "m", "m_prime", "units", "diff_rows", "direct_rows",
                                                "long_rows", "escapes", "ntiles", "layout_bytes",
-                                               "stream_bytes")] + \
+                                               "stream_bytes", "n_singles", "n_wide", "n_intervals")] + \
                [(f, ctypes.c_int) for f in ("W", "R", "Lmin", "zeta_k", "tile_rows", "window_cap",
-                                            "long_row_words", "interval_mode", "max_level", "ngraphs")]
+                                            "stage_bytes", "long_row_bytes", "interval_mode", "max_level",
+                                            "ngraphs")]
 
     def as_dict(self):
         return {f: getattr(self, f) for f, _ in self._fields_}
@@ -176,12 +178,12 @@ def _as_u8(data):
     return arr
 
 
-def bvmv_load(bitstream, device=0, tile_rows=0, window_cap=0, long_row_words=0, interval_mode=0, autotune=0,
-              keep_lists=0, nthreads=0, device_mem_budget=0) -> Graph:
+def bvmv_load(bitstream, device=0, tile_rows=0, window_cap=0, stage_bytes=0, long_row_bytes=0, interval_mode=0,
+              autotune=0, keep_lists=0, nthreads=0, device_mem_budget=0) -> Graph:
     lib = load_library()
     data = _as_u8(bitstream)
-    o = LoadOpts(device, tile_rows, window_cap, long_row_words, interval_mode, autotune, keep_lists, nthreads,
-                 device_mem_budget)
+    o = LoadOpts(device, tile_rows, window_cap, stage_bytes, long_row_bytes, interval_mode, autotune, keep_lists,
+                 nthreads, device_mem_budget)
     h = ctypes.c_void_p()
     _check(lib.bvmv_load(data.ctypes.data, data.size, ctypes.byref(o), ctypes.byref(h)))
     info = Info()
@@ -317,13 +319,13 @@ def bvmv_csr_pagerank(c: Csr, p_out, teleport=None, start=None, damping=0.85, to
     return (res[0].iters, bool(res[0].converged), res[0].residual)
 
 
-def bvmv_layout_selfcheck(bitstream, x, tile_rows=0, window_cap=0, long_row_words=0):
+def bvmv_layout_selfcheck(bitstream, x, tile_rows=0, window_cap=0, stage_bytes=0, long_row_bytes=0):
     """Host interpretation of the device layout (test aid): y = A x in double."""
     data = _as_u8(bitstream)
     x = np.ascontiguousarray(x, dtype=np.float64)
     y = np.zeros_like(x)
     stats = np.zeros(9, dtype=np.int64)
-    o = LoadOpts(0, tile_rows, window_cap, long_row_words, 0, 0, 0, 0, 0)
+    o = LoadOpts(0, tile_rows, window_cap, stage_bytes, long_row_bytes, 0, 0, 0, 0, 0)
     _check(load_library().bvmv_layout_selfcheck(data.ctypes.data, data.size, ctypes.byref(o), x.ctypes.data,
                                                 y.ctypes.data, stats.ctypes.data))
     keys = ["ntiles", "units", "diff_rows", "direct_rows", "long_rows", "escapes", "layout_bytes", "m_prime",

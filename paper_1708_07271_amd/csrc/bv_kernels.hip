@@ -1,19 +1,27 @@
 // HIP kernels for the reuse product on the tiled layout, the plain CSR
-// baseline, and the fused PageRank iteration.  gfx950, wave64, 256 threads.
+// baseline, the fused PageRank iteration and the multi-vector product.
+// gfx950, wave64.
 //
-// One block per tile.  A tile's rows are either direct or reuse the sum of a
-// reference row inside the same tile (y_i = y_{r_i} + sum_j A'_ij x_j, the
-// algorithm after the Proposition of Section "Our Approach"), so no data
-// crosses tiles and the kernel needs no grid-wide synchronisation:
-//   1. row info -> LDS, block scan of row lengths -> per-row word offsets,
-//      list of long rows, deepest level;
-//   2. the tile's 16-bit words and its x window -> LDS (coalesced), and with
-//      prefix mode the exclusive prefix P of the window in double (block
-//      scan), so an interval [s, s+len) costs P[s+len] - P[s];
-//   3. one thread per short row walks its words, a whole block sums each
-//      long row (fixed-shape tree: deterministic);
-//   4. levels 1..max: y_i = y_{i-g_i} + partial_i in LDS;
-//   5. epilogue: store y, or the PageRank update.
+// Single-vector kernels: a tile of up to 64 rows is processed by one
+// wavefront, one row per lane, with no block-wide barrier; a 256-thread
+// block holds 4 consecutive tiles.  A tile's rows are direct or reuse the
+// sum of a reference row inside the same tile (y_i = y_{r_i} +
+// sum_j A'_ij x_j, the algorithm after the Proposition of Section "Our
+// Approach"), so tiles are independent:
+//   1. every global load of the tile is issued at once: the lane's row info,
+//      the three entry streams (16-byte vectors), the x window;
+//   2. a wave scan of the per-row counts gives the stream offsets; with
+//      prefix mode an exclusive prefix P of the window (double) turns an
+//      interval [s, s+len) into P[s+len] - P[s];
+//   3. singles and wide entries are summed by merge-style flat passes: each
+//      lane takes an equal contiguous chunk of entries whatever the row
+//      lengths, and a row split over several lanes is completed by its
+//      owning lane, which adds the later lanes' pieces in lane order
+//      (deterministic);
+//   4. each lane adds its row's intervals; long rows are summed by the whole
+//      wave (fixed reduction tree);
+//   5. reuse levels 1..max: y_i = y_{i-g_i} + partial_i in LDS;
+//   6. epilogue: store y, or the PageRank update.
 #include <hip/hip_runtime.h>
 
 #include "kernels.hpp"
@@ -23,20 +31,15 @@ namespace {
 
 constexpr int kThreads = 256;
 constexpr int kWaves = kThreads / 64;
+static_assert(kWaves == kTilesPerBlock, "one tile per wavefront");
 
 // ------------------------------------------------------------ precision modes
 struct Pair {
   float hi, lo;
 };
 
-// Knuth's TwoSum: s + e == a + b exactly; the error is folded into lo.
-__device__ __forceinline__ void two_sum_into(Pair& a, float v) {
-  const float s = a.hi + v;
-  const float bp = s - a.hi;
-  const float e = (a.hi - (s - bp)) + (v - bp);
-  a.hi = s;
-  a.lo += e;
-}
+// Knuth's TwoSum on the reuse chain: s + e == a + b exactly, then the pair is
+// renormalised.
 __device__ __forceinline__ Pair pair_add(Pair a, Pair b) {
   const float s = a.hi + b.hi;
   const float bp = s - a.hi;
@@ -46,61 +49,191 @@ __device__ __forceinline__ Pair pair_add(Pair a, Pair b) {
   return Pair{hi, e - (hi - s)};
 }
 
+// PAcc accumulates a row's partial sum; CAcc carries sums along reuse chains.
 struct MF64 {
   using X = double;
-  using Acc = double;
+  using PAcc = double;
+  using CAcc = double;
   static constexpr bool kInt = false;
-  __device__ static Acc zero() { return 0.0; }
-  __device__ static void add(Acc& a, X v) { a += v; }
-  __device__ static void add_d(Acc& a, double v) { a += v; }
-  __device__ static Acc comb(Acc a, Acc b) { return a + b; }
-  __device__ static X out(Acc a) { return a; }
-  __device__ static double to_d(Acc a) { return a; }
-  __device__ static Acc shfl_down(Acc a, int d) { return __shfl_down(a, d, 64); }
+  __device__ static PAcc pzero() { return 0.0; }
+  __device__ static void padd(PAcc& a, X v) { a += v; }
+  __device__ static void padd_d(PAcc& a, double v) { a += v; }
+  __device__ static PAcc pcomb(PAcc a, PAcc b) { return a + b; }
+  __device__ static PAcc pshfl_down(PAcc a, int d) { return __shfl_down(a, d, 64); }
+  __device__ static PAcc pbcast(PAcc a, int l) { return __shfl(a, l, 64); }
+  __device__ static CAcc chain(PAcc a) { return a; }
+  __device__ static CAcc comb(CAcc a, CAcc b) { return a + b; }
+  __device__ static X out(CAcc a) { return a; }
+  __device__ static double to_d(CAcc a) { return a; }
 };
+// float everywhere: the naive mode
 struct MF32 {
   using X = float;
-  using Acc = float;
+  using PAcc = float;
+  using CAcc = float;
   static constexpr bool kInt = false;
-  __device__ static Acc zero() { return 0.0f; }
-  __device__ static void add(Acc& a, X v) { a += v; }
-  __device__ static void add_d(Acc& a, double v) { a += float(v); }
-  __device__ static Acc comb(Acc a, Acc b) { return a + b; }
-  __device__ static X out(Acc a) { return a; }
-  __device__ static double to_d(Acc a) { return a; }
-  __device__ static Acc shfl_down(Acc a, int d) { return __shfl_down(a, d, 64); }
+  __device__ static PAcc pzero() { return 0.0f; }
+  __device__ static void padd(PAcc& a, X v) { a += v; }
+  __device__ static void padd_d(PAcc& a, double v) { a += float(v); }
+  __device__ static PAcc pcomb(PAcc a, PAcc b) { return a + b; }
+  __device__ static PAcc pshfl_down(PAcc a, int d) { return __shfl_down(a, d, 64); }
+  __device__ static PAcc pbcast(PAcc a, int l) { return __shfl(a, l, 64); }
+  __device__ static CAcc chain(PAcc a) { return a; }
+  __device__ static CAcc comb(CAcc a, CAcc b) { return a + b; }
+  __device__ static X out(CAcc a) { return a; }
+  __device__ static double to_d(CAcc a) { return a; }
 };
+// float vectors; a row's partial in double (one add per entry), reuse chains
+// as (hi, lo) float pairs with TwoSum compensation
 struct MF32C {
   using X = float;
-  using Acc = Pair;
+  using PAcc = double;
+  using CAcc = Pair;
   static constexpr bool kInt = false;
-  __device__ static Acc zero() { return Pair{0.0f, 0.0f}; }
-  __device__ static void add(Acc& a, X v) { two_sum_into(a, v); }
-  __device__ static void add_d(Acc& a, double v) {
-    const float h = float(v);
-    two_sum_into(a, h);
-    a.lo += float(v - double(h));
+  __device__ static PAcc pzero() { return 0.0; }
+  __device__ static void padd(PAcc& a, X v) { a += double(v); }
+  __device__ static void padd_d(PAcc& a, double v) { a += v; }
+  __device__ static PAcc pcomb(PAcc a, PAcc b) { return a + b; }
+  __device__ static PAcc pshfl_down(PAcc a, int d) { return __shfl_down(a, d, 64); }
+  __device__ static PAcc pbcast(PAcc a, int l) { return __shfl(a, l, 64); }
+  __device__ static CAcc chain(PAcc a) {
+    const float h = float(a);
+    return Pair{h, float(a - double(h))};
   }
-  __device__ static Acc comb(Acc a, Acc b) { return pair_add(a, b); }
-  __device__ static X out(Acc a) { return a.hi + a.lo; }
-  __device__ static double to_d(Acc a) { return double(a.hi) + double(a.lo); }
-  __device__ static Acc shfl_down(Acc a, int d) {
-    return Pair{__shfl_down(a.hi, d, 64), __shfl_down(a.lo, d, 64)};
-  }
+  __device__ static CAcc comb(CAcc a, CAcc b) { return pair_add(a, b); }
+  __device__ static X out(CAcc a) { return a.hi + a.lo; }
+  __device__ static double to_d(CAcc a) { return double(a.hi) + double(a.lo); }
 };
-// integer counting (x = 1): degrees by reuse
+// integer counting with x = 1: degrees by reuse
 struct MINT {
   using X = int32_t;
-  using Acc = int32_t;
+  using PAcc = int32_t;
+  using CAcc = int32_t;
   static constexpr bool kInt = true;
-  __device__ static Acc zero() { return 0; }
-  __device__ static void add(Acc& a, X v) { a += v; }
-  __device__ static void add_d(Acc& a, double v) { a += int32_t(v); }
-  __device__ static Acc comb(Acc a, Acc b) { return a + b; }
-  __device__ static X out(Acc a) { return a; }
-  __device__ static double to_d(Acc a) { return a; }
-  __device__ static Acc shfl_down(Acc a, int d) { return __shfl_down(a, d, 64); }
+  __device__ static PAcc pzero() { return 0; }
+  __device__ static void padd(PAcc& a, X v) { a += v; }
+  __device__ static void padd_d(PAcc& a, double v) { a += int32_t(v); }
+  __device__ static PAcc pcomb(PAcc a, PAcc b) { return a + b; }
+  __device__ static PAcc pshfl_down(PAcc a, int d) { return __shfl_down(a, d, 64); }
+  __device__ static PAcc pbcast(PAcc a, int l) { return __shfl(a, l, 64); }
+  __device__ static CAcc chain(PAcc a) { return a; }
+  __device__ static CAcc comb(CAcc a, CAcc b) { return a + b; }
+  __device__ static X out(CAcc a) { return a; }
+  __device__ static double to_d(CAcc a) { return a; }
 };
+
+__host__ __device__ constexpr size_t align16(size_t v) { return (v + 15) & ~size_t(15); }
+__device__ __forceinline__ uint32_t dalign16u(uint32_t b) { return (b + 15u) & ~15u; }
+// staged stream bytes of a tile (same sum as tile_stage_bytes on the host)
+__device__ __forceinline__ uint32_t dstage_bytes(const TileDesc& t) {
+  return dalign16u(t.n16 * 2u) + dalign16u(t.nwide * 4u) + dalign16u(t.nint * 4u);
+}
+
+// ------------------------------------------------------------- wave helpers
+// LDS written by some lanes of a wave and read by others: keep the order.
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+__device__ __forceinline__ uint32_t lane_id() { return threadIdx.x & 63u; }
+
+__device__ __forceinline__ uint64_t wave_excl_scan_u64(uint64_t v, uint64_t& total) {
+  const uint32_t lane = lane_id();
+  uint64_t inc = v;
+#pragma unroll
+  for (int d = 1; d < 64; d <<= 1) {
+    const uint64_t t = __shfl_up(inc, d, 64);
+    if (lane >= uint32_t(d)) inc += t;
+  }
+  total = __shfl(inc, 63, 64);
+  return inc - v;
+}
+
+__device__ __forceinline__ double wave_excl_scan_f64(double v, double& total) {
+  const uint32_t lane = lane_id();
+  double inc = v;
+#pragma unroll
+  for (int d = 1; d < 64; d <<= 1) {
+    const double t = __shfl_up(inc, d, 64);
+    if (lane >= uint32_t(d)) inc += t;
+  }
+  total = __shfl(inc, 63, 64);
+  return inc - v;
+}
+
+// fixed shuffle tree, result broadcast to all lanes
+template <class M>
+__device__ __forceinline__ typename M::PAcc wave_reduce(typename M::PAcc a) {
+#pragma unroll
+  for (int d = 32; d >= 1; d >>= 1) a = M::pcomb(a, M::pshfl_down(a, d));
+  return M::pbcast(a, 0);
+}
+
+__device__ __forceinline__ double wave_sum_f64(double a) {
+#pragma unroll
+  for (int d = 32; d >= 1; d >>= 1) a += __shfl_down(a, d, 64);
+  return __shfl(a, 0, 64);
+}
+
+// One wave copies nbytes (a multiple of 16) from global to LDS with 16-byte
+// vector loads; each lane issues kBatch loads before its first LDS write, so
+// a tile pays one memory round trip, not one per loop turn.  src and dst are
+// 16-byte aligned.
+template <int kBatch>
+__device__ __forceinline__ void wave_copy16(const void* __restrict__ src, void* dst, uint32_t nbytes) {
+  const uint32_t lane = lane_id();
+  const uint32_t nv = nbytes / 16;
+  const uint4* s = static_cast<const uint4*>(src);
+  uint4* d = static_cast<uint4*>(dst);
+  for (uint32_t base = 0; base < nv; base += 64 * kBatch) {
+    uint4 r[kBatch];
+#pragma unroll
+    for (int j = 0; j < kBatch; ++j) {
+      const uint32_t k = base + lane + 64u * j;
+      if (k < nv) r[j] = s[k];
+    }
+#pragma unroll
+    for (int j = 0; j < kBatch; ++j) {
+      const uint32_t k = base + lane + 64u * j;
+      if (k < nv) d[k] = r[j];
+    }
+  }
+}
+
+// Stage elements [first, first + count) of a global array of `len` elements
+// into the LDS buffer `buf` (room for count + 16 bytes); returns the LDS
+// address of element `first`.  Whole 16-byte vectors when the array is
+// aligned and they stay inside it, else batched element loads.
+template <class T>
+__device__ __forceinline__ T* stage_range(const T* __restrict__ arr, uint64_t len, int64_t first, uint32_t count,
+                                          T* buf) {
+  constexpr uint32_t V = 16 / sizeof(T);
+  const int64_t a0 = first & ~int64_t(V - 1);
+  const uint32_t shift = uint32_t(first - a0);
+  const uint32_t total = shift + count;
+  const uint32_t vec_elems = (total + V - 1) / V * V;
+  if ((reinterpret_cast<uintptr_t>(arr) & 15u) == 0 && uint64_t(a0) + vec_elems <= len) {
+    wave_copy16<4>(arr + a0, buf, vec_elems * uint32_t(sizeof(T)));
+  } else {
+    const uint32_t lane = lane_id();
+    for (uint32_t base = 0; base < total; base += 64 * 8) {
+      T r[8];
+#pragma unroll
+      for (int j = 0; j < 8; ++j) {
+        const uint32_t k = base + lane + 64u * j;
+        if (k < total) r[j] = arr[a0 + k];
+      }
+#pragma unroll
+      for (int j = 0; j < 8; ++j) {
+        const uint32_t k = base + lane + 64u * j;
+        if (k < total) buf[k] = r[j];
+      }
+    }
+  }
+  return buf + shift;
+}
 
 // ------------------------------------------------------------- block helpers
 __device__ __forceinline__ uint64_t block_excl_scan_u64(uint64_t v, uint64_t* s_tmp, uint64_t& total) {
@@ -125,43 +258,6 @@ __device__ __forceinline__ uint64_t block_excl_scan_u64(uint64_t v, uint64_t* s_
   return base + inc - v;
 }
 
-__device__ __forceinline__ double block_excl_scan_f64(double v, double* s_tmp, double& total) {
-  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-  double inc = v;
-#pragma unroll
-  for (int d = 1; d < 64; d <<= 1) {
-    const double t = __shfl_up(inc, d, 64);
-    if (lane >= d) inc += t;
-  }
-  if (lane == 63) s_tmp[wid] = inc;
-  __syncthreads();
-  double base = 0.0, tot = 0.0;
-#pragma unroll
-  for (int w = 0; w < kWaves; ++w) {
-    const double s = s_tmp[w];
-    if (w < wid) base += s;
-    tot += s;
-  }
-  __syncthreads();
-  total = tot;
-  return base + (inc - v);
-}
-
-// Deterministic block reduction (fixed shuffle tree, waves combined in order).
-template <class M>
-__device__ __forceinline__ typename M::Acc block_reduce(typename M::Acc a, typename M::Acc* s_red) {
-  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-#pragma unroll
-  for (int d = 32; d >= 1; d >>= 1) a = M::comb(a, M::shfl_down(a, d));
-  if (lane == 0) s_red[wid] = a;
-  __syncthreads();
-  typename M::Acc r = s_red[0];
-#pragma unroll
-  for (int w = 1; w < kWaves; ++w) r = M::comb(r, s_red[w]);
-  __syncthreads();
-  return r;
-}
-
 __device__ __forceinline__ double block_sum_f64(double a, double* s_red) {
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
 #pragma unroll
@@ -175,51 +271,157 @@ __device__ __forceinline__ double block_sum_f64(double a, double* s_red) {
   return r;
 }
 
-__host__ __device__ constexpr size_t align16(size_t v) { return (v + 15) & ~size_t(15); }
+// Merge-style flat pass of one wave over E entries of a stream split into
+// rows by the exclusive offsets off[0..nrows] (off[nrows] == E).  Lane l sums
+// entries [l*C, (l+1)*C), C = ceil(E/64), cutting at row ends; it adds the
+// pieces of rows that start in its chunk to part[], and keeps the first piece
+// of a row begun by an earlier lane in carry[l].  The lane owning a row that
+// runs past its chunk then adds the following lanes' pieces in lane order,
+// so the result does not depend on scheduling.
+template <class M, class ValFn>
+__device__ __forceinline__ void flat_pass_wave(uint32_t E, uint32_t nrows, const uint32_t* off,
+                                               typename M::PAcc* part, typename M::PAcc* carry, ValFn val) {
+  using PAcc = typename M::PAcc;
+  const uint32_t lane = lane_id();
+  const uint32_t C = (E + 63) / 64;
+  const uint32_t b = min(E, lane * C), end = min(E, b + C);
+  uint32_t own = 0xFFFFFFFFu;  // row owned here that continues past `end`
+  if (b < end) {
+    uint32_t lo = 0, hi = nrows;  // off[lo] <= b < off[hi]
+    while (hi - lo > 1) {
+      const uint32_t mid = (lo + hi) >> 1;
+      if (off[mid] <= b) lo = mid;
+      else hi = mid;
+    }
+    uint32_t r = lo, e = b;
+    bool owner = off[r] == b;
+    while (e < end) {
+      const uint32_t rend = off[r + 1];
+      const uint32_t stop = min(rend, end);
+      PAcc a = M::pzero();
+      for (; e < stop; ++e) M::padd(a, val(e));
+      if (owner) {
+        part[r] = M::pcomb(part[r], a);
+        if (rend > end) own = r;
+      } else {
+        carry[lane] = a;
+      }
+      owner = true;
+      ++r;
+      while (r < nrows && off[r + 1] == e) ++r;  // rows without entries here
+    }
+  }
+  wave_sync();
+  if (own != 0xFFFFFFFFu) {
+    const uint32_t rend = off[own + 1];
+    PAcc s = part[own];
+    for (uint32_t l = lane + 1; l * C < rend; ++l) s = M::pcomb(s, carry[l]);
+    part[own] = s;
+  }
+  wave_sync();
+}
 
-// LDS carve of the tile kernel
+// per-wave LDS carve of the tile kernel (bytes from the wave's base)
 template <class M, bool PREFIX>
-struct Carve {
+struct WaveCarve {
   using X = typename M::X;
-  using Acc = typename M::Acc;
-  __host__ __device__ static size_t info(uint32_t) { return 0; }
-  __host__ __device__ static size_t off(uint32_t t) { return align16(size_t(t) * 4); }
-  __host__ __device__ static size_t list(uint32_t t) { return off(t) + align16(size_t(t) * 4); }
-  __host__ __device__ static size_t part(uint32_t t) { return list(t) + align16(size_t(t) * 4); }
-  __host__ __device__ static size_t y(uint32_t t) { return part(t) + align16(size_t(t) * sizeof(Acc)); }
-  __host__ __device__ static size_t x(uint32_t t) { return y(t) + align16(size_t(t) * sizeof(Acc)); }
-  __host__ __device__ static size_t P(uint32_t t, uint32_t w) {
-    return x(t) + (M::kInt ? 0 : align16(size_t(w) * sizeof(X)));
-  }
-  __host__ __device__ static size_t words(uint32_t t, uint32_t w) {
-    return P(t, w) + (PREFIX ? align16((size_t(w) + 1) * 8) : 0);
-  }
-  __host__ __device__ static size_t red(uint32_t t, uint32_t w, uint32_t e) {
-    return words(t, w) + align16((size_t(e) + 16) * 2);
-  }
-  __host__ __device__ static size_t total(uint32_t t, uint32_t w, uint32_t e) { return red(t, w, e) + 256; }
+  using PAcc = typename M::PAcc;
+  using CAcc = typename M::CAcc;
+  uint32_t WC, SB;
+  __host__ __device__ static constexpr size_t off16() { return 0; }
+  __host__ __device__ static constexpr size_t offw() { return align16(65 * 4); }
+  // y shares the partials' slots: each lane reads its own partial before it
+  // writes its own y, and other lanes' y are read only after a wave_sync
+  static constexpr size_t kSlot = sizeof(PAcc) > sizeof(CAcc) ? sizeof(PAcc) : sizeof(CAcc);
+  __host__ __device__ static constexpr size_t part() { return 2 * align16(65 * 4); }
+  __host__ __device__ static constexpr size_t y() { return part(); }
+  __host__ __device__ static constexpr size_t carry() { return part() + align16(64 * kSlot); }
+  __host__ __device__ static constexpr size_t x() { return carry() + align16(64 * sizeof(PAcc)); }
+  __host__ __device__ size_t P() const { return x() + (M::kInt ? 0 : align16(size_t(WC) * sizeof(X) + 16)); }
+  __host__ __device__ size_t data() const { return P() + (PREFIX && !M::kInt ? align16((size_t(WC) + 1) * 8) : 0); }
+  __host__ __device__ size_t wave_bytes() const { return data() + align16(size_t(SB)); }
+  __host__ __device__ size_t block_bytes() const { return kWaves * wave_bytes() + 256; }
 };
 
 struct TileCtx {
-  uint32_t row0, nrows, graph, tile;
+  uint32_t row0, nrows, graph;
 };
 
 // ---------------------------------------------------------------- epilogues
+// Called by every wave of the block (a wave may have no rows).
 template <class M>
 struct EpiStore {
   typename M::X* y;
-  __device__ void operator()(const TileCtx& tc, const typename M::Acc* s_y, unsigned char*) const {
-    for (uint32_t r = threadIdx.x; r < tc.nrows; r += kThreads) y[tc.row0 + r] = M::out(s_y[r]);
+  __device__ void operator()(const TileCtx& tc, const typename M::CAcc* s_y, unsigned char*) const {
+    const uint32_t lane = lane_id();
+    if (lane < tc.nrows) y[tc.row0 + lane] = M::out(s_y[lane]);
   }
 };
 
-// PageRank update of Eq. (1) with dangling mass sent to the teleport vector,
-// then residual and dangling partials, then the member's last block folds
-// the per-tile partials (fixed order) into the member state.
+// The block's residual and dangling partials go to its slot; the member's
+// last block folds all its blocks' slots in a fixed order into the state.
+__device__ __forceinline__ void pr_block_finish(double rs, double dg, PRState* st, double* slots, int with_resid,
+                                                double tol, int32_t max_iter, int32_t buf, unsigned char* s_blk) {
+  double* blk = reinterpret_cast<double*>(s_blk);
+  __shared__ int s_last;
+  const uint32_t wave = threadIdx.x >> 6, lane = lane_id();
+  if (lane == 0) {
+    blk[2 * wave] = rs;
+    blk[2 * wave + 1] = dg;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double R = blk[0], D = blk[1];
+    for (int w = 1; w < kWaves; ++w) {
+      R += blk[2 * w];
+      D += blk[2 * w + 1];
+    }
+    slots[2 * size_t(blockIdx.x)] = R;
+    slots[2 * size_t(blockIdx.x) + 1] = D;
+    __threadfence();
+    const uint32_t prev = atomicAdd(&st->ticket, 1u);
+    s_last = prev + 1 == st->blk_hi - st->blk_lo;
+  }
+  __syncthreads();
+  if (!s_last) return;
+  __threadfence();
+  double R = 0.0, D = 0.0;
+  for (uint32_t t = st->blk_lo + threadIdx.x; t < st->blk_hi; t += kThreads) {
+    R += __builtin_nontemporal_load(&slots[2 * size_t(t)]);
+    D += __builtin_nontemporal_load(&slots[2 * size_t(t) + 1]);
+  }
+  R = block_sum_f64(R, blk + 8);
+  D = block_sum_f64(D, blk + 8);
+  if (threadIdx.x == 0) {
+    st->delta = D;
+    st->ticket = 0;
+    if (with_resid) {
+      st->resid = R;
+      st->iter += 1;
+      if (R < tol) {
+        st->done = 1;
+        st->converged = 1;
+        st->final_buf = buf;
+      } else if (st->iter >= max_iter) {
+        st->done = 1;
+        st->final_buf = buf;
+      }
+    } else {
+      st->resid = 0.0;
+      st->iter = 0;
+      st->done = 0;
+      st->converged = 0;
+      st->final_buf = 0;
+    }
+    __threadfence();
+  }
+}
+
+// PageRank update of Eq. (1), dangling mass sent to the teleport vector.
 template <class M>
 struct EpiPR {
   PRArgs a;
-  __device__ void operator()(const TileCtx& tc, const typename M::Acc* s_y, unsigned char* scratch) const {
+  __device__ void operator()(const TileCtx& tc, const typename M::CAcc* s_y, unsigned char* s_blk) const {
     using X = typename M::X;
     const X* p = static_cast<const X*>(a.p_cur);
     X* pn = static_cast<X*>(a.p_new);
@@ -228,246 +430,189 @@ struct EpiPR {
     PRState* st = a.st + tc.graph;
     const double delta = st->delta, inv_n = st->inv_n, beta = a.beta;
     double rs = 0.0, dg = 0.0;
-    for (uint32_t r = threadIdx.x; r < tc.nrows; r += kThreads) {
-      const uint32_t v = tc.row0 + r;
-      const double y = M::to_d(s_y[r]);
+    const uint32_t lane = lane_id();
+    if (lane < tc.nrows) {
+      const uint32_t v = tc.row0 + lane;
+      const double y = M::to_d(s_y[lane]);
       const double t = tele ? double(tele[v]) : inv_n;
       const X pnew = X((1.0 - beta) * t + beta * (y + delta * t));
       pn[v] = pnew;
       const int32_t d = a.outdeg[v];
       zn[v] = d > 0 ? pnew / X(d) : X(0);
-      rs += fabs(double(pnew) - double(p[v]));
-      if (d == 0) dg += double(pnew);
+      rs = fabs(double(pnew) - double(p[v]));
+      if (d == 0) dg = double(pnew);
     }
-    double* s_red = reinterpret_cast<double*>(scratch);
-    rs = block_sum_f64(rs, s_red);
-    dg = block_sum_f64(dg, s_red);
-    __shared__ int s_last;
-    if (threadIdx.x == 0) {
-      a.slots[2 * size_t(tc.tile)] = rs;
-      a.slots[2 * size_t(tc.tile) + 1] = dg;
-      __threadfence();
-      const uint32_t prev = atomicAdd(&st->ticket, 1u);
-      s_last = prev + 1 == st->tile_hi - st->tile_lo;
-    }
-    __syncthreads();
-    if (!s_last) return;
-    __threadfence();
-    double R = 0.0, D = 0.0;
-    for (uint32_t t = st->tile_lo + threadIdx.x; t < st->tile_hi; t += kThreads) {
-      R += __builtin_nontemporal_load(&a.slots[2 * size_t(t)]);
-      D += __builtin_nontemporal_load(&a.slots[2 * size_t(t) + 1]);
-    }
-    R = block_sum_f64(R, s_red);
-    D = block_sum_f64(D, s_red);
-    if (threadIdx.x == 0) {
-      st->resid = R;
-      st->delta = D;
-      st->iter += 1;
-      st->ticket = 0;
-      if (R < a.tol) {
-        st->done = 1;
-        st->converged = 1;
-        st->final_buf = a.buf;
-      } else if (st->iter >= a.max_iter) {
-        st->done = 1;
-        st->final_buf = a.buf;
-      }
-      __threadfence();
-    }
+    rs = wave_sum_f64(rs);
+    dg = wave_sum_f64(dg);
+    pr_block_finish(rs, dg, st, a.slots, 1, a.tol, a.max_iter, a.buf, s_blk);
   }
 };
 
 // --------------------------------------------------------------- tile kernel
-template <class M, bool PREFIX>
-__device__ __forceinline__ typename M::Acc short_row(const uint16_t* w, uint32_t len, const typename M::X* sx,
-                                                     const double* sP, const typename M::X* __restrict__ x,
-                                                     int64_t win0) {
-  using X = typename M::X;
-  typename M::Acc a = M::zero();
-  uint32_t k = 0;
-  while (k < len) {
-    const uint32_t wd = w[k++];
-    const bool neg = wd & 0x8000u;
-    const uint32_t off = wd & 0x3FFFu;
-    if (wd & 0x4000u) {
-      const uint32_t ln = w[k++];
-      if constexpr (M::kInt) {
-        M::add(a, neg ? -int32_t(ln) : int32_t(ln));
-      } else if constexpr (PREFIX) {
-        const double d = sP[off + ln] - sP[off];
-        M::add_d(a, neg ? -d : d);
-      } else {
-        for (uint32_t t = 0; t < ln; ++t) {
-          const X v = sx[off + t];
-          M::add(a, neg ? -v : v);
-        }
-      }
-    } else {
-      X v;
-      if constexpr (M::kInt) {
-        if (off == kEscape) k += 2;
-        v = 1;
-      } else if (off == kEscape) {
-        const int32_t rel = int32_t((uint32_t(w[k]) << 16) | uint32_t(w[k + 1]));
-        k += 2;
-        v = x[win0 + rel];
-      } else {
-        v = sx[off];
-      }
-      M::add(a, neg ? -v : v);
-    }
-  }
-  return a;
-}
-
-// Steps 1-2 shared by the single- and multi-vector kernels: row info ->
-// LDS, per-row offsets (short rows: word offset; long rows: entry offset),
-// the list of long rows, the deepest level, and the tile's words -> LDS.
-struct RowsStaged {
-  uint32_t nlong, maxlvl;
-};
-__device__ __forceinline__ RowsStaged stage_rows(const DevLayout& L, const TileDesc& td, uint32_t* s_info,
-                                                 uint32_t* s_off, uint32_t* s_list, uint16_t* s_w,
-                                                 unsigned char* s_red) {
-  __shared__ uint32_t s_nlong, s_maxlvl;
-  const uint32_t tid = threadIdx.x;
-  const uint32_t nrows = td.nrows;
-  // packed per-thread sums: short words | long count << 24 | long entries << 34
-  const uint32_t per = (L.tcap + kThreads - 1) / kThreads;
-  const uint32_t r_begin = tid * per;
-  uint64_t local = 0;
-  uint32_t lvl_max = 0;
-  for (uint32_t q = 0; q < per; ++q) {
-    const uint32_t r = r_begin + q;
-    if (r < nrows) {
-      const uint32_t inf = L.info[td.row0 + r];
-      s_info[r] = inf;
-      const uint64_t len = inf >> 9;
-      local += (inf & kInfoLong) ? ((uint64_t(1) << 24) | (len << 34)) : len;
-      lvl_max = max(lvl_max, (inf >> 4) & 15u);
-    }
-  }
-  if (tid == 0) s_maxlvl = 0;
-  __syncthreads();
-  if (lvl_max) atomicMax(&s_maxlvl, lvl_max);
-  uint64_t total;
-  uint64_t run = block_excl_scan_u64(local, reinterpret_cast<uint64_t*>(s_red), total);
-  for (uint32_t q = 0; q < per; ++q) {
-    const uint32_t r = r_begin + q;
-    if (r < nrows) {
-      const uint32_t inf = s_info[r];
-      const uint64_t len = inf >> 9;
-      if (inf & kInfoLong) {
-        s_off[r] = uint32_t(run >> 34);
-        s_list[(run >> 24) & 1023u] = r;
-        run += (uint64_t(1) << 24) | (len << 34);
-      } else {
-        s_off[r] = uint32_t(run & 0xFFFFFFu);
-        run += len;
-      }
-    }
-  }
-  if (tid == 0) s_nlong = uint32_t((total >> 24) & 1023u);
-  {
-    const uint4* src = reinterpret_cast<const uint4*>(L.words + td.word0);
-    uint4* dst = reinterpret_cast<uint4*>(s_w);
-    const uint32_t nv = (td.nwords + 7) / 8;
-    for (uint32_t k = tid; k < nv; k += kThreads) dst[k] = src[k];
-  }
-  __syncthreads();
-  return RowsStaged{s_nlong, s_maxlvl};
-}
-
 template <class M, bool PREFIX, class Epi>
-__global__ void __launch_bounds__(kThreads) bv_tile_kernel(DevLayout L, const typename M::X* __restrict__ x,
+__global__ void __launch_bounds__(kThreads) bv_wave_kernel(DevLayout L, const typename M::X* __restrict__ x,
                                                            Epi epi, const PRState* __restrict__ skip_done) {
   using X = typename M::X;
-  using Acc = typename M::Acc;
-  using C = Carve<M, PREFIX>;
+  using PAcc = typename M::PAcc;
+  using CAcc = typename M::CAcc;
   extern __shared__ __align__(16) unsigned char smem[];
-  const uint32_t tile = blockIdx.x;
+  const uint32_t wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const uint32_t lane = lane_id();
+  const uint32_t tile = blockIdx.x * kWaves + wave;
   const TileDesc td = L.tiles[tile];
-  if (skip_done && skip_done[td.graph].done) return;
-  const uint32_t T = L.tcap, WC = L.wcap;
-  uint32_t* s_info = reinterpret_cast<uint32_t*>(smem + C::info(T));
-  uint32_t* s_off = reinterpret_cast<uint32_t*>(smem + C::off(T));
-  uint32_t* s_list = reinterpret_cast<uint32_t*>(smem + C::list(T));
-  Acc* s_part = reinterpret_cast<Acc*>(smem + C::part(T));
-  Acc* s_y = reinterpret_cast<Acc*>(smem + C::y(T));
-  X* s_x = reinterpret_cast<X*>(smem + C::x(T));
-  double* s_P = reinterpret_cast<double*>(smem + C::P(T, WC));
-  uint16_t* s_w = reinterpret_cast<uint16_t*>(smem + C::words(T, WC));
-  unsigned char* s_red = smem + C::red(T, WC, L.ecap);
-  const uint32_t tid = threadIdx.x;
+  if (skip_done && skip_done[L.tiles[blockIdx.x * kWaves].graph].done) return;  // whole block, one member
+  const WaveCarve<M, PREFIX> cv{L.wcap, L.sbytes};
+  unsigned char* ws = smem + size_t(wave) * cv.wave_bytes();
+  unsigned char* s_blk = smem + size_t(kWaves) * cv.wave_bytes();
+  uint32_t* s_o16 = reinterpret_cast<uint32_t*>(ws + cv.off16());
+  uint32_t* s_ow = reinterpret_cast<uint32_t*>(ws + cv.offw());
+  PAcc* s_part = reinterpret_cast<PAcc*>(ws + cv.part());
+  CAcc* s_y = reinterpret_cast<CAcc*>(ws + cv.y());
+  PAcc* s_carry = reinterpret_cast<PAcc*>(ws + cv.carry());
+  X* s_xbuf = reinterpret_cast<X*>(ws + cv.x());
+  double* s_P = reinterpret_cast<double*>(ws + cv.P());
+  unsigned char* s_data = ws + cv.data();
   const uint32_t nrows = td.nrows;
-  // 1-2. rows and words
-  const RowsStaged rs = stage_rows(L, td, s_info, s_off, s_list, s_w, s_red);
-  // 2b. the x window, and with prefix mode its exclusive prefix in double
   const int64_t win0 = td.win0;
   const uint32_t winlen = td.winlen;
-  if constexpr (!M::kInt) {
-    for (uint32_t k = tid; k < winlen; k += kThreads) s_x[k] = x[win0 + k];
+  const bool has_row = lane < nrows;
+
+  // 1. all global loads of the tile
+  const uint32_t inf = has_row ? L.info[td.row0 + lane] : 0u;
+  const uint32_t ns = has_row ? uint32_t(L.ns[td.row0 + lane]) : 0u;
+  wave_copy16<4>(L.data + td.data16, s_data, dstage_bytes(td));
+  const X* s_x = s_xbuf;
+  if constexpr (!M::kInt) s_x = stage_range<X>(x, L.n, win0, winlen, s_xbuf);
+  s_part[lane] = M::pzero();
+  const uint16_t* s16 = reinterpret_cast<const uint16_t*>(s_data);
+  const uint32_t* w32 = reinterpret_cast<const uint32_t*>(s_data + dalign16u(td.n16 * 2u));
+  const uint32_t* i32 = reinterpret_cast<const uint32_t*>(s_data + dalign16u(td.n16 * 2u) + dalign16u(td.nwide * 4u));
+
+  // 2. stream offsets: singles | wide << 20 | intervals << 40
+  const bool is_long = inf & kInfoLong;
+  const uint32_t ni = is_long ? 0u : ((inf >> 9) & 15u);
+  const uint64_t A = is_long ? 0 : (uint64_t(ns) | (uint64_t(inf >> 13) << 20) | (uint64_t(ni) << 40));
+  uint64_t totA;
+  const uint64_t ex = wave_excl_scan_u64(A, totA);
+  s_o16[lane] = uint32_t(ex & 0xFFFFFu);
+  s_ow[lane] = uint32_t((ex >> 20) & 0xFFFFFu);
+  const uint32_t oi = uint32_t(ex >> 40);
+  if (lane == 0) {
+    s_o16[64] = uint32_t(totA & 0xFFFFFu);
+    s_ow[64] = uint32_t((totA >> 20) & 0xFFFFFu);
   }
+  const uint32_t lvl = (inf >> 4) & 15u;
   if constexpr (PREFIX && !M::kInt) {
-    __syncthreads();
-    const uint32_t chunk = (winlen + kThreads - 1) / kThreads;
-    const uint32_t b0 = min(winlen, tid * chunk), b1 = min(winlen, b0 + chunk);
-    double acc = 0.0;
-    for (uint32_t k = b0; k < b1; ++k) acc += double(s_x[k]);
-    double tot;
-    double base = block_excl_scan_f64(acc, reinterpret_cast<double*>(s_red), tot);
-    for (uint32_t k = b0; k < b1; ++k) {
-      s_P[k] = base;
-      base += double(s_x[k]);
-    }
-    if (tid == 0) s_P[winlen] = tot;
-  }
-  __syncthreads();
-  // 3a. short rows, one thread each
-  for (uint32_t r = tid; r < nrows; r += kThreads) {
-    const uint32_t inf = s_info[r];
-    if (!(inf & kInfoLong)) s_part[r] = short_row<M, PREFIX>(s_w + s_off[r], inf >> 9, s_x, s_P, x, win0);
-  }
-  // 3b. long rows, the whole block each
-  const uint32_t nlong = rs.nlong;
-  for (uint32_t l = 0; l < nlong; ++l) {
-    const uint32_t r = s_list[l];
-    const uint32_t len = s_info[r] >> 9;
-    const uint32_t* e = L.longs + td.long0 + s_off[r];
-    Acc a = M::zero();
-    for (uint32_t k = tid; k < len; k += kThreads) {
-      const uint32_t v = e[k];
-      X xv;
-      if constexpr (M::kInt) {
-        xv = 1;
-      } else {
-        const int64_t c = int64_t(v & 0x7FFFFFFFu) - int64_t(kLongBias);
-        xv = uint64_t(c) < winlen ? s_x[c] : x[win0 + c];
+    if (td.nint) {
+      wave_sync();
+      const uint32_t chunk = (winlen + 63) / 64;
+      const uint32_t b0 = min(winlen, lane * chunk), b1 = min(winlen, b0 + chunk);
+      double acc = 0.0;
+      for (uint32_t k = b0; k < b1; ++k) acc += double(s_x[k]);
+      double tot;
+      double base = wave_excl_scan_f64(acc, tot);
+      for (uint32_t k = b0; k < b1; ++k) {
+        s_P[k] = base;
+        base += double(s_x[k]);
       }
-      M::add(a, (v & 0x80000000u) ? -xv : xv);
-    }
-    a = block_reduce<M>(a, reinterpret_cast<Acc*>(s_red));
-    if (tid == 0) s_part[r] = a;
-  }
-  __syncthreads();
-  // 4. reuse levels: y_i = y_{i-g} + partial_i
-  for (uint32_t r = tid; r < nrows; r += kThreads)
-    if (((s_info[r] >> 4) & 15u) == 0) s_y[r] = s_part[r];
-  const uint32_t maxlvl = rs.maxlvl;
-  for (uint32_t lv = 1; lv <= maxlvl; ++lv) {
-    __syncthreads();
-    for (uint32_t r = tid; r < nrows; r += kThreads) {
-      const uint32_t inf = s_info[r];
-      if (((inf >> 4) & 15u) == lv) s_y[r] = M::comb(s_y[r - (inf & 15u)], s_part[r]);
+      if (lane == 0) s_P[winlen] = tot;
     }
   }
-  __syncthreads();
-  // 5. epilogue
-  epi(TileCtx{td.row0, nrows, td.graph, tile}, s_y, s_red);
+  wave_sync();
+
+  // 3. singles, then wide entries
+  if (td.n16)
+    flat_pass_wave<M>(td.n16, nrows, s_o16, s_part, s_carry, [&](uint32_t e) -> X {
+      const uint32_t w = s16[e];
+      if constexpr (M::kInt) {
+        return (w & 0x8000u) ? -1 : 1;
+      } else {
+        const X v = s_x[w & 0x7FFFu];
+        return (w & 0x8000u) ? -v : v;
+      }
+    });
+  if (td.nwide)
+    flat_pass_wave<M>(td.nwide, nrows, s_ow, s_part, s_carry, [&](uint32_t e) -> X {
+      const uint32_t w = w32[e];
+      if constexpr (M::kInt) {
+        return (w & 0x80000000u) ? -1 : 1;
+      } else {
+        const int64_t c = int64_t(w & 0x7FFFFFFFu) - int64_t(kLongBias);
+        const X v = uint64_t(c) < winlen ? s_x[c] : x[win0 + c];
+        return (w & 0x80000000u) ? -v : v;
+      }
+    });
+  PAcc a = s_part[lane];
+
+  // 4. the lane's intervals
+  for (uint32_t q = 0; q < ni; ++q) {
+    const uint32_t w = i32[oi + q];
+    const uint32_t s = (w >> 16) & 0x7FFFu, ln = w & 0xFFFFu;
+    const bool neg = w & 0x80000000u;
+    if constexpr (M::kInt) {
+      M::padd(a, neg ? -int32_t(ln) : int32_t(ln));
+    } else if constexpr (PREFIX) {
+      const double d = s_P[s + ln] - s_P[s];
+      M::padd_d(a, neg ? -d : d);
+    } else {
+      for (uint32_t t = 0; t < ln; ++t) M::padd(a, neg ? -s_x[s + t] : s_x[s + t]);
+    }
+  }
+  //    long rows, the whole wave each
+  uint64_t lmask = __ballot(is_long);
+  if (lmask) {
+    const uint64_t cnt = is_long ? (uint64_t(inf >> 13) | (uint64_t(ns) << 19)) : 0;
+    uint64_t totL;
+    const uint64_t exL = wave_excl_scan_u64(cnt, totL);
+    while (lmask) {
+      const int r = __ffsll(static_cast<unsigned long long>(lmask)) - 1;
+      lmask &= lmask - 1;
+      const uint64_t len = __shfl(cnt, r, 64);
+      const uint64_t off = __shfl(exL, r, 64);
+      const uint32_t* e = L.longs + size_t(td.long0) + off;
+      PAcc s = M::pzero();
+      // batches of 8 entries per lane: all loads, then all gathers, then adds
+      for (uint64_t base = 0; base < len; base += 64 * 8) {
+        uint32_t w[8];
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+          const uint64_t k = base + lane + 64u * j;
+          w[j] = k < len ? e[k] : 0u;
+        }
+        X v[8];
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+          if constexpr (M::kInt) {
+            v[j] = 1;
+          } else {
+            const int64_t c = int64_t(w[j] & 0x7FFFFFFFu) - int64_t(kLongBias);
+            v[j] = base + lane + 64u * j >= len ? X(0) : (uint64_t(c) < winlen ? s_x[c] : x[win0 + c]);
+          }
+        }
+#pragma unroll
+        for (int j = 0; j < 8; ++j)
+          if (base + lane + 64u * j < len) M::padd(s, (w[j] & 0x80000000u) ? -v[j] : v[j]);
+      }
+      s = wave_reduce<M>(s);
+      if (lane == uint32_t(r)) a = s;
+    }
+  }
+
+  // 5. reuse levels: y_i = y_{i-g} + partial_i, while some lane has a row at
+  //    the level
+  const CAcc ca = M::chain(a);
+  if (lvl == 0) s_y[lane] = ca;
+  for (uint32_t lv = 1; __ballot(lvl >= lv); ++lv) {
+    wave_sync();
+    if (lvl == lv) s_y[lane] = M::comb(s_y[lane - (inf & 15u)], ca);
+  }
+  wave_sync();
+  // 6. epilogue
+  epi(TileCtx{td.row0, nrows, td.graph}, s_y, s_blk);
 }
 
-// PageRank start: p0 = start (or teleport, or uniform), z0 = p0 / d, dangling mass
+// PageRank start: p0 = start (or teleport, or uniform), z0 = p0 / d, dangling mass.
+// Tiles are read through (row0, nrows) at a stride; the member through `graphs`.
 template <class M>
 __global__ void __launch_bounds__(kThreads) pr_init_kernel(const uint32_t* __restrict__ row0s, uint32_t row_stride,
                                                            const uint32_t* __restrict__ graphs, const void* start_,
@@ -475,221 +620,270 @@ __global__ void __launch_bounds__(kThreads) pr_init_kernel(const uint32_t* __res
                                                            const int32_t* __restrict__ outdeg, PRState* st_all,
                                                            double* slots) {
   using X = typename M::X;
-  // row0s: per tile first row, stride between entries `row_stride` uint32s; nrows at +1
-  const uint32_t tile = blockIdx.x;
-  const uint32_t row0 = row0s[size_t(tile) * row_stride];
-  const uint32_t nrows = row0s[size_t(tile) * row_stride + 1] & 0x7FFFFFFFu;
-  const uint32_t graph = graphs ? graphs[size_t(tile) * row_stride] : 0u;
+  __shared__ __align__(16) unsigned char s_blk[256];
+  const uint32_t wave = threadIdx.x >> 6, lane = lane_id();
+  const size_t tile = size_t(blockIdx.x) * kWaves + wave;
+  const uint32_t row0 = row0s[tile * row_stride];
+  const uint32_t nrows = row0s[tile * row_stride + 1] & 0x7FFFFFFFu;
+  const uint32_t graph = graphs ? graphs[size_t(blockIdx.x) * kWaves * row_stride] : 0u;
   PRState* st = st_all + graph;
   const X* start = static_cast<const X*>(start_);
   const X* tele = static_cast<const X*>(tele_);
   X* p0 = static_cast<X*>(p0_);
   X* z0 = static_cast<X*>(z0_);
-  const double inv_n = st->inv_n;
   double dg = 0.0;
-  for (uint32_t r = threadIdx.x; r < nrows; r += kThreads) {
-    const uint32_t v = row0 + r;
-    const X pv = start ? start[v] : (tele ? tele[v] : X(inv_n));
+  if (lane < nrows) {
+    const uint32_t v = row0 + lane;
+    const X pv = start ? start[v] : (tele ? tele[v] : X(st->inv_n));
     p0[v] = pv;
     const int32_t d = outdeg[v];
     z0[v] = d > 0 ? pv / X(d) : X(0);
-    if (d == 0) dg += double(pv);
+    if (d == 0) dg = double(pv);
   }
-  __shared__ double s_red[kWaves];
-  __shared__ int s_last;
-  dg = block_sum_f64(dg, s_red);
-  if (threadIdx.x == 0) {
-    slots[2 * size_t(tile) + 1] = dg;
-    __threadfence();
-    const uint32_t prev = atomicAdd(&st->ticket, 1u);
-    s_last = prev + 1 == st->tile_hi - st->tile_lo;
-  }
-  __syncthreads();
-  if (!s_last) return;
-  __threadfence();
-  double D = 0.0;
-  for (uint32_t t = st->tile_lo + threadIdx.x; t < st->tile_hi; t += kThreads)
-    D += __builtin_nontemporal_load(&slots[2 * size_t(t) + 1]);
-  D = block_sum_f64(D, s_red);
-  if (threadIdx.x == 0) {
-    st->delta = D;
-    st->resid = 0.0;
-    st->iter = 0;
-    st->done = 0;
-    st->converged = 0;
-    st->final_buf = 0;
-    st->ticket = 0;
-    __threadfence();
-  }
+  dg = wave_sum_f64(dg);
+  pr_block_finish(0.0, dg, st, slots, 0, 0.0, 0, 0, s_blk);
 }
 
 // ---------------------------------------------------------------- CSR kernel
-// A tile is a run of short rows whose columns are staged in LDS, or one long
-// row (bit 31 of nrows) summed by the whole block.
+// Same structure on plain CSR: a wave takes a run of up to 64 rows whose
+// column ids are staged in LDS with an x window (columns inside it read from
+// LDS), summed by the same flat pass; or one long row (bit 31 of nrows)
+// summed by the whole wave.
+template <class M>
+struct CsrCarve {
+  using X = typename M::X;
+  using PAcc = typename M::PAcc;
+  using CAcc = typename M::CAcc;
+  uint32_t WC, CC;
+  __host__ __device__ static constexpr size_t off() { return 0; }
+  __host__ __device__ static constexpr size_t part() { return align16(65 * 4); }
+  __host__ __device__ static constexpr size_t y() { return part() + align16(64 * sizeof(PAcc)); }
+  __host__ __device__ static constexpr size_t carry() { return y() + align16(64 * sizeof(CAcc)); }
+  __host__ __device__ static constexpr size_t x() { return carry() + align16(64 * sizeof(PAcc)); }
+  __host__ __device__ size_t col() const { return x() + align16(size_t(WC) * sizeof(X) + 16); }
+  __host__ __device__ size_t wave_bytes() const { return col() + align16(size_t(CC) * 4 + 16); }
+  __host__ __device__ size_t block_bytes() const { return kWaves * wave_bytes() + 256; }
+};
+
 template <class M, class Epi>
-__global__ void __launch_bounds__(kThreads) csr_tile_kernel(DevCsr C, const typename M::X* __restrict__ x, Epi epi,
+__global__ void __launch_bounds__(kThreads) csr_wave_kernel(DevCsr C, const typename M::X* __restrict__ x, Epi epi,
                                                             const PRState* __restrict__ skip_done) {
   using X = typename M::X;
-  using Acc = typename M::Acc;
+  using PAcc = typename M::PAcc;
+  using CAcc = typename M::CAcc;
   extern __shared__ __align__(16) unsigned char smem[];
   if (skip_done && skip_done[0].done) return;
-  const uint32_t tile = blockIdx.x;
+  const uint32_t wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const uint32_t lane = lane_id();
+  const uint32_t tile = blockIdx.x * kWaves + wave;
   const CsrTile td = C.tiles[tile];
   const bool is_long = td.nrows & 0x80000000u;
   const uint32_t nrows = td.nrows & 0x7FFFFFFFu;
-  const uint32_t RC = C.rcap;
-  uint32_t* s_rp = reinterpret_cast<uint32_t*>(smem);                          // RC + 1
-  Acc* s_y = reinterpret_cast<Acc*>(smem + align16((size_t(RC) + 1) * 4));     // RC
-  uint32_t* s_col = reinterpret_cast<uint32_t*>(smem + align16((size_t(RC) + 1) * 4) + align16(size_t(RC) * sizeof(Acc)));
-  unsigned char* s_red = reinterpret_cast<unsigned char*>(s_col + C.ccap);
-  const uint32_t tid = threadIdx.x;
+  const CsrCarve<M> cv{C.wcap, C.ccap};
+  unsigned char* ws = smem + size_t(wave) * cv.wave_bytes();
+  unsigned char* s_blk = smem + size_t(kWaves) * cv.wave_bytes();
+  uint32_t* s_off = reinterpret_cast<uint32_t*>(ws + cv.off());
+  PAcc* s_part = reinterpret_cast<PAcc*>(ws + cv.part());
+  CAcc* s_y = reinterpret_cast<CAcc*>(ws + cv.y());
+  PAcc* s_carry = reinterpret_cast<PAcc*>(ws + cv.carry());
+  X* s_xbuf = reinterpret_cast<X*>(ws + cv.x());
+  uint32_t* s_colbuf = reinterpret_cast<uint32_t*>(ws + cv.col());
   if (is_long) {
-    Acc a = M::zero();
-    for (uint32_t k = tid; k < td.ncols; k += kThreads) M::add(a, x[C.col[size_t(td.c0) + k]]);
-    a = block_reduce<M>(a, reinterpret_cast<Acc*>(s_red));
-    if (tid == 0) s_y[0] = a;
-  } else {
-    for (uint32_t r = tid; r <= nrows; r += kThreads) s_rp[r] = C.rowptr[td.row0 + r] - td.c0;
-    for (uint32_t k = tid; k < td.ncols; k += kThreads) s_col[k] = C.col[size_t(td.c0) + k];
-    __syncthreads();
-    for (uint32_t r = tid; r < nrows; r += kThreads) {
-      Acc a = M::zero();
-      const uint32_t e = s_rp[r + 1];
-      for (uint32_t k = s_rp[r]; k < e; ++k) M::add(a, x[s_col[k]]);
-      s_y[r] = a;
+    PAcc s = M::pzero();
+    const uint32_t* cl = C.col + size_t(td.c0);
+    for (uint32_t base = 0; base < td.ncols; base += 64 * 8) {  // 8 loads in flight per lane
+      uint32_t c[8];
+#pragma unroll
+      for (int j = 0; j < 8; ++j) {
+        const uint32_t k = base + lane + 64u * j;
+        c[j] = k < td.ncols ? cl[k] : 0u;
+      }
+      X v[8];
+#pragma unroll
+      for (int j = 0; j < 8; ++j) v[j] = base + lane + 64u * j < td.ncols ? x[c[j]] : X(0);
+#pragma unroll
+      for (int j = 0; j < 8; ++j)
+        if (base + lane + 64u * j < td.ncols) M::padd(s, v[j]);
     }
+    s = wave_reduce<M>(s);
+    if (lane == 0) s_y[0] = M::chain(s);
+  } else {
+    const int64_t win0 = td.win0;
+    const uint32_t winlen = td.winlen;
+    if (lane <= nrows) s_off[lane] = C.rowptr[td.row0 + lane] - td.c0;
+    if (lane == 0 && nrows == 64) s_off[64] = C.rowptr[td.row0 + 64] - td.c0;
+    const uint32_t* s_col = stage_range<uint32_t>(C.col, C.col_len, td.c0, td.ncols, s_colbuf);
+    const X* s_x = stage_range<X>(x, C.n, win0, winlen, s_xbuf);
+    s_part[lane] = M::pzero();
+    wave_sync();
+    if (td.ncols)
+      flat_pass_wave<M>(td.ncols, nrows, s_off, s_part, s_carry, [&](uint32_t e) -> X {
+        const int64_t c = int64_t(s_col[e]) - win0;
+        return uint64_t(c) < winlen ? s_x[c] : x[win0 + c];
+      });
+    s_y[lane] = M::chain(s_part[lane]);
   }
-  __syncthreads();
-  epi(TileCtx{td.row0, nrows, 0u, tile}, s_y, s_red);
-}
-
-// ------------------------------------------------------------- dispatching
-template <class M, bool PREFIX, class Epi>
-hipError_t launch_tile(const DevLayout& L, const void* x, const Epi& epi, const PRState* skip, hipStream_t s) {
-  using C = Carve<M, PREFIX>;
-  const size_t smem = C::total(L.tcap, L.wcap, L.ecap);
-  auto k = bv_tile_kernel<M, PREFIX, Epi>;
-  if (smem > 65536) {
-    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(k), hipFuncAttributeMaxDynamicSharedMemorySize,
-                                       int(smem));
-    if (e != hipSuccess) return e;
-  }
-  if (L.ntiles == 0) return hipSuccess;
-  hipLaunchKernelGGL(k, dim3(L.ntiles), dim3(kThreads), smem, s, L, static_cast<const typename M::X*>(x), epi,
-                     skip);
-  return hipGetLastError();
-}
-
-template <class M, class Epi>
-hipError_t launch_csr(const DevCsr& Cs, const void* x, const Epi& epi, const PRState* skip, hipStream_t s) {
-  using Acc = typename M::Acc;
-  const size_t smem = align16((size_t(Cs.rcap) + 1) * 4) + align16(size_t(Cs.rcap) * sizeof(Acc)) +
-                      size_t(Cs.ccap) * 4 + 256;
-  auto k = csr_tile_kernel<M, Epi>;
-  if (smem > 65536) {
-    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(k), hipFuncAttributeMaxDynamicSharedMemorySize,
-                                       int(smem));
-    if (e != hipSuccess) return e;
-  }
-  if (Cs.ntiles == 0) return hipSuccess;
-  hipLaunchKernelGGL(k, dim3(Cs.ntiles), dim3(kThreads), smem, s, Cs, static_cast<const typename M::X*>(x), epi,
-                     skip);
-  return hipGetLastError();
+  wave_sync();
+  epi(TileCtx{td.row0, nrows, 0u}, s_y, s_blk);
 }
 
 // -------------------------------------------------------- multi-vector kernel
 // Y = A X for k right-hand sides, node-major (element (v, c) at v * ld + c).
-// Lanes map to right-hand sides: a team of G lanes handles one row, walking
-// the row's words (broadcast LDS reads) while each lane gathers its column
-// of X, so one pass over the layout serves all k products.  X is not staged
-// (a window would hold G values per column); intervals are summed directly.
-// Partials live in LDS as T x G accumulators and the reuse levels are
-// resolved in place; right-hand sides beyond G are done in further passes
-// over the staged words.
+// One block per tile.  Lanes map to right-hand sides: a team of G lanes
+// handles one row, walking the row's entries (broadcast LDS reads) while
+// each lane gathers its column of X, so one pass over the layout serves all
+// k products.  X is not staged (a window would hold G values per column);
+// intervals are summed directly.  Partials live in LDS as T x G
+// accumulators and the reuse levels are resolved in place; right-hand sides
+// beyond G take further passes over the staged streams.
+struct RowsStaged {
+  uint32_t nlong, maxlvl;
+};
+
+__device__ __forceinline__ RowsStaged block_scan_rows(const TileDesc& td, const uint32_t* s_info, const uint32_t* s_ns,
+                                                      uint32_t* s_o16, uint32_t* s_ow, uint32_t* s_oi, uint32_t* s_ol,
+                                                      uint32_t* s_list, unsigned char* s_red) {
+  __shared__ uint32_t s_nlong, s_maxlvl;
+  const uint32_t tid = threadIdx.x;
+  const uint32_t nrows = td.nrows;  // <= 64 < 256: one row per thread
+  uint64_t A = 0, Bv = 0;
+  uint32_t lvl = 0;
+  if (tid < nrows) {
+    const uint32_t inf = s_info[tid];
+    const uint64_t nw = inf >> 13, ni = (inf >> 9) & 15u;
+    if (inf & kInfoLong) Bv = (uint64_t(1) << 16) | ((nw | (uint64_t(s_ns[tid]) << 19)) << 28);
+    else {
+      A = uint64_t(s_ns[tid]) | (nw << 32);
+      Bv = ni;
+    }
+    lvl = (inf >> 4) & 15u;
+  }
+  if (tid == 0) s_maxlvl = 0;
+  __syncthreads();
+  if (lvl) atomicMax(&s_maxlvl, lvl);
+  uint64_t totA, totB;
+  const uint64_t ra = block_excl_scan_u64(A, reinterpret_cast<uint64_t*>(s_red), totA);
+  const uint64_t rb = block_excl_scan_u64(Bv, reinterpret_cast<uint64_t*>(s_red), totB);
+  if (tid < nrows) {
+    s_o16[tid] = uint32_t(ra & 0xFFFFFFFFu);
+    s_ow[tid] = uint32_t(ra >> 32);
+    s_oi[tid] = uint32_t(rb & 0xFFFFu);
+    s_ol[tid] = uint32_t(rb >> 28);
+    if (s_info[tid] & kInfoLong) s_list[(rb >> 16) & 0xFFFu] = tid;
+  }
+  if (tid == 0) s_nlong = uint32_t((totB >> 16) & 0xFFFu);
+  __syncthreads();
+  return RowsStaged{s_nlong, s_maxlvl};
+}
+
+template <class M, int G>
+struct BatchCarve {
+  using PAcc = typename M::PAcc;
+  using CAcc = typename M::CAcc;
+  uint32_t SB;
+  static constexpr size_t u = align16(65 * 4);
+  __host__ __device__ static constexpr size_t acc() { return 7 * u; }
+  __host__ __device__ static constexpr size_t tmp() { return acc() + align16(64 * G * sizeof(CAcc)); }
+  __host__ __device__ static constexpr size_t data() { return tmp() + align16(kThreads * sizeof(PAcc)); }
+  __host__ __device__ size_t red() const { return data() + align16(size_t(SB)); }
+  __host__ __device__ size_t total() const { return red() + 256; }
+};
+
 template <class M, int G>
 __global__ void __launch_bounds__(kThreads) bv_batch_kernel(DevLayout L, const typename M::X* __restrict__ X,
                                                             typename M::X* __restrict__ Y, int k, int64_t ld) {
   using Xt = typename M::X;
-  using Acc = typename M::Acc;
+  using PAcc = typename M::PAcc;
+  using CAcc = typename M::CAcc;
   constexpr uint32_t kTeams = kThreads / G;
   extern __shared__ __align__(16) unsigned char smem[];
   const TileDesc td = L.tiles[blockIdx.x];
-  const uint32_t T = L.tcap;
+  const BatchCarve<M, G> cv{L.sbytes};
+  constexpr size_t u = BatchCarve<M, G>::u;
   uint32_t* s_info = reinterpret_cast<uint32_t*>(smem);
-  uint32_t* s_off = reinterpret_cast<uint32_t*>(smem + align16(size_t(T) * 4));
-  uint32_t* s_list = reinterpret_cast<uint32_t*>(smem + 2 * align16(size_t(T) * 4));
-  Acc* s_acc = reinterpret_cast<Acc*>(smem + 3 * align16(size_t(T) * 4));
-  Acc* s_tmp = reinterpret_cast<Acc*>(smem + 3 * align16(size_t(T) * 4) + align16(size_t(T) * G * sizeof(Acc)));
-  uint16_t* s_w = reinterpret_cast<uint16_t*>(reinterpret_cast<unsigned char*>(s_tmp) +
-                                              align16(size_t(kThreads) * sizeof(Acc)));
-  unsigned char* s_red = reinterpret_cast<unsigned char*>(s_w) + align16((size_t(L.ecap) + 16) * 2);
-  const RowsStaged rs = stage_rows(L, td, s_info, s_off, s_list, s_w, s_red);
+  uint32_t* s_ns = reinterpret_cast<uint32_t*>(smem + u);
+  uint32_t* s_o16 = reinterpret_cast<uint32_t*>(smem + 2 * u);
+  uint32_t* s_ow = reinterpret_cast<uint32_t*>(smem + 3 * u);
+  uint32_t* s_oi = reinterpret_cast<uint32_t*>(smem + 4 * u);
+  uint32_t* s_ol = reinterpret_cast<uint32_t*>(smem + 5 * u);
+  uint32_t* s_list = reinterpret_cast<uint32_t*>(smem + 6 * u);
+  CAcc* s_acc = reinterpret_cast<CAcc*>(smem + cv.acc());
+  PAcc* s_tmp = reinterpret_cast<PAcc*>(smem + cv.tmp());
+  unsigned char* s_data = smem + cv.data();
+  unsigned char* s_red = smem + cv.red();
   const uint32_t tid = threadIdx.x, team = tid / G, lane = tid % G;
   const uint32_t nrows = td.nrows;
+  {
+    const uint4* src = L.data + td.data16;
+    uint4* dst = reinterpret_cast<uint4*>(s_data);
+    const uint32_t nv = dstage_bytes(td) / 16;
+    for (uint32_t q = tid; q < nv; q += kThreads) dst[q] = src[q];
+    if (tid < nrows) {
+      s_info[tid] = L.info[td.row0 + tid];
+      s_ns[tid] = L.ns[td.row0 + tid];
+    }
+  }
+  __syncthreads();
+  const RowsStaged rs = block_scan_rows(td, s_info, s_ns, s_o16, s_ow, s_oi, s_ol, s_list, s_red);
+  const uint16_t* s16 = reinterpret_cast<const uint16_t*>(s_data);
+  const uint32_t* w32 = reinterpret_cast<const uint32_t*>(s_data + dalign16u(td.n16 * 2u));
+  const uint32_t* i32 = reinterpret_cast<const uint32_t*>(s_data + dalign16u(td.n16 * 2u) + dalign16u(td.nwide * 4u));
   const int64_t win0 = td.win0;
   for (int c0 = 0; c0 < k; c0 += G) {
     const int c = c0 + int(lane);
     const bool act = c < k;
-    const Xt* Xc = X + c;
+    const Xt* Xc = X + (act ? c : 0);
     for (uint32_t r = team; r < nrows; r += kTeams) {
       const uint32_t inf = s_info[r];
       if (inf & kInfoLong) continue;
-      Acc a = M::zero();
-      const uint16_t* w = s_w + s_off[r];
-      const uint32_t len = inf >> 9;
-      uint32_t q = 0;
-      while (q < len) {
-        const uint32_t wd = w[q++];
-        const bool neg = wd & 0x8000u;
-        const uint32_t off = wd & 0x3FFFu;
-        if (wd & 0x4000u) {
-          const uint32_t ln = w[q++];
-          if (act)
-            for (uint32_t t = 0; t < ln; ++t) {
-              const Xt v = Xc[(win0 + int64_t(off + t)) * ld];
-              M::add(a, neg ? -v : v);
-            }
-        } else {
-          int64_t col = win0 + int64_t(off);
-          if (off == kEscape) {
-            col = win0 + int64_t(int32_t((uint32_t(w[q]) << 16) | uint32_t(w[q + 1])));
-            q += 2;
-          }
-          if (act) {
-            const Xt v = Xc[col * ld];
-            M::add(a, neg ? -v : v);
-          }
-        }
+      PAcc a = M::pzero();
+      for (uint32_t e = s_o16[r], en = s_o16[r] + s_ns[r]; e < en; ++e) {
+        const uint32_t w = s16[e];
+        const Xt v = act ? Xc[(win0 + int64_t(w & 0x7FFFu)) * ld] : Xt(0);
+        M::padd(a, (w & 0x8000u) ? -v : v);
       }
-      s_acc[r * G + lane] = a;
+      for (uint32_t e = s_ow[r], en = s_ow[r] + (inf >> 13); e < en; ++e) {
+        const uint32_t w = w32[e];
+        const int64_t col = win0 + int64_t(w & 0x7FFFFFFFu) - int64_t(kLongBias);
+        const Xt v = act ? Xc[col * ld] : Xt(0);
+        M::padd(a, (w & 0x80000000u) ? -v : v);
+      }
+      for (uint32_t e = s_oi[r], en = s_oi[r] + ((inf >> 9) & 15u); e < en; ++e) {
+        const uint32_t w = i32[e];
+        const int64_t s = win0 + int64_t((w >> 16) & 0x7FFFu);
+        const uint32_t ln = w & 0xFFFFu;
+        if (act)
+          for (uint32_t t = 0; t < ln; ++t) {
+            const Xt v = Xc[(s + t) * ld];
+            M::padd(a, (w & 0x80000000u) ? -v : v);
+          }
+      }
+      s_acc[r * G + lane] = M::chain(a);
     }
     for (uint32_t l = 0; l < rs.nlong; ++l) {
       const uint32_t r = s_list[l];
-      const uint32_t len = s_info[r] >> 9;
-      const uint32_t* e = L.longs + td.long0 + s_off[r];
-      Acc a = M::zero();
-      for (uint32_t q = team; q < len; q += kTeams) {
-        const uint32_t v = e[q];
-        const int64_t col = win0 + int64_t(v & 0x7FFFFFFFu) - int64_t(kLongBias);
-        if (act) {
-          const Xt xv = Xc[col * ld];
-          M::add(a, (v & 0x80000000u) ? -xv : xv);
-        }
+      const uint64_t len = uint64_t(s_info[r] >> 13) | (uint64_t(s_ns[r]) << 19);
+      const uint32_t* e = L.longs + size_t(td.long0) + s_ol[r];
+      PAcc a = M::pzero();
+      for (uint64_t q = team; q < len; q += kTeams) {
+        const uint32_t w = e[q];
+        const int64_t col = win0 + int64_t(w & 0x7FFFFFFFu) - int64_t(kLongBias);
+        const Xt v = act ? Xc[col * ld] : Xt(0);
+        M::padd(a, (w & 0x80000000u) ? -v : v);
       }
       s_tmp[team * G + lane] = a;
       __syncthreads();
       if (team == 0) {
-        Acc sum = s_tmp[lane];
-        for (uint32_t t = 1; t < kTeams; ++t) sum = M::comb(sum, s_tmp[t * G + lane]);
-        s_acc[r * G + lane] = sum;
+        PAcc sum = s_tmp[lane];
+        for (uint32_t t = 1; t < kTeams; ++t) sum = M::pcomb(sum, s_tmp[t * G + lane]);
+        s_acc[r * G + lane] = M::chain(sum);
       }
       __syncthreads();
     }
     __syncthreads();
     for (uint32_t lv = 1; lv <= rs.maxlvl; ++lv) {
       for (uint32_t idx = tid; idx < nrows * G; idx += kThreads) {
-        const uint32_t r = idx / G;
-        const uint32_t inf = s_info[r];
+        const uint32_t inf = s_info[idx / G];
         if (((inf >> 4) & 15u) == lv) s_acc[idx] = M::comb(s_acc[idx - (inf & 15u) * G], s_acc[idx]);
       }
       __syncthreads();
@@ -702,46 +896,81 @@ __global__ void __launch_bounds__(kThreads) bv_batch_kernel(DevLayout L, const t
   }
 }
 
+// ------------------------------------------------------------- dispatching
+hipError_t set_lds(const void* k, size_t smem) {
+  if (smem <= 65536) return hipSuccess;
+  return hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, int(smem));
+}
+
+template <class M, bool PREFIX>
+size_t tile_lds(const DevLayout& L) {
+  return WaveCarve<M, PREFIX>{L.wcap, L.sbytes}.block_bytes();
+}
+
+template <class M, bool PREFIX, class Epi>
+hipError_t launch_tile(const DevLayout& L, const void* x, const Epi& epi, const PRState* skip, hipStream_t s) {
+  const size_t smem = tile_lds<M, PREFIX>(L);
+  auto k = bv_wave_kernel<M, PREFIX, Epi>;
+  if (hipError_t e = set_lds(reinterpret_cast<const void*>(k), smem)) return e;
+  if (L.ntiles == 0) return hipSuccess;
+  hipLaunchKernelGGL(k, dim3(L.ntiles / kWaves), dim3(kThreads), smem, s, L, static_cast<const typename M::X*>(x),
+                     epi, skip);
+  return hipGetLastError();
+}
+
+template <class M>
+size_t csr_lds(const DevCsr& C) {
+  return CsrCarve<M>{C.wcap, C.ccap}.block_bytes();
+}
+
+template <class M, class Epi>
+hipError_t launch_csr(const DevCsr& Cs, const void* x, const Epi& epi, const PRState* skip, hipStream_t s) {
+  const size_t smem = csr_lds<M>(Cs);
+  auto k = csr_wave_kernel<M, Epi>;
+  if (hipError_t e = set_lds(reinterpret_cast<const void*>(k), smem)) return e;
+  if (Cs.ntiles == 0) return hipSuccess;
+  hipLaunchKernelGGL(k, dim3(Cs.ntiles / kWaves), dim3(kThreads), smem, s, Cs,
+                     static_cast<const typename M::X*>(x), epi, skip);
+  return hipGetLastError();
+}
+
 template <class M, int G>
-size_t batch_smem(const DevLayout& L) {
-  using Acc = typename M::Acc;
-  return 3 * align16(size_t(L.tcap) * 4) + align16(size_t(L.tcap) * G * sizeof(Acc)) +
-         align16(size_t(kThreads) * sizeof(Acc)) + align16((size_t(L.ecap) + 16) * 2) + 256;
+size_t batch_lds(const DevLayout& L) {
+  return BatchCarve<M, G>{L.sbytes}.total();
 }
 
 template <class M, int G>
 hipError_t launch_batch_g(const DevLayout& L, const void* X, void* Y, int k, int64_t ld, hipStream_t s) {
-  const size_t smem = batch_smem<M, G>(L);
+  const size_t smem = batch_lds<M, G>(L);
   auto kern = bv_batch_kernel<M, G>;
-  if (smem > 65536) {
-    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(kern),
-                                       hipFuncAttributeMaxDynamicSharedMemorySize, int(smem));
-    if (e != hipSuccess) return e;
-  }
+  if (hipError_t e = set_lds(reinterpret_cast<const void*>(kern), smem)) return e;
   if (L.ntiles == 0) return hipSuccess;
   hipLaunchKernelGGL(kern, dim3(L.ntiles), dim3(kThreads), smem, s, L, static_cast<const typename M::X*>(X),
                      static_cast<typename M::X*>(Y), k, ld);
   return hipGetLastError();
 }
 
-// Team width: the smallest power of two >= k (at least 4), shrunk until the
-// T x G accumulators fit the LDS budget.
-template <class M>
-hipError_t launch_batch(const DevLayout& L, const void* X, void* Y, int k, int64_t ld, hipStream_t s) {
-  constexpr size_t kBudget = 96 * 1024;
+// Team width: the smallest power of two >= k, at least 4, at most 64.
+inline int team_width(int k) {
   int G = 4;
   while (G < k && G < 64) G *= 2;
-  auto fits = [&](int g) {
-    switch (g) {
-      case 64: return batch_smem<M, 64>(L) <= kBudget;
-      case 32: return batch_smem<M, 32>(L) <= kBudget;
-      case 16: return batch_smem<M, 16>(L) <= kBudget;
-      case 8: return batch_smem<M, 8>(L) <= kBudget;
-      default: return true;
-    }
-  };
-  while (G > 4 && !fits(G)) G /= 2;
-  switch (G) {
+  return G;
+}
+
+template <class M>
+size_t batch_lds_k(const DevLayout& L, int k) {
+  switch (team_width(k)) {
+    case 64: return batch_lds<M, 64>(L);
+    case 32: return batch_lds<M, 32>(L);
+    case 16: return batch_lds<M, 16>(L);
+    case 8: return batch_lds<M, 8>(L);
+    default: return batch_lds<M, 4>(L);
+  }
+}
+
+template <class M>
+hipError_t launch_batch(const DevLayout& L, const void* X, void* Y, int k, int64_t ld, hipStream_t s) {
+  switch (team_width(k)) {
     case 64: return launch_batch_g<M, 64>(L, X, Y, k, ld, s);
     case 32: return launch_batch_g<M, 32>(L, X, Y, k, ld, s);
     case 16: return launch_batch_g<M, 16>(L, X, Y, k, ld, s);
@@ -752,9 +981,37 @@ hipError_t launch_batch(const DevLayout& L, const void* X, void* Y, int k, int64
 
 }  // namespace
 
+size_t bv_kernel_lds_bytes(const DevLayout& L, int prec, int interval_mode) {
+  const bool prefix = interval_mode == 1;
+  switch (prec) {
+    case 0: return tile_lds<MF64, false>(L);
+    case 1: return prefix ? tile_lds<MF32, true>(L) : tile_lds<MF32, false>(L);
+    case 2: return prefix ? tile_lds<MF32C, true>(L) : tile_lds<MF32C, false>(L);
+    default: return 0;
+  }
+}
+
+size_t csr_kernel_lds_bytes(const DevCsr& C, int prec) {
+  switch (prec) {
+    case 0: return csr_lds<MF64>(C);
+    case 1: return csr_lds<MF32>(C);
+    case 2: return csr_lds<MF32C>(C);
+    default: return 0;
+  }
+}
+
+size_t bv_batch_lds_bytes(const DevLayout& L, int prec, int k) {
+  switch (prec) {
+    case 0: return batch_lds_k<MF64>(L, k);
+    case 1: return batch_lds_k<MF32>(L, k);
+    case 2: return batch_lds_k<MF32C>(L, k);
+    default: return 0;
+  }
+}
+
 hipError_t launch_bv_multiply(const DevLayout& L, int prec, int interval_mode, const void* x, void* y,
                               hipStream_t s) {
-  const bool prefix = interval_mode == 0;
+  const bool prefix = interval_mode == 1;
   switch (prec) {
     case 0:
       return launch_tile<MF64, false>(L, x, EpiStore<MF64>{static_cast<double*>(y)}, nullptr, s);
@@ -775,7 +1032,7 @@ hipError_t launch_bv_degrees(const DevLayout& L, int32_t* deg, hipStream_t s) {
 
 hipError_t launch_bv_pagerank_iter(const DevLayout& L, int prec, int interval_mode, const PRArgs& a,
                                    hipStream_t s) {
-  const bool prefix = interval_mode == 0;
+  const bool prefix = interval_mode == 1;
   switch (prec) {
     case 0:
       return launch_tile<MF64, false>(L, a.z_cur, EpiPR<MF64>{a}, a.st, s);
@@ -797,11 +1054,11 @@ hipError_t launch_pr_init(const DevLayout& L, int prec, const void* start, const
   const uint32_t stride = sizeof(TileDesc) / 4;
   const uint32_t* graphs = base + offsetof(TileDesc, graph) / 4;
   if (prec == 0)
-    hipLaunchKernelGGL(pr_init_kernel<MF64>, dim3(L.ntiles), dim3(kThreads), 0, s, base, stride, graphs, start,
-                       tele, p0, z0, outdeg, st, slots);
+    hipLaunchKernelGGL(pr_init_kernel<MF64>, dim3(L.ntiles / kWaves), dim3(kThreads), 0, s, base, stride, graphs,
+                       start, tele, p0, z0, outdeg, st, slots);
   else
-    hipLaunchKernelGGL(pr_init_kernel<MF32>, dim3(L.ntiles), dim3(kThreads), 0, s, base, stride, graphs, start,
-                       tele, p0, z0, outdeg, st, slots);
+    hipLaunchKernelGGL(pr_init_kernel<MF32>, dim3(L.ntiles / kWaves), dim3(kThreads), 0, s, base, stride, graphs,
+                       start, tele, p0, z0, outdeg, st, slots);
   return hipGetLastError();
 }
 
@@ -837,11 +1094,11 @@ hipError_t launch_csr_pr_init(const DevCsr& C, int prec, const void* start, cons
   const uint32_t* base = reinterpret_cast<const uint32_t*>(C.tiles);
   const uint32_t stride = sizeof(CsrTile) / 4;
   if (prec == 0)
-    hipLaunchKernelGGL(pr_init_kernel<MF64>, dim3(C.ntiles), dim3(kThreads), 0, s, base, stride, nullptr, start,
-                       tele, p0, z0, outdeg, st, slots);
+    hipLaunchKernelGGL(pr_init_kernel<MF64>, dim3(C.ntiles / kWaves), dim3(kThreads), 0, s, base, stride, nullptr,
+                       start, tele, p0, z0, outdeg, st, slots);
   else
-    hipLaunchKernelGGL(pr_init_kernel<MF32>, dim3(C.ntiles), dim3(kThreads), 0, s, base, stride, nullptr, start,
-                       tele, p0, z0, outdeg, st, slots);
+    hipLaunchKernelGGL(pr_init_kernel<MF32>, dim3(C.ntiles / kWaves), dim3(kThreads), 0, s, base, stride, nullptr,
+                       start, tele, p0, z0, outdeg, st, slots);
   return hipGetLastError();
 }
 

@@ -3,6 +3,7 @@
 
 #include <algorithm>
 #include <atomic>
+#include <cstring>
 #include <thread>
 
 namespace bvmv {
@@ -21,7 +22,7 @@ void to_entries(const uint32_t* a, size_t na, bool neg, int min_len, std::vector
     while (e < na && a[e] == a[e - 1] + 1) ++e;
     if (int64_t(e - k) >= min_len) {
       size_t s = k;
-      while (s < e) {  // lengths fit the 16-bit length word
+      while (s < e) {  // lengths fit 16 bits
         size_t l = std::min<size_t>(e - s, 65535);
         out.push_back({a[s], uint32_t(l), neg});
         s += l;
@@ -33,28 +34,51 @@ void to_entries(const uint32_t* a, size_t na, bool neg, int min_len, std::vector
   }
 }
 
-int64_t entry_words(const std::vector<Entry>& es) {
-  int64_t w = 0;
-  for (auto& e : es) w += e.len ? 2 : 1;
-  return w;
+// staged bytes if every entry falls inside the window
+int64_t entry_bytes(const std::vector<Entry>& es) {
+  int64_t b = 0;
+  for (auto& e : es) b += e.len ? 4 : 2;
+  return b;
 }
 
 struct RowPlan {
   std::vector<Entry> ent;
-  int g = 0;        // 0 = direct
-  int64_t est = 0;  // words if every entry falls in the window
-  bool force_long = false;  // its coded words alone overflow a tile
+  int g = 0;                // 0 = direct
+  int64_t est = 0;          // staged bytes if every entry falls in the window
+  bool force_long = false;  // its coded streams alone overflow a tile
 };
 
 struct ChunkOut {
   std::vector<TileDesc> tiles;
   std::vector<uint32_t> info;
-  std::vector<uint16_t> words;
+  std::vector<uint16_t> ns;
+  std::vector<uint8_t> data;
   std::vector<uint32_t> longs;
   int64_t units = 0, diff_rows = 0, direct_rows = 0, long_rows = 0, escapes = 0, m_prime = 0;
+  int64_t n_singles = 0, n_wide = 0, n_intervals = 0;
   int max_level = 0;
   std::string err;
 };
+
+inline uint32_t wide_code(int64_t col, int64_t win0, bool neg) {
+  return (neg ? 0x80000000u : 0u) | uint32_t(col - win0 + int64_t(kLongBias));
+}
+
+// window of at most `cap` columns covering the most points (sorted in place)
+void best_window(std::vector<uint32_t>& pts, int cap, uint32_t def, uint32_t& win0, uint32_t& winlen) {
+  std::sort(pts.begin(), pts.end());
+  win0 = def;
+  winlen = 0;
+  if (pts.empty()) return;
+  size_t best_a = 0, best_b = 0, b = 0;
+  for (size_t a = 0; a < pts.size(); ++a) {
+    if (b < a) b = a;
+    while (b + 1 < pts.size() && int64_t(pts[b + 1]) - int64_t(pts[a]) < cap) ++b;
+    if (b - a > best_b - best_a) { best_a = a; best_b = b; }
+  }
+  win0 = pts[best_a];
+  winlen = pts[best_b] - pts[best_a] + 1;
+}
 
 class Builder {
  public:
@@ -65,9 +89,10 @@ class Builder {
     const uint32_t* Li = g_.col.data() + g_.rowptr[i];
     const size_t di = size_t(g_.rowptr[i + 1] - g_.rowptr[i]);
     rp.ent.clear();
+    rp.force_long = false;
     to_entries(Li, di, false, p_.min_interval, rp.ent);
     rp.g = 0;
-    rp.est = entry_words(rp.ent);
+    rp.est = entry_bytes(rp.ent);
     const int gi = g_.refs[size_t(i)];
     if (gi == 0 || i - gi < i0 || di == 0) return;
     const int64_t r = i - gi;
@@ -80,15 +105,15 @@ class Builder {
     tmp.clear();
     to_entries(K.data(), K.size(), true, p_.min_interval, tmp);
     to_entries(E.data(), E.size(), false, p_.min_interval, tmp);
-    const int64_t w = entry_words(tmp);
-    if (w < rp.est) {
+    const int64_t b = entry_bytes(tmp);
+    if (b < rp.est) {
       rp.ent.swap(tmp);
       rp.g = gi;
-      rp.est = w;
+      rp.est = b;
     }
   }
 
-  // paper's nonzeros of A' for row i: |v_i - v_r| if smaller than |v_i|, else |v_i|
+  // the paper's nonzeros of A' for row i: |v_i - v_r| if smaller than |v_i|, else |v_i|
   int64_t mprime_row(int64_t i) {
     const int64_t di = int64_t(g_.rowptr[i + 1] - g_.rowptr[i]);
     const int gi = g_.refs[size_t(i)];
@@ -107,6 +132,8 @@ class Builder {
     return diff < di ? diff : di;
   }
 
+  bool is_long_row(const RowPlan& rp) const { return rp.force_long || rp.est > p_.long_row_bytes; }
+
   void run_chunk(int64_t lo, int64_t hi, ChunkOut& co) {
     std::vector<RowPlan> plans;
     std::vector<uint32_t> K, E;
@@ -117,25 +144,25 @@ class Builder {
     while (i < hi) {
       const int64_t i0 = i;
       plans.clear();
-      int64_t words = 0;
+      int64_t bytes = 0;
       while (i < hi && i - i0 < p_.tile_rows) {
         plans.emplace_back();
         RowPlan& rp = plans.back();
         plan_row(i, i0, rp, K, E, tmp);
-        const bool is_long = rp.est > p_.long_row_words;
-        if (!is_long && words + rp.est > p_.word_cap && i > i0) {
+        const bool lng = is_long_row(rp);
+        if (!lng && bytes + rp.est + 48 > p_.stage_bytes && i > i0) {
           plans.pop_back();
           break;
         }
-        if (!is_long) words += rp.est;
+        if (!lng) bytes += rp.est;
         ++i;
       }
-      // emit; shrink the tile while escapes push it past the word cap
+      // emit; shrink the tile while escapes push it past the staging budget
       for (;;) {
         if (emit_tile(i0, plans, level.data() - lo, co)) break;
         if (plans.size() == 1) {
           if (plans[0].force_long) { co.err = "row does not fit a tile"; return; }
-          plans[0].force_long = true;  // escapes overflow the staging: sum it block-wide
+          plans[0].force_long = true;  // sum it block-wide instead
           continue;
         }
         plans.pop_back();
@@ -145,12 +172,9 @@ class Builder {
     }
   }
 
-  bool is_long_row(const RowPlan& rp) const { return rp.force_long || rp.est > p_.long_row_words; }
-
-  // Returns false (and emits nothing) if the coded short rows exceed word_cap.
+  // Returns false (and emits nothing) if the staged streams exceed the budget.
   bool emit_tile(int64_t i0, const std::vector<RowPlan>& plans, uint8_t* level, ChunkOut& co) {
     const int64_t nr = int64_t(plans.size());
-    // window: the span of at most window_cap columns covering most points
     std::vector<uint32_t> pts;
     for (auto& rp : plans) {
       if (is_long_row(rp)) continue;
@@ -159,93 +183,97 @@ class Builder {
         if (e.len) pts.push_back(e.col + e.len - 1);
       }
     }
-    std::sort(pts.begin(), pts.end());
-    uint32_t win0 = uint32_t(i0), winlen = 0;
-    if (!pts.empty()) {
-      size_t best_a = 0, best_b = 0, b = 0;
-      for (size_t a = 0; a < pts.size(); ++a) {
-        if (b < a) b = a;
-        while (b + 1 < pts.size() && int64_t(pts[b + 1]) - int64_t(pts[a]) < p_.window_cap) ++b;
-        if (b - a > best_b - best_a) { best_a = a; best_b = b; }
-      }
-      win0 = pts[best_a];
-      winlen = pts[best_b] - pts[best_a] + 1;
-    }
+    uint32_t win0, winlen;
+    best_window(pts, p_.window_cap, uint32_t(i0), win0, winlen);
     auto in_win = [&](int64_t c) { return c >= int64_t(win0) && c < int64_t(win0) + int64_t(winlen); };
-    // code short rows
-    const size_t wbase = co.words.size();
-    std::vector<uint16_t>& W = co.words;
+    std::vector<uint16_t> s16;
+    std::vector<uint32_t> w32, i32;
     std::vector<uint32_t> info(static_cast<size_t>(nr), 0u);
-    int64_t esc = 0;
+    std::vector<uint16_t> nsv(static_cast<size_t>(nr), 0);
     const size_t lbase = co.longs.size();
+    int64_t esc = 0;
     for (int64_t k = 0; k < nr; ++k) {
       const RowPlan& rp = plans[size_t(k)];
       const int64_t i = i0 + k;
-      const bool is_long = is_long_row(rp);
+      const bool lng = is_long_row(rp);
       const int lvl = rp.g ? level[i - rp.g] + 1 : 0;
       level[i] = uint8_t(lvl);
-      uint64_t len = 0;
-      if (!is_long) {
-        const size_t before = W.size();
+      uint64_t c16 = 0, cw = 0, ci = 0;
+      if (!lng) {
+        const size_t b16 = s16.size(), bw = w32.size(), bi = i32.size();
         auto single = [&](uint32_t c, bool neg) {
-          const uint16_t sg = neg ? 0x8000 : 0;
           if (in_win(c)) {
-            W.push_back(uint16_t(sg | (c - win0)));
+            s16.push_back(uint16_t((neg ? 0x8000u : 0u) | (c - win0)));
           } else {
-            const uint32_t rel = uint32_t(int64_t(c) - int64_t(win0));
-            W.push_back(uint16_t(sg | kEscape));
-            W.push_back(uint16_t(rel >> 16));
-            W.push_back(uint16_t(rel & 0xFFFF));
+            w32.push_back(wide_code(c, win0, neg));
             ++esc;
           }
         };
         for (auto& e : rp.ent) {
           if (e.len == 0) {
             single(e.col, e.neg);
-          } else if (in_win(e.col) && in_win(int64_t(e.col) + e.len - 1)) {
-            W.push_back(uint16_t((e.neg ? 0x8000 : 0) | 0x4000 | (e.col - win0)));
-            W.push_back(uint16_t(e.len));
+          } else if (in_win(e.col) && in_win(int64_t(e.col) + e.len - 1) &&
+                     i32.size() - bi < kMaxIntervalsPerRow) {
+            i32.push_back((e.neg ? 0x80000000u : 0u) | ((e.col - win0) << 16) | e.len);
           } else {
             for (uint32_t t = 0; t < e.len; ++t) single(e.col + t, e.neg);
           }
         }
-        len = W.size() - before;
+        c16 = s16.size() - b16;
+        cw = w32.size() - bw;
+        ci = i32.size() - bi;
+        if (c16 > 0xFFFF || cw >= (1u << 19)) {
+          co.longs.resize(lbase);
+          return false;
+        }
       } else {
         for (auto& e : rp.ent) {
           const uint32_t cnt = e.len ? e.len : 1;
-          for (uint32_t t = 0; t < cnt; ++t) {
-            const int64_t rel = int64_t(e.col + t) - int64_t(win0) + int64_t(kLongBias);
-            co.longs.push_back((e.neg ? 0x80000000u : 0u) | uint32_t(rel));
-          }
-          len += cnt;
+          for (uint32_t t = 0; t < cnt; ++t) co.longs.push_back(wide_code(int64_t(e.col) + t, win0, e.neg));
+          cw += cnt;
         }
+        if (cw >= (uint64_t(1) << 35)) {
+          co.err = "row too long for the layout";
+          return true;
+        }
+        c16 = cw >> 19;
+        cw &= (1u << 19) - 1;
       }
-      if (len >= (1u << 23)) {
-        co.err = "row too long for the layout";
-        return true;
-      }
-      info[size_t(k)] = uint32_t(rp.g) | (uint32_t(lvl) << 4) | (is_long ? kInfoLong : 0u) | (uint32_t(len) << 9);
+      info[size_t(k)] = uint32_t(rp.g) | (uint32_t(lvl) << 4) | (lng ? kInfoLong : 0u) | (uint32_t(ci) << 9) |
+                        (uint32_t(cw) << 13);
+      nsv[size_t(k)] = uint16_t(c16);
     }
-    const int64_t nwords = int64_t(W.size() - wbase);
-    if (nwords > p_.word_cap) {
-      W.resize(wbase);
+    TileDesc td{};
+    td.row0 = uint32_t(i0);
+    td.nrows = uint32_t(nr);
+    td.n16 = uint32_t(s16.size());
+    td.nwide = uint32_t(w32.size());
+    td.nint = uint32_t(i32.size());
+    if (tile_stage_bytes(td) > uint32_t(p_.stage_bytes)) {
       co.longs.resize(lbase);
       return false;
     }
-    // pad to a multiple of 8 words so the next tile starts 16-byte aligned
-    while (W.size() % 8) W.push_back(0);
-    TileDesc td;
-    td.row0 = uint32_t(i0);
-    td.nrows = uint32_t(nr);
-    td.word0 = uint32_t(wbase);
-    td.nwords = uint32_t(nwords);
+    // append the three streams, each padded to 16 bytes
+    const size_t base = co.data.size();
+    td.data16 = uint32_t(base / 16);
+    co.data.resize(base + tile_stage_bytes(td), 0);
+    uint8_t* dst = co.data.data() + base;
+    if (!s16.empty()) std::memcpy(dst, s16.data(), s16.size() * 2);
+    dst += align16u(td.n16 * 2u);
+    if (!w32.empty()) std::memcpy(dst, w32.data(), w32.size() * 4);
+    dst += align16u(td.nwide * 4u);
+    if (!i32.empty()) std::memcpy(dst, i32.data(), i32.size() * 4);
     td.win0 = win0;
     td.winlen = winlen;
     td.long0 = uint32_t(lbase);
     td.graph = 0;
     co.tiles.push_back(td);
     co.info.insert(co.info.end(), info.begin(), info.end());
+    co.ns.insert(co.ns.end(), nsv.begin(), nsv.end());
     co.escapes += esc;
+    co.n_singles += td.n16;
+    co.n_wide += td.nwide;
+    co.n_intervals += td.nint;
     for (int64_t k = 0; k < nr; ++k) {
       const RowPlan& rp = plans[size_t(k)];
       co.units += int64_t(rp.ent.size()) + (rp.g ? 1 : 0);
@@ -264,13 +292,14 @@ class Builder {
 }  // namespace
 
 int build_layout(const DecodedGraph& g, const LayoutParams& prm, int nthreads, HostLayout& out, std::string& err) {
-  if (prm.tile_rows < 1 || prm.tile_rows > 1024 || prm.window_cap < 1 || prm.window_cap > 16383 ||
-      prm.word_cap < 64 || prm.word_cap > 65536 || prm.long_row_words < 1 || prm.min_interval < 2) {
+  if (prm.tile_rows < 1 || prm.tile_rows > kTileRowsMax || prm.window_cap < 1 || prm.window_cap > 32767 ||
+      prm.stage_bytes < 256 || prm.stage_bytes > 65536 || prm.long_row_bytes < 16 ||
+      prm.long_row_bytes > prm.stage_bytes || prm.min_interval < 2) {
     err = "layout parameter out of range";
     return -1;
   }
   if (g.n >= int64_t(kLongBias)) {
-    err = "graph too large for 32-bit relative long entries";
+    err = "graph too large for 31-bit relative entries";
     return -1;
   }
   const int64_t n = g.n;
@@ -295,20 +324,22 @@ int build_layout(const DecodedGraph& g, const LayoutParams& prm, int nthreads, H
   out.prm = prm;
   out.n = n;
   out.info.reserve(size_t(n));
+  out.ns.reserve(size_t(n));
   for (auto& co : outs) {
     if (!co.err.empty()) { err = co.err; return -1; }
-    const uint64_t wb = out.words.size(), lb = out.longs.size();
-    if (wb + co.words.size() >= (uint64_t(1) << 32) || lb + co.longs.size() >= (uint64_t(1) << 32)) {
+    const uint64_t db = out.data.size(), lb = out.longs.size();
+    if ((db + co.data.size()) / 16 >= (uint64_t(1) << 32) || lb + co.longs.size() >= (uint64_t(1) << 32)) {
       err = "layout exceeds 32-bit offsets";
       return -1;
     }
     for (auto td : co.tiles) {
-      td.word0 += uint32_t(wb);
+      td.data16 += uint32_t(db / 16);
       td.long0 += uint32_t(lb);
       out.tiles.push_back(td);
     }
     out.info.insert(out.info.end(), co.info.begin(), co.info.end());
-    out.words.insert(out.words.end(), co.words.begin(), co.words.end());
+    out.ns.insert(out.ns.end(), co.ns.begin(), co.ns.end());
+    out.data.insert(out.data.end(), co.data.begin(), co.data.end());
     out.longs.insert(out.longs.end(), co.longs.begin(), co.longs.end());
     out.units += co.units;
     out.diff_rows += co.diff_rows;
@@ -316,28 +347,44 @@ int build_layout(const DecodedGraph& g, const LayoutParams& prm, int nthreads, H
     out.long_rows += co.long_rows;
     out.escapes += co.escapes;
     out.m_prime += co.m_prime;
+    out.n_singles += co.n_singles;
+    out.n_wide += co.n_wide;
+    out.n_intervals += co.n_intervals;
     out.max_level = std::max(out.max_level, co.max_level);
   }
-  // slack so 16-byte vector loads of the last tile stay in bounds
-  out.words.resize(out.words.size() + 16, 0);
+  out.data.resize(out.data.size() + 16, 0);  // one spare block for vector loads
   if (out.longs.empty()) out.longs.push_back(0);
+  // empty tiles up to a whole block of tiles
+  while (out.tiles.size() % kTilesPerBlock) {
+    TileDesc td{};
+    td.row0 = uint32_t(n);
+    out.tiles.push_back(td);
+  }
   return 0;
 }
 
-void build_csr_tiles(const uint64_t* rowptr, int64_t n, int rows_cap, int col_cap, std::vector<CsrTile>& tiles) {
+void build_csr_tiles(const uint64_t* rowptr, const uint32_t* col, int64_t n, int rows_cap, int col_cap,
+                     int long_cols, int window_cap, std::vector<CsrTile>& tiles) {
   tiles.clear();
+  std::vector<uint32_t> pts;
   int64_t i = 0;
   while (i < n) {
-    const int64_t d = int64_t(rowptr[i + 1] - rowptr[i]);
-    if (d > col_cap) {
-      tiles.push_back({uint32_t(i), 1, uint32_t(rowptr[i]), uint32_t(d)});
+    const uint64_t d = rowptr[i + 1] - rowptr[i];
+    if (d > uint64_t(long_cols)) {
+      tiles.push_back({uint32_t(i), 1u | 0x80000000u, uint32_t(rowptr[i]), uint32_t(d), uint32_t(i), 0, 0, 0});
       ++i;
       continue;
     }
     const int64_t i0 = i;
-    while (i < n && i - i0 < rows_cap && int64_t(rowptr[i + 1] - rowptr[i0]) <= col_cap) ++i;
-    tiles.push_back({uint32_t(i0), uint32_t(i - i0), uint32_t(rowptr[i0]), uint32_t(rowptr[i] - rowptr[i0])});
+    while (i < n && i - i0 < rows_cap && rowptr[i + 1] - rowptr[i] <= uint64_t(long_cols) &&
+           rowptr[i + 1] - rowptr[i0] <= uint64_t(col_cap))
+      ++i;
+    CsrTile t{uint32_t(i0), uint32_t(i - i0), uint32_t(rowptr[i0]), uint32_t(rowptr[i] - rowptr[i0]), 0, 0, 0, 0};
+    pts.assign(col + rowptr[i0], col + rowptr[i]);
+    best_window(pts, window_cap, uint32_t(i0), t.win0, t.winlen);
+    tiles.push_back(t);
   }
+  while (tiles.size() % kTilesPerBlock) tiles.push_back({uint32_t(n), 0, 0, 0, uint32_t(n), 0, 0, 0});
 }
 
 }  // namespace bvmv

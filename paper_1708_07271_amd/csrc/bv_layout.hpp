@@ -2,29 +2,34 @@
 //
 // The product y_i = y_{r_i} + sum_j A'_ij x_j (Section "Our Approach") is
 // organised in tiles of consecutive rows.  A row is either
-//   differential: y_i = y_{r_i} - sum over its skipped entries + sum over the
-//     entries it adds (the row v_i - v_{r_i} of A'), or
+//   differential: y_i = y_{r_i} - sum over the reference entries it skips +
+//     sum over the entries it adds (the row v_i - v_{r_i} of A'), or
 //   direct: y_i = sum over its own list,
-// and a row is differential only when that costs fewer entries than direct
-// (the paper keeps v_i when |v_i - v_{r_i}| >= |v_i|) AND its reference lies
-// in the same tile.  Reference chains therefore never leave a tile, so tiles
-// are independent and a tile resolves its chains level by level in LDS
-// (level = 0 for direct rows, level(r_i) + 1 otherwise, at most R).
+// and a row is differential only when that costs less than direct (the paper
+// keeps v_i when |v_i - v_{r_i}| >= |v_i|) AND its reference lies in the same
+// tile.  Reference chains therefore never leave a tile: tiles are independent
+// and each resolves its chains level by level in LDS (level 0 for direct
+// rows, level(r_i) + 1 otherwise, at most R).
 //
-// Entries are single ids or intervals [s, s+len) of consecutive ids, each
-// with a sign.  Per tile, an x window [win0, win0+winlen) is staged in LDS;
-// short rows are coded in 16-bit words relative to it:
-//   bit 15 = subtract, bit 14 = interval;
-//   single:   bits 0..13 = column - win0 (0x3FFF = escape: the next two words
-//             hold the 32-bit two's-complement column - win0, high word first);
-//   interval: bits 0..13 = start - win0, next word = length (both inside the
-//             window).
-// Rows coded in more than `long_row_words` words are long rows: their entries
-// are 32-bit (bit 31 = subtract, bits 0..30 = column - win0 + 2^30, intervals
-// expanded) and a whole block sums them.
+// A row's entries are signed single ids or signed intervals [s, s+len).  Per
+// tile an x window [win0, win0+winlen) is staged in LDS and the entries are
+// split into three fixed-width streams, each in row order:
+//   singles (u16):   bit 15 = subtract, bits 0..14 = column - win0;
+//   wide (u32):      bit 31 = subtract, bits 0..30 = column - win0 + 2^30
+//                    (columns outside the window; intervals that leave the
+//                    window are expanded into these);
+//   intervals (u32): bit 31 = subtract, bits 16..30 = start - win0,
+//                    bits 0..15 = length (inside the window; at most 15 per
+//                    row, further runs are expanded into singles).
+// The three streams of a tile are contiguous, each padded to 16 bytes, at
+// data16 * 16 bytes.  Rows whose staged bytes exceed `long_row_bytes` are long
+// rows: all their entries go to a per-graph long stream (u32, wide encoding,
+// intervals expanded) that the tile's whole wavefront sums.
 //
-// Row info (u32): bits 0..3 reference gap g (0 for direct), 4..7 level,
-// bit 8 long, bits 9..31 length (words for short rows, entries for long).
+// Row info (u32): bits 0..3 reference gap g (0 = direct), 4..7 level, bit 8
+// long, bits 9..12 interval count, bits 13..31 wide count (long rows: low 19
+// bits of the long-entry count).  Row `ns` (u16): singles count (long rows:
+// high bits of the long-entry count).
 #pragma once
 #include <cstdint>
 #include <string>
@@ -37,47 +42,73 @@ namespace bvmv {
 struct TileDesc {
   uint32_t row0;    // first row (global)
   uint32_t nrows;   // rows in the tile
-  uint32_t word0;   // first 16-bit word of the short rows (multiple of 8)
-  uint32_t nwords;  // words of the short rows
+  uint32_t data16;  // tile streams at data16 * 16 bytes
+  uint32_t n16;     // singles
+  uint32_t nwide;   // wide entries
+  uint32_t nint;    // intervals
   uint32_t win0;    // first column of the x window
   uint32_t winlen;  // window length
-  uint32_t long0;   // first 32-bit entry of the long rows
+  uint32_t long0;   // first long entry of the tile's long rows
   uint32_t graph;   // member index inside a group (0 for a single graph)
+  uint32_t pad0, pad1;
 };
 
+inline uint32_t align16u(uint32_t b) { return (b + 15u) & ~15u; }
+// byte size of a tile's staged streams
+inline uint32_t tile_stage_bytes(const TileDesc& t) {
+  return align16u(t.n16 * 2u) + align16u(t.nwide * 4u) + align16u(t.nint * 4u);
+}
+
+// A tile is processed by one 64-lane wavefront (one row per lane); a block
+// holds kTilesPerBlock consecutive tiles, and tile lists are padded with
+// empty tiles to a multiple of it, so a block never spans two graphs of a
+// group.
+constexpr int kTileRowsMax = 64;
+constexpr int kTilesPerBlock = 4;
+
 struct LayoutParams {
-  int tile_rows = 256;
-  int window_cap = 2048;
-  int word_cap = 4096;       // max short-row words per tile (LDS staging)
-  int long_row_words = 192;
-  int min_interval = 3;      // runs of at least this many ids become intervals
+  int tile_rows = 64;
+  int window_cap = 512;
+  int stage_bytes = 4096;      // max staged stream bytes per tile (LDS)
+  int long_row_bytes = 2048;   // rows staging more than this are summed by the whole wave
+  int min_interval = 3;        // runs of at least this many ids become intervals
 };
 
 struct HostLayout {
   LayoutParams prm;
   std::vector<TileDesc> tiles;
   std::vector<uint32_t> info;
-  std::vector<uint16_t> words;
+  std::vector<uint16_t> ns;
+  std::vector<uint8_t> data;    // staged streams of all tiles (16-byte aligned blocks)
   std::vector<uint32_t> longs;
   int64_t n = 0;
   int64_t units = 0, diff_rows = 0, direct_rows = 0, long_rows = 0, escapes = 0, m_prime = 0;
+  int64_t n_singles = 0, n_wide = 0, n_intervals = 0;
   int max_level = 0;
   int64_t bytes() const {
-    return int64_t(tiles.size() * sizeof(TileDesc) + info.size() * 4 + words.size() * 2 + longs.size() * 4);
+    return int64_t(tiles.size() * sizeof(TileDesc) + info.size() * 4 + ns.size() * 2 + data.size() +
+                   longs.size() * 4);
   }
 };
 
 constexpr uint32_t kInfoLong = 1u << 8;
-constexpr uint32_t kEscape = 0x3FFF;
 constexpr uint32_t kLongBias = 1u << 30;
+constexpr uint32_t kMaxIntervalsPerRow = 15;
+
+inline uint32_t info_g(uint32_t inf) { return inf & 15u; }
+inline uint32_t info_level(uint32_t inf) { return (inf >> 4) & 15u; }
+inline uint32_t info_nint(uint32_t inf) { return (inf >> 9) & 15u; }
+inline uint32_t info_nwide(uint32_t inf) { return inf >> 13; }
 
 int build_layout(const DecodedGraph& g, const LayoutParams& prm, int nthreads, HostLayout& out, std::string& err);
 
-// Plain CSR tiles for the baseline: a tile is either a run of rows whose
-// columns fit `word_cap` entries (staged in LDS) or a single long row.
+// Plain CSR tiles for the baseline: runs of rows whose column ids fit the
+// staging budget (with an x window chosen like the compressed tiles'), or a
+// single long row summed block-wide (bit 31 of nrows).
 struct CsrTile {
-  uint32_t row0, nrows, c0, ncols;  // columns [c0, c0+ncols) of rowptr-relative storage
+  uint32_t row0, nrows, c0, ncols, win0, winlen, pad0, pad1;
 };
-void build_csr_tiles(const uint64_t* rowptr, int64_t n, int rows_cap, int col_cap, std::vector<CsrTile>& tiles);
+void build_csr_tiles(const uint64_t* rowptr, const uint32_t* col, int64_t n, int rows_cap, int col_cap,
+                     int long_cols, int window_cap, std::vector<CsrTile>& tiles);
 
 }  // namespace bvmv

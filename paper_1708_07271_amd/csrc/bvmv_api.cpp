@@ -50,15 +50,21 @@ int default_threads(int req) {
   return int(std::max(1u, std::min(hc ? hc : 4u, 16u)));
 }
 
+// Device copy of count elements, followed by `pad` zeroed elements (so that
+// 16-byte vector loads may run past the last element).
 template <class T>
-int dev_upload(T** dst, const T* src, size_t count) {
+int dev_upload(T** dst, const T* src, size_t count, size_t pad = 0) {
   *dst = nullptr;
-  if (count == 0) count = 1;
-  hipError_t e = hipMalloc(reinterpret_cast<void**>(dst), count * sizeof(T));
+  const size_t alloc = std::max<size_t>(count + pad, 1);
+  hipError_t e = hipMalloc(reinterpret_cast<void**>(dst), alloc * sizeof(T));
   if (e != hipSuccess) { *dst = nullptr; return fail(BVMV_ENOMEM, std::string("hipMalloc: ") + hipGetErrorString(e)); }
-  if (src) {
+  if (src && count) {
     e = hipMemcpy(*dst, src, count * sizeof(T), hipMemcpyHostToDevice);
     if (e != hipSuccess) return fail(BVMV_EDEVICE, std::string("hipMemcpy: ") + hipGetErrorString(e));
+  }
+  if (alloc > count) {
+    e = hipMemset(*dst + count, 0, (alloc - count) * sizeof(T));
+    if (e != hipSuccess) return fail(BVMV_EDEVICE, std::string("hipMemset: ") + hipGetErrorString(e));
   }
   return BVMV_OK;
 }
@@ -166,7 +172,8 @@ struct bvmv_graph {
   // device
   TileDesc* d_tiles = nullptr;
   uint32_t* d_info = nullptr;
-  uint16_t* d_words = nullptr;
+  uint16_t* d_ns = nullptr;
+  uint8_t* d_data = nullptr;
   uint32_t* d_longs = nullptr;
   int32_t* d_outdeg = nullptr;
   DevLayout L;
@@ -181,12 +188,14 @@ struct bvmv_graph {
     pr.release();
     dev_free(d_tiles);
     dev_free(d_info);
-    dev_free(d_words);
+    dev_free(d_ns);
+    dev_free(d_data);
     dev_free(d_longs);
     dev_free(d_outdeg);
     d_tiles = nullptr;
     d_info = nullptr;
-    d_words = nullptr;
+    d_ns = nullptr;
+    d_data = nullptr;
     d_longs = nullptr;
     d_outdeg = nullptr;
     if (cap) (void)hipStreamDestroy(cap);
@@ -209,28 +218,45 @@ struct bvmv_csr {
 
 namespace {
 
+// A launch must fit the device's LDS per block.
+int check_lds(int device, size_t bytes) {
+  int lim = 0;
+  if (hipDeviceGetAttribute(&lim, hipDeviceAttributeMaxSharedMemoryPerBlock, device) != hipSuccess || lim <= 0)
+    lim = 65536;
+  if (bytes > size_t(lim))
+    return fail(BVMV_EINVAL, "layout needs " + std::to_string(bytes) + " bytes of LDS per block, the device allows " +
+                                 std::to_string(lim) + ": lower window_cap or stage_bytes");
+  return BVMV_OK;
+}
+
 int upload_layout(bvmv_graph* g) {
   const HostLayout& hl = g->hl;
   if (int rc = dev_upload(&g->d_tiles, hl.tiles.data(), hl.tiles.size())) return rc;
   if (int rc = dev_upload(&g->d_info, hl.info.data(), hl.info.size())) return rc;
-  if (int rc = dev_upload(&g->d_words, hl.words.data(), hl.words.size())) return rc;
+  if (int rc = dev_upload(&g->d_ns, hl.ns.data(), hl.ns.size())) return rc;
+  if (int rc = dev_upload(&g->d_data, hl.data.data(), hl.data.size())) return rc;
   if (int rc = dev_upload(&g->d_longs, hl.longs.data(), hl.longs.size())) return rc;
   if (int rc = dev_upload(&g->d_outdeg, g->h_outdeg.data(), g->h_outdeg.size())) return rc;
   g->L.tiles = g->d_tiles;
   g->L.info = g->d_info;
-  g->L.words = g->d_words;
+  g->L.ns = g->d_ns;
+  g->L.data = reinterpret_cast<const uint4*>(g->d_data);
   g->L.longs = g->d_longs;
   g->L.ntiles = uint32_t(hl.tiles.size());
+  g->L.n = uint32_t(g->n);
   // LDS carve sizes: the largest use of any tile, rounded up
-  uint32_t tcap = 0, wcap = 0, ecap = 0;
+  uint32_t tcap = 0, wcap = 0, sb = 0;
   for (const auto& t : hl.tiles) {
     tcap = std::max(tcap, t.nrows);
     wcap = std::max(wcap, t.winlen);
-    ecap = std::max(ecap, t.nwords);
+    sb = std::max(sb, tile_stage_bytes(t));
   }
   g->L.tcap = std::max<uint32_t>(64, (tcap + 63) / 64 * 64);
   g->L.wcap = std::max<uint32_t>(64, (wcap + 63) / 64 * 64);
-  g->L.ecap = std::max<uint32_t>(64, (ecap + 63) / 64 * 64);
+  g->L.sbytes = std::max<uint32_t>(256, (sb + 255) / 256 * 256);
+  size_t need = 0;
+  for (int prec = 0; prec <= 2; ++prec) need = std::max(need, bv_kernel_lds_bytes(g->L, prec, g->interval_mode));
+  if (int rc = check_lds(g->device, need)) return rc;
   HIP_TRY(hipStreamCreateWithFlags(&g->cap, hipStreamNonBlocking));
   return BVMV_OK;
 }
@@ -250,8 +276,8 @@ int run_pagerank(PRWork& w, hipStream_t cap, const PROptsResolved& o, int interv
     PRState& st = w.h_st[gI];
     std::memset(&st, 0, sizeof(st));
     st.inv_n = 1.0 / double(offsets[size_t(gI) + 1] - offsets[size_t(gI)]);
-    st.tile_lo = tile_offsets[size_t(gI)];
-    st.tile_hi = tile_offsets[size_t(gI) + 1];
+    st.blk_lo = tile_offsets[size_t(gI)] / kTilesPerBlock;
+    st.blk_hi = tile_offsets[size_t(gI) + 1] / kTilesPerBlock;
   }
   HIP_TRY(hipMemcpyAsync(w.st, w.h_st, sizeof(PRState) * size_t(members), hipMemcpyHostToDevice, s));
   HIP_TRY(init(start, tele, w.p[0], w.z[0], s));
@@ -348,12 +374,13 @@ int bvmv_load(const void* bitstream, size_t nbytes, const bvmv_load_opts* opts, 
   *out = nullptr;
   bvmv_load_opts o{};
   if (opts) o = *opts;
-  if (o.tile_rows == 0) o.tile_rows = 256;
-  if (o.window_cap == 0) o.window_cap = 2048;
-  if (o.long_row_words == 0) o.long_row_words = 192;
-  if (!(o.tile_rows == 128 || o.tile_rows == 256 || o.tile_rows == 512) || o.window_cap < 256 ||
-      o.window_cap > 8192 || o.long_row_words < 16 || o.long_row_words > 4096 || o.interval_mode < 0 ||
-      o.interval_mode > 1 || o.device < 0)
+  if (o.tile_rows == 0) o.tile_rows = kTileRowsMax;
+  if (o.window_cap == 0) o.window_cap = 512;
+  if (o.stage_bytes == 0) o.stage_bytes = 4096;
+  if (o.long_row_bytes == 0) o.long_row_bytes = o.stage_bytes / 2;
+  if (o.tile_rows < 8 || o.tile_rows > kTileRowsMax || o.window_cap < 64 || o.window_cap > 8192 ||
+      o.stage_bytes < 512 || o.stage_bytes > 16384 || o.long_row_bytes < 16 || o.long_row_bytes > o.stage_bytes ||
+      o.interval_mode < 0 || o.interval_mode > 1 || o.device < 0)
     return fail(BVMV_EINVAL, "load option out of range");
   int ndev = 0;
   if (hipGetDeviceCount(&ndev) != hipSuccess || o.device >= ndev) return fail(BVMV_EINVAL, "no such device");
@@ -376,8 +403,8 @@ int bvmv_load(const void* bitstream, size_t nbytes, const bvmv_load_opts* opts, 
   LayoutParams prm;
   prm.tile_rows = o.tile_rows;
   prm.window_cap = o.window_cap;
-  prm.long_row_words = o.long_row_words;
-  prm.word_cap = 4096;
+  prm.long_row_bytes = o.long_row_bytes;
+  prm.stage_bytes = o.stage_bytes;
   if (build_layout(g->dec, prm, nt, g->hl, err)) return fail(BVMV_EINVAL, err);
   g->m_prime = g->hl.m_prime;
   if (o.device_mem_budget && uint64_t(g->hl.bytes()) + uint64_t(g->n) * 4 > o.device_mem_budget)
@@ -425,6 +452,7 @@ int bvmv_multiply_batch(bvmv_graph* g, const void* X, void* Y, int k, int64_t ld
   if (!g || !X || !Y) return fail(BVMV_EINVAL, "null argument");
   if (prec < 0 || prec > 2 || k < 1 || k > 64 || ld < k) return fail(BVMV_EINVAL, "bad batch arguments");
   if (X == Y) return fail(BVMV_EINVAL, "X and Y must not overlap");
+  if (int rc = check_lds(g->device, bv_batch_lds_bytes(g->L, prec, k))) return rc;
   DeviceGuard dg(g->device);
   HIP_TRY(launch_bv_multiply_batch(g->L, prec, X, Y, k, ld, static_cast<hipStream_t>(stream)));
   return BVMV_OK;
@@ -474,21 +502,25 @@ int bvmv_group(bvmv_graph* const* graphs, int count, bvmv_graph** out) {
     if (!m || m->ngraphs != 1) return fail(BVMV_EINVAL, "group members must be loaded graphs");
     if (m->device != g->device || m->interval_mode != g->interval_mode)
       return fail(BVMV_EINVAL, "group members must share device and interval mode");
-    const uint64_t rb = uint64_t(g->n), wb = hl.words.size(), lb = hl.longs.size();
-    if (rb + uint64_t(m->n) >= (uint64_t(1) << 30) || wb + m->hl.words.size() >= (uint64_t(1) << 32) ||
+    const uint64_t rb = uint64_t(g->n), db = hl.data.size(), lb = hl.longs.size();
+    if (rb + uint64_t(m->n) >= (uint64_t(1) << 30) || (db + m->hl.data.size()) / 16 >= (uint64_t(1) << 32) ||
         lb + m->hl.longs.size() >= (uint64_t(1) << 32))
       return fail(BVMV_EINVAL, "group too large");
     for (TileDesc td : m->hl.tiles) {
       td.row0 += uint32_t(rb);
       td.win0 += uint32_t(rb);
-      td.word0 += uint32_t(wb);
+      td.data16 += uint32_t(db / 16);
       td.long0 += uint32_t(lb);
       td.graph = uint32_t(i);
       hl.tiles.push_back(td);
     }
     hl.info.insert(hl.info.end(), m->hl.info.begin(), m->hl.info.end());
-    hl.words.insert(hl.words.end(), m->hl.words.begin(), m->hl.words.end());
+    hl.ns.insert(hl.ns.end(), m->hl.ns.begin(), m->hl.ns.end());
+    hl.data.insert(hl.data.end(), m->hl.data.begin(), m->hl.data.end());
     hl.longs.insert(hl.longs.end(), m->hl.longs.begin(), m->hl.longs.end());
+    hl.n_singles += m->hl.n_singles;
+    hl.n_wide += m->hl.n_wide;
+    hl.n_intervals += m->hl.n_intervals;
     g->h_outdeg.insert(g->h_outdeg.end(), m->h_outdeg.begin(), m->h_outdeg.end());
     hl.units += m->hl.units;
     hl.diff_rows += m->hl.diff_rows;
@@ -545,7 +577,11 @@ int bvmv_get_info(const bvmv_graph* g, bvmv_info* out) {
   out->zeta_k = g->zk;
   out->tile_rows = g->hl.prm.tile_rows;
   out->window_cap = g->hl.prm.window_cap;
-  out->long_row_words = g->hl.prm.long_row_words;
+  out->long_row_bytes = g->hl.prm.long_row_bytes;
+  out->stage_bytes = g->hl.prm.stage_bytes;
+  out->n_singles = g->hl.n_singles;
+  out->n_wide = g->hl.n_wide;
+  out->n_intervals = g->hl.n_intervals;
   out->interval_mode = g->interval_mode;
   out->max_level = g->hl.max_level;
   out->ngraphs = g->ngraphs;
@@ -562,10 +598,15 @@ int bvmv_export_csr(const bvmv_graph* g, uint64_t* rowptr, uint32_t* col) {
 
 // ------------------------------------------------------------------ CSR
 int bvmv_csr_create_host(int64_t n, const uint64_t* rowptr, const uint32_t* col, int device, bvmv_csr** out) {
-  if (n < 1 || !rowptr || !col || !out) return fail(BVMV_EINVAL, "bad CSR arguments");
+  if (n < 1 || !rowptr || !out) return fail(BVMV_EINVAL, "bad CSR arguments");
   *out = nullptr;
   const uint64_t m = rowptr[n];
   if (m >= (uint64_t(1) << 32) - 1) return fail(BVMV_EINVAL, "CSR too large for 32-bit row pointers");
+  static const uint32_t kNoColumns = 0;
+  if (!col) {
+    if (m) return fail(BVMV_EINVAL, "bad CSR arguments");
+    col = &kNoColumns;  // an edgeless graph: never read
+  }
   std::unique_ptr<bvmv_csr> c(new bvmv_csr());
   c->device = device;
   c->n = n;
@@ -577,22 +618,12 @@ int bvmv_csr_create_host(int64_t n, const uint64_t* rowptr, const uint32_t* col,
     if (col[k] >= uint64_t(n)) return fail(BVMV_EINVAL, "column out of range");
     ++outdeg[col[k]];
   }
-  const int rcap = 256, ccap = 4096, long_thr = 192;
-  // tiles: runs of short rows (<= rcap rows, <= ccap columns), long rows alone
-  int64_t i = 0;
-  while (i < n) {
-    const uint64_t d = rowptr[i + 1] - rowptr[i];
-    if (d > uint64_t(long_thr)) {
-      c->tiles.push_back({uint32_t(i), 1u | 0x80000000u, uint32_t(rowptr[i]), uint32_t(d)});
-      ++i;
-      continue;
-    }
-    const int64_t i0 = i;
-    while (i < n && i - i0 < rcap && rowptr[i + 1] - rowptr[i] <= uint64_t(long_thr) &&
-           rowptr[i + 1] - rowptr[i0] <= uint64_t(ccap))
-      ++i;
-    c->tiles.push_back({uint32_t(i0), uint32_t(i - i0), uint32_t(rowptr[i0]), uint32_t(rowptr[i] - rowptr[i0])});
-  }
+  // the compressed layout's defaults: 64 rows per wave, 4 KB of staged ids,
+  // rows over 2 KB summed by the whole wave, x windows up to 512 columns
+  const int rcap = kTileRowsMax, ccap = 1024, long_cols = 512, wcap_max = 512;
+  build_csr_tiles(rowptr, col, n, rcap, ccap, long_cols, wcap_max, c->tiles);
+  uint32_t wcap = 0;
+  for (const auto& t : c->tiles) wcap = std::max(wcap, t.winlen);
   DeviceGuard dg(device);
   if (dg.err != hipSuccess) return fail(BVMV_EDEVICE, "hipSetDevice failed");
   auto cleanup = [&] {
@@ -602,7 +633,7 @@ int bvmv_csr_create_host(int64_t n, const uint64_t* rowptr, const uint32_t* col,
     dev_free(c->d_outdeg);
   };
   if (dev_upload(&c->d_tiles, c->tiles.data(), c->tiles.size()) ||
-      dev_upload(&c->d_rowptr, rp32.data(), rp32.size()) || dev_upload(&c->d_col, col, size_t(m)) ||
+      dev_upload(&c->d_rowptr, rp32.data(), rp32.size()) || dev_upload(&c->d_col, col, size_t(m), 4) ||
       dev_upload(&c->d_outdeg, outdeg.data(), outdeg.size())) {
     cleanup();
     return BVMV_ENOMEM;
@@ -615,8 +646,18 @@ int bvmv_csr_create_host(int64_t n, const uint64_t* rowptr, const uint32_t* col,
   c->C.rowptr = c->d_rowptr;
   c->C.col = c->d_col;
   c->C.ntiles = uint32_t(c->tiles.size());
-  c->C.rcap = rcap;
-  c->C.ccap = ccap;
+  c->C.n = uint32_t(n);
+  c->C.col_len = m + 4;
+  uint32_t cmax = 0;
+  for (const auto& t : c->tiles)
+    if (!(t.nrows & 0x80000000u)) cmax = std::max(cmax, t.ncols);
+  c->C.ccap = std::max<uint32_t>(64, (cmax + 63) / 64 * 64);
+  c->C.wcap = std::max<uint32_t>(64, (wcap + 63) / 64 * 64);
+  if (int rc = check_lds(device, std::max(csr_kernel_lds_bytes(c->C, BVMV_F64), csr_kernel_lds_bytes(c->C, BVMV_F32_COMP)))) {
+    cleanup();
+    (void)hipStreamDestroy(c->cap);
+    return rc;
+  }
   *out = c.release();
   return BVMV_OK;
 }

@@ -11,19 +11,29 @@ namespace bvmv {
 struct DevLayout {
   const TileDesc* tiles = nullptr;
   const uint32_t* info = nullptr;
-  const uint16_t* words = nullptr;
+  const uint16_t* ns = nullptr;
+  const uint4* data = nullptr;
   const uint32_t* longs = nullptr;
-  uint32_t ntiles = 0;
-  uint32_t tcap = 256, wcap = 2048, ecap = 4096;  // LDS carve sizes (>= every tile's use)
+  uint32_t ntiles = 0;                              // a multiple of kTilesPerBlock
+  uint32_t tcap = 64, wcap = 512, sbytes = 4096;    // LDS carve sizes (>= every tile's use)
+  uint32_t n = 0;                                   // rows = columns (length of x)
 };
 
 struct DevCsr {
   const CsrTile* tiles = nullptr;
   const uint32_t* rowptr = nullptr;  // n+1, 32-bit
   const uint32_t* col = nullptr;
-  uint32_t ntiles = 0;
-  uint32_t rcap = 256, ccap = 4096;
+  uint32_t ntiles = 0;               // a multiple of kTilesPerBlock
+  uint32_t ccap = 1024, wcap = 512;
+  uint32_t n = 0;                    // rows = columns
+  uint64_t col_len = 0;              // readable elements of col (m plus padding to a 16-byte boundary)
 };
+
+// LDS bytes per block of the single-vector kernels (0 if the mode is unknown);
+// the loader checks them against the device limit.
+size_t bv_kernel_lds_bytes(const DevLayout& L, int prec, int interval_mode);
+size_t csr_kernel_lds_bytes(const DevCsr& C, int prec);
+size_t bv_batch_lds_bytes(const DevLayout& L, int prec, int k);
 
 // Per-member PageRank state, updated by the last block of every iteration.
 struct PRState {
@@ -35,7 +45,7 @@ struct PRState {
   int32_t converged;
   int32_t final_buf; // buffer (0/1) holding the final iterate once done
   uint32_t ticket;   // blocks of the current launch that have finished
-  uint32_t tile_lo, tile_hi;  // tile range of the member
+  uint32_t blk_lo, blk_hi;    // block range of the member (kTilesPerBlock tiles per block)
   uint32_t pad;
 };
 

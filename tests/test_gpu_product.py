@@ -52,9 +52,9 @@ def _csr_mul(P, C, x, prec):
     return yd.cpu().numpy()
 
 
-LAYOUTS = [dict(), dict(tile_rows=128, window_cap=256, long_row_words=16),
-           dict(tile_rows=512, window_cap=8192, long_row_words=4096), dict(interval_mode=1),
-           dict(tile_rows=256, window_cap=512, long_row_words=40, interval_mode=1)]
+LAYOUTS = [dict(), dict(tile_rows=16, window_cap=64, stage_bytes=512, long_row_bytes=16),
+           dict(tile_rows=64, window_cap=2048, stage_bytes=8192), dict(interval_mode=1),
+           dict(tile_rows=32, window_cap=256, stage_bytes=1024, long_row_bytes=40, interval_mode=1)]
 
 
 def _graphs():

@@ -84,20 +84,20 @@ def test_decode_rejects_corruption(P):
             assert e.code == P.BVMV_EFORMAT
 
 
-LAYOUT_CASES = [(256, 2048, 192), (128, 256, 16), (512, 8192, 4096), (256, 512, 40)]
+LAYOUT_CASES = [(64, 1024, 4096, 2048), (16, 64, 512, 16), (64, 8192, 16384, 16384), (32, 256, 1024, 40)]
 
 
-@pytest.mark.parametrize("tile_rows,window_cap,long_words", LAYOUT_CASES)
-def test_layout_interpreter_matches_oracle(P, tile_rows, window_cap, long_words):
+@pytest.mark.parametrize("tile_rows,window_cap,stage,long_bytes", LAYOUT_CASES)
+def test_layout_interpreter_matches_oracle(P, tile_rows, window_cap, stage, long_bytes):
     graphs = [B.web_graph(30_000, 20.0, 41), B.social_graph(20_000, 30.0, 3000, 2.1, 42)]
     for g in graphs:
         enc = B.encode(g)
         x = B.integer_x(g.n, 7, 1000)
-        y, st = P.bvmv_layout_selfcheck(enc.data, x, tile_rows, window_cap, long_words)
+        y, st = P.bvmv_layout_selfcheck(enc.data, x, tile_rows, window_cap, stage, long_bytes)
         assert np.array_equal(y, product.matvec(g.rowptr, g.col, x))
         assert st["max_level"] <= 3
         x = B.uniform_x(g.n, 8)
-        y, _ = P.bvmv_layout_selfcheck(enc.data, x, tile_rows, window_cap, long_words)
+        y, _ = P.bvmv_layout_selfcheck(enc.data, x, tile_rows, window_cap, stage, long_bytes)
         y0 = product.matvec(g.rowptr, g.col, x)
         assert np.max(np.abs(y - y0) / np.maximum(y0, 1e-300)) < 1e-12
 
