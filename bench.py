@@ -88,6 +88,10 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
     ap.add_argument("--only", choices=["bv", "csr", "all"], default="all",
                     help="restrict the timed kernels (profiling runs)")
+    ap.add_argument("--tile-rows", type=int, default=0)
+    ap.add_argument("--window-cap", type=int, default=0)
+    ap.add_argument("--stage-bytes", type=int, default=0)
+    ap.add_argument("--interval-mode", type=int, default=0)
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py runs on one GPU only: the compressed product and PageRank here are single-GPU "
@@ -107,7 +111,8 @@ def main():
     enc = B.encode(g)
     log("graph n=%d m=%d bitstream %.1f MB (%.2f bits/edge) in %.1fs" % (
         g.n, g.m, enc.data.size / 1e6, enc.data.size * 8 / g.m, time.perf_counter() - t0))
-    G = P.bvmv_load(enc.data, keep_lists=1)
+    G = P.bvmv_load(enc.data, keep_lists=1, tile_rows=args.tile_rows, window_cap=args.window_cap,
+                    stage_bytes=args.stage_bytes, interval_mode=args.interval_mode)
     info = G.info()
     C = P.bvmv_csr_create(G)
     log("layout %.1f MB, units %d, m' %d, escapes %d, long rows %d; csr %.1f MB" % (

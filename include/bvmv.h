@@ -60,7 +60,7 @@ typedef enum {
 /* Layout and tuning options of bvmv_load.  Zero fields take defaults. */
 typedef struct {
   int device;            /* HIP device ordinal */
-  int tile_rows;         /* rows per tile (one wavefront each): 8..64 (0 = 64) */
+  int tile_rows;         /* rows per tile (one wavefront each, up to 2 rows a lane): 8..128 (0 = 64) */
   int window_cap;        /* max x-window columns staged per tile: 64..8192 (0 = 512) */
   int stage_bytes;       /* max entry-stream bytes staged in LDS per tile: 512..16384 (0 = 4096) */
   int long_row_bytes;    /* rows staging more than this are summed by the whole wave (0 = stage_bytes/2) */

@@ -2,9 +2,9 @@
 // baseline, the fused PageRank iteration and the multi-vector product.
 // gfx950, wave64.
 //
-// Single-vector kernels: a tile of up to 64 rows is processed by one
-// wavefront, one row per lane, with no block-wide barrier; a 256-thread
-// block holds 4 consecutive tiles.  A tile's rows are direct or reuse the
+// Single-vector kernels: a tile of up to 128 rows is processed by one
+// wavefront, one or two rows per lane, with no block-wide barrier; a
+// 256-thread block holds 4 consecutive tiles.  A tile's rows are direct or reuse the
 // sum of a reference row inside the same tile (y_i = y_{r_i} +
 // sum_j A'_ij x_j, the algorithm after the Proposition of Section "Our
 // Approach"), so tiles are independent:
@@ -13,11 +13,12 @@
 //   2. a wave scan of the per-row counts gives the stream offsets; with
 //      prefix mode an exclusive prefix P of the window (double) turns an
 //      interval [s, s+len) into P[s+len] - P[s];
-//   3. singles and wide entries are summed by merge-style flat passes: each
-//      lane takes an equal contiguous chunk of entries whatever the row
-//      lengths, and a row split over several lanes is completed by its
-//      owning lane, which adds the later lanes' pieces in lane order
-//      (deterministic);
+//   3. singles and wide entries are summed by tagged flat passes: each lane
+//      takes an equal contiguous chunk of entries whatever the row lengths,
+//      reads it 16 bytes at a time and cuts it at row ends, which the row
+//      owners mark beforehand with a one-byte tag per entry; a row split over
+//      several lanes is completed by its owner, which adds the pieces in lane
+//      order (deterministic);
 //   4. each lane adds its row's intervals; long rows are summed by the whole
 //      wave (fixed reduction tree);
 //   5. reuse levels 1..max: y_i = y_{i-g_i} + partial_i in LDS;
@@ -187,13 +188,12 @@ __device__ __forceinline__ void wave_copy16(const void* __restrict__ src, void* 
   const uint32_t nv = nbytes / 16;
   const uint4* s = static_cast<const uint4*>(src);
   uint4* d = static_cast<uint4*>(dst);
+  // Loads are unconditional (lanes past the end re-read the last vector) so
+  // that the batch stays in registers.
   for (uint32_t base = 0; base < nv; base += 64 * kBatch) {
     uint4 r[kBatch];
 #pragma unroll
-    for (int j = 0; j < kBatch; ++j) {
-      const uint32_t k = base + lane + 64u * j;
-      if (k < nv) r[j] = s[k];
-    }
+    for (int j = 0; j < kBatch; ++j) r[j] = s[min(base + lane + 64u * j, nv - 1)];
 #pragma unroll
     for (int j = 0; j < kBatch; ++j) {
       const uint32_t k = base + lane + 64u * j;
@@ -271,74 +271,112 @@ __device__ __forceinline__ double block_sum_f64(double a, double* s_red) {
   return r;
 }
 
-// Merge-style flat pass of one wave over E entries of a stream split into
-// rows by the exclusive offsets off[0..nrows] (off[nrows] == E).  Lane l sums
-// entries [l*C, (l+1)*C), C = ceil(E/64), cutting at row ends; it adds the
-// pieces of rows that start in its chunk to part[], and keeps the first piece
-// of a row begun by an earlier lane in carry[l].  The lane owning a row that
-// runs past its chunk then adds the following lanes' pieces in lane order,
-// so the result does not depend on scheduling.
-template <class M, class ValFn>
-__device__ __forceinline__ void flat_pass_wave(uint32_t E, uint32_t nrows, const uint32_t* off,
-                                               typename M::PAcc* part, typename M::PAcc* carry, ValFn val) {
-  using PAcc = typename M::PAcc;
-  const uint32_t lane = lane_id();
-  const uint32_t C = (E + 63) / 64;
-  const uint32_t b = min(E, lane * C), end = min(E, b + C);
-  uint32_t own = 0xFFFFFFFFu;  // row owned here that continues past `end`
-  if (b < end) {
-    uint32_t lo = 0, hi = nrows;  // off[lo] <= b < off[hi]
-    while (hi - lo > 1) {
-      const uint32_t mid = (lo + hi) >> 1;
-      if (off[mid] <= b) lo = mid;
-      else hi = mid;
-    }
-    uint32_t r = lo, e = b;
-    bool owner = off[r] == b;
-    while (e < end) {
-      const uint32_t rend = off[r + 1];
-      const uint32_t stop = min(rend, end);
-      PAcc a = M::pzero();
-      for (; e < stop; ++e) M::padd(a, val(e));
-      if (owner) {
-        part[r] = M::pcomb(part[r], a);
-        if (rend > end) own = r;
-      } else {
-        carry[lane] = a;
-      }
-      owner = true;
-      ++r;
-      while (r < nrows && off[r + 1] == e) ++r;  // rows without entries here
-    }
-  }
-  wave_sync();
-  if (own != 0xFFFFFFFFu) {
-    const uint32_t rend = off[own + 1];
-    PAcc s = part[own];
-    for (uint32_t l = lane + 1; l * C < rend; ++l) s = M::pcomb(s, carry[l]);
-    part[own] = s;
-  }
-  wave_sync();
+// q = a / C for a < 2^24 and a wave-uniform C >= 1 (float estimate, then an
+// exact correction).
+__device__ __forceinline__ uint32_t div_small(uint32_t a, uint32_t C, float invC) {
+  uint32_t q = uint32_t(float(a) * invC);
+  if (q * C > a) --q;
+  else if ((q + 1) * C <= a) ++q;
+  return q;
 }
 
-// per-wave LDS carve of the tile kernel (bytes from the wave's base)
-template <class M, bool PREFIX>
+// Chunk length of a tagged pass over E entries: ceil(E / 64) rounded up to a
+// multiple of 8, so that every lane's chunk starts on a 16-byte boundary of
+// the stream and of the tag array.
+__device__ __forceinline__ uint32_t tagged_chunk(uint32_t E) { return ((E + 63) / 64 + 7) & ~7u; }
+
+// Tagged flat pass of one wave over the entries [lo, E) of a stream in LDS.
+// Entry e's tag is the tile row whose LAST entry it is, or 0xFF.  Lane l sums
+// its chunk [l*C, (l+1)*C) in order, K = 16 / sizeof(W) entries per 16-byte
+// read; at a tagged entry the running sum (the row's piece inside this chunk)
+// goes to seg[row] and restarts, and the sum left at the chunk end goes to
+// carry[l].  A row that starts in an earlier chunk is completed afterwards by
+// its owner (tagged_row_sum), so no lane waits on another inside the loop and
+// the summation order is fixed.
+template <class M, class W, class ValFn>
+__device__ __forceinline__ void tagged_pass(uint32_t lo, uint32_t E, uint32_t C, const W* words,
+                                            const uint8_t* tags, typename M::PAcc* seg, typename M::PAcc* carry,
+                                            ValFn val) {
+  using PAcc = typename M::PAcc;
+  using X = typename M::X;
+  constexpr uint32_t K = 16 / sizeof(W);
+  const uint32_t lane = lane_id();
+  const uint32_t b = lane * C;
+  if (b >= E) return;
+  const uint32_t end = min(E, b + C);
+  PAcc a = M::pzero();
+  for (uint32_t e = b; e < end; e += K) {
+    const uint4 q = *reinterpret_cast<const uint4*>(words + e);
+    uint32_t tg[K / 4];
+    if constexpr (K == 8) {
+      const uint2 t2 = *reinterpret_cast<const uint2*>(tags + e);
+      tg[0] = t2.x;
+      tg[1] = t2.y;
+    } else {
+      tg[0] = *reinterpret_cast<const uint32_t*>(tags + e);
+    }
+    const uint32_t qw[4] = {q.x, q.y, q.z, q.w};
+    X v[K];
+#pragma unroll
+    for (uint32_t j = 0; j < K; ++j) {
+      const uint32_t w = K == 8 ? ((qw[j / 2] >> (16 * (j & 1))) & 0xFFFFu) : qw[j];
+      const bool ok = e + j >= lo && e + j < end;
+      v[j] = val(w, ok);
+    }
+#pragma unroll
+    for (uint32_t j = 0; j < K; ++j) {
+      M::padd(a, v[j]);
+      const uint32_t t = (tg[j / 4] >> (8 * (j & 3))) & 0xFFu;
+      if (t != 0xFFu && e + j < end) {
+        seg[t] = a;
+        a = M::pzero();
+      }
+    }
+  }
+  carry[lane] = a;
+}
+
+// Owner side of a tagged pass: the sum of the owner's row occupying entries
+// [ob, oe) (oe > ob) of a pass with chunk length C: the pieces of the earlier
+// chunks it spans (carry, in lane order), then its final piece (seg).
+template <class M>
+__device__ __forceinline__ typename M::PAcc tagged_row_sum(uint32_t ob, uint32_t oe, uint32_t C, float invC,
+                                                           const typename M::PAcc* seg_row,
+                                                           const typename M::PAcc* carry) {
+  const uint32_t L0 = div_small(ob, C, invC), L1 = div_small(oe - 1, C, invC);
+  if (L1 == L0) return *seg_row;
+  typename M::PAcc s = carry[L0];
+  for (uint32_t l = L0 + 1; l < L1; ++l) s = M::pcomb(s, carry[l]);
+  return M::pcomb(s, *seg_row);
+}
+
+// Fill n bytes (n a multiple of 16) of LDS with 0xFF.
+__device__ __forceinline__ void wave_fill_ff(uint8_t* dst, uint32_t n) {
+  uint4* d = reinterpret_cast<uint4*>(dst);
+  const uint4 ff = make_uint4(~0u, ~0u, ~0u, ~0u);
+  for (uint32_t k = lane_id(); k < n / 16; k += 64) d[k] = ff;
+}
+
+// per-wave LDS carve of the tile kernel (bytes from the wave's base); a
+// wave holds up to 64 * RPL rows, RPL consecutive rows per lane
+template <class M, bool PREFIX, int RPL>
 struct WaveCarve {
   using X = typename M::X;
   using PAcc = typename M::PAcc;
   using CAcc = typename M::CAcc;
+  static constexpr uint32_t kRows = 64 * RPL;
   uint32_t WC, SB;
-  __host__ __device__ static constexpr size_t off16() { return 0; }
-  __host__ __device__ static constexpr size_t offw() { return align16(65 * 4); }
-  // y shares the partials' slots: each lane reads its own partial before it
-  // writes its own y, and other lanes' y are read only after a wave_sync
+  // y shares the pieces' slots: they are read by their owners before the
+  // reuse levels write y
   static constexpr size_t kSlot = sizeof(PAcc) > sizeof(CAcc) ? sizeof(PAcc) : sizeof(CAcc);
-  __host__ __device__ static constexpr size_t part() { return 2 * align16(65 * 4); }
-  __host__ __device__ static constexpr size_t y() { return part(); }
-  __host__ __device__ static constexpr size_t carry() { return part() + align16(64 * kSlot); }
+  __host__ __device__ static constexpr size_t seg() { return 0; }
+  __host__ __device__ static constexpr size_t y() { return 0; }
+  __host__ __device__ static constexpr size_t carry() { return align16(kRows * kSlot); }
   __host__ __device__ static constexpr size_t x() { return carry() + align16(64 * sizeof(PAcc)); }
   __host__ __device__ size_t P() const { return x() + (M::kInt ? 0 : align16(size_t(WC) * sizeof(X) + 16)); }
-  __host__ __device__ size_t data() const { return P() + (PREFIX && !M::kInt ? align16((size_t(WC) + 1) * 8) : 0); }
+  __host__ __device__ size_t tags() const { return P() + (PREFIX && !M::kInt ? align16((size_t(WC) + 1) * 8) : 0); }
+  // one tag byte per single (the longer of the two tagged streams)
+  __host__ __device__ size_t data() const { return tags() + align16(size_t(SB) / 2 + 16); }
   __host__ __device__ size_t wave_bytes() const { return data() + align16(size_t(SB)); }
   __host__ __device__ size_t block_bytes() const { return kWaves * wave_bytes() + 256; }
 };
@@ -353,8 +391,7 @@ template <class M>
 struct EpiStore {
   typename M::X* y;
   __device__ void operator()(const TileCtx& tc, const typename M::CAcc* s_y, unsigned char*) const {
-    const uint32_t lane = lane_id();
-    if (lane < tc.nrows) y[tc.row0 + lane] = M::out(s_y[lane]);
+    for (uint32_t r = lane_id(); r < tc.nrows; r += 64) y[tc.row0 + r] = M::out(s_y[r]);
   }
 };
 
@@ -430,17 +467,16 @@ struct EpiPR {
     PRState* st = a.st + tc.graph;
     const double delta = st->delta, inv_n = st->inv_n, beta = a.beta;
     double rs = 0.0, dg = 0.0;
-    const uint32_t lane = lane_id();
-    if (lane < tc.nrows) {
-      const uint32_t v = tc.row0 + lane;
-      const double y = M::to_d(s_y[lane]);
+    for (uint32_t r = lane_id(); r < tc.nrows; r += 64) {
+      const uint32_t v = tc.row0 + r;
+      const double y = M::to_d(s_y[r]);
       const double t = tele ? double(tele[v]) : inv_n;
       const X pnew = X((1.0 - beta) * t + beta * (y + delta * t));
       pn[v] = pnew;
       const int32_t d = a.outdeg[v];
       zn[v] = d > 0 ? pnew / X(d) : X(0);
-      rs = fabs(double(pnew) - double(p[v]));
-      if (d == 0) dg = double(pnew);
+      rs += fabs(double(pnew) - double(p[v]));
+      if (d == 0) dg += double(pnew);
     }
     rs = wave_sum_f64(rs);
     dg = wave_sum_f64(dg);
@@ -449,59 +485,71 @@ struct EpiPR {
 };
 
 // --------------------------------------------------------------- tile kernel
-template <class M, bool PREFIX, class Epi>
+// One wavefront per tile of up to 64 * RPL rows; lane l owns rows
+// [l * RPL, (l + 1) * RPL).
+template <class M, bool PREFIX, int RPL, class Epi>
 __global__ void __launch_bounds__(kThreads) bv_wave_kernel(DevLayout L, const typename M::X* __restrict__ x,
                                                            Epi epi, const PRState* __restrict__ skip_done) {
   using X = typename M::X;
   using PAcc = typename M::PAcc;
   using CAcc = typename M::CAcc;
+  using Cv = WaveCarve<M, PREFIX, RPL>;
   extern __shared__ __align__(16) unsigned char smem[];
   const uint32_t wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const uint32_t lane = lane_id();
   const uint32_t tile = blockIdx.x * kWaves + wave;
   const TileDesc td = L.tiles[tile];
   if (skip_done && skip_done[L.tiles[blockIdx.x * kWaves].graph].done) return;  // whole block, one member
-  const WaveCarve<M, PREFIX> cv{L.wcap, L.sbytes};
+  const Cv cv{L.wcap, L.sbytes};
   unsigned char* ws = smem + size_t(wave) * cv.wave_bytes();
   unsigned char* s_blk = smem + size_t(kWaves) * cv.wave_bytes();
-  uint32_t* s_o16 = reinterpret_cast<uint32_t*>(ws + cv.off16());
-  uint32_t* s_ow = reinterpret_cast<uint32_t*>(ws + cv.offw());
-  PAcc* s_part = reinterpret_cast<PAcc*>(ws + cv.part());
+  PAcc* s_seg = reinterpret_cast<PAcc*>(ws + cv.seg());
   CAcc* s_y = reinterpret_cast<CAcc*>(ws + cv.y());
   PAcc* s_carry = reinterpret_cast<PAcc*>(ws + cv.carry());
   X* s_xbuf = reinterpret_cast<X*>(ws + cv.x());
   double* s_P = reinterpret_cast<double*>(ws + cv.P());
+  uint8_t* s_tags = reinterpret_cast<uint8_t*>(ws + cv.tags());
   unsigned char* s_data = ws + cv.data();
   const uint32_t nrows = td.nrows;
   const int64_t win0 = td.win0;
   const uint32_t winlen = td.winlen;
-  const bool has_row = lane < nrows;
+  const uint32_t r0 = lane * RPL;
 
   // 1. all global loads of the tile
-  const uint32_t inf = has_row ? L.info[td.row0 + lane] : 0u;
-  const uint32_t ns = has_row ? uint32_t(L.ns[td.row0 + lane]) : 0u;
+  uint32_t inf[RPL], ns[RPL];
+#pragma unroll
+  for (int q = 0; q < RPL; ++q) {
+    const bool has = r0 + q < nrows;
+    inf[q] = has ? L.info[td.row0 + r0 + q] : 0u;
+    ns[q] = has ? uint32_t(L.ns[td.row0 + r0 + q]) : 0u;
+  }
   wave_copy16<4>(L.data + td.data16, s_data, dstage_bytes(td));
   const X* s_x = s_xbuf;
   if constexpr (!M::kInt) s_x = stage_range<X>(x, L.n, win0, winlen, s_xbuf);
-  s_part[lane] = M::pzero();
   const uint16_t* s16 = reinterpret_cast<const uint16_t*>(s_data);
   const uint32_t* w32 = reinterpret_cast<const uint32_t*>(s_data + dalign16u(td.n16 * 2u));
   const uint32_t* i32 = reinterpret_cast<const uint32_t*>(s_data + dalign16u(td.n16 * 2u) + dalign16u(td.nwide * 4u));
+  wave_fill_ff(s_tags, dalign16u(td.n16 + 16));
 
-  // 2. stream offsets: singles | wide << 20 | intervals << 40
-  const bool is_long = inf & kInfoLong;
-  const uint32_t ni = is_long ? 0u : ((inf >> 9) & 15u);
-  const uint64_t A = is_long ? 0 : (uint64_t(ns) | (uint64_t(inf >> 13) << 20) | (uint64_t(ni) << 40));
-  uint64_t totA;
-  const uint64_t ex = wave_excl_scan_u64(A, totA);
-  s_o16[lane] = uint32_t(ex & 0xFFFFFu);
-  s_ow[lane] = uint32_t((ex >> 20) & 0xFFFFFu);
-  const uint32_t oi = uint32_t(ex >> 40);
-  if (lane == 0) {
-    s_o16[64] = uint32_t(totA & 0xFFFFFu);
-    s_ow[64] = uint32_t((totA >> 20) & 0xFFFFFu);
+  // 2. stream offsets: singles | wide << 20 | intervals << 40, one scan
+  uint64_t A[RPL];
+  uint64_t Asum = 0;
+#pragma unroll
+  for (int q = 0; q < RPL; ++q) {
+    const bool lng = inf[q] & kInfoLong;
+    A[q] = lng ? 0 : (uint64_t(ns[q]) | (uint64_t(inf[q] >> 13) << 20) | (uint64_t((inf[q] >> 9) & 15u) << 40));
+    Asum += A[q];
   }
-  const uint32_t lvl = (inf >> 4) & 15u;
+  uint64_t totA;
+  uint64_t run = wave_excl_scan_u64(Asum, totA);
+  uint32_t o16[RPL], ow[RPL], oi[RPL];
+#pragma unroll
+  for (int q = 0; q < RPL; ++q) {
+    o16[q] = uint32_t(run & 0xFFFFFu);
+    ow[q] = uint32_t((run >> 20) & 0xFFFFFu);
+    oi[q] = uint32_t(run >> 40);
+    run += A[q];
+  }
   if constexpr (PREFIX && !M::kInt) {
     if (td.nint) {
       wave_sync();
@@ -518,22 +566,49 @@ __global__ void __launch_bounds__(kThreads) bv_wave_kernel(DevLayout L, const ty
       if (lane == 0) s_P[winlen] = tot;
     }
   }
+  wave_sync();  // tag fill before the owners' tags
+#pragma unroll
+  for (int q = 0; q < RPL; ++q)
+    if (A[q] & 0xFFFFFu) s_tags[o16[q] + ns[q] - 1] = uint8_t(r0 + q);
   wave_sync();
 
-  // 3. singles, then wide entries
-  if (td.n16)
-    flat_pass_wave<M>(td.n16, nrows, s_o16, s_part, s_carry, [&](uint32_t e) -> X {
-      const uint32_t w = s16[e];
+  // 3. singles, then wide entries (tagged flat passes); the owner adds its
+  //    rows' pieces to its registers
+  PAcc a[RPL];
+#pragma unroll
+  for (int q = 0; q < RPL; ++q) a[q] = M::pzero();
+  if (td.n16) {
+    const uint32_t C = tagged_chunk(td.n16);
+    const float invC = 1.0f / float(C);
+    tagged_pass<M, uint16_t>(0, td.n16, C, s16, s_tags, s_seg, s_carry, [&](uint32_t w, bool ok) -> X {
+      // words past the chunk are zero padding or later chunks' entries, so
+      // the gather stays inside the window and is masked afterwards
       if constexpr (M::kInt) {
-        return (w & 0x8000u) ? -1 : 1;
+        return ok ? ((w & 0x8000u) ? -1 : 1) : 0;
       } else {
-        const X v = s_x[w & 0x7FFFu];
-        return (w & 0x8000u) ? -v : v;
+        X v = s_x[w & 0x7FFFu];
+        v = (w & 0x8000u) ? -v : v;
+        return ok ? v : X(0);
       }
     });
-  if (td.nwide)
-    flat_pass_wave<M>(td.nwide, nrows, s_ow, s_part, s_carry, [&](uint32_t e) -> X {
-      const uint32_t w = w32[e];
+    wave_sync();
+#pragma unroll
+    for (int q = 0; q < RPL; ++q)
+      if (A[q] & 0xFFFFFu) a[q] = tagged_row_sum<M>(o16[q], o16[q] + ns[q], C, invC, s_seg + r0 + q, s_carry);
+  }
+  if (td.nwide) {
+    const uint32_t E = td.nwide;
+    wave_sync();  // the singles' pieces are read
+    wave_fill_ff(s_tags, dalign16u(E + 16));
+    wave_sync();
+#pragma unroll
+    for (int q = 0; q < RPL; ++q)
+      if ((A[q] >> 20) & 0xFFFFFu) s_tags[ow[q] + (inf[q] >> 13) - 1] = uint8_t(r0 + q);
+    wave_sync();
+    const uint32_t C = tagged_chunk(E);
+    const float invC = 1.0f / float(C);
+    tagged_pass<M, uint32_t>(0, E, C, w32, s_tags, s_seg, s_carry, [&](uint32_t w, bool ok) -> X {
+      if (!ok) return X(0);
       if constexpr (M::kInt) {
         return (w & 0x80000000u) ? -1 : 1;
       } else {
@@ -542,69 +617,104 @@ __global__ void __launch_bounds__(kThreads) bv_wave_kernel(DevLayout L, const ty
         return (w & 0x80000000u) ? -v : v;
       }
     });
-  PAcc a = s_part[lane];
+    wave_sync();
+#pragma unroll
+    for (int q = 0; q < RPL; ++q)
+      if ((A[q] >> 20) & 0xFFFFFu)
+        a[q] = M::pcomb(a[q], tagged_row_sum<M>(ow[q], ow[q] + (inf[q] >> 13), C, invC, s_seg + r0 + q, s_carry));
+  }
 
-  // 4. the lane's intervals
-  for (uint32_t q = 0; q < ni; ++q) {
-    const uint32_t w = i32[oi + q];
-    const uint32_t s = (w >> 16) & 0x7FFFu, ln = w & 0xFFFFu;
-    const bool neg = w & 0x80000000u;
-    if constexpr (M::kInt) {
-      M::padd(a, neg ? -int32_t(ln) : int32_t(ln));
-    } else if constexpr (PREFIX) {
-      const double d = s_P[s + ln] - s_P[s];
-      M::padd_d(a, neg ? -d : d);
-    } else {
-      for (uint32_t t = 0; t < ln; ++t) M::padd(a, neg ? -s_x[s + t] : s_x[s + t]);
+  // 4. each lane's intervals
+#pragma unroll
+  for (int q = 0; q < RPL; ++q) {
+    const uint32_t ni = (inf[q] & kInfoLong) ? 0u : ((inf[q] >> 9) & 15u);
+    for (uint32_t t = 0; t < ni; ++t) {
+      const uint32_t w = i32[oi[q] + t];
+      const uint32_t s = (w >> 16) & 0x7FFFu, ln = w & 0xFFFFu;
+      const bool neg = w & 0x80000000u;
+      if constexpr (M::kInt) {
+        M::padd(a[q], neg ? -int32_t(ln) : int32_t(ln));
+      } else if constexpr (PREFIX) {
+        const double d = s_P[s + ln] - s_P[s];
+        M::padd_d(a[q], neg ? -d : d);
+      } else {
+        for (uint32_t u = 0; u < ln; ++u) M::padd(a[q], neg ? -s_x[s + u] : s_x[s + u]);
+      }
     }
   }
   //    long rows, the whole wave each
-  uint64_t lmask = __ballot(is_long);
-  if (lmask) {
-    const uint64_t cnt = is_long ? (uint64_t(inf >> 13) | (uint64_t(ns) << 19)) : 0;
+  bool any_long = false;
+#pragma unroll
+  for (int q = 0; q < RPL; ++q) any_long |= (inf[q] & kInfoLong) != 0;
+  if (__ballot(any_long)) {
+    uint64_t cnt[RPL], csum = 0;
+#pragma unroll
+    for (int q = 0; q < RPL; ++q) {
+      cnt[q] = (inf[q] & kInfoLong) ? (uint64_t(inf[q] >> 13) | (uint64_t(ns[q]) << 19)) : 0;
+      csum += cnt[q];
+    }
     uint64_t totL;
-    const uint64_t exL = wave_excl_scan_u64(cnt, totL);
-    while (lmask) {
-      const int r = __ffsll(static_cast<unsigned long long>(lmask)) - 1;
-      lmask &= lmask - 1;
-      const uint64_t len = __shfl(cnt, r, 64);
-      const uint64_t off = __shfl(exL, r, 64);
-      const uint32_t* e = L.longs + size_t(td.long0) + off;
-      PAcc s = M::pzero();
-      // batches of 8 entries per lane: all loads, then all gathers, then adds
-      for (uint64_t base = 0; base < len; base += 64 * 8) {
-        uint32_t w[8];
+    uint64_t exL = wave_excl_scan_u64(csum, totL);
+    uint64_t offq[RPL];
 #pragma unroll
-        for (int j = 0; j < 8; ++j) {
-          const uint64_t k = base + lane + 64u * j;
-          w[j] = k < len ? e[k] : 0u;
-        }
-        X v[8];
+    for (int q = 0; q < RPL; ++q) {
+      offq[q] = exL;
+      exL += cnt[q];
+    }
 #pragma unroll
-        for (int j = 0; j < 8; ++j) {
-          if constexpr (M::kInt) {
-            v[j] = 1;
-          } else {
-            const int64_t c = int64_t(w[j] & 0x7FFFFFFFu) - int64_t(kLongBias);
-            v[j] = base + lane + 64u * j >= len ? X(0) : (uint64_t(c) < winlen ? s_x[c] : x[win0 + c]);
+    for (int q = 0; q < RPL; ++q) {
+      uint64_t lmask = __ballot((inf[q] & kInfoLong) != 0);
+      while (lmask) {
+        const int l = __ffsll(static_cast<unsigned long long>(lmask)) - 1;
+        lmask &= lmask - 1;
+        const uint64_t len = __shfl(cnt[q], l, 64);
+        const uint64_t off = __shfl(offq[q], l, 64);
+        const uint32_t* e = L.longs + size_t(td.long0) + off;
+        PAcc s = M::pzero();
+        // batches of 8 entries per lane: all loads, then all gathers, then adds
+        for (uint64_t base = 0; base < len; base += 64 * 8) {
+          uint32_t w[8];
+#pragma unroll
+          for (int j = 0; j < 8; ++j) {
+            const uint64_t k = base + lane + 64u * j;
+            w[j] = k < len ? e[k] : 0u;
           }
-        }
+          X v[8];
 #pragma unroll
-        for (int j = 0; j < 8; ++j)
-          if (base + lane + 64u * j < len) M::padd(s, (w[j] & 0x80000000u) ? -v[j] : v[j]);
+          for (int j = 0; j < 8; ++j) {
+            if constexpr (M::kInt) {
+              v[j] = 1;
+            } else {
+              const int64_t c = int64_t(w[j] & 0x7FFFFFFFu) - int64_t(kLongBias);
+              v[j] = base + lane + 64u * j >= len ? X(0) : (uint64_t(c) < winlen ? s_x[c] : x[win0 + c]);
+            }
+          }
+#pragma unroll
+          for (int j = 0; j < 8; ++j)
+            if (base + lane + 64u * j < len) M::padd(s, (w[j] & 0x80000000u) ? -v[j] : v[j]);
+        }
+        s = wave_reduce<M>(s);
+        if (lane == uint32_t(l)) a[q] = s;
       }
-      s = wave_reduce<M>(s);
-      if (lane == uint32_t(r)) a = s;
     }
   }
 
-  // 5. reuse levels: y_i = y_{i-g} + partial_i, while some lane has a row at
-  //    the level
-  const CAcc ca = M::chain(a);
-  if (lvl == 0) s_y[lane] = ca;
-  for (uint32_t lv = 1; __ballot(lvl >= lv); ++lv) {
+  // 5. reuse levels: y_i = y_{i-g} + partial_i, while some row is at the level
+  wave_sync();  // every piece is read before y overwrites the slots
+  CAcc ca[RPL];
+  uint32_t lvmax = 0;
+#pragma unroll
+  for (int q = 0; q < RPL; ++q) {
+    ca[q] = M::chain(a[q]);
+    const uint32_t lv = (inf[q] >> 4) & 15u;
+    lvmax = max(lvmax, lv);
+    if (lv == 0) s_y[r0 + q] = ca[q];
+  }
+  for (uint32_t lv = 1; __ballot(lvmax >= lv); ++lv) {
     wave_sync();
-    if (lvl == lv) s_y[lane] = M::comb(s_y[lane - (inf & 15u)], ca);
+#pragma unroll
+    for (int q = 0; q < RPL; ++q)
+      if (((inf[q] >> 4) & 15u) == lv) s_y[r0 + q] = M::comb(s_y[r0 + q - (inf[q] & 15u)], ca[q]);
   }
   wave_sync();
   // 6. epilogue
@@ -632,8 +742,8 @@ __global__ void __launch_bounds__(kThreads) pr_init_kernel(const uint32_t* __res
   X* p0 = static_cast<X*>(p0_);
   X* z0 = static_cast<X*>(z0_);
   double dg = 0.0;
-  if (lane < nrows) {
-    const uint32_t v = row0 + lane;
+  for (uint32_t r = lane; r < nrows; r += 64) {
+    const uint32_t v = row0 + r;
     const X pv = start ? start[v] : (tele ? tele[v] : X(st->inv_n));
     p0[v] = pv;
     const int32_t d = outdeg[v];
@@ -655,12 +765,13 @@ struct CsrCarve {
   using PAcc = typename M::PAcc;
   using CAcc = typename M::CAcc;
   uint32_t WC, CC;
-  __host__ __device__ static constexpr size_t off() { return 0; }
-  __host__ __device__ static constexpr size_t part() { return align16(65 * 4); }
-  __host__ __device__ static constexpr size_t y() { return part() + align16(64 * sizeof(PAcc)); }
-  __host__ __device__ static constexpr size_t carry() { return y() + align16(64 * sizeof(CAcc)); }
+  static constexpr size_t kSlot = sizeof(PAcc) > sizeof(CAcc) ? sizeof(PAcc) : sizeof(CAcc);
+  __host__ __device__ static constexpr size_t seg() { return 0; }  // y shares the pieces' slots
+  __host__ __device__ static constexpr size_t y() { return 0; }
+  __host__ __device__ static constexpr size_t carry() { return align16(64 * kSlot); }
   __host__ __device__ static constexpr size_t x() { return carry() + align16(64 * sizeof(PAcc)); }
-  __host__ __device__ size_t col() const { return x() + align16(size_t(WC) * sizeof(X) + 16); }
+  __host__ __device__ size_t tags() const { return x() + align16(size_t(WC) * sizeof(X) + 16); }
+  __host__ __device__ size_t col() const { return tags() + align16(size_t(CC) + 32); }
   __host__ __device__ size_t wave_bytes() const { return col() + align16(size_t(CC) * 4 + 16); }
   __host__ __device__ size_t block_bytes() const { return kWaves * wave_bytes() + 256; }
 };
@@ -682,11 +793,11 @@ __global__ void __launch_bounds__(kThreads) csr_wave_kernel(DevCsr C, const type
   const CsrCarve<M> cv{C.wcap, C.ccap};
   unsigned char* ws = smem + size_t(wave) * cv.wave_bytes();
   unsigned char* s_blk = smem + size_t(kWaves) * cv.wave_bytes();
-  uint32_t* s_off = reinterpret_cast<uint32_t*>(ws + cv.off());
-  PAcc* s_part = reinterpret_cast<PAcc*>(ws + cv.part());
+  PAcc* s_seg = reinterpret_cast<PAcc*>(ws + cv.seg());
   CAcc* s_y = reinterpret_cast<CAcc*>(ws + cv.y());
   PAcc* s_carry = reinterpret_cast<PAcc*>(ws + cv.carry());
   X* s_xbuf = reinterpret_cast<X*>(ws + cv.x());
+  uint8_t* s_tags = reinterpret_cast<uint8_t*>(ws + cv.tags());
   uint32_t* s_colbuf = reinterpret_cast<uint32_t*>(ws + cv.col());
   if (is_long) {
     PAcc s = M::pzero();
@@ -710,18 +821,39 @@ __global__ void __launch_bounds__(kThreads) csr_wave_kernel(DevCsr C, const type
   } else {
     const int64_t win0 = td.win0;
     const uint32_t winlen = td.winlen;
-    if (lane <= nrows) s_off[lane] = C.rowptr[td.row0 + lane] - td.c0;
-    if (lane == 0 && nrows == 64) s_off[64] = C.rowptr[td.row0 + 64] - td.c0;
-    const uint32_t* s_col = stage_range<uint32_t>(C.col, C.col_len, td.c0, td.ncols, s_colbuf);
+    // the lane's row: entries [ob, oe) counted from the 16-byte aligned
+    // start of the staged column ids
+    const uint32_t shift = td.c0 & 3u;
+    uint32_t ob = 0, oe = 0;
+    if (lane < nrows) {
+      ob = uint32_t(C.rowptr[td.row0 + lane] - td.c0) + shift;
+      oe = uint32_t(C.rowptr[td.row0 + lane + 1] - td.c0) + shift;
+    }
+    stage_range<uint32_t>(C.col, C.col_len, td.c0, td.ncols, s_colbuf);
     const X* s_x = stage_range<X>(x, C.n, win0, winlen, s_xbuf);
-    s_part[lane] = M::pzero();
+    const uint32_t E = td.ncols + shift;
+    wave_fill_ff(s_tags, dalign16u(E + 16));
     wave_sync();
-    if (td.ncols)
-      flat_pass_wave<M>(td.ncols, nrows, s_off, s_part, s_carry, [&](uint32_t e) -> X {
-        const int64_t c = int64_t(s_col[e]) - win0;
-        return uint64_t(c) < winlen ? s_x[c] : x[win0 + c];
+    if (oe > ob) s_tags[oe - 1] = uint8_t(lane);
+    wave_sync();
+    PAcc a = M::pzero();
+    if (td.ncols) {
+      const uint32_t Cc = tagged_chunk(E);
+      const float invC = 1.0f / float(Cc);
+      // every staged word is a column id < n (neighbouring rows' or the
+      // zero padding), so only the choice of source depends on `ok`
+      tagged_pass<M, uint32_t>(shift, E, Cc, s_colbuf, s_tags, s_seg, s_carry, [&](uint32_t c, bool ok) -> X {
+        const int64_t d = int64_t(c) - win0;
+        const bool inwin = uint64_t(d) < winlen;
+        X v = s_x[inwin ? uint32_t(d) : 0u];
+        if (ok && !inwin) v = x[c];
+        return ok ? v : X(0);
       });
-    s_y[lane] = M::chain(s_part[lane]);
+      wave_sync();
+      if (oe > ob) a = tagged_row_sum<M>(ob, oe, Cc, invC, s_seg + lane, s_carry);
+      wave_sync();  // pieces read before y overwrites the slots
+    }
+    s_y[lane] = M::chain(a);
   }
   wave_sync();
   epi(TileCtx{td.row0, nrows, 0u}, s_y, s_blk);
@@ -780,11 +912,11 @@ template <class M, int G>
 struct BatchCarve {
   using PAcc = typename M::PAcc;
   using CAcc = typename M::CAcc;
-  uint32_t SB;
-  static constexpr size_t u = align16(65 * 4);
-  __host__ __device__ static constexpr size_t acc() { return 7 * u; }
-  __host__ __device__ static constexpr size_t tmp() { return acc() + align16(64 * G * sizeof(CAcc)); }
-  __host__ __device__ static constexpr size_t data() { return tmp() + align16(kThreads * sizeof(PAcc)); }
+  uint32_t T, SB;  // rows per tile (<= 256, one per thread), staged bytes
+  __host__ __device__ size_t u() const { return align16((size_t(T) + 1) * 4); }
+  __host__ __device__ size_t acc() const { return 7 * u(); }
+  __host__ __device__ size_t tmp() const { return acc() + align16(size_t(T) * G * sizeof(CAcc)); }
+  __host__ __device__ size_t data() const { return tmp() + align16(kThreads * sizeof(PAcc)); }
   __host__ __device__ size_t red() const { return data() + align16(size_t(SB)); }
   __host__ __device__ size_t total() const { return red() + 256; }
 };
@@ -798,8 +930,8 @@ __global__ void __launch_bounds__(kThreads) bv_batch_kernel(DevLayout L, const t
   constexpr uint32_t kTeams = kThreads / G;
   extern __shared__ __align__(16) unsigned char smem[];
   const TileDesc td = L.tiles[blockIdx.x];
-  const BatchCarve<M, G> cv{L.sbytes};
-  constexpr size_t u = BatchCarve<M, G>::u;
+  const BatchCarve<M, G> cv{L.tcap, L.sbytes};
+  const size_t u = cv.u();
   uint32_t* s_info = reinterpret_cast<uint32_t*>(smem);
   uint32_t* s_ns = reinterpret_cast<uint32_t*>(smem + u);
   uint32_t* s_o16 = reinterpret_cast<uint32_t*>(smem + 2 * u);
@@ -902,20 +1034,35 @@ hipError_t set_lds(const void* k, size_t smem) {
   return hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, int(smem));
 }
 
+// rows per lane of the kernel instance that covers the layout's tiles
+inline int rows_per_lane(const DevLayout& L) { return L.tcap <= 64 ? 1 : 2; }
+static_assert(kTileRowsMax <= 128, "row tags are bytes below 0xFF");
+
 template <class M, bool PREFIX>
 size_t tile_lds(const DevLayout& L) {
-  return WaveCarve<M, PREFIX>{L.wcap, L.sbytes}.block_bytes();
+  switch (rows_per_lane(L)) {
+    case 1: return WaveCarve<M, PREFIX, 1>{L.wcap, L.sbytes}.block_bytes();
+    default: return WaveCarve<M, PREFIX, 2>{L.wcap, L.sbytes}.block_bytes();
+  }
 }
 
-template <class M, bool PREFIX, class Epi>
-hipError_t launch_tile(const DevLayout& L, const void* x, const Epi& epi, const PRState* skip, hipStream_t s) {
-  const size_t smem = tile_lds<M, PREFIX>(L);
-  auto k = bv_wave_kernel<M, PREFIX, Epi>;
+template <class M, bool PREFIX, int RPL, class Epi>
+hipError_t launch_tile_rpl(const DevLayout& L, const void* x, const Epi& epi, const PRState* skip, hipStream_t s) {
+  const size_t smem = WaveCarve<M, PREFIX, RPL>{L.wcap, L.sbytes}.block_bytes();
+  auto k = bv_wave_kernel<M, PREFIX, RPL, Epi>;
   if (hipError_t e = set_lds(reinterpret_cast<const void*>(k), smem)) return e;
   if (L.ntiles == 0) return hipSuccess;
   hipLaunchKernelGGL(k, dim3(L.ntiles / kWaves), dim3(kThreads), smem, s, L, static_cast<const typename M::X*>(x),
                      epi, skip);
   return hipGetLastError();
+}
+
+template <class M, bool PREFIX, class Epi>
+hipError_t launch_tile(const DevLayout& L, const void* x, const Epi& epi, const PRState* skip, hipStream_t s) {
+  switch (rows_per_lane(L)) {
+    case 1: return launch_tile_rpl<M, PREFIX, 1>(L, x, epi, skip, s);
+    default: return launch_tile_rpl<M, PREFIX, 2>(L, x, epi, skip, s);
+  }
 }
 
 template <class M>
@@ -936,7 +1083,7 @@ hipError_t launch_csr(const DevCsr& Cs, const void* x, const Epi& epi, const PRS
 
 template <class M, int G>
 size_t batch_lds(const DevLayout& L) {
-  return BatchCarve<M, G>{L.sbytes}.total();
+  return BatchCarve<M, G>{L.tcap, L.sbytes}.total();
 }
 
 template <class M, int G>
@@ -958,8 +1105,8 @@ inline int team_width(int k) {
 }
 
 template <class M>
-size_t batch_lds_k(const DevLayout& L, int k) {
-  switch (team_width(k)) {
+size_t batch_lds_g(const DevLayout& L, int G) {
+  switch (G) {
     case 64: return batch_lds<M, 64>(L);
     case 32: return batch_lds<M, 32>(L);
     case 16: return batch_lds<M, 16>(L);
@@ -968,9 +1115,23 @@ size_t batch_lds_k(const DevLayout& L, int k) {
   }
 }
 
+// team width halved while the tile's T x G accumulators exceed 96 KB of LDS
+// (further right-hand sides are taken by extra passes over the tile)
+template <class M>
+int pick_g(const DevLayout& L, int k) {
+  int G = team_width(k);
+  while (G > 4 && batch_lds_g<M>(L, G) > 96 * 1024) G /= 2;
+  return G;
+}
+
+template <class M>
+size_t batch_lds_k(const DevLayout& L, int k) {
+  return batch_lds_g<M>(L, pick_g<M>(L, k));
+}
+
 template <class M>
 hipError_t launch_batch(const DevLayout& L, const void* X, void* Y, int k, int64_t ld, hipStream_t s) {
-  switch (team_width(k)) {
+  switch (pick_g<M>(L, k)) {
     case 64: return launch_batch_g<M, 64>(L, X, Y, k, ld, s);
     case 32: return launch_batch_g<M, 32>(L, X, Y, k, ld, s);
     case 16: return launch_batch_g<M, 16>(L, X, Y, k, ld, s);

@@ -59,11 +59,11 @@ inline uint32_t tile_stage_bytes(const TileDesc& t) {
   return align16u(t.n16 * 2u) + align16u(t.nwide * 4u) + align16u(t.nint * 4u);
 }
 
-// A tile is processed by one 64-lane wavefront (one row per lane); a block
-// holds kTilesPerBlock consecutive tiles, and tile lists are padded with
-// empty tiles to a multiple of it, so a block never spans two graphs of a
-// group.
-constexpr int kTileRowsMax = 64;
+// A tile is processed by one 64-lane wavefront (up to 2 consecutive rows per
+// lane); a block holds kTilesPerBlock consecutive tiles, and tile lists are
+// padded with empty tiles to a multiple of it, so a block never spans two
+// graphs of a group.
+constexpr int kTileRowsMax = 128;
 constexpr int kTilesPerBlock = 4;
 
 struct LayoutParams {

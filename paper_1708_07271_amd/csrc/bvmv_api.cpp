@@ -374,7 +374,7 @@ int bvmv_load(const void* bitstream, size_t nbytes, const bvmv_load_opts* opts, 
   *out = nullptr;
   bvmv_load_opts o{};
   if (opts) o = *opts;
-  if (o.tile_rows == 0) o.tile_rows = kTileRowsMax;
+  if (o.tile_rows == 0) o.tile_rows = 64;
   if (o.window_cap == 0) o.window_cap = 512;
   if (o.stage_bytes == 0) o.stage_bytes = 4096;
   if (o.long_row_bytes == 0) o.long_row_bytes = o.stage_bytes / 2;
@@ -620,7 +620,7 @@ int bvmv_csr_create_host(int64_t n, const uint64_t* rowptr, const uint32_t* col,
   }
   // the compressed layout's defaults: 64 rows per wave, 4 KB of staged ids,
   // rows over 2 KB summed by the whole wave, x windows up to 512 columns
-  const int rcap = kTileRowsMax, ccap = 1024, long_cols = 512, wcap_max = 512;
+  const int rcap = 64, ccap = 1024, long_cols = 512, wcap_max = 512;
   build_csr_tiles(rowptr, col, n, rcap, ccap, long_cols, wcap_max, c->tiles);
   uint32_t wcap = 0;
   for (const auto& t : c->tiles) wcap = std::max(wcap, t.winlen);
