@@ -61,11 +61,11 @@ typedef enum {
 typedef struct {
   int device;            /* HIP device ordinal */
   int tile_rows;         /* rows per tile (one wavefront each, up to 2 rows a lane): 8..128 (0 = 64) */
-  int window_cap;        /* max x-window columns staged per tile: 64..8192 (0 = 512) */
+  int window_cap;        /* max x-window columns staged per tile: 64..8191 (0 = 512) */
   int stage_bytes;       /* max entry-stream bytes staged in LDS per tile: 512..16384 (0 = 4096) */
   int long_row_bytes;    /* rows staging more than this are summed by the whole wave (0 = stage_bytes/2) */
-  int interval_mode;     /* 0 = intervals summed entry by entry from the LDS window (default);
-                            1 = interval sums from a per-tile prefix of x, P[s+len] - P[s] */
+  int interval_mode;     /* 0 = interval sums from a per-tile prefix of x, P[s+len] - P[s] (default);
+                            1 = intervals summed entry by entry from the staged x window */
   int autotune;          /* 1 = time candidate layouts at load and keep the fastest */
   int keep_lists;        /* 1 = keep the decoded lists on the host (export, CSR baseline) */
   int nthreads;          /* host decode / layout threads (0 = hardware concurrency, max 16) */

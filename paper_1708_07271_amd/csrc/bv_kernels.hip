@@ -67,7 +67,8 @@ struct MF64 {
   __device__ static X out(CAcc a) { return a; }
   __device__ static double to_d(CAcc a) { return a; }
 };
-// float everywhere: the naive mode
+// float everywhere: the naive mode (window values and prefix sums are read
+// from the staged doubles and rounded to float)
 struct MF32 {
   using X = float;
   using PAcc = float;
@@ -127,7 +128,7 @@ __host__ __device__ constexpr size_t align16(size_t v) { return (v + 15) & ~size
 __device__ __forceinline__ uint32_t dalign16u(uint32_t b) { return (b + 15u) & ~15u; }
 // staged stream bytes of a tile (same sum as tile_stage_bytes on the host)
 __device__ __forceinline__ uint32_t dstage_bytes(const TileDesc& t) {
-  return dalign16u(t.n16 * 2u) + dalign16u(t.nwide * 4u) + dalign16u(t.nint * 4u);
+  return dalign16u(t.n16 * 2u) + dalign16u(t.nwide * 4u);
 }
 
 // ------------------------------------------------------------- wave helpers
@@ -280,74 +281,198 @@ __device__ __forceinline__ uint32_t div_small(uint32_t a, uint32_t C, float invC
   return q;
 }
 
-// Chunk length of a tagged pass over E entries: ceil(E / 64) rounded up to a
-// multiple of 8, so that every lane's chunk starts on a 16-byte boundary of
-// the stream and of the tag array.
-__device__ __forceinline__ uint32_t tagged_chunk(uint32_t E) { return ((E + 63) / 64 + 7) & ~7u; }
-
-// Tagged flat pass of one wave over the entries [lo, E) of a stream in LDS.
-// Entry e's tag is the tile row whose LAST entry it is, or 0xFF.  Lane l sums
-// its chunk [l*C, (l+1)*C) in order, K = 16 / sizeof(W) entries per 16-byte
-// read; at a tagged entry the running sum (the row's piece inside this chunk)
-// goes to seg[row] and restarts, and the sum left at the chunk end goes to
-// carry[l].  A row that starts in an earlier chunk is completed afterwards by
-// its owner (tagged_row_sum), so no lane waits on another inside the loop and
-// the summation order is fixed.
-template <class M, class W, class ValFn>
-__device__ __forceinline__ void tagged_pass(uint32_t lo, uint32_t E, uint32_t C, const W* words,
-                                            const uint8_t* tags, typename M::PAcc* seg, typename M::PAcc* carry,
-                                            ValFn val) {
-  using PAcc = typename M::PAcc;
-  using X = typename M::X;
-  constexpr uint32_t K = 16 / sizeof(W);
-  const uint32_t lane = lane_id();
-  const uint32_t b = lane * C;
-  if (b >= E) return;
-  const uint32_t end = min(E, b + C);
-  PAcc a = M::pzero();
-  for (uint32_t e = b; e < end; e += K) {
-    const uint4 q = *reinterpret_cast<const uint4*>(words + e);
-    uint32_t tg[K / 4];
-    if constexpr (K == 8) {
-      const uint2 t2 = *reinterpret_cast<const uint2*>(tags + e);
-      tg[0] = t2.x;
-      tg[1] = t2.y;
-    } else {
-      tg[0] = *reinterpret_cast<const uint32_t*>(tags + e);
-    }
-    const uint32_t qw[4] = {q.x, q.y, q.z, q.w};
-    X v[K];
-#pragma unroll
-    for (uint32_t j = 0; j < K; ++j) {
-      const uint32_t w = K == 8 ? ((qw[j / 2] >> (16 * (j & 1))) & 0xFFFFu) : qw[j];
-      const bool ok = e + j >= lo && e + j < end;
-      v[j] = val(w, ok);
-    }
-#pragma unroll
-    for (uint32_t j = 0; j < K; ++j) {
-      M::padd(a, v[j]);
-      const uint32_t t = (tg[j / 4] >> (8 * (j & 3))) & 0xFFu;
-      if (t != 0xFFu && e + j < end) {
-        seg[t] = a;
-        a = M::pzero();
-      }
-    }
-  }
-  carry[lane] = a;
+// Inclusive wave scan of a u32 by DPP row shifts and row broadcasts (no LDS).
+__device__ __forceinline__ uint32_t wave_incl_scan_u32(uint32_t v) {
+  int x = int(v);
+  x += __builtin_amdgcn_update_dpp(0, x, 0x111, 0xf, 0xf, true);  // row_shr:1
+  x += __builtin_amdgcn_update_dpp(0, x, 0x112, 0xf, 0xf, true);  // row_shr:2
+  x += __builtin_amdgcn_update_dpp(0, x, 0x114, 0xf, 0xf, true);  // row_shr:4
+  x += __builtin_amdgcn_update_dpp(0, x, 0x118, 0xf, 0xf, true);  // row_shr:8
+  x += __builtin_amdgcn_update_dpp(0, x, 0x142, 0xa, 0xf, false); // row_bcast:15 into rows 1, 3
+  x += __builtin_amdgcn_update_dpp(0, x, 0x143, 0xc, 0xf, false); // row_bcast:31 into rows 2, 3
+  return uint32_t(x);
 }
 
-// Owner side of a tagged pass: the sum of the owner's row occupying entries
+// One DPP step of a double scan: the value of the lane `ctrl` selects
+// (0 outside the row or in rows the row mask leaves out) is added.
+template <int kCtrl, int kRowMask, bool kBound>
+__device__ __forceinline__ double dpp_add_f64(double v) {
+  const uint64_t b = uint64_t(__double_as_longlong(v));
+  const uint32_t lo = uint32_t(__builtin_amdgcn_update_dpp(0, int(uint32_t(b)), kCtrl, kRowMask, 0xf, kBound));
+  const uint32_t hi = uint32_t(__builtin_amdgcn_update_dpp(0, int(uint32_t(b >> 32)), kCtrl, kRowMask, 0xf, kBound));
+  return v + __longlong_as_double(int64_t((uint64_t(hi) << 32) | lo));
+}
+
+// Inclusive wave scan of a double (same DPP pattern as the u32 scan).
+__device__ __forceinline__ double wave_incl_scan_f64(double v) {
+  v = dpp_add_f64<0x111, 0xf, true>(v);
+  v = dpp_add_f64<0x112, 0xf, true>(v);
+  v = dpp_add_f64<0x114, 0xf, true>(v);
+  v = dpp_add_f64<0x118, 0xf, true>(v);
+  v = dpp_add_f64<0x142, 0xa, false>(v);
+  v = dpp_add_f64<0x143, 0xc, false>(v);
+  return v;
+}
+
+// Stage a tile's x window into the LDS array Z (doubles): Z[0] = 0,
+// Z[2j+2] = x[win0+j] for j < n, and, with `prefix`, Z[2p+1] = P[p] =
+// x[win0] + ... + x[win0+p-1] for p <= n (odd entries are left undefined
+// otherwise; no entry reads them then).  Lane l takes the ceil(n/64)
+// consecutive values from l*ceil(n/64) on, 8 loads in flight; a wave scan of
+// the lanes' sums gives each lane's first prefix.  Z + 1 is 16-byte aligned,
+// so every (P[j], x[j]) pair is one 16-byte LDS write.
+template <class X>
+__device__ __forceinline__ void stage_window(const X* __restrict__ x, int64_t win0, uint32_t n, bool prefix,
+                                             double* Z) {
+  const uint32_t lane = lane_id();
+  const uint32_t ch = (n + 63) / 64;
+  const uint32_t b = min(n, lane * ch), e = min(n, b + ch);
+  const uint32_t ng = (e - b + 7) / 8;
+  const X* xw = x + win0;
+  X v[8];
+  double t = 0.0;
+  for (uint32_t g = 0; g < ng; ++g) {
+    const uint32_t k = b + 8 * g;
+#pragma unroll
+    for (int j = 0; j < 8; ++j) v[j] = xw[min(k + uint32_t(j), e - 1)];
+    if (prefix)
+#pragma unroll
+      for (int j = 0; j < 8; ++j)
+        if (k + uint32_t(j) < e) t += double(v[j]);
+  }
+  double run = 0.0;
+  if (prefix) {
+    const double inc = wave_incl_scan_f64(t);
+    run = inc - t;
+    if (lane == 63) Z[2 * size_t(n) + 1] = inc;
+  }
+  if (lane == 0) Z[0] = 0.0;
+  double2* Zp = reinterpret_cast<double2*>(Z + 1);  // Zp[j] = (P[j], x[win0+j])
+  for (uint32_t g = 0; g < ng; ++g) {
+    const uint32_t k = b + 8 * g;
+    if (ng > 1)
+#pragma unroll
+      for (int j = 0; j < 8; ++j) v[j] = xw[min(k + uint32_t(j), e - 1)];
+#pragma unroll
+    for (int j = 0; j < 8; ++j)
+      if (k + uint32_t(j) < e) {
+        const double xv = double(v[j]);
+        Zp[k + j] = make_double2(run, xv);
+        run += xv;
+      }
+  }
+}
+
+// set bits of m in the lanes below this one
+__device__ __forceinline__ uint32_t lanes_below(uint64_t m) {
+  return __builtin_amdgcn_mbcnt_hi(uint32_t(m >> 32), __builtin_amdgcn_mbcnt_lo(uint32_t(m), 0u));
+}
+
+// Chunk length of a flat pass over E entries: ceil(E / 64) rounded up to a
+// multiple of `Q` (so that a lane's chunk starts on a 4-byte boundary of a
+// u16 stream, Q = 2, or on a 4-entry boundary of the CSR tags, Q = 4).
+template <uint32_t Q>
+__device__ __forceinline__ uint32_t flat_chunk(uint32_t E) { return ((E + 63) / 64 + Q - 1) / Q * Q; }
+
+constexpr int kRound = 8;  // stream dwords a lane has in flight per round of a flat pass
+
+// Load dwords first .. first + kRound - 1 of a stream, clamped to its last
+// dword (never out of bounds; clamped dwords are never used).
+__device__ __forceinline__ void load_round(const uint32_t* __restrict__ g, uint32_t first, uint32_t last,
+                                           uint32_t (&d)[kRound]) {
+#pragma unroll
+  for (int k = 0; k < kRound; ++k) d[k] = g[min(first + uint32_t(k), last)];
+}
+
+// Geometry of a lane's chunk of a flat pass: P entries per dword, the chunk
+// [b, b + C) clipped to the E entries, nd dwords from dword d0 on, and the
+// stream's last dword.
+template <uint32_t P>
+struct Chunk {
+  uint32_t b, nd, d0, last;
+  __device__ Chunk(uint32_t E, uint32_t C) {
+    b = lane_id() * C;
+    const uint32_t cnt = b < E ? min(E, b + C) - b : 0u;
+    nd = (cnt + P - 1) / P;
+    d0 = b / P;
+    last = E ? (E + P - 1) / P - 1 : 0u;
+  }
+};
+
+// Flat pass of one wave over a stream of E entries (P per dword) whose last
+// entry in every row carries the row-end bit kEnd.  Lane l sums its chunk
+// [l*C, min(E, (l+1)*C)) in order, kRound dwords per round (the first round,
+// `pre`, loaded by the caller ahead of other work): every value of the round
+// is read first, then the running sum takes them in order.  At a row end the
+// running sum -- that row's piece in this chunk -- goes to seg[slot] and
+// restarts, slot counting the rows that end in the stream from `slot0` on
+// (the lane's exclusive count of row ends); the sum left at the chunk end
+// goes to carry[l].  A row that starts in an earlier chunk is completed by
+// its owner (flat_row_sum): no lane waits on another inside the loop, and the
+// summation order is fixed.  Dwords past the chunk are clamped copies of
+// stream words (their values are read but not added); with u16 words the
+// chunk's last dword may hold the zero padding word after the stream's end,
+// which `val` maps to 0.
+template <class M, uint32_t P, uint32_t kEnd, class ValFn, class AddFn>
+__device__ __forceinline__ void end_pass(uint32_t E, uint32_t C, const uint32_t* __restrict__ g,
+                                         const uint32_t (&pre)[kRound], uint32_t slot0, typename M::PAcc* seg,
+                                         typename M::PAcc* carry, ValFn val, AddFn add) {
+  using PAcc = typename M::PAcc;
+  const Chunk<P> ch(E, C);
+  if (ch.nd == 0) return;
+  PAcc a = M::pzero();
+  uint32_t slot = slot0;
+  auto round = [&](const uint32_t (&d)[kRound], uint32_t r) {
+    decltype(val(0u)) v[kRound * P];
+#pragma unroll
+    for (int k = 0; k < kRound; ++k)
+#pragma unroll
+      for (uint32_t h = 0; h < P; ++h) v[k * P + h] = val(P == 2 ? (h ? d[k] >> 16 : d[k] & 0xFFFFu) : d[k]);
+#pragma unroll
+    for (int k = 0; k < kRound; ++k) {
+      if (r + uint32_t(k) >= ch.nd) break;
+#pragma unroll
+      for (uint32_t h = 0; h < P; ++h) {
+        add(a, v[k * P + h]);
+        if ((P == 2 ? (h ? d[k] >> 16 : d[k]) : d[k]) & kEnd) {
+          seg[slot++] = a;
+          a = M::pzero();
+        }
+      }
+    }
+  };
+  round(pre, 0);
+  for (uint32_t r = kRound; r < ch.nd; r += kRound) {
+    uint32_t q[kRound];
+    load_round(g, ch.d0 + r, ch.last, q);
+    round(q, r);
+  }
+  carry[lane_id()] = a;
+}
+
+// Row ends inside the lane's chunk of an end-bit stream (see end_pass).
+template <uint32_t P, uint32_t m>
+__device__ __forceinline__ uint32_t chunk_ends(uint32_t E, uint32_t C, const uint32_t* __restrict__ g,
+                                               const uint32_t (&pre)[kRound]) {
+  const Chunk<P> ch(E, C);
+  uint32_t n = 0;
+#pragma unroll
+  for (int k = 0; k < kRound; ++k) n += __popc(uint32_t(k) < ch.nd ? pre[k] & m : 0u);
+  for (uint32_t r = kRound; r < ch.nd; ++r) n += __popc(g[ch.d0 + r] & m);
+  return n;
+}
+
+// Owner side of a flat pass: the sum of the owner's row occupying entries
 // [ob, oe) (oe > ob) of a pass with chunk length C: the pieces of the earlier
-// chunks it spans (carry, in lane order), then its final piece (seg).
+// chunks it spans (carry, in lane order), then its final piece.
 template <class M>
-__device__ __forceinline__ typename M::PAcc tagged_row_sum(uint32_t ob, uint32_t oe, uint32_t C, float invC,
-                                                           const typename M::PAcc* seg_row,
-                                                           const typename M::PAcc* carry) {
+__device__ __forceinline__ typename M::PAcc flat_row_sum(uint32_t ob, uint32_t oe, uint32_t C, float invC,
+                                                         typename M::PAcc last, const typename M::PAcc* carry) {
   const uint32_t L0 = div_small(ob, C, invC), L1 = div_small(oe - 1, C, invC);
-  if (L1 == L0) return *seg_row;
+  if (L1 == L0) return last;
   typename M::PAcc s = carry[L0];
   for (uint32_t l = L0 + 1; l < L1; ++l) s = M::pcomb(s, carry[l]);
-  return M::pcomb(s, *seg_row);
+  return M::pcomb(s, last);
 }
 
 // Fill n bytes (n a multiple of 16) of LDS with 0xFF.
@@ -359,25 +484,23 @@ __device__ __forceinline__ void wave_fill_ff(uint8_t* dst, uint32_t n) {
 
 // per-wave LDS carve of the tile kernel (bytes from the wave's base); a
 // wave holds up to 64 * RPL rows, RPL consecutive rows per lane
-template <class M, bool PREFIX, int RPL>
+template <class M, int RPL>
 struct WaveCarve {
   using X = typename M::X;
   using PAcc = typename M::PAcc;
   using CAcc = typename M::CAcc;
   static constexpr uint32_t kRows = 64 * RPL;
-  uint32_t WC, SB;
+  uint32_t WC;
   // y shares the pieces' slots: they are read by their owners before the
   // reuse levels write y
   static constexpr size_t kSlot = sizeof(PAcc) > sizeof(CAcc) ? sizeof(PAcc) : sizeof(CAcc);
   __host__ __device__ static constexpr size_t seg() { return 0; }
   __host__ __device__ static constexpr size_t y() { return 0; }
   __host__ __device__ static constexpr size_t carry() { return align16(kRows * kSlot); }
-  __host__ __device__ static constexpr size_t x() { return carry() + align16(64 * sizeof(PAcc)); }
-  __host__ __device__ size_t P() const { return x() + (M::kInt ? 0 : align16(size_t(WC) * sizeof(X) + 16)); }
-  __host__ __device__ size_t tags() const { return P() + (PREFIX && !M::kInt ? align16((size_t(WC) + 1) * 8) : 0); }
-  // one tag byte per single (the longer of the two tagged streams)
-  __host__ __device__ size_t data() const { return tags() + align16(size_t(SB) / 2 + 16); }
-  __host__ __device__ size_t wave_bytes() const { return data() + align16(size_t(SB)); }
+  // the window array Z, placed 8 bytes past a 16-byte boundary so that Z + 1
+  // is 16-byte aligned
+  __host__ __device__ static constexpr size_t Z() { return carry() + align16(64 * sizeof(PAcc)) + 8; }
+  __host__ __device__ size_t wave_bytes() const { return align16(Z() + (M::kInt ? 0 : (2 * size_t(WC) + 2) * 8)); }
   __host__ __device__ size_t block_bytes() const { return kWaves * wave_bytes() + 256; }
 };
 
@@ -487,35 +610,43 @@ struct EpiPR {
 // --------------------------------------------------------------- tile kernel
 // One wavefront per tile of up to 64 * RPL rows; lane l owns rows
 // [l * RPL, (l + 1) * RPL).
-template <class M, bool PREFIX, int RPL, class Epi>
+template <class M, int RPL, class Epi>
 __global__ void __launch_bounds__(kThreads) bv_wave_kernel(DevLayout L, const typename M::X* __restrict__ x,
                                                            Epi epi, const PRState* __restrict__ skip_done) {
   using X = typename M::X;
   using PAcc = typename M::PAcc;
   using CAcc = typename M::CAcc;
-  using Cv = WaveCarve<M, PREFIX, RPL>;
+  using Cv = WaveCarve<M, RPL>;
   extern __shared__ __align__(16) unsigned char smem[];
   const uint32_t wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const uint32_t lane = lane_id();
   const uint32_t tile = blockIdx.x * kWaves + wave;
   const TileDesc td = L.tiles[tile];
   if (skip_done && skip_done[L.tiles[blockIdx.x * kWaves].graph].done) return;  // whole block, one member
-  const Cv cv{L.wcap, L.sbytes};
+  const Cv cv{L.wcap};
   unsigned char* ws = smem + size_t(wave) * cv.wave_bytes();
   unsigned char* s_blk = smem + size_t(kWaves) * cv.wave_bytes();
   PAcc* s_seg = reinterpret_cast<PAcc*>(ws + cv.seg());
   CAcc* s_y = reinterpret_cast<CAcc*>(ws + cv.y());
   PAcc* s_carry = reinterpret_cast<PAcc*>(ws + cv.carry());
-  X* s_xbuf = reinterpret_cast<X*>(ws + cv.x());
-  double* s_P = reinterpret_cast<double*>(ws + cv.P());
-  uint8_t* s_tags = reinterpret_cast<uint8_t*>(ws + cv.tags());
-  unsigned char* s_data = ws + cv.data();
+  double* Z = reinterpret_cast<double*>(ws + cv.Z());
   const uint32_t nrows = td.nrows;
   const int64_t win0 = td.win0;
   const uint32_t winlen = td.winlen;
   const uint32_t r0 = lane * RPL;
+  const uint32_t n16 = td.n16, nwide = td.nwide;
+  const uint32_t* g16 = reinterpret_cast<const uint32_t*>(L.data + td.data16);  // singles stream
+  const uint32_t* gw = g16 + dalign16u(n16 * 2u) / 4;                          // wide entries
 
-  // 1. all global loads of the tile
+  // 1. all global loads of the tile: the first round of the lane's singles
+  //    chunk, its rows' info, and the x window (with its prefix sums when the
+  //    tile has intervals) into Z
+  const uint32_t C16 = flat_chunk<2>(n16);
+  uint32_t pre[kRound];
+  {
+    const Chunk<2> ch(n16, C16);
+    if (n16) load_round(g16, ch.d0, ch.last, pre);
+  }
   uint32_t inf[RPL], ns[RPL];
 #pragma unroll
   for (int q = 0; q < RPL; ++q) {
@@ -523,126 +654,103 @@ __global__ void __launch_bounds__(kThreads) bv_wave_kernel(DevLayout L, const ty
     inf[q] = has ? L.info[td.row0 + r0 + q] : 0u;
     ns[q] = has ? uint32_t(L.ns[td.row0 + r0 + q]) : 0u;
   }
-  wave_copy16<4>(L.data + td.data16, s_data, dstage_bytes(td));
-  const X* s_x = s_xbuf;
-  if constexpr (!M::kInt) s_x = stage_range<X>(x, L.n, win0, winlen, s_xbuf);
-  const uint16_t* s16 = reinterpret_cast<const uint16_t*>(s_data);
-  const uint32_t* w32 = reinterpret_cast<const uint32_t*>(s_data + dalign16u(td.n16 * 2u));
-  const uint32_t* i32 = reinterpret_cast<const uint32_t*>(s_data + dalign16u(td.n16 * 2u) + dalign16u(td.nwide * 4u));
-  wave_fill_ff(s_tags, dalign16u(td.n16 + 16));
+  if constexpr (!M::kInt) stage_window<X>(x, win0, winlen, td.nint != 0, Z);
 
-  // 2. stream offsets: singles | wide << 20 | intervals << 40, one scan
-  uint64_t A[RPL];
-  uint64_t Asum = 0;
+  // 2. offsets of the lanes' rows in the streams, and of their row ends
+  uint32_t c16[RPL], cw[RPL], s16 = 0, sw = 0;
+  uint64_t m16[RPL], mw[RPL];
 #pragma unroll
   for (int q = 0; q < RPL; ++q) {
     const bool lng = inf[q] & kInfoLong;
-    A[q] = lng ? 0 : (uint64_t(ns[q]) | (uint64_t(inf[q] >> 13) << 20) | (uint64_t((inf[q] >> 9) & 15u) << 40));
-    Asum += A[q];
+    c16[q] = lng ? 0u : ns[q];
+    cw[q] = lng ? 0u : (inf[q] >> 13);
+    s16 += c16[q];
+    sw += cw[q];
+    m16[q] = __ballot(c16[q] != 0);
+    mw[q] = __ballot(cw[q] != 0);
   }
-  uint64_t totA;
-  uint64_t run = wave_excl_scan_u64(Asum, totA);
-  uint32_t o16[RPL], ow[RPL], oi[RPL];
+  // the lanes' singles (bits 0..15) and the row ends in the lane's chunk (16..31)
+  const uint32_t sc16 = s16 | ((n16 ? chunk_ends<2, kS16End | (kS16End << 16)>(n16, C16, g16, pre) : 0u) << 16);
+  const uint32_t ex16 = wave_incl_scan_u32(sc16) - sc16;
+  uint32_t o16[RPL], k16[RPL], kw[RPL];
+  {
+    uint32_t a16 = ex16 & 0xFFFFu, b16 = 0, bw = 0;
 #pragma unroll
-  for (int q = 0; q < RPL; ++q) {
-    o16[q] = uint32_t(run & 0xFFFFFu);
-    ow[q] = uint32_t((run >> 20) & 0xFFFFFu);
-    oi[q] = uint32_t(run >> 40);
-    run += A[q];
-  }
-  if constexpr (PREFIX && !M::kInt) {
-    if (td.nint) {
-      wave_sync();
-      const uint32_t chunk = (winlen + 63) / 64;
-      const uint32_t b0 = min(winlen, lane * chunk), b1 = min(winlen, b0 + chunk);
-      double acc = 0.0;
-      for (uint32_t k = b0; k < b1; ++k) acc += double(s_x[k]);
-      double tot;
-      double base = wave_excl_scan_f64(acc, tot);
-      for (uint32_t k = b0; k < b1; ++k) {
-        s_P[k] = base;
-        base += double(s_x[k]);
-      }
-      if (lane == 0) s_P[winlen] = tot;
+    for (int q = 0; q < RPL; ++q) {
+      b16 += lanes_below(m16[q]);
+      bw += lanes_below(mw[q]);
+    }
+#pragma unroll
+    for (int q = 0; q < RPL; ++q) {
+      o16[q] = a16;
+      k16[q] = b16;
+      kw[q] = bw;
+      a16 += c16[q];
+      b16 += c16[q] != 0;
+      bw += cw[q] != 0;
     }
   }
-  wave_sync();  // tag fill before the owners' tags
-#pragma unroll
-  for (int q = 0; q < RPL; ++q)
-    if (A[q] & 0xFFFFFu) s_tags[o16[q] + ns[q] - 1] = uint8_t(r0 + q);
   wave_sync();
 
-  // 3. singles, then wide entries (tagged flat passes); the owner adds its
-  //    rows' pieces to its registers
+  // 3. singles (with the intervals' prefix pairs), then wide entries: flat
+  //    passes cut at the row-end bits; the owner adds its rows' pieces in
+  //    registers
   PAcc a[RPL];
 #pragma unroll
   for (int q = 0; q < RPL; ++q) a[q] = M::pzero();
-  if (td.n16) {
-    const uint32_t C = tagged_chunk(td.n16);
-    const float invC = 1.0f / float(C);
-    tagged_pass<M, uint16_t>(0, td.n16, C, s16, s_tags, s_seg, s_carry, [&](uint32_t w, bool ok) -> X {
-      // words past the chunk are zero padding or later chunks' entries, so
-      // the gather stays inside the window and is masked afterwards
-      if constexpr (M::kInt) {
-        return ok ? ((w & 0x8000u) ? -1 : 1) : 0;
-      } else {
-        X v = s_x[w & 0x7FFFu];
-        v = (w & 0x8000u) ? -v : v;
-        return ok ? v : X(0);
-      }
-    });
+  if (n16) {
+    const float invC = __builtin_amdgcn_rcpf(float(C16));
+    if constexpr (M::kInt) {
+      // degrees: a column counts 1, a prefix entry P[p] counts p
+      end_pass<M, 2, kS16End>(n16, C16, g16, pre, ex16 >> 16, s_seg, s_carry, [&](uint32_t w) -> X {
+        const int32_t f = int32_t(w & kS16Off);
+        const int32_t v = (f & 1) ? (f >> 1) : (f ? 1 : 0);
+        return (w & kS16Neg) ? -v : v;
+      }, [](PAcc& acc, X v) { M::padd(acc, v); });
+    } else {
+      end_pass<M, 2, kS16End>(n16, C16, g16, pre, ex16 >> 16, s_seg, s_carry, [&](uint32_t w) -> double {
+        const double v = Z[w & kS16Off];
+        return (w & kS16Neg) ? -v : v;
+      }, [](PAcc& acc, double v) { M::padd_d(acc, v); });
+    }
     wave_sync();
 #pragma unroll
     for (int q = 0; q < RPL; ++q)
-      if (A[q] & 0xFFFFFu) a[q] = tagged_row_sum<M>(o16[q], o16[q] + ns[q], C, invC, s_seg + r0 + q, s_carry);
+      if (c16[q]) a[q] = flat_row_sum<M>(o16[q], o16[q] + c16[q], C16, invC, s_seg[k16[q]], s_carry);
   }
-  if (td.nwide) {
-    const uint32_t E = td.nwide;
+  // window value of column win0 + c, else the global one
+  auto xval = [&](int64_t c) -> X {
+    if constexpr (M::kInt) {
+      return 1;
+    } else {
+      return uint64_t(c) < winlen ? X(Z[2 * c + 2]) : x[win0 + c];
+    }
+  };
+  if (nwide) {
+    const uint32_t Cw = flat_chunk<1>(nwide);
+    const float invC = __builtin_amdgcn_rcpf(float(Cw));
+    uint32_t prew[kRound];
+    {
+      const Chunk<1> ch(nwide, Cw);
+      load_round(gw, ch.d0, ch.last, prew);
+    }
+    const uint32_t scw = sw | (chunk_ends<1, kWideEnd>(nwide, Cw, gw, prew) << 16);
+    const uint32_t exw = wave_incl_scan_u32(scw) - scw;
     wave_sync();  // the singles' pieces are read
-    wave_fill_ff(s_tags, dalign16u(E + 16));
+    end_pass<M, 1, kWideEnd>(nwide, Cw, gw, prew, exw >> 16, s_seg, s_carry, [&](uint32_t w) -> X {
+      const X v = xval(int64_t(w & kWideOff) - int64_t(kWideBias));
+      return (w & kWideNeg) ? -v : v;
+    }, [](PAcc& acc, X v) { M::padd(acc, v); });
     wave_sync();
+    uint32_t aw = exw & 0xFFFFu;
 #pragma unroll
-    for (int q = 0; q < RPL; ++q)
-      if ((A[q] >> 20) & 0xFFFFFu) s_tags[ow[q] + (inf[q] >> 13) - 1] = uint8_t(r0 + q);
-    wave_sync();
-    const uint32_t C = tagged_chunk(E);
-    const float invC = 1.0f / float(C);
-    tagged_pass<M, uint32_t>(0, E, C, w32, s_tags, s_seg, s_carry, [&](uint32_t w, bool ok) -> X {
-      if (!ok) return X(0);
-      if constexpr (M::kInt) {
-        return (w & 0x80000000u) ? -1 : 1;
-      } else {
-        const int64_t c = int64_t(w & 0x7FFFFFFFu) - int64_t(kLongBias);
-        const X v = uint64_t(c) < winlen ? s_x[c] : x[win0 + c];
-        return (w & 0x80000000u) ? -v : v;
-      }
-    });
-    wave_sync();
-#pragma unroll
-    for (int q = 0; q < RPL; ++q)
-      if ((A[q] >> 20) & 0xFFFFFu)
-        a[q] = M::pcomb(a[q], tagged_row_sum<M>(ow[q], ow[q] + (inf[q] >> 13), C, invC, s_seg + r0 + q, s_carry));
-  }
-
-  // 4. each lane's intervals
-#pragma unroll
-  for (int q = 0; q < RPL; ++q) {
-    const uint32_t ni = (inf[q] & kInfoLong) ? 0u : ((inf[q] >> 9) & 15u);
-    for (uint32_t t = 0; t < ni; ++t) {
-      const uint32_t w = i32[oi[q] + t];
-      const uint32_t s = (w >> 16) & 0x7FFFu, ln = w & 0xFFFFu;
-      const bool neg = w & 0x80000000u;
-      if constexpr (M::kInt) {
-        M::padd(a[q], neg ? -int32_t(ln) : int32_t(ln));
-      } else if constexpr (PREFIX) {
-        const double d = s_P[s + ln] - s_P[s];
-        M::padd_d(a[q], neg ? -d : d);
-      } else {
-        for (uint32_t u = 0; u < ln; ++u) M::padd(a[q], neg ? -s_x[s + u] : s_x[s + u]);
-      }
+    for (int q = 0; q < RPL; ++q) {
+      if (cw[q]) a[q] = M::pcomb(a[q], flat_row_sum<M>(aw, aw + cw[q], Cw, invC, s_seg[kw[q]], s_carry));
+      aw += cw[q];
     }
   }
-  //    long rows, the whole wave each
+
+  // 4. long rows, the whole wave each
   bool any_long = false;
 #pragma unroll
   for (int q = 0; q < RPL; ++q) any_long |= (inf[q] & kInfoLong) != 0;
@@ -681,14 +789,9 @@ __global__ void __launch_bounds__(kThreads) bv_wave_kernel(DevLayout L, const ty
           }
           X v[8];
 #pragma unroll
-          for (int j = 0; j < 8; ++j) {
-            if constexpr (M::kInt) {
-              v[j] = 1;
-            } else {
-              const int64_t c = int64_t(w[j] & 0x7FFFFFFFu) - int64_t(kLongBias);
-              v[j] = base + lane + 64u * j >= len ? X(0) : (uint64_t(c) < winlen ? s_x[c] : x[win0 + c]);
-            }
-          }
+          for (int j = 0; j < 8; ++j)
+            v[j] = base + lane + 64u * j >= len ? X(0)
+                                               : xval(int64_t(w[j] & 0x7FFFFFFFu) - int64_t(kLongBias));
 #pragma unroll
           for (int j = 0; j < 8; ++j)
             if (base + lane + 64u * j < len) M::padd(s, (w[j] & 0x80000000u) ? -v[j] : v[j]);
@@ -771,10 +874,51 @@ struct CsrCarve {
   __host__ __device__ static constexpr size_t carry() { return align16(64 * kSlot); }
   __host__ __device__ static constexpr size_t x() { return carry() + align16(64 * sizeof(PAcc)); }
   __host__ __device__ size_t tags() const { return x() + align16(size_t(WC) * sizeof(X) + 16); }
-  __host__ __device__ size_t col() const { return tags() + align16(size_t(CC) + 32); }
-  __host__ __device__ size_t wave_bytes() const { return col() + align16(size_t(CC) * 4 + 16); }
+  __host__ __device__ size_t wave_bytes() const { return tags() + align16(size_t(CC) + 64); }
   __host__ __device__ size_t block_bytes() const { return kWaves * wave_bytes() + 256; }
 };
+
+constexpr int kCsrPre = 4;  // 16-byte batches of the lane's column ids loaded up front (16 ids)
+
+// Tagged flat pass of the CSR tile: as end_pass, but over 16-byte batches of
+// column ids (4 per batch; the first kCsrPre batches loaded by the caller) in
+// entries counted from the 16-byte aligned id at or before the tile's first
+// (entries before `lo` belong to no row of the tile).  Entry e's row end is
+// read from tags[e] (the tile row whose last entry it is, or 0xFF), written
+// beforehand by the row owners, and the piece goes to seg[row].
+template <class M, class ValFn>
+__device__ __forceinline__ void csr_pass(uint32_t lo, uint32_t E, uint32_t C, const uint4* __restrict__ g,
+                                         const uint4 (&pre)[kCsrPre], const uint8_t* tags, typename M::PAcc* seg,
+                                         typename M::PAcc* carry, ValFn val) {
+  using PAcc = typename M::PAcc;
+  using X = typename M::X;
+  const uint32_t lane = lane_id();
+  const uint32_t b = lane * C;
+  if (b >= E) return;
+  const uint32_t end = min(E, b + C);
+  PAcc a = M::pzero();
+  auto batch = [&](const uint4& q, uint32_t e) {
+    const uint32_t tg = *reinterpret_cast<const uint32_t*>(tags + e);
+    const uint32_t c[4] = {q.x, q.y, q.z, q.w};
+    X v[4];
+#pragma unroll
+    for (uint32_t j = 0; j < 4; ++j) v[j] = val(c[j], e + j >= lo && e + j < end);
+#pragma unroll
+    for (uint32_t j = 0; j < 4; ++j) {
+      M::padd(a, v[j]);
+      const uint32_t t = (tg >> (8 * j)) & 0xFFu;
+      if (t != 0xFFu && e + j < end) {
+        seg[t] = a;
+        a = M::pzero();
+      }
+    }
+  };
+#pragma unroll
+  for (int k = 0; k < kCsrPre; ++k)
+    if (b + uint32_t(k) * 4 < end) batch(pre[k], b + uint32_t(k) * 4);
+  for (uint32_t k = kCsrPre; b + k * 4 < end; ++k) batch(g[b / 4 + k], b + k * 4);
+  carry[lane] = a;
+}
 
 template <class M, class Epi>
 __global__ void __launch_bounds__(kThreads) csr_wave_kernel(DevCsr C, const typename M::X* __restrict__ x, Epi epi,
@@ -798,7 +942,6 @@ __global__ void __launch_bounds__(kThreads) csr_wave_kernel(DevCsr C, const type
   PAcc* s_carry = reinterpret_cast<PAcc*>(ws + cv.carry());
   X* s_xbuf = reinterpret_cast<X*>(ws + cv.x());
   uint8_t* s_tags = reinterpret_cast<uint8_t*>(ws + cv.tags());
-  uint32_t* s_colbuf = reinterpret_cast<uint32_t*>(ws + cv.col());
   if (is_long) {
     PAcc s = M::pzero();
     const uint32_t* cl = C.col + size_t(td.c0);
@@ -821,28 +964,34 @@ __global__ void __launch_bounds__(kThreads) csr_wave_kernel(DevCsr C, const type
   } else {
     const int64_t win0 = td.win0;
     const uint32_t winlen = td.winlen;
-    // the lane's row: entries [ob, oe) counted from the 16-byte aligned
-    // start of the staged column ids
+    // entries are counted from the 16-byte aligned column id at or before
+    // c0; the lane's chunk of ids is read straight from global memory
     const uint32_t shift = td.c0 & 3u;
+    const uint32_t E = td.ncols + shift;
+    const uint4* g = reinterpret_cast<const uint4*>(C.col + (size_t(td.c0) - shift));
+    const uint32_t Cc = flat_chunk<4>(E);
+    uint4 pre[kCsrPre];
+    if (td.ncols) {
+      const uint32_t nb = (E + 3) / 4;
+#pragma unroll
+      for (int k = 0; k < kCsrPre; ++k) pre[k] = g[min(lane * Cc / 4 + uint32_t(k), nb - 1)];
+    }
     uint32_t ob = 0, oe = 0;
     if (lane < nrows) {
       ob = uint32_t(C.rowptr[td.row0 + lane] - td.c0) + shift;
       oe = uint32_t(C.rowptr[td.row0 + lane + 1] - td.c0) + shift;
     }
-    stage_range<uint32_t>(C.col, C.col_len, td.c0, td.ncols, s_colbuf);
     const X* s_x = stage_range<X>(x, C.n, win0, winlen, s_xbuf);
-    const uint32_t E = td.ncols + shift;
     wave_fill_ff(s_tags, dalign16u(E + 16));
     wave_sync();
     if (oe > ob) s_tags[oe - 1] = uint8_t(lane);
     wave_sync();
     PAcc a = M::pzero();
     if (td.ncols) {
-      const uint32_t Cc = tagged_chunk(E);
       const float invC = 1.0f / float(Cc);
-      // every staged word is a column id < n (neighbouring rows' or the
-      // zero padding), so only the choice of source depends on `ok`
-      tagged_pass<M, uint32_t>(shift, E, Cc, s_colbuf, s_tags, s_seg, s_carry, [&](uint32_t c, bool ok) -> X {
+      // ids past the chunk are the next rows' or the array's zero padding,
+      // so every gather stays in bounds; only the source depends on `ok`
+      csr_pass<M>(shift, E, Cc, g, pre, s_tags, s_seg, s_carry, [&](uint32_t c, bool ok) -> X {
         const int64_t d = int64_t(c) - win0;
         const bool inwin = uint64_t(d) < winlen;
         X v = s_x[inwin ? uint32_t(d) : 0u];
@@ -850,7 +999,7 @@ __global__ void __launch_bounds__(kThreads) csr_wave_kernel(DevCsr C, const type
         return ok ? v : X(0);
       });
       wave_sync();
-      if (oe > ob) a = tagged_row_sum<M>(ob, oe, Cc, invC, s_seg + lane, s_carry);
+      if (oe > ob) a = flat_row_sum<M>(ob, oe, Cc, invC, s_seg[lane], s_carry);
       wave_sync();  // pieces read before y overwrites the slots
     }
     s_y[lane] = M::chain(a);
@@ -873,7 +1022,7 @@ struct RowsStaged {
 };
 
 __device__ __forceinline__ RowsStaged block_scan_rows(const TileDesc& td, const uint32_t* s_info, const uint32_t* s_ns,
-                                                      uint32_t* s_o16, uint32_t* s_ow, uint32_t* s_oi, uint32_t* s_ol,
+                                                      uint32_t* s_o16, uint32_t* s_ow, uint32_t* s_ol,
                                                       uint32_t* s_list, unsigned char* s_red) {
   __shared__ uint32_t s_nlong, s_maxlvl;
   const uint32_t tid = threadIdx.x;
@@ -882,12 +1031,9 @@ __device__ __forceinline__ RowsStaged block_scan_rows(const TileDesc& td, const 
   uint32_t lvl = 0;
   if (tid < nrows) {
     const uint32_t inf = s_info[tid];
-    const uint64_t nw = inf >> 13, ni = (inf >> 9) & 15u;
+    const uint64_t nw = inf >> 13;
     if (inf & kInfoLong) Bv = (uint64_t(1) << 16) | ((nw | (uint64_t(s_ns[tid]) << 19)) << 28);
-    else {
-      A = uint64_t(s_ns[tid]) | (nw << 32);
-      Bv = ni;
-    }
+    else A = uint64_t(s_ns[tid]) | (nw << 32);
     lvl = (inf >> 4) & 15u;
   }
   if (tid == 0) s_maxlvl = 0;
@@ -899,7 +1045,6 @@ __device__ __forceinline__ RowsStaged block_scan_rows(const TileDesc& td, const 
   if (tid < nrows) {
     s_o16[tid] = uint32_t(ra & 0xFFFFFFFFu);
     s_ow[tid] = uint32_t(ra >> 32);
-    s_oi[tid] = uint32_t(rb & 0xFFFFu);
     s_ol[tid] = uint32_t(rb >> 28);
     if (s_info[tid] & kInfoLong) s_list[(rb >> 16) & 0xFFFu] = tid;
   }
@@ -936,7 +1081,6 @@ __global__ void __launch_bounds__(kThreads) bv_batch_kernel(DevLayout L, const t
   uint32_t* s_ns = reinterpret_cast<uint32_t*>(smem + u);
   uint32_t* s_o16 = reinterpret_cast<uint32_t*>(smem + 2 * u);
   uint32_t* s_ow = reinterpret_cast<uint32_t*>(smem + 3 * u);
-  uint32_t* s_oi = reinterpret_cast<uint32_t*>(smem + 4 * u);
   uint32_t* s_ol = reinterpret_cast<uint32_t*>(smem + 5 * u);
   uint32_t* s_list = reinterpret_cast<uint32_t*>(smem + 6 * u);
   CAcc* s_acc = reinterpret_cast<CAcc*>(smem + cv.acc());
@@ -956,10 +1100,9 @@ __global__ void __launch_bounds__(kThreads) bv_batch_kernel(DevLayout L, const t
     }
   }
   __syncthreads();
-  const RowsStaged rs = block_scan_rows(td, s_info, s_ns, s_o16, s_ow, s_oi, s_ol, s_list, s_red);
+  const RowsStaged rs = block_scan_rows(td, s_info, s_ns, s_o16, s_ow, s_ol, s_list, s_red);
   const uint16_t* s16 = reinterpret_cast<const uint16_t*>(s_data);
   const uint32_t* w32 = reinterpret_cast<const uint32_t*>(s_data + dalign16u(td.n16 * 2u));
-  const uint32_t* i32 = reinterpret_cast<const uint32_t*>(s_data + dalign16u(td.n16 * 2u) + dalign16u(td.nwide * 4u));
   const int64_t win0 = td.win0;
   for (int c0 = 0; c0 < k; c0 += G) {
     const int c = c0 + int(lane);
@@ -971,24 +1114,24 @@ __global__ void __launch_bounds__(kThreads) bv_batch_kernel(DevLayout L, const t
       PAcc a = M::pzero();
       for (uint32_t e = s_o16[r], en = s_o16[r] + s_ns[r]; e < en; ++e) {
         const uint32_t w = s16[e];
-        const Xt v = act ? Xc[(win0 + int64_t(w & 0x7FFFu)) * ld] : Xt(0);
-        M::padd(a, (w & 0x8000u) ? -v : v);
+        const uint32_t f = w & kS16Off;
+        if (f & 1) {
+          // an interval pair +P[b] - P[a]: the sum of X over columns [a, b) of the window
+          const uint32_t f2 = s16[++e] & kS16Off;
+          PAcc t = M::pzero();
+          if (act)
+            for (int64_t c = win0 + (f2 >> 1), c1 = win0 + (f >> 1); c < c1; ++c) M::padd(t, Xc[c * ld]);
+          a = M::pcomb(a, (w & kS16Neg) ? -t : t);
+        } else {
+          const Xt v = act ? Xc[(win0 + int64_t(f >> 1) - 1) * ld] : Xt(0);
+          M::padd(a, (w & kS16Neg) ? -v : v);
+        }
       }
       for (uint32_t e = s_ow[r], en = s_ow[r] + (inf >> 13); e < en; ++e) {
         const uint32_t w = w32[e];
-        const int64_t col = win0 + int64_t(w & 0x7FFFFFFFu) - int64_t(kLongBias);
+        const int64_t col = win0 + int64_t(w & kWideOff) - int64_t(kWideBias);
         const Xt v = act ? Xc[col * ld] : Xt(0);
-        M::padd(a, (w & 0x80000000u) ? -v : v);
-      }
-      for (uint32_t e = s_oi[r], en = s_oi[r] + ((inf >> 9) & 15u); e < en; ++e) {
-        const uint32_t w = i32[e];
-        const int64_t s = win0 + int64_t((w >> 16) & 0x7FFFu);
-        const uint32_t ln = w & 0xFFFFu;
-        if (act)
-          for (uint32_t t = 0; t < ln; ++t) {
-            const Xt v = Xc[(s + t) * ld];
-            M::padd(a, (w & 0x80000000u) ? -v : v);
-          }
+        M::padd(a, (w & kWideNeg) ? -v : v);
       }
       s_acc[r * G + lane] = M::chain(a);
     }
@@ -1038,18 +1181,18 @@ hipError_t set_lds(const void* k, size_t smem) {
 inline int rows_per_lane(const DevLayout& L) { return L.tcap <= 64 ? 1 : 2; }
 static_assert(kTileRowsMax <= 128, "row tags are bytes below 0xFF");
 
-template <class M, bool PREFIX>
+template <class M>
 size_t tile_lds(const DevLayout& L) {
   switch (rows_per_lane(L)) {
-    case 1: return WaveCarve<M, PREFIX, 1>{L.wcap, L.sbytes}.block_bytes();
-    default: return WaveCarve<M, PREFIX, 2>{L.wcap, L.sbytes}.block_bytes();
+    case 1: return WaveCarve<M, 1>{L.wcap}.block_bytes();
+    default: return WaveCarve<M, 2>{L.wcap}.block_bytes();
   }
 }
 
-template <class M, bool PREFIX, int RPL, class Epi>
+template <class M, int RPL, class Epi>
 hipError_t launch_tile_rpl(const DevLayout& L, const void* x, const Epi& epi, const PRState* skip, hipStream_t s) {
-  const size_t smem = WaveCarve<M, PREFIX, RPL>{L.wcap, L.sbytes}.block_bytes();
-  auto k = bv_wave_kernel<M, PREFIX, RPL, Epi>;
+  const size_t smem = WaveCarve<M, RPL>{L.wcap}.block_bytes();
+  auto k = bv_wave_kernel<M, RPL, Epi>;
   if (hipError_t e = set_lds(reinterpret_cast<const void*>(k), smem)) return e;
   if (L.ntiles == 0) return hipSuccess;
   hipLaunchKernelGGL(k, dim3(L.ntiles / kWaves), dim3(kThreads), smem, s, L, static_cast<const typename M::X*>(x),
@@ -1057,11 +1200,11 @@ hipError_t launch_tile_rpl(const DevLayout& L, const void* x, const Epi& epi, co
   return hipGetLastError();
 }
 
-template <class M, bool PREFIX, class Epi>
+template <class M, class Epi>
 hipError_t launch_tile(const DevLayout& L, const void* x, const Epi& epi, const PRState* skip, hipStream_t s) {
   switch (rows_per_lane(L)) {
-    case 1: return launch_tile_rpl<M, PREFIX, 1>(L, x, epi, skip, s);
-    default: return launch_tile_rpl<M, PREFIX, 2>(L, x, epi, skip, s);
+    case 1: return launch_tile_rpl<M, 1>(L, x, epi, skip, s);
+    default: return launch_tile_rpl<M, 2>(L, x, epi, skip, s);
   }
 }
 
@@ -1142,12 +1285,11 @@ hipError_t launch_batch(const DevLayout& L, const void* X, void* Y, int k, int64
 
 }  // namespace
 
-size_t bv_kernel_lds_bytes(const DevLayout& L, int prec, int interval_mode) {
-  const bool prefix = interval_mode == 1;
+size_t bv_kernel_lds_bytes(const DevLayout& L, int prec) {
   switch (prec) {
-    case 0: return tile_lds<MF64, false>(L);
-    case 1: return prefix ? tile_lds<MF32, true>(L) : tile_lds<MF32, false>(L);
-    case 2: return prefix ? tile_lds<MF32C, true>(L) : tile_lds<MF32C, false>(L);
+    case 0: return tile_lds<MF64>(L);
+    case 1: return tile_lds<MF32>(L);
+    case 2: return tile_lds<MF32C>(L);
     default: return 0;
   }
 }
@@ -1170,41 +1312,25 @@ size_t bv_batch_lds_bytes(const DevLayout& L, int prec, int k) {
   }
 }
 
-hipError_t launch_bv_multiply(const DevLayout& L, int prec, int interval_mode, const void* x, void* y,
-                              hipStream_t s) {
-  const bool prefix = interval_mode == 1;
+hipError_t launch_bv_multiply(const DevLayout& L, int prec, const void* x, void* y, hipStream_t s) {
   switch (prec) {
-    case 0:
-      return launch_tile<MF64, false>(L, x, EpiStore<MF64>{static_cast<double*>(y)}, nullptr, s);
-    case 1:
-      return prefix ? launch_tile<MF32, true>(L, x, EpiStore<MF32>{static_cast<float*>(y)}, nullptr, s)
-                    : launch_tile<MF32, false>(L, x, EpiStore<MF32>{static_cast<float*>(y)}, nullptr, s);
-    case 2:
-      return prefix ? launch_tile<MF32C, true>(L, x, EpiStore<MF32C>{static_cast<float*>(y)}, nullptr, s)
-                    : launch_tile<MF32C, false>(L, x, EpiStore<MF32C>{static_cast<float*>(y)}, nullptr, s);
-    default:
-      return hipErrorInvalidValue;
+    case 0: return launch_tile<MF64>(L, x, EpiStore<MF64>{static_cast<double*>(y)}, nullptr, s);
+    case 1: return launch_tile<MF32>(L, x, EpiStore<MF32>{static_cast<float*>(y)}, nullptr, s);
+    case 2: return launch_tile<MF32C>(L, x, EpiStore<MF32C>{static_cast<float*>(y)}, nullptr, s);
+    default: return hipErrorInvalidValue;
   }
 }
 
 hipError_t launch_bv_degrees(const DevLayout& L, int32_t* deg, hipStream_t s) {
-  return launch_tile<MINT, false>(L, nullptr, EpiStore<MINT>{deg}, nullptr, s);
+  return launch_tile<MINT>(L, nullptr, EpiStore<MINT>{deg}, nullptr, s);
 }
 
-hipError_t launch_bv_pagerank_iter(const DevLayout& L, int prec, int interval_mode, const PRArgs& a,
-                                   hipStream_t s) {
-  const bool prefix = interval_mode == 1;
+hipError_t launch_bv_pagerank_iter(const DevLayout& L, int prec, const PRArgs& a, hipStream_t s) {
   switch (prec) {
-    case 0:
-      return launch_tile<MF64, false>(L, a.z_cur, EpiPR<MF64>{a}, a.st, s);
-    case 1:
-      return prefix ? launch_tile<MF32, true>(L, a.z_cur, EpiPR<MF32>{a}, a.st, s)
-                    : launch_tile<MF32, false>(L, a.z_cur, EpiPR<MF32>{a}, a.st, s);
-    case 2:
-      return prefix ? launch_tile<MF32C, true>(L, a.z_cur, EpiPR<MF32C>{a}, a.st, s)
-                    : launch_tile<MF32C, false>(L, a.z_cur, EpiPR<MF32C>{a}, a.st, s);
-    default:
-      return hipErrorInvalidValue;
+    case 0: return launch_tile<MF64>(L, a.z_cur, EpiPR<MF64>{a}, a.st, s);
+    case 1: return launch_tile<MF32>(L, a.z_cur, EpiPR<MF32>{a}, a.st, s);
+    case 2: return launch_tile<MF32C>(L, a.z_cur, EpiPR<MF32C>{a}, a.st, s);
+    default: return hipErrorInvalidValue;
   }
 }
 

@@ -60,8 +60,14 @@ struct ChunkOut {
   std::string err;
 };
 
-inline uint32_t wide_code(int64_t col, int64_t win0, bool neg) {
+inline uint32_t long_code(int64_t col, int64_t win0, bool neg) {
   return (neg ? 0x80000000u : 0u) | uint32_t(col - win0 + int64_t(kLongBias));
+}
+inline bool wide_fits(int64_t col, int64_t win0) {
+  return col - win0 >= -int64_t(kWideBias) && col - win0 < int64_t(kWideBias);
+}
+inline uint32_t wide_code(int64_t col, int64_t win0, bool neg) {
+  return (neg ? kWideNeg : 0u) | uint32_t(col - win0 + int64_t(kWideBias));
 }
 
 // window of at most `cap` columns covering the most points (sorted in place)
@@ -159,7 +165,9 @@ class Builder {
       }
       // emit; shrink the tile while escapes push it past the staging budget
       for (;;) {
-        if (emit_tile(i0, plans, level.data() - lo, co)) break;
+        const int rc = emit_tile(i0, plans, level.data() - lo, co);
+        if (rc == kEmitted) break;
+        if (rc == kRetry) continue;  // a row was made long
         if (plans.size() == 1) {
           if (plans[0].force_long) { co.err = "row does not fit a tile"; return; }
           plans[0].force_long = true;  // sum it block-wide instead
@@ -172,8 +180,11 @@ class Builder {
     }
   }
 
-  // Returns false (and emits nothing) if the staged streams exceed the budget.
-  bool emit_tile(int64_t i0, const std::vector<RowPlan>& plans, uint8_t* level, ChunkOut& co) {
+  // kEmitted, or (emitting nothing) kOverflow if the staged streams exceed
+  // the budget, or kRetry after marking long a row whose column is out of
+  // the wide code's reach.
+  static constexpr int kEmitted = 0, kOverflow = 1, kRetry = 2;
+  int emit_tile(int64_t i0, std::vector<RowPlan>& plans, uint8_t* level, ChunkOut& co) {
     const int64_t nr = int64_t(plans.size());
     std::vector<uint32_t> pts;
     for (auto& rp : plans) {
@@ -187,23 +198,35 @@ class Builder {
     best_window(pts, p_.window_cap, uint32_t(i0), win0, winlen);
     auto in_win = [&](int64_t c) { return c >= int64_t(win0) && c < int64_t(win0) + int64_t(winlen); };
     std::vector<uint16_t> s16;
-    std::vector<uint32_t> w32, i32;
+    std::vector<uint32_t> w32;
+    uint32_t npairs = 0;
     std::vector<uint32_t> info(static_cast<size_t>(nr), 0u);
     std::vector<uint16_t> nsv(static_cast<size_t>(nr), 0);
     const size_t lbase = co.longs.size();
     int64_t esc = 0;
+    for (int64_t k = 0; k < nr; ++k) {
+      RowPlan& rp = plans[size_t(k)];
+      if (!is_long_row(rp))
+        for (auto& e : rp.ent) {
+          const uint32_t cnt = e.len ? e.len : 1;
+          if (!wide_fits(e.col, win0) || !wide_fits(int64_t(e.col) + cnt - 1, win0)) {
+            rp.force_long = true;
+            return kRetry;
+          }
+        }
+    }
     for (int64_t k = 0; k < nr; ++k) {
       const RowPlan& rp = plans[size_t(k)];
       const int64_t i = i0 + k;
       const bool lng = is_long_row(rp);
       const int lvl = rp.g ? level[i - rp.g] + 1 : 0;
       level[i] = uint8_t(lvl);
-      uint64_t c16 = 0, cw = 0, ci = 0;
+      uint64_t c16 = 0, cw = 0;
       if (!lng) {
-        const size_t b16 = s16.size(), bw = w32.size(), bi = i32.size();
+        const size_t b16 = s16.size(), bw = w32.size();
         auto single = [&](uint32_t c, bool neg) {
           if (in_win(c)) {
-            s16.push_back(uint16_t((neg ? 0x8000u : 0u) | (c - win0)));
+            s16.push_back(uint16_t((neg ? kS16Neg : 0u) | (2u * (c - win0) + 2u)));
           } else {
             w32.push_back(wide_code(c, win0, neg));
             ++esc;
@@ -212,35 +235,38 @@ class Builder {
         for (auto& e : rp.ent) {
           if (e.len == 0) {
             single(e.col, e.neg);
-          } else if (in_win(e.col) && in_win(int64_t(e.col) + e.len - 1) &&
-                     i32.size() - bi < kMaxIntervalsPerRow) {
-            i32.push_back((e.neg ? 0x80000000u : 0u) | ((e.col - win0) << 16) | e.len);
+          } else if (in_win(e.col) && in_win(int64_t(e.col) + e.len - 1)) {
+            // +P[s+len] - P[s] (signs swapped for a subtracted interval)
+            const uint32_t sw0 = e.col - win0;
+            s16.push_back(uint16_t((e.neg ? kS16Neg : 0u) | (2u * (sw0 + e.len) + 1u)));
+            s16.push_back(uint16_t((e.neg ? 0u : kS16Neg) | (2u * sw0 + 1u)));
+            ++npairs;
           } else {
             for (uint32_t t = 0; t < e.len; ++t) single(e.col + t, e.neg);
           }
         }
         c16 = s16.size() - b16;
         cw = w32.size() - bw;
-        ci = i32.size() - bi;
+        if (c16) s16.back() = uint16_t(s16.back() | kS16End);
+        if (cw) w32.back() |= kWideEnd;
         if (c16 > 0xFFFF || cw >= (1u << 19)) {
           co.longs.resize(lbase);
-          return false;
+          return kOverflow;
         }
       } else {
         for (auto& e : rp.ent) {
           const uint32_t cnt = e.len ? e.len : 1;
-          for (uint32_t t = 0; t < cnt; ++t) co.longs.push_back(wide_code(int64_t(e.col) + t, win0, e.neg));
+          for (uint32_t t = 0; t < cnt; ++t) co.longs.push_back(long_code(int64_t(e.col) + t, win0, e.neg));
           cw += cnt;
         }
         if (cw >= (uint64_t(1) << 35)) {
           co.err = "row too long for the layout";
-          return true;
+          return kEmitted;
         }
         c16 = cw >> 19;
         cw &= (1u << 19) - 1;
       }
-      info[size_t(k)] = uint32_t(rp.g) | (uint32_t(lvl) << 4) | (lng ? kInfoLong : 0u) | (uint32_t(ci) << 9) |
-                        (uint32_t(cw) << 13);
+      info[size_t(k)] = uint32_t(rp.g) | (uint32_t(lvl) << 4) | (lng ? kInfoLong : 0u) | (uint32_t(cw) << 13);
       nsv[size_t(k)] = uint16_t(c16);
     }
     TileDesc td{};
@@ -248,12 +274,12 @@ class Builder {
     td.nrows = uint32_t(nr);
     td.n16 = uint32_t(s16.size());
     td.nwide = uint32_t(w32.size());
-    td.nint = uint32_t(i32.size());
+    td.nint = npairs;
     if (tile_stage_bytes(td) > uint32_t(p_.stage_bytes)) {
       co.longs.resize(lbase);
-      return false;
+      return kOverflow;
     }
-    // append the three streams, each padded to 16 bytes
+    // append the two streams, each padded to 16 bytes
     const size_t base = co.data.size();
     td.data16 = uint32_t(base / 16);
     co.data.resize(base + tile_stage_bytes(td), 0);
@@ -261,8 +287,7 @@ class Builder {
     if (!s16.empty()) std::memcpy(dst, s16.data(), s16.size() * 2);
     dst += align16u(td.n16 * 2u);
     if (!w32.empty()) std::memcpy(dst, w32.data(), w32.size() * 4);
-    dst += align16u(td.nwide * 4u);
-    if (!i32.empty()) std::memcpy(dst, i32.data(), i32.size() * 4);
+
     td.win0 = win0;
     td.winlen = winlen;
     td.long0 = uint32_t(lbase);
@@ -281,7 +306,7 @@ class Builder {
       if (is_long_row(rp)) ++co.long_rows;
       co.max_level = std::max<int>(co.max_level, level[i0 + k]);
     }
-    return true;
+    return kEmitted;
   }
 
  private:
@@ -292,7 +317,7 @@ class Builder {
 }  // namespace
 
 int build_layout(const DecodedGraph& g, const LayoutParams& prm, int nthreads, HostLayout& out, std::string& err) {
-  if (prm.tile_rows < 1 || prm.tile_rows > kTileRowsMax || prm.window_cap < 1 || prm.window_cap > 32767 ||
+  if (prm.tile_rows < 1 || prm.tile_rows > kTileRowsMax || prm.window_cap < 1 || 2 * prm.window_cap + 1 > int(kS16Off) ||
       prm.stage_bytes < 256 || prm.stage_bytes > 65536 || prm.long_row_bytes < 16 ||
       prm.long_row_bytes > prm.stage_bytes || prm.min_interval < 2) {
     err = "layout parameter out of range";

@@ -12,24 +12,33 @@
 // rows, level(r_i) + 1 otherwise, at most R).
 //
 // A row's entries are signed single ids or signed intervals [s, s+len).  Per
-// tile an x window [win0, win0+winlen) is staged in LDS and the entries are
-// split into three fixed-width streams, each in row order:
-//   singles (u16):   bit 15 = subtract, bits 0..14 = column - win0;
-//   wide (u32):      bit 31 = subtract, bits 0..30 = column - win0 + 2^30
-//                    (columns outside the window; intervals that leave the
-//                    window are expanded into these);
-//   intervals (u32): bit 31 = subtract, bits 16..30 = start - win0,
-//                    bits 0..15 = length (inside the window; at most 15 per
-//                    row, further runs are expanded into singles).
-// The three streams of a tile are contiguous, each padded to 16 bytes, at
-// data16 * 16 bytes.  Rows whose staged bytes exceed `long_row_bytes` are long
-// rows: all their entries go to a per-graph long stream (u32, wide encoding,
-// intervals expanded) that the tile's whole wavefront sums.
+// tile an x window [win0, win0+winlen) is staged in LDS together with its
+// prefix sums P[p] = x[win0] + ... + x[win0+p-1] (p = 0..winlen), both as
+// doubles in one array Z: Z[0] = 0, Z[2p+1] = P[p], Z[2j+2] = x[win0+j].  An
+// interval inside the window is the pair +P[s+len] - P[s] (the O(1) interval
+// sum of Section "Our Approach"), so the tile's entries form two fixed-width
+// streams, each in row order:
+//   singles (u16):   bit 15 = subtract, bit 14 = last entry of its row,
+//                    bits 0..13 = f, the Z index: 2j+2 for column win0+j,
+//                    2p+1 for P[p] (an interval's pair, upper end first);
+//                    f = 0 is the zero padding word, which adds nothing;
+//   wide (u32):      bit 31 = subtract, bit 30 = last wide entry of its row,
+//                    bits 0..29 = column - win0 + 2^29 (columns outside the
+//                    window; intervals that leave the window are expanded
+//                    into these).
+// The row-end bits let a wave cut an equal share of a stream into row pieces
+// without reading the row offsets.  The two streams of a tile are contiguous,
+// each padded with zero words to 16 bytes, at data16 * 16 bytes.  Rows whose
+// staged bytes exceed `long_row_bytes` (or with a column too far from the
+// window for the wide code) are long rows: all their entries go to a
+// per-graph long stream (u32: bit 31 = subtract, bits 0..30 = column - win0 +
+// 2^30, intervals expanded) that the tile's whole wavefront sums.
 //
 // Row info (u32): bits 0..3 reference gap g (0 = direct), 4..7 level, bit 8
-// long, bits 9..12 interval count, bits 13..31 wide count (long rows: low 19
-// bits of the long-entry count).  Row `ns` (u16): singles count (long rows:
-// high bits of the long-entry count).
+// long, bits 9..12 zero, bits 13..31 wide count (long rows: low 19 bits of
+// the long-entry count).  Row `ns` (u16): singles-stream count (long rows:
+// high bits of the long-entry count).  TileDesc.nint counts the tile's
+// interval pairs (0: the tile needs no prefix sums).
 #pragma once
 #include <cstdint>
 #include <string>
@@ -43,9 +52,9 @@ struct TileDesc {
   uint32_t row0;    // first row (global)
   uint32_t nrows;   // rows in the tile
   uint32_t data16;  // tile streams at data16 * 16 bytes
-  uint32_t n16;     // singles
+  uint32_t n16;     // singles-stream entries
   uint32_t nwide;   // wide entries
-  uint32_t nint;    // intervals
+  uint32_t nint;    // interval pairs among the singles
   uint32_t win0;    // first column of the x window
   uint32_t winlen;  // window length
   uint32_t long0;   // first long entry of the tile's long rows
@@ -54,10 +63,8 @@ struct TileDesc {
 };
 
 inline uint32_t align16u(uint32_t b) { return (b + 15u) & ~15u; }
-// byte size of a tile's staged streams
-inline uint32_t tile_stage_bytes(const TileDesc& t) {
-  return align16u(t.n16 * 2u) + align16u(t.nwide * 4u) + align16u(t.nint * 4u);
-}
+// byte size of a tile's streams
+inline uint32_t tile_stage_bytes(const TileDesc& t) { return align16u(t.n16 * 2u) + align16u(t.nwide * 4u); }
 
 // A tile is processed by one 64-lane wavefront (up to 2 consecutive rows per
 // lane); a block holds kTilesPerBlock consecutive tiles, and tile lists are
@@ -71,7 +78,7 @@ struct LayoutParams {
   int window_cap = 512;
   int stage_bytes = 4096;      // max staged stream bytes per tile (LDS)
   int long_row_bytes = 2048;   // rows staging more than this are summed by the whole wave
-  int min_interval = 3;        // runs of at least this many ids become intervals
+  int min_interval = 3;        // runs of at least this many ids become intervals (a huge value: none)
 };
 
 struct HostLayout {
@@ -92,12 +99,13 @@ struct HostLayout {
 };
 
 constexpr uint32_t kInfoLong = 1u << 8;
-constexpr uint32_t kLongBias = 1u << 30;
-constexpr uint32_t kMaxIntervalsPerRow = 15;
+constexpr uint32_t kLongBias = 1u << 30;    // long stream: column - win0 + 2^30
+constexpr uint32_t kS16Neg = 0x8000u, kS16End = 0x4000u, kS16Off = 0x3FFFu;  // kS16Off masks f
+constexpr uint32_t kWideNeg = 0x80000000u, kWideEnd = 0x40000000u, kWideOff = 0x3FFFFFFFu;
+constexpr uint32_t kWideBias = 1u << 29;    // wide stream: column - win0 + 2^29
 
 inline uint32_t info_g(uint32_t inf) { return inf & 15u; }
 inline uint32_t info_level(uint32_t inf) { return (inf >> 4) & 15u; }
-inline uint32_t info_nint(uint32_t inf) { return (inf >> 9) & 15u; }
 inline uint32_t info_nwide(uint32_t inf) { return inf >> 13; }
 
 int build_layout(const DecodedGraph& g, const LayoutParams& prm, int nthreads, HostLayout& out, std::string& err);

@@ -3,6 +3,7 @@
 // entry streams and the long rows exactly as the kernels do and resolves the
 // reuse levels, so layout mistakes show up without a device.  No product
 // entry point calls it.
+#include <climits>
 #include <cstring>
 #include <string>
 #include <vector>
@@ -29,6 +30,7 @@ extern "C" int bvmv_layout_selfcheck(const void* bitstream, size_t nbytes, const
     if (opts->window_cap) prm.window_cap = opts->window_cap;
     if (opts->stage_bytes) prm.stage_bytes = opts->stage_bytes;
     prm.long_row_bytes = opts->long_row_bytes ? opts->long_row_bytes : prm.stage_bytes / 2;
+    if (opts->interval_mode == 1) prm.min_interval = INT_MAX;
   }
   HostLayout hl;
   if (build_layout(dg, prm, 4, hl, err)) return set_error(BVMV_EINVAL, err);
@@ -38,12 +40,23 @@ extern "C" int bvmv_layout_selfcheck(const void* bitstream, size_t nbytes, const
     const uint8_t* base = hl.data.data() + size_t(td.data16) * 16;
     const uint16_t* s16 = reinterpret_cast<const uint16_t*>(base);
     const uint32_t* w32 = reinterpret_cast<const uint32_t*>(base + align16u(td.n16 * 2u));
-    const uint32_t* i32 = reinterpret_cast<const uint32_t*>(base + align16u(td.n16 * 2u) + align16u(td.nwide * 4u));
     const int64_t win0 = td.win0;
+    // Z[0] = 0, Z[2p+1] = P[p] (prefix sums of the window), Z[2j+2] = x[win0+j]
+    std::vector<double> Z(2 * size_t(td.winlen) + 2, 0.0);
+    {
+      double run = 0.0;
+      for (uint32_t j = 0; j < td.winlen; ++j) {
+        Z[2 * size_t(j) + 1] = run;
+        Z[2 * size_t(j) + 2] = x[win0 + j];
+        run += x[win0 + j];
+      }
+      Z[2 * size_t(td.winlen) + 1] = run;
+    }
+    uint32_t pairs = 0;
     part.assign(td.nrows, 0.0);
     yy.assign(td.nrows, 0.0);
-    uint64_t o16 = 0, ow = 0, oi = 0, ol = 0;
-    auto wide = [&](uint32_t w) {
+    uint64_t o16 = 0, ow = 0, ol = 0;
+    auto lng = [&](uint32_t w) {
       const int64_t c = win0 + int64_t(w & 0x7FFFFFFFu) - int64_t(kLongBias);
       return (w & 0x80000000u) ? -x[c] : x[c];
     };
@@ -53,30 +66,49 @@ extern "C" int bvmv_layout_selfcheck(const void* bitstream, size_t nbytes, const
       double a = 0.0;
       if (inf & kInfoLong) {
         const uint64_t len = uint64_t(info_nwide(inf)) | (uint64_t(ns) << 19);
-        for (uint64_t k = 0; k < len; ++k) a += wide(hl.longs[td.long0 + ol + k]);
+        for (uint64_t k = 0; k < len; ++k) a += lng(hl.longs[td.long0 + ol + k]);
         ol += len;
       } else {
         for (uint32_t k = 0; k < ns; ++k) {
           const uint32_t w = s16[o16 + k];
-          if ((w & 0x7FFFu) >= td.winlen) return set_error(BVMV_EINVAL, "single outside the window");
-          a += (w & 0x8000u) ? -x[win0 + (w & 0x7FFFu)] : x[win0 + (w & 0x7FFFu)];
+          const uint32_t f = w & kS16Off;
+          if (f == 0 || f > 2 * td.winlen + 1) return set_error(BVMV_EINVAL, "single outside the window");
+          if (((w & kS16End) != 0) != (k + 1 == ns)) return set_error(BVMV_EINVAL, "single row-end bit misplaced");
+          if (f & 1) {  // an interval: +P[b] then -P[a], a < b, opposite signs
+            if (k + 1 >= ns) return set_error(BVMV_EINVAL, "unpaired prefix entry");
+            const uint32_t w2 = s16[o16 + k + 1], f2 = w2 & kS16Off;
+            if (!(f2 & 1) || f2 >= f || ((w ^ w2) & kS16Neg) == 0 || (w & kS16End))
+              return set_error(BVMV_EINVAL, "malformed interval pair");
+            const double v = Z[f] - Z[f2];
+            a += (w & kS16Neg) ? -v : v;
+            ++k;
+            ++pairs;
+            if (((w2 & kS16End) != 0) != (k + 1 == ns)) return set_error(BVMV_EINVAL, "single row-end bit misplaced");
+            continue;
+          }
+          a += (w & kS16Neg) ? -Z[f] : Z[f];
         }
         o16 += ns;
-        for (uint32_t k = 0; k < info_nwide(inf); ++k) a += wide(w32[ow + k]);
-        ow += info_nwide(inf);
-        for (uint32_t k = 0; k < info_nint(inf); ++k) {
-          const uint32_t w = i32[oi + k];
-          const uint32_t s = (w >> 16) & 0x7FFFu, ln = w & 0xFFFFu;
-          if (s + ln > td.winlen) return set_error(BVMV_EINVAL, "interval outside the window");
-          double v = 0.0;
-          for (uint32_t t = 0; t < ln; ++t) v += x[win0 + s + t];
-          a += (w & 0x80000000u) ? -v : v;
+        for (uint32_t k = 0; k < info_nwide(inf); ++k) {
+          const uint32_t w = w32[ow + k];
+          if (((w & kWideEnd) != 0) != (k + 1 == info_nwide(inf)))
+            return set_error(BVMV_EINVAL, "wide row-end bit misplaced");
+          const int64_t c = win0 + int64_t(w & kWideOff) - int64_t(kWideBias);
+          if (c < 0 || c >= int64_t(hl.n)) return set_error(BVMV_EINVAL, "wide column out of range");
+          a += (w & kWideNeg) ? -x[c] : x[c];
         }
-        oi += info_nint(inf);
+        ow += info_nwide(inf);
+        if ((inf >> 9) & 15u) return set_error(BVMV_EINVAL, "row info bits 9..12 set");
       }
       part[r] = a;
     }
-    if (o16 != td.n16 || ow != td.nwide || oi != td.nint) return set_error(BVMV_EINVAL, "tile stream count mismatch");
+    if (o16 != td.n16 || ow != td.nwide || pairs != td.nint)
+      return set_error(BVMV_EINVAL, "tile stream count mismatch");
+    // padding words up to 16 bytes are zero (no row-end bit)
+    for (uint32_t k = td.n16; k < align16u(td.n16 * 2u) / 2; ++k)
+      if (s16[k]) return set_error(BVMV_EINVAL, "nonzero singles padding");
+    for (uint32_t k = td.nwide; k < align16u(td.nwide * 4u) / 4; ++k)
+      if (w32[k]) return set_error(BVMV_EINVAL, "nonzero wide padding");
     for (uint32_t lv = 0; lv <= 15; ++lv)
       for (uint32_t r = 0; r < td.nrows; ++r) {
         const uint32_t inf = hl.info[td.row0 + r];

@@ -2,6 +2,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <climits>
 #include <cmath>
 #include <cstring>
 #include <memory>
@@ -90,7 +91,7 @@ struct PRWork {
   // key of the captured graph
   const void* key_tele = nullptr;
   double key_beta = -1, key_tol = -1;
-  int key_max_iter = -1, key_chunk = -1, key_mode = -1;
+  int key_max_iter = -1, key_chunk = -1;
 
   void drop_graph() {
     if (exec) (void)hipGraphExecDestroy(exec);
@@ -255,7 +256,7 @@ int upload_layout(bvmv_graph* g) {
   g->L.wcap = std::max<uint32_t>(64, (wcap + 63) / 64 * 64);
   g->L.sbytes = std::max<uint32_t>(256, (sb + 255) / 256 * 256);
   size_t need = 0;
-  for (int prec = 0; prec <= 2; ++prec) need = std::max(need, bv_kernel_lds_bytes(g->L, prec, g->interval_mode));
+  for (int prec = 0; prec <= 2; ++prec) need = std::max(need, bv_kernel_lds_bytes(g->L, prec));
   if (int rc = check_lds(g->device, need)) return rc;
   HIP_TRY(hipStreamCreateWithFlags(&g->cap, hipStreamNonBlocking));
   return BVMV_OK;
@@ -264,7 +265,7 @@ int upload_layout(bvmv_graph* g) {
 // Launch chunked PageRank on a tile layout or a CSR.  `iter` launches one
 // iteration on stream s with the given args; `init` the start kernel.
 template <class IterFn, class InitFn>
-int run_pagerank(PRWork& w, hipStream_t cap, const PROptsResolved& o, int interval_mode, int64_t n,
+int run_pagerank(PRWork& w, hipStream_t cap, const PROptsResolved& o, int64_t n,
                  const std::vector<int64_t>& offsets, const std::vector<uint32_t>& tile_offsets,
                  const void* tele, const void* start, void* p_out, bvmv_pr_result* res, hipStream_t s,
                  const int32_t* outdeg, IterFn iter, InitFn init) {
@@ -282,7 +283,7 @@ int run_pagerank(PRWork& w, hipStream_t cap, const PROptsResolved& o, int interv
   HIP_TRY(hipMemcpyAsync(w.st, w.h_st, sizeof(PRState) * size_t(members), hipMemcpyHostToDevice, s));
   HIP_TRY(init(start, tele, w.p[0], w.z[0], s));
   const bool same = w.exec && w.key_tele == tele && w.key_beta == o.beta && w.key_tol == o.tol &&
-                    w.key_max_iter == o.max_iter && w.key_chunk == o.chunk && w.key_mode == interval_mode;
+                    w.key_max_iter == o.max_iter && w.key_chunk == o.chunk;
   if (!same) {
     w.drop_graph();
     HIP_TRY(hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal));
@@ -317,7 +318,6 @@ int run_pagerank(PRWork& w, hipStream_t cap, const PROptsResolved& o, int interv
     w.key_tol = o.tol;
     w.key_max_iter = o.max_iter;
     w.key_chunk = o.chunk;
-    w.key_mode = interval_mode;
   }
   const int max_replays = (o.max_iter + o.chunk - 1) / o.chunk + 1;
   for (int rep = 0; rep < max_replays; ++rep) {
@@ -378,7 +378,7 @@ int bvmv_load(const void* bitstream, size_t nbytes, const bvmv_load_opts* opts, 
   if (o.window_cap == 0) o.window_cap = 512;
   if (o.stage_bytes == 0) o.stage_bytes = 4096;
   if (o.long_row_bytes == 0) o.long_row_bytes = o.stage_bytes / 2;
-  if (o.tile_rows < 8 || o.tile_rows > kTileRowsMax || o.window_cap < 64 || o.window_cap > 8192 ||
+  if (o.tile_rows < 8 || o.tile_rows > kTileRowsMax || o.window_cap < 64 || o.window_cap > 8191 ||
       o.stage_bytes < 512 || o.stage_bytes > 16384 || o.long_row_bytes < 16 || o.long_row_bytes > o.stage_bytes ||
       o.interval_mode < 0 || o.interval_mode > 1 || o.device < 0)
     return fail(BVMV_EINVAL, "load option out of range");
@@ -405,6 +405,7 @@ int bvmv_load(const void* bitstream, size_t nbytes, const bvmv_load_opts* opts, 
   prm.window_cap = o.window_cap;
   prm.long_row_bytes = o.long_row_bytes;
   prm.stage_bytes = o.stage_bytes;
+  if (o.interval_mode == 1) prm.min_interval = INT_MAX;  // runs stay single entries
   if (build_layout(g->dec, prm, nt, g->hl, err)) return fail(BVMV_EINVAL, err);
   g->m_prime = g->hl.m_prime;
   if (o.device_mem_budget && uint64_t(g->hl.bytes()) + uint64_t(g->n) * 4 > o.device_mem_budget)
@@ -444,7 +445,7 @@ int bvmv_multiply(bvmv_graph* g, const void* x, void* y, int prec, void* stream)
   if (prec < 0 || prec > 2) return fail(BVMV_EINVAL, "bad precision");
   if (x == y) return fail(BVMV_EINVAL, "x and y must not overlap");
   DeviceGuard dg(g->device);
-  HIP_TRY(launch_bv_multiply(g->L, prec, g->interval_mode, x, y, static_cast<hipStream_t>(stream)));
+  HIP_TRY(launch_bv_multiply(g->L, prec, x, y, static_cast<hipStream_t>(stream)));
   return BVMV_OK;
 }
 
@@ -474,13 +475,12 @@ int bvmv_pagerank(bvmv_graph* g, const bvmv_pr_opts* opts, const void* teleport,
   DeviceGuard dg(g->device);
   hipStream_t s = static_cast<hipStream_t>(stream);
   DevLayout L = g->L;
-  const int mode = g->interval_mode;
   const int prec = o.prec;
-  auto iter = [&](const PRArgs& a, hipStream_t cs) { return launch_bv_pagerank_iter(L, prec, mode, a, cs); };
+  auto iter = [&](const PRArgs& a, hipStream_t cs) { return launch_bv_pagerank_iter(L, prec, a, cs); };
   auto init = [&](const void* st, const void* te, void* p0, void* z0, hipStream_t ss) {
     return launch_pr_init(L, prec, st, te, p0, z0, g->d_outdeg, g->pr.st, g->pr.slots, ss);
   };
-  return run_pagerank(g->pr, g->cap, o, mode, g->n, g->offsets, g->tile_offsets, teleport, start, p_out, res, s,
+  return run_pagerank(g->pr, g->cap, o, g->n, g->offsets, g->tile_offsets, teleport, start, p_out, res, s,
                       g->d_outdeg,
                       iter, init);
 }
@@ -500,8 +500,7 @@ int bvmv_group(bvmv_graph* const* graphs, int count, bvmv_graph** out) {
   for (int i = 0; i < count; ++i) {
     const bvmv_graph* m = graphs[i];
     if (!m || m->ngraphs != 1) return fail(BVMV_EINVAL, "group members must be loaded graphs");
-    if (m->device != g->device || m->interval_mode != g->interval_mode)
-      return fail(BVMV_EINVAL, "group members must share device and interval mode");
+    if (m->device != g->device) return fail(BVMV_EINVAL, "group members must share the device");
     const uint64_t rb = uint64_t(g->n), db = hl.data.size(), lb = hl.longs.size();
     if (rb + uint64_t(m->n) >= (uint64_t(1) << 30) || (db + m->hl.data.size()) / 16 >= (uint64_t(1) << 32) ||
         lb + m->hl.longs.size() >= (uint64_t(1) << 32))
@@ -691,7 +690,7 @@ int bvmv_csr_pagerank(bvmv_csr* c, const bvmv_pr_opts* opts, const void* telepor
   auto init = [&](const void* st, const void* te, void* p0, void* z0, hipStream_t ss) {
     return launch_csr_pr_init(C, prec, st, te, p0, z0, c->d_outdeg, c->pr.st, c->pr.slots, ss);
   };
-  return run_pagerank(c->pr, c->cap, o, 0, c->n, offsets, toffs, teleport, start, p_out, res,
+  return run_pagerank(c->pr, c->cap, o, c->n, offsets, toffs, teleport, start, p_out, res,
                       static_cast<hipStream_t>(stream), c->d_outdeg, iter, init);
 }
 

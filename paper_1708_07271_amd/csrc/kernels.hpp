@@ -31,7 +31,7 @@ struct DevCsr {
 
 // LDS bytes per block of the single-vector kernels (0 if the mode is unknown);
 // the loader checks them against the device limit.
-size_t bv_kernel_lds_bytes(const DevLayout& L, int prec, int interval_mode);
+size_t bv_kernel_lds_bytes(const DevLayout& L, int prec);
 size_t csr_kernel_lds_bytes(const DevCsr& C, int prec);
 size_t bv_batch_lds_bytes(const DevLayout& L, int prec, int k);
 
@@ -63,11 +63,9 @@ struct PRArgs {
   int32_t buf;           // index of p_new's buffer (0/1)
 };
 
-hipError_t launch_bv_multiply(const DevLayout& L, int prec, int interval_mode, const void* x, void* y,
-                              hipStream_t s);
+hipError_t launch_bv_multiply(const DevLayout& L, int prec, const void* x, void* y, hipStream_t s);
 hipError_t launch_bv_degrees(const DevLayout& L, int32_t* deg, hipStream_t s);
-hipError_t launch_bv_pagerank_iter(const DevLayout& L, int prec, int interval_mode, const PRArgs& a,
-                                   hipStream_t s);
+hipError_t launch_bv_pagerank_iter(const DevLayout& L, int prec, const PRArgs& a, hipStream_t s);
 // z = p / d, dangling mass and state reset for the start vector (tile grid)
 hipError_t launch_pr_init(const DevLayout& L, int prec, const void* start, const void* tele, void* p0, void* z0,
                           const int32_t* outdeg, PRState* st, double* slots, hipStream_t s);

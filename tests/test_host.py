@@ -84,7 +84,7 @@ def test_decode_rejects_corruption(P):
             assert e.code == P.BVMV_EFORMAT
 
 
-LAYOUT_CASES = [(64, 1024, 4096, 2048), (16, 64, 512, 16), (64, 8192, 16384, 16384), (32, 256, 1024, 40)]
+LAYOUT_CASES = [(64, 1024, 4096, 2048), (16, 64, 512, 16), (64, 8191, 16384, 16384), (32, 256, 1024, 40)]
 
 
 @pytest.mark.parametrize("tile_rows,window_cap,stage,long_bytes", LAYOUT_CASES)
