@@ -92,6 +92,8 @@ def main():
     ap.add_argument("--window-cap", type=int, default=0)
     ap.add_argument("--stage-bytes", type=int, default=0)
     ap.add_argument("--interval-mode", type=int, default=0)
+    ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
+                    help="only run torch copies of MIB MiB (the calibration kernel for HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py runs on one GPU only: the compressed product and PageRank here are single-GPU "
@@ -101,11 +103,22 @@ def main():
     import numpy as np
     import torch
 
-    import bvinputs as B
-    import paper_1708_07271_amd as P
-
     assert torch.cuda.is_available(), "bench.py needs a HIP device"
     dev = torch.device("cuda:0")
+    if args.copy_probe:
+        # a plain device copy of known size: FETCH_SIZE / WRITE_SIZE of this
+        # kernel calibrate the counters read on the product kernels
+        n = args.copy_probe * (1 << 20) // 4
+        a = torch.ones(n, dtype=torch.float32, device=dev)
+        b = torch.empty_like(a)
+        for _ in range(args.steps):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_probe_bytes": 4 * n, "launches": args.steps}), flush=True)
+        return
+
+    import bvinputs as B
+    import paper_1708_07271_amd as P
     t0 = time.perf_counter()
     g = B.workload_graph(args.workload)
     enc = B.encode(g)
@@ -172,12 +185,13 @@ def main():
         "config": {"workload": args.workload, "n": g.n, "m": g.m, "precision": "f32 two-sum compensated",
                    "x": "uniform[0,1) float32, seed 102"},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": PEAK_HBM_GBS, "unit": "GB/s",
-                     "frac": achieved / PEAK_HBM_GBS, "traffic": load_traffic("bv_tile_kernel", args.workload),
-                     "kernel": "bv_tile_kernel", "alg_bytes_per_launch": alg_bytes},
+                     "frac": achieved / PEAK_HBM_GBS, "traffic": load_traffic("bv_wave_kernel", args.workload),
+                     "kernel": "bv_wave_kernel", "alg_bytes_per_launch": alg_bytes},
         "layout": {"bytes": info["layout_bytes"], "bytes_per_edge": info["layout_bytes"] / g.m,
                    "m_prime": info["m_prime"], "m_over_m_prime": g.m / max(info["m_prime"], 1),
                    "units": info["units"], "escapes": info["escapes"], "long_rows": info["long_rows"],
-                   "bitstream_bits_per_edge": enc.data.size * 8 / g.m},
+                   "singles": info["n_singles"], "wide": info["n_wide"], "interval_pairs": info["n_intervals"],
+                   "tiles": info["ntiles"], "bitstream_bits_per_edge": enc.data.size * 8 / g.m},
     }
     if ms_csr is not None:
         result["csr"] = {"edges_per_s": g.m / (ms_csr * 1e-3), "ms": ms_csr, "bytes": csr_bytes,

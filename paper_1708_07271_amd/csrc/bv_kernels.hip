@@ -518,12 +518,12 @@ struct EpiStore {
   }
 };
 
-// The block's residual and dangling partials go to its slot; the member's
-// last block folds all its blocks' slots in a fixed order into the state.
-__device__ __forceinline__ void pr_block_finish(double rs, double dg, PRState* st, double* slots, int with_resid,
-                                                double tol, int32_t max_iter, int32_t buf, unsigned char* s_blk) {
+// The block's residual and dangling partials go to its slot with plain
+// stores; pr_finish_kernel folds a member's slots, in a fixed order, after the
+// launch (the kernel boundary makes them visible: no device-scope fence,
+// which on a multi-XCD part would write back the L2 once per block).
+__device__ __forceinline__ void pr_block_partial(double rs, double dg, double* slots, unsigned char* s_blk) {
   double* blk = reinterpret_cast<double*>(s_blk);
-  __shared__ int s_last;
   const uint32_t wave = threadIdx.x >> 6, lane = lane_id();
   if (lane == 0) {
     blk[2 * wave] = rs;
@@ -538,23 +538,28 @@ __device__ __forceinline__ void pr_block_finish(double rs, double dg, PRState* s
     }
     slots[2 * size_t(blockIdx.x)] = R;
     slots[2 * size_t(blockIdx.x) + 1] = D;
-    __threadfence();
-    const uint32_t prev = atomicAdd(&st->ticket, 1u);
-    s_last = prev + 1 == st->blk_hi - st->blk_lo;
   }
-  __syncthreads();
-  if (!s_last) return;
-  __threadfence();
+}
+
+// One block per member: the member's residual and dangling mass from its
+// blocks' slots, then the stopping test (with_resid = 1, after an iteration;
+// members already done were skipped by the iteration and are left alone) or
+// the start state (with_resid = 0, after pr_init_kernel).
+__global__ void __launch_bounds__(kThreads) pr_finish_kernel(PRState* st_all, const double* __restrict__ slots,
+                                                             int with_resid, double tol, int32_t max_iter,
+                                                             int32_t buf) {
+  __shared__ double s_red[kWaves];
+  PRState* st = st_all + blockIdx.x;
+  if (with_resid && st->done) return;
   double R = 0.0, D = 0.0;
   for (uint32_t t = st->blk_lo + threadIdx.x; t < st->blk_hi; t += kThreads) {
-    R += __builtin_nontemporal_load(&slots[2 * size_t(t)]);
-    D += __builtin_nontemporal_load(&slots[2 * size_t(t) + 1]);
+    R += slots[2 * size_t(t)];
+    D += slots[2 * size_t(t) + 1];
   }
-  R = block_sum_f64(R, blk + 8);
-  D = block_sum_f64(D, blk + 8);
+  R = block_sum_f64(R, s_red);
+  D = block_sum_f64(D, s_red);
   if (threadIdx.x == 0) {
     st->delta = D;
-    st->ticket = 0;
     if (with_resid) {
       st->resid = R;
       st->iter += 1;
@@ -573,7 +578,6 @@ __device__ __forceinline__ void pr_block_finish(double rs, double dg, PRState* s
       st->converged = 0;
       st->final_buf = 0;
     }
-    __threadfence();
   }
 }
 
@@ -603,7 +607,7 @@ struct EpiPR {
     }
     rs = wave_sum_f64(rs);
     dg = wave_sum_f64(dg);
-    pr_block_finish(rs, dg, st, a.slots, 1, a.tol, a.max_iter, a.buf, s_blk);
+    pr_block_partial(rs, dg, a.slots, s_blk);
   }
 };
 
@@ -854,7 +858,7 @@ __global__ void __launch_bounds__(kThreads) pr_init_kernel(const uint32_t* __res
     if (d == 0) dg = double(pv);
   }
   dg = wave_sum_f64(dg);
-  pr_block_finish(0.0, dg, st, slots, 0, 0.0, 0, 0, s_blk);
+  pr_block_partial(0.0, dg, slots, s_blk);
 }
 
 // ---------------------------------------------------------------- CSR kernel
@@ -1325,17 +1329,25 @@ hipError_t launch_bv_degrees(const DevLayout& L, int32_t* deg, hipStream_t s) {
   return launch_tile<MINT>(L, nullptr, EpiStore<MINT>{deg}, nullptr, s);
 }
 
+hipError_t launch_pr_finish(const PRArgs& a, hipStream_t s) {
+  hipLaunchKernelGGL(pr_finish_kernel, dim3(a.members), dim3(kThreads), 0, s, a.st, a.slots, 1, a.tol, a.max_iter,
+                     a.buf);
+  return hipGetLastError();
+}
+
 hipError_t launch_bv_pagerank_iter(const DevLayout& L, int prec, const PRArgs& a, hipStream_t s) {
+  hipError_t e;
   switch (prec) {
-    case 0: return launch_tile<MF64>(L, a.z_cur, EpiPR<MF64>{a}, a.st, s);
-    case 1: return launch_tile<MF32>(L, a.z_cur, EpiPR<MF32>{a}, a.st, s);
-    case 2: return launch_tile<MF32C>(L, a.z_cur, EpiPR<MF32C>{a}, a.st, s);
+    case 0: e = launch_tile<MF64>(L, a.z_cur, EpiPR<MF64>{a}, a.st, s); break;
+    case 1: e = launch_tile<MF32>(L, a.z_cur, EpiPR<MF32>{a}, a.st, s); break;
+    case 2: e = launch_tile<MF32C>(L, a.z_cur, EpiPR<MF32C>{a}, a.st, s); break;
     default: return hipErrorInvalidValue;
   }
+  return e != hipSuccess ? e : launch_pr_finish(a, s);
 }
 
 hipError_t launch_pr_init(const DevLayout& L, int prec, const void* start, const void* tele, void* p0, void* z0,
-                          const int32_t* outdeg, PRState* st, double* slots, hipStream_t s) {
+                          const int32_t* outdeg, PRState* st, double* slots, int members, hipStream_t s) {
   if (L.ntiles == 0) return hipSuccess;
   const uint32_t* base = reinterpret_cast<const uint32_t*>(L.tiles);
   const uint32_t stride = sizeof(TileDesc) / 4;
@@ -1346,6 +1358,8 @@ hipError_t launch_pr_init(const DevLayout& L, int prec, const void* start, const
   else
     hipLaunchKernelGGL(pr_init_kernel<MF32>, dim3(L.ntiles / kWaves), dim3(kThreads), 0, s, base, stride, graphs,
                        start, tele, p0, z0, outdeg, st, slots);
+  if (hipError_t e = hipGetLastError()) return e;
+  hipLaunchKernelGGL(pr_finish_kernel, dim3(members), dim3(kThreads), 0, s, st, slots, 0, 0.0, 0, 0);
   return hipGetLastError();
 }
 
@@ -1363,16 +1377,14 @@ hipError_t launch_csr_multiply(const DevCsr& C, int prec, const void* x, void* y
 }
 
 hipError_t launch_csr_pagerank_iter(const DevCsr& C, int prec, const PRArgs& a, hipStream_t s) {
+  hipError_t e;
   switch (prec) {
-    case 0:
-      return launch_csr<MF64>(C, a.z_cur, EpiPR<MF64>{a}, a.st, s);
-    case 1:
-      return launch_csr<MF32>(C, a.z_cur, EpiPR<MF32>{a}, a.st, s);
-    case 2:
-      return launch_csr<MF32C>(C, a.z_cur, EpiPR<MF32C>{a}, a.st, s);
-    default:
-      return hipErrorInvalidValue;
+    case 0: e = launch_csr<MF64>(C, a.z_cur, EpiPR<MF64>{a}, a.st, s); break;
+    case 1: e = launch_csr<MF32>(C, a.z_cur, EpiPR<MF32>{a}, a.st, s); break;
+    case 2: e = launch_csr<MF32C>(C, a.z_cur, EpiPR<MF32C>{a}, a.st, s); break;
+    default: return hipErrorInvalidValue;
   }
+  return e != hipSuccess ? e : launch_pr_finish(a, s);
 }
 
 hipError_t launch_csr_pr_init(const DevCsr& C, int prec, const void* start, const void* tele, void* p0, void* z0,
@@ -1386,6 +1398,8 @@ hipError_t launch_csr_pr_init(const DevCsr& C, int prec, const void* start, cons
   else
     hipLaunchKernelGGL(pr_init_kernel<MF32>, dim3(C.ntiles / kWaves), dim3(kThreads), 0, s, base, stride, nullptr,
                        start, tele, p0, z0, outdeg, st, slots);
+  if (hipError_t e = hipGetLastError()) return e;
+  hipLaunchKernelGGL(pr_finish_kernel, dim3(1), dim3(kThreads), 0, s, st, slots, 0, 0.0, 0, 0);
   return hipGetLastError();
 }
 

@@ -302,6 +302,7 @@ int run_pagerank(PRWork& w, hipStream_t cap, const PROptsResolved& o, int64_t n,
       a.tol = o.tol;
       a.max_iter = o.max_iter;
       a.buf = (c + 1) % 2;
+      a.members = members;
       ce = iter(a, cap);
     }
     hipGraph_t gr = nullptr;
@@ -478,7 +479,7 @@ int bvmv_pagerank(bvmv_graph* g, const bvmv_pr_opts* opts, const void* teleport,
   const int prec = o.prec;
   auto iter = [&](const PRArgs& a, hipStream_t cs) { return launch_bv_pagerank_iter(L, prec, a, cs); };
   auto init = [&](const void* st, const void* te, void* p0, void* z0, hipStream_t ss) {
-    return launch_pr_init(L, prec, st, te, p0, z0, g->d_outdeg, g->pr.st, g->pr.slots, ss);
+    return launch_pr_init(L, prec, st, te, p0, z0, g->d_outdeg, g->pr.st, g->pr.slots, int(g->offsets.size()) - 1, ss);
   };
   return run_pagerank(g->pr, g->cap, o, g->n, g->offsets, g->tile_offsets, teleport, start, p_out, res, s,
                       g->d_outdeg,

@@ -44,9 +44,7 @@ struct PRState {
   int32_t done;      // 1 once converged or out of iterations
   int32_t converged;
   int32_t final_buf; // buffer (0/1) holding the final iterate once done
-  uint32_t ticket;   // blocks of the current launch that have finished
   uint32_t blk_lo, blk_hi;    // block range of the member (kTilesPerBlock tiles per block)
-  uint32_t pad;
 };
 
 struct PRArgs {
@@ -61,6 +59,7 @@ struct PRArgs {
   double beta, tol;
   int32_t max_iter;
   int32_t buf;           // index of p_new's buffer (0/1)
+  int32_t members;       // member graphs (PRState entries)
 };
 
 hipError_t launch_bv_multiply(const DevLayout& L, int prec, const void* x, void* y, hipStream_t s);
@@ -68,7 +67,7 @@ hipError_t launch_bv_degrees(const DevLayout& L, int32_t* deg, hipStream_t s);
 hipError_t launch_bv_pagerank_iter(const DevLayout& L, int prec, const PRArgs& a, hipStream_t s);
 // z = p / d, dangling mass and state reset for the start vector (tile grid)
 hipError_t launch_pr_init(const DevLayout& L, int prec, const void* start, const void* tele, void* p0, void* z0,
-                          const int32_t* outdeg, PRState* st, double* slots, hipStream_t s);
+                          const int32_t* outdeg, PRState* st, double* slots, int members, hipStream_t s);
 
 hipError_t launch_csr_multiply(const DevCsr& C, int prec, const void* x, void* y, hipStream_t s);
 hipError_t launch_csr_pagerank_iter(const DevCsr& C, int prec, const PRArgs& a, hipStream_t s);
