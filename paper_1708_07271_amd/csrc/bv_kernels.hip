@@ -553,8 +553,8 @@ __global__ void __launch_bounds__(kThreads) pr_finish_kernel(PRState* st_all, co
   if (with_resid && st->done) return;
   double R = 0.0, D = 0.0;
   for (uint32_t t = st->blk_lo + threadIdx.x; t < st->blk_hi; t += kThreads) {
-    R += slots[2 * size_t(t)];
-    D += slots[2 * size_t(t) + 1];
+    R += slots[2 * (size_t(st->slot0) + t)];
+    D += slots[2 * (size_t(st->slot0) + t) + 1];
   }
   R = block_sum_f64(R, s_red);
   D = block_sum_f64(D, s_red);
@@ -1063,16 +1063,86 @@ struct BatchCarve {
   using CAcc = typename M::CAcc;
   uint32_t T, SB;  // rows per tile (<= 256, one per thread), staged bytes
   __host__ __device__ size_t u() const { return align16((size_t(T) + 1) * 4); }
-  __host__ __device__ size_t acc() const { return 7 * u(); }
+  __host__ __device__ size_t acc() const { return 6 * u(); }
   __host__ __device__ size_t tmp() const { return acc() + align16(size_t(T) * G * sizeof(CAcc)); }
-  __host__ __device__ size_t data() const { return tmp() + align16(kThreads * sizeof(PAcc)); }
+  // two doubles per thread for the PageRank epilogue's per-column sums
+  __host__ __device__ size_t pr() const { return tmp() + align16(kThreads * sizeof(PAcc)); }
+  __host__ __device__ size_t data() const { return pr() + 2 * kThreads * sizeof(double); }
   __host__ __device__ size_t red() const { return data() + align16(size_t(SB)); }
   __host__ __device__ size_t total() const { return red() + 256; }
 };
 
-template <class M, int G>
+// Multi-vector epilogues, called by every thread for the right-hand sides
+// [c0, c0 + G) once their sums are in s_acc (row r, column c0 + l at r*G + l).
+template <class M>
+struct EpiStoreBatch {
+  typename M::X* Y;
+  int k;
+  int64_t ld;
+  template <int G>
+  __device__ void run(const TileDesc& td, const typename M::CAcc* s_acc, int c0, double*) const {
+    for (uint32_t idx = threadIdx.x; idx < td.nrows * G; idx += kThreads) {
+      const int cc = c0 + int(idx % G);
+      if (cc < k) Y[int64_t(td.row0 + idx / G) * ld + cc] = M::out(s_acc[idx]);
+    }
+  }
+};
+
+// Personalized PageRank update of Eq. (1) for every right-hand side c (its
+// own teleport column, dangling mass and stopping state); columns already
+// done are left alone.  Thread t always holds column c0 + t % G, so its
+// residual and dangling sums are per column; the block's sums per column go
+// to slot (c * blocks + block) for pr_finish_kernel.
+template <class M>
+struct EpiPRBatch {
+  PRArgs a;
+  template <int G>
+  __device__ void run(const TileDesc& td, const typename M::CAcc* s_acc, int c0, double* s_pr) const {
+    using X = typename M::X;
+    const X* p = static_cast<const X*>(a.p_cur);
+    X* pn = static_cast<X*>(a.p_new);
+    X* zn = static_cast<X*>(a.z_new);
+    const X* tele = static_cast<const X*>(a.tele);
+    const int k = a.k;
+    const int cc = c0 + int(threadIdx.x % G);
+    const bool act = cc < k && !a.st[cc].done;
+    double rs = 0.0, dg = 0.0;
+    if (act) {
+      const PRState& st = a.st[cc];
+      const double delta = st.delta, inv_n = st.inv_n, beta = a.beta;
+      for (uint32_t idx = threadIdx.x; idx < td.nrows * G; idx += kThreads) {
+        const uint32_t v = td.row0 + idx / G;
+        const int64_t e = int64_t(v) * k + cc;
+        const double y = M::to_d(s_acc[idx]);
+        const double t = tele ? double(tele[e]) : inv_n;
+        const X pnew = X((1.0 - beta) * t + beta * (y + delta * t));
+        pn[e] = pnew;
+        const int32_t d = a.outdeg[v];
+        zn[e] = d > 0 ? pnew / X(d) : X(0);
+        rs += fabs(double(pnew) - double(p[e]));
+        if (d == 0) dg += double(pnew);
+      }
+    }
+    s_pr[2 * threadIdx.x] = rs;
+    s_pr[2 * threadIdx.x + 1] = dg;
+    __syncthreads();
+    if (threadIdx.x < G && c0 + int(threadIdx.x) < k) {
+      double R = 0.0, D = 0.0;
+      for (uint32_t t = threadIdx.x; t < kThreads; t += G) {
+        R += s_pr[2 * t];
+        D += s_pr[2 * t + 1];
+      }
+      const size_t slot = size_t(c0 + threadIdx.x) * gridDim.x + blockIdx.x;
+      a.slots[2 * slot] = R;
+      a.slots[2 * slot + 1] = D;
+    }
+    __syncthreads();
+  }
+};
+
+template <class M, int G, class Epi>
 __global__ void __launch_bounds__(kThreads) bv_batch_kernel(DevLayout L, const typename M::X* __restrict__ X,
-                                                            typename M::X* __restrict__ Y, int k, int64_t ld) {
+                                                            int k, int64_t ld, Epi epi) {
   using Xt = typename M::X;
   using PAcc = typename M::PAcc;
   using CAcc = typename M::CAcc;
@@ -1085,10 +1155,11 @@ __global__ void __launch_bounds__(kThreads) bv_batch_kernel(DevLayout L, const t
   uint32_t* s_ns = reinterpret_cast<uint32_t*>(smem + u);
   uint32_t* s_o16 = reinterpret_cast<uint32_t*>(smem + 2 * u);
   uint32_t* s_ow = reinterpret_cast<uint32_t*>(smem + 3 * u);
-  uint32_t* s_ol = reinterpret_cast<uint32_t*>(smem + 5 * u);
-  uint32_t* s_list = reinterpret_cast<uint32_t*>(smem + 6 * u);
+  uint32_t* s_ol = reinterpret_cast<uint32_t*>(smem + 4 * u);
+  uint32_t* s_list = reinterpret_cast<uint32_t*>(smem + 5 * u);
   CAcc* s_acc = reinterpret_cast<CAcc*>(smem + cv.acc());
   PAcc* s_tmp = reinterpret_cast<PAcc*>(smem + cv.tmp());
+  double* s_pr = reinterpret_cast<double*>(smem + cv.pr());
   unsigned char* s_data = smem + cv.data();
   unsigned char* s_red = smem + cv.red();
   const uint32_t tid = threadIdx.x, team = tid / G, lane = tid % G;
@@ -1124,7 +1195,7 @@ __global__ void __launch_bounds__(kThreads) bv_batch_kernel(DevLayout L, const t
           const uint32_t f2 = s16[++e] & kS16Off;
           PAcc t = M::pzero();
           if (act)
-            for (int64_t c = win0 + (f2 >> 1), c1 = win0 + (f >> 1); c < c1; ++c) M::padd(t, Xc[c * ld]);
+            for (int64_t cl = win0 + (f2 >> 1), c1 = win0 + (f >> 1); cl < c1; ++cl) M::padd(t, Xc[cl * ld]);
           a = M::pcomb(a, (w & kS16Neg) ? -t : t);
         } else {
           const Xt v = act ? Xc[(win0 + int64_t(f >> 1) - 1) * ld] : Xt(0);
@@ -1167,11 +1238,61 @@ __global__ void __launch_bounds__(kThreads) bv_batch_kernel(DevLayout L, const t
       }
       __syncthreads();
     }
-    for (uint32_t idx = tid; idx < nrows * G; idx += kThreads) {
-      const int cc = c0 + int(idx % G);
-      if (cc < k) Y[int64_t(td.row0 + idx / G) * ld + cc] = M::out(s_acc[idx]);
+    epi.template run<G>(td, s_acc, c0, s_pr);
+    __syncthreads();
+  }
+}
+
+// Personalized PageRank start for k right-hand sides: p0 = start (or the
+// teleport columns, or uniform), z0 = p0 / d, and each column's dangling mass
+// per block (slot c * blocks + block), folded by pr_finish_kernel.
+template <class M, int G>
+__global__ void __launch_bounds__(kThreads) pr_init_batch_kernel(DevLayout L, int k, const void* start_,
+                                                                 const void* tele_, void* p0_, void* z0_,
+                                                                 const int32_t* __restrict__ outdeg,
+                                                                 const PRState* st, double* slots) {
+  using X = typename M::X;
+  __shared__ double s_pr[kThreads];
+  const TileDesc td = L.tiles[blockIdx.x];
+  const X* start = static_cast<const X*>(start_);
+  const X* tele = static_cast<const X*>(tele_);
+  X* p0 = static_cast<X*>(p0_);
+  X* z0 = static_cast<X*>(z0_);
+  for (int c0 = 0; c0 < k; c0 += G) {
+    const int cc = c0 + int(threadIdx.x % G);
+    double dg = 0.0;
+    if (cc < k) {
+      for (uint32_t idx = threadIdx.x; idx < td.nrows * G; idx += kThreads) {
+        const uint32_t v = td.row0 + idx / G;
+        const int64_t e = int64_t(v) * k + cc;
+        const X pv = start ? start[e] : (tele ? tele[e] : X(st[cc].inv_n));
+        p0[e] = pv;
+        const int32_t d = outdeg[v];
+        z0[e] = d > 0 ? pv / X(d) : X(0);
+        if (d == 0) dg += double(pv);
+      }
+    }
+    s_pr[threadIdx.x] = dg;
+    __syncthreads();
+    if (threadIdx.x < G && c0 + int(threadIdx.x) < k) {
+      double D = 0.0;
+      for (uint32_t t = threadIdx.x; t < kThreads; t += G) D += s_pr[t];
+      const size_t slot = size_t(c0 + threadIdx.x) * gridDim.x + blockIdx.x;
+      slots[2 * slot] = 0.0;
+      slots[2 * slot + 1] = D;
     }
     __syncthreads();
+  }
+}
+
+// p_out column c = the buffer holding column c's final iterate.
+template <class X>
+__global__ void __launch_bounds__(kThreads) pr_select_kernel(const PRState* __restrict__ st, const X* __restrict__ p0,
+                                                             const X* __restrict__ p1, X* __restrict__ out,
+                                                             int64_t total, int k) {
+  for (int64_t e = int64_t(blockIdx.x) * kThreads + threadIdx.x; e < total; e += int64_t(gridDim.x) * kThreads) {
+    const int c = int(e % k);
+    out[e] = st[c].final_buf ? p1[e] : p0[e];
   }
 }
 
@@ -1233,14 +1354,14 @@ size_t batch_lds(const DevLayout& L) {
   return BatchCarve<M, G>{L.tcap, L.sbytes}.total();
 }
 
-template <class M, int G>
-hipError_t launch_batch_g(const DevLayout& L, const void* X, void* Y, int k, int64_t ld, hipStream_t s) {
+template <class M, int G, class Epi>
+hipError_t launch_batch_g(const DevLayout& L, const void* X, int k, int64_t ld, const Epi& epi, hipStream_t s) {
   const size_t smem = batch_lds<M, G>(L);
-  auto kern = bv_batch_kernel<M, G>;
+  auto kern = bv_batch_kernel<M, G, Epi>;
   if (hipError_t e = set_lds(reinterpret_cast<const void*>(kern), smem)) return e;
   if (L.ntiles == 0) return hipSuccess;
-  hipLaunchKernelGGL(kern, dim3(L.ntiles), dim3(kThreads), smem, s, L, static_cast<const typename M::X*>(X),
-                     static_cast<typename M::X*>(Y), k, ld);
+  hipLaunchKernelGGL(kern, dim3(L.ntiles), dim3(kThreads), smem, s, L, static_cast<const typename M::X*>(X), k, ld,
+                     epi);
   return hipGetLastError();
 }
 
@@ -1262,8 +1383,7 @@ size_t batch_lds_g(const DevLayout& L, int G) {
   }
 }
 
-// team width halved while the tile's T x G accumulators exceed 96 KB of LDS
-// (further right-hand sides are taken by extra passes over the tile)
+// the widest team whose LDS carve stays within 96 KB
 template <class M>
 int pick_g(const DevLayout& L, int k) {
   int G = team_width(k);
@@ -1276,14 +1396,31 @@ size_t batch_lds_k(const DevLayout& L, int k) {
   return batch_lds_g<M>(L, pick_g<M>(L, k));
 }
 
-template <class M>
-hipError_t launch_batch(const DevLayout& L, const void* X, void* Y, int k, int64_t ld, hipStream_t s) {
+template <class M, class Epi>
+hipError_t launch_batch(const DevLayout& L, const void* X, int k, int64_t ld, const Epi& epi, hipStream_t s) {
   switch (pick_g<M>(L, k)) {
-    case 64: return launch_batch_g<M, 64>(L, X, Y, k, ld, s);
-    case 32: return launch_batch_g<M, 32>(L, X, Y, k, ld, s);
-    case 16: return launch_batch_g<M, 16>(L, X, Y, k, ld, s);
-    case 8: return launch_batch_g<M, 8>(L, X, Y, k, ld, s);
-    default: return launch_batch_g<M, 4>(L, X, Y, k, ld, s);
+    case 64: return launch_batch_g<M, 64>(L, X, k, ld, epi, s);
+    case 32: return launch_batch_g<M, 32>(L, X, k, ld, epi, s);
+    case 16: return launch_batch_g<M, 16>(L, X, k, ld, epi, s);
+    case 8: return launch_batch_g<M, 8>(L, X, k, ld, epi, s);
+    default: return launch_batch_g<M, 4>(L, X, k, ld, epi, s);
+  }
+}
+
+template <class M>
+hipError_t launch_batch_init(const DevLayout& L, int k, const void* start, const void* tele, void* p0, void* z0,
+                             const int32_t* outdeg, const PRState* st, double* slots, hipStream_t s) {
+  if (L.ntiles == 0) return hipSuccess;
+  auto go = [&](auto kern) {
+    hipLaunchKernelGGL(kern, dim3(L.ntiles), dim3(kThreads), 0, s, L, k, start, tele, p0, z0, outdeg, st, slots);
+    return hipGetLastError();
+  };
+  switch (team_width(k)) {
+    case 64: return go(pr_init_batch_kernel<M, 64>);
+    case 32: return go(pr_init_batch_kernel<M, 32>);
+    case 16: return go(pr_init_batch_kernel<M, 16>);
+    case 8: return go(pr_init_batch_kernel<M, 8>);
+    default: return go(pr_init_batch_kernel<M, 4>);
   }
 }
 
@@ -1406,15 +1543,47 @@ hipError_t launch_csr_pr_init(const DevCsr& C, int prec, const void* start, cons
 hipError_t launch_bv_multiply_batch(const DevLayout& L, int prec, const void* X, void* Y, int k, int64_t ld,
                                     hipStream_t s) {
   switch (prec) {
-    case 0:
-      return launch_batch<MF64>(L, X, Y, k, ld, s);
-    case 1:
-      return launch_batch<MF32>(L, X, Y, k, ld, s);
-    case 2:
-      return launch_batch<MF32C>(L, X, Y, k, ld, s);
-    default:
-      return hipErrorInvalidValue;
+    case 0: return launch_batch<MF64>(L, X, k, ld, EpiStoreBatch<MF64>{static_cast<double*>(Y), k, ld}, s);
+    case 1: return launch_batch<MF32>(L, X, k, ld, EpiStoreBatch<MF32>{static_cast<float*>(Y), k, ld}, s);
+    case 2: return launch_batch<MF32C>(L, X, k, ld, EpiStoreBatch<MF32C>{static_cast<float*>(Y), k, ld}, s);
+    default: return hipErrorInvalidValue;
   }
+}
+
+hipError_t launch_bv_batch_pagerank_iter(const DevLayout& L, int prec, const PRArgs& a, hipStream_t s) {
+  hipError_t e;
+  switch (prec) {
+    case 0: e = launch_batch<MF64>(L, a.z_cur, a.k, a.k, EpiPRBatch<MF64>{a}, s); break;
+    case 1: e = launch_batch<MF32>(L, a.z_cur, a.k, a.k, EpiPRBatch<MF32>{a}, s); break;
+    case 2: e = launch_batch<MF32C>(L, a.z_cur, a.k, a.k, EpiPRBatch<MF32C>{a}, s); break;
+    default: return hipErrorInvalidValue;
+  }
+  return e != hipSuccess ? e : launch_pr_finish(a, s);
+}
+
+hipError_t launch_batch_pr_init(const DevLayout& L, int prec, int k, const void* start, const void* tele, void* p0,
+                                void* z0, const int32_t* outdeg, PRState* st, double* slots, hipStream_t s) {
+  hipError_t e = prec == 0 ? launch_batch_init<MF64>(L, k, start, tele, p0, z0, outdeg, st, slots, s)
+                           : launch_batch_init<MF32>(L, k, start, tele, p0, z0, outdeg, st, slots, s);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(pr_finish_kernel, dim3(k), dim3(kThreads), 0, s, st, slots, 0, 0.0, 0, 0);
+  return hipGetLastError();
+}
+
+hipError_t launch_pr_select(int prec, const PRState* st, const void* p0, const void* p1, void* out, int64_t n, int k,
+                            hipStream_t s) {
+  const int64_t total = n * k;
+  const uint32_t blocks = uint32_t(std::min<int64_t>((total + kThreads - 1) / kThreads, 65536));
+  if (total == 0) return hipSuccess;
+  if (prec == 0)
+    hipLaunchKernelGGL(pr_select_kernel<double>, dim3(blocks), dim3(kThreads), 0, s, st,
+                       static_cast<const double*>(p0), static_cast<const double*>(p1), static_cast<double*>(out),
+                       total, k);
+  else
+    hipLaunchKernelGGL(pr_select_kernel<float>, dim3(blocks), dim3(kThreads), 0, s, st,
+                       static_cast<const float*>(p0), static_cast<const float*>(p1), static_cast<float*>(out), total,
+                       k);
+  return hipGetLastError();
 }
 
 }  // namespace bvmv

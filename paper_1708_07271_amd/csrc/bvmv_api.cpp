@@ -182,11 +182,13 @@ struct bvmv_graph {
   int ngraphs = 1;
   std::vector<int64_t> offsets;        // ngraphs + 1
   std::vector<uint32_t> tile_offsets;  // ngraphs + 1
-  PRWork pr;
+  PRWork pr;   // one right-hand side per member
+  PRWork prb;  // k right-hand sides
   hipStream_t cap = nullptr;
 
   void release_device() {
     pr.release();
+    prb.release();
     dev_free(d_tiles);
     dev_free(d_info);
     dev_free(d_ns);
@@ -262,24 +264,20 @@ int upload_layout(bvmv_graph* g) {
   return BVMV_OK;
 }
 
-// Launch chunked PageRank on a tile layout or a CSR.  `iter` launches one
-// iteration on stream s with the given args; `init` the start kernel.
-template <class IterFn, class InitFn>
-int run_pagerank(PRWork& w, hipStream_t cap, const PROptsResolved& o, int64_t n,
-                 const std::vector<int64_t>& offsets, const std::vector<uint32_t>& tile_offsets,
-                 const void* tele, const void* start, void* p_out, bvmv_pr_result* res, hipStream_t s,
-                 const int32_t* outdeg, IterFn iter, InitFn init) {
-  const int members = int(offsets.size()) - 1;
-  if (int rc = w.ensure(o.prec, n, members, int64_t(tile_offsets.back()))) return rc;
+// Launch chunked PageRank on a tile layout, a group or a CSR, for one or k
+// right-hand sides.  `states` holds the members' start states (1/n, slot
+// ranges); p and z hold n_elems elements; `iter` launches one iteration on a
+// stream, `init` the start kernels, `out` writes p_out from the final
+// buffers once every member is done.
+template <class IterFn, class InitFn, class OutFn>
+int run_pagerank(PRWork& w, hipStream_t cap, const PROptsResolved& o, int64_t n_elems, int k,
+                 const std::vector<PRState>& states, int64_t nslots, const void* tele, const void* start,
+                 bvmv_pr_result* res, hipStream_t s, const int32_t* outdeg, IterFn iter, InitFn init, OutFn out) {
+  const int members = int(states.size());
+  if (int rc = w.ensure(o.prec, n_elems, members, nslots)) return rc;
   if (!outdeg || !w.p[0] || !w.p[1] || !w.z[0] || !w.z[1] || !w.st || !w.slots || !w.h_st)
     return fail(BVMV_EINVAL, "PageRank working set is incomplete");
-  for (int gI = 0; gI < members; ++gI) {
-    PRState& st = w.h_st[gI];
-    std::memset(&st, 0, sizeof(st));
-    st.inv_n = 1.0 / double(offsets[size_t(gI) + 1] - offsets[size_t(gI)]);
-    st.blk_lo = tile_offsets[size_t(gI)] / kTilesPerBlock;
-    st.blk_hi = tile_offsets[size_t(gI) + 1] / kTilesPerBlock;
-  }
+  std::memcpy(w.h_st, states.data(), sizeof(PRState) * size_t(members));
   HIP_TRY(hipMemcpyAsync(w.st, w.h_st, sizeof(PRState) * size_t(members), hipMemcpyHostToDevice, s));
   HIP_TRY(init(start, tele, w.p[0], w.z[0], s));
   const bool same = w.exec && w.key_tele == tele && w.key_beta == o.beta && w.key_tol == o.tol &&
@@ -303,6 +301,7 @@ int run_pagerank(PRWork& w, hipStream_t cap, const PROptsResolved& o, int64_t n,
       a.max_iter = o.max_iter;
       a.buf = (c + 1) % 2;
       a.members = members;
+      a.k = k;
       ce = iter(a, cap);
     }
     hipGraph_t gr = nullptr;
@@ -329,15 +328,10 @@ int run_pagerank(PRWork& w, hipStream_t cap, const PROptsResolved& o, int64_t n,
     for (int gI = 0; gI < members; ++gI) all = all && w.h_st[gI].done;
     if (all) break;
   }
-  const size_t es = elem_size(o.prec);
+  HIP_TRY(out(w, s));
   int status = BVMV_OK;
   for (int gI = 0; gI < members; ++gI) {
     const PRState& st = w.h_st[gI];
-    const size_t off = size_t(offsets[size_t(gI)]) * es;
-    const size_t bytes = size_t(offsets[size_t(gI) + 1] - offsets[size_t(gI)]) * es;
-    const int fb = st.done ? st.final_buf : 0;
-    HIP_TRY(hipMemcpyAsync(static_cast<char*>(p_out) + off, static_cast<const char*>(w.p[fb]) + off, bytes,
-                           hipMemcpyDeviceToDevice, s));
     if (res) {
       res[gI].iters = st.iter;
       res[gI].converged = st.converged;
@@ -460,6 +454,35 @@ int bvmv_multiply_batch(bvmv_graph* g, const void* X, void* Y, int k, int64_t ld
   return BVMV_OK;
 }
 
+// Start states of the members of a single graph or a group (one right-hand
+// side each): 1/n and the member's block range (kTilesPerBlock tiles per block).
+std::vector<PRState> member_states(const std::vector<int64_t>& offsets, const std::vector<uint32_t>& tile_offsets) {
+  std::vector<PRState> v(offsets.size() - 1);
+  for (size_t gI = 0; gI < v.size(); ++gI) {
+    std::memset(&v[gI], 0, sizeof(PRState));
+    v[gI].inv_n = 1.0 / double(offsets[gI + 1] - offsets[gI]);
+    v[gI].blk_lo = tile_offsets[gI] / kTilesPerBlock;
+    v[gI].blk_hi = tile_offsets[gI + 1] / kTilesPerBlock;
+  }
+  return v;
+}
+
+// p_out rows of each member from the buffer holding its final iterate
+hipError_t copy_member_outputs(const PRWork& w, const std::vector<int64_t>& offsets, int prec, void* p_out,
+                               hipStream_t s) {
+  const size_t es = elem_size(prec);
+  for (size_t gI = 0; gI + 1 < offsets.size(); ++gI) {
+    const PRState& st = w.h_st[gI];
+    const size_t off = size_t(offsets[gI]) * es;
+    const size_t bytes = size_t(offsets[gI + 1] - offsets[gI]) * es;
+    const int fb = st.done ? st.final_buf : 0;
+    if (hipError_t e = hipMemcpyAsync(static_cast<char*>(p_out) + off, static_cast<const char*>(w.p[fb]) + off,
+                                      bytes, hipMemcpyDeviceToDevice, s))
+      return e;
+  }
+  return hipSuccess;
+}
+
 int bvmv_degrees(bvmv_graph* g, int32_t* deg, void* stream) {
   if (!g || !deg) return fail(BVMV_EINVAL, "null argument");
   DeviceGuard dg(g->device);
@@ -472,18 +495,44 @@ int bvmv_pagerank(bvmv_graph* g, const bvmv_pr_opts* opts, const void* teleport,
   if (!g || !p_out) return fail(BVMV_EINVAL, "null argument");
   PROptsResolved o;
   if (int rc = resolve_pr_opts(opts, o)) return rc;
-  if (k != 1) return fail(BVMV_EINVAL, "k > 1 needs the batched PageRank entry");
+  if (k < 1 || k > 64) return fail(BVMV_EINVAL, "k must be in 1..64");
+  if (k > 1 && g->ngraphs != 1) return fail(BVMV_EINVAL, "k > 1 needs a single graph, not a group");
   DeviceGuard dg(g->device);
   hipStream_t s = static_cast<hipStream_t>(stream);
   DevLayout L = g->L;
   const int prec = o.prec;
-  auto iter = [&](const PRArgs& a, hipStream_t cs) { return launch_bv_pagerank_iter(L, prec, a, cs); };
+  if (k == 1) {
+    auto iter = [&](const PRArgs& a, hipStream_t cs) { return launch_bv_pagerank_iter(L, prec, a, cs); };
+    auto init = [&](const void* st, const void* te, void* p0, void* z0, hipStream_t ss) {
+      return launch_pr_init(L, prec, st, te, p0, z0, g->d_outdeg, g->pr.st, g->pr.slots,
+                            int(g->offsets.size()) - 1, ss);
+    };
+    auto out = [&](const PRWork& w, hipStream_t ss) { return copy_member_outputs(w, g->offsets, prec, p_out, ss); };
+    return run_pagerank(g->pr, g->cap, o, g->n, 1, member_states(g->offsets, g->tile_offsets),
+                        int64_t(L.ntiles) / kTilesPerBlock + 1, teleport, start, res, s, g->d_outdeg, iter, init,
+                        out);
+  }
+  // k right-hand sides: one state per column, each column's block partials at
+  // slots c * ntiles .. (c + 1) * ntiles - 1 (one block per tile)
+  std::vector<PRState> states(static_cast<size_t>(k));
+  for (int c = 0; c < k; ++c) {
+    std::memset(&states[size_t(c)], 0, sizeof(PRState));
+    states[size_t(c)].inv_n = 1.0 / double(g->n);
+    states[size_t(c)].blk_lo = 0;
+    states[size_t(c)].blk_hi = L.ntiles;
+    states[size_t(c)].slot0 = uint32_t(c) * L.ntiles;
+  }
+  if (int64_t(L.ntiles) * k >= (int64_t(1) << 32)) return fail(BVMV_EINVAL, "too many tiles for k right-hand sides");
+  PRWork& w = g->prb;
+  auto iter = [&](const PRArgs& a, hipStream_t cs) { return launch_bv_batch_pagerank_iter(L, prec, a, cs); };
   auto init = [&](const void* st, const void* te, void* p0, void* z0, hipStream_t ss) {
-    return launch_pr_init(L, prec, st, te, p0, z0, g->d_outdeg, g->pr.st, g->pr.slots, int(g->offsets.size()) - 1, ss);
+    return launch_batch_pr_init(L, prec, k, st, te, p0, z0, g->d_outdeg, w.st, w.slots, ss);
   };
-  return run_pagerank(g->pr, g->cap, o, g->n, g->offsets, g->tile_offsets, teleport, start, p_out, res, s,
-                      g->d_outdeg,
-                      iter, init);
+  auto out = [&](const PRWork& ww, hipStream_t ss) {
+    return launch_pr_select(prec, ww.st, ww.p[0], ww.p[1], p_out, g->n, k, ss);
+  };
+  return run_pagerank(w, g->cap, o, g->n * k, k, states, int64_t(L.ntiles) * k + 1, teleport, start, res, s,
+                      g->d_outdeg, iter, init, out);
 }
 
 int bvmv_group(bvmv_graph* const* graphs, int count, bvmv_graph** out) {
@@ -686,13 +735,17 @@ int bvmv_csr_pagerank(bvmv_csr* c, const bvmv_pr_opts* opts, const void* telepor
   DevCsr C = c->C;
   const int prec = o.prec;
   std::vector<int64_t> offsets{0, c->n};
-  std::vector<uint32_t> toffs{0, C.ntiles};
+  std::vector<PRState> states(1);
+  std::memset(&states[0], 0, sizeof(PRState));
+  states[0].inv_n = 1.0 / double(c->n);
+  states[0].blk_hi = C.ntiles / kTilesPerBlock;
   auto iter = [&](const PRArgs& a, hipStream_t cs) { return launch_csr_pagerank_iter(C, prec, a, cs); };
   auto init = [&](const void* st, const void* te, void* p0, void* z0, hipStream_t ss) {
     return launch_csr_pr_init(C, prec, st, te, p0, z0, c->d_outdeg, c->pr.st, c->pr.slots, ss);
   };
-  return run_pagerank(c->pr, c->cap, o, c->n, offsets, toffs, teleport, start, p_out, res,
-                      static_cast<hipStream_t>(stream), c->d_outdeg, iter, init);
+  auto out = [&](const PRWork& w, hipStream_t ss) { return copy_member_outputs(w, offsets, prec, p_out, ss); };
+  return run_pagerank(c->pr, c->cap, o, c->n, 1, states, int64_t(C.ntiles) / kTilesPerBlock + 1, teleport, start,
+                      res, static_cast<hipStream_t>(stream), c->d_outdeg, iter, init, out);
 }
 
 int64_t bvmv_csr_bytes(const bvmv_csr* c) {

@@ -44,7 +44,9 @@ struct PRState {
   int32_t done;      // 1 once converged or out of iterations
   int32_t converged;
   int32_t final_buf; // buffer (0/1) holding the final iterate once done
-  uint32_t blk_lo, blk_hi;    // block range of the member (kTilesPerBlock tiles per block)
+  uint32_t blk_lo, blk_hi;    // block range of the member's partial slots
+  uint32_t slot0;             // the member's first slot (slots slot0 + blk_lo .. slot0 + blk_hi - 1)
+  uint32_t pad;
 };
 
 struct PRArgs {
@@ -59,7 +61,8 @@ struct PRArgs {
   double beta, tol;
   int32_t max_iter;
   int32_t buf;           // index of p_new's buffer (0/1)
-  int32_t members;       // member graphs (PRState entries)
+  int32_t members;       // PRState entries (member graphs, or right-hand sides)
+  int32_t k;             // right-hand sides (node-major p, z, teleport with leading dimension k)
 };
 
 hipError_t launch_bv_multiply(const DevLayout& L, int prec, const void* x, void* y, hipStream_t s);
@@ -75,6 +78,13 @@ hipError_t launch_csr_pr_init(const DevCsr& C, int prec, const void* start, cons
                               const int32_t* outdeg, PRState* st, double* slots, hipStream_t s);
 
 // Y = A X for k <= 64 right-hand sides, node-major with leading dimension ld
+// Batched personalized PageRank (k right-hand sides, node-major n x k).
+hipError_t launch_bv_batch_pagerank_iter(const DevLayout& L, int prec, const PRArgs& a, hipStream_t s);
+hipError_t launch_batch_pr_init(const DevLayout& L, int prec, int k, const void* start, const void* tele, void* p0,
+                                void* z0, const int32_t* outdeg, PRState* st, double* slots, hipStream_t s);
+// out = per column c, the buffer (p0 or p1) holding column c's final iterate
+hipError_t launch_pr_select(int prec, const PRState* st, const void* p0, const void* p1, void* out, int64_t n, int k,
+                            hipStream_t s);
 hipError_t launch_bv_multiply_batch(const DevLayout& L, int prec, const void* X, void* Y, int k, int64_t ld,
                                     hipStream_t s);
 

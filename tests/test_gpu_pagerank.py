@@ -98,6 +98,68 @@ def test_personalized_start_and_limits(P):
     assert np.max(np.abs(p4 - v)) < 1e-16
 
 
+def _pr_k(P, G, n, k, prec, V=None, start=None, **kw):
+    """k personalized PageRanks at once (node-major n x k)."""
+    dt = torch.float64 if prec == P.BVMV_F64 else torch.float32
+    nd = np.float64 if dt == torch.float64 else np.float32
+    p = torch.empty(n * k, dtype=dt, device=DEV)
+    tv = torch.from_numpy(np.ascontiguousarray(V, dtype=nd).reshape(-1)).to(DEV) if V is not None else None
+    sv = torch.from_numpy(np.ascontiguousarray(start, dtype=nd).reshape(-1)).to(DEV) if start is not None else None
+    res = P.bvmv_pagerank(G, p, teleport=tv, start=sv, prec=prec, k=k, **kw)
+    torch.cuda.synchronize()
+    return p.cpu().numpy().astype(np.float64).reshape(n, k), res
+
+
+@pytest.mark.parametrize("prec_name,tol", [("f64", 1e-12), ("f32c", 1e-5)])
+def test_batched_personalized(P, prec_name, tol):
+    """k teleport sets in one launch sequence: each column is the oracle's
+    personalized PageRank (iteration-matched), columns stop independently."""
+    prec = P.PREC_NAMES[prec_name]
+    g = B.web_graph(30_000, 15.0, 81)
+    G = P.bvmv_load(B.encode(g).data)
+    k = 6
+    V = B.teleport_sets(g.n, k, 16, seed=7).astype(np.float64)
+    p, res = _pr_k(P, G, g.n, k, prec, V)
+    assert len(res) == k
+    iters = set()
+    for c in range(k):
+        it, ok, r = res[c]
+        assert ok and r < 1e-6
+        _, t_or, _, ok_or = pagerank.pagerank(g.rowptr, g.col, 0.85, teleport=V[:, c], tol=1e-6)
+        assert ok_or and abs(it - t_or) <= 1
+        p_ref = pagerank.pagerank(g.rowptr, g.col, 0.85, teleport=V[:, c], iters=it)[0]
+        assert np.max(np.abs(p[:, c] - p_ref)) < tol * np.max(p_ref), c
+        assert abs(p[:, c].sum() - 1.0) < (1e-12 if prec == P.BVMV_F64 else 1e-5)
+        iters.add(it)
+    # deterministic
+    p2, res2 = _pr_k(P, G, g.n, k, prec, V)
+    assert np.array_equal(p, p2) and res == res2
+
+
+def test_batched_uniform_and_limits(P):
+    """Uniform teleport in every column equals the single-vector run; an
+    iteration limit stops every column at max_iter with NOT_CONVERGED."""
+    g = B.web_graph(20_000, 12.0, 82)
+    G = P.bvmv_load(B.encode(g).data)
+    k = 3
+    p, res = _pr_k(P, G, g.n, k, P.BVMV_F64)
+    p1, ((it1, ok1, r1),) = _pr(P, G, g.n, P.BVMV_F64)
+    for c in range(k):
+        assert abs(res[c][0] - it1) <= 1 and res[c][1]
+        ref = pagerank.pagerank(g.rowptr, g.col, 0.85, iters=res[c][0])[0]
+        assert np.max(np.abs(p[:, c] - ref)) < 1e-12 * np.max(ref)
+    V = B.teleport_sets(g.n, k, 16, seed=9).astype(np.float64)
+    p3, res3 = _pr_k(P, G, g.n, k, P.BVMV_F64, V, max_iter=4)
+    for c in range(k):
+        assert res3[c][0] == 4 and not res3[c][1]
+        ref = pagerank.pagerank(g.rowptr, g.col, 0.85, teleport=V[:, c], iters=4)[0]
+        assert np.max(np.abs(p3[:, c] - ref)) < 1e-15
+    # warm start from the converged columns: done almost at once
+    p4, _ = _pr_k(P, G, g.n, k, P.BVMV_F64, V)
+    p5, res5 = _pr_k(P, G, g.n, k, P.BVMV_F64, V, start=p4)
+    assert all(r[0] <= 2 and r[1] for r in res5)
+
+
 def test_edgeless_and_determinism(P):
     G = P.bvmv_load(B.encode(B.empty_graph(500)).data)
     p, ((it, ok, r),) = _pr(P, G, 500, P.BVMV_F32_COMP)
