@@ -77,6 +77,60 @@ def cpu_baseline(g, x64, budget_s):
                       % (reps, g.m)}
 
 
+def bench_batch(args, B, P, np, torch, dev):
+    """K personalized PageRanks (teleport sets of 16 random seeds, seed 104):
+    one batched launch sequence against K single-vector runs, plus the
+    K-vector product against K single products."""
+    K = args.batch
+    wl = args.workload if args.workload != "web-n2p20-d20" else "web-n8e6-d25"
+    t0 = time.perf_counter()
+    g = B.workload_graph(wl)
+    enc = B.encode(g)
+    log("graph %s n=%d m=%d (%.1fs)" % (wl, g.n, g.m, time.perf_counter() - t0))
+    G = P.bvmv_load(enc.data, tile_rows=args.tile_rows, window_cap=args.window_cap, stage_bytes=args.stage_bytes,
+                    interval_mode=args.interval_mode)
+    info = G.info()
+    del enc
+    prec = P.BVMV_F32_COMP
+    V = torch.from_numpy(B.teleport_sets(g.n, K, 16, seed=104).reshape(-1)).to(dev)
+    X = torch.from_numpy(np.random.default_rng(105).random((g.n, K), dtype=np.float32)).to(dev)
+    Y = torch.empty_like(X)
+    ms_batch = time_launches(lambda: P.bvmv_multiply_batch(G, X, Y, prec), max(args.steps // 10, 5),
+                             max(args.warmup // 10, 2), torch)
+    x1 = X[:, 0].contiguous()
+    y1 = torch.empty_like(x1)
+    ms_one = time_launches(lambda: P.bvmv_multiply(G, x1, y1, prec), args.steps, args.warmup, torch)
+    log("product: %d-vector %.3f ms, single %.4f ms" % (K, ms_batch, ms_one))
+    p = torch.empty(g.n * K, dtype=torch.float32, device=dev)
+    P.bvmv_pagerank(G, p, teleport=V, prec=prec, k=K)  # warm (capture)
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    res = P.bvmv_pagerank(G, p, teleport=V, prec=prec, k=K)
+    torch.cuda.synchronize()
+    s_batch = time.perf_counter() - t
+    Vc = V.view(g.n, K)
+    p1 = torch.empty(g.n, dtype=torch.float32, device=dev)
+    cols = [Vc[:, c].contiguous() for c in range(K)]
+    P.bvmv_pagerank(G, p1, teleport=cols[0], prec=prec)
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    it_single = []
+    for c in range(K):
+        (it, ok, r), = P.bvmv_pagerank(G, p1, teleport=cols[c], prec=prec)
+        it_single.append(it)
+    torch.cuda.synchronize()
+    s_single = time.perf_counter() - t
+    log("pagerank: batched %.3f s, %d single runs %.3f s" % (s_batch, K, s_single))
+    out = {"mode": "batched-personalized-pagerank", "workload": wl, "n": g.n, "m": g.m, "k": K,
+           "layout_bytes": info["layout_bytes"], "dtype": "f32",
+           "product_ms": {"batched": ms_batch, "single": ms_one, "speedup_vs_k_singles": K * ms_one / ms_batch,
+                          "edges_per_s_batched": K * g.m / (ms_batch * 1e-3)},
+           "pagerank_s": {"batched": s_batch, "k_single_runs": s_single, "speedup": s_single / s_batch},
+           "iterations": {"batched": [r[0] for r in res], "single": it_single},
+           "converged": all(r[1] for r in res)}
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -92,6 +146,9 @@ def main():
     ap.add_argument("--window-cap", type=int, default=0)
     ap.add_argument("--stage-bytes", type=int, default=0)
     ap.add_argument("--interval-mode", type=int, default=0)
+    ap.add_argument("--batch", type=int, default=0, metavar="K",
+                    help="batched personalized PageRank with K teleport sets of 16 seeds (workload "
+                         "web-n8e6-d25 unless --workload is given) instead of the single-vector metric")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="only run torch copies of MIB MiB (the calibration kernel for HBM byte counters)")
     args = ap.parse_args()
@@ -119,6 +176,9 @@ def main():
 
     import bvinputs as B
     import paper_1708_07271_amd as P
+
+    if args.batch:
+        return bench_batch(args, B, P, np, torch, dev)
     t0 = time.perf_counter()
     g = B.workload_graph(args.workload)
     enc = B.encode(g)

@@ -1187,26 +1187,55 @@ __global__ void __launch_bounds__(kThreads) bv_batch_kernel(DevLayout L, const t
       const uint32_t inf = s_info[r];
       if (inf & kInfoLong) continue;
       PAcc a = M::pzero();
-      for (uint32_t e = s_o16[r], en = s_o16[r] + s_ns[r]; e < en; ++e) {
-        const uint32_t w = s16[e];
-        const uint32_t f = w & kS16Off;
-        if (f & 1) {
-          // an interval pair +P[b] - P[a]: the sum of X over columns [a, b) of the window
-          const uint32_t f2 = s16[++e] & kS16Off;
-          PAcc t = M::pzero();
-          if (act)
-            for (int64_t cl = win0 + (f2 >> 1), c1 = win0 + (f >> 1); cl < c1; ++cl) M::padd(t, Xc[cl * ld]);
-          a = M::pcomb(a, (w & kS16Neg) ? -t : t);
-        } else {
-          const Xt v = act ? Xc[(win0 + int64_t(f >> 1) - 1) * ld] : Xt(0);
-          M::padd(a, (w & kS16Neg) ? -v : v);
+      // the row's columns in stream order, intervals expanded: 8 at a time
+      // are decoded (a single is a run of length 1), then their X values
+      // are loaded together, then added in order
+      uint32_t e = s_o16[r];
+      const uint32_t en = e + s_ns[r];
+      int64_t ia = 0, ib = 0;  // pending run of columns [ia, ib)
+      bool ineg = false;
+      while (ia < ib || e < en) {
+        int64_t col[8];
+        bool neg[8], ok[8];
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+          if (ia >= ib && e < en) {
+            const uint32_t w = s16[e++];
+            const uint32_t f = w & kS16Off;
+            ineg = w & kS16Neg;
+            if (f & 1) {  // an interval pair +P[b] - P[a]: columns [a, b) of the window
+              const uint32_t f2 = s16[e++] & kS16Off;
+              ia = win0 + (f2 >> 1);
+              ib = win0 + (f >> 1);
+            } else {
+              ia = win0 + int64_t(f >> 1) - 1;
+              ib = ia + 1;
+            }
+          }
+          ok[j] = ia < ib;
+          col[j] = ok[j] ? ia : win0;
+          neg[j] = ineg;
+          if (ok[j]) ++ia;
         }
+        Xt v[8];
+#pragma unroll
+        for (int j = 0; j < 8; ++j) v[j] = (act && ok[j]) ? Xc[col[j] * ld] : Xt(0);
+#pragma unroll
+        for (int j = 0; j < 8; ++j) M::padd(a, neg[j] ? -v[j] : v[j]);
       }
-      for (uint32_t e = s_ow[r], en = s_ow[r] + (inf >> 13); e < en; ++e) {
-        const uint32_t w = w32[e];
-        const int64_t col = win0 + int64_t(w & kWideOff) - int64_t(kWideBias);
-        const Xt v = act ? Xc[col * ld] : Xt(0);
-        M::padd(a, (w & kWideNeg) ? -v : v);
+      for (uint32_t e2 = s_ow[r], en2 = s_ow[r] + (inf >> 13); e2 < en2; e2 += 8) {
+        Xt v[8];
+        bool neg[8];
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+          const bool okj = e2 + j < en2;
+          const uint32_t w = okj ? w32[e2 + j] : 0u;
+          const int64_t colj = win0 + int64_t(w & kWideOff) - int64_t(kWideBias);
+          neg[j] = w & kWideNeg;
+          v[j] = (act && okj) ? Xc[colj * ld] : Xt(0);
+        }
+#pragma unroll
+        for (int j = 0; j < 8; ++j) M::padd(a, neg[j] ? -v[j] : v[j]);
       }
       s_acc[r * G + lane] = M::chain(a);
     }
