@@ -103,18 +103,23 @@ def parse_header(data):
     return hdr, data[off:]
 
 
-def decode(data):
+def decode(data, with_stats=False):
     """Decode a bitstream into (rowptr uint64, col uint32, refs uint8, header).
 
     refs[i] = g_i = i - r_i (0 = no reference).  Raises FormatError on any
     inconsistency (ids out of range, unsorted or duplicate ids, a reference
-    outside the window or deeper than R, counts that do not add up)."""
+    outside the window or deeper than R, counts that do not add up).
+
+    With `with_stats`, also returns an (n, 5) int64 array of how each row is
+    coded: reference-chain depth, reference entries skipped, intervals,
+    their total length, residuals."""
     hdr, body = parse_header(data)
     n, W, R, Lmin, zk = hdr["n"], hdr["W"], hdr["R"], hdr["Lmin"], hdr["zeta_k"]
     br = BitReader(body, hdr["body_bits"])
     lists: list[list[int]] = []
     refs = np.zeros(n, dtype=np.uint8)
     depth = [0] * n
+    stats = np.zeros((n, 5), dtype=np.int64)
     for i in range(n):
         d = br.gamma()
         if d == 0:
@@ -146,6 +151,8 @@ def decode(data):
             if keep:                      # b even: the rest is copied
                 copied.extend(ref[pos:])
             refs[i] = g
+            stats[i, 0] = depth[i]
+            stats[i, 1] = len(ref) - len(copied)
         ne = d - len(copied)
         if ne < 0:
             raise FormatError("more copied entries than the degree at node %d" % i)
@@ -164,6 +171,7 @@ def decode(data):
             nres = ne - len(extras)
             if nres < 0:
                 raise FormatError("intervals exceed the degree at node %d" % i)
+            stats[i, 2:5] = (nint, len(extras), nres)
             res = []
             prev = None
             for k in range(nres):
@@ -187,4 +195,6 @@ def decode(data):
     rowptr = np.zeros(n + 1, dtype=np.uint64)
     rowptr[1:] = np.cumsum([len(r) for r in lists])
     col = np.fromiter((j for r in lists for j in r), dtype=np.uint32, count=m)
+    if with_stats:
+        return rowptr, col, refs, hdr, stats
     return rowptr, col, refs, hdr

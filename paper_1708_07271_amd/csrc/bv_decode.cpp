@@ -89,6 +89,7 @@ struct SegOut {
   std::vector<uint32_t> col;      // lists of rows [lo, hi)
   std::vector<uint64_t> len;      // per row
   std::vector<uint8_t> refs;
+  std::vector<RowStats> stats;
   uint64_t end_pos = 0;
   std::string err;
 };
@@ -101,6 +102,7 @@ void decode_range(const StreamHeader& h, const uint8_t* padded, uint64_t lo, uin
   const uint64_t nrow = hi - lo;
   std::vector<uint64_t> start(nrow), len(nrow, 0);
   std::vector<uint8_t> depth(nrow, 0), refs(nrow, 0);
+  std::vector<RowStats> stats(nrow, RowStats{0, 0, 0, 0, 0});
   std::vector<uint32_t> col;
   col.reserve(size_t(nrow * 24));
   std::vector<uint32_t> copied, extras;
@@ -141,6 +143,8 @@ void decode_range(const StreamHeader& h, const uint8_t* padded, uint64_t lo, uin
       if (!in.ok()) { fail("truncated stream", i); return; }
       if (keep) copied.insert(copied.end(), rl + p, rl + rlen);
       refs[li] = uint8_t(g);
+      stats[li].depth = depth[li];
+      stats[li].skipped = uint32_t(rlen - copied.size());
     }
     if (copied.size() > d) { fail("more copied entries than the degree", i); return; }
     const uint64_t ne = d - copied.size();
@@ -162,6 +166,9 @@ void decode_range(const StreamHeader& h, const uint8_t* padded, uint64_t lo, uin
       }
       const uint64_t nres = ne - extras.size();
       const size_t int_end = extras.size();
+      stats[li].nint = uint32_t(nint);
+      stats[li].intlen = uint32_t(int_end);
+      stats[li].nres = uint32_t(nres);
       int64_t prev = 0;
       for (uint64_t k = 0; k < nres; ++k) {
         int64_t j = k == 0 ? int64_t(i) + nu_inv(in.zeta(h.zeta_k)) : prev + 1 + int64_t(in.zeta(h.zeta_k));
@@ -183,6 +190,7 @@ void decode_range(const StreamHeader& h, const uint8_t* padded, uint64_t lo, uin
   out.col.swap(col);
   out.len.swap(len);
   out.refs.swap(refs);
+  out.stats.swap(stats);
 }
 
 }  // namespace
@@ -266,6 +274,7 @@ int decode_stream(const uint8_t* data, size_t nbytes, int nthreads, DecodedGraph
   out.n = int64_t(n);
   out.rowptr.assign(n + 1, 0);
   out.refs.resize(n);
+  out.stats.resize(n);
   uint64_t m = 0, row = 0;
   for (auto& o : outs) m += o.col.size();
   if (m != h.m) { err = "edge count differs from the header"; return -2; }
@@ -275,6 +284,7 @@ int decode_stream(const uint8_t* data, size_t nbytes, int nthreads, DecodedGraph
     std::memcpy(out.col.data() + pos, o.col.data(), o.col.size() * 4);
     for (size_t k = 0; k < o.len.size(); ++k) {
       out.refs[row] = o.refs[k];
+      out.stats[row] = o.stats[k];
       out.rowptr[row + 1] = out.rowptr[row] + o.len[k];
       ++row;
     }

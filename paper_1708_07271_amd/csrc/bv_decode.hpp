@@ -19,11 +19,19 @@ struct StreamHeader {
   size_t body_bytes = 0;
 };
 
+// How a row is coded in the stream (counts read while decoding it): the depth
+// of its reference chain, the reference entries it skips, its intervals and
+// their total length, and its residuals.
+struct RowStats {
+  uint32_t depth, skipped, nint, intlen, nres;
+};
+
 struct DecodedGraph {
   int64_t n = 0, m = 0;
   std::vector<uint64_t> rowptr;  // n+1
   std::vector<uint32_t> col;     // m
   std::vector<uint8_t> refs;     // n, g_i (0 = none)
+  std::vector<RowStats> stats;   // n
   StreamHeader hdr;
 };
 

@@ -248,3 +248,92 @@ def test_pagerank_mass_conserved():
     for it in (1, 5, 30):
         p = pagerank.pagerank(g.rowptr, g.col, 0.85, iters=it)[0]
         assert abs(p.sum() - 1.0) < 1e-12
+
+
+# ------------------------------------------------------------ warm-start oracle
+from oracle import features as feat  # noqa: E402
+from oracle import mlp  # noqa: E402
+
+
+def test_bf16_rounding_values():
+    # exact values stay; halfway cases go to the even neighbour; above half rounds up
+    cases = [(1.0, 1.0), (-2.5, -2.5), (0.0, 0.0),
+             (1 + 2 ** -8, 1.0),                       # halfway between 1 and 1 + 2^-7 (odd): to 1
+             (1 + 3 * 2 ** -8, 1 + 2 ** -6),           # halfway between 1 + 2^-7 (odd) and 1 + 2^-6: up
+             (1 + 2 ** -8 + 2 ** -20, 1 + 2 ** -7),    # above half: up
+             (1 + 2 ** -8 - 2 ** -20, 1.0),            # below half: down
+             (3.0 * 2 ** 100, 3.0 * 2 ** 100), (0.1, 0.10009765625)]
+    for a, want in cases:
+        assert mlp.bf16(np.array([a]))[0] == want, a
+
+
+def test_gelu_identities():
+    z = np.linspace(-6, 6, 49)
+    assert mlp.gelu(np.array([0.0]))[0] == 0.0
+    assert np.max(np.abs(mlp.gelu(z) - mlp.gelu(-z) - z)) < 1e-14       # z Phi(z) + z Phi(-z) = z
+    assert abs(mlp.gelu(np.array([1.0]))[0] - 0.8413447460685429) < 1e-15  # Phi(1) = 0.84134474606854...
+    h = 1e-6
+    fd = (mlp.gelu(z + h) - mlp.gelu(z - h)) / (2 * h)
+    assert np.max(np.abs(fd - mlp.gelu_grad(z))) < 1e-8
+
+
+def test_mlp_gradient_finite_differences():
+    rng = np.random.default_rng(5)
+    theta = mlp.init_params(3) + rng.normal(0, 0.05, mlp.NPARAM)   # nonzero biases too
+    X = rng.normal(0, 1, (7, mlp.NIN))
+    t = rng.normal(0, 1, 7)
+    L, g = mlp.grad(theta, X, t, quantize=False)
+    assert abs(L - mlp.loss(theta, X, t, quantize=False)) < 1e-15
+    idx = np.concatenate([rng.choice(768, 40, replace=False), 768 + np.arange(64)[::7],
+                          832 + rng.choice(4096, 60, replace=False), 4928 + np.arange(64)[::5],
+                          4992 + np.arange(64)[::3], [5056]])
+    h = 1e-6
+    for i in idx:
+        e = np.zeros(mlp.NPARAM)
+        e[i] = h
+        fd = (mlp.loss(theta + e, X, t, False) - mlp.loss(theta - e, X, t, False)) / (2 * h)
+        assert abs(fd - g[i]) < 1e-7 * max(1.0, abs(g[i])), i
+
+
+def test_mlp_quantized_close_to_exact():
+    rng = np.random.default_rng(6)
+    theta = mlp.init_params(4)
+    X = rng.normal(0, 1, (50, mlp.NIN))
+    t = rng.normal(0, 1, 50)
+    s_q, _ = mlp.forward(theta, X, True)
+    s_e, _ = mlp.forward(mlp.pack(mlp.weights_bf16(theta)), X, False)
+    assert np.max(np.abs(s_q - s_e)) < 0.05 * max(1.0, np.max(np.abs(s_e)))
+    _, gq = mlp.grad(theta, X, t, True)
+    _, ge = mlp.grad(mlp.pack(mlp.weights_bf16(theta)), X, t, False)
+    assert np.linalg.norm(gq - ge) < 0.05 * np.linalg.norm(ge)
+
+
+def test_adam_first_step_closed_form():
+    # after one step mhat = g and vhat = g^2, so theta moves by lr g / (|g| + eps)
+    g = np.array([0.3, -2.0, 1e-3, 0.0])
+    th0 = np.array([1.0, 2.0, 3.0, 4.0])
+    opt = mlp.Adam(4, lr=0.01)
+    th1 = opt.step(th0, g)
+    assert np.allclose(th1, th0 - 0.01 * g / (np.abs(g) + 1e-8), rtol=0, atol=1e-15)
+
+
+def test_row_stats_match_lists():
+    g = B.web_graph(3000, 12.0, 21)
+    enc = B.encode(g)
+    rowptr, col, refs, hdr, st = bvdecode.decode(enc.data, with_stats=True)
+    want = feat.row_stats_from_lists(rowptr, col, refs, hdr["Lmin"])
+    assert np.array_equal(st, want)
+    assert st[:, 0].max() <= hdr["R"] and st[:, 2].sum() > 0 and st[:, 1].sum() > 0
+
+
+def test_features_closed_forms_star():
+    # loaded rows: row 0 lists every other node (all of them link to 0); other rows empty
+    n = 40
+    g = B.from_lists([list(range(1, n))] + [[] for _ in range(n - 1)])
+    rowptr, col, refs, hdr, st = bvdecode.decode(B.encode(g).data, with_stats=True)
+    F = feat.features(rowptr, col, st, hdr["R"])
+    assert np.allclose(F[0, :4], [math.log1p(n - 1), 0.0, 0.0, 1.0])
+    assert np.allclose(F[1:, :4], [0.0, math.log(2.0), 0.0, 0.0])
+    assert np.allclose(F[0, 4:8], [0.0, math.log(2.0), math.log1p(n - 1), 0.0])   # one interval 1..n-1
+    assert np.allclose(F[0, 8:11], [math.log(2.0), 0.0, math.log1p(n * (n - 1))])
+    assert np.allclose(F[1:, 4:11], 0.0) and np.allclose(F[:, 11], math.log(n))
