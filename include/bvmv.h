@@ -104,12 +104,17 @@ typedef struct {
   int prec;         /* BVMV_F32_COMP (default), BVMV_F32 or BVMV_F64 */
   int chunk;        /* iterations per captured HIP graph replay (0 = default 16) */
   int exact_zero_damping;  /* 1 = use damping exactly as given, even 0 */
+  int fallback_check;      /* 1 (k = 1, single graph, start given): run one iteration from
+                              `start` and one from the teleport vector, and keep `start` only
+                              if its residual is the smaller; the probes are not counted */
 } bvmv_pr_opts;
 
 typedef struct {
   int iters;          /* iterations run (the t at which the stopping test held) */
   int converged;      /* 1 if residual < tol */
   double residual;    /* ||p_t - p_{t-1}||_1 of the last iteration */
+  int used_start;     /* 1: started from `start`; 0: from the teleport vector (no start, or
+                         the fallback check rejected it) */
 } bvmv_pr_result;
 
 /* PageRank by the power method, Eq. (1), on the loaded rows read as IN-LINK
@@ -192,6 +197,48 @@ void bvmv_csr_free(bvmv_csr* c);
  * inconsistent. */
 int bvmv_layout_selfcheck(const void* bitstream, size_t nbytes, const bvmv_load_opts* opts, const double* x,
                           double* y, int64_t* stats);
+
+/* ---------------------------------------------------------------------------
+ * Learned PageRank warm start (not in the paper; the paper's PageRank starts
+ * from the uniform vector, Section "Experimental Evaluation").  A small MLP
+ * predicts s_v ~ log(n p*_v) from 12 structural features of node v; the start
+ * vector is p0 proportional to exp(s).  By the L1 contraction of Eq. (1) the
+ * fixed point does not depend on the start, so a warm start only changes the
+ * number of iterations.
+ * ------------------------------------------------------------------------- */
+#define BVMV_NFEAT 12        /* features per node */
+#define BVMV_MLP_PARAMS 5057 /* W1 (64x12), b1 (64), W2 (64x64), b2 (64), w3 (64), b3 (1), row-major (out, in) */
+typedef struct bvmv_mlp bvmv_mlp;
+
+/* Features of every node into F (device, n x 12 node-major FP32), rows read as
+ * in-link lists: log1p(in-degree), log1p(out-degree d), reference-chain depth
+ * / R, [d = 0], log1p of the row's skipped reference entries, intervals,
+ * interval length and residuals in the stream, log1p of the mean out-degree
+ * and of the mean in-degree of the in-neighbours, log1p(n sum over
+ * in-neighbours u of 1/d_u), log n.  Uses the degree pass and three products. */
+int bvmv_features(bvmv_graph* g, float* F, void* stream);
+
+/* A network on `device` with the given FP32 master parameters (HOST array of
+ * BVMV_MLP_PARAMS); weights are used as BF16 copies, biases as FP32; Adam
+ * state zero.  Synchronous. */
+int bvmv_mlp_create(int device, const float* params, bvmv_mlp** out);
+/* HOST copy of the FP32 master parameters.  Synchronous. */
+int bvmv_mlp_params(const bvmv_mlp* m, float* params);
+/* s = network(F) for n rows: F device n x 12, s device n floats.  GEMM
+ * operands BF16 (round to nearest even), FP32 accumulation; biases, GELU and
+ * the output layer FP32. */
+int bvmv_mlp_forward(bvmv_mlp* m, const float* F, int64_t n, float* s, void* stream);
+/* Gradient of the mean squared error (1/n) sum (s_i - target_i)^2 over n <= 2^20
+ * rows: grad device, BVMV_MLP_PARAMS + 1 floats (the gradient, then the loss). */
+int bvmv_mlp_gradient(bvmv_mlp* m, const float* F, const float* target, int64_t n, float* grad, void* stream);
+/* One training step: the gradient on (F, target), then Adam (b1 = 0.9,
+ * b2 = 0.999, eps = 1e-8) with learning rate lr.  loss: device float or NULL. */
+int bvmv_mlp_train_step(bvmv_mlp* m, const float* F, const float* target, int64_t n, float lr, float* loss,
+                        void* stream);
+/* Warm start of g: features, the network, p0 = exp(s - max s) / sum into p0
+ * (device, n elements of the prec's type: double for BVMV_F64, float else). */
+int bvmv_warm_start(bvmv_graph* g, bvmv_mlp* m, int prec, void* p0, void* stream);
+void bvmv_mlp_free(bvmv_mlp* m);
 
 void bvmv_free(bvmv_graph* g);
 const char* bvmv_last_error(void);

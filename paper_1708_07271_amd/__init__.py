@@ -39,11 +39,17 @@ class LoadOpts(ctypes.Structure):
 
 class PROpts(ctypes.Structure):
     _fields_ = [("damping", ctypes.c_double), ("tol", ctypes.c_double), ("max_iter", ctypes.c_int),
-                ("prec", ctypes.c_int), ("chunk", ctypes.c_int), ("exact_zero_damping", ctypes.c_int)]
+                ("prec", ctypes.c_int), ("chunk", ctypes.c_int), ("exact_zero_damping", ctypes.c_int),
+                ("fallback_check", ctypes.c_int)]
 
 
 class PRResult(ctypes.Structure):
-    _fields_ = [("iters", ctypes.c_int), ("converged", ctypes.c_int), ("residual", ctypes.c_double)]
+    _fields_ = [("iters", ctypes.c_int), ("converged", ctypes.c_int), ("residual", ctypes.c_double),
+                ("used_start", ctypes.c_int)]
+
+
+NFEAT = 12
+MLP_PARAMS = 5057
 
 
 class Info(ctypes.Structure):
@@ -89,6 +95,14 @@ def load_library():
         "bvmv_csr_free": ([vp], None),
         "bvmv_free": ([vp], None),
         "bvmv_layout_selfcheck": ([vp, sz, P(LoadOpts), vp, vp, vp], i32),
+        "bvmv_features": ([vp, vp, vp], i32),
+        "bvmv_mlp_create": ([i32, vp, P(vp)], i32),
+        "bvmv_mlp_params": ([vp, vp], i32),
+        "bvmv_mlp_forward": ([vp, vp, i64, vp, vp], i32),
+        "bvmv_mlp_gradient": ([vp, vp, vp, i64, vp, vp], i32),
+        "bvmv_mlp_train_step": ([vp, vp, vp, i64, ctypes.c_float, vp, vp], i32),
+        "bvmv_warm_start": ([vp, vp, i32, vp, vp], i32),
+        "bvmv_mlp_free": ([vp], None),
         "bvmv_last_error": ([], ctypes.c_char_p),
         "bvmv_version": ([], ctypes.c_char_p),
     }
@@ -209,13 +223,14 @@ def bvmv_multiply_batch(g: Graph, X, Y, prec=BVMV_F32_COMP, stream=None):
                                               _stream_ptr(stream)))
 
 
-def _pr_opts(damping, tol, max_iter, prec, chunk):
-    return PROpts(damping, tol, max_iter, _prec(prec), chunk, 1 if damping == 0.0 else 0)
+def _pr_opts(damping, tol, max_iter, prec, chunk, fallback_check=0):
+    return PROpts(damping, tol, max_iter, _prec(prec), chunk, 1 if damping == 0.0 else 0, int(fallback_check))
 
 
-def bvmv_pagerank(g: Graph, p_out, teleport=None, start=None, damping=0.85, tol=1e-6, max_iter=1000,
-                  prec=BVMV_F32_COMP, chunk=16, k=1, stream=None):
-    """Returns a list of (iters, converged, residual), one per column (or member of a group)."""
+def bvmv_pagerank_detail(g: Graph, p_out, teleport=None, start=None, damping=0.85, tol=1e-6, max_iter=1000,
+                         prec=BVMV_F32_COMP, chunk=16, k=1, fallback_check=0, stream=None):
+    """Returns a list of dicts (iters, converged, residual, used_start), one per
+    column (or member of a group)."""
     p = _prec(prec)
     dt = _vec_dtype(p)
     lib = load_library()
@@ -223,12 +238,20 @@ def bvmv_pagerank(g: Graph, p_out, teleport=None, start=None, damping=0.85, tol=
     if g.members is not None:
         nres = len(g.members)
     res = (PRResult * max(nres, 1))()
-    o = _pr_opts(damping, tol, max_iter, p, chunk)
+    o = _pr_opts(damping, tol, max_iter, p, chunk, fallback_check)
     tp = _dev_ptr(teleport, dt, g.n * k) if teleport is not None else ctypes.c_void_p(None)
     sp = _dev_ptr(start, dt, g.n * k) if start is not None else ctypes.c_void_p(None)
     _check(lib.bvmv_pagerank(g.handle, ctypes.byref(o), tp, sp, _dev_ptr(p_out, dt, g.n * k), k, res,
                              _stream_ptr(stream)), allow=(BVMV_OK, BVMV_NOT_CONVERGED))
-    return [(r.iters, bool(r.converged), r.residual) for r in res[:nres]]
+    return [dict(iters=r.iters, converged=bool(r.converged), residual=r.residual, used_start=r.used_start)
+            for r in res[:nres]]
+
+
+def bvmv_pagerank(g: Graph, p_out, teleport=None, start=None, damping=0.85, tol=1e-6, max_iter=1000,
+                  prec=BVMV_F32_COMP, chunk=16, k=1, stream=None):
+    """Returns a list of (iters, converged, residual), one per column (or member of a group)."""
+    out = bvmv_pagerank_detail(g, p_out, teleport, start, damping, tol, max_iter, prec, chunk, k, 0, stream)
+    return [(r["iters"], r["converged"], r["residual"]) for r in out]
 
 
 def bvmv_group(graphs) -> Graph:
@@ -335,3 +358,73 @@ def bvmv_layout_selfcheck(bitstream, x, tile_rows=0, window_cap=0, stage_bytes=0
 
 def bvmv_version():
     return load_library().bvmv_version().decode()
+
+
+# ------------------------------------------------------------ learned warm start
+class Mlp:
+    """Handle of a warm-start network (FP32 master parameters, BF16 weight
+    copies and Adam state on the device)."""
+
+    def __init__(self, handle):
+        self._h = ctypes.c_void_p(handle)
+
+    @property
+    def handle(self):
+        return self._h
+
+    def __del__(self):
+        if getattr(self, "_h", None) and self._h.value and _lib is not None:
+            _lib.bvmv_mlp_free(self._h)
+            self._h = ctypes.c_void_p(None)
+
+
+def bvmv_features(g: Graph, F, stream=None):
+    """F: (n, 12) float32 device tensor."""
+    import torch
+    _check(load_library().bvmv_features(g.handle, _dev_ptr(F, torch.float32, g.n * NFEAT), _stream_ptr(stream)))
+
+
+def bvmv_mlp_create(params, device=0) -> Mlp:
+    params = np.ascontiguousarray(params, dtype=np.float32)
+    if params.size != MLP_PARAMS:
+        raise ValueError("expected %d parameters" % MLP_PARAMS)
+    h = ctypes.c_void_p()
+    _check(load_library().bvmv_mlp_create(device, params.ctypes.data, ctypes.byref(h)))
+    return Mlp(h.value)
+
+
+def bvmv_mlp_params(m: Mlp):
+    out = np.zeros(MLP_PARAMS, dtype=np.float32)
+    _check(load_library().bvmv_mlp_params(m.handle, out.ctypes.data))
+    return out
+
+
+def bvmv_mlp_forward(m: Mlp, F, s, stream=None):
+    import torch
+    n = s.numel()
+    _check(load_library().bvmv_mlp_forward(m.handle, _dev_ptr(F, torch.float32, n * NFEAT),
+                                           n, _dev_ptr(s, torch.float32, n), _stream_ptr(stream)))
+
+
+def bvmv_mlp_gradient(m: Mlp, F, target, grad, stream=None):
+    """grad: float32 device tensor of MLP_PARAMS + 1 (the gradient, then the loss)."""
+    import torch
+    n = target.numel()
+    _check(load_library().bvmv_mlp_gradient(m.handle, _dev_ptr(F, torch.float32, n * NFEAT),
+                                            _dev_ptr(target, torch.float32, n), n,
+                                            _dev_ptr(grad, torch.float32, MLP_PARAMS + 1), _stream_ptr(stream)))
+
+
+def bvmv_mlp_train_step(m: Mlp, F, target, lr, loss=None, stream=None):
+    import torch
+    n = target.numel()
+    lp = _dev_ptr(loss, torch.float32, 1) if loss is not None else ctypes.c_void_p(None)
+    _check(load_library().bvmv_mlp_train_step(m.handle, _dev_ptr(F, torch.float32, n * NFEAT),
+                                              _dev_ptr(target, torch.float32, n), n, float(lr), lp,
+                                              _stream_ptr(stream)))
+
+
+def bvmv_warm_start(g: Graph, m: Mlp, p0, prec=BVMV_F32_COMP, stream=None):
+    p = _prec(prec)
+    _check(load_library().bvmv_warm_start(g.handle, m.handle, p, _dev_ptr(p0, _vec_dtype(p), g.n),
+                                          _stream_ptr(stream)))

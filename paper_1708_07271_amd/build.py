@@ -15,7 +15,7 @@ CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "libbvmv.so")
 BUILD = os.path.join(ROOT, "_build")
 
-SOURCES = ["bv_decode.cpp", "bv_layout.cpp", "bv_layout_check.cpp", "bvmv_api.cpp", "bv_kernels.hip"]
+SOURCES = ["bv_decode.cpp", "bv_layout.cpp", "bv_layout_check.cpp", "bvmv_api.cpp", "bv_kernels.hip", "mlp_kernels.hip"]
 ARCH = os.environ.get("BVMV_OFFLOAD_ARCH", "gfx950")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 

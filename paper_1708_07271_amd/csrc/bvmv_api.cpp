@@ -131,7 +131,7 @@ struct PRWork {
 
 struct PROptsResolved {
   double beta, tol;
-  int max_iter, prec, chunk;
+  int max_iter, prec, chunk, fallback;
 };
 
 int resolve_pr_opts(const bvmv_pr_opts* o, PROptsResolved& r) {
@@ -140,7 +140,9 @@ int resolve_pr_opts(const bvmv_pr_opts* o, PROptsResolved& r) {
   r.max_iter = 1000;
   r.prec = BVMV_F32_COMP;
   r.chunk = 16;
+  r.fallback = 0;
   if (o) {
+    r.fallback = o->fallback_check;
     if (o->damping != 0.0 || o->exact_zero_damping) r.beta = o->damping;
     if (o->tol != 0.0) r.tol = o->tol;
     if (o->max_iter) r.max_iter = o->max_iter;
@@ -177,6 +179,7 @@ struct bvmv_graph {
   uint8_t* d_data = nullptr;
   uint32_t* d_longs = nullptr;
   int32_t* d_outdeg = nullptr;
+  uint32_t* d_stats = nullptr;  // per-row coding statistics (5 u32), uploaded by bvmv_features
   DevLayout L;
   // group
   int ngraphs = 1;
@@ -195,6 +198,8 @@ struct bvmv_graph {
     dev_free(d_data);
     dev_free(d_longs);
     dev_free(d_outdeg);
+    dev_free(d_stats);
+    d_stats = nullptr;
     d_tiles = nullptr;
     d_info = nullptr;
     d_ns = nullptr;
@@ -277,33 +282,56 @@ int run_pagerank(PRWork& w, hipStream_t cap, const PROptsResolved& o, int64_t n_
   if (int rc = w.ensure(o.prec, n_elems, members, nslots)) return rc;
   if (!outdeg || !w.p[0] || !w.p[1] || !w.z[0] || !w.z[1] || !w.st || !w.slots || !w.h_st)
     return fail(BVMV_EINVAL, "PageRank working set is incomplete");
-  std::memcpy(w.h_st, states.data(), sizeof(PRState) * size_t(members));
-  HIP_TRY(hipMemcpyAsync(w.st, w.h_st, sizeof(PRState) * size_t(members), hipMemcpyHostToDevice, s));
-  HIP_TRY(init(start, tele, w.p[0], w.z[0], s));
+  // arguments of the iteration that reads buffer c % 2 and writes the other
+  auto args = [&](int c) {
+    PRArgs a{};
+    a.p_cur = w.p[c % 2];
+    a.p_new = w.p[(c + 1) % 2];
+    a.z_cur = w.z[c % 2];
+    a.z_new = w.z[(c + 1) % 2];
+    a.tele = tele;
+    a.outdeg = outdeg;
+    a.st = w.st;
+    a.slots = w.slots;
+    a.beta = o.beta;
+    a.tol = o.tol;
+    a.max_iter = o.max_iter;
+    a.buf = (c + 1) % 2;
+    a.members = members;
+    a.k = k;
+    return a;
+  };
+  auto reset = [&](const void* st0) -> int {
+    std::memcpy(w.h_st, states.data(), sizeof(PRState) * size_t(members));
+    HIP_TRY(hipMemcpyAsync(w.st, w.h_st, sizeof(PRState) * size_t(members), hipMemcpyHostToDevice, s));
+    HIP_TRY(init(st0, tele, w.p[0], w.z[0], s));
+    return BVMV_OK;
+  };
+  int used = start ? 1 : 0;
+  if (o.fallback && start && members == 1 && k == 1) {
+    // one eager iteration from each candidate start; keep `start` only if
+    // its first residual is the smaller
+    double r[2] = {0.0, 0.0};
+    for (int cand = 0; cand < 2; ++cand) {
+      if (int rc = reset(cand == 0 ? start : nullptr)) return rc;
+      HIP_TRY(iter(args(0), s));
+      HIP_TRY(hipMemcpyAsync(w.h_st, w.st, sizeof(PRState), hipMemcpyDeviceToHost, s));
+      HIP_TRY(hipStreamSynchronize(s));
+      r[cand] = w.h_st[0].resid;
+    }
+    if (!(r[0] < r[1])) {
+      start = nullptr;
+      used = 0;
+    }
+  }
+  if (int rc = reset(start)) return rc;
   const bool same = w.exec && w.key_tele == tele && w.key_beta == o.beta && w.key_tol == o.tol &&
                     w.key_max_iter == o.max_iter && w.key_chunk == o.chunk;
   if (!same) {
     w.drop_graph();
     HIP_TRY(hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal));
     hipError_t ce = hipSuccess;
-    for (int c = 0; c < o.chunk && ce == hipSuccess; ++c) {
-      PRArgs a{};
-      a.p_cur = w.p[c % 2];
-      a.p_new = w.p[(c + 1) % 2];
-      a.z_cur = w.z[c % 2];
-      a.z_new = w.z[(c + 1) % 2];
-      a.tele = tele;
-      a.outdeg = outdeg;
-      a.st = w.st;
-      a.slots = w.slots;
-      a.beta = o.beta;
-      a.tol = o.tol;
-      a.max_iter = o.max_iter;
-      a.buf = (c + 1) % 2;
-      a.members = members;
-      a.k = k;
-      ce = iter(a, cap);
-    }
+    for (int c = 0; c < o.chunk && ce == hipSuccess; ++c) ce = iter(args(c), cap);
     hipGraph_t gr = nullptr;
     hipError_t ee = hipStreamEndCapture(cap, &gr);
     if (ce != hipSuccess) {
@@ -336,6 +364,7 @@ int run_pagerank(PRWork& w, hipStream_t cap, const PROptsResolved& o, int64_t n_
       res[gI].iters = st.iter;
       res[gI].converged = st.converged;
       res[gI].residual = st.resid;
+      res[gI].used_start = used;
     }
     if (!st.converged) status = BVMV_NOT_CONVERGED;
   }
@@ -343,6 +372,28 @@ int run_pagerank(PRWork& w, hipStream_t cap, const PROptsResolved& o, int64_t n_
 }
 
 }  // namespace
+
+namespace {
+template <class T>
+struct DevBuf {  // device scratch freed on scope exit
+  T* p = nullptr;
+  hipError_t alloc(size_t count) { return hipMalloc(reinterpret_cast<void**>(&p), std::max<size_t>(count, 1) * sizeof(T)); }
+  ~DevBuf() { dev_free(p); }
+};
+}  // namespace
+
+// ------------------------------------------------------------ learned warm start
+struct bvmv_mlp {
+  int device = 0;
+  float* theta = nullptr;   // FP32 master parameters
+  uint16_t* wq = nullptr;   // BF16 weight copies
+  float* m = nullptr;       // Adam moments
+  float* v = nullptr;
+  float* grad = nullptr;    // gradient + loss
+  float* part = nullptr;    // per-tile gradient partials
+  int64_t part_rows = 0;
+  int step = 0;
+};
 
 extern "C" {
 
@@ -765,6 +816,149 @@ void bvmv_csr_free(bvmv_csr* c) {
     if (c->cap) (void)hipStreamDestroy(c->cap);
   }
   delete c;
+}
+
+
+
+int bvmv_features(bvmv_graph* g, float* F, void* stream) {
+  if (!g || !F) return fail(BVMV_EINVAL, "null argument");
+  if (g->ngraphs != 1) return fail(BVMV_EINVAL, "features need a single graph");
+  if (g->dec.stats.size() != size_t(g->n)) return fail(BVMV_EINVAL, "row statistics missing");
+  DeviceGuard dg(g->device);
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  const int64_t n = g->n;
+  if (!g->d_stats) {
+    static_assert(sizeof(RowStats) == 5 * sizeof(uint32_t), "row statistics layout");
+    if (dev_upload(&g->d_stats, reinterpret_cast<const uint32_t*>(g->dec.stats.data()), size_t(n) * 5))
+      return BVMV_ENOMEM;
+  }
+  DevBuf<int32_t> indeg;
+  DevBuf<float> xb, yb;
+  if (indeg.alloc(size_t(n)) || xb.alloc(3 * size_t(n)) || yb.alloc(3 * size_t(n)))
+    return fail(BVMV_ENOMEM, "feature scratch");
+  float* xd = xb.p;
+  float* xi = xb.p + n;
+  float* xv = xb.p + 2 * n;
+  float* yd = yb.p;
+  float* yi = yb.p + n;
+  float* yv = yb.p + 2 * n;
+  HIP_TRY(launch_bv_degrees(g->L, indeg.p, s));
+  HIP_TRY(launch_feature_inputs(n, indeg.p, g->d_outdeg, xd, xi, xv, s));
+  HIP_TRY(launch_bv_multiply(g->L, BVMV_F32_COMP, xd, yd, s));
+  HIP_TRY(launch_bv_multiply(g->L, BVMV_F32_COMP, xi, yi, s));
+  HIP_TRY(launch_bv_multiply(g->L, BVMV_F32_COMP, xv, yv, s));
+  HIP_TRY(launch_features(n, indeg.p, g->d_outdeg, g->d_stats, yd, yi, yv, 1.0f / float(std::max(g->R, 1)), F, s));
+  // the scratch is freed on return: wait for the kernels that use it
+  HIP_TRY(hipStreamSynchronize(s));
+  return BVMV_OK;
+}
+
+int bvmv_mlp_create(int device, const float* params, bvmv_mlp** out) {
+  if (!params || !out) return fail(BVMV_EINVAL, "null argument");
+  *out = nullptr;
+  DeviceGuard dg(device);
+  if (dg.err != hipSuccess) return fail(BVMV_EDEVICE, "hipSetDevice failed");
+  std::unique_ptr<bvmv_mlp> m(new bvmv_mlp());
+  m->device = device;
+  auto cleanup = [&] {
+    dev_free(m->theta);
+    dev_free(m->wq);
+    dev_free(m->m);
+    dev_free(m->v);
+    dev_free(m->grad);
+  };
+  if (dev_upload(&m->theta, params, kMlpParams) ||
+      hipMalloc(reinterpret_cast<void**>(&m->wq), kMlpWeights * sizeof(uint16_t)) != hipSuccess ||
+      hipMalloc(reinterpret_cast<void**>(&m->m), kMlpParams * sizeof(float)) != hipSuccess ||
+      hipMalloc(reinterpret_cast<void**>(&m->v), kMlpParams * sizeof(float)) != hipSuccess ||
+      hipMalloc(reinterpret_cast<void**>(&m->grad), (kMlpParams + 1) * sizeof(float)) != hipSuccess) {
+    cleanup();
+    return fail(BVMV_ENOMEM, "network allocation");
+  }
+  if (hipMemset(m->m, 0, kMlpParams * sizeof(float)) != hipSuccess ||
+      hipMemset(m->v, 0, kMlpParams * sizeof(float)) != hipSuccess ||
+      launch_mlp_quantize(m->theta, m->wq, nullptr) != hipSuccess || hipDeviceSynchronize() != hipSuccess) {
+    cleanup();
+    return fail(BVMV_EDEVICE, "network initialisation");
+  }
+  *out = m.release();
+  return BVMV_OK;
+}
+
+int bvmv_mlp_params(const bvmv_mlp* m, float* params) {
+  if (!m || !params) return fail(BVMV_EINVAL, "null argument");
+  DeviceGuard dg(m->device);
+  HIP_TRY(hipDeviceSynchronize());
+  HIP_TRY(hipMemcpy(params, m->theta, kMlpParams * sizeof(float), hipMemcpyDeviceToHost));
+  return BVMV_OK;
+}
+
+int bvmv_mlp_forward(bvmv_mlp* m, const float* F, int64_t n, float* s, void* stream) {
+  if (!m || !F || !s || n < 0) return fail(BVMV_EINVAL, "bad network arguments");
+  DeviceGuard dg(m->device);
+  HIP_TRY(launch_mlp_forward(m->theta, m->wq, F, n, s, static_cast<hipStream_t>(stream)));
+  return BVMV_OK;
+}
+
+int bvmv_mlp_gradient(bvmv_mlp* m, const float* F, const float* target, int64_t n, float* grad, void* stream) {
+  if (!m || !F || !target || !grad || n < 1 || n > kMlpMaxBatch) return fail(BVMV_EINVAL, "bad network arguments");
+  DeviceGuard dg(m->device);
+  const int64_t rows = (n + 31) / 32;
+  if (rows > m->part_rows) {
+    HIP_TRY(hipStreamSynchronize(static_cast<hipStream_t>(stream)));
+    dev_free(m->part);
+    m->part = nullptr;
+    m->part_rows = 0;
+    if (hipMalloc(reinterpret_cast<void**>(&m->part), size_t(rows) * (kMlpParams + 1) * sizeof(float)) != hipSuccess)
+      return fail(BVMV_ENOMEM, "gradient partials");
+    m->part_rows = rows;
+  }
+  HIP_TRY(launch_mlp_gradient(m->theta, m->wq, F, target, n, m->part, grad, static_cast<hipStream_t>(stream)));
+  return BVMV_OK;
+}
+
+int bvmv_mlp_train_step(bvmv_mlp* m, const float* F, const float* target, int64_t n, float lr, float* loss,
+                        void* stream) {
+  if (!m || !(lr > 0.0f)) return fail(BVMV_EINVAL, "bad network arguments");
+  if (int rc = bvmv_mlp_gradient(m, F, target, n, m->grad, stream)) return rc;
+  DeviceGuard dg(m->device);
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  HIP_TRY(launch_mlp_adam(m->theta, m->wq, m->m, m->v, m->grad, lr, 0.9f, 0.999f, 1e-8f, ++m->step, s));
+  if (loss) HIP_TRY(hipMemcpyAsync(loss, m->grad + kMlpParams, sizeof(float), hipMemcpyDeviceToDevice, s));
+  return BVMV_OK;
+}
+
+int bvmv_warm_start(bvmv_graph* g, bvmv_mlp* m, int prec, void* p0, void* stream) {
+  if (!g || !m || !p0) return fail(BVMV_EINVAL, "null argument");
+  if (prec < 0 || prec > 2) return fail(BVMV_EINVAL, "bad precision");
+  if (g->device != m->device) return fail(BVMV_EINVAL, "graph and network on different devices");
+  DeviceGuard dg(g->device);
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  const int64_t n = g->n;
+  DevBuf<float> F, sv, mpart;
+  DevBuf<double> spart;
+  if (F.alloc(size_t(n) * kMlpIn) || sv.alloc(size_t(n)) || mpart.alloc(kStartBlocks) || spart.alloc(kStartBlocks))
+    return fail(BVMV_ENOMEM, "warm-start scratch");
+  if (int rc = bvmv_features(g, F.p, stream)) return rc;
+  HIP_TRY(launch_mlp_forward(m->theta, m->wq, F.p, n, sv.p, s));
+  HIP_TRY(launch_start_vector(sv.p, n, mpart.p, spart.p, prec, p0, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  return BVMV_OK;
+}
+
+void bvmv_mlp_free(bvmv_mlp* m) {
+  if (!m) return;
+  {
+    DeviceGuard dg(m->device);
+    (void)hipDeviceSynchronize();
+    dev_free(m->theta);
+    dev_free(m->wq);
+    dev_free(m->m);
+    dev_free(m->v);
+    dev_free(m->grad);
+    dev_free(m->part);
+  }
+  delete m;
 }
 
 }  // extern "C"

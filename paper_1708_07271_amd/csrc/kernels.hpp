@@ -88,4 +88,31 @@ hipError_t launch_pr_select(int prec, const PRState* st, const void* p0, const v
 hipError_t launch_bv_multiply_batch(const DevLayout& L, int prec, const void* X, void* Y, int k, int64_t ld,
                                     hipStream_t s);
 
+
+// ------------------------------------------------------------ learned warm start
+constexpr int kMlpIn = 12, kMlpHidden = 64;
+constexpr int kMlpParams = kMlpHidden * kMlpIn + kMlpHidden + kMlpHidden * kMlpHidden + kMlpHidden + kMlpHidden + 1;
+constexpr int kMlpWeights = kMlpHidden * kMlpIn + kMlpHidden * kMlpHidden + kMlpHidden;  // BF16 copies
+constexpr int64_t kMlpMaxBatch = 1 << 20; // feature rows per gradient call
+constexpr int kStartBlocks = 1024;
+// s = MLP(F) for n feature rows (node-major n x 12)
+hipError_t launch_mlp_forward(const float* theta, const uint16_t* wq, const float* F, int64_t n, float* s,
+                              hipStream_t st);
+// grad[0..kMlpParams) = gradient of the mean squared error, grad[kMlpParams] = the loss;
+// part: one row of kMlpParams + 1 floats per 32 feature rows (ceil(n / 32) rows)
+int mlp_grad_blocks(int64_t n);
+hipError_t launch_mlp_gradient(const float* theta, const uint16_t* wq, const float* F, const float* target, int64_t n,
+                               float* part, float* grad, hipStream_t st);
+hipError_t launch_mlp_adam(float* theta, uint16_t* wq, float* m, float* v, const float* grad, float lr, float b1,
+                           float b2, float eps, int step, hipStream_t st);
+hipError_t launch_mlp_quantize(const float* theta, uint16_t* wq, hipStream_t st);
+hipError_t launch_feature_inputs(int64_t n, const int32_t* indeg, const int32_t* outdeg, float* xd, float* xi,
+                                 float* xv, hipStream_t st);
+hipError_t launch_features(int64_t n, const int32_t* indeg, const int32_t* outdeg, const uint32_t* stats,
+                           const float* yd, const float* yi, const float* yv, float inv_r, float* F, hipStream_t st);
+// p0 = exp(s - max s) / sum (prec 0: double p0, else float); mpart: kStartBlocks floats,
+// spart: kStartBlocks doubles
+hipError_t launch_start_vector(const float* s, int64_t n, float* mpart, double* spart, int prec, void* p0,
+                               hipStream_t st);
+
 }  // namespace bvmv
