@@ -3,9 +3,9 @@
 TEST INFRASTRUCTURE: CPU oracle, imported only by tests, the smoke check and
 the benchmark's CPU-baseline leg.
 
-The network predicts s_v ~ log(n p*_v) from node v's 12 features (see
-oracle.features); the warm start is p0_v proportional to exp(s_v).  Its
-defined arithmetic, which the device kernels follow:
+The network maps node v's 12 inputs (oracle.features) to s_v, its estimate
+of the remaining PageRank correction at a warm restart (oracle.restart).
+Its defined arithmetic, which the device kernels follow:
   - parameters: W1 (64 x 12), b1 (64), W2 (64 x 64), b2 (64), w3 (64), b3;
     the weights W1, W2, w3 are BF16 values (round-to-nearest-even copies of
     FP32 master weights), the biases FP32;

@@ -326,14 +326,114 @@ def test_row_stats_match_lists():
     assert st[:, 0].max() <= hdr["R"] and st[:, 2].sum() > 0 and st[:, 1].sum() > 0
 
 
-def test_features_closed_forms_star():
+def test_structural_closed_forms_star():
     # loaded rows: row 0 lists every other node (all of them link to 0); other rows empty
     n = 40
     g = B.from_lists([list(range(1, n))] + [[] for _ in range(n - 1)])
     rowptr, col, refs, hdr, st = bvdecode.decode(B.encode(g).data, with_stats=True)
-    F = feat.features(rowptr, col, st, hdr["R"])
+    F = feat.structural(rowptr, col, st, hdr["R"])
+    assert F.shape == (n, 8)
     assert np.allclose(F[0, :4], [math.log1p(n - 1), 0.0, 0.0, 1.0])
     assert np.allclose(F[1:, :4], [0.0, math.log(2.0), 0.0, 0.0])
-    assert np.allclose(F[0, 4:8], [0.0, math.log(2.0), math.log1p(n - 1), 0.0])   # one interval 1..n-1
-    assert np.allclose(F[0, 8:11], [math.log(2.0), 0.0, math.log1p(n * (n - 1))])
-    assert np.allclose(F[1:, 4:11], 0.0) and np.allclose(F[:, 11], math.log(n))
+    assert np.allclose(F[0, 4:6], [math.log(2.0), 0.0])          # one interval 1..n-1, no residual
+    # in-neighbours of 0 have out-degree 1 and in-degree 0
+    assert np.allclose(F[0, 6:8], [math.log(2.0), 0.0])
+    assert np.allclose(F[1:, 4:8], 0.0)
+
+
+def _cycle2_iterates(beta, s0, ks):
+    """Iterates of the oracle power method on the 2-cycle from s0."""
+    g = B.from_lists([[1], [0]])
+    return [pagerank.pagerank(g.rowptr, g.col, beta, start=s0, iters=k)[0] if k else np.array(s0) for k in ks]
+
+
+def test_trajectory_and_target_single_mode():
+    # On the 2-cycle the error of the power method is one eigenmode: e_k =
+    # (-beta)^k e_0, p* = (1/2, 1/2).  Then p_K - p_{K-1} = e_K (1 + 1/beta),
+    # so the remaining correction p* - p_K = -e_K is the last step times
+    # beta / (1 + beta) with a minus sign, and each older step is the newer one
+    # divided by -beta.
+    beta, K = 0.85, 6
+    pK3, pK2, pK1, pK = _cycle2_iterates(beta, [0.9, 0.1], [K - 3, K - 2, K - 1, K])
+    Tr, delta = feat.trajectory(pK, pK1, pK2, pK3)
+    e = 0.4 * beta ** K
+    assert abs(delta - 2 * e * (1 + 1 / beta)) < 1e-15
+    assert np.allclose(Tr[:, 0], np.log(2 * pK), rtol=0, atol=1e-15)
+    assert np.allclose(Tr[:, 1], [1.0, -1.0], rtol=0, atol=1e-12)      # K even: p_K above 1/2 at node 0
+    assert np.allclose(Tr[:, 2], Tr[:, 1] / -beta, rtol=0, atol=1e-12)
+    assert np.allclose(Tr[:, 3], Tr[:, 1] / beta ** 2, rtol=0, atol=1e-12)
+    t = feat.target([0.5, 0.5], pK, delta)
+    assert np.allclose(t, -Tr[:, 1] * beta / (1 + beta), rtol=0, atol=1e-12)
+
+
+def test_restart_vector_perfect_and_floor():
+    rng = np.random.default_rng(5)
+    ps = rng.uniform(0.5, 1.5, 30)
+    ps /= ps.sum()
+    pK = ps * rng.uniform(0.9, 1.1, 30)
+    pK /= pK.sum()
+    delta = 0.037
+    # the target as prediction restores p* exactly
+    assert np.allclose(feat.restart_vector(pK, feat.target(ps, pK, delta), delta), ps, rtol=0, atol=1e-16)
+    # zero prediction keeps p_K; a very negative one floors every entry, which normalises back to p_K
+    assert np.allclose(feat.restart_vector(pK, np.zeros(30), delta), pK, rtol=0, atol=1e-16)
+    assert np.allclose(feat.restart_vector(pK, np.full(30, -1e12), delta), pK, rtol=0, atol=1e-16)
+    # partial floor: entries below p_K / 1000 are raised to it
+    s = np.zeros(30)
+    s[3] = -1e12
+    q = np.maximum(pK + s * delta / 30, pK / 1000)
+    assert q[3] == pK[3] / 1000
+    assert np.allclose(feat.restart_vector(pK, s, delta), q / q.sum(), rtol=0, atol=1e-16)
+
+
+def _small_web():
+    g = B.web_graph(3000, 10.0, 17)
+    rowptr, col, refs, hdr, st = bvdecode.decode(B.encode(g).data, with_stats=True)
+    return rowptr, col, feat.structural(rowptr, col, st, hdr["R"])
+
+
+def test_restarted_zero_and_rejected_predictions_follow_plain_method():
+    from oracle import restart
+    rowptr, col, Fs = _small_web()
+    p0, t0, r0, ok0 = pagerank.pagerank(rowptr, col, 0.85, tol=1e-8)
+    # zero prediction: each restart is p_K itself (up to the sum's rounding), accepted
+    p, t, r, ok, info = restart.pagerank_restarted(rowptr, col, lambda F: np.zeros(len(F)), Fs, tol=1e-8)
+    assert ok and t == t0 and info["accepted"] == 3 and info["rejected"] == 0
+    assert np.max(np.abs(p - p0)) < 1e-15
+    # a wild prediction is rejected once, costs one product, the rest is the plain run
+    p, t, r, ok, info = restart.pagerank_restarted(rowptr, col, lambda F: np.full(len(F), 1e9), Fs, tol=1e-8)
+    assert ok and t == t0 and info == dict(products=t0 + 1, accepted=0, rejected=1)
+    assert np.array_equal(p, p0)
+
+
+def test_restarted_perfect_prediction_converges_after_restart():
+    from oracle import restart
+    rowptr, col, Fs = _small_web()
+    n = len(rowptr) - 1
+    ps = pagerank.pagerank(rowptr, col, 0.85, tol=1e-15, max_iter=5000)[0]
+    K = 8
+    pK = pagerank.pagerank(rowptr, col, 0.85, iters=K)[0]
+    pK1 = pagerank.pagerank(rowptr, col, 0.85, iters=K - 1)[0]
+    delta = np.abs(pK - pK1).sum()
+    p, t, r, ok, info = restart.pagerank_restarted(rowptr, col, lambda F: feat.target(ps, pK, delta), Fs,
+                                                   tol=1e-8, K=K)
+    assert ok and t == K + 1 and info == dict(products=K + 1, accepted=1, rejected=0)
+    assert np.abs(p - ps).sum() < 1e-12
+
+
+def test_restarted_matches_dense_fixed_point():
+    from oracle import restart
+    # a noisy predictor still ends at the unique fixed point within the plain method's bound
+    g = B.web_graph(400, 6.0, 3)
+    rowptr, col, refs, hdr, st = bvdecode.decode(B.encode(g).data, with_stats=True)
+    Fs = feat.structural(rowptr, col, st, hdr["R"])
+    n = len(rowptr) - 1
+    A = np.zeros((n, n))
+    for v in range(n):
+        A[col[int(rowptr[v]):int(rowptr[v + 1])], v] = 1.0      # row v lists u -> v
+    exact = pagerank.pagerank_dense(A, 0.85)
+    rng = np.random.default_rng(9)
+    p, t, r, ok, info = restart.pagerank_restarted(rowptr, col, lambda F: F[:, 9] + rng.normal(0, 0.5, len(F)),
+                                                   Fs, tol=1e-9, K=5)
+    assert ok and abs(p.sum() - 1.0) < 1e-12
+    assert np.abs(p - exact).sum() <= r * 0.85 / 0.15 + 1e-13
