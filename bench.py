@@ -9,6 +9,7 @@ line.  Single GPU only."""
 import argparse
 import hashlib
 import json
+import math
 import os
 import sys
 import time
@@ -131,6 +132,92 @@ def bench_batch(args, B, P, np, torch, dev):
     print(json.dumps(out), flush=True)
 
 
+def bench_warm(args, B, P, np, torch, dev):
+    """Learned warm restarts: restart samples (the 12 inputs after K = 10 plain
+    iterations from the uniform vector, and the target n (p* - p_K) / delta
+    from the method's own FP64 PageRank) of generated web-like graphs (n
+    log-uniform in [1e5, 1e6], mean degree 20, graph seeds 2000 + i), the
+    network trained on the device (Adam, batches of 8192 nodes, network seed
+    4000, cosine learning rate), then PageRank of an unseen graph (seed 3000)
+    to L1 1e-6: plain, with learned restarts (every 10 iterations, at most 3),
+    and with a zero network (every restart accepted and the identity: the
+    restart overhead alone).  Each PageRank is timed end to end, median of 3;
+    the learned run's first call, which also computes the structural inputs
+    once for the graph, is reported apart."""
+    from oracle import mlp as _oracle_mlp  # parameter initialisation only (seeded uniform Glorot)
+    K = 10
+    rng = np.random.default_rng(2000)
+    sizes = np.round(10 ** rng.uniform(5, 6, args.warm_graphs)).astype(np.int64)
+    Fs, Ts = [], []
+    t0 = time.perf_counter()
+    for i, n in enumerate(sizes):
+        g = B.web_graph(int(n), 20.0, 2000 + i)
+        G = P.bvmv_load(B.encode(g).data)
+        ps = torch.empty(g.n, dtype=torch.float64, device=dev)
+        P.bvmv_pagerank(G, ps, tol=1e-12, max_iter=5000, prec=P.BVMV_F64)
+        F = torch.empty(g.n, P.NFEAT, device=dev)
+        T = torch.empty(g.n, device=dev)
+        P.bvmv_restart_sample(G, K, F, T, ps.float())
+        Fs.append(F)
+        Ts.append(T)
+        del G, g
+        if i % 20 == 0:
+            log("training data: graph %d/%d (%.1fs)" % (i, len(sizes), time.perf_counter() - t0))
+    F = torch.cat(Fs)
+    T = torch.cat(Ts).contiguous()
+    del Fs, Ts
+    t_data = time.perf_counter() - t0
+    log("training data: %d graphs, %d nodes (%.1fs)" % (len(sizes), F.shape[0], t_data))
+    m = P.bvmv_mlp_create(_oracle_mlp.init_params(4000))
+    loss = torch.empty(1, device=dev)
+    gen = torch.Generator(device=dev).manual_seed(4000)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    losses = []
+    for it in range(args.warm_steps):
+        lr = 3e-3 * (0.5 * (1 + math.cos(math.pi * it / args.warm_steps)) + 0.01)
+        idx = torch.randint(0, F.shape[0], (8192,), device=dev, generator=gen)
+        P.bvmv_mlp_train_step(m, F[idx].contiguous(), T[idx].contiguous(), lr, loss)
+        if it % max(1, args.warm_steps // 10) == 0 or it == args.warm_steps - 1:
+            losses.append(float(loss.item()))
+    torch.cuda.synchronize()
+    t_train = time.perf_counter() - t0
+    log("training: %d steps in %.2fs, loss %s" % (args.warm_steps, t_train, ["%.4f" % v for v in losses]))
+    del F, T
+    g = B.web_graph(args.warm_test_n, 20.0, 3000)
+    G = P.bvmv_load(B.encode(g).data)
+    n = g.n
+    p = torch.empty(n, device=dev)
+    zero = P.bvmv_mlp_create(np.zeros(P.MLP_PARAMS, dtype=np.float32))
+
+    def timed(fn):
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        r = fn()
+        torch.cuda.synchronize()
+        return r, time.perf_counter() - t
+
+    P.bvmv_pagerank(G, p)  # graph capture
+    (rf,), s_first = timed(lambda: P.bvmv_pagerank_detail(G, p, mlp=m))
+    runs = {}
+    for name, kw in (("plain", {}), ("learned", {"mlp": m}), ("zero_network", {"mlp": zero})):
+        ts = []
+        for _ in range(3):
+            (r,), t = timed(lambda: P.bvmv_pagerank_detail(G, p, **kw))
+            ts.append(t)
+        runs[name] = dict(iters=r["iters"], products=r["products"], accepted=r["restarts_accepted"],
+                          rejected=r["restarts_rejected"], converged=bool(r["converged"]),
+                          seconds=float(np.median(ts)))
+        log("pagerank n=%d %s: %s" % (n, name, runs[name]))
+    out = {"mode": "learned-warm-restart", "train_graphs": len(sizes), "train_nodes": int(sizes.sum()),
+           "restart_every": K, "train_steps": args.warm_steps, "train_seconds": t_train, "data_seconds": t_data,
+           "loss_trace": losses, "test_n": n, "test_m": g.m, "dtype": "f32 two-sum compensated",
+           "first_learned_call_seconds": s_first, **runs,
+           "speedup_learned_vs_plain": runs["plain"]["seconds"] / runs["learned"]["seconds"],
+           "product_ratio_learned_vs_plain": runs["learned"]["products"] / runs["plain"]["products"]}
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -149,6 +236,12 @@ def main():
     ap.add_argument("--batch", type=int, default=0, metavar="K",
                     help="batched personalized PageRank with K teleport sets of 16 seeds (workload "
                          "web-n8e6-d25 unless --workload is given) instead of the single-vector metric")
+    ap.add_argument("--warm-start", action="store_true",
+                    help="learned warm restarts: train the network on generated graphs, then PageRank of an "
+                         "unseen graph with restarts against the plain method")
+    ap.add_argument("--warm-graphs", type=int, default=200)
+    ap.add_argument("--warm-steps", type=int, default=3000)
+    ap.add_argument("--warm-test-n", type=int, default=5_000_000)
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="only run torch copies of MIB MiB (the calibration kernel for HBM byte counters)")
     args = ap.parse_args()
@@ -179,6 +272,8 @@ def main():
 
     if args.batch:
         return bench_batch(args, B, P, np, torch, dev)
+    if args.warm_start:
+        return bench_warm(args, B, P, np, torch, dev)
     t0 = time.perf_counter()
     g = B.workload_graph(args.workload)
     enc = B.encode(g)

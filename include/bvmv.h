@@ -94,6 +94,8 @@ int bvmv_multiply(bvmv_graph* g, const void* x, void* y, int prec, void* stream)
  * BVMV_F64 (double). */
 int bvmv_multiply_batch(bvmv_graph* g, const void* X, void* Y, int k, int64_t ld, int prec, void* stream);
 
+typedef struct bvmv_mlp bvmv_mlp;  /* the warm-restart network (declared with its entry points below) */
+
 /* PageRank options.  damping = beta, the weight of following links (the
  * paper's teleport probability a is 1 - beta).  Iteration stops at the first
  * t with ||p_t - p_{t-1}||_1 < tol (accumulated in double), or at max_iter. */
@@ -107,14 +109,22 @@ typedef struct {
   int fallback_check;      /* 1 (k = 1, single graph, start given): run one iteration from
                               `start` and one from the teleport vector, and keep `start` only
                               if its residual is the smaller; the probes are not counted */
+  const bvmv_mlp* mlp;     /* non-NULL: learned warm restarts with this network (k = 1, single
+                              graph, uniform teleport, no start vector; see the learned
+                              section below) */
+  int restart_every;       /* K >= 3: a restart after every K iterations (0 = default 10) */
+  int max_restarts;        /* restarts to try (0 = default 3); the first rejected one ends them */
 } bvmv_pr_opts;
 
 typedef struct {
-  int iters;          /* iterations run (the t at which the stopping test held) */
+  int iters;          /* iterations run (the t at which the stopping test held); an accepted
+                         restart's probe iteration is one of them */
   int converged;      /* 1 if residual < tol */
   double residual;    /* ||p_t - p_{t-1}||_1 of the last iteration */
   int used_start;     /* 1: started from `start`; 0: from the teleport vector (no start, or
                          the fallback check rejected it) */
+  int products;       /* matrix products run: iters + rejected restart probes */
+  int restarts_accepted, restarts_rejected;
 } bvmv_pr_result;
 
 /* PageRank by the power method, Eq. (1), on the loaded rows read as IN-LINK
@@ -199,24 +209,42 @@ int bvmv_layout_selfcheck(const void* bitstream, size_t nbytes, const bvmv_load_
                           double* y, int64_t* stats);
 
 /* ---------------------------------------------------------------------------
- * Learned PageRank warm start (not in the paper; the paper's PageRank starts
- * from the uniform vector, Section "Experimental Evaluation").  A small MLP
- * predicts s_v ~ log(n p*_v) from 12 structural features of node v; the start
- * vector is p0 proportional to exp(s).  By the L1 contraction of Eq. (1) the
- * fixed point does not depend on the start, so a warm start only changes the
- * number of iterations.
+ * Learned PageRank warm restarts (not in the paper; its PageRank starts from
+ * the uniform vector, Section "Experimental Evaluation").  Every K iterations
+ * of Eq. (1) a small MLP maps 12 inputs per node v to s_v, its estimate of
+ * the remaining correction t_v = n (p*_v - p_K(v)) / delta in units of the
+ * last step, delta = ||p_K - p_{K-1}||_1; the restart vector is
+ * p'_v = max(p_K(v) + s_v delta / n, p_K(v) / 1000) / sum.  One iteration from
+ * p' gives its residual r'; p' is kept only if r' < damping * delta (the L1
+ * contraction bounds the plain method's next residual by damping * delta),
+ * otherwise the run goes on from p_K and no further restart is tried.  The
+ * fixed point does not depend on the restarts: the stopping test and its
+ * error bound are the plain method's.
+ * Inputs of node v (rows read as in-link lists):
+ *   0 log1p(in-degree)   1 log1p(out-degree d)   2 reference-chain depth / R
+ *   3 [d = 0]   4 log1p(intervals of the row)   5 log1p(residuals of the row)
+ *   6 log1p(mean out-degree of the in-neighbours)
+ *   7 log1p(mean in-degree of the in-neighbours)
+ *   8 log(n p_K)   9 n (p_K - p_{K-1}) / delta   10 n (p_{K-1} - p_{K-2}) / delta
+ *   11 n (p_{K-2} - p_{K-3}) / delta
  * ------------------------------------------------------------------------- */
-#define BVMV_NFEAT 12        /* features per node */
+#define BVMV_NFEAT 12        /* inputs per node */
 #define BVMV_MLP_PARAMS 5057 /* W1 (64x12), b1 (64), W2 (64x64), b2 (64), w3 (64), b3 (1), row-major (out, in) */
-typedef struct bvmv_mlp bvmv_mlp;
 
-/* Features of every node into F (device, n x 12 node-major FP32), rows read as
- * in-link lists: log1p(in-degree), log1p(out-degree d), reference-chain depth
- * / R, [d = 0], log1p of the row's skipped reference entries, intervals,
- * interval length and residuals in the stream, log1p of the mean out-degree
- * and of the mean in-degree of the in-neighbours, log1p(n sum over
- * in-neighbours u of 1/d_u), log n.  Uses the degree pass and three products. */
+/* The structural inputs 0..7 of every node into columns 0..7 of F (device,
+ * n x 12 node-major FP32); columns 8..11 are left as they are.  Uses the
+ * degree pass and two products; uploads the row coding statistics once per
+ * graph.  Single graph only.  Synchronous. */
 int bvmv_features(bvmv_graph* g, float* F, void* stream);
+
+/* A training sample of g: K >= 3 plain iterations from the uniform vector
+ * (prec as for bvmv_pagerank), then all 12 inputs into F (device n x 12) and,
+ * if p_star (device, n of the prec's type) is given, the target
+ * t = n (p_star - p_K) / delta into T (device n floats).  delta: HOST double
+ * or NULL.  BVMV_EINVAL if the run converges within K iterations (delta would
+ * be below tol).  Single graph only.  Synchronous. */
+int bvmv_restart_sample(bvmv_graph* g, int K, int prec, const void* p_star, float* F, float* T, double* delta,
+                        void* stream);
 
 /* A network on `device` with the given FP32 master parameters (HOST array of
  * BVMV_MLP_PARAMS); weights are used as BF16 copies, biases as FP32; Adam
@@ -235,9 +263,6 @@ int bvmv_mlp_gradient(bvmv_mlp* m, const float* F, const float* target, int64_t 
  * b2 = 0.999, eps = 1e-8) with learning rate lr.  loss: device float or NULL. */
 int bvmv_mlp_train_step(bvmv_mlp* m, const float* F, const float* target, int64_t n, float lr, float* loss,
                         void* stream);
-/* Warm start of g: features, the network, p0 = exp(s - max s) / sum into p0
- * (device, n elements of the prec's type: double for BVMV_F64, float else). */
-int bvmv_warm_start(bvmv_graph* g, bvmv_mlp* m, int prec, void* p0, void* stream);
 void bvmv_mlp_free(bvmv_mlp* m);
 
 void bvmv_free(bvmv_graph* g);

@@ -40,12 +40,14 @@ class LoadOpts(ctypes.Structure):
 class PROpts(ctypes.Structure):
     _fields_ = [("damping", ctypes.c_double), ("tol", ctypes.c_double), ("max_iter", ctypes.c_int),
                 ("prec", ctypes.c_int), ("chunk", ctypes.c_int), ("exact_zero_damping", ctypes.c_int),
-                ("fallback_check", ctypes.c_int)]
+                ("fallback_check", ctypes.c_int), ("mlp", ctypes.c_void_p), ("restart_every", ctypes.c_int),
+                ("max_restarts", ctypes.c_int)]
 
 
 class PRResult(ctypes.Structure):
     _fields_ = [("iters", ctypes.c_int), ("converged", ctypes.c_int), ("residual", ctypes.c_double),
-                ("used_start", ctypes.c_int)]
+                ("used_start", ctypes.c_int), ("products", ctypes.c_int), ("restarts_accepted", ctypes.c_int),
+                ("restarts_rejected", ctypes.c_int)]
 
 
 NFEAT = 12
@@ -101,7 +103,7 @@ def load_library():
         "bvmv_mlp_forward": ([vp, vp, i64, vp, vp], i32),
         "bvmv_mlp_gradient": ([vp, vp, vp, i64, vp, vp], i32),
         "bvmv_mlp_train_step": ([vp, vp, vp, i64, ctypes.c_float, vp, vp], i32),
-        "bvmv_warm_start": ([vp, vp, i32, vp, vp], i32),
+        "bvmv_restart_sample": ([vp, i32, i32, vp, vp, vp, P(ctypes.c_double), vp], i32),
         "bvmv_mlp_free": ([vp], None),
         "bvmv_last_error": ([], ctypes.c_char_p),
         "bvmv_version": ([], ctypes.c_char_p),
@@ -223,14 +225,18 @@ def bvmv_multiply_batch(g: Graph, X, Y, prec=BVMV_F32_COMP, stream=None):
                                               _stream_ptr(stream)))
 
 
-def _pr_opts(damping, tol, max_iter, prec, chunk, fallback_check=0):
-    return PROpts(damping, tol, max_iter, _prec(prec), chunk, 1 if damping == 0.0 else 0, int(fallback_check))
+def _pr_opts(damping, tol, max_iter, prec, chunk, fallback_check=0, mlp=None, restart_every=0, max_restarts=0):
+    return PROpts(damping, tol, max_iter, _prec(prec), chunk, 1 if damping == 0.0 else 0, int(fallback_check),
+                  mlp.handle if mlp is not None else None, int(restart_every), int(max_restarts))
 
 
 def bvmv_pagerank_detail(g: Graph, p_out, teleport=None, start=None, damping=0.85, tol=1e-6, max_iter=1000,
-                         prec=BVMV_F32_COMP, chunk=16, k=1, fallback_check=0, stream=None):
-    """Returns a list of dicts (iters, converged, residual, used_start), one per
-    column (or member of a group)."""
+                         prec=BVMV_F32_COMP, chunk=16, k=1, fallback_check=0, stream=None, mlp=None,
+                         restart_every=0, max_restarts=0):
+    """Returns a list of dicts (iters, converged, residual, used_start,
+    products, restarts_accepted, restarts_rejected), one per column (or member
+    of a group).  With `mlp`, learned warm restarts every `restart_every`
+    iterations (0 = 10), at most `max_restarts` (0 = 3)."""
     p = _prec(prec)
     dt = _vec_dtype(p)
     lib = load_library()
@@ -238,12 +244,13 @@ def bvmv_pagerank_detail(g: Graph, p_out, teleport=None, start=None, damping=0.8
     if g.members is not None:
         nres = len(g.members)
     res = (PRResult * max(nres, 1))()
-    o = _pr_opts(damping, tol, max_iter, p, chunk, fallback_check)
+    o = _pr_opts(damping, tol, max_iter, p, chunk, fallback_check, mlp, restart_every, max_restarts)
     tp = _dev_ptr(teleport, dt, g.n * k) if teleport is not None else ctypes.c_void_p(None)
     sp = _dev_ptr(start, dt, g.n * k) if start is not None else ctypes.c_void_p(None)
     _check(lib.bvmv_pagerank(g.handle, ctypes.byref(o), tp, sp, _dev_ptr(p_out, dt, g.n * k), k, res,
                              _stream_ptr(stream)), allow=(BVMV_OK, BVMV_NOT_CONVERGED))
-    return [dict(iters=r.iters, converged=bool(r.converged), residual=r.residual, used_start=r.used_start)
+    return [dict(iters=r.iters, converged=bool(r.converged), residual=r.residual, used_start=r.used_start,
+                 products=r.products, restarts_accepted=r.restarts_accepted, restarts_rejected=r.restarts_rejected)
             for r in res[:nres]]
 
 
@@ -379,7 +386,7 @@ class Mlp:
 
 
 def bvmv_features(g: Graph, F, stream=None):
-    """F: (n, 12) float32 device tensor."""
+    """Structural inputs into columns 0..7 of F, an (n, 12) float32 device tensor."""
     import torch
     _check(load_library().bvmv_features(g.handle, _dev_ptr(F, torch.float32, g.n * NFEAT), _stream_ptr(stream)))
 
@@ -424,7 +431,17 @@ def bvmv_mlp_train_step(m: Mlp, F, target, lr, loss=None, stream=None):
                                               _stream_ptr(stream)))
 
 
-def bvmv_warm_start(g: Graph, m: Mlp, p0, prec=BVMV_F32_COMP, stream=None):
+def bvmv_restart_sample(g: Graph, K, F, T=None, p_star=None, prec=BVMV_F32_COMP, stream=None):
+    """K plain iterations from the uniform vector, then the 12 inputs into F
+    ((n, 12) float32) and, with p_star, the target into T ((n,) float32).
+    Returns delta = ||p_K - p_{K-1}||_1."""
+    import torch
     p = _prec(prec)
-    _check(load_library().bvmv_warm_start(g.handle, m.handle, p, _dev_ptr(p0, _vec_dtype(p), g.n),
-                                          _stream_ptr(stream)))
+    if (T is None) != (p_star is None):
+        raise ValueError("T and p_star go together")
+    d = ctypes.c_double()
+    _check(load_library().bvmv_restart_sample(
+        g.handle, int(K), p, _dev_ptr(p_star, _vec_dtype(p), g.n) if p_star is not None else ctypes.c_void_p(None),
+        _dev_ptr(F, torch.float32, g.n * NFEAT), _dev_ptr(T, torch.float32, g.n) if T is not None else
+        ctypes.c_void_p(None), ctypes.byref(d), _stream_ptr(stream)))
+    return d.value

@@ -544,10 +544,11 @@ __device__ __forceinline__ void pr_block_partial(double rs, double dg, double* s
 // One block per member: the member's residual and dangling mass from its
 // blocks' slots, then the stopping test (with_resid = 1, after an iteration;
 // members already done were skipped by the iteration and are left alone) or
-// the start state (with_resid = 0, after pr_init_kernel).
+// the start state (with_resid = 0, after pr_init_kernel), whose iteration
+// count is iter0 (nonzero when a run resumes from a restart vector).
 __global__ void __launch_bounds__(kThreads) pr_finish_kernel(PRState* st_all, const double* __restrict__ slots,
                                                              int with_resid, double tol, int32_t max_iter,
-                                                             int32_t buf) {
+                                                             int32_t buf, int32_t iter0) {
   __shared__ double s_red[kWaves];
   PRState* st = st_all + blockIdx.x;
   if (with_resid && st->done) return;
@@ -573,7 +574,7 @@ __global__ void __launch_bounds__(kThreads) pr_finish_kernel(PRState* st_all, co
       }
     } else {
       st->resid = 0.0;
-      st->iter = 0;
+      st->iter = iter0;
       st->done = 0;
       st->converged = 0;
       st->final_buf = 0;
@@ -829,13 +830,15 @@ __global__ void __launch_bounds__(kThreads) bv_wave_kernel(DevLayout L, const ty
 }
 
 // PageRank start: p0 = start (or teleport, or uniform), z0 = p0 / d, dangling mass.
+// With `normalize`, p0 = start / (the member's delta field), which then holds
+// the start's sum (restart_vector_kernel and an init-mode finish put it there).
 // Tiles are read through (row0, nrows) at a stride; the member through `graphs`.
 template <class M>
 __global__ void __launch_bounds__(kThreads) pr_init_kernel(const uint32_t* __restrict__ row0s, uint32_t row_stride,
                                                            const uint32_t* __restrict__ graphs, const void* start_,
                                                            const void* tele_, void* p0_, void* z0_,
                                                            const int32_t* __restrict__ outdeg, PRState* st_all,
-                                                           double* slots) {
+                                                           double* slots, int normalize) {
   using X = typename M::X;
   __shared__ __align__(16) unsigned char s_blk[256];
   const uint32_t wave = threadIdx.x >> 6, lane = lane_id();
@@ -848,17 +851,86 @@ __global__ void __launch_bounds__(kThreads) pr_init_kernel(const uint32_t* __res
   const X* tele = static_cast<const X*>(tele_);
   X* p0 = static_cast<X*>(p0_);
   X* z0 = static_cast<X*>(z0_);
+  const double inv_sum = normalize ? 1.0 / st->delta : 1.0;
   double dg = 0.0;
   for (uint32_t r = lane; r < nrows; r += 64) {
     const uint32_t v = row0 + r;
-    const X pv = start ? start[v] : (tele ? tele[v] : X(st->inv_n));
+    const X pv = start ? (normalize ? X(double(start[v]) * inv_sum) : start[v]) : (tele ? tele[v] : X(st->inv_n));
     p0[v] = pv;
     const int32_t d = outdeg[v];
     z0[v] = d > 0 ? pv / X(d) : X(0);
-    if (d == 0) dg = double(pv);
+    if (d == 0) dg += double(pv);
   }
   dg = wave_sum_f64(dg);
   pr_block_partial(0.0, dg, slots, s_blk);
+}
+
+// ----------------------------------------------------------- warm restarts
+// Inputs 8..11 of the restart network for every row v of a tile, from the
+// last four iterates p_K, p_{K-1}, p_{K-2}, p_{K-3} of the member, whose
+// delta = ||p_K - p_{K-1}||_1 is its state's residual and whose node count is
+// 1 / inv_n: log(n p_K), then n (p_j - p_{j-1}) / delta for the last three
+// steps, newest first.  With p_star given, also the training target
+// T_v = n (p*_v - p_K(v)) / delta.  F is node-major with 12 floats a row.
+template <class M>
+__global__ void __launch_bounds__(kThreads) restart_inputs_kernel(
+    const uint32_t* __restrict__ row0s, uint32_t row_stride, const uint32_t* __restrict__ graphs, const void* pK_,
+    const void* pK1_, const void* pK2_, const void* pK3_, const void* p_star_, const PRState* __restrict__ st_all,
+    float* __restrict__ F, float* __restrict__ T) {
+  using X = typename M::X;
+  const uint32_t wave = threadIdx.x >> 6, lane = lane_id();
+  const size_t tile = size_t(blockIdx.x) * kWaves + wave;
+  const uint32_t row0 = row0s[tile * row_stride];
+  const uint32_t nrows = row0s[tile * row_stride + 1] & 0x7FFFFFFFu;
+  const uint32_t graph = graphs ? graphs[size_t(blockIdx.x) * kWaves * row_stride] : 0u;
+  const PRState* st = st_all + graph;
+  const double n = 1.0 / st->inv_n, scale = n / st->resid;
+  const X* pK = static_cast<const X*>(pK_);
+  const X* pK1 = static_cast<const X*>(pK1_);
+  const X* pK2 = static_cast<const X*>(pK2_);
+  const X* pK3 = static_cast<const X*>(pK3_);
+  const X* p_star = static_cast<const X*>(p_star_);
+  for (uint32_t r = lane; r < nrows; r += 64) {
+    const uint32_t v = row0 + r;
+    const double a = double(pK[v]), b = double(pK1[v]), c = double(pK2[v]), d = double(pK3[v]);
+    float* f = F + size_t(v) * 12;
+    f[8] = float(log(n * a));
+    f[9] = float(scale * (a - b));
+    f[10] = float(scale * (b - c));
+    f[11] = float(scale * (c - d));
+    if (p_star) T[v] = float(scale * (double(p_star[v]) - a));
+  }
+}
+
+// Unnormalised restart vector q_v = max(p_K(v) + s_v delta / n, p_K(v) / 1000)
+// (delta and n as above), stored in the iterate's type; the block sums of the
+// stored values go to the dangling half of the block's slot, so that an
+// init-mode pr_finish_kernel leaves each member's sum of q in its delta field.
+template <class M>
+__global__ void __launch_bounds__(kThreads) restart_vector_kernel(
+    const uint32_t* __restrict__ row0s, uint32_t row_stride, const uint32_t* __restrict__ graphs, const void* pK_,
+    const float* __restrict__ s, const PRState* __restrict__ st_all, void* q_, double* slots) {
+  using X = typename M::X;
+  __shared__ __align__(16) unsigned char s_blk[256];
+  const uint32_t wave = threadIdx.x >> 6, lane = lane_id();
+  const size_t tile = size_t(blockIdx.x) * kWaves + wave;
+  const uint32_t row0 = row0s[tile * row_stride];
+  const uint32_t nrows = row0s[tile * row_stride + 1] & 0x7FFFFFFFu;
+  const uint32_t graph = graphs ? graphs[size_t(blockIdx.x) * kWaves * row_stride] : 0u;
+  const PRState* st = st_all + graph;
+  const double step = st->resid * st->inv_n;
+  const X* pK = static_cast<const X*>(pK_);
+  X* q = static_cast<X*>(q_);
+  double sum = 0.0;
+  for (uint32_t r = lane; r < nrows; r += 64) {
+    const uint32_t v = row0 + r;
+    const double a = double(pK[v]);
+    const X qv = X(fmax(a + double(s[v]) * step, 1e-3 * a));
+    q[v] = qv;
+    sum += double(qv);
+  }
+  sum = wave_sum_f64(sum);
+  pr_block_partial(0.0, sum, slots, s_blk);
 }
 
 // ---------------------------------------------------------------- CSR kernel
@@ -1497,7 +1569,7 @@ hipError_t launch_bv_degrees(const DevLayout& L, int32_t* deg, hipStream_t s) {
 
 hipError_t launch_pr_finish(const PRArgs& a, hipStream_t s) {
   hipLaunchKernelGGL(pr_finish_kernel, dim3(a.members), dim3(kThreads), 0, s, a.st, a.slots, 1, a.tol, a.max_iter,
-                     a.buf);
+                     a.buf, 0);
   return hipGetLastError();
 }
 
@@ -1513,19 +1585,54 @@ hipError_t launch_bv_pagerank_iter(const DevLayout& L, int prec, const PRArgs& a
 }
 
 hipError_t launch_pr_init(const DevLayout& L, int prec, const void* start, const void* tele, void* p0, void* z0,
-                          const int32_t* outdeg, PRState* st, double* slots, int members, hipStream_t s) {
+                          const int32_t* outdeg, PRState* st, double* slots, int members, hipStream_t s,
+                          int normalize, int32_t iter0) {
   if (L.ntiles == 0) return hipSuccess;
   const uint32_t* base = reinterpret_cast<const uint32_t*>(L.tiles);
   const uint32_t stride = sizeof(TileDesc) / 4;
   const uint32_t* graphs = base + offsetof(TileDesc, graph) / 4;
   if (prec == 0)
     hipLaunchKernelGGL(pr_init_kernel<MF64>, dim3(L.ntiles / kWaves), dim3(kThreads), 0, s, base, stride, graphs,
-                       start, tele, p0, z0, outdeg, st, slots);
+                       start, tele, p0, z0, outdeg, st, slots, normalize);
   else
     hipLaunchKernelGGL(pr_init_kernel<MF32>, dim3(L.ntiles / kWaves), dim3(kThreads), 0, s, base, stride, graphs,
-                       start, tele, p0, z0, outdeg, st, slots);
+                       start, tele, p0, z0, outdeg, st, slots, normalize);
   if (hipError_t e = hipGetLastError()) return e;
-  hipLaunchKernelGGL(pr_finish_kernel, dim3(members), dim3(kThreads), 0, s, st, slots, 0, 0.0, 0, 0);
+  hipLaunchKernelGGL(pr_finish_kernel, dim3(members), dim3(kThreads), 0, s, st, slots, 0, 0.0, 0, 0, iter0);
+  return hipGetLastError();
+}
+
+hipError_t launch_restart_inputs(const DevLayout& L, int prec, const void* pK, const void* pK1, const void* pK2,
+                                 const void* pK3, const void* p_star, const PRState* st, float* F, float* T,
+                                 hipStream_t s) {
+  if (L.ntiles == 0) return hipSuccess;
+  const uint32_t* base = reinterpret_cast<const uint32_t*>(L.tiles);
+  const uint32_t stride = sizeof(TileDesc) / 4;
+  const uint32_t* graphs = base + offsetof(TileDesc, graph) / 4;
+  if (prec == 0)
+    hipLaunchKernelGGL(restart_inputs_kernel<MF64>, dim3(L.ntiles / kWaves), dim3(kThreads), 0, s, base, stride,
+                       graphs, pK, pK1, pK2, pK3, p_star, st, F, T);
+  else
+    hipLaunchKernelGGL(restart_inputs_kernel<MF32>, dim3(L.ntiles / kWaves), dim3(kThreads), 0, s, base, stride,
+                       graphs, pK, pK1, pK2, pK3, p_star, st, F, T);
+  return hipGetLastError();
+}
+
+hipError_t launch_restart_vector(const DevLayout& L, int prec, const void* pK, const float* svec, PRState* st,
+                                 void* q, double* slots, int members, hipStream_t s) {
+  if (L.ntiles == 0) return hipSuccess;
+  const uint32_t* base = reinterpret_cast<const uint32_t*>(L.tiles);
+  const uint32_t stride = sizeof(TileDesc) / 4;
+  const uint32_t* graphs = base + offsetof(TileDesc, graph) / 4;
+  if (prec == 0)
+    hipLaunchKernelGGL(restart_vector_kernel<MF64>, dim3(L.ntiles / kWaves), dim3(kThreads), 0, s, base, stride,
+                       graphs, pK, svec, st, q, slots);
+  else
+    hipLaunchKernelGGL(restart_vector_kernel<MF32>, dim3(L.ntiles / kWaves), dim3(kThreads), 0, s, base, stride,
+                       graphs, pK, svec, st, q, slots);
+  if (hipError_t e = hipGetLastError()) return e;
+  // each member's sum of q into its delta field
+  hipLaunchKernelGGL(pr_finish_kernel, dim3(members), dim3(kThreads), 0, s, st, slots, 0, 0.0, 0, 0, 0);
   return hipGetLastError();
 }
 
@@ -1560,12 +1667,12 @@ hipError_t launch_csr_pr_init(const DevCsr& C, int prec, const void* start, cons
   const uint32_t stride = sizeof(CsrTile) / 4;
   if (prec == 0)
     hipLaunchKernelGGL(pr_init_kernel<MF64>, dim3(C.ntiles / kWaves), dim3(kThreads), 0, s, base, stride, nullptr,
-                       start, tele, p0, z0, outdeg, st, slots);
+                       start, tele, p0, z0, outdeg, st, slots, 0);
   else
     hipLaunchKernelGGL(pr_init_kernel<MF32>, dim3(C.ntiles / kWaves), dim3(kThreads), 0, s, base, stride, nullptr,
-                       start, tele, p0, z0, outdeg, st, slots);
+                       start, tele, p0, z0, outdeg, st, slots, 0);
   if (hipError_t e = hipGetLastError()) return e;
-  hipLaunchKernelGGL(pr_finish_kernel, dim3(1), dim3(kThreads), 0, s, st, slots, 0, 0.0, 0, 0);
+  hipLaunchKernelGGL(pr_finish_kernel, dim3(1), dim3(kThreads), 0, s, st, slots, 0, 0.0, 0, 0, 0);
   return hipGetLastError();
 }
 
@@ -1595,7 +1702,7 @@ hipError_t launch_batch_pr_init(const DevLayout& L, int prec, int k, const void*
   hipError_t e = prec == 0 ? launch_batch_init<MF64>(L, k, start, tele, p0, z0, outdeg, st, slots, s)
                            : launch_batch_init<MF32>(L, k, start, tele, p0, z0, outdeg, st, slots, s);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(pr_finish_kernel, dim3(k), dim3(kThreads), 0, s, st, slots, 0, 0.0, 0, 0);
+  hipLaunchKernelGGL(pr_finish_kernel, dim3(k), dim3(kThreads), 0, s, st, slots, 0, 0.0, 0, 0, 0);
   return hipGetLastError();
 }
 

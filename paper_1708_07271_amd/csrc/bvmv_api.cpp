@@ -129,9 +129,53 @@ struct PRWork {
   }
 };
 
+// Buffers of the learned warm restarts kept with a graph: the 12 network
+// inputs per node (structural columns filled once), the network output, and
+// two iterate snapshots of the iterate type.
+struct LearnWork {
+  int64_t n = 0;
+  int prec = -1;
+  float* F = nullptr;
+  float* s = nullptr;
+  void* t[2] = {nullptr, nullptr};
+  bool struct_ready = false;
+
+  void release() {
+    dev_free(F);
+    dev_free(s);
+    dev_free(t[0]);
+    dev_free(t[1]);
+    F = s = nullptr;
+    t[0] = t[1] = nullptr;
+    n = 0;
+    prec = -1;
+    struct_ready = false;
+  }
+  int ensure(int pr, int64_t nn) {
+    if (n != nn) {
+      release();
+      HIP_TRY(hipMalloc(reinterpret_cast<void**>(&F), size_t(std::max<int64_t>(nn, 1)) * kMlpIn * sizeof(float)));
+      HIP_TRY(hipMalloc(reinterpret_cast<void**>(&s), size_t(std::max<int64_t>(nn, 1)) * sizeof(float)));
+      n = nn;
+    }
+    if (prec != pr) {
+      dev_free(t[0]);
+      dev_free(t[1]);
+      t[0] = t[1] = nullptr;
+      prec = -1;
+      for (int b = 0; b < 2; ++b)
+        HIP_TRY(hipMalloc(&t[b], size_t(std::max<int64_t>(nn, 1)) * elem_size(pr)));
+      prec = pr;
+    }
+    return BVMV_OK;
+  }
+};
+
 struct PROptsResolved {
   double beta, tol;
   int max_iter, prec, chunk, fallback;
+  const bvmv_mlp* mlp;
+  int restart_every, max_restarts;
 };
 
 int resolve_pr_opts(const bvmv_pr_opts* o, PROptsResolved& r) {
@@ -141,8 +185,14 @@ int resolve_pr_opts(const bvmv_pr_opts* o, PROptsResolved& r) {
   r.prec = BVMV_F32_COMP;
   r.chunk = 16;
   r.fallback = 0;
+  r.mlp = nullptr;
+  r.restart_every = 10;
+  r.max_restarts = 3;
   if (o) {
     r.fallback = o->fallback_check;
+    r.mlp = o->mlp;
+    if (o->restart_every) r.restart_every = o->restart_every;
+    if (o->max_restarts) r.max_restarts = o->max_restarts;
     if (o->damping != 0.0 || o->exact_zero_damping) r.beta = o->damping;
     if (o->tol != 0.0) r.tol = o->tol;
     if (o->max_iter) r.max_iter = o->max_iter;
@@ -150,7 +200,8 @@ int resolve_pr_opts(const bvmv_pr_opts* o, PROptsResolved& r) {
     if (o->chunk) r.chunk = o->chunk;
   }
   if (!(r.beta >= 0.0 && r.beta < 1.0) || !(r.tol > 0.0) || r.max_iter < 1 || r.prec < 0 || r.prec > 2 ||
-      r.chunk < 1 || r.chunk > 1024)
+      r.chunk < 1 || r.chunk > 1024 || r.restart_every < 3 || r.restart_every > 100000 || r.max_restarts < 0 ||
+      r.max_restarts > 100000)
     return fail(BVMV_EINVAL, "PageRank option out of range");
   if (r.chunk % 2) ++r.chunk;  // even, so every replay starts from buffer 0
   return BVMV_OK;
@@ -187,11 +238,13 @@ struct bvmv_graph {
   std::vector<uint32_t> tile_offsets;  // ngraphs + 1
   PRWork pr;   // one right-hand side per member
   PRWork prb;  // k right-hand sides
+  LearnWork lw;
   hipStream_t cap = nullptr;
 
   void release_device() {
     pr.release();
     prb.release();
+    lw.release();
     dev_free(d_tiles);
     dev_free(d_info);
     dev_free(d_ns);
@@ -269,69 +322,47 @@ int upload_layout(bvmv_graph* g) {
   return BVMV_OK;
 }
 
-// Launch chunked PageRank on a tile layout, a group or a CSR, for one or k
-// right-hand sides.  `states` holds the members' start states (1/n, slot
-// ranges); p and z hold n_elems elements; `iter` launches one iteration on a
-// stream, `init` the start kernels, `out` writes p_out from the final
-// buffers once every member is done.
-template <class IterFn, class InitFn, class OutFn>
-int run_pagerank(PRWork& w, hipStream_t cap, const PROptsResolved& o, int64_t n_elems, int k,
-                 const std::vector<PRState>& states, int64_t nslots, const void* tele, const void* start,
-                 bvmv_pr_result* res, hipStream_t s, const int32_t* outdeg, IterFn iter, InitFn init, OutFn out) {
-  const int members = int(states.size());
-  if (int rc = w.ensure(o.prec, n_elems, members, nslots)) return rc;
-  if (!outdeg || !w.p[0] || !w.p[1] || !w.z[0] || !w.z[1] || !w.st || !w.slots || !w.h_st)
-    return fail(BVMV_EINVAL, "PageRank working set is incomplete");
-  // arguments of the iteration that reads buffer c % 2 and writes the other
-  auto args = [&](int c) {
-    PRArgs a{};
-    a.p_cur = w.p[c % 2];
-    a.p_new = w.p[(c + 1) % 2];
-    a.z_cur = w.z[c % 2];
-    a.z_new = w.z[(c + 1) % 2];
-    a.tele = tele;
-    a.outdeg = outdeg;
-    a.st = w.st;
-    a.slots = w.slots;
-    a.beta = o.beta;
-    a.tol = o.tol;
-    a.max_iter = o.max_iter;
-    a.buf = (c + 1) % 2;
-    a.members = members;
-    a.k = k;
-    return a;
-  };
-  auto reset = [&](const void* st0) -> int {
-    std::memcpy(w.h_st, states.data(), sizeof(PRState) * size_t(members));
-    HIP_TRY(hipMemcpyAsync(w.st, w.h_st, sizeof(PRState) * size_t(members), hipMemcpyHostToDevice, s));
-    HIP_TRY(init(st0, tele, w.p[0], w.z[0], s));
-    return BVMV_OK;
-  };
-  int used = start ? 1 : 0;
-  if (o.fallback && start && members == 1 && k == 1) {
-    // one eager iteration from each candidate start; keep `start` only if
-    // its first residual is the smaller
-    double r[2] = {0.0, 0.0};
-    for (int cand = 0; cand < 2; ++cand) {
-      if (int rc = reset(cand == 0 ? start : nullptr)) return rc;
-      HIP_TRY(iter(args(0), s));
-      HIP_TRY(hipMemcpyAsync(w.h_st, w.st, sizeof(PRState), hipMemcpyDeviceToHost, s));
-      HIP_TRY(hipStreamSynchronize(s));
-      r[cand] = w.h_st[0].resid;
-    }
-    if (!(r[0] < r[1])) {
-      start = nullptr;
-      used = 0;
-    }
-  }
-  if (int rc = reset(start)) return rc;
+// Arguments of the iteration that reads buffer c % 2 and writes the other.
+PRArgs pr_args(const PRWork& w, const PROptsResolved& o, const void* tele, const int32_t* outdeg, int members, int k,
+               int c) {
+  PRArgs a{};
+  a.p_cur = w.p[c % 2];
+  a.p_new = w.p[(c + 1) % 2];
+  a.z_cur = w.z[c % 2];
+  a.z_new = w.z[(c + 1) % 2];
+  a.tele = tele;
+  a.outdeg = outdeg;
+  a.st = w.st;
+  a.slots = w.slots;
+  a.beta = o.beta;
+  a.tol = o.tol;
+  a.max_iter = o.max_iter;
+  a.buf = (c + 1) % 2;
+  a.members = members;
+  a.k = k;
+  return a;
+}
+
+// Host copy of the members' states (synchronises s).
+int read_states(PRWork& w, int members, hipStream_t s) {
+  HIP_TRY(hipMemcpyAsync(w.h_st, w.st, sizeof(PRState) * size_t(members), hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  return BVMV_OK;
+}
+
+// Replay a captured chunk of o.chunk iterations, starting from buffer 0,
+// until every member is done; the chunk is captured once and kept with the
+// working set while its key holds.
+template <class IterFn>
+int replay_until_done(PRWork& w, hipStream_t cap, const PROptsResolved& o, const void* tele, const int32_t* outdeg,
+                      int members, int k, hipStream_t s, IterFn iter) {
   const bool same = w.exec && w.key_tele == tele && w.key_beta == o.beta && w.key_tol == o.tol &&
                     w.key_max_iter == o.max_iter && w.key_chunk == o.chunk;
   if (!same) {
     w.drop_graph();
     HIP_TRY(hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal));
     hipError_t ce = hipSuccess;
-    for (int c = 0; c < o.chunk && ce == hipSuccess; ++c) ce = iter(args(c), cap);
+    for (int c = 0; c < o.chunk && ce == hipSuccess; ++c) ce = iter(pr_args(w, o, tele, outdeg, members, k, c), cap);
     hipGraph_t gr = nullptr;
     hipError_t ee = hipStreamEndCapture(cap, &gr);
     if (ce != hipSuccess) {
@@ -350,13 +381,17 @@ int run_pagerank(PRWork& w, hipStream_t cap, const PROptsResolved& o, int64_t n_
   const int max_replays = (o.max_iter + o.chunk - 1) / o.chunk + 1;
   for (int rep = 0; rep < max_replays; ++rep) {
     HIP_TRY(hipGraphLaunch(w.exec, s));
-    HIP_TRY(hipMemcpyAsync(w.h_st, w.st, sizeof(PRState) * size_t(members), hipMemcpyDeviceToHost, s));
-    HIP_TRY(hipStreamSynchronize(s));
+    if (int rc = read_states(w, members, s)) return rc;
     bool all = true;
     for (int gI = 0; gI < members; ++gI) all = all && w.h_st[gI].done;
     if (all) break;
   }
-  HIP_TRY(out(w, s));
+  return BVMV_OK;
+}
+
+// Results from the host copy of the states; BVMV_NOT_CONVERGED if a member
+// did not converge.
+int fill_results(const PRWork& w, int members, int used, int rejected, int accepted, bvmv_pr_result* res) {
   int status = BVMV_OK;
   for (int gI = 0; gI < members; ++gI) {
     const PRState& st = w.h_st[gI];
@@ -365,10 +400,54 @@ int run_pagerank(PRWork& w, hipStream_t cap, const PROptsResolved& o, int64_t n_
       res[gI].converged = st.converged;
       res[gI].residual = st.resid;
       res[gI].used_start = used;
+      res[gI].products = st.iter + rejected;
+      res[gI].restarts_accepted = accepted;
+      res[gI].restarts_rejected = rejected;
     }
     if (!st.converged) status = BVMV_NOT_CONVERGED;
   }
   return status;
+}
+
+// Launch chunked PageRank on a tile layout, a group or a CSR, for one or k
+// right-hand sides.  `states` holds the members' start states (1/n, slot
+// ranges); p and z hold n_elems elements; `iter` launches one iteration on a
+// stream, `init` the start kernels, `out` writes p_out from the final
+// buffers once every member is done.
+template <class IterFn, class InitFn, class OutFn>
+int run_pagerank(PRWork& w, hipStream_t cap, const PROptsResolved& o, int64_t n_elems, int k,
+                 const std::vector<PRState>& states, int64_t nslots, const void* tele, const void* start,
+                 bvmv_pr_result* res, hipStream_t s, const int32_t* outdeg, IterFn iter, InitFn init, OutFn out) {
+  const int members = int(states.size());
+  if (int rc = w.ensure(o.prec, n_elems, members, nslots)) return rc;
+  if (!outdeg || !w.p[0] || !w.p[1] || !w.z[0] || !w.z[1] || !w.st || !w.slots || !w.h_st)
+    return fail(BVMV_EINVAL, "PageRank working set is incomplete");
+  auto reset = [&](const void* st0) -> int {
+    std::memcpy(w.h_st, states.data(), sizeof(PRState) * size_t(members));
+    HIP_TRY(hipMemcpyAsync(w.st, w.h_st, sizeof(PRState) * size_t(members), hipMemcpyHostToDevice, s));
+    HIP_TRY(init(st0, tele, w.p[0], w.z[0], s));
+    return BVMV_OK;
+  };
+  int used = start ? 1 : 0;
+  if (o.fallback && start && members == 1 && k == 1) {
+    // one eager iteration from each candidate start; keep `start` only if
+    // its first residual is the smaller
+    double r[2] = {0.0, 0.0};
+    for (int cand = 0; cand < 2; ++cand) {
+      if (int rc = reset(cand == 0 ? start : nullptr)) return rc;
+      HIP_TRY(iter(pr_args(w, o, tele, outdeg, members, k, 0), s));
+      if (int rc = read_states(w, 1, s)) return rc;
+      r[cand] = w.h_st[0].resid;
+    }
+    if (!(r[0] < r[1])) {
+      start = nullptr;
+      used = 0;
+    }
+  }
+  if (int rc = reset(start)) return rc;
+  if (int rc = replay_until_done(w, cap, o, tele, outdeg, members, k, s, iter)) return rc;
+  HIP_TRY(out(w, s));
+  return fill_results(w, members, used, 0, 0, res);
 }
 
 }  // namespace
@@ -383,6 +462,35 @@ struct DevBuf {  // device scratch freed on scope exit
 }  // namespace
 
 // ------------------------------------------------------------ learned warm start
+namespace {
+std::vector<PRState> member_states(const std::vector<int64_t>& offsets, const std::vector<uint32_t>& tile_offsets) {
+  std::vector<PRState> v(offsets.size() - 1);
+  for (size_t gI = 0; gI < v.size(); ++gI) {
+    std::memset(&v[gI], 0, sizeof(PRState));
+    v[gI].inv_n = 1.0 / double(offsets[gI + 1] - offsets[gI]);
+    v[gI].blk_lo = tile_offsets[gI] / kTilesPerBlock;
+    v[gI].blk_hi = tile_offsets[gI + 1] / kTilesPerBlock;
+  }
+  return v;
+}
+
+// p_out rows of each member from the buffer holding its final iterate
+hipError_t copy_member_outputs(const PRWork& w, const std::vector<int64_t>& offsets, int prec, void* p_out,
+                               hipStream_t s) {
+  const size_t es = elem_size(prec);
+  for (size_t gI = 0; gI + 1 < offsets.size(); ++gI) {
+    const PRState& st = w.h_st[gI];
+    const size_t off = size_t(offsets[gI]) * es;
+    const size_t bytes = size_t(offsets[gI + 1] - offsets[gI]) * es;
+    const int fb = st.done ? st.final_buf : 0;
+    if (hipError_t e = hipMemcpyAsync(static_cast<char*>(p_out) + off, static_cast<const char*>(w.p[fb]) + off,
+                                      bytes, hipMemcpyDeviceToDevice, s))
+      return e;
+  }
+  return hipSuccess;
+}
+}  // namespace
+
 struct bvmv_mlp {
   int device = 0;
   float* theta = nullptr;   // FP32 master parameters
@@ -394,6 +502,136 @@ struct bvmv_mlp {
   int64_t part_rows = 0;
   int step = 0;
 };
+
+
+namespace {
+
+// Structural inputs 0..7 of every node into columns 0..7 of F (synchronous:
+// the scratch is freed on return).
+int compute_structural(bvmv_graph* g, float* F, hipStream_t s) {
+  if (g->dec.stats.size() != size_t(g->n)) return fail(BVMV_EINVAL, "row statistics missing");
+  const int64_t n = g->n;
+  if (!g->d_stats) {
+    static_assert(sizeof(RowStats) == 5 * sizeof(uint32_t), "row statistics layout");
+    if (int rc = dev_upload(&g->d_stats, reinterpret_cast<const uint32_t*>(g->dec.stats.data()), size_t(n) * 5))
+      return rc;
+  }
+  DevBuf<int32_t> indeg;
+  DevBuf<float> xb, yb;
+  if (indeg.alloc(size_t(n)) || xb.alloc(2 * size_t(n)) || yb.alloc(2 * size_t(n)))
+    return fail(BVMV_ENOMEM, "feature scratch");
+  float* xd = xb.p;
+  float* xi = xb.p + n;
+  float* yd = yb.p;
+  float* yi = yb.p + n;
+  HIP_TRY(launch_bv_degrees(g->L, indeg.p, s));
+  HIP_TRY(launch_feature_inputs(n, indeg.p, g->d_outdeg, xd, xi, s));
+  HIP_TRY(launch_bv_multiply(g->L, BVMV_F32_COMP, xd, yd, s));
+  HIP_TRY(launch_bv_multiply(g->L, BVMV_F32_COMP, xi, yi, s));
+  HIP_TRY(launch_features(n, indeg.p, g->d_outdeg, g->d_stats, yd, yi, 1.0f / float(std::max(g->R, 1)), F, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  return BVMV_OK;
+}
+
+// Plain PageRank from the uniform vector (or a restart) on a single graph,
+// driven eagerly.  `c` is the buffer index of the current iterate and `since`
+// the number of iterations since the start or the last kept restart; the
+// phase runs until since = K, copying the iterate K - 3 into lw.t[0] and the
+// iterate K - 2 into lw.t[1] just before the buffers they occupy are
+// overwritten, so that at the end p_K, p_{K-1}, p_{K-2}, p_{K-3} are in
+// w.p[c % 2], w.p[(c + 1) % 2], lw.t[1], lw.t[0].  Iterations of a member
+// already done are skipped by the kernels.
+int run_phase(bvmv_graph* g, const PROptsResolved& o, int K, int& c, int& since, hipStream_t s) {
+  PRWork& w = g->pr;
+  LearnWork& lw = g->lw;
+  const size_t bytes = size_t(g->n) * elem_size(o.prec);
+  for (; since < K; ++since, ++c) {
+    if (since == K - 2) HIP_TRY(hipMemcpyAsync(lw.t[0], w.p[(c + 1) % 2], bytes, hipMemcpyDeviceToDevice, s));
+    if (since == K - 1) HIP_TRY(hipMemcpyAsync(lw.t[1], w.p[(c + 1) % 2], bytes, hipMemcpyDeviceToDevice, s));
+    HIP_TRY(launch_bv_pagerank_iter(g->L, o.prec, pr_args(w, o, nullptr, g->d_outdeg, 1, 1, c), s));
+  }
+  return BVMV_OK;
+}
+
+// Working sets and the uniform start state for run_phase.
+int start_learned(bvmv_graph* g, const PROptsResolved& o, hipStream_t s) {
+  PRWork& w = g->pr;
+  const std::vector<PRState> states = member_states(g->offsets, g->tile_offsets);
+  if (int rc = w.ensure(o.prec, g->n, 1, int64_t(g->L.ntiles) / kTilesPerBlock + 1)) return rc;
+  if (int rc = g->lw.ensure(o.prec, g->n)) return rc;
+  std::memcpy(w.h_st, states.data(), sizeof(PRState));
+  HIP_TRY(hipMemcpyAsync(w.st, w.h_st, sizeof(PRState), hipMemcpyHostToDevice, s));
+  HIP_TRY(launch_pr_init(g->L, o.prec, nullptr, nullptr, w.p[0], w.z[0], g->d_outdeg, w.st, w.slots, 1, s));
+  return BVMV_OK;
+}
+
+// PageRank with learned warm restarts (single graph, uniform teleport).
+// After each phase of K iterations: the inputs, the network, the restart
+// vector q and its sum, p' = q / sum as the new iterate with the iteration
+// count kept, and one probe iteration.  The probe's residual r' decides:
+// kept if r' < beta * delta, else the run resumes from p_K (saved in
+// lw.t[1]) and no further restart is tried.  The rest runs as captured chunks.
+int run_learned(bvmv_graph* g, const PROptsResolved& o, const bvmv_mlp* m, void* p_out, bvmv_pr_result* res,
+                hipStream_t s) {
+  PRWork& w = g->pr;
+  LearnWork& lw = g->lw;
+  if (int rc = start_learned(g, o, s)) return rc;
+  if (!lw.struct_ready) {
+    if (int rc = compute_structural(g, lw.F, s)) return rc;
+    lw.struct_ready = true;
+  }
+  const DevLayout& L = g->L;
+  const size_t bytes = size_t(g->n) * elem_size(o.prec);
+  int c = 0, since = 0, accepted = 0, rejected = 0;
+  bool done = false;
+  while (accepted + rejected < o.max_restarts) {
+    if (int rc = run_phase(g, o, o.restart_every, c, since, s)) return rc;
+    if (int rc = read_states(w, 1, s)) return rc;
+    const PRState st = w.h_st[0];
+    if (st.done) {
+      done = true;
+      break;
+    }
+    const double delta = st.resid;
+    HIP_TRY(launch_restart_inputs(L, o.prec, w.p[c % 2], w.p[(c + 1) % 2], lw.t[1], lw.t[0], nullptr, w.st, lw.F,
+                                  nullptr, s));
+    HIP_TRY(launch_mlp_forward(m->theta, m->wq, lw.F, g->n, lw.s, s));
+    HIP_TRY(launch_restart_vector(L, o.prec, w.p[c % 2], lw.s, w.st, lw.t[0], w.slots, 1, s));
+    HIP_TRY(hipMemcpyAsync(lw.t[1], w.p[c % 2], bytes, hipMemcpyDeviceToDevice, s));
+    HIP_TRY(launch_pr_init(L, o.prec, lw.t[0], nullptr, w.p[0], w.z[0], g->d_outdeg, w.st, w.slots, 1, s, 1, st.iter));
+    HIP_TRY(launch_bv_pagerank_iter(L, o.prec, pr_args(w, o, nullptr, g->d_outdeg, 1, 1, 0), s));
+    c = 1;
+    if (int rc = read_states(w, 1, s)) return rc;
+    if (w.h_st[0].resid < o.beta * delta) {
+      ++accepted;
+      since = 1;
+      if (w.h_st[0].done) {
+        done = true;
+        break;
+      }
+    } else {
+      ++rejected;
+      HIP_TRY(launch_pr_init(L, o.prec, lw.t[1], nullptr, w.p[0], w.z[0], g->d_outdeg, w.st, w.slots, 1, s, 0,
+                             st.iter));
+      c = 0;
+      break;
+    }
+  }
+  if (!done && c % 2) {
+    // the captured chunk starts from buffer 0
+    HIP_TRY(launch_bv_pagerank_iter(L, o.prec, pr_args(w, o, nullptr, g->d_outdeg, 1, 1, c), s));
+    if (int rc = read_states(w, 1, s)) return rc;
+    done = w.h_st[0].done;
+  }
+  if (!done) {
+    auto iter = [&](const PRArgs& a, hipStream_t cs) { return launch_bv_pagerank_iter(L, o.prec, a, cs); };
+    if (int rc = replay_until_done(w, g->cap, o, nullptr, g->d_outdeg, 1, 1, s, iter)) return rc;
+  }
+  HIP_TRY(copy_member_outputs(w, g->offsets, o.prec, p_out, s));
+  return fill_results(w, 1, 0, rejected, accepted, res);
+}
+
+}  // namespace
 
 extern "C" {
 
@@ -507,32 +745,6 @@ int bvmv_multiply_batch(bvmv_graph* g, const void* X, void* Y, int k, int64_t ld
 
 // Start states of the members of a single graph or a group (one right-hand
 // side each): 1/n and the member's block range (kTilesPerBlock tiles per block).
-std::vector<PRState> member_states(const std::vector<int64_t>& offsets, const std::vector<uint32_t>& tile_offsets) {
-  std::vector<PRState> v(offsets.size() - 1);
-  for (size_t gI = 0; gI < v.size(); ++gI) {
-    std::memset(&v[gI], 0, sizeof(PRState));
-    v[gI].inv_n = 1.0 / double(offsets[gI + 1] - offsets[gI]);
-    v[gI].blk_lo = tile_offsets[gI] / kTilesPerBlock;
-    v[gI].blk_hi = tile_offsets[gI + 1] / kTilesPerBlock;
-  }
-  return v;
-}
-
-// p_out rows of each member from the buffer holding its final iterate
-hipError_t copy_member_outputs(const PRWork& w, const std::vector<int64_t>& offsets, int prec, void* p_out,
-                               hipStream_t s) {
-  const size_t es = elem_size(prec);
-  for (size_t gI = 0; gI + 1 < offsets.size(); ++gI) {
-    const PRState& st = w.h_st[gI];
-    const size_t off = size_t(offsets[gI]) * es;
-    const size_t bytes = size_t(offsets[gI + 1] - offsets[gI]) * es;
-    const int fb = st.done ? st.final_buf : 0;
-    if (hipError_t e = hipMemcpyAsync(static_cast<char*>(p_out) + off, static_cast<const char*>(w.p[fb]) + off,
-                                      bytes, hipMemcpyDeviceToDevice, s))
-      return e;
-  }
-  return hipSuccess;
-}
 
 int bvmv_degrees(bvmv_graph* g, int32_t* deg, void* stream) {
   if (!g || !deg) return fail(BVMV_EINVAL, "null argument");
@@ -552,6 +764,12 @@ int bvmv_pagerank(bvmv_graph* g, const bvmv_pr_opts* opts, const void* teleport,
   hipStream_t s = static_cast<hipStream_t>(stream);
   DevLayout L = g->L;
   const int prec = o.prec;
+  if (o.mlp) {
+    if (k != 1 || g->ngraphs != 1 || teleport || start)
+      return fail(BVMV_EINVAL, "learned restarts need k = 1, a single graph, uniform teleport and no start vector");
+    if (o.mlp->device != g->device) return fail(BVMV_EINVAL, "graph and network on different devices");
+    return run_learned(g, o, o.mlp, p_out, res, s);
+  }
   if (k == 1) {
     auto iter = [&](const PRArgs& a, hipStream_t cs) { return launch_bv_pagerank_iter(L, prec, a, cs); };
     auto init = [&](const void* st, const void* te, void* p0, void* z0, hipStream_t ss) {
@@ -823,33 +1041,33 @@ void bvmv_csr_free(bvmv_csr* c) {
 int bvmv_features(bvmv_graph* g, float* F, void* stream) {
   if (!g || !F) return fail(BVMV_EINVAL, "null argument");
   if (g->ngraphs != 1) return fail(BVMV_EINVAL, "features need a single graph");
-  if (g->dec.stats.size() != size_t(g->n)) return fail(BVMV_EINVAL, "row statistics missing");
+  DeviceGuard dg(g->device);
+  return compute_structural(g, F, static_cast<hipStream_t>(stream));
+}
+
+int bvmv_restart_sample(bvmv_graph* g, int K, int prec, const void* p_star, float* F, float* T, double* delta,
+                        void* stream) {
+  if (!g || !F || (p_star && !T)) return fail(BVMV_EINVAL, "null argument");
+  if (g->ngraphs != 1) return fail(BVMV_EINVAL, "restart samples need a single graph");
+  if (K < 3 || prec < 0 || prec > 2) return fail(BVMV_EINVAL, "K must be >= 3 and prec valid");
   DeviceGuard dg(g->device);
   hipStream_t s = static_cast<hipStream_t>(stream);
-  const int64_t n = g->n;
-  if (!g->d_stats) {
-    static_assert(sizeof(RowStats) == 5 * sizeof(uint32_t), "row statistics layout");
-    if (dev_upload(&g->d_stats, reinterpret_cast<const uint32_t*>(g->dec.stats.data()), size_t(n) * 5))
-      return BVMV_ENOMEM;
-  }
-  DevBuf<int32_t> indeg;
-  DevBuf<float> xb, yb;
-  if (indeg.alloc(size_t(n)) || xb.alloc(3 * size_t(n)) || yb.alloc(3 * size_t(n)))
-    return fail(BVMV_ENOMEM, "feature scratch");
-  float* xd = xb.p;
-  float* xi = xb.p + n;
-  float* xv = xb.p + 2 * n;
-  float* yd = yb.p;
-  float* yi = yb.p + n;
-  float* yv = yb.p + 2 * n;
-  HIP_TRY(launch_bv_degrees(g->L, indeg.p, s));
-  HIP_TRY(launch_feature_inputs(n, indeg.p, g->d_outdeg, xd, xi, xv, s));
-  HIP_TRY(launch_bv_multiply(g->L, BVMV_F32_COMP, xd, yd, s));
-  HIP_TRY(launch_bv_multiply(g->L, BVMV_F32_COMP, xi, yi, s));
-  HIP_TRY(launch_bv_multiply(g->L, BVMV_F32_COMP, xv, yv, s));
-  HIP_TRY(launch_features(n, indeg.p, g->d_outdeg, g->d_stats, yd, yi, yv, 1.0f / float(std::max(g->R, 1)), F, s));
-  // the scratch is freed on return: wait for the kernels that use it
+  bvmv_pr_opts po{};
+  po.prec = prec;
+  po.max_iter = K + 1;
+  PROptsResolved o;
+  if (int rc = resolve_pr_opts(&po, o)) return rc;
+  if (int rc = compute_structural(g, F, s)) return rc;
+  if (int rc = start_learned(g, o, s)) return rc;
+  int c = 0, since = 0;
+  if (int rc = run_phase(g, o, K, c, since, s)) return rc;
+  if (int rc = read_states(g->pr, 1, s)) return rc;
+  if (g->pr.h_st[0].done) return fail(BVMV_EINVAL, "PageRank converged within K iterations");
+  PRWork& w = g->pr;
+  HIP_TRY(launch_restart_inputs(g->L, prec, w.p[c % 2], w.p[(c + 1) % 2], g->lw.t[1], g->lw.t[0], p_star, w.st, F, T,
+                                s));
   HIP_TRY(hipStreamSynchronize(s));
+  if (delta) *delta = w.h_st[0].resid;
   return BVMV_OK;
 }
 
@@ -925,24 +1143,6 @@ int bvmv_mlp_train_step(bvmv_mlp* m, const float* F, const float* target, int64_
   hipStream_t s = static_cast<hipStream_t>(stream);
   HIP_TRY(launch_mlp_adam(m->theta, m->wq, m->m, m->v, m->grad, lr, 0.9f, 0.999f, 1e-8f, ++m->step, s));
   if (loss) HIP_TRY(hipMemcpyAsync(loss, m->grad + kMlpParams, sizeof(float), hipMemcpyDeviceToDevice, s));
-  return BVMV_OK;
-}
-
-int bvmv_warm_start(bvmv_graph* g, bvmv_mlp* m, int prec, void* p0, void* stream) {
-  if (!g || !m || !p0) return fail(BVMV_EINVAL, "null argument");
-  if (prec < 0 || prec > 2) return fail(BVMV_EINVAL, "bad precision");
-  if (g->device != m->device) return fail(BVMV_EINVAL, "graph and network on different devices");
-  DeviceGuard dg(g->device);
-  hipStream_t s = static_cast<hipStream_t>(stream);
-  const int64_t n = g->n;
-  DevBuf<float> F, sv, mpart;
-  DevBuf<double> spart;
-  if (F.alloc(size_t(n) * kMlpIn) || sv.alloc(size_t(n)) || mpart.alloc(kStartBlocks) || spart.alloc(kStartBlocks))
-    return fail(BVMV_ENOMEM, "warm-start scratch");
-  if (int rc = bvmv_features(g, F.p, stream)) return rc;
-  HIP_TRY(launch_mlp_forward(m->theta, m->wq, F.p, n, sv.p, s));
-  HIP_TRY(launch_start_vector(sv.p, n, mpart.p, spart.p, prec, p0, s));
-  HIP_TRY(hipStreamSynchronize(s));
   return BVMV_OK;
 }
 

@@ -69,8 +69,19 @@ hipError_t launch_bv_multiply(const DevLayout& L, int prec, const void* x, void*
 hipError_t launch_bv_degrees(const DevLayout& L, int32_t* deg, hipStream_t s);
 hipError_t launch_bv_pagerank_iter(const DevLayout& L, int prec, const PRArgs& a, hipStream_t s);
 // z = p / d, dangling mass and state reset for the start vector (tile grid)
+// (normalize: p0 = start / the member's delta field; iter0: the states' iteration count)
 hipError_t launch_pr_init(const DevLayout& L, int prec, const void* start, const void* tele, void* p0, void* z0,
-                          const int32_t* outdeg, PRState* st, double* slots, int members, hipStream_t s);
+                          const int32_t* outdeg, PRState* st, double* slots, int members, hipStream_t s,
+                          int normalize = 0, int32_t iter0 = 0);
+// Warm restart: inputs 8..11 of every node into F (n x 12) and, with p_star,
+// the target into T, from the last four iterates and the states' residuals.
+hipError_t launch_restart_inputs(const DevLayout& L, int prec, const void* pK, const void* pK1, const void* pK2,
+                                 const void* pK3, const void* p_star, const PRState* st, float* F, float* T,
+                                 hipStream_t s);
+// Unnormalised restart vector q from p_K and the network output s; each
+// member's sum of q ends in its state's delta field.
+hipError_t launch_restart_vector(const DevLayout& L, int prec, const void* pK, const float* svec, PRState* st,
+                                 void* q, double* slots, int members, hipStream_t s);
 
 hipError_t launch_csr_multiply(const DevCsr& C, int prec, const void* x, void* y, hipStream_t s);
 hipError_t launch_csr_pagerank_iter(const DevCsr& C, int prec, const PRArgs& a, hipStream_t s);
@@ -94,7 +105,6 @@ constexpr int kMlpIn = 12, kMlpHidden = 64;
 constexpr int kMlpParams = kMlpHidden * kMlpIn + kMlpHidden + kMlpHidden * kMlpHidden + kMlpHidden + kMlpHidden + 1;
 constexpr int kMlpWeights = kMlpHidden * kMlpIn + kMlpHidden * kMlpHidden + kMlpHidden;  // BF16 copies
 constexpr int64_t kMlpMaxBatch = 1 << 20; // feature rows per gradient call
-constexpr int kStartBlocks = 1024;
 // s = MLP(F) for n feature rows (node-major n x 12)
 hipError_t launch_mlp_forward(const float* theta, const uint16_t* wq, const float* F, int64_t n, float* s,
                               hipStream_t st);
@@ -106,13 +116,11 @@ hipError_t launch_mlp_gradient(const float* theta, const uint16_t* wq, const flo
 hipError_t launch_mlp_adam(float* theta, uint16_t* wq, float* m, float* v, const float* grad, float lr, float b1,
                            float b2, float eps, int step, hipStream_t st);
 hipError_t launch_mlp_quantize(const float* theta, uint16_t* wq, hipStream_t st);
+// product inputs of the structural features: d and indeg as floats
 hipError_t launch_feature_inputs(int64_t n, const int32_t* indeg, const int32_t* outdeg, float* xd, float* xi,
-                                 float* xv, hipStream_t st);
+                                 hipStream_t st);
+// structural inputs 0..7 into columns 0..7 of F (n x 12); yd = B d, yi = B indeg
 hipError_t launch_features(int64_t n, const int32_t* indeg, const int32_t* outdeg, const uint32_t* stats,
-                           const float* yd, const float* yi, const float* yv, float inv_r, float* F, hipStream_t st);
-// p0 = exp(s - max s) / sum (prec 0: double p0, else float); mpart: kStartBlocks floats,
-// spart: kStartBlocks doubles
-hipError_t launch_start_vector(const float* s, int64_t n, float* mpart, double* spart, int prec, void* p0,
-                               hipStream_t st);
+                           const float* yd, const float* yi, float inv_r, float* F, hipStream_t st);
 
 }  // namespace bvmv

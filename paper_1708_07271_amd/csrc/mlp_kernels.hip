@@ -380,17 +380,16 @@ __global__ void __launch_bounds__(kThreads) mlp_quantize_kernel(const float* __r
   else if (p >= oW3 && p < oB3) wq[qW3 + (p - oW3)] = bf16_bits(theta[p]);
 }
 
-// ----------------------------------------------------------------- features
-// Feature row of node v (see the oracle's definition):
-//  log1p(indeg), log1p(d), depth/R, [d = 0], log1p(skipped), log1p(intervals),
-//  log1p(interval length), log1p(residuals), log1p(Bd / max(indeg,1)),
-//  log1p(B indeg / max(indeg,1)), log1p(n B invd), log n.
+// ------------------------------------------------------- structural inputs
+// Columns 0..7 of node v's input row: log1p(indeg), log1p(d), depth / R,
+// [d = 0], log1p(intervals), log1p(residuals), log1p(B d / max(indeg, 1)),
+// log1p(B indeg / max(indeg, 1)).  stats holds 5 u32 per row: depth, skipped
+// reference entries, intervals, interval length, residuals.
 __global__ void __launch_bounds__(kThreads) features_kernel(int64_t n, const int32_t* __restrict__ indeg,
                                                             const int32_t* __restrict__ outdeg,
                                                             const uint32_t* __restrict__ stats,
                                                             const float* __restrict__ yd,
-                                                            const float* __restrict__ yi,
-                                                            const float* __restrict__ yv, float inv_r,
+                                                            const float* __restrict__ yi, float inv_r,
                                                             float* __restrict__ F) {
   for (int64_t v = int64_t(blockIdx.x) * kThreads + threadIdx.x; v < n; v += int64_t(gridDim.x) * kThreads) {
     const float ind = float(indeg[v]), d = float(outdeg[v]);
@@ -401,95 +400,21 @@ __global__ void __launch_bounds__(kThreads) features_kernel(int64_t n, const int
     f[1] = log1pf(d);
     f[2] = float(st[0]) * inv_r;
     f[3] = d == 0.0f ? 1.0f : 0.0f;
-    f[4] = log1pf(float(st[1]));
-    f[5] = log1pf(float(st[2]));
-    f[6] = log1pf(float(st[3]));
-    f[7] = log1pf(float(st[4]));
-    f[8] = log1pf(yd[v] / den);
-    f[9] = log1pf(yi[v] / den);
-    f[10] = log1pf(float(n) * yv[v]);
-    f[11] = logf(float(n));
+    f[4] = log1pf(float(st[2]));
+    f[5] = log1pf(float(st[4]));
+    f[6] = log1pf(yd[v] / den);
+    f[7] = log1pf(yi[v] / den);
   }
 }
 
-// product inputs of the features: d, indeg and 1/d (0 for d = 0) as floats
+// product inputs of the structural features: d and indeg as floats
 __global__ void __launch_bounds__(kThreads) feature_inputs_kernel(int64_t n, const int32_t* __restrict__ indeg,
                                                                   const int32_t* __restrict__ outdeg,
-                                                                  float* __restrict__ xd, float* __restrict__ xi,
-                                                                  float* __restrict__ xv) {
+                                                                  float* __restrict__ xd, float* __restrict__ xi) {
   for (int64_t v = int64_t(blockIdx.x) * kThreads + threadIdx.x; v < n; v += int64_t(gridDim.x) * kThreads) {
-    const int32_t d = outdeg[v];
-    xd[v] = float(d);
+    xd[v] = float(outdeg[v]);
     xi[v] = float(indeg[v]);
-    xv[v] = d > 0 ? 1.0f / float(d) : 0.0f;
   }
-}
-
-// ---------------------------------------------------------------- warm start
-// p0 = exp(s - max s) / sum: block maxima and sums, then one block folds them
-// in a fixed order.
-__device__ __forceinline__ float block_max(float a, float* s_red) {
-  for (int d = 32; d >= 1; d >>= 1) a = fmaxf(a, __shfl_xor(a, d, 64));
-  if ((threadIdx.x & 63) == 0) s_red[threadIdx.x >> 6] = a;
-  __syncthreads();
-  float r = s_red[0];
-  for (int w = 1; w < kThreads / 64; ++w) r = fmaxf(r, s_red[w]);
-  __syncthreads();
-  return r;
-}
-__device__ __forceinline__ double block_sum(double a, double* s_red) {
-  for (int d = 32; d >= 1; d >>= 1) a += __shfl_xor(a, d, 64);
-  if ((threadIdx.x & 63) == 0) s_red[threadIdx.x >> 6] = a;
-  __syncthreads();
-  double r = s_red[0];
-  for (int w = 1; w < kThreads / 64; ++w) r += s_red[w];
-  __syncthreads();
-  return r;
-}
-
-__global__ void __launch_bounds__(kThreads) start_max_kernel(const float* __restrict__ s, int64_t n,
-                                                             float* __restrict__ part) {
-  __shared__ float s_red[kThreads / 64];
-  float m = -INFINITY;
-  for (int64_t v = int64_t(blockIdx.x) * kThreads + threadIdx.x; v < n; v += int64_t(gridDim.x) * kThreads)
-    m = fmaxf(m, s[v]);
-  m = block_max(m, s_red);
-  if (threadIdx.x == 0) part[blockIdx.x] = m;
-}
-
-__global__ void __launch_bounds__(kThreads) start_sum_kernel(const float* __restrict__ s, int64_t n,
-                                                             const float* __restrict__ mpart, int nparts,
-                                                             double* __restrict__ spart) {
-  __shared__ float s_m[kThreads / 64];
-  __shared__ double s_red[kThreads / 64];
-  float m = -INFINITY;
-  for (int p = threadIdx.x; p < nparts; p += kThreads) m = fmaxf(m, mpart[p]);
-  m = block_max(m, s_m);
-  double acc = 0.0;
-  for (int64_t v = int64_t(blockIdx.x) * kThreads + threadIdx.x; v < n; v += int64_t(gridDim.x) * kThreads)
-    acc += double(expf(s[v] - m));
-  acc = block_sum(acc, s_red);
-  if (threadIdx.x == 0) spart[blockIdx.x] = acc;
-}
-
-template <class X>
-__global__ void __launch_bounds__(kThreads) start_write_kernel(const float* __restrict__ s, int64_t n,
-                                                               const float* __restrict__ mpart,
-                                                               const double* __restrict__ spart, int nparts,
-                                                               X* __restrict__ p0) {
-  __shared__ float s_m[kThreads / 64];
-  __shared__ double s_red[kThreads / 64];
-  float m = -INFINITY;
-  double tot = 0.0;
-  for (int p = threadIdx.x; p < nparts; p += kThreads) {
-    m = fmaxf(m, mpart[p]);
-    tot += spart[p];
-  }
-  m = block_max(m, s_m);
-  tot = block_sum(tot, s_red);
-  const double inv = 1.0 / tot;
-  for (int64_t v = int64_t(blockIdx.x) * kThreads + threadIdx.x; v < n; v += int64_t(gridDim.x) * kThreads)
-    p0[v] = X(double(expf(s[v] - m)) * inv);
 }
 
 int grid_for(int64_t items, int cap) { return int(std::max<int64_t>(1, std::min<int64_t>((items + kThreads - 1) / kThreads, cap))); }
@@ -533,31 +458,16 @@ hipError_t launch_mlp_quantize(const float* theta, uint16_t* wq, hipStream_t st)
 }
 
 hipError_t launch_feature_inputs(int64_t n, const int32_t* indeg, const int32_t* outdeg, float* xd, float* xi,
-                                 float* xv, hipStream_t st) {
+                                 hipStream_t st) {
   hipLaunchKernelGGL(feature_inputs_kernel, dim3(grid_for(n, 4096)), dim3(kThreads), 0, st, n, indeg, outdeg, xd,
-                     xi, xv);
+                     xi);
   return hipGetLastError();
 }
 
 hipError_t launch_features(int64_t n, const int32_t* indeg, const int32_t* outdeg, const uint32_t* stats,
-                           const float* yd, const float* yi, const float* yv, float inv_r, float* F,
-                           hipStream_t st) {
+                           const float* yd, const float* yi, float inv_r, float* F, hipStream_t st) {
   hipLaunchKernelGGL(features_kernel, dim3(grid_for(n, 4096)), dim3(kThreads), 0, st, n, indeg, outdeg, stats, yd,
-                     yi, yv, inv_r, F);
-  return hipGetLastError();
-}
-
-hipError_t launch_start_vector(const float* s, int64_t n, float* mpart, double* spart, int prec, void* p0,
-                               hipStream_t st) {
-  const int nb = grid_for(n, kStartBlocks);
-  hipLaunchKernelGGL(start_max_kernel, dim3(nb), dim3(kThreads), 0, st, s, n, mpart);
-  hipLaunchKernelGGL(start_sum_kernel, dim3(nb), dim3(kThreads), 0, st, s, n, mpart, nb, spart);
-  if (prec == 0)
-    hipLaunchKernelGGL(start_write_kernel<double>, dim3(nb), dim3(kThreads), 0, st, s, n, mpart, spart, nb,
-                       static_cast<double*>(p0));
-  else
-    hipLaunchKernelGGL(start_write_kernel<float>, dim3(nb), dim3(kThreads), 0, st, s, n, mpart, spart, nb,
-                       static_cast<float*>(p0));
+                     yi, inv_r, F);
   return hipGetLastError();
 }
 

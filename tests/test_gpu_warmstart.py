@@ -1,16 +1,19 @@
-"""Learned warm start on the device against the CPU oracle: features, the MLP
-forward and gradient (MFMA kernels), Adam, the start vector, and end to end
-PageRank from a trained network with the fallback check."""
+"""Learned warm restarts on the device against the CPU oracle: structural
+inputs, restart samples (trajectory inputs and targets), the MLP forward and
+gradient (MFMA kernels), Adam, and PageRank with restarts: exact agreement
+with the plain method for a zero network and for a rejected restart, parity
+with the oracle's restarted run, and the gain of a trained network."""
 import numpy as np
 import pytest
 import torch
 
 import bvinputs as B
-from oracle import bvdecode, mlp, pagerank
+from oracle import bvdecode, mlp, pagerank, restart
 from oracle import features as feat
 
 pytestmark = pytest.mark.gpu
 DEV = torch.device("cuda:0")
+F64, F32C = 0, 2
 
 
 @pytest.fixture(scope="module")
@@ -28,22 +31,64 @@ def _theta(seed):
     return (mlp.init_params(seed) + rng.normal(0, 0.05, mlp.NPARAM)).astype(np.float32).astype(np.float64)
 
 
+def _decoded(enc):
+    rowptr, col, refs, hdr, st = bvdecode.decode(enc.data, with_stats=True)
+    return rowptr, col, feat.structural(rowptr, col, st, hdr["R"])
+
+
 def test_features_match_oracle(P):
     g = B.web_graph(20_000, 15.0, 31)
     enc = B.encode(g)
     G = P.bvmv_load(enc.data)
-    F = torch.empty(g.n, P.NFEAT, device=DEV)
+    F = torch.full((g.n, P.NFEAT), 7.0, device=DEV)
     P.bvmv_features(G, F)
     torch.cuda.synchronize()
-    rowptr, col, refs, hdr, st = bvdecode.decode(enc.data, with_stats=True)
-    Fo = feat.features(rowptr, col, st, hdr["R"])
+    _, _, Fo = _decoded(enc)
     Fg = F.cpu().numpy().astype(np.float64)
-    # integer-derived features agree to float32 rounding of the logarithm; the
-    # three product features to the product's FP32 tolerance
-    assert np.max(np.abs(Fg[:, :8] - Fo[:, :8])) < 2e-6
-    assert np.max(np.abs(Fg[:, 8:11] - Fo[:, 8:11]) / (1 + np.abs(Fo[:, 8:11]))) < 2e-5
-    assert np.max(np.abs(Fg[:, 11] - Fo[:, 11])) < 2e-6
+    # integer-derived inputs agree to float32 rounding of the logarithm; the two
+    # product inputs to the product's FP32 tolerance; columns 8..11 untouched
+    assert np.max(np.abs(Fg[:, :6] - Fo[:, :6])) < 2e-6
+    assert np.max(np.abs(Fg[:, 6:8] - Fo[:, 6:8]) / (1 + np.abs(Fo[:, 6:8]))) < 2e-5
+    assert np.all(Fg[:, 8:] == 7.0)
 
+
+@pytest.mark.parametrize("prec,K", [(F64, 6), (F64, 10), (F32C, 10)])
+def test_restart_sample_matches_oracle(P, prec, K):
+    g = B.web_graph(30_000, 15.0, 32)
+    enc = B.encode(g)
+    G = P.bvmv_load(enc.data)
+    rowptr, col, Fs = _decoded(enc)
+    its = [pagerank.pagerank(rowptr, col, 0.85, iters=k)[0] for k in (K - 3, K - 2, K - 1, K)]
+    Tr, delta = feat.trajectory(its[3], its[2], its[1], its[0])
+    ps = pagerank.pagerank(rowptr, col, 0.85, tol=1e-13, max_iter=5000)[0]
+    dt = torch.float64 if prec == F64 else torch.float32
+    F = torch.empty(g.n, P.NFEAT, device=DEV)
+    T = torch.empty(g.n, device=DEV)
+    d = P.bvmv_restart_sample(G, K, F, T, torch.from_numpy(ps).to(dt).to(DEV), prec=prec)
+    torch.cuda.synchronize()
+    Fg = F.cpu().numpy().astype(np.float64)
+    Tg = T.cpu().numpy().astype(np.float64)
+    To = feat.target(ps, its[3], delta)
+    if prec == F64:
+        assert abs(d - delta) < 1e-12 * delta
+        assert np.max(np.abs(Fg[:, 8:] - Tr) / (1 + np.abs(Tr))) < 2e-6    # FP32 storage of the inputs
+        assert np.max(np.abs(Tg - To) / (1 + np.abs(To))) < 2e-6
+    else:
+        # FP32 iterates: delta to 1e-5, the step differences to what FP32
+        # rounding of p (~6e-8 relative) leaves of a step that is ~1e-3 of p
+        assert abs(d - delta) < 1e-5 * delta
+        assert np.max(np.abs(Fg[:, 8] - Tr[:, 0])) < 1e-5
+        assert np.max(np.abs(Fg[:, 9:] - Tr[:, 1:]) / (1 + np.abs(Tr[:, 1:]))) < 5e-3
+        assert np.max(np.abs(Tg - To) / (1 + np.abs(To))) < 5e-3
+    assert np.max(np.abs(Fg[:, :6] - Fs[:, :6])) < 2e-6
+
+
+def test_restart_sample_rejects_converged(P):
+    # uniform is the fixed point of the complete graph: converged at once
+    G = P.bvmv_load(B.encode(B.complete_graph(50)).data)
+    F = torch.empty(50, P.NFEAT, device=DEV)
+    with pytest.raises(P.BvmvError):
+        P.bvmv_restart_sample(G, 5, F)
 
 @pytest.mark.parametrize("n", [32, 1000, 4099])
 def test_mlp_forward_matches_oracle(P, n):
@@ -110,16 +155,80 @@ def test_adam_step_matches_oracle(P):
     assert np.max(np.abs(s.cpu().numpy() - so) / (1 + np.abs(so))) < 1e-3
 
 
-def _train(P, graphs, steps, seed=1):
-    """Train on (features, log(n p*)) of the given loaded graphs."""
+def _zero_theta():
+    return np.zeros(mlp.NPARAM)
+
+
+def _const_theta(b3):
+    th = np.zeros(mlp.NPARAM)
+    th[-1] = b3
+    return th
+
+
+@pytest.mark.parametrize("prec", [F64, F32C])
+def test_learned_zero_network_follows_plain(P, prec):
+    g = B.web_graph(40_000, 15.0, 51)
+    G = P.bvmv_load(B.encode(g).data)
+    dt = torch.float64 if prec == F64 else torch.float32
+    pp = torch.empty(g.n, dtype=dt, device=DEV)
+    rp = P.bvmv_pagerank_detail(G, pp, prec=prec)[0]
+    m = P.bvmv_mlp_create(_zero_theta())
+    pl = torch.empty(g.n, dtype=dt, device=DEV)
+    rl = P.bvmv_pagerank_detail(G, pl, prec=prec, mlp=m)[0]
+    # s = 0: each restart is p_K divided by its own sum, accepted
+    assert rl["converged"] and rl["restarts_accepted"] == 3 and rl["restarts_rejected"] == 0
+    assert abs(rl["iters"] - rp["iters"]) <= (0 if prec == F64 else 1)
+    assert rl["products"] == rl["iters"]
+    tol = 1e-12 if prec == F64 else 2e-6
+    assert float(((pl.double() - pp.double()).abs() / pp.double()).max()) < tol
+
+
+@pytest.mark.parametrize("prec", [F64, F32C])
+def test_learned_rejected_restart_is_plain_run(P, prec):
+    g = B.web_graph(40_000, 15.0, 52)
+    G = P.bvmv_load(B.encode(g).data)
+    dt = torch.float64 if prec == F64 else torch.float32
+    pp = torch.empty(g.n, dtype=dt, device=DEV)
+    rp = P.bvmv_pagerank_detail(G, pp, prec=prec)[0]
+    m = P.bvmv_mlp_create(_const_theta(1e6))
+    pl = torch.empty(g.n, dtype=dt, device=DEV)
+    rl = P.bvmv_pagerank_detail(G, pl, prec=prec, mlp=m)[0]
+    # a wild correction fails the probe once; the run resumes from p_K itself
+    assert rl["restarts_accepted"] == 0 and rl["restarts_rejected"] == 1
+    assert rl["iters"] == rp["iters"] and rl["products"] == rp["iters"] + 1
+    assert torch.equal(pl, pp)
+
+
+def test_learned_argument_errors(P):
+    g = B.web_graph(5000, 10.0, 53)
+    G = P.bvmv_load(B.encode(g).data)
+    m = P.bvmv_mlp_create(_zero_theta())
+    p = torch.empty(g.n, device=DEV)
+    with pytest.raises(P.BvmvError):
+        P.bvmv_pagerank_detail(G, p, mlp=m, restart_every=2)
+    with pytest.raises(P.BvmvError):
+        P.bvmv_pagerank_detail(G, p, mlp=m, start=torch.full((g.n,), 1.0 / g.n, device=DEV))
+    with pytest.raises(P.BvmvError):
+        P.bvmv_pagerank_detail(G, p, mlp=m, teleport=torch.full((g.n,), 1.0 / g.n, device=DEV))
+    with pytest.raises(P.BvmvError):
+        P.bvmv_pagerank_detail(G, torch.empty(g.n * 2, device=DEV), mlp=m, k=2)
+    grp = P.bvmv_group([G, G])
+    with pytest.raises(P.BvmvError):
+        P.bvmv_pagerank_detail(grp, torch.empty(2 * g.n, device=DEV), mlp=m)
+
+
+def _train(P, graphs, steps, K=10, seed=1):
+    """Train on restart samples (inputs after K plain iterations, targets from
+    the method's own converged PageRank in FP64) of the given loaded graphs."""
     Fs, Ts = [], []
     for G, n in graphs:
+        ps = torch.empty(n, dtype=torch.float64, device=DEV)
+        P.bvmv_pagerank(G, ps, tol=1e-12, max_iter=5000, prec=F64)
         F = torch.empty(n, P.NFEAT, device=DEV)
-        P.bvmv_features(G, F)
-        p = torch.empty(n, device=DEV)
-        P.bvmv_pagerank(G, p)
+        T = torch.empty(n, device=DEV)
+        P.bvmv_restart_sample(G, K, F, T, ps.float(), prec=F32C)
         Fs.append(F)
-        Ts.append(torch.log(p * n))
+        Ts.append(T)
     F = torch.cat(Fs)
     T = torch.cat(Ts).contiguous()
     m = P.bvmv_mlp_create(mlp.init_params(seed))
@@ -134,31 +243,46 @@ def _train(P, graphs, steps, seed=1):
     return m, first, float(loss.item())
 
 
-def test_warm_start_end_to_end(P):
-    train = [B.web_graph(n, 15.0, 40 + i) for i, n in enumerate((30_000, 50_000, 40_000))]
+@pytest.fixture(scope="module")
+def trained(P):
+    train = [B.web_graph(n, 15.0, 40 + i) for i, n in enumerate((60_000, 90_000, 75_000, 50_000))]
     Gs = [(P.bvmv_load(B.encode(g).data), g.n) for g in train]
-    m, l0, l1 = _train(P, Gs, 400)
-    assert l1 < 0.5 * l0
-    g = B.web_graph(60_000, 15.0, 77)
+    return _train(P, Gs, 1500)
+
+
+def test_training_reduces_loss(P, trained):
+    m, l0, l1 = trained
+    assert l1 < 0.3 * l0
+
+
+def test_learned_matches_oracle_restarted_run(P, trained):
+    m = trained[0]
+    theta = P.bvmv_mlp_params(m).astype(np.float64)
+    g = B.web_graph(20_000, 15.0, 61)
+    enc = B.encode(g)
+    G = P.bvmv_load(enc.data)
+    rowptr, col, Fs = _decoded(enc)
+    pl = torch.empty(g.n, dtype=torch.float64, device=DEV)
+    rl = P.bvmv_pagerank_detail(G, pl, prec=F64, mlp=m)[0]
+    po, to, ro, oko, info = restart.pagerank_restarted(
+        rowptr, col, lambda F: mlp.forward(theta, F.astype(np.float32), quantize=True)[0], Fs)
+    assert rl["converged"] and oko
+    # the decisions agree; the BF16 network's order of summation may move the
+    # stopping iteration by one
+    assert (rl["restarts_accepted"], rl["restarts_rejected"]) == (info["accepted"], info["rejected"])
+    assert abs(rl["iters"] - to) <= 1
+    assert float(np.abs(pl.cpu().numpy() - po).sum()) < 2 * (0.85 / 0.15) * 1e-6
+
+
+def test_learned_restarts_gain(P, trained):
+    m = trained[0]
+    g = B.web_graph(200_000, 15.0, 77)
     G = P.bvmv_load(B.encode(g).data)
-    p0 = torch.empty(g.n, device=DEV)
-    P.bvmv_warm_start(G, m, p0)
-    torch.cuda.synchronize()
-    assert abs(float(p0.double().sum()) - 1.0) < 1e-5 and float(p0.min()) > 0
     pu = torch.empty(g.n, device=DEV)
-    (iu, oku, ru), = P.bvmv_pagerank(G, pu)
+    ru = P.bvmv_pagerank_detail(G, pu)[0]
     pw = torch.empty(g.n, device=DEV)
-    rw = P.bvmv_pagerank_detail(G, pw, start=p0, fallback_check=1)[0]
-    assert oku and rw["converged"] and rw["used_start"] == 1
-    assert rw["iters"] < iu
-    # same fixed point within the L1 contraction bound (beta / (1 - beta)) * tol, twice
+    rw = P.bvmv_pagerank_detail(G, pw, mlp=m)[0]
+    assert ru["converged"] and rw["converged"] and rw["restarts_accepted"] >= 1
+    # at least 15% fewer products than the plain method, same fixed point
+    assert rw["products"] <= 0.85 * ru["products"], (rw, ru)
     assert float((pw.double() - pu.double()).abs().sum()) < 2 * (0.85 / 0.15) * 1e-6 + 1e-5
-    # against the oracle started from the same warm vector, iteration-matched
-    p_ref = pagerank.pagerank(g.rowptr, g.col, 0.85, start=p0.cpu().numpy().astype(np.float64),
-                              iters=rw["iters"])[0]
-    assert np.max(np.abs(pw.cpu().numpy() - p_ref) / p_ref) < 1e-5
-    # a bad start is rejected by the fallback check
-    bad = torch.zeros(g.n, device=DEV)
-    bad[0] = 1.0
-    rb = P.bvmv_pagerank_detail(G, pw, start=bad, fallback_check=1)[0]
-    assert rb["used_start"] == 0 and rb["iters"] == iu
