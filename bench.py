@@ -132,6 +132,76 @@ def bench_batch(args, B, P, np, torch, dev):
     print(json.dumps(out), flush=True)
 
 
+def bench_ragged(args, B, P, np, torch, dev):
+    """Ragged batch: 48 web-like graphs, n_g = round(10^(4 + 2 u_g)) with u_g
+    uniform from seed 999, mean out-degree 20, graph seeds 1000 + g.  Global
+    PageRank (beta 0.85, uniform teleport, L1 1e-6) of every graph, timed as
+    48 separate calls and as one group (one launch sequence for all members),
+    each with the fixed default layout and with autotuned layouts; plus one
+    product over the whole group.  Median of 3 after a warm-up call."""
+    rng = np.random.default_rng(999)
+    sizes = np.round(10 ** (4 + 2 * rng.random(48))).astype(np.int64)
+    t0 = time.perf_counter()
+    encs = [B.encode(B.web_graph(int(n), 20.0, 1000 + i)).data for i, n in enumerate(sizes)]
+    log("ragged: %d graphs, n in [%d, %d], sum n %d (%.1fs)" % (len(sizes), sizes.min(), sizes.max(), sizes.sum(),
+                                                                 time.perf_counter() - t0))
+    t0 = time.perf_counter()
+    fixed = [P.bvmv_load(e) for e in encs]
+    t_fixed = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    auto = [P.bvmv_load(e, autotune=1) for e in encs]
+    t_auto = time.perf_counter() - t0
+    picks = {}
+    for G in auto:
+        info = P.bvmv_get_info(G)
+        key = "%dx%d" % (info["tile_rows"], info["window_cap"])
+        picks[key] = picks.get(key, 0) + 1
+    log("load: fixed %.2fs, autotuned %.2fs, picks %s" % (t_fixed, t_auto, picks))
+    m_total = sum(P.bvmv_get_info(G)["m"] for G in fixed)
+
+    def timed(fn, reps=3):
+        fn()
+        ts = []
+        for _ in range(reps):
+            torch.cuda.synchronize()
+            t = time.perf_counter()
+            r = fn()
+            torch.cuda.synchronize()
+            ts.append(time.perf_counter() - t)
+        return r, float(np.median(ts))
+
+    outs = [torch.empty(int(n), device=dev) for n in sizes]
+
+    def solo(Gs):
+        return [P.bvmv_pagerank_detail(G, o)[0] for G, o in zip(Gs, outs)]
+
+    res = {}
+    for name, Gs in (("fixed", fixed), ("autotuned", auto)):
+        r, t = timed(lambda: solo(Gs))
+        res["solo_" + name] = {"seconds": t, "max_iters": max(x["iters"] for x in r),
+                               "converged": all(x["converged"] for x in r)}
+        grp = P.bvmv_group(Gs)
+        pg = torch.empty(int(sizes.sum()), device=dev)
+        r, t = timed(lambda: P.bvmv_pagerank_detail(grp, pg))
+        offs = P.bvmv_group_offsets(grp)
+        solo(Gs)
+        diff = max(float((pg[offs[i]:offs[i + 1]] - outs[i]).abs().max()) for i in range(len(Gs)))
+        x = torch.rand(int(sizes.sum()), device=dev, generator=torch.Generator(device=dev).manual_seed(5))
+        y = torch.empty_like(x)
+        ms = time_launches(lambda: P.bvmv_multiply(grp, x, y), 50, 5, torch)
+        res["group_" + name] = {"seconds": t, "max_iters": max(x_["iters"] for x_ in r),
+                                "converged": all(x_["converged"] for x_ in r), "max_abs_diff_vs_solo": diff,
+                                "product_ms": ms, "product_edges_per_s": m_total / (ms * 1e-3)}
+        log("%s: solo %.4fs, group %.4fs (diff %.2e), group product %.4f ms"
+            % (name, res["solo_" + name]["seconds"], t, diff, ms))
+    out = {"mode": "ragged-batch", "graphs": len(sizes), "sum_n": int(sizes.sum()), "sum_m": int(m_total),
+           "n_min": int(sizes.min()), "n_max": int(sizes.max()), "dtype": "f32 two-sum compensated",
+           "load_seconds_fixed": t_fixed, "load_seconds_autotuned": t_auto, "autotune_picks": picks, **res,
+           "speedup_group_vs_solo_fixed": res["solo_fixed"]["seconds"] / res["group_fixed"]["seconds"],
+           "speedup_group_autotuned_vs_solo_fixed": res["solo_fixed"]["seconds"] / res["group_autotuned"]["seconds"]}
+    print(json.dumps(out), flush=True)
+
+
 def bench_warm(args, B, P, np, torch, dev):
     """Learned warm restarts: restart samples (the 12 inputs after K = 10 plain
     iterations from the uniform vector, and the target n (p* - p_K) / delta
@@ -139,7 +209,7 @@ def bench_warm(args, B, P, np, torch, dev):
     log-uniform in [1e5, 1e6], mean degree 20, graph seeds 2000 + i), the
     network trained on the device (Adam, batches of 8192 nodes, network seed
     4000, cosine learning rate), then PageRank of an unseen graph (seed 3000)
-    to L1 1e-6: plain, with learned restarts (every 10 iterations, at most 3),
+    to L1 1e-6: plain, with learned restarts (every 10 iterations, at most 2),
     and with a zero network (every restart accepted and the identity: the
     restart overhead alone).  Each PageRank is timed end to end, median of 3;
     the learned run's first call, which also computes the structural inputs
@@ -239,6 +309,8 @@ def main():
     ap.add_argument("--warm-start", action="store_true",
                     help="learned warm restarts: train the network on generated graphs, then PageRank of an "
                          "unseen graph with restarts against the plain method")
+    ap.add_argument("--ragged", action="store_true",
+                    help="ragged batch of 48 graphs: solo against grouped PageRank, fixed against autotuned layouts")
     ap.add_argument("--warm-graphs", type=int, default=200)
     ap.add_argument("--warm-steps", type=int, default=3000)
     ap.add_argument("--warm-test-n", type=int, default=5_000_000)
@@ -274,6 +346,8 @@ def main():
         return bench_batch(args, B, P, np, torch, dev)
     if args.warm_start:
         return bench_warm(args, B, P, np, torch, dev)
+    if args.ragged:
+        return bench_ragged(args, B, P, np, torch, dev)
     t0 = time.perf_counter()
     g = B.workload_graph(args.workload)
     enc = B.encode(g)

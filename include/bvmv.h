@@ -66,7 +66,12 @@ typedef struct {
   int long_row_bytes;    /* rows staging more than this are summed by the whole wave (0 = stage_bytes/2) */
   int interval_mode;     /* 0 = interval sums from a per-tile prefix of x, P[s+len] - P[s] (default);
                             1 = intervals summed entry by entry from the staged x window */
-  int autotune;          /* 1 = time candidate layouts at load and keep the fastest */
+  int autotune;          /* 1 = build and time candidate layouts at load (tile_rows, window_cap and
+                            stage_bytes among six settings, FP32 two-sum product, 20 launches
+                            each) and keep the fastest; the choice is remembered for the rest
+                            of the process per size bucket (floor(log2 n), mean degree).  The
+                            options' tile_rows, window_cap, stage_bytes, long_row_bytes are then
+                            ignored */
   int keep_lists;        /* 1 = keep the decoded lists on the host (export, CSR baseline) */
   int nthreads;          /* host decode / layout threads (0 = hardware concurrency, max 16) */
   uint64_t device_mem_budget;  /* bytes; 0 = unlimited.  Layout larger than this -> BVMV_ENOMEM */
@@ -113,7 +118,7 @@ typedef struct {
                               graph, uniform teleport, no start vector; see the learned
                               section below) */
   int restart_every;       /* K >= 3: a restart after every K iterations (0 = default 10) */
-  int max_restarts;        /* restarts to try (0 = default 3); the first rejected one ends them */
+  int max_restarts;        /* restarts to try (0 = default 2); the first rejected one ends them */
 } bvmv_pr_opts;
 
 typedef struct {
@@ -169,6 +174,8 @@ typedef struct {
   int tile_rows, window_cap, stage_bytes, long_row_bytes, interval_mode;
   int max_level;            /* deepest reuse level in the layout (<= R) */
   int ngraphs;              /* 1, or the member count of a group */
+  int autotuned;            /* 0: layout from the options; 1: chosen by timing candidate layouts at
+                               load; 2: the autotuner's earlier choice for this size bucket */
 } bvmv_info;
 int bvmv_get_info(const bvmv_graph* g, bvmv_info* out);
 

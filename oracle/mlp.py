@@ -14,7 +14,9 @@ Its defined arithmetic, which the device kernels follow:
     accumulation's own rounding; biases and GELU apply to the sums;
   - z1 = W1 bf(x) + b1, h1 = gelu(z1); z2 = W2 bf(h1) + b2, h2 = gelu(z2);
     s = w3 . h2 + b3 (the last layer takes h2 unrounded);
-  - gelu(z) = z Phi(z), Phi the standard normal CDF (via erf);
+  - gelu(z) = z sigma(1.702 z), sigma the logistic function: the sigmoid form
+    of GELU (Hendrycks & Gimpel), within 0.021 of z Phi(z) everywhere and one
+    exponential and one reciprocal on the device;
   - loss: mean squared error over the batch; backward by the chain rule with
     the same BF16 rounding of the operands of each product (bf(dz2) with
     bf(h1) and W2; bf(dz1) with bf(x));
@@ -48,16 +50,25 @@ def bf16(a):
     return u.astype(np.uint32).view(np.float32).astype(np.float64).reshape(np.shape(a))
 
 
-_erf = np.vectorize(math.erf, otypes=[np.float64])
+GELU_A = 1.702
+
+
+def _sigma(u):
+    """Logistic function 1 / (1 + exp(-u)), written through tanh so that it
+    does not overflow."""
+    return 0.5 * (1.0 + np.tanh(0.5 * np.asarray(u, dtype=np.float64)))
 
 
 def gelu(z):
-    return z * 0.5 * (1.0 + _erf(z / math.sqrt(2.0)))
+    z = np.asarray(z, dtype=np.float64)
+    return z * _sigma(GELU_A * z)
 
 
 def gelu_grad(z):
-    """d/dz z Phi(z) = Phi(z) + z phi(z)."""
-    return 0.5 * (1.0 + _erf(z / math.sqrt(2.0))) + z * np.exp(-0.5 * z * z) / math.sqrt(2.0 * math.pi)
+    """d/dz z s(a z) = s + a z s (1 - s), s = sigma(a z)."""
+    z = np.asarray(z, dtype=np.float64)
+    s = _sigma(GELU_A * z)
+    return s + GELU_A * z * s * (1.0 - s)
 
 
 def unpack(theta):

@@ -28,7 +28,7 @@ from .product import matvec
 
 
 def pagerank_restarted(rowptr, col, predict, F_struct, beta=0.85, tol=1e-6, max_iter=1000, K=10,
-                       max_restarts=3):
+                       max_restarts=2):
     """Returns (p, iters, resid, converged, info): iters counts the kept
     iterations (an accepted probe is one), info = dict(products, accepted,
     rejected) with products = iters + rejected probes.

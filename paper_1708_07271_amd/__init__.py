@@ -60,7 +60,7 @@ class Info(ctypes.Structure):
                                                "stream_bytes", "n_singles", "n_wide", "n_intervals")] + \
                [(f, ctypes.c_int) for f in ("W", "R", "Lmin", "zeta_k", "tile_rows", "window_cap",
                                             "stage_bytes", "long_row_bytes", "interval_mode", "max_level",
-                                            "ngraphs")]
+                                            "ngraphs", "autotuned")]
 
     def as_dict(self):
         return {f: getattr(self, f) for f, _ in self._fields_}
@@ -236,7 +236,7 @@ def bvmv_pagerank_detail(g: Graph, p_out, teleport=None, start=None, damping=0.8
     """Returns a list of dicts (iters, converged, residual, used_start,
     products, restarts_accepted, restarts_rejected), one per column (or member
     of a group).  With `mlp`, learned warm restarts every `restart_every`
-    iterations (0 = 10), at most `max_restarts` (0 = 3)."""
+    iterations (0 = 10), at most `max_restarts` (0 = 2)."""
     p = _prec(prec)
     dt = _vec_dtype(p)
     lib = load_library()

@@ -25,6 +25,8 @@
 //   6. epilogue: store y, or the PageRank update.
 #include <hip/hip_runtime.h>
 
+#include <type_traits>
+
 #include "kernels.hpp"
 
 namespace bvmv {
@@ -462,6 +464,104 @@ __device__ __forceinline__ uint32_t chunk_ends(uint32_t E, uint32_t C, const uin
   return n;
 }
 
+// Bit-field extract and the sign word of an entry as single VALU operations
+// (the compiler otherwise rewrites them into shift-and-mask pairs).
+template <int O, int W>
+__device__ __forceinline__ uint32_t vbfe(uint32_t d) {
+  uint32_t r;
+  asm("v_bfe_u32 %0, %1, %2, %3" : "=v"(r) : "v"(d), "i"(O), "i"(W));
+  return r;
+}
+// high word of +-1.0: 0x3FF00000 with the sign bit of d's bit 15 (h = 0) or 31 (h = 1)
+template <int H>
+__device__ __forceinline__ uint32_t sign_word(uint32_t d, uint32_t one_hi, uint32_t sign_mask) {
+  uint32_t r;
+  if constexpr (H == 0) {
+    const uint32_t b = vbfe<15, 1>(d);
+    asm("v_lshl_or_b32 %0, %1, 31, %2" : "=v"(r) : "v"(b), "v"(one_hi));
+  } else {
+    asm("v_bfi_b32 %0, %1, %2, %3" : "=v"(r) : "v"(sign_mask), "v"(d), "v"(one_hi));
+  }
+  return r;
+}
+
+// Load dwords first .. first + kRound - 1 of a stream; those at or past `end`
+// (the end of the lane's chunk) read as 0: an entry that adds Z[0] = 0 and
+// ends no row.
+__device__ __forceinline__ void load_round_z(const uint32_t* __restrict__ g, uint32_t first, uint32_t end,
+                                             uint32_t last, uint32_t (&d)[kRound]) {
+#pragma unroll
+  for (int k = 0; k < kRound; ++k) {
+    const uint32_t i = first + uint32_t(k);
+    const uint32_t w = g[min(i, last)];
+    d[k] = i < end ? w : 0u;
+  }
+}
+
+// Singles pass of the two-sum mode by running sums.  Lane l adds its chunk's
+// entries in order into one double that is never reset, and stores the
+// running value after every entry at *p.  p starts at seg + slot0, slot0 =
+// (row ends in earlier chunks) + l, and steps past every row end, so each of
+// the lane's slots ends up holding the running sum at one row end, and the
+// slot after its last row end the running sum at the chunk's end (each lane
+// has one slot more than its row ends).  Rows are read back as differences
+// (run_row_sum); the running sums stay within a few rows' sums, far inside
+// the mode's tolerance.  An entry's sign enters as a factor +-1 built from
+// its sign bit.  Rounds of kRound dwords are taken two dwords at a time while
+// some lane of the wave has them (`pre` and later rounds load the dwords past
+// the lane's chunk as 0).
+__device__ __forceinline__ void run_pass(uint32_t ndmax, const Chunk<2>& ch, const uint32_t* __restrict__ g,
+                                         const uint32_t (&pre)[kRound], uint32_t slot0, double* seg,
+                                         const double* Z) {
+  double acc = 0.0;
+  double* p = seg + slot0;
+  const uint32_t one_hi = 0x3FF00000u, sign_mask = 0x80000000u;
+  // entry H (0: bits 0..15, 1: bits 16..31) of dword d: 14 bits of f, the
+  // row-end bit, the sign bit
+  auto entry = [&](auto hc, uint32_t d, double v) {
+    constexpr int H = decltype(hc)::value;
+    const double sg = __hiloint2double(int(sign_word<H>(d, one_hi, sign_mask)), 0);
+    acc = fma(sg, v, acc);
+    *p = acc;
+    p += vbfe<16 * H + 14, 1>(d);
+  };
+  using H0 = std::integral_constant<int, 0>;
+  using H1 = std::integral_constant<int, 1>;
+  auto round = [&](const uint32_t (&d)[kRound], uint32_t r) {
+#pragma unroll
+    for (int k = 0; k < kRound; k += 2) {
+      if (r + uint32_t(k) >= ndmax) break;
+      const double v0 = Z[d[k] & kS16Off], v1 = Z[vbfe<16, 14>(d[k])];
+      const double v2 = Z[d[k + 1] & kS16Off], v3 = Z[vbfe<16, 14>(d[k + 1])];
+      entry(H0{}, d[k], v0);
+      entry(H1{}, d[k], v1);
+      entry(H0{}, d[k + 1], v2);
+      entry(H1{}, d[k + 1], v3);
+    }
+  };
+  round(pre, 0);
+  for (uint32_t r = kRound; r < ndmax; r += kRound) {
+    uint32_t q[kRound];
+    load_round_z(g, ch.d0 + r, ch.d0 + ch.nd, ch.last, q);
+    round(q, r);
+  }
+}
+
+// Owner side of run_pass: the sum of the owner's row, entries [ob, oe) with
+// oe > ob, whose end is row end number gi of the stream (its rank among the
+// rows that have entries).  In every chunk l from L0 to L1 the row's running
+// sum sits in slot gi + l (the row's end in chunk L1, the chunk's end in the
+// others), less the running sum at the previous row's end when that lies in
+// chunk L0 (the row does not start the chunk).
+__device__ __forceinline__ double run_row_sum(uint32_t ob, uint32_t oe, uint32_t C, float invC, uint32_t gi,
+                                              const double* seg) {
+  const uint32_t L0 = div_small(ob, C, invC), L1 = div_small(oe - 1, C, invC);
+  double s = seg[gi + L0];
+  for (uint32_t l = L0 + 1; l <= L1; ++l) s += seg[gi + l];
+  if (ob != L0 * C) s -= seg[gi - 1 + L0];
+  return s;
+}
+
 // Owner side of a flat pass: the sum of the owner's row occupying entries
 // [ob, oe) (oe > ob) of a pass with chunk length C: the pieces of the earlier
 // chunks it spans (carry, in lane order), then its final piece.
@@ -496,7 +596,8 @@ struct WaveCarve {
   static constexpr size_t kSlot = sizeof(PAcc) > sizeof(CAcc) ? sizeof(PAcc) : sizeof(CAcc);
   __host__ __device__ static constexpr size_t seg() { return 0; }
   __host__ __device__ static constexpr size_t y() { return 0; }
-  __host__ __device__ static constexpr size_t carry() { return align16(kRows * kSlot); }
+  // (kRows + 64 slots: the running-sum pass keeps one more slot per lane)
+  __host__ __device__ static constexpr size_t carry() { return align16((kRows + 64) * kSlot); }
   // the window array Z, placed 8 bytes past a 16-byte boundary so that Z + 1
   // is 16-byte aligned
   __host__ __device__ static constexpr size_t Z() { return carry() + align16(64 * sizeof(PAcc)) + 8; }
@@ -646,11 +747,15 @@ __global__ void __launch_bounds__(kThreads) bv_wave_kernel(DevLayout L, const ty
   // 1. all global loads of the tile: the first round of the lane's singles
   //    chunk, its rows' info, and the x window (with its prefix sums when the
   //    tile has intervals) into Z
+  constexpr bool kRun = std::is_same<M, MF32C>::value;  // running-sum singles pass
   const uint32_t C16 = flat_chunk<2>(n16);
+  const Chunk<2> ch16(n16, C16);
   uint32_t pre[kRound];
-  {
-    const Chunk<2> ch(n16, C16);
-    if (n16) load_round(g16, ch.d0, ch.last, pre);
+  if (n16) {
+    if constexpr (kRun)
+      load_round_z(g16, ch16.d0, ch16.d0 + ch16.nd, ch16.last, pre);
+    else
+      load_round(g16, ch16.d0, ch16.last, pre);
   }
   uint32_t inf[RPL], ns[RPL];
 #pragma unroll
@@ -705,7 +810,13 @@ __global__ void __launch_bounds__(kThreads) bv_wave_kernel(DevLayout L, const ty
   for (int q = 0; q < RPL; ++q) a[q] = M::pzero();
   if (n16) {
     const float invC = __builtin_amdgcn_rcpf(float(C16));
-    if constexpr (M::kInt) {
+    if constexpr (kRun) {
+      run_pass((min(C16, n16) + 1) / 2, ch16, g16, pre, (ex16 >> 16) + lane, s_seg, Z);
+      wave_sync();
+#pragma unroll
+      for (int q = 0; q < RPL; ++q)
+        if (c16[q]) a[q] = run_row_sum(o16[q], o16[q] + c16[q], C16, invC, k16[q], s_seg);
+    } else if constexpr (M::kInt) {
       // degrees: a column counts 1, a prefix entry P[p] counts p
       end_pass<M, 2, kS16End>(n16, C16, g16, pre, ex16 >> 16, s_seg, s_carry, [&](uint32_t w) -> X {
         const int32_t f = int32_t(w & kS16Off);
@@ -718,10 +829,12 @@ __global__ void __launch_bounds__(kThreads) bv_wave_kernel(DevLayout L, const ty
         return (w & kS16Neg) ? -v : v;
       }, [](PAcc& acc, double v) { M::padd_d(acc, v); });
     }
-    wave_sync();
+    if constexpr (!kRun) {
+      wave_sync();
 #pragma unroll
-    for (int q = 0; q < RPL; ++q)
-      if (c16[q]) a[q] = flat_row_sum<M>(o16[q], o16[q] + c16[q], C16, invC, s_seg[k16[q]], s_carry);
+      for (int q = 0; q < RPL; ++q)
+        if (c16[q]) a[q] = flat_row_sum<M>(o16[q], o16[q] + c16[q], C16, invC, s_seg[k16[q]], s_carry);
+    }
   }
   // window value of column win0 + c, else the global one
   auto xval = [&](int64_t c) -> X {

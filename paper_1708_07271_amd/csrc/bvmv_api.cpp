@@ -5,7 +5,9 @@
 #include <climits>
 #include <cmath>
 #include <cstring>
+#include <map>
 #include <memory>
+#include <mutex>
 #include <string>
 #include <thread>
 #include <vector>
@@ -187,7 +189,7 @@ int resolve_pr_opts(const bvmv_pr_opts* o, PROptsResolved& r) {
   r.fallback = 0;
   r.mlp = nullptr;
   r.restart_every = 10;
-  r.max_restarts = 3;
+  r.max_restarts = 2;
   if (o) {
     r.fallback = o->fallback_check;
     r.mlp = o->mlp;
@@ -234,6 +236,7 @@ struct bvmv_graph {
   DevLayout L;
   // group
   int ngraphs = 1;
+  int autotuned = 0;                   // 1: layout chosen by timing, 2: from the autotuner's cache
   std::vector<int64_t> offsets;        // ngraphs + 1
   std::vector<uint32_t> tile_offsets;  // ngraphs + 1
   PRWork pr;   // one right-hand side per member
@@ -633,6 +636,56 @@ int run_learned(bvmv_graph* g, const PROptsResolved& o, const bvmv_mlp* m, void*
 
 }  // namespace
 
+
+namespace {
+
+// Candidate layouts of the load-time autotuner: (tile rows, x-window columns,
+// staged entry bytes).  The stage grows with the tile so that rows of the
+// same length stay off the long-row path.
+constexpr int kTuneCands[][3] = {{32, 256, 2048}, {64, 384, 3072}, {64, 512, 4096},
+                                 {64, 768, 6144}, {128, 768, 6144}, {128, 1024, 8192}};
+constexpr int kTuneCount = int(sizeof(kTuneCands) / sizeof(kTuneCands[0]));
+
+// The winner per size bucket (floor(log2 n), rounded 2 log2(mean degree + 1)),
+// kept for the life of the process.
+std::mutex g_tune_mu;
+std::map<std::pair<int, int>, int> g_tune_cache;
+
+std::pair<int, int> tune_key(int64_t n, int64_t m) {
+  int ln = 0;
+  while ((int64_t(1) << (ln + 1)) <= n) ++ln;
+  const double deg = n > 0 ? double(m) / double(n) : 0.0;
+  return {ln, int(std::lround(2.0 * std::log2(deg + 1.0)))};
+}
+
+// Average time of one FP32 two-sum product on the uploaded layout: two
+// warm-up launches, then `reps` back-to-back launches between HIP events.
+int time_product(bvmv_graph* g, const float* x, float* y, int reps, float* us) {
+  hipStream_t s = nullptr;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  HIP_TRY(hipStreamCreateWithFlags(&s, hipStreamNonBlocking));
+  auto cleanup = [&] {
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    (void)hipStreamDestroy(s);
+  };
+  hipError_t e = hipEventCreate(&e0);
+  if (e == hipSuccess) e = hipEventCreate(&e1);
+  for (int i = 0; i < 2 && e == hipSuccess; ++i) e = launch_bv_multiply(g->L, BVMV_F32_COMP, x, y, s);
+  if (e == hipSuccess) e = hipEventRecord(e0, s);
+  for (int i = 0; i < reps && e == hipSuccess; ++i) e = launch_bv_multiply(g->L, BVMV_F32_COMP, x, y, s);
+  if (e == hipSuccess) e = hipEventRecord(e1, s);
+  if (e == hipSuccess) e = hipEventSynchronize(e1);
+  float ms = 0.0f;
+  if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+  cleanup();
+  if (e != hipSuccess) return fail(BVMV_EDEVICE, std::string("autotune timing: ") + hipGetErrorString(e));
+  *us = 1000.0f * ms / float(reps);
+  return BVMV_OK;
+}
+
+}  // namespace
+
 extern "C" {
 
 const char* bvmv_last_error(void) { return g_err.c_str(); }
@@ -690,19 +743,64 @@ int bvmv_load(const void* bitstream, size_t nbytes, const bvmv_load_opts* opts, 
   prm.long_row_bytes = o.long_row_bytes;
   prm.stage_bytes = o.stage_bytes;
   if (o.interval_mode == 1) prm.min_interval = INT_MAX;  // runs stay single entries
+  DeviceGuard dg(o.device);
+  if (dg.err != hipSuccess) return fail(BVMV_EDEVICE, "hipSetDevice failed");
+  if (o.autotune) {
+    // candidate layouts, each built, uploaded and timed in turn; the fastest
+    // (or the cached winner of this size bucket) is rebuilt below
+    const std::pair<int, int> key = tune_key(g->n, g->m);
+    int best = -1;
+    {
+      std::lock_guard<std::mutex> lk(g_tune_mu);
+      auto it = g_tune_cache.find(key);
+      if (it != g_tune_cache.end()) best = it->second;
+    }
+    g->autotuned = best >= 0 ? 2 : 1;
+    if (best < 0) {
+      DevBuf<float> xb, yb;
+      if (xb.alloc(size_t(g->n)) || yb.alloc(size_t(g->n))) return fail(BVMV_ENOMEM, "autotune vectors");
+      HIP_TRY(hipMemset(xb.p, 0, size_t(std::max<int64_t>(g->n, 1)) * sizeof(float)));
+      float best_us = 0.0f;
+      for (int c = 0; c < kTuneCount; ++c) {
+        LayoutParams cp = prm;
+        cp.tile_rows = kTuneCands[c][0];
+        cp.window_cap = kTuneCands[c][1];
+        cp.stage_bytes = kTuneCands[c][2];
+        cp.long_row_bytes = cp.stage_bytes / 2;
+        g->hl = HostLayout();
+        if (build_layout(g->dec, cp, nt, g->hl, err)) continue;
+        if (upload_layout(g.get()) != BVMV_OK) {  // e.g. more LDS than a block may use
+          g->release_device();
+          continue;
+        }
+        float us = 0.0f;
+        const int rc = time_product(g.get(), xb.p, yb.p, 20, &us);
+        g->release_device();
+        if (rc) return rc;
+        if (best < 0 || us < best_us) {
+          best = c;
+          best_us = us;
+        }
+      }
+      if (best < 0) return fail(BVMV_EINVAL, "no autotune candidate fits the device");
+      std::lock_guard<std::mutex> lk(g_tune_mu);
+      g_tune_cache[key] = best;
+    }
+    prm.tile_rows = kTuneCands[best][0];
+    prm.window_cap = kTuneCands[best][1];
+    prm.stage_bytes = kTuneCands[best][2];
+    prm.long_row_bytes = prm.stage_bytes / 2;
+    g->hl = HostLayout();
+  }
   if (build_layout(g->dec, prm, nt, g->hl, err)) return fail(BVMV_EINVAL, err);
   g->m_prime = g->hl.m_prime;
   if (o.device_mem_budget && uint64_t(g->hl.bytes()) + uint64_t(g->n) * 4 > o.device_mem_budget)
     return fail(BVMV_ENOMEM, "layout exceeds the device memory budget");
   g->offsets = {0, g->n};
   g->tile_offsets = {0, uint32_t(g->hl.tiles.size())};
-  {
-    DeviceGuard dg(o.device);
-    if (dg.err != hipSuccess) return fail(BVMV_EDEVICE, "hipSetDevice failed");
-    if (int rc = upload_layout(g.get())) {
-      g->release_device();
-      return rc;
-    }
+  if (int rc = upload_layout(g.get())) {
+    g->release_device();
+    return rc;
   }
   if (o.keep_lists) {
     g->lists_kept = true;
@@ -903,6 +1001,7 @@ int bvmv_get_info(const bvmv_graph* g, bvmv_info* out) {
   out->interval_mode = g->interval_mode;
   out->max_level = g->hl.max_level;
   out->ngraphs = g->ngraphs;
+  out->autotuned = g->autotuned;
   return BVMV_OK;
 }
 

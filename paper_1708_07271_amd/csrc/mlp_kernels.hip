@@ -37,10 +37,14 @@ __device__ __forceinline__ uint16_t bf16_bits(float f) {
 }
 __device__ __forceinline__ float bf16_float(uint16_t b) { return __uint_as_float(uint32_t(b) << 16); }
 
-// gelu(z) = z Phi(z) and its derivative Phi(z) + z phi(z)
-__device__ __forceinline__ float gelu(float z) { return 0.5f * z * (1.0f + erff(z * 0.70710678118654752f)); }
+// gelu(z) = z s(1.702 z) with s the logistic function (the sigmoid form of
+// GELU), and its derivative s + 1.702 z s (1 - s); one exponential and one
+// reciprocal each (exp(-u) overflowing to +inf gives s = 0)
+__device__ __forceinline__ float gelu_s(float z) { return __builtin_amdgcn_rcpf(1.0f + __expf(-1.702f * z)); }
+__device__ __forceinline__ float gelu(float z) { return z * gelu_s(z); }
 __device__ __forceinline__ float gelu_grad(float z) {
-  return 0.5f * (1.0f + erff(z * 0.70710678118654752f)) + z * expf(-0.5f * z * z) * 0.39894228040143268f;
+  const float s = gelu_s(z);
+  return s + 1.702f * z * s * (1.0f - s);
 }
 
 __device__ __forceinline__ f16v mfma(s4 a, s4 b, f16v c) { return __builtin_amdgcn_mfma_f32_32x32x8bf16_1k(a, b, c, 0, 0, 0); }

@@ -204,6 +204,43 @@ def test_group_block_diagonal(P):
         assert np.array_equal(y[seg], _mul(P, Gs[i], x[seg], P.BVMV_F32_COMP))
 
 
+# the autotuner's candidate layouts (tile rows, window columns, staged bytes)
+TUNE_CANDS = [(32, 256, 2048), (64, 384, 3072), (64, 512, 4096), (64, 768, 6144), (128, 768, 6144),
+              (128, 1024, 8192)]
+
+
+@pytest.mark.parametrize("cand", TUNE_CANDS)
+def test_autotune_candidates_exact(P, graphs, cand):
+    # every layout the autotuner may pick gives the exact sums on integer x
+    for name, (g, enc) in graphs.items():
+        print("case", name, cand, flush=True)
+        G = P.bvmv_load(enc.data, tile_rows=cand[0], window_cap=cand[1], stage_bytes=cand[2])
+        xi = B.integer_x(g.n, 8, 7).astype(np.float32)
+        refi = product.matvec(g.rowptr, g.col, xi.astype(np.float64))
+        for prec in (P.BVMV_F32, P.BVMV_F32_COMP):
+            assert np.array_equal(_mul(P, G, xi, prec), refi)
+        x = B.uniform_x(g.n, 9)
+        assert _rel(_mul(P, G, x, P.BVMV_F64), product.matvec(g.rowptr, g.col, x)) < 1e-12
+
+
+def test_autotune_load(P):
+    g = B.web_graph(50_000, 17.0, 71)
+    enc = B.encode(g)
+    G = P.bvmv_load(enc.data, autotune=1)
+    info = P.bvmv_get_info(G)
+    assert info["autotuned"] in (1, 2)
+    assert (info["tile_rows"], info["window_cap"], info["stage_bytes"]) in TUNE_CANDS
+    # the same size bucket again: the remembered choice
+    G2 = P.bvmv_load(enc.data, autotune=1)
+    info2 = P.bvmv_get_info(G2)
+    assert info2["autotuned"] == 2 and info2["tile_rows"] == info["tile_rows"]
+    assert info2["window_cap"] == info["window_cap"]
+    x = B.uniform_x(g.n, 72, np.float32)
+    ref = product.matvec(g.rowptr, g.col, x.astype(np.float64))
+    assert _rel(_mul(P, G, x, P.BVMV_F32_COMP), ref) < 1e-5
+    assert P.bvmv_get_info(P.bvmv_load(enc.data))["autotuned"] == 0
+
+
 @pytest.mark.slow
 def test_full_size_web_2p20(P):
     """n = 2^20, mean out-degree 20: every row against the oracle, and sampled
