@@ -316,55 +316,6 @@ __device__ __forceinline__ double wave_incl_scan_f64(double v) {
   return v;
 }
 
-// Stage a tile's x window into the LDS array Z (doubles): Z[0] = 0,
-// Z[2j+2] = x[win0+j] for j < n, and, with `prefix`, Z[2p+1] = P[p] =
-// x[win0] + ... + x[win0+p-1] for p <= n (odd entries are left undefined
-// otherwise; no entry reads them then).  Lane l takes the ceil(n/64)
-// consecutive values from l*ceil(n/64) on, 8 loads in flight; a wave scan of
-// the lanes' sums gives each lane's first prefix.  Z + 1 is 16-byte aligned,
-// so every (P[j], x[j]) pair is one 16-byte LDS write.
-template <class X>
-__device__ __forceinline__ void stage_window(const X* __restrict__ x, int64_t win0, uint32_t n, bool prefix,
-                                             double* Z) {
-  const uint32_t lane = lane_id();
-  const uint32_t ch = (n + 63) / 64;
-  const uint32_t b = min(n, lane * ch), e = min(n, b + ch);
-  const uint32_t ng = (e - b + 7) / 8;
-  const X* xw = x + win0;
-  X v[8];
-  double t = 0.0;
-  for (uint32_t g = 0; g < ng; ++g) {
-    const uint32_t k = b + 8 * g;
-#pragma unroll
-    for (int j = 0; j < 8; ++j) v[j] = xw[min(k + uint32_t(j), e - 1)];
-    if (prefix)
-#pragma unroll
-      for (int j = 0; j < 8; ++j)
-        if (k + uint32_t(j) < e) t += double(v[j]);
-  }
-  double run = 0.0;
-  if (prefix) {
-    const double inc = wave_incl_scan_f64(t);
-    run = inc - t;
-    if (lane == 63) Z[2 * size_t(n) + 1] = inc;
-  }
-  if (lane == 0) Z[0] = 0.0;
-  double2* Zp = reinterpret_cast<double2*>(Z + 1);  // Zp[j] = (P[j], x[win0+j])
-  for (uint32_t g = 0; g < ng; ++g) {
-    const uint32_t k = b + 8 * g;
-    if (ng > 1)
-#pragma unroll
-      for (int j = 0; j < 8; ++j) v[j] = xw[min(k + uint32_t(j), e - 1)];
-#pragma unroll
-    for (int j = 0; j < 8; ++j)
-      if (k + uint32_t(j) < e) {
-        const double xv = double(v[j]);
-        Zp[k + j] = make_double2(run, xv);
-        run += xv;
-      }
-  }
-}
-
 // set bits of m in the lanes below this one
 __device__ __forceinline__ uint32_t lanes_below(uint64_t m) {
   return __builtin_amdgcn_mbcnt_hi(uint32_t(m >> 32), __builtin_amdgcn_mbcnt_lo(uint32_t(m), 0u));
@@ -607,6 +558,7 @@ struct WaveCarve {
 
 struct TileCtx {
   uint32_t row0, nrows, graph;
+  uint32_t slot;  // the block partial's slot (PageRank epilogue)
 };
 
 // ---------------------------------------------------------------- epilogues
@@ -623,7 +575,8 @@ struct EpiStore {
 // stores; pr_finish_kernel folds a member's slots, in a fixed order, after the
 // launch (the kernel boundary makes them visible: no device-scope fence,
 // which on a multi-XCD part would write back the L2 once per block).
-__device__ __forceinline__ void pr_block_partial(double rs, double dg, double* slots, unsigned char* s_blk) {
+__device__ __forceinline__ void pr_block_partial(double rs, double dg, double* slots, unsigned char* s_blk,
+                                                 uint32_t slot) {
   double* blk = reinterpret_cast<double*>(s_blk);
   const uint32_t wave = threadIdx.x >> 6, lane = lane_id();
   if (lane == 0) {
@@ -637,8 +590,8 @@ __device__ __forceinline__ void pr_block_partial(double rs, double dg, double* s
       R += blk[2 * w];
       D += blk[2 * w + 1];
     }
-    slots[2 * size_t(blockIdx.x)] = R;
-    slots[2 * size_t(blockIdx.x) + 1] = D;
+    slots[2 * size_t(slot)] = R;
+    slots[2 * size_t(slot) + 1] = D;
   }
 }
 
@@ -709,33 +662,110 @@ struct EpiPR {
     }
     rs = wave_sum_f64(rs);
     dg = wave_sum_f64(dg);
-    pr_block_partial(rs, dg, a.slots, s_blk);
+    pr_block_partial(rs, dg, a.slots, s_blk, tc.slot);
   }
 };
 
 // --------------------------------------------------------------- tile kernel
-// One wavefront per tile of up to 64 * RPL rows; lane l owns rows
-// [l * RPL, (l + 1) * RPL).
-template <class M, int RPL, class Epi>
-__global__ void __launch_bounds__(kThreads) bv_wave_kernel(DevLayout L, const typename M::X* __restrict__ x,
-                                                           Epi epi, const PRState* __restrict__ skip_done) {
+// Global data of one tile, loaded before any of it is used: the first round
+// of the lane's singles chunk, its rows' info, and its first SV values of
+// the x window.
+template <class M, int RPL, int SV>
+struct TileLoads {
+  uint32_t pre[kRound];
+  uint32_t inf[RPL], ns[RPL];
+  typename M::X xs[M::kInt ? 1 : SV];  // (the integer mode stages no window)
+};
+
+// Issue a tile's loads into `ld` from safe (clamped) addresses only; the
+// values are masked where process_tile uses them, so all the loads are in
+// flight together before the first is waited for.
+template <class M, int RPL, int SV>
+__device__ __forceinline__ void issue_loads(const DevLayout& L, const TileDesc& td,
+                                            const typename M::X* __restrict__ x, TileLoads<M, RPL, SV>& ld) {
+  const uint32_t lane = lane_id(), r0 = lane * RPL;
+  const uint32_t n16 = td.n16;
+  if (n16) {
+    const uint32_t* g16 = reinterpret_cast<const uint32_t*>(L.data + td.data16);
+    const Chunk<2> ch(n16, flat_chunk<2>(n16));
+    load_round(g16, ch.d0, ch.last, ld.pre);
+  }
+#pragma unroll
+  for (int q = 0; q < RPL; ++q) {
+    const uint32_t r = r0 + q < td.nrows ? td.row0 + r0 + q : 0u;
+    ld.inf[q] = L.info[r];
+    ld.ns[q] = uint32_t(L.ns[r]);
+  }
+  if constexpr (!M::kInt) {
+    const uint32_t n = td.winlen;
+    if (n) {
+      const uint32_t c = (n + 63) / 64, b = min(n, lane * c), e = min(n, b + c);
+      const typename M::X* xw = x + td.win0;
+#pragma unroll
+      for (int j = 0; j < SV; ++j) ld.xs[j] = xw[e > b ? min(b + uint32_t(j), e - 1) : 0u];
+    }
+  }
+}
+
+// Stage a tile's x window of n values into the LDS array Z (doubles): Z[0] =
+// 0, Z[2j+2] = x[win0+j] for j < n, and, with `prefix`, Z[2p+1] = P[p] =
+// x[win0] + ... + x[win0+p-1] for p <= n (odd entries are left undefined
+// otherwise; no entry reads them then).  Lane l takes the ceil(n/64)
+// consecutive values from l*ceil(n/64) on: the first SV come from the loads
+// issued with the tile's others, a longer chunk loads the rest here.  A wave
+// scan of the lanes' sums gives each lane's first prefix.  Z + 1 is 16-byte
+// aligned, so every (P[j], x[j]) pair is one 16-byte LDS write.
+template <class X, int SV>
+__device__ __forceinline__ void stage_regs(const X (&xs)[SV], const X* __restrict__ xw, uint32_t n, bool prefix,
+                                           double* Z) {
+  const uint32_t lane = lane_id();
+  const uint32_t ch = (n + 63) / 64;
+  const uint32_t b = min(n, lane * ch), e = min(n, b + ch);
+  double t = 0.0;
+  if (prefix) {
+#pragma unroll
+    for (int j = 0; j < SV; ++j)
+      if (b + uint32_t(j) < e) t += double(xs[j]);
+    for (uint32_t k = b + SV; k < e; ++k) t += double(xw[k]);
+  }
+  double run = 0.0;
+  if (prefix) {
+    const double inc = wave_incl_scan_f64(t);
+    run = inc - t;
+    if (lane == 63) Z[2 * size_t(n) + 1] = inc;
+  }
+  if (lane == 0) Z[0] = 0.0;
+  double2* Zp = reinterpret_cast<double2*>(Z + 1);  // Zp[j] = (P[j], x[win0+j])
+#pragma unroll
+  for (int j = 0; j < SV; ++j)
+    if (b + uint32_t(j) < e) {
+      const double xv = double(xs[j]);
+      Zp[b + j] = make_double2(run, xv);
+      run += xv;
+    }
+  for (uint32_t k = b + SV; k < e; ++k) {
+    const double xv = double(xw[k]);
+    Zp[k] = make_double2(run, xv);
+    run += xv;
+  }
+}
+
+// One tile by one wavefront, its global data already in `ld`: tile rows
+// [row0, row0 + nrows), lane l owns rows [l * RPL, (l + 1) * RPL).
+template <class M, int RPL, int SV, class Epi>
+__device__ __forceinline__ void process_tile(const DevLayout& L, const TileDesc& td, const TileLoads<M, RPL, SV>& ld,
+                                             const typename M::X* __restrict__ x, const Epi& epi, uint32_t slot,
+                                             unsigned char* ws, unsigned char* s_blk) {
   using X = typename M::X;
   using PAcc = typename M::PAcc;
   using CAcc = typename M::CAcc;
   using Cv = WaveCarve<M, RPL>;
-  extern __shared__ __align__(16) unsigned char smem[];
-  const uint32_t wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  constexpr bool kRun = std::is_same<M, MF32C>::value;  // running-sum singles pass
+  PAcc* s_seg = reinterpret_cast<PAcc*>(ws + Cv::seg());
+  CAcc* s_y = reinterpret_cast<CAcc*>(ws + Cv::y());
+  PAcc* s_carry = reinterpret_cast<PAcc*>(ws + Cv::carry());
+  double* Z = reinterpret_cast<double*>(ws + Cv::Z());
   const uint32_t lane = lane_id();
-  const uint32_t tile = blockIdx.x * kWaves + wave;
-  const TileDesc td = L.tiles[tile];
-  if (skip_done && skip_done[L.tiles[blockIdx.x * kWaves].graph].done) return;  // whole block, one member
-  const Cv cv{L.wcap};
-  unsigned char* ws = smem + size_t(wave) * cv.wave_bytes();
-  unsigned char* s_blk = smem + size_t(kWaves) * cv.wave_bytes();
-  PAcc* s_seg = reinterpret_cast<PAcc*>(ws + cv.seg());
-  CAcc* s_y = reinterpret_cast<CAcc*>(ws + cv.y());
-  PAcc* s_carry = reinterpret_cast<PAcc*>(ws + cv.carry());
-  double* Z = reinterpret_cast<double*>(ws + cv.Z());
   const uint32_t nrows = td.nrows;
   const int64_t win0 = td.win0;
   const uint32_t winlen = td.winlen;
@@ -743,28 +773,27 @@ __global__ void __launch_bounds__(kThreads) bv_wave_kernel(DevLayout L, const ty
   const uint32_t n16 = td.n16, nwide = td.nwide;
   const uint32_t* g16 = reinterpret_cast<const uint32_t*>(L.data + td.data16);  // singles stream
   const uint32_t* gw = g16 + dalign16u(n16 * 2u) / 4;                          // wide entries
-
-  // 1. all global loads of the tile: the first round of the lane's singles
-  //    chunk, its rows' info, and the x window (with its prefix sums when the
-  //    tile has intervals) into Z
-  constexpr bool kRun = std::is_same<M, MF32C>::value;  // running-sum singles pass
   const uint32_t C16 = flat_chunk<2>(n16);
   const Chunk<2> ch16(n16, C16);
+  // the loaded words, masked: stream dwords past the lane's chunk are 0
+  // in the running-sum mode (clamped copies otherwise), rows past the tile 0
   uint32_t pre[kRound];
-  if (n16) {
+#pragma unroll
+  for (int k = 0; k < kRound; ++k) {
     if constexpr (kRun)
-      load_round_z(g16, ch16.d0, ch16.d0 + ch16.nd, ch16.last, pre);
+      pre[k] = n16 && uint32_t(k) < ch16.nd ? ld.pre[k] : 0u;
     else
-      load_round(g16, ch16.d0, ch16.last, pre);
+      pre[k] = n16 ? ld.pre[k] : 0u;
   }
   uint32_t inf[RPL], ns[RPL];
 #pragma unroll
   for (int q = 0; q < RPL; ++q) {
     const bool has = r0 + q < nrows;
-    inf[q] = has ? L.info[td.row0 + r0 + q] : 0u;
-    ns[q] = has ? uint32_t(L.ns[td.row0 + r0 + q]) : 0u;
+    inf[q] = has ? ld.inf[q] : 0u;
+    ns[q] = has ? ld.ns[q] : 0u;
   }
-  if constexpr (!M::kInt) stage_window<X>(x, win0, winlen, td.nint != 0, Z);
+  // 1. the x window (with its prefix sums when the tile has intervals) into Z
+  if constexpr (!M::kInt) stage_regs<X, SV>(ld.xs, x + win0, winlen, td.nint != 0, Z);
 
   // 2. offsets of the lanes' rows in the streams, and of their row ends
   uint32_t c16[RPL], cw[RPL], s16 = 0, sw = 0;
@@ -939,7 +968,26 @@ __global__ void __launch_bounds__(kThreads) bv_wave_kernel(DevLayout L, const ty
   }
   wave_sync();
   // 6. epilogue
-  epi(TileCtx{td.row0, nrows, td.graph}, s_y, s_blk);
+  epi(TileCtx{td.row0, nrows, td.graph, slot}, s_y, s_blk);
+}
+
+// Tile kernel: block b takes the group of kWaves consecutive tiles from
+// kWaves * b on, wave w the w-th.  A block of a member that is done
+// (skip_done) returns at once.
+template <class M, int RPL, int SV, class Epi>
+__global__ void __launch_bounds__(kThreads) bv_wave_kernel(DevLayout L, const typename M::X* __restrict__ x,
+                                                           Epi epi, const PRState* __restrict__ skip_done) {
+  using Cv = WaveCarve<M, RPL>;
+  extern __shared__ __align__(16) unsigned char smem[];
+  const uint32_t wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const Cv cv{L.wcap};
+  unsigned char* ws = smem + size_t(wave) * cv.wave_bytes();
+  unsigned char* s_blk = smem + size_t(kWaves) * cv.wave_bytes();
+  const TileDesc td = L.tiles[blockIdx.x * kWaves + wave];
+  if (skip_done && skip_done[td.graph].done) return;  // a block holds one member's tiles
+  TileLoads<M, RPL, SV> ld;
+  issue_loads<M, RPL, SV>(L, td, x, ld);
+  process_tile<M, RPL, SV>(L, td, ld, x, epi, blockIdx.x, ws, s_blk);
 }
 
 // PageRank start: p0 = start (or teleport, or uniform), z0 = p0 / d, dangling mass.
@@ -975,7 +1023,7 @@ __global__ void __launch_bounds__(kThreads) pr_init_kernel(const uint32_t* __res
     if (d == 0) dg += double(pv);
   }
   dg = wave_sum_f64(dg);
-  pr_block_partial(0.0, dg, slots, s_blk);
+  pr_block_partial(0.0, dg, slots, s_blk, blockIdx.x);
 }
 
 // ----------------------------------------------------------- warm restarts
@@ -1043,7 +1091,7 @@ __global__ void __launch_bounds__(kThreads) restart_vector_kernel(
     sum += double(qv);
   }
   sum = wave_sum_f64(sum);
-  pr_block_partial(0.0, sum, slots, s_blk);
+  pr_block_partial(0.0, sum, slots, s_blk, blockIdx.x);
 }
 
 // ---------------------------------------------------------------- CSR kernel
@@ -1194,7 +1242,7 @@ __global__ void __launch_bounds__(kThreads) csr_wave_kernel(DevCsr C, const type
     s_y[lane] = M::chain(a);
   }
   wave_sync();
-  epi(TileCtx{td.row0, nrows, 0u}, s_y, s_blk);
+  epi(TileCtx{td.row0, nrows, 0u, blockIdx.x}, s_y, s_blk);
 }
 
 // -------------------------------------------------------- multi-vector kernel
@@ -1528,15 +1576,23 @@ size_t tile_lds(const DevLayout& L) {
   }
 }
 
-template <class M, int RPL, class Epi>
-hipError_t launch_tile_rpl(const DevLayout& L, const void* x, const Epi& epi, const PRState* skip, hipStream_t s) {
+template <class M, int RPL, int SV, class Epi>
+hipError_t launch_tile_sv(const DevLayout& L, const void* x, const Epi& epi, const PRState* skip, hipStream_t s) {
   const size_t smem = WaveCarve<M, RPL>{L.wcap}.block_bytes();
-  auto k = bv_wave_kernel<M, RPL, Epi>;
+  auto k = bv_wave_kernel<M, RPL, SV, Epi>;
   if (hipError_t e = set_lds(reinterpret_cast<const void*>(k), smem)) return e;
   if (L.ntiles == 0) return hipSuccess;
   hipLaunchKernelGGL(k, dim3(L.ntiles / kWaves), dim3(kThreads), smem, s, L, static_cast<const typename M::X*>(x),
                      epi, skip);
   return hipGetLastError();
+}
+
+// window values a lane loads up front: 8 up to 512 columns, else 16 (a longer
+// lane chunk loads the rest while it stages)
+template <class M, int RPL, class Epi>
+hipError_t launch_tile_rpl(const DevLayout& L, const void* x, const Epi& epi, const PRState* skip, hipStream_t s) {
+  if (L.wcap <= 512) return launch_tile_sv<M, RPL, 8>(L, x, epi, skip, s);
+  return launch_tile_sv<M, RPL, 16>(L, x, epi, skip, s);
 }
 
 template <class M, class Epi>
