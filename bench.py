@@ -132,6 +132,47 @@ def bench_batch(args, B, P, np, torch, dev):
     print(json.dumps(out), flush=True)
 
 
+def bench_social(args, B, P, np, torch, dev):
+    """Social-like workload social-n4e6-d40 (n = 4e6, out-degree from a
+    truncated shifted power law with exponent 2.1, mean 40, max 50000, weak
+    copying, BFS order; x uniform[0,1) float32, seed 103): per-entry relative
+    error of the two-sum compensated and the naive FP32 products against the
+    FP64 oracle on the same float32 x (max, 99th percentile, median), and the
+    compressed product against the CSR baseline on this GPU."""
+    from oracle import product as _oracle_product  # the FP64 reference of the error columns
+    t0 = time.perf_counter()
+    g = B.workload_graph("social-n4e6-d40")
+    enc = B.encode(g)
+    log("social: n %d, m %d, %.2f bits/edge (%.1fs)" % (g.n, g.m, 8.0 * enc.data.size / g.m, time.perf_counter() - t0))
+    G = P.bvmv_load(enc.data, keep_lists=1)
+    C = P.bvmv_csr_create(G)
+    info = P.bvmv_get_info(G)
+    x32 = B.uniform_x(g.n, 103, np.float32)
+    ref = _oracle_product.matvec(g.rowptr, g.col, x32.astype(np.float64))
+    nz = ref != 0
+    x = torch.from_numpy(x32).to(dev)
+    y = torch.empty_like(x)
+    err = {}
+    for name, prec in (("f32_two_sum", P.BVMV_F32_COMP), ("f32_naive", P.BVMV_F32)):
+        P.bvmv_multiply(G, x, y, prec)
+        torch.cuda.synchronize()
+        rel = np.abs(y.cpu().numpy().astype(np.float64)[nz] - ref[nz]) / np.abs(ref[nz])
+        err[name] = {"max": float(rel.max()), "p99": float(np.percentile(rel, 99)), "median": float(np.median(rel))}
+        log("%s: max rel err %.3e, p99 %.3e" % (name, err[name]["max"], err[name]["p99"]))
+    ms_bv = time_launches(lambda: P.bvmv_multiply(G, x, y), args.steps, args.warmup, torch)
+    ms_csr = time_launches(lambda: P.bvmv_csr_multiply(C, x, y), args.steps, args.warmup, torch)
+    alg = info["layout_bytes"] + 8 * g.n
+    out = {"mode": "social", "workload": "social-n4e6-d40", "n": g.n, "m": g.m,
+           "bitstream_bits_per_edge": 8.0 * enc.data.size / g.m, "layout_bytes": info["layout_bytes"],
+           "layout_bytes_per_edge": info["layout_bytes"] / g.m, "m_over_m_prime": g.m / max(info["m_prime"], 1),
+           "long_rows": info["long_rows"], "escapes": info["escapes"], "rel_error_vs_f64_oracle": err,
+           "compressed": {"ms": ms_bv, "edges_per_s": g.m / (ms_bv * 1e-3), "alg_GBs": alg / (ms_bv * 1e-3) / 1e9},
+           "csr": {"ms": ms_csr, "edges_per_s": g.m / (ms_csr * 1e-3), "bytes": C.bytes() + 8 * g.n,
+                   "alg_GBs": (C.bytes() + 8 * g.n) / (ms_csr * 1e-3) / 1e9},
+           "speedup_compressed_vs_csr": ms_csr / ms_bv}
+    print(json.dumps(out), flush=True)
+
+
 def bench_ragged(args, B, P, np, torch, dev):
     """Ragged batch: 48 web-like graphs, n_g = round(10^(4 + 2 u_g)) with u_g
     uniform from seed 999, mean out-degree 20, graph seeds 1000 + g.  Global
@@ -309,6 +350,8 @@ def main():
     ap.add_argument("--warm-start", action="store_true",
                     help="learned warm restarts: train the network on generated graphs, then PageRank of an "
                          "unseen graph with restarts against the plain method")
+    ap.add_argument("--social", action="store_true",
+                    help="social-like workload (n = 4e6): FP32 error against the FP64 oracle, compressed vs CSR")
     ap.add_argument("--ragged", action="store_true",
                     help="ragged batch of 48 graphs: solo against grouped PageRank, fixed against autotuned layouts")
     ap.add_argument("--warm-graphs", type=int, default=200)
@@ -348,6 +391,8 @@ def main():
         return bench_warm(args, B, P, np, torch, dev)
     if args.ragged:
         return bench_ragged(args, B, P, np, torch, dev)
+    if args.social:
+        return bench_social(args, B, P, np, torch, dev)
     t0 = time.perf_counter()
     g = B.workload_graph(args.workload)
     enc = B.encode(g)
