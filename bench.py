@@ -18,7 +18,8 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 PEAK_HBM_GBS = 8000.0
-KERNEL_SOURCES = ["paper_1708_07271_amd/csrc/bv_kernels.hip", "paper_1708_07271_amd/csrc/bv_layout.cpp"]
+KERNEL_SOURCES = ["paper_1708_07271_amd/csrc/bv_kernels.hip", "paper_1708_07271_amd/csrc/bv_layout.cpp",
+                  "paper_1708_07271_amd/csrc/bv_layout.hpp", "paper_1708_07271_amd/csrc/bvmv_api.cpp"]
 
 
 def log(*a):

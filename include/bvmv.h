@@ -61,7 +61,7 @@ typedef enum {
 typedef struct {
   int device;            /* HIP device ordinal */
   int tile_rows;         /* rows per tile (one wavefront each, up to 2 rows a lane): 8..128 (0 = 64) */
-  int window_cap;        /* max x-window columns staged per tile: 64..8191 (0 = 512) */
+  int window_cap;        /* max x-window columns staged per tile: 64..8191 (0 = 256) */
   int stage_bytes;       /* max entry-stream bytes staged in LDS per tile: 512..16384 (0 = 4096) */
   int long_row_bytes;    /* rows staging more than this are summed by the whole wave (0 = stage_bytes/2) */
   int interval_mode;     /* 0 = interval sums from a per-tile prefix of x, P[s+len] - P[s] (default);

@@ -75,7 +75,7 @@ constexpr int kTilesPerBlock = 4;
 
 struct LayoutParams {
   int tile_rows = 64;
-  int window_cap = 512;
+  int window_cap = 256;
   int stage_bytes = 4096;      // max staged stream bytes per tile (LDS)
   int long_row_bytes = 2048;   // rows staging more than this are summed by the whole wave
   int min_interval = 3;        // runs of at least this many ids become intervals (a huge value: none)

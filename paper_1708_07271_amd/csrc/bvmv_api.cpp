@@ -642,8 +642,8 @@ namespace {
 // Candidate layouts of the load-time autotuner: (tile rows, x-window columns,
 // staged entry bytes).  The stage grows with the tile so that rows of the
 // same length stay off the long-row path.
-constexpr int kTuneCands[][3] = {{32, 256, 2048}, {64, 384, 3072}, {64, 512, 4096},
-                                 {64, 768, 6144}, {128, 768, 6144}, {128, 1024, 8192}};
+constexpr int kTuneCands[][3] = {{32, 256, 2048}, {64, 256, 4096}, {64, 384, 3072},
+                                 {64, 512, 4096}, {64, 768, 6144}, {128, 768, 6144}};
 constexpr int kTuneCount = int(sizeof(kTuneCands) / sizeof(kTuneCands[0]));
 
 // The winner per size bucket (floor(log2 n), rounded 2 log2(mean degree + 1)),
@@ -712,7 +712,7 @@ int bvmv_load(const void* bitstream, size_t nbytes, const bvmv_load_opts* opts, 
   bvmv_load_opts o{};
   if (opts) o = *opts;
   if (o.tile_rows == 0) o.tile_rows = 64;
-  if (o.window_cap == 0) o.window_cap = 512;
+  if (o.window_cap == 0) o.window_cap = 256;
   if (o.stage_bytes == 0) o.stage_bytes = 4096;
   if (o.long_row_bytes == 0) o.long_row_bytes = o.stage_bytes / 2;
   if (o.tile_rows < 8 || o.tile_rows > kTileRowsMax || o.window_cap < 64 || o.window_cap > 8191 ||

@@ -205,8 +205,8 @@ def test_group_block_diagonal(P):
 
 
 # the autotuner's candidate layouts (tile rows, window columns, staged bytes)
-TUNE_CANDS = [(32, 256, 2048), (64, 384, 3072), (64, 512, 4096), (64, 768, 6144), (128, 768, 6144),
-              (128, 1024, 8192)]
+TUNE_CANDS = [(32, 256, 2048), (64, 256, 4096), (64, 384, 3072), (64, 512, 4096), (64, 768, 6144),
+              (128, 768, 6144)]
 
 
 @pytest.mark.parametrize("cand", TUNE_CANDS)
