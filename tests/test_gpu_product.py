@@ -255,3 +255,40 @@ def test_full_size_web_2p20(P):
     assert _rel(y[rows], product.matvec_rows(g.rowptr, g.col, x64, rows)) < 1e-5
     xi = B.integer_x(g.n, 4, 7).astype(np.float32)
     assert np.array_equal(_mul(P, G, xi, P.BVMV_F32_COMP), product.matvec(g.rowptr, g.col, xi))
+
+
+@pytest.mark.slow
+def test_full_size_social_4e6(P):
+    """social-n4e6-d40 (n = 4e6, m = 1.6e8, BFS order), in the launch
+    configuration bench.py --social times: two-sum FP32 within 1e-5 of the
+    correctly rounded sums on sampled rows, naive FP32 within 1e-3, and
+    integer x exact on every row."""
+    g = B.workload_graph("social-n4e6-d40")
+    G = P.bvmv_load(B.encode(g).data)
+    x32 = B.uniform_x(g.n, 103, np.float32)
+    rows = np.random.default_rng(1).choice(g.n, 3000, replace=False)
+    ref = product.matvec_rows(g.rowptr, g.col, x32.astype(np.float64), rows)
+    assert _rel(_mul(P, G, x32, P.BVMV_F32_COMP)[rows], ref) < 1e-5
+    assert _rel(_mul(P, G, x32, P.BVMV_F32)[rows], ref) < 1e-3
+    xi = B.integer_x(g.n, 5, 7).astype(np.float32)
+    assert np.array_equal(_mul(P, G, xi, P.BVMV_F32_COMP), product.matvec(g.rowptr, g.col, xi.astype(np.float64)))
+
+
+@pytest.mark.slow
+def test_full_size_batch_8e6(P):
+    """web-n8e6-d25 with 32 right-hand sides (the batched personalized
+    PageRank workload): every column of the batched product within 1e-5 of
+    the correctly rounded sums on sampled rows."""
+    g = B.workload_graph("web-n8e6-d25")
+    G = P.bvmv_load(B.encode(g).data)
+    k = 32
+    X = np.random.default_rng(104).random((g.n, k), dtype=np.float32)
+    Xd = torch.from_numpy(X).to(DEV)
+    Yd = torch.empty_like(Xd)
+    P.bvmv_multiply_batch(G, Xd, Yd, P.BVMV_F32_COMP)
+    torch.cuda.synchronize()
+    rows = np.random.default_rng(2).choice(g.n, 400, replace=False)
+    Yr = Yd[torch.from_numpy(rows).to(DEV)].cpu().numpy()
+    for c in (0, 7, 31):
+        ref = product.matvec_rows(g.rowptr, g.col, X[:, c].astype(np.float64), rows)
+        assert _rel(Yr[:, c], ref) < 1e-5, c

@@ -217,6 +217,34 @@ def test_learned_argument_errors(P):
         P.bvmv_pagerank_detail(grp, torch.empty(2 * g.n, device=DEV), mlp=m)
 
 
+def test_learned_edge_cases(P):
+    m = P.bvmv_mlp_create(_const_theta(1e6))
+    # converges before the first restart: the plain run, no probe
+    g = B.complete_graph(60)
+    G = P.bvmv_load(B.encode(g).data)
+    p = torch.empty(g.n, dtype=torch.float64, device=DEV)
+    r = P.bvmv_pagerank_detail(G, p, prec=F64, mlp=m)[0]
+    assert r["converged"] and r["iters"] == 1 and r["products"] == 1 and r["restarts_rejected"] == 0
+    assert torch.allclose(p, torch.full_like(p, 1.0 / g.n), rtol=0, atol=1e-15)
+    # max_iter below K: no restart, the plain run's state at max_iter
+    g = B.web_graph(20_000, 12.0, 54)
+    G = P.bvmv_load(B.encode(g).data)
+    pp = torch.empty(g.n, dtype=torch.float64, device=DEV)
+    rp = P.bvmv_pagerank_detail(G, pp, prec=F64, max_iter=6)[0]
+    pl = torch.empty(g.n, dtype=torch.float64, device=DEV)
+    rl = P.bvmv_pagerank_detail(G, pl, prec=F64, max_iter=6, mlp=m)[0]
+    assert not rp["converged"] and not rl["converged"]
+    assert rl["iters"] == rp["iters"] == 6 and rl["products"] == 6
+    assert torch.equal(pl, pp)
+    # restart_every = 3 (the smallest): still the plain fixed point within the bound
+    pw = torch.empty(g.n, dtype=torch.float64, device=DEV)
+    rw = P.bvmv_pagerank_detail(G, pw, prec=F64, mlp=P.bvmv_mlp_create(_zero_theta()), restart_every=3)[0]
+    pu = torch.empty(g.n, dtype=torch.float64, device=DEV)
+    ru = P.bvmv_pagerank_detail(G, pu, prec=F64)[0]
+    assert rw["converged"] and rw["restarts_accepted"] == 2
+    assert float((pw - pu).abs().sum()) < 2 * (0.85 / 0.15) * 1e-6
+
+
 def _train(P, graphs, steps, K=10, seed=1):
     """Train on restart samples (inputs after K plain iterations, targets from
     the method's own converged PageRank in FP64) of the given loaded graphs."""
