@@ -94,12 +94,13 @@ def bench_batch(args, B, P, np, torch, dev):
     info = G.info()
     del enc
     prec = P.BVMV_F32_COMP
-    V = torch.from_numpy(B.teleport_sets(g.n, K, 16, seed=104).reshape(-1)).to(dev)
-    X = torch.from_numpy(np.random.default_rng(105).random((g.n, K), dtype=np.float32)).to(dev)
+    # each right-hand side is one contiguous vector: row c of a (K, n) tensor
+    V = torch.from_numpy(np.ascontiguousarray(B.teleport_sets(g.n, K, 16, seed=104).T).reshape(-1)).to(dev)
+    X = torch.from_numpy(np.random.default_rng(105).random((K, g.n), dtype=np.float32)).to(dev)
     Y = torch.empty_like(X)
     ms_batch = time_launches(lambda: P.bvmv_multiply_batch(G, X, Y, prec), max(args.steps // 10, 5),
                              max(args.warmup // 10, 2), torch)
-    x1 = X[:, 0].contiguous()
+    x1 = X[0].contiguous()
     y1 = torch.empty_like(x1)
     ms_one = time_launches(lambda: P.bvmv_multiply(G, x1, y1, prec), args.steps, args.warmup, torch)
     log("product: %d-vector %.3f ms, single %.4f ms" % (K, ms_batch, ms_one))
@@ -110,9 +111,9 @@ def bench_batch(args, B, P, np, torch, dev):
     res = P.bvmv_pagerank(G, p, teleport=V, prec=prec, k=K)
     torch.cuda.synchronize()
     s_batch = time.perf_counter() - t
-    Vc = V.view(g.n, K)
+    Vc = V.view(K, g.n)
     p1 = torch.empty(g.n, dtype=torch.float32, device=dev)
-    cols = [Vc[:, c].contiguous() for c in range(K)]
+    cols = [Vc[c].contiguous() for c in range(K)]
     P.bvmv_pagerank(G, p1, teleport=cols[0], prec=prec)
     torch.cuda.synchronize()
     t = time.perf_counter()

@@ -20,8 +20,9 @@
  *   - Vectors passed as `const void*` / `void*` are DEVICE pointers owned by
  *     the caller, of the element type the precision selects (double for
  *     BVMV_F64, float otherwise), contiguous unless a leading dimension is
- *     given.  Multi-vector arguments are node-major: element (v, c) of an
- *     n x k block lives at v * ld + c.
+ *     given.  Multi-vector arguments are column-major: element (v, c) of an
+ *     n x k block lives at c * ld + v, so each right-hand side is one
+ *     contiguous vector.
  *   - `stream` is a hipStream_t (NULL = the null stream).  Calls enqueue work
  *     on it and return without synchronising, except where stated.
  *   - Return value: a bvmv_status.  On a negative status the outputs are
@@ -93,10 +94,11 @@ int bvmv_load(const void* bitstream, size_t nbytes, const bvmv_load_opts* opts, 
  * Deterministic: the same inputs give bit-identical y. */
 int bvmv_multiply(bvmv_graph* g, const void* x, void* y, int prec, void* stream);
 
-/* Y = A X for k right-hand sides at once (one pass over the layout serves all
- * k products).  X, Y: node-major n x k blocks with leading dimension ld >= k
- * (elements).  1 <= k <= 64.  prec: BVMV_F32 or BVMV_F32_COMP (float) or
- * BVMV_F64 (double). */
+/* Y = A X for k right-hand sides at once: every tile of the layout is decoded
+ * once and multiplies the k columns one after another.  X, Y: column-major
+ * n x k blocks with leading dimension ld >= n (elements).  1 <= k <= 64.
+ * prec: BVMV_F32 or BVMV_F32_COMP (float) or BVMV_F64 (double).  Column c of
+ * Y is bit-identical to bvmv_multiply of column c of X. */
 int bvmv_multiply_batch(bvmv_graph* g, const void* X, void* Y, int k, int64_t ld, int prec, void* stream);
 
 typedef struct bvmv_mlp bvmv_mlp;  /* the warm-restart network (declared with its entry points below) */
@@ -138,7 +140,7 @@ typedef struct {
  * Per iteration: delta = sum of p_u over d_u = 0 (double); z_u = p_u / d_u;
  * y = B z (the compressed product); p'_v = (1-beta) v_v + beta (y_v + delta v_v);
  * residual = ||p' - p||_1 (double).  Dangling mass goes to the teleport vector.
- * teleport: device n x k node-major (ld = k) of the prec's element type, each
+ * teleport: device n x k column-major (ld = n) of the prec's element type, each
  *   column a probability vector; NULL = uniform 1/n (k must then be 1, or the
  *   graph a group: each member graph gets its own uniform vector).
  * start: device n x k start vectors; NULL = the teleport vector.

@@ -215,13 +215,14 @@ def bvmv_multiply(g: Graph, x, y, prec=BVMV_F32_COMP, stream=None):
 
 
 def bvmv_multiply_batch(g: Graph, X, Y, prec=BVMV_F32_COMP, stream=None):
-    """X, Y: (n, k) node-major device tensors (row stride = ld)."""
+    """X, Y: (k, n) contiguous device tensors, row c = right-hand side c (the
+    column-major n x k blocks of the C interface, leading dimension n)."""
     p = _prec(prec)
     dt = _vec_dtype(p)
-    if X.dim() != 2 or X.shape != Y.shape or X.shape[0] != g.n:
-        raise ValueError("X and Y must be (n, k)")
-    k = X.shape[1]
-    _check(load_library().bvmv_multiply_batch(g.handle, _dev_ptr(X, dt), _dev_ptr(Y, dt), k, k, p,
+    if X.dim() != 2 or X.shape != Y.shape or X.shape[1] != g.n:
+        raise ValueError("X and Y must be (k, n)")
+    k = X.shape[0]
+    _check(load_library().bvmv_multiply_batch(g.handle, _dev_ptr(X, dt), _dev_ptr(Y, dt), k, g.n, p,
                                               _stream_ptr(stream)))
 
 

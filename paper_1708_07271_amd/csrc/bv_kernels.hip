@@ -566,7 +566,7 @@ struct TileCtx {
 template <class M>
 struct EpiStore {
   typename M::X* y;
-  __device__ void operator()(const TileCtx& tc, const typename M::CAcc* s_y, unsigned char*) const {
+  __device__ void operator()(const TileCtx& tc, const typename M::CAcc* s_y, unsigned char*, int) const {
     for (uint32_t r = lane_id(); r < tc.nrows; r += 64) y[tc.row0 + r] = M::out(s_y[r]);
   }
 };
@@ -640,7 +640,7 @@ __global__ void __launch_bounds__(kThreads) pr_finish_kernel(PRState* st_all, co
 template <class M>
 struct EpiPR {
   PRArgs a;
-  __device__ void operator()(const TileCtx& tc, const typename M::CAcc* s_y, unsigned char* s_blk) const {
+  __device__ void operator()(const TileCtx& tc, const typename M::CAcc* s_y, unsigned char* s_blk, int) const {
     using X = typename M::X;
     const X* p = static_cast<const X*>(a.p_cur);
     X* pn = static_cast<X*>(a.p_new);
@@ -666,7 +666,167 @@ struct EpiPR {
   }
 };
 
+// Epilogues of the multi-vector tile kernel.  prepare(tc) runs once per wave
+// before the tile is decoded and returns per-lane state; fetch(tc, c) issues
+// vector c's global loads one vector ahead of their use; skip(st, c) passes
+// over vector c (block-uniform); col(...) takes vector c's sums; finish(...)
+// runs once per block after the last vector, with every wave present.
+constexpr int kEpiRows = kTileRowsMax / 64;  // rows of a tile per lane
+
+__device__ __forceinline__ double readlane_f64(double v, int l) {
+  const uint64_t u = __double_as_longlong(v);
+  const uint32_t lo = __builtin_amdgcn_readlane(uint32_t(u), l), hi = __builtin_amdgcn_readlane(uint32_t(u >> 32), l);
+  return __longlong_as_double(int64_t((uint64_t(hi) << 32) | lo));
+}
+
+// Column c of a column-major block (leading dimension ld) for the tile's rows.
+template <class M>
+struct EpiStoreCols {
+  typename M::X* y;
+  int64_t ld;
+  struct State {};
+  struct Fetch {};
+  __device__ State prepare(const TileCtx&) const { return {}; }
+  __device__ Fetch fetch(const TileCtx&, int) const { return {}; }
+  __device__ bool skip(const State&, int) const { return false; }
+  __device__ void col(const TileCtx& tc, const typename M::CAcc* s_y, int c, State&, const Fetch&) const {
+    typename M::X* yc = y + int64_t(c) * ld + tc.row0;
+    for (uint32_t r = lane_id(); r < tc.nrows; r += 64) yc[r] = M::out(s_y[r]);
+  }
+  __device__ void finish(const State&, unsigned char*, size_t, uint32_t) const {}
+};
+
+// Personalized PageRank update of Eq. (1) for right-hand sides c = 0 .. k-1
+// (k <= 64): each its own teleport column, dangling mass and stopping state
+// st[c]; p, z and the teleport vectors are column-major with leading
+// dimension n.  Lane c of every wave holds column c's state (read once) and
+// the wave's residual and dangling partial sums of column c; finish() adds
+// the block's waves and stores column c's pair to slot c * blocks + block.
+// Columns that are done are passed over and their slots left alone.
+template <class M>
+struct EpiPRCols {
+  using X = typename M::X;
+  PRArgs a;
+  int64_t n;
+  struct State {
+    uint64_t done;  // bit c: column c is done
+    double delta, inv_n, rs, dg;
+    int32_t d[kEpiRows];  // out-degrees of the lane's rows lane + 64 q
+  };
+  struct Fetch {
+    X p[kEpiRows], t[kEpiRows];  // p and the teleport value of the lane's rows
+  };
+  __device__ State prepare(const TileCtx& tc) const {
+    const uint32_t lane = lane_id();
+    const bool has = lane < uint32_t(a.k);
+    const PRState* st = a.st + (has ? lane : 0u);
+    State S;
+    S.delta = st->delta;
+    S.inv_n = st->inv_n;
+    S.done = __ballot(has && st->done != 0);
+    S.rs = 0.0;
+    S.dg = 0.0;
+#pragma unroll
+    for (int q = 0; q < kEpiRows; ++q) {
+      const uint32_t r = lane + 64u * q;
+      S.d[q] = a.outdeg[r < tc.nrows ? tc.row0 + r : 0u];
+    }
+    return S;
+  }
+  // (rows past the tile read element 0: every address is in bounds)
+  __device__ Fetch fetch(const TileCtx& tc, int c) const {
+    const X* p = static_cast<const X*>(a.p_cur);
+    const X* tele = static_cast<const X*>(a.tele);
+    Fetch f;
+#pragma unroll
+    for (int q = 0; q < kEpiRows; ++q) {
+      const uint32_t r = lane_id() + 64u * q;
+      const int64_t e = r < tc.nrows ? int64_t(c) * n + tc.row0 + r : 0;
+      f.p[q] = p[e];
+      f.t[q] = tele ? tele[e] : X(0);
+    }
+    return f;
+  }
+  __device__ bool skip(const State& S, int c) const { return (S.done >> c) & 1u; }
+  __device__ void col(const TileCtx& tc, const typename M::CAcc* s_y, int c, State& S, const Fetch& f) const {
+    const int64_t base = int64_t(c) * n + tc.row0;
+    X* pn = static_cast<X*>(a.p_new) + base;
+    X* zn = static_cast<X*>(a.z_new) + base;
+    const double delta = readlane_f64(S.delta, c), inv_n = readlane_f64(S.inv_n, c), beta = a.beta;
+    double rs = 0.0, dg = 0.0;
+#pragma unroll
+    for (int q = 0; q < kEpiRows; ++q) {
+      const uint32_t r = lane_id() + 64u * q;
+      if (r < tc.nrows) {
+        const double y = M::to_d(s_y[r]);
+        const double t = a.tele ? double(f.t[q]) : inv_n;
+        const X pnew = X((1.0 - beta) * t + beta * (y + delta * t));
+        pn[r] = pnew;
+        const int32_t d = S.d[q];
+        zn[r] = d > 0 ? pnew / X(d) : X(0);
+        rs += fabs(double(pnew) - double(f.p[q]));
+        if (d == 0) dg += double(pnew);
+      }
+    }
+    rs = wave_sum_f64(rs);
+    dg = wave_sum_f64(dg);
+    if (lane_id() == uint32_t(c)) {
+      S.rs = rs;
+      S.dg = dg;
+    }
+  }
+  // smem: the block's LDS, wave w's region at w * wbytes (>= 1 KiB each, free
+  // once the wave's last vector is done)
+  __device__ void finish(const State& S, unsigned char* smem, size_t wbytes, uint32_t slot) const {
+    const uint32_t wave = threadIdx.x >> 6, lane = lane_id();
+    reinterpret_cast<double2*>(smem + wave * wbytes)[lane] = make_double2(S.rs, S.dg);
+    __syncthreads();
+    if (wave == 0 && lane < uint32_t(a.k) && !((S.done >> lane) & 1u)) {
+      double R = 0.0, D = 0.0;
+      for (int w = 0; w < kWaves; ++w) {
+        const double2 v = reinterpret_cast<const double2*>(smem + w * wbytes)[lane];
+        R += v.x;
+        D += v.y;
+      }
+      const size_t q = size_t(lane) * gridDim.x + slot;
+      a.slots[2 * q] = R;
+      a.slots[2 * q + 1] = D;
+    }
+  }
+};
+
 // --------------------------------------------------------------- tile kernel
+// The vectors a tile kernel multiplies (col(c) = the first element of vector
+// c).  OneCol: one vector x, whose window values come with the tile's other
+// loads.  Cols: columns 0 .. k-1 of a column-major block (element (v, c) at
+// c * ld + v), taken one after another by the same decoded tile.
+template <class X>
+struct OneCol {
+  const X* x;
+  static constexpr bool kMulti = false;
+  __device__ int count() const { return 1; }
+  __device__ const X* col(int) const { return x; }
+};
+template <class X>
+struct Cols {
+  const X* x;
+  int k;
+  int64_t ld;
+  static constexpr bool kMulti = true;
+  __device__ int count() const { return k; }
+  __device__ const X* col(int c) const { return x + int64_t(c) * ld; }
+};
+
+// The lane's first SV values of column c's x window (clamped addresses).
+template <class X, int SV, class Src>
+__device__ __forceinline__ void load_window(const Src& src, int64_t win0, uint32_t n, int c, X (&xs)[SV]) {
+  const uint32_t lane = lane_id();
+  const uint32_t w = (n + 63) / 64, b = min(n, lane * w), e = min(n, b + w);
+  const X* xc = src.col(c) + win0;
+#pragma unroll
+  for (int j = 0; j < SV; ++j) xs[j] = xc[e > b ? min(b + uint32_t(j), e - 1) : 0u];
+}
+
 // Global data of one tile, loaded before any of it is used: the first round
 // of the lane's singles chunk, its rows' info, and its first SV values of
 // the x window.
@@ -680,9 +840,9 @@ struct TileLoads {
 // Issue a tile's loads into `ld` from safe (clamped) addresses only; the
 // values are masked where process_tile uses them, so all the loads are in
 // flight together before the first is waited for.
-template <class M, int RPL, int SV>
-__device__ __forceinline__ void issue_loads(const DevLayout& L, const TileDesc& td,
-                                            const typename M::X* __restrict__ x, TileLoads<M, RPL, SV>& ld) {
+template <class M, int RPL, int SV, class Src>
+__device__ __forceinline__ void issue_loads(const DevLayout& L, const TileDesc& td, const Src& src,
+                                            TileLoads<M, RPL, SV>& ld) {
   const uint32_t lane = lane_id(), r0 = lane * RPL;
   const uint32_t n16 = td.n16;
   if (n16) {
@@ -696,28 +856,20 @@ __device__ __forceinline__ void issue_loads(const DevLayout& L, const TileDesc& 
     ld.inf[q] = L.info[r];
     ld.ns[q] = uint32_t(L.ns[r]);
   }
-  if constexpr (!M::kInt) {
-    const uint32_t n = td.winlen;
-    if (n) {
-      const uint32_t c = (n + 63) / 64, b = min(n, lane * c), e = min(n, b + c);
-      const typename M::X* xw = x + td.win0;
-#pragma unroll
-      for (int j = 0; j < SV; ++j) ld.xs[j] = xw[e > b ? min(b + uint32_t(j), e - 1) : 0u];
-    }
-  }
+  if constexpr (!M::kInt && !Src::kMulti)
+    if (td.winlen) load_window(src, td.win0, td.winlen, 0, ld.xs);
 }
 
 // Stage a tile's x window of n values into the LDS array Z (doubles): Z[0] =
 // 0, Z[2j+2] = x[win0+j] for j < n, and, with `prefix`, Z[2p+1] = P[p] =
 // x[win0] + ... + x[win0+p-1] for p <= n (odd entries are left undefined
 // otherwise; no entry reads them then).  Lane l takes the ceil(n/64)
-// consecutive values from l*ceil(n/64) on: the first SV come from the loads
-// issued with the tile's others, a longer chunk loads the rest here.  A wave
+// consecutive values from l*ceil(n/64) on: the first SV are in xs, a longer
+// chunk reads the rest here through xw(j), the window's j-th value.  A wave
 // scan of the lanes' sums gives each lane's first prefix.  Z + 1 is 16-byte
 // aligned, so every (P[j], x[j]) pair is one 16-byte LDS write.
-template <class X, int SV>
-__device__ __forceinline__ void stage_regs(const X (&xs)[SV], const X* __restrict__ xw, uint32_t n, bool prefix,
-                                           double* Z) {
+template <class X, int SV, class XA>
+__device__ __forceinline__ void stage_regs(const X (&xs)[SV], XA xw, uint32_t n, bool prefix, double* Z) {
   const uint32_t lane = lane_id();
   const uint32_t ch = (n + 63) / 64;
   const uint32_t b = min(n, lane * ch), e = min(n, b + ch);
@@ -726,7 +878,7 @@ __device__ __forceinline__ void stage_regs(const X (&xs)[SV], const X* __restric
 #pragma unroll
     for (int j = 0; j < SV; ++j)
       if (b + uint32_t(j) < e) t += double(xs[j]);
-    for (uint32_t k = b + SV; k < e; ++k) t += double(xw[k]);
+    for (uint32_t k = b + SV; k < e; ++k) t += double(xw(k));
   }
   double run = 0.0;
   if (prefix) {
@@ -744,18 +896,20 @@ __device__ __forceinline__ void stage_regs(const X (&xs)[SV], const X* __restric
       run += xv;
     }
   for (uint32_t k = b + SV; k < e; ++k) {
-    const double xv = double(xw[k]);
+    const double xv = double(xw(k));
     Zp[k] = make_double2(run, xv);
     run += xv;
   }
 }
 
 // One tile by one wavefront, its global data already in `ld`: tile rows
-// [row0, row0 + nrows), lane l owns rows [l * RPL, (l + 1) * RPL).
-template <class M, int RPL, int SV, class Epi>
+// [row0, row0 + nrows), lane l owns rows [l * RPL, (l + 1) * RPL).  The
+// decode (offsets, row ranks, chunk row ends) is done once; then for each
+// vector of the source its window is staged and steps 3 to 6 run.
+template <class M, int RPL, int SV, class Src, class Epi>
 __device__ __forceinline__ void process_tile(const DevLayout& L, const TileDesc& td, const TileLoads<M, RPL, SV>& ld,
-                                             const typename M::X* __restrict__ x, const Epi& epi, uint32_t slot,
-                                             unsigned char* ws, unsigned char* s_blk) {
+                                             const Src& src, const Epi& epi, uint32_t slot, unsigned char* ws,
+                                             unsigned char* s_blk) {
   using X = typename M::X;
   using PAcc = typename M::PAcc;
   using CAcc = typename M::CAcc;
@@ -765,6 +919,15 @@ __device__ __forceinline__ void process_tile(const DevLayout& L, const TileDesc&
   CAcc* s_y = reinterpret_cast<CAcc*>(ws + Cv::y());
   PAcc* s_carry = reinterpret_cast<PAcc*>(ws + Cv::carry());
   double* Z = reinterpret_cast<double*>(ws + Cv::Z());
+  static_assert(!(Src::kMulti && M::kInt), "the integer mode multiplies one vector");
+  // the multi-vector epilogue's per-lane state, read before the decode
+  const TileCtx tc{td.row0, td.nrows, td.graph, slot};
+  [[maybe_unused]] auto S = [&] {
+    if constexpr (Src::kMulti)
+      return epi.prepare(tc);
+    else
+      return 0;
+  }();
   const uint32_t lane = lane_id();
   const uint32_t nrows = td.nrows;
   const int64_t win0 = td.win0;
@@ -792,9 +955,6 @@ __device__ __forceinline__ void process_tile(const DevLayout& L, const TileDesc&
     inf[q] = has ? ld.inf[q] : 0u;
     ns[q] = has ? ld.ns[q] : 0u;
   }
-  // 1. the x window (with its prefix sums when the tile has intervals) into Z
-  if constexpr (!M::kInt) stage_regs<X, SV>(ld.xs, x + win0, winlen, td.nint != 0, Z);
-
   // 2. offsets of the lanes' rows in the streams, and of their row ends
   uint32_t c16[RPL], cw[RPL], s16 = 0, sw = 0;
   uint64_t m16[RPL], mw[RPL];
@@ -831,6 +991,37 @@ __device__ __forceinline__ void process_tile(const DevLayout& L, const TileDesc&
   }
   wave_sync();
 
+  X xs_next[SV];
+  [[maybe_unused]] auto f_next = [&] {
+    if constexpr (Src::kMulti)
+      return epi.fetch(tc, 0);
+    else
+      return 0;
+  }();
+  if constexpr (Src::kMulti)
+    if (winlen) load_window(src, win0, winlen, 0, xs_next);
+  for (int col = 0; col < src.count(); ++col) {
+  [[maybe_unused]] const auto f_cur = f_next;
+  const X* xcol = src.col(col);
+  // 1. the x window of this vector (with its prefix sums when the tile has
+  //    intervals) into Z; the next vector's window values are loaded meanwhile
+  //    (also when this vector is passed over, so that they stay in step)
+  if constexpr (!M::kInt) {
+    if constexpr (Src::kMulti) {
+      X xs[SV];
+#pragma unroll
+      for (int j = 0; j < SV; ++j) xs[j] = xs_next[j];
+      if (col + 1 < src.count()) {
+        f_next = epi.fetch(tc, col + 1);
+        if (winlen) load_window(src, win0, winlen, col + 1, xs_next);
+      }
+      if (epi.skip(S, col)) continue;
+      stage_regs<X, SV>(xs, [&](uint32_t j) { return xcol[win0 + j]; }, winlen, td.nint != 0, Z);
+    } else {
+      stage_regs<X, SV>(ld.xs, [&](uint32_t j) { return xcol[win0 + j]; }, winlen, td.nint != 0, Z);
+    }
+  }
+  wave_sync();
   // 3. singles (with the intervals' prefix pairs), then wide entries: flat
   //    passes cut at the row-end bits; the owner adds its rows' pieces in
   //    registers
@@ -865,12 +1056,15 @@ __device__ __forceinline__ void process_tile(const DevLayout& L, const TileDesc&
         if (c16[q]) a[q] = flat_row_sum<M>(o16[q], o16[q] + c16[q], C16, invC, s_seg[k16[q]], s_carry);
     }
   }
-  // window value of column win0 + c, else the global one
+  // window value of column win0 + c, else the global one (read through a
+  // global address-space pointer, so that the two loads stay apart: merged
+  // into one flat load, the double-precision instances do not compile)
   auto xval = [&](int64_t c) -> X {
     if constexpr (M::kInt) {
       return 1;
     } else {
-      return uint64_t(c) < winlen ? X(Z[2 * c + 2]) : x[win0 + c];
+      using GX = const __attribute__((address_space(1))) X;
+      return uint64_t(c) < winlen ? X(Z[2 * c + 2]) : ((GX*)xcol)[win0 + c];
     }
   };
   if (nwide) {
@@ -968,15 +1162,24 @@ __device__ __forceinline__ void process_tile(const DevLayout& L, const TileDesc&
   }
   wave_sync();
   // 6. epilogue
-  epi(TileCtx{td.row0, nrows, td.graph, slot}, s_y, s_blk);
+  if constexpr (Src::kMulti)
+    epi.col(tc, s_y, col, S, f_cur);
+  else
+    epi(tc, s_y, s_blk, col);
+  wave_sync();  // y is read before the next vector's pieces overwrite it
+  }
+  if constexpr (Src::kMulti) {
+    const size_t wb = Cv{L.wcap}.wave_bytes();
+    epi.finish(S, s_blk - kWaves * wb, wb, slot);
+  }
 }
 
 // Tile kernel: block b takes the group of kWaves consecutive tiles from
-// kWaves * b on, wave w the w-th.  A block of a member that is done
-// (skip_done) returns at once.
-template <class M, int RPL, int SV, class Epi>
-__global__ void __launch_bounds__(kThreads) bv_wave_kernel(DevLayout L, const typename M::X* __restrict__ x,
-                                                           Epi epi, const PRState* __restrict__ skip_done) {
+// kWaves * b on, wave w the w-th, and multiplies the source's vectors.  A
+// block of a member that is done (skip_done) returns at once.
+template <class M, int RPL, int SV, class Src, class Epi>
+__global__ void __launch_bounds__(kThreads) bv_wave_kernel(DevLayout L, Src src, Epi epi,
+                                                           const PRState* __restrict__ skip_done) {
   using Cv = WaveCarve<M, RPL>;
   extern __shared__ __align__(16) unsigned char smem[];
   const uint32_t wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
@@ -986,8 +1189,8 @@ __global__ void __launch_bounds__(kThreads) bv_wave_kernel(DevLayout L, const ty
   const TileDesc td = L.tiles[blockIdx.x * kWaves + wave];
   if (skip_done && skip_done[td.graph].done) return;  // a block holds one member's tiles
   TileLoads<M, RPL, SV> ld;
-  issue_loads<M, RPL, SV>(L, td, x, ld);
-  process_tile<M, RPL, SV>(L, td, ld, x, epi, blockIdx.x, ws, s_blk);
+  issue_loads<M, RPL, SV>(L, td, src, ld);
+  process_tile<M, RPL, SV>(L, td, ld, src, epi, blockIdx.x, ws, s_blk);
 }
 
 // PageRank start: p0 = start (or teleport, or uniform), z0 = p0 / d, dangling mass.
@@ -1024,6 +1227,40 @@ __global__ void __launch_bounds__(kThreads) pr_init_kernel(const uint32_t* __res
   }
   dg = wave_sum_f64(dg);
   pr_block_partial(0.0, dg, slots, s_blk, blockIdx.x);
+}
+
+// Personalized PageRank start for k right-hand sides on the tile kernel's
+// grid: p0 = start (or the teleport columns, or uniform), z0 = p0 / d, and
+// each column's dangling mass per block (slot c * blocks + block).  Every
+// n x k block is column-major with leading dimension n.
+template <class M>
+__global__ void __launch_bounds__(kThreads) pr_init_cols_kernel(DevLayout L, int k, const void* start_,
+                                                                const void* tele_, void* p0_, void* z0_,
+                                                                const int32_t* __restrict__ outdeg,
+                                                                const PRState* st_all, double* slots) {
+  using X = typename M::X;
+  __shared__ __align__(16) unsigned char s_blk[256];
+  const uint32_t wave = threadIdx.x >> 6, lane = lane_id();
+  const TileDesc td = L.tiles[blockIdx.x * kWaves + wave];
+  const X* start = static_cast<const X*>(start_);
+  const X* tele = static_cast<const X*>(tele_);
+  X* p0 = static_cast<X*>(p0_);
+  X* z0 = static_cast<X*>(z0_);
+  for (int c = 0; c < k; ++c) {
+    double dg = 0.0;
+    for (uint32_t r = lane; r < td.nrows; r += 64) {
+      const uint32_t v = td.row0 + r;
+      const int64_t e = int64_t(c) * L.n + v;
+      const X pv = start ? start[e] : (tele ? tele[e] : X(st_all[c].inv_n));
+      p0[e] = pv;
+      const int32_t d = outdeg[v];
+      z0[e] = d > 0 ? pv / X(d) : X(0);
+      if (d == 0) dg += double(pv);
+    }
+    dg = wave_sum_f64(dg);
+    pr_block_partial(0.0, dg, slots, s_blk, uint32_t(c) * gridDim.x + blockIdx.x);
+    __syncthreads();  // s_blk is read before the next column writes it
+  }
 }
 
 // ----------------------------------------------------------- warm restarts
@@ -1242,320 +1479,19 @@ __global__ void __launch_bounds__(kThreads) csr_wave_kernel(DevCsr C, const type
     s_y[lane] = M::chain(a);
   }
   wave_sync();
-  epi(TileCtx{td.row0, nrows, 0u, blockIdx.x}, s_y, s_blk);
+  epi(TileCtx{td.row0, nrows, 0u, blockIdx.x}, s_y, s_blk, 0);
 }
 
-// -------------------------------------------------------- multi-vector kernel
-// Y = A X for k right-hand sides, node-major (element (v, c) at v * ld + c).
-// One block per tile.  Lanes map to right-hand sides: a team of G lanes
-// handles one row, walking the row's entries (broadcast LDS reads) while
-// each lane gathers its column of X, so one pass over the layout serves all
-// k products.  X is not staged (a window would hold G values per column);
-// intervals are summed directly.  Partials live in LDS as T x G
-// accumulators and the reuse levels are resolved in place; right-hand sides
-// beyond G take further passes over the staged streams.
-struct RowsStaged {
-  uint32_t nlong, maxlvl;
-};
-
-__device__ __forceinline__ RowsStaged block_scan_rows(const TileDesc& td, const uint32_t* s_info, const uint32_t* s_ns,
-                                                      uint32_t* s_o16, uint32_t* s_ow, uint32_t* s_ol,
-                                                      uint32_t* s_list, unsigned char* s_red) {
-  __shared__ uint32_t s_nlong, s_maxlvl;
-  const uint32_t tid = threadIdx.x;
-  const uint32_t nrows = td.nrows;  // <= 64 < 256: one row per thread
-  uint64_t A = 0, Bv = 0;
-  uint32_t lvl = 0;
-  if (tid < nrows) {
-    const uint32_t inf = s_info[tid];
-    const uint64_t nw = inf >> 13;
-    if (inf & kInfoLong) Bv = (uint64_t(1) << 16) | ((nw | (uint64_t(s_ns[tid]) << 19)) << 28);
-    else A = uint64_t(s_ns[tid]) | (nw << 32);
-    lvl = (inf >> 4) & 15u;
-  }
-  if (tid == 0) s_maxlvl = 0;
-  __syncthreads();
-  if (lvl) atomicMax(&s_maxlvl, lvl);
-  uint64_t totA, totB;
-  const uint64_t ra = block_excl_scan_u64(A, reinterpret_cast<uint64_t*>(s_red), totA);
-  const uint64_t rb = block_excl_scan_u64(Bv, reinterpret_cast<uint64_t*>(s_red), totB);
-  if (tid < nrows) {
-    s_o16[tid] = uint32_t(ra & 0xFFFFFFFFu);
-    s_ow[tid] = uint32_t(ra >> 32);
-    s_ol[tid] = uint32_t(rb >> 28);
-    if (s_info[tid] & kInfoLong) s_list[(rb >> 16) & 0xFFFu] = tid;
-  }
-  if (tid == 0) s_nlong = uint32_t((totB >> 16) & 0xFFFu);
-  __syncthreads();
-  return RowsStaged{s_nlong, s_maxlvl};
-}
-
-template <class M, int G>
-struct BatchCarve {
-  using PAcc = typename M::PAcc;
-  using CAcc = typename M::CAcc;
-  uint32_t T, SB;  // rows per tile (<= 256, one per thread), staged bytes
-  __host__ __device__ size_t u() const { return align16((size_t(T) + 1) * 4); }
-  __host__ __device__ size_t acc() const { return 6 * u(); }
-  __host__ __device__ size_t tmp() const { return acc() + align16(size_t(T) * G * sizeof(CAcc)); }
-  // two doubles per thread for the PageRank epilogue's per-column sums
-  __host__ __device__ size_t pr() const { return tmp() + align16(kThreads * sizeof(PAcc)); }
-  __host__ __device__ size_t data() const { return pr() + 2 * kThreads * sizeof(double); }
-  __host__ __device__ size_t red() const { return data() + align16(size_t(SB)); }
-  __host__ __device__ size_t total() const { return red() + 256; }
-};
-
-// Multi-vector epilogues, called by every thread for the right-hand sides
-// [c0, c0 + G) once their sums are in s_acc (row r, column c0 + l at r*G + l).
-template <class M>
-struct EpiStoreBatch {
-  typename M::X* Y;
-  int k;
-  int64_t ld;
-  template <int G>
-  __device__ void run(const TileDesc& td, const typename M::CAcc* s_acc, int c0, double*) const {
-    for (uint32_t idx = threadIdx.x; idx < td.nrows * G; idx += kThreads) {
-      const int cc = c0 + int(idx % G);
-      if (cc < k) Y[int64_t(td.row0 + idx / G) * ld + cc] = M::out(s_acc[idx]);
-    }
-  }
-};
-
-// Personalized PageRank update of Eq. (1) for every right-hand side c (its
-// own teleport column, dangling mass and stopping state); columns already
-// done are left alone.  Thread t always holds column c0 + t % G, so its
-// residual and dangling sums are per column; the block's sums per column go
-// to slot (c * blocks + block) for pr_finish_kernel.
-template <class M>
-struct EpiPRBatch {
-  PRArgs a;
-  template <int G>
-  __device__ void run(const TileDesc& td, const typename M::CAcc* s_acc, int c0, double* s_pr) const {
-    using X = typename M::X;
-    const X* p = static_cast<const X*>(a.p_cur);
-    X* pn = static_cast<X*>(a.p_new);
-    X* zn = static_cast<X*>(a.z_new);
-    const X* tele = static_cast<const X*>(a.tele);
-    const int k = a.k;
-    const int cc = c0 + int(threadIdx.x % G);
-    const bool act = cc < k && !a.st[cc].done;
-    double rs = 0.0, dg = 0.0;
-    if (act) {
-      const PRState& st = a.st[cc];
-      const double delta = st.delta, inv_n = st.inv_n, beta = a.beta;
-      for (uint32_t idx = threadIdx.x; idx < td.nrows * G; idx += kThreads) {
-        const uint32_t v = td.row0 + idx / G;
-        const int64_t e = int64_t(v) * k + cc;
-        const double y = M::to_d(s_acc[idx]);
-        const double t = tele ? double(tele[e]) : inv_n;
-        const X pnew = X((1.0 - beta) * t + beta * (y + delta * t));
-        pn[e] = pnew;
-        const int32_t d = a.outdeg[v];
-        zn[e] = d > 0 ? pnew / X(d) : X(0);
-        rs += fabs(double(pnew) - double(p[e]));
-        if (d == 0) dg += double(pnew);
-      }
-    }
-    s_pr[2 * threadIdx.x] = rs;
-    s_pr[2 * threadIdx.x + 1] = dg;
-    __syncthreads();
-    if (threadIdx.x < G && c0 + int(threadIdx.x) < k) {
-      double R = 0.0, D = 0.0;
-      for (uint32_t t = threadIdx.x; t < kThreads; t += G) {
-        R += s_pr[2 * t];
-        D += s_pr[2 * t + 1];
-      }
-      const size_t slot = size_t(c0 + threadIdx.x) * gridDim.x + blockIdx.x;
-      a.slots[2 * slot] = R;
-      a.slots[2 * slot + 1] = D;
-    }
-    __syncthreads();
-  }
-};
-
-template <class M, int G, class Epi>
-__global__ void __launch_bounds__(kThreads) bv_batch_kernel(DevLayout L, const typename M::X* __restrict__ X,
-                                                            int k, int64_t ld, Epi epi) {
-  using Xt = typename M::X;
-  using PAcc = typename M::PAcc;
-  using CAcc = typename M::CAcc;
-  constexpr uint32_t kTeams = kThreads / G;
-  extern __shared__ __align__(16) unsigned char smem[];
-  const TileDesc td = L.tiles[blockIdx.x];
-  const BatchCarve<M, G> cv{L.tcap, L.sbytes};
-  const size_t u = cv.u();
-  uint32_t* s_info = reinterpret_cast<uint32_t*>(smem);
-  uint32_t* s_ns = reinterpret_cast<uint32_t*>(smem + u);
-  uint32_t* s_o16 = reinterpret_cast<uint32_t*>(smem + 2 * u);
-  uint32_t* s_ow = reinterpret_cast<uint32_t*>(smem + 3 * u);
-  uint32_t* s_ol = reinterpret_cast<uint32_t*>(smem + 4 * u);
-  uint32_t* s_list = reinterpret_cast<uint32_t*>(smem + 5 * u);
-  CAcc* s_acc = reinterpret_cast<CAcc*>(smem + cv.acc());
-  PAcc* s_tmp = reinterpret_cast<PAcc*>(smem + cv.tmp());
-  double* s_pr = reinterpret_cast<double*>(smem + cv.pr());
-  unsigned char* s_data = smem + cv.data();
-  unsigned char* s_red = smem + cv.red();
-  const uint32_t tid = threadIdx.x, team = tid / G, lane = tid % G;
-  const uint32_t nrows = td.nrows;
-  {
-    const uint4* src = L.data + td.data16;
-    uint4* dst = reinterpret_cast<uint4*>(s_data);
-    const uint32_t nv = dstage_bytes(td) / 16;
-    for (uint32_t q = tid; q < nv; q += kThreads) dst[q] = src[q];
-    if (tid < nrows) {
-      s_info[tid] = L.info[td.row0 + tid];
-      s_ns[tid] = L.ns[td.row0 + tid];
-    }
-  }
-  __syncthreads();
-  const RowsStaged rs = block_scan_rows(td, s_info, s_ns, s_o16, s_ow, s_ol, s_list, s_red);
-  const uint16_t* s16 = reinterpret_cast<const uint16_t*>(s_data);
-  const uint32_t* w32 = reinterpret_cast<const uint32_t*>(s_data + dalign16u(td.n16 * 2u));
-  const int64_t win0 = td.win0;
-  for (int c0 = 0; c0 < k; c0 += G) {
-    const int c = c0 + int(lane);
-    const bool act = c < k;
-    const Xt* Xc = X + (act ? c : 0);
-    for (uint32_t r = team; r < nrows; r += kTeams) {
-      const uint32_t inf = s_info[r];
-      if (inf & kInfoLong) continue;
-      PAcc a = M::pzero();
-      // the row's columns in stream order, intervals expanded: 8 at a time
-      // are decoded (a single is a run of length 1), then their X values
-      // are loaded together, then added in order
-      uint32_t e = s_o16[r];
-      const uint32_t en = e + s_ns[r];
-      int64_t ia = 0, ib = 0;  // pending run of columns [ia, ib)
-      bool ineg = false;
-      while (ia < ib || e < en) {
-        int64_t col[8];
-        bool neg[8], ok[8];
-#pragma unroll
-        for (int j = 0; j < 8; ++j) {
-          if (ia >= ib && e < en) {
-            const uint32_t w = s16[e++];
-            const uint32_t f = w & kS16Off;
-            ineg = w & kS16Neg;
-            if (f & 1) {  // an interval pair +P[b] - P[a]: columns [a, b) of the window
-              const uint32_t f2 = s16[e++] & kS16Off;
-              ia = win0 + (f2 >> 1);
-              ib = win0 + (f >> 1);
-            } else {
-              ia = win0 + int64_t(f >> 1) - 1;
-              ib = ia + 1;
-            }
-          }
-          ok[j] = ia < ib;
-          col[j] = ok[j] ? ia : win0;
-          neg[j] = ineg;
-          if (ok[j]) ++ia;
-        }
-        Xt v[8];
-#pragma unroll
-        for (int j = 0; j < 8; ++j) v[j] = (act && ok[j]) ? Xc[col[j] * ld] : Xt(0);
-#pragma unroll
-        for (int j = 0; j < 8; ++j) M::padd(a, neg[j] ? -v[j] : v[j]);
-      }
-      for (uint32_t e2 = s_ow[r], en2 = s_ow[r] + (inf >> 13); e2 < en2; e2 += 8) {
-        Xt v[8];
-        bool neg[8];
-#pragma unroll
-        for (int j = 0; j < 8; ++j) {
-          const bool okj = e2 + j < en2;
-          const uint32_t w = okj ? w32[e2 + j] : 0u;
-          const int64_t colj = win0 + int64_t(w & kWideOff) - int64_t(kWideBias);
-          neg[j] = w & kWideNeg;
-          v[j] = (act && okj) ? Xc[colj * ld] : Xt(0);
-        }
-#pragma unroll
-        for (int j = 0; j < 8; ++j) M::padd(a, neg[j] ? -v[j] : v[j]);
-      }
-      s_acc[r * G + lane] = M::chain(a);
-    }
-    for (uint32_t l = 0; l < rs.nlong; ++l) {
-      const uint32_t r = s_list[l];
-      const uint64_t len = uint64_t(s_info[r] >> 13) | (uint64_t(s_ns[r]) << 19);
-      const uint32_t* e = L.longs + size_t(td.long0) + s_ol[r];
-      PAcc a = M::pzero();
-      for (uint64_t q = team; q < len; q += kTeams) {
-        const uint32_t w = e[q];
-        const int64_t col = win0 + int64_t(w & 0x7FFFFFFFu) - int64_t(kLongBias);
-        const Xt v = act ? Xc[col * ld] : Xt(0);
-        M::padd(a, (w & 0x80000000u) ? -v : v);
-      }
-      s_tmp[team * G + lane] = a;
-      __syncthreads();
-      if (team == 0) {
-        PAcc sum = s_tmp[lane];
-        for (uint32_t t = 1; t < kTeams; ++t) sum = M::pcomb(sum, s_tmp[t * G + lane]);
-        s_acc[r * G + lane] = M::chain(sum);
-      }
-      __syncthreads();
-    }
-    __syncthreads();
-    for (uint32_t lv = 1; lv <= rs.maxlvl; ++lv) {
-      for (uint32_t idx = tid; idx < nrows * G; idx += kThreads) {
-        const uint32_t inf = s_info[idx / G];
-        if (((inf >> 4) & 15u) == lv) s_acc[idx] = M::comb(s_acc[idx - (inf & 15u) * G], s_acc[idx]);
-      }
-      __syncthreads();
-    }
-    epi.template run<G>(td, s_acc, c0, s_pr);
-    __syncthreads();
-  }
-}
-
-// Personalized PageRank start for k right-hand sides: p0 = start (or the
-// teleport columns, or uniform), z0 = p0 / d, and each column's dangling mass
-// per block (slot c * blocks + block), folded by pr_finish_kernel.
-template <class M, int G>
-__global__ void __launch_bounds__(kThreads) pr_init_batch_kernel(DevLayout L, int k, const void* start_,
-                                                                 const void* tele_, void* p0_, void* z0_,
-                                                                 const int32_t* __restrict__ outdeg,
-                                                                 const PRState* st, double* slots) {
-  using X = typename M::X;
-  __shared__ double s_pr[kThreads];
-  const TileDesc td = L.tiles[blockIdx.x];
-  const X* start = static_cast<const X*>(start_);
-  const X* tele = static_cast<const X*>(tele_);
-  X* p0 = static_cast<X*>(p0_);
-  X* z0 = static_cast<X*>(z0_);
-  for (int c0 = 0; c0 < k; c0 += G) {
-    const int cc = c0 + int(threadIdx.x % G);
-    double dg = 0.0;
-    if (cc < k) {
-      for (uint32_t idx = threadIdx.x; idx < td.nrows * G; idx += kThreads) {
-        const uint32_t v = td.row0 + idx / G;
-        const int64_t e = int64_t(v) * k + cc;
-        const X pv = start ? start[e] : (tele ? tele[e] : X(st[cc].inv_n));
-        p0[e] = pv;
-        const int32_t d = outdeg[v];
-        z0[e] = d > 0 ? pv / X(d) : X(0);
-        if (d == 0) dg += double(pv);
-      }
-    }
-    s_pr[threadIdx.x] = dg;
-    __syncthreads();
-    if (threadIdx.x < G && c0 + int(threadIdx.x) < k) {
-      double D = 0.0;
-      for (uint32_t t = threadIdx.x; t < kThreads; t += G) D += s_pr[t];
-      const size_t slot = size_t(c0 + threadIdx.x) * gridDim.x + blockIdx.x;
-      slots[2 * slot] = 0.0;
-      slots[2 * slot + 1] = D;
-    }
-    __syncthreads();
-  }
-}
-
-// p_out column c = the buffer holding column c's final iterate.
+// p_out column c (column-major, leading dimension n; column c = blockIdx.y)
+// = the buffer holding column c's final iterate.
 template <class X>
 __global__ void __launch_bounds__(kThreads) pr_select_kernel(const PRState* __restrict__ st, const X* __restrict__ p0,
                                                              const X* __restrict__ p1, X* __restrict__ out,
-                                                             int64_t total, int k) {
-  for (int64_t e = int64_t(blockIdx.x) * kThreads + threadIdx.x; e < total; e += int64_t(gridDim.x) * kThreads) {
-    const int c = int(e % k);
-    out[e] = st[c].final_buf ? p1[e] : p0[e];
-  }
+                                                             int64_t n) {
+  const int64_t base = int64_t(blockIdx.y) * n;
+  const X* src = (st[blockIdx.y].final_buf ? p1 : p0) + base;
+  for (int64_t v = int64_t(blockIdx.x) * kThreads + threadIdx.x; v < n; v += int64_t(gridDim.x) * kThreads)
+    out[base + v] = src[v];
 }
 
 // ------------------------------------------------------------- dispatching
@@ -1576,31 +1512,43 @@ size_t tile_lds(const DevLayout& L) {
   }
 }
 
-template <class M, int RPL, int SV, class Epi>
-hipError_t launch_tile_sv(const DevLayout& L, const void* x, const Epi& epi, const PRState* skip, hipStream_t s) {
+template <class M, int RPL, int SV, class Src, class Epi>
+hipError_t launch_tile_sv(const DevLayout& L, const Src& src, const Epi& epi, const PRState* skip, hipStream_t s) {
   const size_t smem = WaveCarve<M, RPL>{L.wcap}.block_bytes();
-  auto k = bv_wave_kernel<M, RPL, SV, Epi>;
+  // a multi-vector epilogue combines 64 pairs of doubles per wave region
+  if (Src::kMulti && WaveCarve<M, RPL>{L.wcap}.wave_bytes() < 64 * sizeof(double2)) return hipErrorInvalidValue;
+  auto k = bv_wave_kernel<M, RPL, SV, Src, Epi>;
   if (hipError_t e = set_lds(reinterpret_cast<const void*>(k), smem)) return e;
   if (L.ntiles == 0) return hipSuccess;
-  hipLaunchKernelGGL(k, dim3(L.ntiles / kWaves), dim3(kThreads), smem, s, L, static_cast<const typename M::X*>(x),
-                     epi, skip);
+  hipLaunchKernelGGL(k, dim3(L.ntiles / kWaves), dim3(kThreads), smem, s, L, src, epi, skip);
   return hipGetLastError();
 }
 
 // window values a lane loads up front: 8 up to 512 columns, else 16 (a longer
 // lane chunk loads the rest while it stages)
-template <class M, int RPL, class Epi>
-hipError_t launch_tile_rpl(const DevLayout& L, const void* x, const Epi& epi, const PRState* skip, hipStream_t s) {
-  if (L.wcap <= 512) return launch_tile_sv<M, RPL, 8>(L, x, epi, skip, s);
-  return launch_tile_sv<M, RPL, 16>(L, x, epi, skip, s);
+template <class M, int RPL, class Src, class Epi>
+hipError_t launch_tile_rpl(const DevLayout& L, const Src& src, const Epi& epi, const PRState* skip, hipStream_t s) {
+  if (L.wcap <= 512) return launch_tile_sv<M, RPL, 8>(L, src, epi, skip, s);
+  return launch_tile_sv<M, RPL, 16>(L, src, epi, skip, s);
+}
+
+template <class M, class Src, class Epi>
+hipError_t launch_tile_src(const DevLayout& L, const Src& src, const Epi& epi, const PRState* skip, hipStream_t s) {
+  switch (rows_per_lane(L)) {
+    case 1: return launch_tile_rpl<M, 1>(L, src, epi, skip, s);
+    default: return launch_tile_rpl<M, 2>(L, src, epi, skip, s);
+  }
 }
 
 template <class M, class Epi>
 hipError_t launch_tile(const DevLayout& L, const void* x, const Epi& epi, const PRState* skip, hipStream_t s) {
-  switch (rows_per_lane(L)) {
-    case 1: return launch_tile_rpl<M, 1>(L, x, epi, skip, s);
-    default: return launch_tile_rpl<M, 2>(L, x, epi, skip, s);
-  }
+  return launch_tile_src<M>(L, OneCol<typename M::X>{static_cast<const typename M::X*>(x)}, epi, skip, s);
+}
+
+// k columns of a column-major block, each multiplied by the tile kernel's shared decode
+template <class M, class Epi>
+hipError_t launch_tile_cols(const DevLayout& L, const void* X, int k, int64_t ld, const Epi& epi, hipStream_t s) {
+  return launch_tile_src<M>(L, Cols<typename M::X>{static_cast<const typename M::X*>(X), k, ld}, epi, nullptr, s);
 }
 
 template <class M>
@@ -1619,81 +1567,6 @@ hipError_t launch_csr(const DevCsr& Cs, const void* x, const Epi& epi, const PRS
   return hipGetLastError();
 }
 
-template <class M, int G>
-size_t batch_lds(const DevLayout& L) {
-  return BatchCarve<M, G>{L.tcap, L.sbytes}.total();
-}
-
-template <class M, int G, class Epi>
-hipError_t launch_batch_g(const DevLayout& L, const void* X, int k, int64_t ld, const Epi& epi, hipStream_t s) {
-  const size_t smem = batch_lds<M, G>(L);
-  auto kern = bv_batch_kernel<M, G, Epi>;
-  if (hipError_t e = set_lds(reinterpret_cast<const void*>(kern), smem)) return e;
-  if (L.ntiles == 0) return hipSuccess;
-  hipLaunchKernelGGL(kern, dim3(L.ntiles), dim3(kThreads), smem, s, L, static_cast<const typename M::X*>(X), k, ld,
-                     epi);
-  return hipGetLastError();
-}
-
-// Team width: the smallest power of two >= k, at least 4, at most 64.
-inline int team_width(int k) {
-  int G = 4;
-  while (G < k && G < 64) G *= 2;
-  return G;
-}
-
-template <class M>
-size_t batch_lds_g(const DevLayout& L, int G) {
-  switch (G) {
-    case 64: return batch_lds<M, 64>(L);
-    case 32: return batch_lds<M, 32>(L);
-    case 16: return batch_lds<M, 16>(L);
-    case 8: return batch_lds<M, 8>(L);
-    default: return batch_lds<M, 4>(L);
-  }
-}
-
-// the widest team whose LDS carve stays within 96 KB
-template <class M>
-int pick_g(const DevLayout& L, int k) {
-  int G = team_width(k);
-  while (G > 4 && batch_lds_g<M>(L, G) > 96 * 1024) G /= 2;
-  return G;
-}
-
-template <class M>
-size_t batch_lds_k(const DevLayout& L, int k) {
-  return batch_lds_g<M>(L, pick_g<M>(L, k));
-}
-
-template <class M, class Epi>
-hipError_t launch_batch(const DevLayout& L, const void* X, int k, int64_t ld, const Epi& epi, hipStream_t s) {
-  switch (pick_g<M>(L, k)) {
-    case 64: return launch_batch_g<M, 64>(L, X, k, ld, epi, s);
-    case 32: return launch_batch_g<M, 32>(L, X, k, ld, epi, s);
-    case 16: return launch_batch_g<M, 16>(L, X, k, ld, epi, s);
-    case 8: return launch_batch_g<M, 8>(L, X, k, ld, epi, s);
-    default: return launch_batch_g<M, 4>(L, X, k, ld, epi, s);
-  }
-}
-
-template <class M>
-hipError_t launch_batch_init(const DevLayout& L, int k, const void* start, const void* tele, void* p0, void* z0,
-                             const int32_t* outdeg, const PRState* st, double* slots, hipStream_t s) {
-  if (L.ntiles == 0) return hipSuccess;
-  auto go = [&](auto kern) {
-    hipLaunchKernelGGL(kern, dim3(L.ntiles), dim3(kThreads), 0, s, L, k, start, tele, p0, z0, outdeg, st, slots);
-    return hipGetLastError();
-  };
-  switch (team_width(k)) {
-    case 64: return go(pr_init_batch_kernel<M, 64>);
-    case 32: return go(pr_init_batch_kernel<M, 32>);
-    case 16: return go(pr_init_batch_kernel<M, 16>);
-    case 8: return go(pr_init_batch_kernel<M, 8>);
-    default: return go(pr_init_batch_kernel<M, 4>);
-  }
-}
-
 }  // namespace
 
 size_t bv_kernel_lds_bytes(const DevLayout& L, int prec) {
@@ -1710,15 +1583,6 @@ size_t csr_kernel_lds_bytes(const DevCsr& C, int prec) {
     case 0: return csr_lds<MF64>(C);
     case 1: return csr_lds<MF32>(C);
     case 2: return csr_lds<MF32C>(C);
-    default: return 0;
-  }
-}
-
-size_t bv_batch_lds_bytes(const DevLayout& L, int prec, int k) {
-  switch (prec) {
-    case 0: return batch_lds_k<MF64>(L, k);
-    case 1: return batch_lds_k<MF32>(L, k);
-    case 2: return batch_lds_k<MF32C>(L, k);
     default: return 0;
   }
 }
@@ -1768,6 +1632,42 @@ hipError_t launch_pr_init(const DevLayout& L, int prec, const void* start, const
                        start, tele, p0, z0, outdeg, st, slots, normalize);
   if (hipError_t e = hipGetLastError()) return e;
   hipLaunchKernelGGL(pr_finish_kernel, dim3(members), dim3(kThreads), 0, s, st, slots, 0, 0.0, 0, 0, iter0);
+  return hipGetLastError();
+}
+
+hipError_t launch_bv_multiply_cols(const DevLayout& L, int prec, const void* X, void* Y, int k, int64_t ld,
+                                   hipStream_t s) {
+  switch (prec) {
+    case 0: return launch_tile_cols<MF64>(L, X, k, ld, EpiStoreCols<MF64>{static_cast<double*>(Y), ld}, s);
+    case 1: return launch_tile_cols<MF32>(L, X, k, ld, EpiStoreCols<MF32>{static_cast<float*>(Y), ld}, s);
+    case 2: return launch_tile_cols<MF32C>(L, X, k, ld, EpiStoreCols<MF32C>{static_cast<float*>(Y), ld}, s);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+hipError_t launch_bv_cols_pagerank_iter(const DevLayout& L, int prec, const PRArgs& a, hipStream_t s) {
+  if (a.k < 1 || a.k > 64) return hipErrorInvalidValue;  // lane c of a wave holds column c
+  hipError_t e;
+  switch (prec) {
+    case 0: e = launch_tile_cols<MF64>(L, a.z_cur, a.k, L.n, EpiPRCols<MF64>{a, L.n}, s); break;
+    case 1: e = launch_tile_cols<MF32>(L, a.z_cur, a.k, L.n, EpiPRCols<MF32>{a, L.n}, s); break;
+    case 2: e = launch_tile_cols<MF32C>(L, a.z_cur, a.k, L.n, EpiPRCols<MF32C>{a, L.n}, s); break;
+    default: return hipErrorInvalidValue;
+  }
+  return e != hipSuccess ? e : launch_pr_finish(a, s);
+}
+
+hipError_t launch_cols_pr_init(const DevLayout& L, int prec, int k, const void* start, const void* tele, void* p0,
+                               void* z0, const int32_t* outdeg, PRState* st, double* slots, hipStream_t s) {
+  if (L.ntiles == 0) return hipSuccess;
+  if (prec == 0)
+    hipLaunchKernelGGL(pr_init_cols_kernel<MF64>, dim3(L.ntiles / kWaves), dim3(kThreads), 0, s, L, k, start, tele,
+                       p0, z0, outdeg, st, slots);
+  else
+    hipLaunchKernelGGL(pr_init_cols_kernel<MF32>, dim3(L.ntiles / kWaves), dim3(kThreads), 0, s, L, k, start, tele,
+                       p0, z0, outdeg, st, slots);
+  if (hipError_t e = hipGetLastError()) return e;
+  hipLaunchKernelGGL(pr_finish_kernel, dim3(k), dim3(kThreads), 0, s, st, slots, 0, 0.0, 0, 0, 0);
   return hipGetLastError();
 }
 
@@ -1845,49 +1745,16 @@ hipError_t launch_csr_pr_init(const DevCsr& C, int prec, const void* start, cons
   return hipGetLastError();
 }
 
-hipError_t launch_bv_multiply_batch(const DevLayout& L, int prec, const void* X, void* Y, int k, int64_t ld,
-                                    hipStream_t s) {
-  switch (prec) {
-    case 0: return launch_batch<MF64>(L, X, k, ld, EpiStoreBatch<MF64>{static_cast<double*>(Y), k, ld}, s);
-    case 1: return launch_batch<MF32>(L, X, k, ld, EpiStoreBatch<MF32>{static_cast<float*>(Y), k, ld}, s);
-    case 2: return launch_batch<MF32C>(L, X, k, ld, EpiStoreBatch<MF32C>{static_cast<float*>(Y), k, ld}, s);
-    default: return hipErrorInvalidValue;
-  }
-}
-
-hipError_t launch_bv_batch_pagerank_iter(const DevLayout& L, int prec, const PRArgs& a, hipStream_t s) {
-  hipError_t e;
-  switch (prec) {
-    case 0: e = launch_batch<MF64>(L, a.z_cur, a.k, a.k, EpiPRBatch<MF64>{a}, s); break;
-    case 1: e = launch_batch<MF32>(L, a.z_cur, a.k, a.k, EpiPRBatch<MF32>{a}, s); break;
-    case 2: e = launch_batch<MF32C>(L, a.z_cur, a.k, a.k, EpiPRBatch<MF32C>{a}, s); break;
-    default: return hipErrorInvalidValue;
-  }
-  return e != hipSuccess ? e : launch_pr_finish(a, s);
-}
-
-hipError_t launch_batch_pr_init(const DevLayout& L, int prec, int k, const void* start, const void* tele, void* p0,
-                                void* z0, const int32_t* outdeg, PRState* st, double* slots, hipStream_t s) {
-  hipError_t e = prec == 0 ? launch_batch_init<MF64>(L, k, start, tele, p0, z0, outdeg, st, slots, s)
-                           : launch_batch_init<MF32>(L, k, start, tele, p0, z0, outdeg, st, slots, s);
-  if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(pr_finish_kernel, dim3(k), dim3(kThreads), 0, s, st, slots, 0, 0.0, 0, 0, 0);
-  return hipGetLastError();
-}
-
 hipError_t launch_pr_select(int prec, const PRState* st, const void* p0, const void* p1, void* out, int64_t n, int k,
                             hipStream_t s) {
-  const int64_t total = n * k;
-  const uint32_t blocks = uint32_t(std::min<int64_t>((total + kThreads - 1) / kThreads, 65536));
-  if (total == 0) return hipSuccess;
+  if (n == 0 || k == 0) return hipSuccess;
+  const dim3 grid(uint32_t(std::min<int64_t>((n + kThreads - 1) / kThreads, 4096)), uint32_t(k));
   if (prec == 0)
-    hipLaunchKernelGGL(pr_select_kernel<double>, dim3(blocks), dim3(kThreads), 0, s, st,
-                       static_cast<const double*>(p0), static_cast<const double*>(p1), static_cast<double*>(out),
-                       total, k);
+    hipLaunchKernelGGL(pr_select_kernel<double>, grid, dim3(kThreads), 0, s, st, static_cast<const double*>(p0),
+                       static_cast<const double*>(p1), static_cast<double*>(out), n);
   else
-    hipLaunchKernelGGL(pr_select_kernel<float>, dim3(blocks), dim3(kThreads), 0, s, st,
-                       static_cast<const float*>(p0), static_cast<const float*>(p1), static_cast<float*>(out), total,
-                       k);
+    hipLaunchKernelGGL(pr_select_kernel<float>, grid, dim3(kThreads), 0, s, st, static_cast<const float*>(p0),
+                       static_cast<const float*>(p1), static_cast<float*>(out), n);
   return hipGetLastError();
 }
 

@@ -833,16 +833,12 @@ int bvmv_multiply(bvmv_graph* g, const void* x, void* y, int prec, void* stream)
 
 int bvmv_multiply_batch(bvmv_graph* g, const void* X, void* Y, int k, int64_t ld, int prec, void* stream) {
   if (!g || !X || !Y) return fail(BVMV_EINVAL, "null argument");
-  if (prec < 0 || prec > 2 || k < 1 || k > 64 || ld < k) return fail(BVMV_EINVAL, "bad batch arguments");
+  if (prec < 0 || prec > 2 || k < 1 || k > 64 || ld < g->n) return fail(BVMV_EINVAL, "bad batch arguments");
   if (X == Y) return fail(BVMV_EINVAL, "X and Y must not overlap");
-  if (int rc = check_lds(g->device, bv_batch_lds_bytes(g->L, prec, k))) return rc;
   DeviceGuard dg(g->device);
-  HIP_TRY(launch_bv_multiply_batch(g->L, prec, X, Y, k, ld, static_cast<hipStream_t>(stream)));
+  HIP_TRY(launch_bv_multiply_cols(g->L, prec, X, Y, k, ld, static_cast<hipStream_t>(stream)));
   return BVMV_OK;
 }
-
-// Start states of the members of a single graph or a group (one right-hand
-// side each): 1/n and the member's block range (kTilesPerBlock tiles per block).
 
 int bvmv_degrees(bvmv_graph* g, int32_t* deg, void* stream) {
   if (!g || !deg) return fail(BVMV_EINVAL, "null argument");
@@ -880,25 +876,26 @@ int bvmv_pagerank(bvmv_graph* g, const bvmv_pr_opts* opts, const void* teleport,
                         out);
   }
   // k right-hand sides: one state per column, each column's block partials at
-  // slots c * ntiles .. (c + 1) * ntiles - 1 (one block per tile)
+  // slots c * groups .. (c + 1) * groups - 1 (one block per group of tiles)
+  const uint32_t groups = L.ntiles / kTilesPerBlock;
+  if (int64_t(groups) * k >= (int64_t(1) << 32)) return fail(BVMV_EINVAL, "too many tiles for k right-hand sides");
   std::vector<PRState> states(static_cast<size_t>(k));
   for (int c = 0; c < k; ++c) {
     std::memset(&states[size_t(c)], 0, sizeof(PRState));
     states[size_t(c)].inv_n = 1.0 / double(g->n);
     states[size_t(c)].blk_lo = 0;
-    states[size_t(c)].blk_hi = L.ntiles;
-    states[size_t(c)].slot0 = uint32_t(c) * L.ntiles;
+    states[size_t(c)].blk_hi = groups;
+    states[size_t(c)].slot0 = uint32_t(c) * groups;
   }
-  if (int64_t(L.ntiles) * k >= (int64_t(1) << 32)) return fail(BVMV_EINVAL, "too many tiles for k right-hand sides");
   PRWork& w = g->prb;
-  auto iter = [&](const PRArgs& a, hipStream_t cs) { return launch_bv_batch_pagerank_iter(L, prec, a, cs); };
+  auto iter = [&](const PRArgs& a, hipStream_t cs) { return launch_bv_cols_pagerank_iter(L, prec, a, cs); };
   auto init = [&](const void* st, const void* te, void* p0, void* z0, hipStream_t ss) {
-    return launch_batch_pr_init(L, prec, k, st, te, p0, z0, g->d_outdeg, w.st, w.slots, ss);
+    return launch_cols_pr_init(L, prec, k, st, te, p0, z0, g->d_outdeg, w.st, w.slots, ss);
   };
   auto out = [&](const PRWork& ww, hipStream_t ss) {
     return launch_pr_select(prec, ww.st, ww.p[0], ww.p[1], p_out, g->n, k, ss);
   };
-  return run_pagerank(w, g->cap, o, g->n * k, k, states, int64_t(L.ntiles) * k + 1, teleport, start, res, s,
+  return run_pagerank(w, g->cap, o, g->n * k, k, states, int64_t(groups) * k + 1, teleport, start, res, s,
                       g->d_outdeg, iter, init, out);
 }
 

@@ -33,7 +33,6 @@ struct DevCsr {
 // the loader checks them against the device limit.
 size_t bv_kernel_lds_bytes(const DevLayout& L, int prec);
 size_t csr_kernel_lds_bytes(const DevCsr& C, int prec);
-size_t bv_batch_lds_bytes(const DevLayout& L, int prec, int k);
 
 // Per-member PageRank state, updated by the last block of every iteration.
 struct PRState {
@@ -62,7 +61,7 @@ struct PRArgs {
   int32_t max_iter;
   int32_t buf;           // index of p_new's buffer (0/1)
   int32_t members;       // PRState entries (member graphs, or right-hand sides)
-  int32_t k;             // right-hand sides (node-major p, z, teleport with leading dimension k)
+  int32_t k;             // right-hand sides (column-major p, z, teleport with leading dimension n)
 };
 
 hipError_t launch_bv_multiply(const DevLayout& L, int prec, const void* x, void* y, hipStream_t s);
@@ -73,6 +72,15 @@ hipError_t launch_bv_pagerank_iter(const DevLayout& L, int prec, const PRArgs& a
 hipError_t launch_pr_init(const DevLayout& L, int prec, const void* start, const void* tele, void* p0, void* z0,
                           const int32_t* outdeg, PRState* st, double* slots, int members, hipStream_t s,
                           int normalize = 0, int32_t iter0 = 0);
+// k columns of a column-major block (leading dimension ld) through the tile
+// kernel: the tile is decoded once and each column staged and summed in turn
+hipError_t launch_bv_multiply_cols(const DevLayout& L, int prec, const void* X, void* Y, int k, int64_t ld,
+                                   hipStream_t s);
+// one personalized PageRank iteration for a.k <= 64 columns (p, z column-major,
+// ld = n; column c's state a.st[c], its block partials at slots c * groups + group)
+hipError_t launch_bv_cols_pagerank_iter(const DevLayout& L, int prec, const PRArgs& a, hipStream_t s);
+hipError_t launch_cols_pr_init(const DevLayout& L, int prec, int k, const void* start, const void* tele, void* p0,
+                               void* z0, const int32_t* outdeg, PRState* st, double* slots, hipStream_t s);
 // Warm restart: inputs 8..11 of every node into F (n x 12) and, with p_star,
 // the target into T, from the last four iterates and the states' residuals.
 hipError_t launch_restart_inputs(const DevLayout& L, int prec, const void* pK, const void* pK1, const void* pK2,
@@ -88,16 +96,10 @@ hipError_t launch_csr_pagerank_iter(const DevCsr& C, int prec, const PRArgs& a, 
 hipError_t launch_csr_pr_init(const DevCsr& C, int prec, const void* start, const void* tele, void* p0, void* z0,
                               const int32_t* outdeg, PRState* st, double* slots, hipStream_t s);
 
-// Y = A X for k <= 64 right-hand sides, node-major with leading dimension ld
-// Batched personalized PageRank (k right-hand sides, node-major n x k).
-hipError_t launch_bv_batch_pagerank_iter(const DevLayout& L, int prec, const PRArgs& a, hipStream_t s);
-hipError_t launch_batch_pr_init(const DevLayout& L, int prec, int k, const void* start, const void* tele, void* p0,
-                                void* z0, const int32_t* outdeg, PRState* st, double* slots, hipStream_t s);
-// out = per column c, the buffer (p0 or p1) holding column c's final iterate
+// out column c (column-major, ld = n) = the buffer (p0 or p1) holding column
+// c's final iterate
 hipError_t launch_pr_select(int prec, const PRState* st, const void* p0, const void* p1, void* out, int64_t n, int k,
                             hipStream_t s);
-hipError_t launch_bv_multiply_batch(const DevLayout& L, int prec, const void* X, void* Y, int k, int64_t ld,
-                                    hipStream_t s);
 
 
 // ------------------------------------------------------------ learned warm start

@@ -99,15 +99,17 @@ def test_personalized_start_and_limits(P):
 
 
 def _pr_k(P, G, n, k, prec, V=None, start=None, **kw):
-    """k personalized PageRanks at once (node-major n x k)."""
+    """k personalized PageRanks at once.  V, start and the result are (n, k)
+    host arrays; on the device each right-hand side is one contiguous
+    vector (column-major n x k)."""
     dt = torch.float64 if prec == P.BVMV_F64 else torch.float32
     nd = np.float64 if dt == torch.float64 else np.float32
     p = torch.empty(n * k, dtype=dt, device=DEV)
-    tv = torch.from_numpy(np.ascontiguousarray(V, dtype=nd).reshape(-1)).to(DEV) if V is not None else None
-    sv = torch.from_numpy(np.ascontiguousarray(start, dtype=nd).reshape(-1)).to(DEV) if start is not None else None
+    tv = torch.from_numpy(np.ascontiguousarray(V.T, dtype=nd).reshape(-1)).to(DEV) if V is not None else None
+    sv = torch.from_numpy(np.ascontiguousarray(start.T, dtype=nd).reshape(-1)).to(DEV) if start is not None else None
     res = P.bvmv_pagerank(G, p, teleport=tv, start=sv, prec=prec, k=k, **kw)
     torch.cuda.synchronize()
-    return p.cpu().numpy().astype(np.float64).reshape(n, k), res
+    return p.cpu().numpy().astype(np.float64).reshape(k, n).T, res
 
 
 @pytest.mark.parametrize("prec_name,tol", [("f64", 1e-12), ("f32c", 1e-5)])

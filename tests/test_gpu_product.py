@@ -168,25 +168,26 @@ def test_batch_matches_oracle(P, graphs, k):
         G = P.bvmv_load(enc.data)
         rng = np.random.default_rng(k)
         X = rng.random((g.n, k), dtype=np.float32)
-        Xd = torch.from_numpy(X).to(DEV)
+        # right-hand side c is row c of the (k, n) device tensors
+        Xd = torch.from_numpy(np.ascontiguousarray(X.T)).to(DEV)
         Yd = torch.empty_like(Xd)
         P.bvmv_multiply_batch(G, Xd, Yd, P.BVMV_F32_COMP)
         torch.cuda.synchronize()
-        Y = Yd.cpu().numpy()
+        Y = Yd.cpu().numpy().T
         for c in range(0, k, max(1, k // 4)):
             assert _rel(Y[:, c], product.matvec(g.rowptr, g.col, X[:, c].astype(np.float64))) < 1e-5
         Xi = rng.integers(0, 8, size=(g.n, k)).astype(np.float32)
-        Xd = torch.from_numpy(Xi).to(DEV)
+        Xd = torch.from_numpy(np.ascontiguousarray(Xi.T)).to(DEV)
         P.bvmv_multiply_batch(G, Xd, Yd, P.BVMV_F32)
         torch.cuda.synchronize()
-        Y = Yd.cpu().numpy()
+        Y = Yd.cpu().numpy().T
         for c in range(k):
             assert np.array_equal(Y[:, c], product.matvec(g.rowptr, g.col, Xi[:, c].astype(np.float64)))
-        Xd64 = torch.from_numpy(X.astype(np.float64)).to(DEV)
+        Xd64 = torch.from_numpy(np.ascontiguousarray(X.T, dtype=np.float64)).to(DEV)
         Yd64 = torch.empty_like(Xd64)
         P.bvmv_multiply_batch(G, Xd64, Yd64, P.BVMV_F64)
         torch.cuda.synchronize()
-        assert _rel(Yd64.cpu().numpy()[:, k - 1], product.matvec(g.rowptr, g.col, X[:, k - 1].astype(np.float64))) < 1e-12
+        assert _rel(Yd64.cpu().numpy()[k - 1], product.matvec(g.rowptr, g.col, X[:, k - 1].astype(np.float64))) < 1e-12
 
 
 def test_group_block_diagonal(P):
@@ -283,12 +284,12 @@ def test_full_size_batch_8e6(P):
     G = P.bvmv_load(B.encode(g).data)
     k = 32
     X = np.random.default_rng(104).random((g.n, k), dtype=np.float32)
-    Xd = torch.from_numpy(X).to(DEV)
+    Xd = torch.from_numpy(np.ascontiguousarray(X.T)).to(DEV)
     Yd = torch.empty_like(Xd)
     P.bvmv_multiply_batch(G, Xd, Yd, P.BVMV_F32_COMP)
     torch.cuda.synchronize()
     rows = np.random.default_rng(2).choice(g.n, 400, replace=False)
-    Yr = Yd[torch.from_numpy(rows).to(DEV)].cpu().numpy()
+    Yr = Yd[:, torch.from_numpy(rows).to(DEV)].cpu().numpy().T
     for c in (0, 7, 31):
         ref = product.matvec_rows(g.rowptr, g.col, X[:, c].astype(np.float64), rows)
         assert _rel(Yr[:, c], ref) < 1e-5, c
