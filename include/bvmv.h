@@ -116,9 +116,9 @@ typedef struct {
   int fallback_check;      /* 1 (k = 1, single graph, start given): run one iteration from
                               `start` and one from the teleport vector, and keep `start` only
                               if its residual is the smaller; the probes are not counted */
-  const bvmv_mlp* mlp;     /* non-NULL: learned warm restarts with this network (k = 1, single
-                              graph, uniform teleport, no start vector; see the learned
-                              section below) */
+  const bvmv_mlp* mlp;     /* non-NULL: learned warm restarts with this network (k = 1, uniform
+                              teleport, no start vector; a single graph or a group whose
+                              members share R; see the learned section below) */
   int restart_every;       /* K >= 3: a restart after every K iterations (0 = default 10) */
   int max_restarts;        /* restarts to try (0 = default 2); the first rejected one ends them */
 } bvmv_pr_opts;
@@ -229,6 +229,12 @@ int bvmv_layout_selfcheck(const void* bitstream, size_t nbytes, const bvmv_load_
  * otherwise the run goes on from p_K and no further restart is tried.  The
  * fixed point does not depend on the restarts: the stopping test and its
  * error bound are the plain method's.
+ * On a group every member is restarted at the same phase boundary, and only
+ * while every member is still iterating; each member keeps or rejects its
+ * restart by its own probe (a rejecting member goes on from its p_K with the
+ * state it had), and after any rejection no member is restarted again.  With
+ * one restart (max_restarts = 1) each member's result is bit-identical to
+ * its run alone.
  * Inputs of node v (rows read as in-link lists):
  *   0 log1p(in-degree)   1 log1p(out-degree d)   2 reference-chain depth / R
  *   3 [d = 0]   4 log1p(intervals of the row)   5 log1p(residuals of the row)

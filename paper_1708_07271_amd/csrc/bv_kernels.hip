@@ -261,19 +261,6 @@ __device__ __forceinline__ uint64_t block_excl_scan_u64(uint64_t v, uint64_t* s_
   return base + inc - v;
 }
 
-__device__ __forceinline__ double block_sum_f64(double a, double* s_red) {
-  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-#pragma unroll
-  for (int d = 32; d >= 1; d >>= 1) a += __shfl_down(a, d, 64);
-  if (lane == 0) s_red[wid] = a;
-  __syncthreads();
-  double r = s_red[0];
-#pragma unroll
-  for (int w = 1; w < kWaves; ++w) r += s_red[w];
-  __syncthreads();
-  return r;
-}
-
 // q = a / C for a < 2^24 and a wave-uniform C >= 1 (float estimate, then an
 // exact correction).
 __device__ __forceinline__ uint32_t div_small(uint32_t a, uint32_t C, float invC) {
@@ -562,10 +549,28 @@ struct TileCtx {
 };
 
 // ---------------------------------------------------------------- epilogues
-// Called by every wave of the block (a wave may have no rows).
+// Every wave of the block calls them (a wave may have no rows).  In the tile
+// kernel: prepare(tc) runs once per wave before the tile is decoded and
+// returns per-lane state; fetch(tc, c) issues vector c's global loads ahead
+// of their use (vector 0 with the tile's own loads, vector c + 1 while c is
+// summed); skip(st, c) passes over vector c (block-uniform); col(...) takes
+// vector c's sums; finish(...) runs once per block after the last vector,
+// with every wave present.  operator() is the CSR kernel's one-call form.
+constexpr int kEpiRows = kTileRowsMax / 64;  // rows of a tile per lane
+
 template <class M>
 struct EpiStore {
   typename M::X* y;
+  struct State {};
+  struct Fetch {};
+  __device__ State prepare(const TileCtx&) const { return {}; }
+  __device__ Fetch fetch(const TileCtx&, int) const { return {}; }
+  __device__ bool skip(const State&, int) const { return false; }
+  __device__ void col(const TileCtx& tc, const typename M::CAcc* s_y, unsigned char*, int, State&,
+                      const Fetch&) const {
+    for (uint32_t r = lane_id(); r < tc.nrows; r += 64) y[tc.row0 + r] = M::out(s_y[r]);
+  }
+  __device__ void finish(const State&, unsigned char*, size_t, uint32_t) const {}
   __device__ void operator()(const TileCtx& tc, const typename M::CAcc* s_y, unsigned char*, int) const {
     for (uint32_t r = lane_id(); r < tc.nrows; r += 64) y[tc.row0 + r] = M::out(s_y[r]);
   }
@@ -603,16 +608,37 @@ __device__ __forceinline__ void pr_block_partial(double rs, double dg, double* s
 __global__ void __launch_bounds__(kThreads) pr_finish_kernel(PRState* st_all, const double* __restrict__ slots,
                                                              int with_resid, double tol, int32_t max_iter,
                                                              int32_t buf, int32_t iter0) {
-  __shared__ double s_red[kWaves];
+  __shared__ double2 s_red[kWaves];
   PRState* st = st_all + blockIdx.x;
   if (with_resid && st->done) return;
+  // each thread's slots t, t + 256, ... in batches of kU loads in flight
+  constexpr int kU = 16;
+  const double2* sl = reinterpret_cast<const double2*>(slots) + st->slot0;
+  const uint32_t hi = st->blk_hi;
   double R = 0.0, D = 0.0;
-  for (uint32_t t = st->blk_lo + threadIdx.x; t < st->blk_hi; t += kThreads) {
-    R += slots[2 * (size_t(st->slot0) + t)];
-    D += slots[2 * (size_t(st->slot0) + t) + 1];
+  for (uint32_t b = st->blk_lo + threadIdx.x; b < hi; b += kThreads * kU) {
+    double2 v[kU];
+#pragma unroll
+    for (int u = 0; u < kU; ++u) {
+      const uint32_t t = b + uint32_t(u) * kThreads;
+      v[u] = t < hi ? sl[t] : make_double2(0.0, 0.0);
+    }
+#pragma unroll
+    for (int u = 0; u < kU; ++u) {
+      R += v[u].x;
+      D += v[u].y;
+    }
   }
-  R = block_sum_f64(R, s_red);
-  D = block_sum_f64(D, s_red);
+  R = wave_sum_f64(R);
+  D = wave_sum_f64(D);
+  if (lane_id() == 0) s_red[threadIdx.x >> 6] = make_double2(R, D);
+  __syncthreads();
+  R = s_red[0].x;
+  D = s_red[0].y;
+  for (int w = 1; w < kWaves; ++w) {
+    R += s_red[w].x;
+    D += s_red[w].y;
+  }
   if (threadIdx.x == 0) {
     st->delta = D;
     if (with_resid) {
@@ -664,14 +690,70 @@ struct EpiPR {
     dg = wave_sum_f64(dg);
     pr_block_partial(rs, dg, a.slots, s_blk, tc.slot);
   }
+  // the tile kernel's form: out-degrees, p and the teleport values are loaded
+  // with the tile's own loads (rows past the tile read element 0)
+  using X = typename M::X;
+  struct State {
+    int32_t d[kEpiRows];
+    double delta, inv_n;  // the member's dangling mass and 1/n
+  };
+  struct Fetch {
+    X p[kEpiRows], t[kEpiRows];
+  };
+  __device__ State prepare(const TileCtx& tc) const {
+    State S;
+    const PRState* st = a.st + tc.graph;
+    S.delta = st->delta;
+    S.inv_n = st->inv_n;
+#pragma unroll
+    for (int q = 0; q < kEpiRows; ++q) {
+      const uint32_t r = lane_id() + 64u * q;
+      S.d[q] = a.outdeg[r < tc.nrows ? tc.row0 + r : 0u];
+    }
+    return S;
+  }
+  __device__ Fetch fetch(const TileCtx& tc, int) const {
+    const X* p = static_cast<const X*>(a.p_cur);
+    const X* tele = static_cast<const X*>(a.tele);
+    Fetch f;
+#pragma unroll
+    for (int q = 0; q < kEpiRows; ++q) {
+      const uint32_t r = lane_id() + 64u * q;
+      const uint32_t v = r < tc.nrows ? tc.row0 + r : 0u;
+      f.p[q] = p[v];
+      f.t[q] = tele ? tele[v] : X(0);
+    }
+    return f;
+  }
+  __device__ bool skip(const State&, int) const { return false; }
+  __device__ void col(const TileCtx& tc, const typename M::CAcc* s_y, unsigned char* s_blk, int, State& S,
+                      const Fetch& f) const {
+    X* pn = static_cast<X*>(a.p_new) + tc.row0;
+    X* zn = static_cast<X*>(a.z_new) + tc.row0;
+    const double delta = S.delta, inv_n = S.inv_n, beta = a.beta;
+    double rs = 0.0, dg = 0.0;
+#pragma unroll
+    for (int q = 0; q < kEpiRows; ++q) {
+      const uint32_t r = lane_id() + 64u * q;
+      if (r < tc.nrows) {
+        const double y = M::to_d(s_y[r]);
+        const double t = a.tele ? double(f.t[q]) : inv_n;
+        const X pnew = X((1.0 - beta) * t + beta * (y + delta * t));
+        pn[r] = pnew;
+        const int32_t d = S.d[q];
+        zn[r] = d > 0 ? pnew / X(d) : X(0);
+        rs += fabs(double(pnew) - double(f.p[q]));
+        if (d == 0) dg += double(pnew);
+      }
+    }
+    rs = wave_sum_f64(rs);
+    dg = wave_sum_f64(dg);
+    pr_block_partial(rs, dg, a.slots, s_blk, tc.slot);
+  }
+  __device__ void finish(const State&, unsigned char*, size_t, uint32_t) const {}
 };
 
-// Epilogues of the multi-vector tile kernel.  prepare(tc) runs once per wave
-// before the tile is decoded and returns per-lane state; fetch(tc, c) issues
-// vector c's global loads one vector ahead of their use; skip(st, c) passes
-// over vector c (block-uniform); col(...) takes vector c's sums; finish(...)
-// runs once per block after the last vector, with every wave present.
-constexpr int kEpiRows = kTileRowsMax / 64;  // rows of a tile per lane
+// Multi-vector epilogues (the same interface).
 
 __device__ __forceinline__ double readlane_f64(double v, int l) {
   const uint64_t u = __double_as_longlong(v);
@@ -689,7 +771,8 @@ struct EpiStoreCols {
   __device__ State prepare(const TileCtx&) const { return {}; }
   __device__ Fetch fetch(const TileCtx&, int) const { return {}; }
   __device__ bool skip(const State&, int) const { return false; }
-  __device__ void col(const TileCtx& tc, const typename M::CAcc* s_y, int c, State&, const Fetch&) const {
+  __device__ void col(const TileCtx& tc, const typename M::CAcc* s_y, unsigned char*, int c, State&,
+                      const Fetch&) const {
     typename M::X* yc = y + int64_t(c) * ld + tc.row0;
     for (uint32_t r = lane_id(); r < tc.nrows; r += 64) yc[r] = M::out(s_y[r]);
   }
@@ -748,7 +831,8 @@ struct EpiPRCols {
     return f;
   }
   __device__ bool skip(const State& S, int c) const { return (S.done >> c) & 1u; }
-  __device__ void col(const TileCtx& tc, const typename M::CAcc* s_y, int c, State& S, const Fetch& f) const {
+  __device__ void col(const TileCtx& tc, const typename M::CAcc* s_y, unsigned char*, int c, State& S,
+                      const Fetch& f) const {
     const int64_t base = int64_t(c) * n + tc.row0;
     X* pn = static_cast<X*>(a.p_new) + base;
     X* zn = static_cast<X*>(a.z_new) + base;
@@ -922,12 +1006,7 @@ __device__ __forceinline__ void process_tile(const DevLayout& L, const TileDesc&
   static_assert(!(Src::kMulti && M::kInt), "the integer mode multiplies one vector");
   // the multi-vector epilogue's per-lane state, read before the decode
   const TileCtx tc{td.row0, td.nrows, td.graph, slot};
-  [[maybe_unused]] auto S = [&] {
-    if constexpr (Src::kMulti)
-      return epi.prepare(tc);
-    else
-      return 0;
-  }();
+  auto S = epi.prepare(tc);
   const uint32_t lane = lane_id();
   const uint32_t nrows = td.nrows;
   const int64_t win0 = td.win0;
@@ -992,16 +1071,11 @@ __device__ __forceinline__ void process_tile(const DevLayout& L, const TileDesc&
   wave_sync();
 
   X xs_next[SV];
-  [[maybe_unused]] auto f_next = [&] {
-    if constexpr (Src::kMulti)
-      return epi.fetch(tc, 0);
-    else
-      return 0;
-  }();
+  auto f_next = epi.fetch(tc, 0);
   if constexpr (Src::kMulti)
     if (winlen) load_window(src, win0, winlen, 0, xs_next);
   for (int col = 0; col < src.count(); ++col) {
-  [[maybe_unused]] const auto f_cur = f_next;
+  const auto f_cur = f_next;
   const X* xcol = src.col(col);
   // 1. the x window of this vector (with its prefix sums when the tile has
   //    intervals) into Z; the next vector's window values are loaded meanwhile
@@ -1162,16 +1236,11 @@ __device__ __forceinline__ void process_tile(const DevLayout& L, const TileDesc&
   }
   wave_sync();
   // 6. epilogue
-  if constexpr (Src::kMulti)
-    epi.col(tc, s_y, col, S, f_cur);
-  else
-    epi(tc, s_y, s_blk, col);
+  epi.col(tc, s_y, s_blk, col, S, f_cur);
   wave_sync();  // y is read before the next vector's pieces overwrite it
   }
-  if constexpr (Src::kMulti) {
-    const size_t wb = Cv{L.wcap}.wave_bytes();
-    epi.finish(S, s_blk - kWaves * wb, wb, slot);
-  }
+  const size_t wb = Cv{L.wcap}.wave_bytes();
+  epi.finish(S, s_blk - kWaves * wb, wb, slot);
 }
 
 // Tile kernel: block b takes the group of kWaves consecutive tiles from
@@ -1482,6 +1551,20 @@ __global__ void __launch_bounds__(kThreads) csr_wave_kernel(DevCsr C, const type
   epi(TileCtx{td.row0, nrows, 0u, blockIdx.x}, s_y, s_blk, 0);
 }
 
+// Rows [r0, r1) of p and z from src: p = src and z = src / d (0 where d = 0),
+// as the PageRank epilogue writes them.
+template <class X>
+__global__ void __launch_bounds__(kThreads) pr_restore_kernel(const X* __restrict__ src, X* __restrict__ p,
+                                                              X* __restrict__ z, const int32_t* __restrict__ outdeg,
+                                                              int64_t r0, int64_t r1) {
+  for (int64_t v = r0 + int64_t(blockIdx.x) * kThreads + threadIdx.x; v < r1; v += int64_t(gridDim.x) * kThreads) {
+    const X pv = src[v];
+    p[v] = pv;
+    const int32_t d = outdeg[v];
+    z[v] = d > 0 ? pv / X(d) : X(0);
+  }
+}
+
 // p_out column c (column-major, leading dimension n; column c = blockIdx.y)
 // = the buffer holding column c's final iterate.
 template <class X>
@@ -1742,6 +1825,19 @@ hipError_t launch_csr_pr_init(const DevCsr& C, int prec, const void* start, cons
                        start, tele, p0, z0, outdeg, st, slots, 0);
   if (hipError_t e = hipGetLastError()) return e;
   hipLaunchKernelGGL(pr_finish_kernel, dim3(1), dim3(kThreads), 0, s, st, slots, 0, 0.0, 0, 0, 0);
+  return hipGetLastError();
+}
+
+hipError_t launch_pr_restore(int prec, const void* src, void* p, void* z, const int32_t* outdeg, int64_t r0,
+                             int64_t r1, hipStream_t s) {
+  if (r1 <= r0) return hipSuccess;
+  const uint32_t blocks = uint32_t(std::min<int64_t>((r1 - r0 + kThreads - 1) / kThreads, 4096));
+  if (prec == 0)
+    hipLaunchKernelGGL(pr_restore_kernel<double>, dim3(blocks), dim3(kThreads), 0, s, static_cast<const double*>(src),
+                       static_cast<double*>(p), static_cast<double*>(z), outdeg, r0, r1);
+  else
+    hipLaunchKernelGGL(pr_restore_kernel<float>, dim3(blocks), dim3(kThreads), 0, s, static_cast<const float*>(src),
+                       static_cast<float*>(p), static_cast<float*>(z), outdeg, r0, r1);
   return hipGetLastError();
 }
 

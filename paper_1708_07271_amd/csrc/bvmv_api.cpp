@@ -394,18 +394,21 @@ int replay_until_done(PRWork& w, hipStream_t cap, const PROptsResolved& o, const
 
 // Results from the host copy of the states; BVMV_NOT_CONVERGED if a member
 // did not converge.
-int fill_results(const PRWork& w, int members, int used, int rejected, int accepted, bvmv_pr_result* res) {
+// rejected / accepted: per-member restart counts, or null (none).
+int fill_results(const PRWork& w, int members, int used, const int* rejected, const int* accepted,
+                 bvmv_pr_result* res) {
   int status = BVMV_OK;
   for (int gI = 0; gI < members; ++gI) {
     const PRState& st = w.h_st[gI];
     if (res) {
+      const int rj = rejected ? rejected[gI] : 0, ac = accepted ? accepted[gI] : 0;
       res[gI].iters = st.iter;
       res[gI].converged = st.converged;
       res[gI].residual = st.resid;
       res[gI].used_start = used;
-      res[gI].products = st.iter + rejected;
-      res[gI].restarts_accepted = accepted;
-      res[gI].restarts_rejected = rejected;
+      res[gI].products = st.iter + rj;
+      res[gI].restarts_accepted = ac;
+      res[gI].restarts_rejected = rj;
     }
     if (!st.converged) status = BVMV_NOT_CONVERGED;
   }
@@ -551,7 +554,7 @@ int run_phase(bvmv_graph* g, const PROptsResolved& o, int K, int& c, int& since,
   for (; since < K; ++since, ++c) {
     if (since == K - 2) HIP_TRY(hipMemcpyAsync(lw.t[0], w.p[(c + 1) % 2], bytes, hipMemcpyDeviceToDevice, s));
     if (since == K - 1) HIP_TRY(hipMemcpyAsync(lw.t[1], w.p[(c + 1) % 2], bytes, hipMemcpyDeviceToDevice, s));
-    HIP_TRY(launch_bv_pagerank_iter(g->L, o.prec, pr_args(w, o, nullptr, g->d_outdeg, 1, 1, c), s));
+    HIP_TRY(launch_bv_pagerank_iter(g->L, o.prec, pr_args(w, o, nullptr, g->d_outdeg, g->ngraphs, 1, c), s));
   }
   return BVMV_OK;
 }
@@ -560,24 +563,28 @@ int run_phase(bvmv_graph* g, const PROptsResolved& o, int K, int& c, int& since,
 int start_learned(bvmv_graph* g, const PROptsResolved& o, hipStream_t s) {
   PRWork& w = g->pr;
   const std::vector<PRState> states = member_states(g->offsets, g->tile_offsets);
-  if (int rc = w.ensure(o.prec, g->n, 1, int64_t(g->L.ntiles) / kTilesPerBlock + 1)) return rc;
+  const int M = g->ngraphs;
+  if (int rc = w.ensure(o.prec, g->n, M, int64_t(g->L.ntiles) / kTilesPerBlock + 1)) return rc;
   if (int rc = g->lw.ensure(o.prec, g->n)) return rc;
-  std::memcpy(w.h_st, states.data(), sizeof(PRState));
-  HIP_TRY(hipMemcpyAsync(w.st, w.h_st, sizeof(PRState), hipMemcpyHostToDevice, s));
-  HIP_TRY(launch_pr_init(g->L, o.prec, nullptr, nullptr, w.p[0], w.z[0], g->d_outdeg, w.st, w.slots, 1, s));
+  std::memcpy(w.h_st, states.data(), sizeof(PRState) * size_t(M));
+  HIP_TRY(hipMemcpyAsync(w.st, w.h_st, sizeof(PRState) * size_t(M), hipMemcpyHostToDevice, s));
+  HIP_TRY(launch_pr_init(g->L, o.prec, nullptr, nullptr, w.p[0], w.z[0], g->d_outdeg, w.st, w.slots, M, s));
   return BVMV_OK;
 }
 
-// PageRank with learned warm restarts (single graph, uniform teleport).
-// After each phase of K iterations: the inputs, the network, the restart
-// vector q and its sum, p' = q / sum as the new iterate with the iteration
-// count kept, and one probe iteration.  The probe's residual r' decides:
-// kept if r' < beta * delta, else the run resumes from p_K (saved in
-// lw.t[1]) and no further restart is tried.  The rest runs as captured chunks.
+// PageRank with learned warm restarts (a single graph or a group, uniform
+// teleport).  After each phase of K iterations: the inputs, the network, the
+// restart vector q and its sum, p' = q / sum as every member's new iterate
+// with the iteration count kept, and one probe iteration.  Each member keeps
+// its restart if its probe residual r' < beta * delta, else it resumes from
+// p_K (saved in lw.t[1]) with the state it had at the phase's end.  A restart
+// is tried only while every member is active, and not after a rejection.
+// The rest runs as captured chunks.
 int run_learned(bvmv_graph* g, const PROptsResolved& o, const bvmv_mlp* m, void* p_out, bvmv_pr_result* res,
                 hipStream_t s) {
   PRWork& w = g->pr;
   LearnWork& lw = g->lw;
+  const int M = g->ngraphs;
   if (int rc = start_learned(g, o, s)) return rc;
   if (!lw.struct_ready) {
     if (int rc = compute_structural(g, lw.F, s)) return rc;
@@ -585,53 +592,71 @@ int run_learned(bvmv_graph* g, const PROptsResolved& o, const bvmv_mlp* m, void*
   }
   const DevLayout& L = g->L;
   const size_t bytes = size_t(g->n) * elem_size(o.prec);
-  int c = 0, since = 0, accepted = 0, rejected = 0;
+  std::vector<int> accepted(size_t(M), 0), rejected(size_t(M), 0);
+  std::vector<PRState> at_k(static_cast<size_t>(M));
+  int c = 0, since = 0;
   bool done = false;
-  while (accepted + rejected < o.max_restarts) {
+  auto all_done = [&] {
+    for (int i = 0; i < M; ++i)
+      if (!w.h_st[i].done) return false;
+    return true;
+  };
+  for (int tried = 0; tried < o.max_restarts; ++tried) {
     if (int rc = run_phase(g, o, o.restart_every, c, since, s)) return rc;
-    if (int rc = read_states(w, 1, s)) return rc;
-    const PRState st = w.h_st[0];
-    if (st.done) {
+    if (int rc = read_states(w, M, s)) return rc;
+    if (all_done()) {
       done = true;
       break;
     }
-    const double delta = st.resid;
+    bool any_done = false;
+    for (int i = 0; i < M; ++i) any_done = any_done || w.h_st[i].done;
+    if (any_done) break;
+    std::copy(w.h_st, w.h_st + M, at_k.begin());  // every member at iteration at_k[0].iter
     HIP_TRY(launch_restart_inputs(L, o.prec, w.p[c % 2], w.p[(c + 1) % 2], lw.t[1], lw.t[0], nullptr, w.st, lw.F,
                                   nullptr, s));
     HIP_TRY(launch_mlp_forward(m->theta, m->wq, lw.F, g->n, lw.s, s));
-    HIP_TRY(launch_restart_vector(L, o.prec, w.p[c % 2], lw.s, w.st, lw.t[0], w.slots, 1, s));
+    HIP_TRY(launch_restart_vector(L, o.prec, w.p[c % 2], lw.s, w.st, lw.t[0], w.slots, M, s));
     HIP_TRY(hipMemcpyAsync(lw.t[1], w.p[c % 2], bytes, hipMemcpyDeviceToDevice, s));
-    HIP_TRY(launch_pr_init(L, o.prec, lw.t[0], nullptr, w.p[0], w.z[0], g->d_outdeg, w.st, w.slots, 1, s, 1, st.iter));
-    HIP_TRY(launch_bv_pagerank_iter(L, o.prec, pr_args(w, o, nullptr, g->d_outdeg, 1, 1, 0), s));
+    HIP_TRY(launch_pr_init(L, o.prec, lw.t[0], nullptr, w.p[0], w.z[0], g->d_outdeg, w.st, w.slots, M, s, 1,
+                           at_k[0].iter));
+    HIP_TRY(launch_bv_pagerank_iter(L, o.prec, pr_args(w, o, nullptr, g->d_outdeg, M, 1, 0), s));
     c = 1;
-    if (int rc = read_states(w, 1, s)) return rc;
-    if (w.h_st[0].resid < o.beta * delta) {
-      ++accepted;
-      since = 1;
-      if (w.h_st[0].done) {
-        done = true;
-        break;
+    if (int rc = read_states(w, M, s)) return rc;
+    bool any_rejected = false;
+    for (int i = 0; i < M; ++i) {
+      if (w.h_st[i].resid < o.beta * at_k[size_t(i)].resid) {
+        ++accepted[size_t(i)];
+        continue;
       }
-    } else {
-      ++rejected;
-      HIP_TRY(launch_pr_init(L, o.prec, lw.t[1], nullptr, w.p[0], w.z[0], g->d_outdeg, w.st, w.slots, 1, s, 0,
-                             st.iter));
-      c = 0;
+      // back to p_K and the phase-end state (the probe still counts as a product)
+      ++rejected[size_t(i)];
+      any_rejected = true;
+      HIP_TRY(launch_pr_restore(o.prec, lw.t[1], w.p[1], w.z[1], g->d_outdeg, g->offsets[size_t(i)],
+                                g->offsets[size_t(i) + 1], s));
+      w.h_st[i] = at_k[size_t(i)];
+    }
+    if (any_rejected) {
+      HIP_TRY(hipMemcpyAsync(w.st, w.h_st, sizeof(PRState) * size_t(M), hipMemcpyHostToDevice, s));
+      break;
+    }
+    since = 1;
+    if (all_done()) {
+      done = true;
       break;
     }
   }
   if (!done && c % 2) {
     // the captured chunk starts from buffer 0
-    HIP_TRY(launch_bv_pagerank_iter(L, o.prec, pr_args(w, o, nullptr, g->d_outdeg, 1, 1, c), s));
-    if (int rc = read_states(w, 1, s)) return rc;
-    done = w.h_st[0].done;
+    HIP_TRY(launch_bv_pagerank_iter(L, o.prec, pr_args(w, o, nullptr, g->d_outdeg, M, 1, c), s));
+    if (int rc = read_states(w, M, s)) return rc;
+    done = all_done();
   }
   if (!done) {
     auto iter = [&](const PRArgs& a, hipStream_t cs) { return launch_bv_pagerank_iter(L, o.prec, a, cs); };
-    if (int rc = replay_until_done(w, g->cap, o, nullptr, g->d_outdeg, 1, 1, s, iter)) return rc;
+    if (int rc = replay_until_done(w, g->cap, o, nullptr, g->d_outdeg, M, 1, s, iter)) return rc;
   }
   HIP_TRY(copy_member_outputs(w, g->offsets, o.prec, p_out, s));
-  return fill_results(w, 1, 0, rejected, accepted, res);
+  return fill_results(w, M, 0, rejected.data(), accepted.data(), res);
 }
 
 }  // namespace
@@ -859,8 +884,8 @@ int bvmv_pagerank(bvmv_graph* g, const bvmv_pr_opts* opts, const void* teleport,
   DevLayout L = g->L;
   const int prec = o.prec;
   if (o.mlp) {
-    if (k != 1 || g->ngraphs != 1 || teleport || start)
-      return fail(BVMV_EINVAL, "learned restarts need k = 1, a single graph, uniform teleport and no start vector");
+    if (k != 1 || teleport || start)
+      return fail(BVMV_EINVAL, "learned restarts need k = 1, uniform teleport and no start vector");
     if (o.mlp->device != g->device) return fail(BVMV_EINVAL, "graph and network on different devices");
     return run_learned(g, o, o.mlp, p_out, res, s);
   }
@@ -950,6 +975,14 @@ int bvmv_group(bvmv_graph* const* graphs, int count, bvmv_graph** out) {
     g->tile_offsets.push_back(uint32_t(hl.tiles.size()));
   }
   hl.n = g->n;
+  // row statistics for the learned restarts' inputs: kept when every member
+  // has them and the members share R (the depth input is depth / R)
+  bool stats = true;
+  for (int i = 0; i < count; ++i)
+    stats = stats && graphs[i]->dec.stats.size() == size_t(graphs[i]->n) && graphs[i]->R == graphs[0]->R;
+  if (stats)
+    for (int i = 0; i < count; ++i)
+      g->dec.stats.insert(g->dec.stats.end(), graphs[i]->dec.stats.begin(), graphs[i]->dec.stats.end());
   g->W = graphs[0]->W;
   g->R = graphs[0]->R;
   g->Lmin = graphs[0]->Lmin;

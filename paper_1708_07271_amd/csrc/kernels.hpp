@@ -96,6 +96,9 @@ hipError_t launch_csr_pagerank_iter(const DevCsr& C, int prec, const PRArgs& a, 
 hipError_t launch_csr_pr_init(const DevCsr& C, int prec, const void* start, const void* tele, void* p0, void* z0,
                               const int32_t* outdeg, PRState* st, double* slots, hipStream_t s);
 
+// rows [r0, r1) of p and z restored from the iterate src (z = src / d)
+hipError_t launch_pr_restore(int prec, const void* src, void* p, void* z, const int32_t* outdeg, int64_t r0,
+                             int64_t r1, hipStream_t s);
 // out column c (column-major, ld = n) = the buffer (p0 or p1) holding column
 // c's final iterate
 hipError_t launch_pr_select(int prec, const PRState* st, const void* p0, const void* p1, void* out, int64_t n, int k,

@@ -212,7 +212,9 @@ def test_learned_argument_errors(P):
         P.bvmv_pagerank_detail(G, p, mlp=m, teleport=torch.full((g.n,), 1.0 / g.n, device=DEV))
     with pytest.raises(P.BvmvError):
         P.bvmv_pagerank_detail(G, torch.empty(g.n * 2, device=DEV), mlp=m, k=2)
-    grp = P.bvmv_group([G, G])
+    # a group whose members were coded with different R has no depth input
+    G4 = P.bvmv_load(B.encode(g, R=4).data)
+    grp = P.bvmv_group([G, G4])
     with pytest.raises(P.BvmvError):
         P.bvmv_pagerank_detail(grp, torch.empty(2 * g.n, device=DEV), mlp=m)
 
@@ -243,6 +245,96 @@ def test_learned_edge_cases(P):
     ru = P.bvmv_pagerank_detail(G, pu, prec=F64)[0]
     assert rw["converged"] and rw["restarts_accepted"] == 2
     assert float((pw - pu).abs().sum()) < 2 * (0.85 / 0.15) * 1e-6
+
+
+# ---------------------------------------------------------------- groups
+# Learned restarts on a group (block-diagonal union of graphs): every member
+# is restarted at the same phase boundary while all are active, and each
+# keeps or rejects its restart on its own probe.
+
+def _group_members():
+    return [B.web_graph(15_000, 15.0, 81), B.web_graph(30_000, 6.0, 82), B.web_graph(20_000, 30.0, 83)]
+
+
+def _group_run(P, gs, prec, **kw):
+    Gs = [P.bvmv_load(B.encode(g).data) for g in gs]
+    grp = P.bvmv_group(Gs)
+    dt = torch.float64 if prec == F64 else torch.float32
+    n = sum(g.n for g in gs)
+    pg = torch.empty(n, dtype=dt, device=DEV)
+    rg = P.bvmv_pagerank_detail(grp, pg, prec=prec, **kw)
+    solo = []
+    for G, g in zip(Gs, gs):
+        ps = torch.empty(g.n, dtype=dt, device=DEV)
+        solo.append((ps, P.bvmv_pagerank_detail(G, ps, prec=prec, **kw)[0]))
+    offs = np.cumsum([0] + [g.n for g in gs])
+    return pg, rg, solo, offs
+
+
+@pytest.mark.parametrize("prec", [F64, F32C])
+def test_group_learned_zero_network_matches_solo_runs(P, prec):
+    """Zero network: every member keeps both restarts, exactly as alone."""
+    gs = _group_members()
+    pg, rg, solo, offs = _group_run(P, gs, prec, mlp=P.bvmv_mlp_create(_zero_theta()))
+    for i, (ps, rs) in enumerate(solo):
+        print("member", i, rg[i], flush=True)
+        assert rg[i] == rs and rg[i]["restarts_accepted"] == 2 and rg[i]["converged"]
+        assert torch.equal(pg[offs[i]:offs[i + 1]], ps)
+
+
+@pytest.mark.parametrize("prec", [F64, F32C])
+def test_group_learned_mixed_decisions(P, prec):
+    """A constant correction of 1.75 deltas fails the probe of the first two
+    members and passes the third's (decided by the oracle's restarted run).
+    With one restart the group's members are exactly their solo runs, and
+    their decisions and fixed points are the oracle's."""
+    gs = _group_members()
+    m = P.bvmv_mlp_create(_const_theta(1.75))
+    pg, rg, solo, offs = _group_run(P, gs, prec, mlp=m, max_restarts=1)
+    assert [r["restarts_accepted"] for r in rg] == [0, 0, 1]
+    assert [r["restarts_rejected"] for r in rg] == [1, 1, 0]
+    for i, (g, (ps, rs)) in enumerate(zip(gs, solo)):
+        assert rg[i] == rs
+        assert torch.equal(pg[offs[i]:offs[i + 1]], ps)
+        rowptr, col, Fs = _decoded(B.encode(g))
+        po, to, ro, oko, info = restart.pagerank_restarted(rowptr, col, lambda F: np.full(F.shape[0], 1.75), Fs,
+                                                           max_restarts=1)
+        assert oko and (rg[i]["restarts_accepted"], rg[i]["restarts_rejected"]) == (info["accepted"], info["rejected"])
+        assert abs(rg[i]["iters"] - to) <= 1
+        assert float(np.abs(ps.double().cpu().numpy() - po).sum()) < 2 * (0.85 / 0.15) * 1e-6
+
+
+def test_group_learned_rejection_ends_restarts(P):
+    """After a member rejects, no member is restarted again: with the default
+    two restarts, the accepting member of the mixed group is restarted once."""
+    gs = _group_members()
+    pg, rg, solo, offs = _group_run(P, gs, F64, mlp=P.bvmv_mlp_create(_const_theta(1.75)))
+    assert [(r["restarts_accepted"], r["restarts_rejected"]) for r in rg] == [(0, 1), (0, 1), (1, 0)]
+    assert all(r["converged"] for r in rg)
+    # the rejecting members are their plain runs (one extra product each)
+    Gs = [P.bvmv_load(B.encode(g).data) for g in gs[:2]]
+    for i, G in enumerate(Gs):
+        pp = torch.empty(gs[i].n, dtype=torch.float64, device=DEV)
+        rp = P.bvmv_pagerank_detail(G, pp, prec=F64)[0]
+        assert rg[i]["iters"] == rp["iters"] and rg[i]["products"] == rp["iters"] + 1
+        assert torch.equal(pg[offs[i]:offs[i + 1]], pp)
+
+
+def test_group_learned_no_restart_once_a_member_is_done(P):
+    """A member that converges within the first phase (a complete graph, one
+    iteration) holds every restart back: the group's run is its plain run."""
+    gs = [B.complete_graph(60), B.web_graph(20_000, 12.0, 84)]
+    Gs = [P.bvmv_load(B.encode(g).data) for g in gs]
+    grp = P.bvmv_group(Gs)
+    n = sum(g.n for g in gs)
+    pl = torch.empty(n, dtype=torch.float64, device=DEV)
+    rl = P.bvmv_pagerank_detail(grp, pl, prec=F64, mlp=P.bvmv_mlp_create(_zero_theta()))
+    pp = torch.empty(n, dtype=torch.float64, device=DEV)
+    rp = P.bvmv_pagerank_detail(grp, pp, prec=F64)
+    for a, b in zip(rl, rp):
+        assert a["restarts_accepted"] == a["restarts_rejected"] == 0
+        assert a["iters"] == b["iters"] and a["products"] == b["iters"]
+    assert torch.equal(pl, pp)
 
 
 def _train(P, graphs, steps, K=10, seed=1):
