@@ -175,6 +175,18 @@ def bench_social(args, B, P, np, torch, dev):
     print(json.dumps(out), flush=True)
 
 
+def ragged_encs(B, np):
+    """The 48 ragged web-like graphs: n_g = round(10^(4 + 2 u_g)), u_g uniform
+    from seed 999, mean out-degree 20, graph seeds 1000 + g (bitstreams)."""
+    rng = np.random.default_rng(999)
+    sizes = np.round(10 ** (4 + 2 * rng.random(48))).astype(np.int64)
+    t0 = time.perf_counter()
+    encs = [B.encode(B.web_graph(int(n), 20.0, 1000 + i)).data for i, n in enumerate(sizes)]
+    log("ragged: %d graphs, n in [%d, %d], sum n %d (%.1fs)" % (len(sizes), sizes.min(), sizes.max(), sizes.sum(),
+                                                                 time.perf_counter() - t0))
+    return sizes, encs
+
+
 def bench_ragged(args, B, P, np, torch, dev):
     """Ragged batch: 48 web-like graphs, n_g = round(10^(4 + 2 u_g)) with u_g
     uniform from seed 999, mean out-degree 20, graph seeds 1000 + g.  Global
@@ -182,12 +194,7 @@ def bench_ragged(args, B, P, np, torch, dev):
     48 separate calls and as one group (one launch sequence for all members),
     each with the fixed default layout and with autotuned layouts; plus one
     product over the whole group.  Median of 3 after a warm-up call."""
-    rng = np.random.default_rng(999)
-    sizes = np.round(10 ** (4 + 2 * rng.random(48))).astype(np.int64)
-    t0 = time.perf_counter()
-    encs = [B.encode(B.web_graph(int(n), 20.0, 1000 + i)).data for i, n in enumerate(sizes)]
-    log("ragged: %d graphs, n in [%d, %d], sum n %d (%.1fs)" % (len(sizes), sizes.min(), sizes.max(), sizes.sum(),
-                                                                 time.perf_counter() - t0))
+    sizes, encs = ragged_encs(B, np)
     t0 = time.perf_counter()
     fixed = [P.bvmv_load(e) for e in encs]
     t_fixed = time.perf_counter() - t0
@@ -256,7 +263,8 @@ def bench_warm(args, B, P, np, torch, dev):
     and with a zero network (every restart accepted and the identity: the
     restart overhead alone).  Each PageRank is timed end to end, median of 3;
     the learned run's first call, which also computes the structural inputs
-    once for the graph, is reported apart."""
+    once for the graph, is reported apart.  The same three runs then cover the
+    ragged group of 48 graphs (one launch sequence for all members)."""
     from oracle import mlp as _oracle_mlp  # parameter initialisation only (seeded uniform Glorot)
     K = 10
     rng = np.random.default_rng(2000)
@@ -322,12 +330,32 @@ def bench_warm(args, B, P, np, torch, dev):
                           rejected=r["restarts_rejected"], converged=bool(r["converged"]),
                           seconds=float(np.median(ts)))
         log("pagerank n=%d %s: %s" % (n, name, runs[name]))
+    # the same network on the ragged group of 48 graphs (one launch sequence)
+    _, encs = ragged_encs(B, np)
+    members = [P.bvmv_load(e) for e in encs]
+    grp = P.bvmv_group(members)
+    pg = torch.empty(grp.n, device=dev)
+    P.bvmv_pagerank(grp, pg)  # graph capture
+    timed(lambda: P.bvmv_pagerank_detail(grp, pg, mlp=m))  # structural inputs, once
+    group = {}
+    for name, kw in (("plain", {}), ("learned", {"mlp": m}), ("zero_network", {"mlp": zero})):
+        ts = []
+        for _ in range(3):
+            rs, t = timed(lambda: P.bvmv_pagerank_detail(grp, pg, **kw))
+            ts.append(t)
+        group[name] = dict(max_iters=max(r["iters"] for r in rs), products=sum(r["products"] for r in rs),
+                           members_accepting=sum(1 for r in rs if r["restarts_accepted"] > 0),
+                           members_rejecting=sum(1 for r in rs if r["restarts_rejected"] > 0),
+                           converged=all(r["converged"] for r in rs), seconds=float(np.median(ts)))
+        log("pagerank ragged group (%d graphs, n=%d) %s: %s" % (len(members), grp.n, name, group[name]))
+    group["speedup_learned_vs_plain"] = group["plain"]["seconds"] / group["learned"]["seconds"]
     out = {"mode": "learned-warm-restart", "train_graphs": len(sizes), "train_nodes": int(sizes.sum()),
            "restart_every": K, "train_steps": args.warm_steps, "train_seconds": t_train, "data_seconds": t_data,
            "loss_trace": losses, "test_n": n, "test_m": g.m, "dtype": "f32 two-sum compensated",
            "first_learned_call_seconds": s_first, **runs,
            "speedup_learned_vs_plain": runs["plain"]["seconds"] / runs["learned"]["seconds"],
-           "product_ratio_learned_vs_plain": runs["learned"]["products"] / runs["plain"]["products"]}
+           "product_ratio_learned_vs_plain": runs["learned"]["products"] / runs["plain"]["products"],
+           "ragged_group": {"graphs": len(members), "n": grp.n, **group}}
     print(json.dumps(out), flush=True)
 
 
