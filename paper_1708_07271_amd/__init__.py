@@ -215,15 +215,24 @@ def bvmv_multiply(g: Graph, x, y, prec=BVMV_F32_COMP, stream=None):
 
 
 def bvmv_multiply_batch(g: Graph, X, Y, prec=BVMV_F32_COMP, stream=None):
-    """X, Y: (k, n) contiguous device tensors, row c = right-hand side c (the
-    column-major n x k blocks of the C interface, leading dimension n)."""
+    """X, Y: (k, n) device tensors, row c = right-hand side c (the column-major
+    n x k blocks of the C interface).  Rows may be views into longer rows:
+    both tensors need unit element stride and the same row stride ld >= n,
+    which is passed as the leading dimension."""
+    import torch
     p = _prec(prec)
     dt = _vec_dtype(p)
     if X.dim() != 2 or X.shape != Y.shape or X.shape[1] != g.n:
         raise ValueError("X and Y must be (k, n)")
     k = X.shape[0]
-    _check(load_library().bvmv_multiply_batch(g.handle, _dev_ptr(X, dt), _dev_ptr(Y, dt), k, g.n, p,
-                                              _stream_ptr(stream)))
+    ld = X.stride(0) if k > 1 else g.n
+    if (k > 1 and Y.stride(0) != ld) or X.stride(1) != 1 or Y.stride(1) != 1 or ld < g.n:
+        raise ValueError("X and Y need unit element stride and one row stride >= n")
+    for t in (X, Y):
+        if not isinstance(t, torch.Tensor) or not t.is_cuda or t.dtype != dt:
+            raise TypeError("expected %s device tensors" % dt)
+    _check(load_library().bvmv_multiply_batch(g.handle, ctypes.c_void_p(X.data_ptr()), ctypes.c_void_p(Y.data_ptr()),
+                                              k, ld, p, _stream_ptr(stream)))
 
 
 def _pr_opts(damping, tol, max_iter, prec, chunk, fallback_check=0, mlp=None, restart_every=0, max_restarts=0):

@@ -553,9 +553,10 @@ struct TileCtx {
 // kernel: prepare(tc) runs once per wave before the tile is decoded and
 // returns per-lane state; fetch(tc, c) issues vector c's global loads ahead
 // of their use (vector 0 with the tile's own loads, vector c + 1 while c is
-// summed); skip(st, c) passes over vector c (block-uniform); col(...) takes
-// vector c's sums; finish(...) runs once per block after the last vector,
-// with every wave present.  operator() is the CSR kernel's one-call form.
+// summed); skip(st, c) passes over vector c and all_done(st) over the whole
+// tile (both block-uniform); col(...) takes vector c's sums; finish(...) runs
+// once per block after the last vector, with every wave present.  operator()
+// is the CSR kernel's one-call form.
 constexpr int kEpiRows = kTileRowsMax / 64;  // rows of a tile per lane
 
 template <class M>
@@ -566,6 +567,7 @@ struct EpiStore {
   __device__ State prepare(const TileCtx&) const { return {}; }
   __device__ Fetch fetch(const TileCtx&, int) const { return {}; }
   __device__ bool skip(const State&, int) const { return false; }
+  __device__ bool all_done(const State&) const { return false; }
   __device__ void col(const TileCtx& tc, const typename M::CAcc* s_y, unsigned char*, int, State&,
                       const Fetch&) const {
     for (uint32_t r = lane_id(); r < tc.nrows; r += 64) y[tc.row0 + r] = M::out(s_y[r]);
@@ -726,6 +728,7 @@ struct EpiPR {
     return f;
   }
   __device__ bool skip(const State&, int) const { return false; }
+  __device__ bool all_done(const State&) const { return false; }
   __device__ void col(const TileCtx& tc, const typename M::CAcc* s_y, unsigned char* s_blk, int, State& S,
                       const Fetch& f) const {
     X* pn = static_cast<X*>(a.p_new) + tc.row0;
@@ -771,6 +774,7 @@ struct EpiStoreCols {
   __device__ State prepare(const TileCtx&) const { return {}; }
   __device__ Fetch fetch(const TileCtx&, int) const { return {}; }
   __device__ bool skip(const State&, int) const { return false; }
+  __device__ bool all_done(const State&) const { return false; }
   __device__ void col(const TileCtx& tc, const typename M::CAcc* s_y, unsigned char*, int c, State&,
                       const Fetch&) const {
     typename M::X* yc = y + int64_t(c) * ld + tc.row0;
@@ -831,6 +835,9 @@ struct EpiPRCols {
     return f;
   }
   __device__ bool skip(const State& S, int c) const { return (S.done >> c) & 1u; }
+  __device__ bool all_done(const State& S) const {
+    return S.done == (a.k >= 64 ? ~uint64_t(0) : (uint64_t(1) << a.k) - 1);
+  }
   __device__ void col(const TileCtx& tc, const typename M::CAcc* s_y, unsigned char*, int c, State& S,
                       const Fetch& f) const {
     const int64_t base = int64_t(c) * n + tc.row0;
@@ -1007,6 +1014,7 @@ __device__ __forceinline__ void process_tile(const DevLayout& L, const TileDesc&
   // the multi-vector epilogue's per-lane state, read before the decode
   const TileCtx tc{td.row0, td.nrows, td.graph, slot};
   auto S = epi.prepare(tc);
+  if (epi.all_done(S)) return;  // every vector is done: the whole block returns
   const uint32_t lane = lane_id();
   const uint32_t nrows = td.nrows;
   const int64_t win0 = td.win0;

@@ -190,6 +190,29 @@ def test_batch_matches_oracle(P, graphs, k):
         assert _rel(Yd64.cpu().numpy()[k - 1], product.matvec(g.rowptr, g.col, X[:, k - 1].astype(np.float64))) < 1e-12
 
 
+def test_batch_leading_dimension(P):
+    """Right-hand sides as rows of a wider buffer (ld = n + 37): the padding
+    is neither read into the products nor written."""
+    g = B.web_graph(9000, 12.0, 71)
+    G = P.bvmv_load(B.encode(g).data)
+    k, ld = 5, g.n + 37
+    rng = np.random.default_rng(71)
+    Xb = torch.from_numpy(rng.random((k, ld), dtype=np.float32)).to(DEV)
+    Yb = torch.full((k, ld), -7.0, device=DEV)
+    P.bvmv_multiply_batch(G, Xb[:, :g.n], Yb[:, :g.n], P.BVMV_F32_COMP)
+    torch.cuda.synchronize()
+    X = Xb.cpu().numpy()
+    Y = Yb.cpu().numpy()
+    assert np.all(Y[:, g.n:] == -7.0)
+    for c in range(k):
+        assert _rel(Y[c, :g.n], product.matvec(g.rowptr, g.col, X[c, :g.n].astype(np.float64))) < 1e-5
+    # each column equals the single-vector product bit for bit
+    y1 = torch.empty(g.n, device=DEV)
+    P.bvmv_multiply(G, Xb[3, :g.n].contiguous(), y1, P.BVMV_F32_COMP)
+    torch.cuda.synchronize()
+    assert torch.equal(y1, Yb[3, :g.n])
+
+
 def test_group_block_diagonal(P):
     sizes = [1000, 5000, 20_000, 300]
     gs = [B.web_graph(n, 12.0, 50 + i) for i, n in enumerate(sizes)]
