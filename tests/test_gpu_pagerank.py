@@ -162,6 +162,24 @@ def test_batched_uniform_and_limits(P):
     assert all(r[0] <= 2 and r[1] for r in res5)
 
 
+def test_batched_64_columns_equal_single_runs(P):
+    """The largest batch (k = 64, one column per lane of the epilogue's
+    state): every column is bit-identical to the single-vector run with its
+    teleport vector, with the same iteration count, although the columns stop
+    at different iterations."""
+    g = B.web_graph(12_000, 10.0, 85)
+    G = P.bvmv_load(B.encode(g).data)
+    k = 64
+    V = B.teleport_sets(g.n, k, 16, seed=11).astype(np.float32)
+    p, res = _pr_k(P, G, g.n, k, P.BVMV_F32_COMP, V)
+    assert len({r[0] for r in res}) > 1
+    for c in range(0, k, 9):
+        print("column", c, flush=True)
+        pc, ((it, ok, r),) = _pr(P, G, g.n, P.BVMV_F32_COMP, teleport=V[:, c].astype(np.float64))
+        assert ok and res[c][1] and res[c][0] == it
+        assert np.array_equal(p[:, c], pc)
+
+
 def test_edgeless_and_determinism(P):
     G = P.bvmv_load(B.encode(B.empty_graph(500)).data)
     p, ((it, ok, r),) = _pr(P, G, 500, P.BVMV_F32_COMP)
