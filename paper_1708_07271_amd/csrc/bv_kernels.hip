@@ -1346,12 +1346,13 @@ __global__ void __launch_bounds__(kThreads) pr_init_cols_kernel(DevLayout L, int
 // delta = ||p_K - p_{K-1}||_1 is its state's residual and whose node count is
 // 1 / inv_n: log(n p_K), then n (p_j - p_{j-1}) / delta for the last three
 // steps, newest first.  With p_star given, also the training target
-// T_v = n (p*_v - p_K(v)) / delta.  F is node-major with 12 floats a row.
+// T_v = n (p*_v - p_K(v)) / delta.  The four inputs of v are one 16-byte
+// store at Ft + v * ft_stride.
 template <class M>
 __global__ void __launch_bounds__(kThreads) restart_inputs_kernel(
     const uint32_t* __restrict__ row0s, uint32_t row_stride, const uint32_t* __restrict__ graphs, const void* pK_,
     const void* pK1_, const void* pK2_, const void* pK3_, const void* p_star_, const PRState* __restrict__ st_all,
-    float* __restrict__ F, float* __restrict__ T) {
+    float* __restrict__ Ft, int64_t ft_stride, float* __restrict__ T) {
   using X = typename M::X;
   const uint32_t wave = threadIdx.x >> 6, lane = lane_id();
   const size_t tile = size_t(blockIdx.x) * kWaves + wave;
@@ -1368,11 +1369,8 @@ __global__ void __launch_bounds__(kThreads) restart_inputs_kernel(
   for (uint32_t r = lane; r < nrows; r += 64) {
     const uint32_t v = row0 + r;
     const double a = double(pK[v]), b = double(pK1[v]), c = double(pK2[v]), d = double(pK3[v]);
-    float* f = F + size_t(v) * 12;
-    f[8] = float(log(n * a));
-    f[9] = float(scale * (a - b));
-    f[10] = float(scale * (b - c));
-    f[11] = float(scale * (c - d));
+    *reinterpret_cast<float4*>(Ft + int64_t(v) * ft_stride) =
+        make_float4(float(log(n * a)), float(scale * (a - b)), float(scale * (b - c)), float(scale * (c - d)));
     if (p_star) T[v] = float(scale * (double(p_star[v]) - a));
   }
 }
@@ -1763,18 +1761,19 @@ hipError_t launch_cols_pr_init(const DevLayout& L, int prec, int k, const void* 
 }
 
 hipError_t launch_restart_inputs(const DevLayout& L, int prec, const void* pK, const void* pK1, const void* pK2,
-                                 const void* pK3, const void* p_star, const PRState* st, float* F, float* T,
-                                 hipStream_t s) {
+                                 const void* pK3, const void* p_star, const PRState* st, float* Ft,
+                                 int64_t ft_stride, float* T, hipStream_t s) {
   if (L.ntiles == 0) return hipSuccess;
+  if ((reinterpret_cast<uintptr_t>(Ft) | uintptr_t(ft_stride) * 4) & 15) return hipErrorInvalidValue;
   const uint32_t* base = reinterpret_cast<const uint32_t*>(L.tiles);
   const uint32_t stride = sizeof(TileDesc) / 4;
   const uint32_t* graphs = base + offsetof(TileDesc, graph) / 4;
   if (prec == 0)
     hipLaunchKernelGGL(restart_inputs_kernel<MF64>, dim3(L.ntiles / kWaves), dim3(kThreads), 0, s, base, stride,
-                       graphs, pK, pK1, pK2, pK3, p_star, st, F, T);
+                       graphs, pK, pK1, pK2, pK3, p_star, st, Ft, ft_stride, T);
   else
     hipLaunchKernelGGL(restart_inputs_kernel<MF32>, dim3(L.ntiles / kWaves), dim3(kThreads), 0, s, base, stride,
-                       graphs, pK, pK1, pK2, pK3, p_star, st, F, T);
+                       graphs, pK, pK1, pK2, pK3, p_star, st, Ft, ft_stride, T);
   return hipGetLastError();
 }
 

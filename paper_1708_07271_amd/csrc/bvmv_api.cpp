@@ -131,23 +131,26 @@ struct PRWork {
   }
 };
 
-// Buffers of the learned warm restarts kept with a graph: the 12 network
-// inputs per node (structural columns filled once), the network output, and
-// two iterate snapshots of the iterate type.
+// Buffers of the learned warm restarts kept with a graph: the network inputs
+// per node (the 8 structural ones, n x 8, filled once; the 4 of the current
+// restart, n x 4), the network output, and two iterate snapshots of the
+// iterate type.
 struct LearnWork {
   int64_t n = 0;
   int prec = -1;
-  float* F = nullptr;
+  float* Fs = nullptr;
+  float* Ft = nullptr;
   float* s = nullptr;
   void* t[2] = {nullptr, nullptr};
   bool struct_ready = false;
 
   void release() {
-    dev_free(F);
+    dev_free(Fs);
+    dev_free(Ft);
     dev_free(s);
     dev_free(t[0]);
     dev_free(t[1]);
-    F = s = nullptr;
+    Fs = Ft = s = nullptr;
     t[0] = t[1] = nullptr;
     n = 0;
     prec = -1;
@@ -156,7 +159,8 @@ struct LearnWork {
   int ensure(int pr, int64_t nn) {
     if (n != nn) {
       release();
-      HIP_TRY(hipMalloc(reinterpret_cast<void**>(&F), size_t(std::max<int64_t>(nn, 1)) * kMlpIn * sizeof(float)));
+      HIP_TRY(hipMalloc(reinterpret_cast<void**>(&Fs), size_t(std::max<int64_t>(nn, 1)) * 8 * sizeof(float)));
+      HIP_TRY(hipMalloc(reinterpret_cast<void**>(&Ft), size_t(std::max<int64_t>(nn, 1)) * 4 * sizeof(float)));
       HIP_TRY(hipMalloc(reinterpret_cast<void**>(&s), size_t(std::max<int64_t>(nn, 1)) * sizeof(float)));
       n = nn;
     }
@@ -514,7 +518,7 @@ namespace {
 
 // Structural inputs 0..7 of every node into columns 0..7 of F (synchronous:
 // the scratch is freed on return).
-int compute_structural(bvmv_graph* g, float* F, hipStream_t s) {
+int compute_structural(bvmv_graph* g, float* F, int64_t stride, hipStream_t s) {
   if (g->dec.stats.size() != size_t(g->n)) return fail(BVMV_EINVAL, "row statistics missing");
   const int64_t n = g->n;
   if (!g->d_stats) {
@@ -534,7 +538,8 @@ int compute_structural(bvmv_graph* g, float* F, hipStream_t s) {
   HIP_TRY(launch_feature_inputs(n, indeg.p, g->d_outdeg, xd, xi, s));
   HIP_TRY(launch_bv_multiply(g->L, BVMV_F32_COMP, xd, yd, s));
   HIP_TRY(launch_bv_multiply(g->L, BVMV_F32_COMP, xi, yi, s));
-  HIP_TRY(launch_features(n, indeg.p, g->d_outdeg, g->d_stats, yd, yi, 1.0f / float(std::max(g->R, 1)), F, s));
+  HIP_TRY(launch_features(n, indeg.p, g->d_outdeg, g->d_stats, yd, yi, 1.0f / float(std::max(g->R, 1)), F, stride,
+                          s));
   HIP_TRY(hipStreamSynchronize(s));
   return BVMV_OK;
 }
@@ -587,7 +592,7 @@ int run_learned(bvmv_graph* g, const PROptsResolved& o, const bvmv_mlp* m, void*
   const int M = g->ngraphs;
   if (int rc = start_learned(g, o, s)) return rc;
   if (!lw.struct_ready) {
-    if (int rc = compute_structural(g, lw.F, s)) return rc;
+    if (int rc = compute_structural(g, lw.Fs, 8, s)) return rc;
     lw.struct_ready = true;
   }
   const DevLayout& L = g->L;
@@ -612,9 +617,9 @@ int run_learned(bvmv_graph* g, const PROptsResolved& o, const bvmv_mlp* m, void*
     for (int i = 0; i < M; ++i) any_done = any_done || w.h_st[i].done;
     if (any_done) break;
     std::copy(w.h_st, w.h_st + M, at_k.begin());  // every member at iteration at_k[0].iter
-    HIP_TRY(launch_restart_inputs(L, o.prec, w.p[c % 2], w.p[(c + 1) % 2], lw.t[1], lw.t[0], nullptr, w.st, lw.F,
-                                  nullptr, s));
-    HIP_TRY(launch_mlp_forward(m->theta, m->wq, lw.F, g->n, lw.s, s));
+    HIP_TRY(launch_restart_inputs(L, o.prec, w.p[c % 2], w.p[(c + 1) % 2], lw.t[1], lw.t[0], nullptr, w.st, lw.Ft,
+                                  4, nullptr, s));
+    HIP_TRY(launch_mlp_forward(m->theta, m->wq, FeatIn{lw.Fs, lw.Ft, 8, 4}, g->n, lw.s, s));
     HIP_TRY(launch_restart_vector(L, o.prec, w.p[c % 2], lw.s, w.st, lw.t[0], w.slots, M, s));
     HIP_TRY(hipMemcpyAsync(lw.t[1], w.p[c % 2], bytes, hipMemcpyDeviceToDevice, s));
     HIP_TRY(launch_pr_init(L, o.prec, lw.t[0], nullptr, w.p[0], w.z[0], g->d_outdeg, w.st, w.slots, M, s, 1,
@@ -1171,7 +1176,7 @@ int bvmv_features(bvmv_graph* g, float* F, void* stream) {
   if (!g || !F) return fail(BVMV_EINVAL, "null argument");
   if (g->ngraphs != 1) return fail(BVMV_EINVAL, "features need a single graph");
   DeviceGuard dg(g->device);
-  return compute_structural(g, F, static_cast<hipStream_t>(stream));
+  return compute_structural(g, F, kMlpIn, static_cast<hipStream_t>(stream));
 }
 
 int bvmv_restart_sample(bvmv_graph* g, int K, int prec, const void* p_star, float* F, float* T, double* delta,
@@ -1186,14 +1191,14 @@ int bvmv_restart_sample(bvmv_graph* g, int K, int prec, const void* p_star, floa
   po.max_iter = K + 1;
   PROptsResolved o;
   if (int rc = resolve_pr_opts(&po, o)) return rc;
-  if (int rc = compute_structural(g, F, s)) return rc;
+  if (int rc = compute_structural(g, F, kMlpIn, s)) return rc;
   if (int rc = start_learned(g, o, s)) return rc;
   int c = 0, since = 0;
   if (int rc = run_phase(g, o, K, c, since, s)) return rc;
   if (int rc = read_states(g->pr, 1, s)) return rc;
   if (g->pr.h_st[0].done) return fail(BVMV_EINVAL, "PageRank converged within K iterations");
   PRWork& w = g->pr;
-  HIP_TRY(launch_restart_inputs(g->L, prec, w.p[c % 2], w.p[(c + 1) % 2], g->lw.t[1], g->lw.t[0], p_star, w.st, F, T,
+  HIP_TRY(launch_restart_inputs(g->L, prec, w.p[c % 2], w.p[(c + 1) % 2], g->lw.t[1], g->lw.t[0], p_star, w.st, F + 8, kMlpIn, T,
                                 s));
   HIP_TRY(hipStreamSynchronize(s));
   if (delta) *delta = w.h_st[0].resid;
@@ -1243,7 +1248,7 @@ int bvmv_mlp_params(const bvmv_mlp* m, float* params) {
 int bvmv_mlp_forward(bvmv_mlp* m, const float* F, int64_t n, float* s, void* stream) {
   if (!m || !F || !s || n < 0) return fail(BVMV_EINVAL, "bad network arguments");
   DeviceGuard dg(m->device);
-  HIP_TRY(launch_mlp_forward(m->theta, m->wq, F, n, s, static_cast<hipStream_t>(stream)));
+  HIP_TRY(launch_mlp_forward(m->theta, m->wq, feat_rows12(F), n, s, static_cast<hipStream_t>(stream)));
   return BVMV_OK;
 }
 

@@ -81,11 +81,12 @@ hipError_t launch_bv_multiply_cols(const DevLayout& L, int prec, const void* X, 
 hipError_t launch_bv_cols_pagerank_iter(const DevLayout& L, int prec, const PRArgs& a, hipStream_t s);
 hipError_t launch_cols_pr_init(const DevLayout& L, int prec, int k, const void* start, const void* tele, void* p0,
                                void* z0, const int32_t* outdeg, PRState* st, double* slots, hipStream_t s);
-// Warm restart: inputs 8..11 of every node into F (n x 12) and, with p_star,
-// the target into T, from the last four iterates and the states' residuals.
+// Warm restart: inputs 8..11 of every node v into Ft + v * ft_stride (four
+// floats, 16-byte aligned) and, with p_star, the target into T, from the last
+// four iterates and the states' residuals.
 hipError_t launch_restart_inputs(const DevLayout& L, int prec, const void* pK, const void* pK1, const void* pK2,
-                                 const void* pK3, const void* p_star, const PRState* st, float* F, float* T,
-                                 hipStream_t s);
+                                 const void* pK3, const void* p_star, const PRState* st, float* Ft,
+                                 int64_t ft_stride, float* T, hipStream_t s);
 // Unnormalised restart vector q from p_K and the network output s; each
 // member's sum of q ends in its state's delta field.
 hipError_t launch_restart_vector(const DevLayout& L, int prec, const void* pK, const float* svec, PRState* st,
@@ -110,8 +111,18 @@ constexpr int kMlpIn = 12, kMlpHidden = 64;
 constexpr int kMlpParams = kMlpHidden * kMlpIn + kMlpHidden + kMlpHidden * kMlpHidden + kMlpHidden + kMlpHidden + 1;
 constexpr int kMlpWeights = kMlpHidden * kMlpIn + kMlpHidden * kMlpHidden + kMlpHidden;  // BF16 copies
 constexpr int64_t kMlpMaxBatch = 1 << 20; // feature rows per gradient call
-// s = MLP(F) for n feature rows (node-major n x 12)
-hipError_t launch_mlp_forward(const float* theta, const uint16_t* wq, const float* F, int64_t n, float* s,
+// The network's inputs of node v: inputs 0..7 at s + v * ss, inputs 8..11 at
+// t + v * ts (16-byte aligned rows).  The public n x 12 rows are {F, F + 8,
+// 12, 12}; the learned restarts keep the two parts apart ({Fs, Ft, 8, 4}) so
+// that each restart writes its four inputs as whole rows.
+struct FeatIn {
+  const float* s;
+  const float* t;
+  int64_t ss, ts;
+};
+__host__ __device__ inline FeatIn feat_rows12(const float* F) { return FeatIn{F, F + 8, 12, 12}; }
+// s = MLP(inputs) for n nodes
+hipError_t launch_mlp_forward(const float* theta, const uint16_t* wq, const FeatIn& in, int64_t n, float* s,
                               hipStream_t st);
 // grad[0..kMlpParams) = gradient of the mean squared error, grad[kMlpParams] = the loss;
 // part: one row of kMlpParams + 1 floats per 32 feature rows (ceil(n / 32) rows)
@@ -124,8 +135,9 @@ hipError_t launch_mlp_quantize(const float* theta, uint16_t* wq, hipStream_t st)
 // product inputs of the structural features: d and indeg as floats
 hipError_t launch_feature_inputs(int64_t n, const int32_t* indeg, const int32_t* outdeg, float* xd, float* xi,
                                  hipStream_t st);
-// structural inputs 0..7 into columns 0..7 of F (n x 12); yd = B d, yi = B indeg
+// structural inputs 0..7 into F + v * stride (stride 12: columns 0..7 of the
+// n x 12 rows; stride 8: rows of their own); yd = B d, yi = B indeg
 hipError_t launch_features(int64_t n, const int32_t* indeg, const int32_t* outdeg, const uint32_t* stats,
-                           const float* yd, const float* yi, float inv_r, float* F, hipStream_t st);
+                           const float* yd, const float* yi, float inv_r, float* F, int64_t stride, hipStream_t st);
 
 }  // namespace bvmv

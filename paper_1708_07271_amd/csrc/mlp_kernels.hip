@@ -21,6 +21,9 @@ namespace {
 
 typedef short s4 __attribute__((ext_vector_type(4)));
 typedef float f16v __attribute__((ext_vector_type(16)));
+typedef float f2v __attribute__((ext_vector_type(2)));
+typedef __bf16 bf2v __attribute__((ext_vector_type(2)));
+typedef uint32_t u2v __attribute__((ext_vector_type(2)));
 
 constexpr int kThreads = 256;
 constexpr int kNin = kMlpIn, kNh = kMlpHidden;
@@ -49,13 +52,11 @@ __device__ __forceinline__ float gelu_grad(float z) {
 
 __device__ __forceinline__ f16v mfma(s4 a, s4 b, f16v c) { return __builtin_amdgcn_mfma_f32_32x32x8bf16_1k(a, b, c, 0, 0, 0); }
 
+// four values rounded to BF16 (to nearest, ties to even: the same rounding
+// as bf16_bits for finite values), two per conversion instruction
 __device__ __forceinline__ s4 pack4(float a, float b, float c, float d) {
-  s4 r;
-  r[0] = short(bf16_bits(a));
-  r[1] = short(bf16_bits(b));
-  r[2] = short(bf16_bits(c));
-  r[3] = short(bf16_bits(d));
-  return r;
+  const bf2v lo = __builtin_convertvector((f2v){a, b}, bf2v), hi = __builtin_convertvector((f2v){c, d}, bf2v);
+  return __builtin_bit_cast(s4, (u2v){__builtin_bit_cast(uint32_t, lo), __builtin_bit_cast(uint32_t, hi)});
 }
 
 __device__ __forceinline__ uint32_t lane_id() { return threadIdx.x & 63u; }
@@ -84,23 +85,25 @@ struct alignas(16) WaveLds {
   float G[32];                 // per-node output gradient
 };
 
-// Forward of one 32-node tile by one wave.  F: node-major features (n x 12).
-// Returns per-lane registers needed by the backward pass.
+// Forward of one 32-node tile by one wave, node-major (rows of each product
+// are the tile's nodes), keeping what the backward pass needs.
 struct Fwd {
   f16v z1[2], z2[2];   // pre-activations, D layout (rows = nodes, column = hidden % 32 of block b)
   s4 h1q[2][4];        // bf16(h1) as A/B operands over 8-node steps (D registers 4s..4s+3)
   float s;             // output of node lane % 32 (both halves)
 };
 
-__device__ __forceinline__ void load_x_tile(const float* __restrict__ F, int64_t n, int64_t node0, s4 (&a1)[2]) {
+// Inputs 4h .. 4h+3 and 8 + 4h .. 8 + 4h + 3 (zero past 11) of node
+// node0 + lane % 32 (zero past n).
+__device__ __forceinline__ void load_x_tile(const FeatIn& in, int64_t n, int64_t node0, s4 (&a1)[2]) {
   const uint32_t lane = lane_id(), h = lane >> 5;
   const int64_t node = node0 + (lane & 31);
   float x[8] = {0, 0, 0, 0, 0, 0, 0, 0};
   if (node < n) {
-    const float4 lo = *reinterpret_cast<const float4*>(F + node * kNin + 4 * h);
+    const float4 lo = *reinterpret_cast<const float4*>(in.s + node * in.ss + 4 * h);
     x[0] = lo.x; x[1] = lo.y; x[2] = lo.z; x[3] = lo.w;
     if (h == 0) {
-      const float4 hi = *reinterpret_cast<const float4*>(F + node * kNin + 8);
+      const float4 hi = *reinterpret_cast<const float4*>(in.t + node * in.ts);
       x[4] = hi.x; x[5] = hi.y; x[6] = hi.z; x[7] = hi.w;
     }
   }
@@ -141,11 +144,11 @@ __device__ __forceinline__ void load_weights(const float* __restrict__ theta, co
   W.b3 = theta[oB3];
 }
 
-__device__ __forceinline__ void forward_tile(const float* __restrict__ F, int64_t n, int64_t node0,
-                                             const FwdWeights& W, const uint16_t* s_w2, WaveLds& L, Fwd& o) {
+__device__ __forceinline__ void forward_tile(const FeatIn& in, int64_t n, int64_t node0, const FwdWeights& W,
+                                             const uint16_t* s_w2, WaveLds& L, Fwd& o) {
   const uint32_t lane = lane_id(), h = lane >> 5, c = lane & 31;
   s4 a1[2];
-  load_x_tile(F, n, node0, a1);
+  load_x_tile(in, n, node0, a1);
   const f16v zero = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
   // layer 1: z1 = W1 bf(x) + b1, h1 = gelu(z1)
 #pragma unroll
@@ -197,24 +200,73 @@ __device__ __forceinline__ void forward_tile(const float* __restrict__ F, int64_
 }
 
 // ------------------------------------------------------------------ forward
+// Inference, one 32-node tile per wave and turn, in the transposed form: the
+// hidden units are the rows of each product and the tile's nodes its columns,
+//   layer 1: z1' (64 x 32) = W1 x',        A = rows of W1, B = x' (inputs x nodes)
+//   layer 2: z2' (64 x 32) = W2 bf(h1)',   A = rows of W2, B = bf(h1)'
+// so that the D registers 4s .. 4s+3 of layer 1's block s / 4 are, for the
+// lane's node, hidden units 8s + 4h + e: layer 2's B operand of step s, with
+// no transpose through LDS.  Register v of block b holds unit 32b + drow(v, h);
+// the output layer sums the lane's 32 units and the other half's.  The
+// arithmetic is the node-major form's (the same operands and roundings).
 __global__ void __launch_bounds__(kThreads) mlp_forward_kernel(const float* __restrict__ theta,
-                                                               const uint16_t* __restrict__ wq,
-                                                               const float* __restrict__ F, int64_t n,
+                                                               const uint16_t* __restrict__ wq, FeatIn in, int64_t n,
                                                                float* __restrict__ out) {
-  __shared__ WaveLds lds[kThreads / 64];
   __shared__ __align__(16) uint16_t s_w2[kNh * kSStride];
-  stage_w2(wq, s_w2);
-  const uint32_t wave = threadIdx.x >> 6, lane = lane_id();
-  WaveLds& L = lds[wave];
+  __shared__ __align__(16) float s_c[3 * kNh];  // b1, b2, and w3 as its BF16 value
+  for (uint32_t q = threadIdx.x; q < uint32_t(kNh); q += kThreads) {
+    s_c[q] = theta[oB1 + q];
+    s_c[kNh + q] = theta[oB2 + q];
+    s_c[2 * kNh + q] = bf16_float(wq[qW3 + q]);
+  }
+  stage_w2(wq, s_w2);  // (ends with a block barrier)
+  const uint32_t wave = threadIdx.x >> 6, lane = lane_id(), h = lane >> 5, c = lane & 31;
   FwdWeights W;
   load_weights(theta, wq, W);
+  const f16v zero = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
   const int64_t ntiles = (n + 31) / 32;
   const int64_t stride = int64_t(gridDim.x) * (kThreads / 64);
   for (int64_t t = int64_t(blockIdx.x) * (kThreads / 64) + wave; t < ntiles; t += stride) {
-    Fwd o;
-    forward_tile(F, n, t * 32, W, s_w2, L, o);
-    const int64_t node = t * 32 + (lane & 31);
-    if (lane < 32 && node < n) out[node] = o.s;
+    // zero (t < 2^40), but not known to the compiler: the LDS operands below
+    // are read once per tile instead of being held in registers for the loop
+    const uint32_t z = uint32_t(t >> 40);
+    s4 a1[2];
+    load_x_tile(in, n, t * 32, a1);
+    // layer 1: h1 = gelu(W1 x + b1), rounded to BF16
+    s4 h1q[2][4];
+#pragma unroll
+    for (int b = 0; b < 2; ++b) {
+      f16v d = mfma(W.b1[b][0], a1[0], zero);
+      d = mfma(W.b1[b][1], a1[1], d);
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const float4 bb = *reinterpret_cast<const float4*>(&s_c[z + 32 * b + 8 * q + 4 * h]);
+        h1q[b][q] = pack4(gelu(d[4 * q] + bb.x), gelu(d[4 * q + 1] + bb.y), gelu(d[4 * q + 2] + bb.z),
+                          gelu(d[4 * q + 3] + bb.w));
+      }
+    }
+    // layer 2 and the output layer: s = w3 . gelu(W2 bf(h1) + b2) + b3
+    float part = 0.0f;
+#pragma unroll
+    for (int b = 0; b < 2; ++b) {
+      f16v d = zero;
+#pragma unroll
+      for (int s = 0; s < 8; ++s)  // A[j][k] = W2[j][k], j = 32b + lane % 32, k = 8s + 4h + e
+        d = mfma(*reinterpret_cast<const s4*>(&s_w2[z + (32 * b + c) * kSStride + 8 * s + 4 * h]), h1q[s / 4][s % 4],
+                 d);
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const float4 bb = *reinterpret_cast<const float4*>(&s_c[z + kNh + 32 * b + 8 * q + 4 * h]);
+        const float4 ww = *reinterpret_cast<const float4*>(&s_c[z + 2 * kNh + 32 * b + 8 * q + 4 * h]);
+        part += gelu(d[4 * q] + bb.x) * ww.x;
+        part += gelu(d[4 * q + 1] + bb.y) * ww.y;
+        part += gelu(d[4 * q + 2] + bb.z) * ww.z;
+        part += gelu(d[4 * q + 3] + bb.w) * ww.w;
+      }
+    }
+    part += __shfl_xor(part, 32, 64);
+    const int64_t node = t * 32 + c;
+    if (lane < 32 && node < n) out[node] = part + W.b3;
   }
 }
 
@@ -243,7 +295,7 @@ __global__ void __launch_bounds__(kThreads) mlp_backward_kernel(const float* __r
   const float inv_n = 1.0f / float(n);
   const int64_t node0 = t * 32;
   Fwd o;
-  forward_tile(F, n, node0, W, s_w2, L, o);
+  forward_tile(feat_rows12(F), n, node0, W, s_w2, L, o);
   // output gradient g_i = 2 (s_i - t_i) / n of node i = lane % 32
   const int64_t node = node0 + c;
   float gi = 0.0f, lsum = 0.0f;
@@ -394,12 +446,12 @@ __global__ void __launch_bounds__(kThreads) features_kernel(int64_t n, const int
                                                             const uint32_t* __restrict__ stats,
                                                             const float* __restrict__ yd,
                                                             const float* __restrict__ yi, float inv_r,
-                                                            float* __restrict__ F) {
+                                                            float* __restrict__ F, int64_t stride) {
   for (int64_t v = int64_t(blockIdx.x) * kThreads + threadIdx.x; v < n; v += int64_t(gridDim.x) * kThreads) {
     const float ind = float(indeg[v]), d = float(outdeg[v]);
     const float den = fmaxf(ind, 1.0f);
     const uint32_t* st = stats + 5 * v;
-    float* f = F + v * kNin;
+    float* f = F + v * stride;
     f[0] = log1pf(ind);
     f[1] = log1pf(d);
     f[2] = float(st[0]) * inv_r;
@@ -425,12 +477,15 @@ int grid_for(int64_t items, int cap) { return int(std::max<int64_t>(1, std::min<
 
 }  // namespace
 
-hipError_t launch_mlp_forward(const float* theta, const uint16_t* wq, const float* F, int64_t n, float* s,
+hipError_t launch_mlp_forward(const float* theta, const uint16_t* wq, const FeatIn& in, int64_t n, float* s,
                               hipStream_t st) {
   if (n <= 0) return hipSuccess;
+  if (((reinterpret_cast<uintptr_t>(in.s) | reinterpret_cast<uintptr_t>(in.t) | uintptr_t(in.ss) * 4 |
+        uintptr_t(in.ts) * 4) & 15) || in.ss < 8 || in.ts < 4)
+    return hipErrorInvalidValue;
   const int64_t tiles = (n + 31) / 32;
   const int blocks = int(std::min<int64_t>((tiles + 3) / 4, 4096));
-  hipLaunchKernelGGL(mlp_forward_kernel, dim3(blocks), dim3(kThreads), 0, st, theta, wq, F, n, s);
+  hipLaunchKernelGGL(mlp_forward_kernel, dim3(blocks), dim3(kThreads), 0, st, theta, wq, in, n, s);
   return hipGetLastError();
 }
 
@@ -469,9 +524,9 @@ hipError_t launch_feature_inputs(int64_t n, const int32_t* indeg, const int32_t*
 }
 
 hipError_t launch_features(int64_t n, const int32_t* indeg, const int32_t* outdeg, const uint32_t* stats,
-                           const float* yd, const float* yi, float inv_r, float* F, hipStream_t st) {
+                           const float* yd, const float* yi, float inv_r, float* F, int64_t stride, hipStream_t st) {
   hipLaunchKernelGGL(features_kernel, dim3(grid_for(n, 4096)), dim3(kThreads), 0, st, n, indeg, outdeg, stats, yd,
-                     yi, inv_r, F);
+                     yi, inv_r, F, stride);
   return hipGetLastError();
 }
 
