@@ -243,6 +243,9 @@ int bvmv_layout_selfcheck(const void* bitstream, size_t nbytes, const bvmv_load_
  *   8 log(n p_K)   9 n (p_K - p_{K-1}) / delta   10 n (p_{K-1} - p_{K-2}) / delta
  *   11 n (p_{K-2} - p_{K-3}) / delta
  * ------------------------------------------------------------------------- */
+/* Input rows F (device, n x 12 node-major FP32) must start on a 16-byte
+ * boundary: the kernels move each row's inputs as 16-byte vectors.  A
+ * misaligned F gives BVMV_EINVAL. */
 #define BVMV_NFEAT 12        /* inputs per node */
 #define BVMV_MLP_PARAMS 5057 /* W1 (64x12), b1 (64), W2 (64x64), b2 (64), w3 (64), b3 (1), row-major (out, in) */
 

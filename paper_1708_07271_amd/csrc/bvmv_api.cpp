@@ -1174,6 +1174,7 @@ void bvmv_csr_free(bvmv_csr* c) {
 
 int bvmv_features(bvmv_graph* g, float* F, void* stream) {
   if (!g || !F) return fail(BVMV_EINVAL, "null argument");
+  if (reinterpret_cast<uintptr_t>(F) & 15) return fail(BVMV_EINVAL, "F must be 16-byte aligned");
   if (g->ngraphs != 1) return fail(BVMV_EINVAL, "features need a single graph");
   DeviceGuard dg(g->device);
   return compute_structural(g, F, kMlpIn, static_cast<hipStream_t>(stream));
@@ -1182,6 +1183,7 @@ int bvmv_features(bvmv_graph* g, float* F, void* stream) {
 int bvmv_restart_sample(bvmv_graph* g, int K, int prec, const void* p_star, float* F, float* T, double* delta,
                         void* stream) {
   if (!g || !F || (p_star && !T)) return fail(BVMV_EINVAL, "null argument");
+  if (reinterpret_cast<uintptr_t>(F) & 15) return fail(BVMV_EINVAL, "F must be 16-byte aligned");
   if (g->ngraphs != 1) return fail(BVMV_EINVAL, "restart samples need a single graph");
   if (K < 3 || prec < 0 || prec > 2) return fail(BVMV_EINVAL, "K must be >= 3 and prec valid");
   DeviceGuard dg(g->device);
@@ -1247,6 +1249,7 @@ int bvmv_mlp_params(const bvmv_mlp* m, float* params) {
 
 int bvmv_mlp_forward(bvmv_mlp* m, const float* F, int64_t n, float* s, void* stream) {
   if (!m || !F || !s || n < 0) return fail(BVMV_EINVAL, "bad network arguments");
+  if (reinterpret_cast<uintptr_t>(F) & 15) return fail(BVMV_EINVAL, "F must be 16-byte aligned");
   DeviceGuard dg(m->device);
   HIP_TRY(launch_mlp_forward(m->theta, m->wq, feat_rows12(F), n, s, static_cast<hipStream_t>(stream)));
   return BVMV_OK;
@@ -1254,6 +1257,7 @@ int bvmv_mlp_forward(bvmv_mlp* m, const float* F, int64_t n, float* s, void* str
 
 int bvmv_mlp_gradient(bvmv_mlp* m, const float* F, const float* target, int64_t n, float* grad, void* stream) {
   if (!m || !F || !target || !grad || n < 1 || n > kMlpMaxBatch) return fail(BVMV_EINVAL, "bad network arguments");
+  if (reinterpret_cast<uintptr_t>(F) & 15) return fail(BVMV_EINVAL, "F must be 16-byte aligned");
   DeviceGuard dg(m->device);
   const int64_t rows = (n + 31) / 32;
   if (rows > m->part_rows) {

@@ -212,6 +212,13 @@ def test_learned_argument_errors(P):
         P.bvmv_pagerank_detail(G, p, mlp=m, teleport=torch.full((g.n,), 1.0 / g.n, device=DEV))
     with pytest.raises(P.BvmvError):
         P.bvmv_pagerank_detail(G, torch.empty(g.n * 2, device=DEV), mlp=m, k=2)
+    # input rows off a 16-byte boundary are refused (the kernels read them as
+    # 16-byte vectors)
+    Fb = torch.zeros(100 * 12 + 1, device=DEV)
+    with pytest.raises(P.BvmvError):
+        P.bvmv_mlp_forward(m, Fb[1:], torch.empty(100, device=DEV))
+    with pytest.raises(P.BvmvError):
+        P.bvmv_features(G, torch.zeros(g.n * 12 + 1, device=DEV)[1:])
     # a group whose members were coded with different R has no depth input
     G4 = P.bvmv_load(B.encode(g, R=4).data)
     grp = P.bvmv_group([G, G4])
