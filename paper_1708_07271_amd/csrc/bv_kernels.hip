@@ -315,13 +315,27 @@ template <uint32_t Q>
 __device__ __forceinline__ uint32_t flat_chunk(uint32_t E) { return ((E + 63) / 64 + Q - 1) / Q * Q; }
 
 constexpr int kRound = 8;  // stream dwords a lane has in flight per round of a flat pass
+static_assert(kDataPadBytes >= 4 * kRound, "a round may read kRound dwords past a stream's last dword");
 
 // Load dwords first .. first + kRound - 1 of a stream, clamped to its last
-// dword (never out of bounds; clamped dwords are never used).
+// dword: every word is an entry of the stream (end_pass decodes whole rounds,
+// gathers included, before it stops at the lane's chunk end).
 __device__ __forceinline__ void load_round(const uint32_t* __restrict__ g, uint32_t first, uint32_t last,
                                            uint32_t (&d)[kRound]) {
 #pragma unroll
   for (int k = 0; k < kRound; ++k) d[k] = g[min(first + uint32_t(k), last)];
+}
+
+// Load dwords f .. f + kRound - 1, f = min(first, last), with one address and
+// immediate offsets.  Dwords past `last` belong to the next stream or to the
+// zero padding of at least kRound dwords that ends the device data array, so
+// the loads stay in bounds; only for passes that zero every word past the
+// lane's chunk before decoding it (the running-sum singles pass).
+__device__ __forceinline__ void load_round_raw(const uint32_t* __restrict__ g, uint32_t first, uint32_t last,
+                                               uint32_t (&d)[kRound]) {
+  const uint32_t* q = g + min(first, last);
+#pragma unroll
+  for (int k = 0; k < kRound; ++k) d[k] = q[k];
 }
 
 // Geometry of a lane's chunk of a flat pass: P entries per dword, the chunk
@@ -423,16 +437,17 @@ __device__ __forceinline__ uint32_t sign_word(uint32_t d, uint32_t one_hi, uint3
   return r;
 }
 
-// Load dwords first .. first + kRound - 1 of a stream; those at or past `end`
-// (the end of the lane's chunk) read as 0: an entry that adds Z[0] = 0 and
-// ends no row.
+// Load dwords first .. first + kRound - 1 of a stream (first <= last: the
+// words past it are in bounds as for load_round); those at or past `end` (the
+// end of the lane's chunk) read as 0: an entry that adds Z[0] = 0 and ends no
+// row.
 __device__ __forceinline__ void load_round_z(const uint32_t* __restrict__ g, uint32_t first, uint32_t end,
                                              uint32_t last, uint32_t (&d)[kRound]) {
+  const uint32_t* q = g + min(first, last);
 #pragma unroll
   for (int k = 0; k < kRound; ++k) {
-    const uint32_t i = first + uint32_t(k);
-    const uint32_t w = g[min(i, last)];
-    d[k] = i < end ? w : 0u;
+    const uint32_t w = q[k];
+    d[k] = first + uint32_t(k) < end ? w : 0u;
   }
 }
 
@@ -939,7 +954,12 @@ __device__ __forceinline__ void issue_loads(const DevLayout& L, const TileDesc& 
   if (n16) {
     const uint32_t* g16 = reinterpret_cast<const uint32_t*>(L.data + td.data16);
     const Chunk<2> ch(n16, flat_chunk<2>(n16));
-    load_round(g16, ch.d0, ch.last, ld.pre);
+    // the running-sum mode zeros the words past the lane's chunk before use;
+    // the other modes decode whole rounds (clamped copies)
+    if constexpr (std::is_same<M, MF32C>::value)
+      load_round_raw(g16, ch.d0, ch.last, ld.pre);
+    else
+      load_round(g16, ch.d0, ch.last, ld.pre);
   }
 #pragma unroll
   for (int q = 0; q < RPL; ++q) {
@@ -964,6 +984,31 @@ __device__ __forceinline__ void stage_regs(const X (&xs)[SV], XA xw, uint32_t n,
   const uint32_t lane = lane_id();
   const uint32_t ch = (n + 63) / 64;
   const uint32_t b = min(n, lane * ch), e = min(n, b + ch);
+  if (ch <= uint32_t(SV)) {
+    // the lane's chunk is in registers: the values past it count as zeros,
+    // so the sums are those of the general form below, term for term
+    const uint32_t cnt = e - b;
+    double xv[SV];
+#pragma unroll
+    for (int j = 0; j < SV; ++j) xv[j] = uint32_t(j) < cnt ? double(xs[j]) : 0.0;
+    double run = 0.0;
+    if (prefix) {
+      double t = xv[0];
+#pragma unroll
+      for (int j = 1; j < SV; ++j) t += xv[j];
+      const double inc = wave_incl_scan_f64(t);
+      run = inc - t;
+      if (lane == 63) Z[2 * size_t(n) + 1] = inc;
+    }
+    if (lane == 0) Z[0] = 0.0;
+    double2* Zp = reinterpret_cast<double2*>(Z + 1);
+#pragma unroll
+    for (int j = 0; j < SV; ++j) {
+      if (uint32_t(j) < cnt) Zp[b + j] = make_double2(run, xv[j]);
+      run += xv[j];
+    }
+    return;
+  }
   double t = 0.0;
   if (prefix) {
 #pragma unroll
@@ -1613,10 +1658,12 @@ hipError_t launch_tile_sv(const DevLayout& L, const Src& src, const Epi& epi, co
   return hipGetLastError();
 }
 
-// window values a lane loads up front: 8 up to 512 columns, else 16 (a longer
-// lane chunk loads the rest while it stages)
+// window values a lane loads up front: 4 up to 256 columns, 8 up to 512, else
+// 16 (a longer lane chunk loads the rest while it stages); no more than the
+// widest chunk, since every slot costs loads and staging work
 template <class M, int RPL, class Src, class Epi>
 hipError_t launch_tile_rpl(const DevLayout& L, const Src& src, const Epi& epi, const PRState* skip, hipStream_t s) {
+  if (L.wcap <= 256) return launch_tile_sv<M, RPL, 4>(L, src, epi, skip, s);
   if (L.wcap <= 512) return launch_tile_sv<M, RPL, 8>(L, src, epi, skip, s);
   return launch_tile_sv<M, RPL, 16>(L, src, epi, skip, s);
 }

@@ -302,7 +302,9 @@ int upload_layout(bvmv_graph* g) {
   if (int rc = dev_upload(&g->d_tiles, hl.tiles.data(), hl.tiles.size())) return rc;
   if (int rc = dev_upload(&g->d_info, hl.info.data(), hl.info.size())) return rc;
   if (int rc = dev_upload(&g->d_ns, hl.ns.data(), hl.ns.size())) return rc;
-  if (int rc = dev_upload(&g->d_data, hl.data.data(), hl.data.size())) return rc;
+  // zero padding after the last stream: a lane's round of stream words may
+  // run up to kRound dwords past its stream's last dword
+  if (int rc = dev_upload(&g->d_data, hl.data.data(), hl.data.size(), kDataPadBytes)) return rc;
   if (int rc = dev_upload(&g->d_longs, hl.longs.data(), hl.longs.size())) return rc;
   if (int rc = dev_upload(&g->d_outdeg, g->h_outdeg.data(), g->h_outdeg.size())) return rc;
   g->L.tiles = g->d_tiles;

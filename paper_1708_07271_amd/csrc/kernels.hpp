@@ -8,6 +8,10 @@
 
 namespace bvmv {
 
+// Zero bytes after the last stream of the device data array (the tile kernel
+// reads whole rounds of stream words without clamping them to the stream).
+constexpr size_t kDataPadBytes = 64;
+
 struct DevLayout {
   const TileDesc* tiles = nullptr;
   const uint32_t* info = nullptr;
