@@ -392,7 +392,7 @@ def main():
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py runs on one GPU only: the compressed product and PageRank here are single-GPU "
-              "kernels (see DESIGN.md for how the path would shard)", file=sys.stderr)
+              "kernels; independent graphs or right-hand sides would go one set per GPU", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np
