@@ -261,13 +261,12 @@ __device__ __forceinline__ uint64_t block_excl_scan_u64(uint64_t v, uint64_t* s_
   return base + inc - v;
 }
 
-// q = a / C for a < 2^24 and a wave-uniform C >= 1 (float estimate, then an
-// exact correction).
-__device__ __forceinline__ uint32_t div_small(uint32_t a, uint32_t C, float invC) {
-  uint32_t q = uint32_t(float(a) * invC);
-  if (q * C > a) --q;
-  else if ((q + 1) * C <= a) ++q;
-  return q;
+// q = floor(a / C) for an entry offset a of a flat pass (a < 64 C) and its
+// chunk length C < 2^14, from invC within 1 ulp of 1 / C: (a + 1/2) / C lies
+// at least 1 / (2C) > 3e-5 from every integer, while one fused multiply-add
+// of a value below 65 errs by less than 2e-5.
+__device__ __forceinline__ uint32_t div_small(uint32_t a, uint32_t /*C*/, float invC) {
+  return uint32_t(fmaf(float(a), invC, 0.5f * invC));
 }
 
 // Inclusive wave scan of a u32 by DPP row shifts and row broadcasts (no LDS).
@@ -404,14 +403,15 @@ __device__ __forceinline__ void end_pass(uint32_t E, uint32_t C, const uint32_t*
   carry[lane_id()] = a;
 }
 
-// Row ends inside the lane's chunk of an end-bit stream (see end_pass).
-template <uint32_t P, uint32_t m>
+// Row ends inside the lane's chunk of an end-bit stream (see end_pass);
+// kZeroed: the words of `pre` past the chunk are already 0.
+template <uint32_t P, uint32_t m, bool kZeroed = false>
 __device__ __forceinline__ uint32_t chunk_ends(uint32_t E, uint32_t C, const uint32_t* __restrict__ g,
                                                const uint32_t (&pre)[kRound]) {
   const Chunk<P> ch(E, C);
   uint32_t n = 0;
 #pragma unroll
-  for (int k = 0; k < kRound; ++k) n += __popc(uint32_t(k) < ch.nd ? pre[k] & m : 0u);
+  for (int k = 0; k < kRound; ++k) n += __popc(kZeroed || uint32_t(k) < ch.nd ? pre[k] & m : 0u);
   for (uint32_t r = kRound; r < ch.nd; ++r) n += __popc(g[ch.d0 + r] & m);
   return n;
 }
@@ -927,10 +927,11 @@ struct Cols {
 template <class X, int SV, class Src>
 __device__ __forceinline__ void load_window(const Src& src, int64_t win0, uint32_t n, int c, X (&xs)[SV]) {
   const uint32_t lane = lane_id();
-  const uint32_t w = (n + 63) / 64, b = min(n, lane * w), e = min(n, b + w);
+  const uint32_t w = (n + 63) / 64, b = min(n, lane * w);
   const X* xc = src.col(c) + win0;
+  // values past the lane's chunk are read (in the window) but never used
 #pragma unroll
-  for (int j = 0; j < SV; ++j) xs[j] = xc[e > b ? min(b + uint32_t(j), e - 1) : 0u];
+  for (int j = 0; j < SV; ++j) xs[j] = xc[min(b + uint32_t(j), n - 1)];
 }
 
 // Global data of one tile, loaded before any of it is used: the first round
@@ -1101,7 +1102,7 @@ __device__ __forceinline__ void process_tile(const DevLayout& L, const TileDesc&
     mw[q] = __ballot(cw[q] != 0);
   }
   // the lanes' singles (bits 0..15) and the row ends in the lane's chunk (16..31)
-  const uint32_t sc16 = s16 | ((n16 ? chunk_ends<2, kS16End | (kS16End << 16)>(n16, C16, g16, pre) : 0u) << 16);
+  const uint32_t sc16 = s16 | ((n16 ? chunk_ends<2, kS16End | (kS16End << 16), kRun>(n16, C16, g16, pre) : 0u) << 16);
   const uint32_t ex16 = wave_incl_scan_u32(sc16) - sc16;
   uint32_t o16[RPL], k16[RPL], kw[RPL];
   {
