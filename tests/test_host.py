@@ -120,3 +120,25 @@ def test_layout_crafted_edge_cases(P):
     for case in LAYOUT_CASES:
         y, _ = P.bvmv_layout_selfcheck(enc.data, x, *case)
         assert np.array_equal(y, product.matvec(g.rowptr, g.col, x))
+
+
+def _chunk_index(a, C, rcp_offset):
+    """The tile kernel's chunk index of an entry offset a: floor of one fused
+    multiply-add (a + 1/2) * r in single precision, r = 1/C rounded to single
+    precision and moved by rcp_offset ulps (the hardware reciprocal is within
+    1 ulp).  The product is formed in double (exact to far below the margin)
+    and rounded once to single."""
+    r = np.float32(1.0 / C)
+    r = np.nextafter(r, np.float32(np.inf if rcp_offset > 0 else -np.inf), dtype=np.float32) if rcp_offset else r
+    v = (a.astype(np.float64) + 0.5) * np.float64(r)
+    return np.floor(v.astype(np.float32)).astype(np.int64)
+
+
+@pytest.mark.parametrize("C", list(range(1, 131)) + [255, 1000, 4096, 16383])
+def test_chunk_index_formula_is_exact(C):
+    """floor((a + 1/2) r) = a // C for every entry offset a < 64 C of a flat
+    pass, whichever way the reciprocal rounds: (a + 1/2) / C stays at least
+    1 / (2C) from every integer, far beyond the single-precision error."""
+    a = np.arange(64 * C, dtype=np.int64)
+    for off in (-1, 0, 1):
+        assert np.array_equal(_chunk_index(a, C, off), a // C), (C, off)
