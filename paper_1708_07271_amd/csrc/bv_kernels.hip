@@ -923,7 +923,8 @@ struct Cols {
   __device__ const X* col(int c) const { return x + int64_t(c) * ld; }
 };
 
-// The lane's first SV values of column c's x window (clamped addresses).
+// The lane's first SV values of column c's x window (addresses clamped to
+// the window; the slots past the lane's chunk hold values it never uses).
 template <class X, int SV, class Src>
 __device__ __forceinline__ void load_window(const Src& src, int64_t win0, uint32_t n, int c, X (&xs)[SV]) {
   const uint32_t lane = lane_id();
@@ -944,9 +945,10 @@ struct TileLoads {
   typename M::X xs[M::kInt ? 1 : SV];  // (the integer mode stages no window)
 };
 
-// Issue a tile's loads into `ld` from safe (clamped) addresses only; the
-// values are masked where process_tile uses them, so all the loads are in
-// flight together before the first is waited for.
+// Issue a tile's loads into `ld` from in-bounds addresses only (clamped, or
+// within the zero padding after the last stream); the values are masked
+// where process_tile uses them, so all the loads are in flight together
+// before the first is waited for.
 template <class M, int RPL, int SV, class Src>
 __device__ __forceinline__ void issue_loads(const DevLayout& L, const TileDesc& td, const Src& src,
                                             TileLoads<M, RPL, SV>& ld) {
