@@ -148,6 +148,34 @@ def test_edge_cases(P):
         assert np.array_equal(_mul(P, G, x.astype(np.float32), P.BVMV_F32_COMP), product.matvec(g.rowptr, g.col, x))
 
 
+@pytest.mark.parametrize("lay", range(len(LAYOUTS)))
+def test_entries_at_the_end_of_the_stream_array(P, lay):
+    """The last tile's rows reach far outside their window (wide entries) and
+    hold runs (prefix pairs in the singles stream), so the device stream array
+    ends with both kinds of entry and then only its zero padding.  Each flat
+    pass reads whole rounds of stream words near that end: the pass that
+    decodes whole rounds (other precisions, wide entries) must see only words
+    of its own stream, and the running-sum pass must zero what lies past its
+    chunk.  Every mode matches the oracle."""
+    n = 5000
+    lists = [[(i + 1) % n] for i in range(n)]
+    for i in range(n - 48, n):
+        lists[i] = sorted(({0, 3, 7, 11, i - 1500, i - 3100} | set(range(i - 40, i - 30))) - {i})
+    g = B.from_lists(lists)
+    G = P.bvmv_load(B.encode(g).data, **LAYOUTS[lay])
+    assert P.bvmv_get_info(G)["escapes"] > 0
+    x = B.uniform_x(n, 77)
+    assert _rel(_mul(P, G, x, P.BVMV_F64), product.matvec(g.rowptr, g.col, x)) < 1e-12
+    x32 = x.astype(np.float32)
+    ref32 = product.matvec(g.rowptr, g.col, x32.astype(np.float64))
+    assert _rel(_mul(P, G, x32, P.BVMV_F32_COMP), ref32) < 1e-5
+    assert _rel(_mul(P, G, x32, P.BVMV_F32), ref32) < 1e-3
+    xi = B.integer_x(n, 5, 9)
+    refi = product.matvec(g.rowptr, g.col, xi)
+    for prec in (P.BVMV_F32, P.BVMV_F32_COMP):
+        assert np.array_equal(_mul(P, G, xi.astype(np.float32), prec), refi)
+
+
 def test_csr_baseline(P, graphs):
     for name, (g, enc) in graphs.items():
         G = P.bvmv_load(enc.data, keep_lists=1)
