@@ -142,3 +142,15 @@ def test_chunk_index_formula_is_exact(C):
     a = np.arange(64 * C, dtype=np.int64)
     for off in (-1, 0, 1):
         assert np.array_equal(_chunk_index(a, C, off), a // C), (C, off)
+
+
+def test_bench_refuses_several_gpus():
+    """bench.py is single-GPU: --gpus 2 exits with status 2 and a message,
+    before any device work."""
+    import subprocess
+    import sys
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    r = subprocess.run([sys.executable, os.path.join(root, "bench.py"), "--gpus", "2"], capture_output=True,
+                       text=True, timeout=120, env=dict(os.environ, WORLD_SIZE="1"))
+    assert r.returncode == 2
+    assert "one GPU" in r.stderr and not r.stdout.strip()
