@@ -281,7 +281,7 @@ int decode_stream(const uint8_t* data, size_t nbytes, int nthreads, DecodedGraph
   out.col.resize(m);
   uint64_t pos = 0;
   for (auto& o : outs) {
-    std::memcpy(out.col.data() + pos, o.col.data(), o.col.size() * 4);
+    if (!o.col.empty()) std::memcpy(out.col.data() + pos, o.col.data(), o.col.size() * 4);
     for (size_t k = 0; k < o.len.size(); ++k) {
       out.refs[row] = o.refs[k];
       out.stats[row] = o.stats[k];

@@ -154,3 +154,47 @@ def test_bench_refuses_several_gpus():
                        text=True, timeout=120, env=dict(os.environ, WORLD_SIZE="1"))
     assert r.returncode == 2
     assert "one GPU" in r.stderr and not r.stdout.strip()
+
+
+def test_host_decode_and_layout_under_sanitizers(tmp_path):
+    """The host decoder, layout builder and layout interpreter built with
+    AddressSanitizer and UndefinedBehaviorSanitizer (g++, host code only) and
+    run on generator graphs, crafted edge cases and damaged streams
+    (tests/native/sanitize_host.cpp)."""
+    import shutil
+    import subprocess
+    if shutil.which("g++") is None:
+        pytest.skip("no g++")
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    csrc = os.path.join(root, "paper_1708_07271_amd", "csrc")
+    exe = str(tmp_path / "sanitize_host")
+    cmd = ["g++", "-std=c++17", "-O1", "-g", "-fno-omit-frame-pointer", "-fsanitize=address,undefined",
+           "-fno-sanitize-recover=all", "-I", csrc, "-I", os.path.join(root, "include"),
+           os.path.join(root, "tests", "native", "sanitize_host.cpp"), os.path.join(csrc, "bv_decode.cpp"),
+           os.path.join(csrc, "bv_layout.cpp"), os.path.join(csrc, "bv_layout_check.cpp"), "-lpthread", "-o", exe]
+    r = subprocess.run(cmd, capture_output=True, text=True, timeout=600)
+    assert r.returncode == 0, r.stderr[-3000:]
+    rng = np.random.default_rng(3)
+    graphs = [B.web_graph(3000, 15.0, 91), B.social_graph(2000, 20.0, 1500, 2.1, 92), B.empty_graph(1),
+              B.empty_graph(300), B.complete_graph(40), B.from_lists([[0], [0, 1], [1, 2]])]
+    n = 6000
+    lists = [[] for _ in range(n)]
+    lists[1] = list(range(0, 300))
+    lists[2] = list(range(0, 300))
+    lists[5] = sorted(rng.choice(n, 5000, replace=False).tolist())
+    lists[6] = sorted(set(lists[5][:4500]) | {n - 1})
+    lists[n - 1] = list(range(n - 20, n))
+    for i in range(100, 140):
+        lists[i] = sorted(({0, i, i - 50, n - 1} | set(range(i + 5, i + 30))) - {i - 1})
+    graphs.append(B.from_lists(lists))
+    files = []
+    for k, g in enumerate(graphs):
+        for W, R, stride in ((7, 3, 64), (1, 1, 65536), (15, 0, 7)):
+            f = tmp_path / ("g%d_w%d_r%d.bv" % (k, W, R))
+            f.write_bytes(bytes(B.encode(g, W=W, R=R, stride=stride).data))
+            files.append(str(f))
+    env = dict(os.environ, ASAN_OPTIONS="detect_leaks=1:abort_on_error=0:verify_asan_link_order=0",
+               UBSAN_OPTIONS="halt_on_error=1:print_stacktrace=1")
+    r = subprocess.run([exe] + files, capture_output=True, text=True, timeout=600, env=env)
+    assert r.returncode == 0, (r.stdout[-2000:], r.stderr[-4000:])
+    assert r.stdout.startswith("ok %d" % len(files))
