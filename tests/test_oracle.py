@@ -120,6 +120,8 @@ def test_product_dense_bruteforce():
         yd = product.matvec_dense(*_csr(g), x)
         assert np.allclose(y, yd, rtol=1e-14, atol=0)
         assert np.allclose(product.matvec(*_csr(g), x), y, rtol=1e-14, atol=0)
+        rows = np.array([0, 1, 17, 400, g.n - 2, g.n - 1])
+        assert np.allclose(product.matvec_rows(*_csr(g), x, rows), yd[rows], rtol=1e-14, atol=0)
 
 
 def test_product_closed_forms():
@@ -443,3 +445,51 @@ def test_restarted_matches_dense_fixed_point():
                                                    Fs, tol=1e-9, K=5)
     assert ok and abs(p.sum() - 1.0) < 1e-12
     assert np.abs(p - exact).sum() <= r * 0.85 / 0.15 + 1e-13
+
+
+def test_restart_kept_only_under_the_contraction_bound():
+    """The probe keeps a restart only when its step is below beta times the
+    step it replaces: beta bounds the plain method's L1 contraction, so a kept
+    restart never converges slower than not restarting.  The probe's ratio
+    rho = ||q - p'||_1 / ||p_K - p_{K-1}||_1 is computed here through the
+    plain power method (started from p_K and from the restart vector p') and
+    the pinned restart-vector function; restarts with rho below beta, between
+    beta and 1, and between 1 and 2 must be kept, dropped and dropped."""
+    from oracle import restart
+    rowptr, col, Fs = _small_web()
+    beta, K = 0.85, 10
+    ps = pagerank.pagerank(rowptr, col, beta, tol=1e-15, max_iter=5000)[0]
+    pK = pagerank.pagerank(rowptr, col, beta, iters=K)[0]
+    pK1 = pagerank.pagerank(rowptr, col, beta, iters=K - 1)[0]
+    delta = np.abs(pK - pK1).sum()
+    t_true = feat.target(ps, pK, delta)
+
+    def rho(c):
+        q0 = feat.restart_vector(pK, c * t_true, delta)
+        r = pagerank.pagerank(rowptr, col, beta, start=q0, iters=1)[2]
+        return r / delta
+
+    cs = np.linspace(-4.0, 6.0, 201)
+    rs = np.array([rho(c) for c in cs])
+    windows = {"keep": (0.0, 0.97 * beta), "drop_beta": (1.03 * beta, 0.97), "drop_one": (1.03, 1.97)}
+    for name, (lo, hi) in windows.items():
+        inside = np.flatnonzero((rs > lo) & (rs < hi))
+        assert inside.size, name
+        c = float(cs[inside[0]])
+        p, t, r, ok, info = restart.pagerank_restarted(rowptr, col, lambda F: c * t_true, Fs, beta=beta, tol=1e-8,
+                                                       K=K, max_restarts=1)
+        want = (1, 0) if name == "keep" else (0, 1)
+        assert (info["accepted"], info["rejected"]) == want, (name, c, rs[inside[0]])
+
+
+def test_structural_depth_input_is_normalised():
+    """Input 2 is the row's reference-chain depth over R: on a copying-model
+    graph whose chains reach the bound R it takes the values 0, 1/R, ..., 1,
+    reaches 1, and is 0 exactly on rows coded without a reference."""
+    g = B.web_graph(3000, 10.0, 17)
+    for R in (1, 3, 5):
+        rowptr, col, refs, hdr, st = bvdecode.decode(B.encode(g, R=R).data, with_stats=True)
+        F = feat.structural(rowptr, col, st, hdr["R"])
+        k = F[:, 2] * R
+        assert np.allclose(k, np.round(k), atol=1e-12) and k.min() == 0.0 and k.max() == R
+        assert np.array_equal(F[:, 2] == 0.0, refs == 0)
