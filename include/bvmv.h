@@ -62,9 +62,14 @@ typedef enum {
 typedef struct {
   int device;            /* HIP device ordinal */
   int tile_rows;         /* rows per tile (one wavefront each, up to 2 rows a lane): 8..128 (0 = 64) */
-  int window_cap;        /* max x-window columns staged per tile: 64..8191 (0 = 256) */
-  int stage_bytes;       /* max entry-stream bytes staged in LDS per tile: 512..16384 (0 = 4096) */
-  int long_row_bytes;    /* rows staging more than this are summed by the whole wave (0 = stage_bytes/2) */
+  int window_cap;        /* max x-window columns staged in LDS per tile: 64..8191 (0 = 256).  A block
+                            holds four tiles' windows at 16 bytes a column plus about 2 KiB a tile,
+                            so a layout whose widest window does not fit the device's LDS per block
+                            is refused at load with BVMV_EINVAL (160 KiB: about 2400 columns) */
+  int stage_bytes;       /* max entry-stream bytes of one tile; a new tile starts before a tile's
+                            streams would exceed it: 512..16384 (0 = 4096) */
+  int long_row_bytes;    /* rows whose entries would take more stream bytes than this are summed by
+                            the whole wave from their own array (0 = stage_bytes/2) */
   int interval_mode;     /* 0 = interval sums from a per-tile prefix of x, P[s+len] - P[s] (default);
                             1 = intervals summed entry by entry from the staged x window */
   int autotune;          /* 1 = build and time candidate layouts at load (tile_rows, window_cap and
@@ -197,7 +202,12 @@ int bvmv_decode(const void* bitstream, size_t nbytes, int nthreads, uint64_t* ro
 
 /* Plain CSR baseline built the same way (row tiles, LDS-staged column ids,
  * whole-block long rows).  From a graph loaded with keep_lists = 1, or from
- * host CSR arrays. */
+ * host CSR arrays (copied; the caller keeps them): rowptr holds n + 1
+ * offsets, rowptr[0] = 0 and nondecreasing; col holds rowptr[n] column ids
+ * below n, in any order within a row (a repeated id counts twice); col may
+ * be NULL when rowptr[n] = 0.  BVMV_EINVAL, before any device work, for
+ * n < 1 or n >= 2^32 - 1, a null pointer, offsets that start elsewhere or
+ * decrease, or a column id out of range. */
 int bvmv_csr_create(const bvmv_graph* g, bvmv_csr** out);
 int bvmv_csr_create_host(int64_t n, const uint64_t* rowptr, const uint32_t* col, int device, bvmv_csr** out);
 int bvmv_csr_multiply(bvmv_csr* c, const void* x, void* y, int prec, void* stream);

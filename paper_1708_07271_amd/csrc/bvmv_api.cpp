@@ -1054,6 +1054,12 @@ int bvmv_export_csr(const bvmv_graph* g, uint64_t* rowptr, uint32_t* col) {
 int bvmv_csr_create_host(int64_t n, const uint64_t* rowptr, const uint32_t* col, int device, bvmv_csr** out) {
   if (n < 1 || !rowptr || !out) return fail(BVMV_EINVAL, "bad CSR arguments");
   *out = nullptr;
+  if (uint64_t(n) >= 0xFFFFFFFFull) return fail(BVMV_EINVAL, "n too large for 32-bit row ids");
+  // a decreasing offset would make a row length wrap around and send the
+  // tiles' column reads past the array
+  if (rowptr[0] != 0) return fail(BVMV_EINVAL, "rowptr[0] must be 0");
+  for (int64_t i = 0; i < n; ++i)
+    if (rowptr[i + 1] < rowptr[i]) return fail(BVMV_EINVAL, "rowptr must be nondecreasing");
   const uint64_t m = rowptr[n];
   if (m >= (uint64_t(1) << 32) - 1) return fail(BVMV_EINVAL, "CSR too large for 32-bit row pointers");
   static const uint32_t kNoColumns = 0;

@@ -176,6 +176,40 @@ def test_entries_at_the_end_of_the_stream_array(P, lay):
         assert np.array_equal(_mul(P, G, xi.astype(np.float32), prec), refi)
 
 
+def test_largest_layouts(P, graphs):
+    """The widest x windows the device's LDS admits.  On the social graph
+    (uniform random targets) every tile's best window fills the cap, so a cap
+    of 8191 columns must be refused at load with an LDS error, before any
+    launch; the widest accepted cap, for 64- and 128-row tiles, stages its
+    window through the general (more than 16 values per lane) path and must
+    still be exact on integer x and within tolerance on uniform x."""
+    g, enc = graphs["social-n3e4-d30"]
+    with pytest.raises(P.BvmvError) as e:
+        P.bvmv_load(enc.data, window_cap=8191, stage_bytes=16384)
+    assert e.value.code == P.BVMV_EINVAL and "LDS" in str(e.value)
+    xi = B.integer_x(g.n, 3, 1000)
+    want_i = product.matvec(g.rowptr, g.col, xi)
+    x = B.uniform_x(g.n, 4)
+    want = product.matvec_exact(g.rowptr, g.col, x)
+    x32 = x.astype(np.float32)
+    want32 = product.matvec_exact(g.rowptr, g.col, x32.astype(np.float64))
+    for rows in (64, 128):
+        G, cap = None, 0
+        for cap in (4096, 3072, 2560, 2496, 2432, 2368, 2304, 2048):
+            try:
+                G = P.bvmv_load(enc.data, tile_rows=rows, window_cap=cap, stage_bytes=16384)
+                break
+            except P.BvmvError as err:
+                assert err.code == P.BVMV_EINVAL and "LDS" in str(err)
+        assert G is not None and cap >= 2048, rows
+        print("largest window cap for %d-row tiles: %d" % (rows, cap), flush=True)
+        for prec in (P.BVMV_F64, P.BVMV_F32, P.BVMV_F32_COMP):
+            xp = xi if prec == P.BVMV_F64 else xi.astype(np.float32)
+            assert np.array_equal(_mul(P, G, xp, prec), want_i), (rows, prec)
+        assert _rel(_mul(P, G, x, P.BVMV_F64), want) < 1e-12
+        assert _rel(_mul(P, G, x32, P.BVMV_F32_COMP), want32) < 1e-5
+
+
 def test_csr_baseline(P, graphs):
     for name, (g, enc) in graphs.items():
         G = P.bvmv_load(enc.data, keep_lists=1)

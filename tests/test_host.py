@@ -198,3 +198,56 @@ def test_host_decode_and_layout_under_sanitizers(tmp_path):
     r = subprocess.run([exe] + files, capture_output=True, text=True, timeout=600, env=env)
     assert r.returncode == 0, (r.stdout[-2000:], r.stderr[-4000:])
     assert r.stdout.startswith("ok %d" % len(files))
+
+
+def test_api_rejects_bad_arguments_before_device_work(P):
+    """Every argument check that precedes device work answers BVMV_EINVAL with
+    a message, also on a machine without a GPU: null handles and buffers,
+    load options out of range, malformed host CSR arrays (offsets that do not
+    start at 0 or decrease, which would make a row length wrap; column ids out
+    of range), empty groups, a null network."""
+    import ctypes
+    lib = P.load_library()
+    h = ctypes.c_void_p()
+    data = np.frombuffer(bytes(B.encode(B.web_graph(200, 5.0, 1)).data), dtype=np.uint8)
+
+    def einval(rc, text):
+        assert rc == P.BVMV_EINVAL, (rc, text)
+        msg = lib.bvmv_last_error().decode()
+        assert text in msg, (text, msg)
+
+    einval(lib.bvmv_load(None, 0, None, ctypes.byref(h)), "null argument")
+    for field, bad in (("tile_rows", 7), ("tile_rows", 129), ("window_cap", 63), ("window_cap", 8192),
+                       ("stage_bytes", 511), ("stage_bytes", 16385), ("long_row_bytes", 15),
+                       ("long_row_bytes", 5000), ("interval_mode", 2), ("interval_mode", -1), ("device", -1)):
+        with pytest.raises(P.BvmvError) as e:
+            P.bvmv_load(data, **{field: bad})
+        assert e.value.code == P.BVMV_EINVAL and "load option out of range" in str(e.value), field
+    einval(lib.bvmv_multiply(None, None, None, 0, None), "null argument")
+    einval(lib.bvmv_multiply_batch(None, None, None, 1, 1, 0, None), "null argument")
+    einval(lib.bvmv_pagerank(None, None, None, None, None, 1, None, None), "null argument")
+    einval(lib.bvmv_degrees(None, None, None), "null argument")
+    einval(lib.bvmv_group(None, 0, ctypes.byref(h)), "bad group arguments")
+    einval(lib.bvmv_csr_create(None, ctypes.byref(h)), "null argument")
+    einval(lib.bvmv_csr_multiply(None, None, None, 0, None), "null argument")
+    einval(lib.bvmv_csr_pagerank(None, None, None, None, None, None, None), "null argument")
+    einval(lib.bvmv_features(None, None, None), "null argument")
+    einval(lib.bvmv_restart_sample(None, 10, 0, None, None, None, None, None), "null argument")
+    einval(lib.bvmv_mlp_create(0, None, ctypes.byref(h)), "null argument")
+    einval(lib.bvmv_mlp_forward(None, None, 1, None, None), "bad network arguments")
+    einval(lib.bvmv_mlp_gradient(None, None, None, 1, None, None), "bad network arguments")
+
+    def csr(rowptr, col, text):
+        rp = np.ascontiguousarray(rowptr, dtype=np.uint64)
+        c = np.ascontiguousarray(col if len(col) else [0], dtype=np.uint32)
+        einval(lib.bvmv_csr_create_host(rp.size - 1, rp.ctypes.data, c.ctypes.data, 0, ctypes.byref(h)), text)
+        assert h.value is None
+
+    csr([0], [], "bad CSR arguments")                        # n = 0
+    csr([1, 2, 3], [0, 1, 0], "rowptr[0] must be 0")
+    csr([0, 5, 3], [0, 1, 0, 1, 0], "rowptr must be nondecreasing")
+    csr([0, 2, 1, 4], [0, 1, 2, 0], "rowptr must be nondecreasing")
+    csr([0, 1, 2], [0, 7], "column out of range")
+    einval(lib.bvmv_csr_create_host(2, None, None, 0, ctypes.byref(h)), "bad CSR arguments")
+    rp = np.array([0, 1, 1], dtype=np.uint64)
+    einval(lib.bvmv_csr_create_host(2, rp.ctypes.data, None, 0, ctypes.byref(h)), "bad CSR arguments")
