@@ -128,10 +128,6 @@ struct MINT {
 
 __host__ __device__ constexpr size_t align16(size_t v) { return (v + 15) & ~size_t(15); }
 __device__ __forceinline__ uint32_t dalign16u(uint32_t b) { return (b + 15u) & ~15u; }
-// staged stream bytes of a tile (same sum as tile_stage_bytes on the host)
-__device__ __forceinline__ uint32_t dstage_bytes(const TileDesc& t) {
-  return dalign16u(t.n16 * 2u) + dalign16u(t.nwide * 4u);
-}
 
 // ------------------------------------------------------------- wave helpers
 // LDS written by some lanes of a wave and read by others: keep the order.
