@@ -7,8 +7,8 @@ The power method of Eq. (1) (oracle.pagerank, same readings) from the
 uniform vector, interrupted every K iterations (counted from the last
 restart) by a warm restart predicted per node by a network: the inputs of
 oracle.features from the last four iterates, the network's estimate s of the
-remaining correction, and the restart vector p'.  The plain method is the
-judge: one iteration from p' gives q = G p' and the residual r' =
+remaining correction, and the restart vector p'.  The plain method
+decides: one iteration from p' gives q = G p' and the residual r' =
 ||q - p'||_1, and p' is kept only if r' < beta * delta, delta = ||p_K -
 p_{K-1}||_1.  Since G is a beta-contraction in the L1 norm, the plain
 method's next residual ||G p_K - p_K||_1 is at most beta * delta, so a kept
