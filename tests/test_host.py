@@ -251,3 +251,59 @@ def test_api_rejects_bad_arguments_before_device_work(P):
     einval(lib.bvmv_csr_create_host(2, None, None, 0, ctypes.byref(h)), "bad CSR arguments")
     rp = np.array([0, 1, 1], dtype=np.uint64)
     einval(lib.bvmv_csr_create_host(2, rp.ctypes.data, None, 0, ctypes.byref(h)), "bad CSR arguments")
+
+
+def test_layout_property_random_graphs(P):
+    """Property test: for random small graphs (row lengths from empty to dense,
+    clustered or scattered ids, runs that become intervals, rows copied from
+    earlier rows), random encoder settings and random tile / window / stage
+    shapes, the host interpreter of the device layout gives the oracle's
+    product exactly on integer x, and the host decoder gives the lists back."""
+    hyp = pytest.importorskip("hypothesis")
+    st = hyp.strategies
+
+    @st.composite
+    def graph_case(draw):
+        n = draw(st.integers(1, 400))
+        seed = draw(st.integers(0, 2**31 - 1))
+        rng = np.random.default_rng(seed)
+        lists = []
+        for i in range(n):
+            kind = draw(st.sampled_from(["empty", "near", "far", "run", "copy", "dense"]))
+            if kind == "empty":
+                row = []
+            elif kind == "near":
+                row = (i + rng.integers(-20, 21, rng.integers(1, 12))) % n
+            elif kind == "far":
+                row = rng.integers(0, n, rng.integers(1, 30))
+            elif kind == "run":
+                s = int(rng.integers(0, n))
+                row = list(range(s, min(n, s + int(rng.integers(1, 60)))))
+            elif kind == "copy" and lists:
+                src = lists[max(0, i - int(rng.integers(1, 9)))]
+                keep = [c for c in src if rng.random() < 0.8]
+                row = keep + list(rng.integers(0, n, rng.integers(0, 4)))
+            else:
+                row = rng.choice(n, min(n, int(rng.integers(1, 400))), replace=False)
+            lists.append(sorted(set(int(c) for c in row)))
+        enc = dict(W=draw(st.integers(0, 15)), R=draw(st.integers(0, 15)), Lmin=draw(st.integers(2, 8)),
+                   zeta_k=draw(st.integers(1, 5)), stride=draw(st.sampled_from([7, 64, 65536])))
+        stage = draw(st.sampled_from([512, 1024, 4096, 16384]))
+        lay = (draw(st.sampled_from([8, 16, 32, 64, 96, 128])), draw(st.integers(64, 1024)), stage,
+               draw(st.integers(16, stage)))
+        return lists, enc, lay
+
+    @hyp.settings(max_examples=150, deadline=None, database=None, derandomize=True)
+    @hyp.given(graph_case())
+    def check(case):
+        lists, enc_opts, lay = case
+        g = B.from_lists(lists)
+        enc = B.encode(g, **enc_opts)
+        rowptr, col, _ = P.bvmv_decode(enc.data)
+        assert np.array_equal(rowptr, g.rowptr) and np.array_equal(col, g.col)
+        x = B.integer_x(g.n, 3, 1000)
+        y, info = P.bvmv_layout_selfcheck(enc.data, x, *lay)
+        assert np.array_equal(y, product.matvec(g.rowptr, g.col, x)), (enc_opts, lay)
+        assert info["max_level"] <= max(enc_opts["R"], 0)
+
+    check()
