@@ -3,14 +3,17 @@ scattered, run-like, copied and dense rows), random encoder settings and
 random tile / window / stage shapes within the load options' ranges.  On
 integer x every mode must give the oracle's sums exactly; on uniform x the
 FP64 path is within 1e-12 and the two-sum FP32 path within 1e-5 relative;
-a small multi-vector product must equal its single products.  The examples
+a small multi-vector product must equal its single products; the degrees
+are exact; PageRank with a random teleport vector matches the oracle run
+for the same number of iterations within 1e-12; and a two-member group
+gives each member's solo product bit for bit.  The examples
 are derandomized, so a run is repeatable, and each case is printed before it
 runs."""
 import numpy as np
 import pytest
 
 import bvinputs as B
-from oracle import product
+from oracle import pagerank, product
 
 pytestmark = pytest.mark.gpu
 
@@ -109,7 +112,27 @@ def test_random_graphs_and_layouts(P):
         Yh, Xh = Y.cpu().numpy(), X.cpu().numpy()
         for c in range(k):
             assert np.array_equal(Yh[c], product.matvec(g.rowptr, g.col, Xh[c])), c
-        del G
+        deg = torch.empty(n, dtype=torch.int32, device=DEV)
+        P.bvmv_degrees(G, deg)
+        torch.cuda.synchronize()
+        assert np.array_equal(deg.cpu().numpy(), np.diff(g.rowptr.astype(np.int64)))
+        # PageRank: rows are read as in-link lists, as loaded
+        tele = np.random.default_rng(seed + 1).dirichlet(np.ones(n))
+        pd = torch.empty(n, dtype=torch.float64, device=DEV)
+        ((it, ok, r),) = P.bvmv_pagerank(G, pd, teleport=torch.from_numpy(tele).to(DEV), prec=P.BVMV_F64)
+        torch.cuda.synchronize()
+        assert ok and r < 1e-6
+        p_ref = pagerank.pagerank(g.rowptr, g.col, 0.85, teleport=tele, iters=it)[0]
+        assert np.max(np.abs(pd.cpu().numpy() - p_ref) / p_ref) < 1e-12
+        # a group of this graph and another one, same layout options
+        g2 = B.from_lists(_lists(max(1, n // 2), seed + 2, mix))
+        G2 = P.bvmv_load(B.encode(g2, **enc_opts).data, **lay)
+        grp = P.bvmv_group([G, G2])
+        xg = np.concatenate([x32, B.uniform_x(g2.n, 7).astype(np.float32)])
+        yg = _run(P, grp, xg, P.BVMV_F32_COMP)
+        assert np.array_equal(yg[:n], _run(P, G, xg[:n].copy(), P.BVMV_F32_COMP))
+        assert np.array_equal(yg[n:], _run(P, G2, xg[n:].copy(), P.BVMV_F32_COMP))
+        del grp, G2, G
 
     check()
     assert count[0] == 40
