@@ -6,14 +6,16 @@ FP64 path is within 1e-12 and the two-sum FP32 path within 1e-5 relative;
 a small multi-vector product must equal its single products; the degrees
 are exact; PageRank with a random teleport vector matches the oracle run
 for the same number of iterations within 1e-12; and a two-member group
-gives each member's solo product bit for bit.  The examples
+gives each member's solo product bit for bit; a two-column personalized
+PageRank gives each column's single run bit for bit; and learned restarts
+with a zero network follow the plain run (kept or rejected, a restart is p_K).  The examples
 are derandomized, so a run is repeatable, and each case is printed before it
 runs."""
 import numpy as np
 import pytest
 
 import bvinputs as B
-from oracle import pagerank, product
+from oracle import mlp, pagerank, product
 
 pytestmark = pytest.mark.gpu
 
@@ -132,7 +134,30 @@ def test_random_graphs_and_layouts(P):
         yg = _run(P, grp, xg, P.BVMV_F32_COMP)
         assert np.array_equal(yg[:n], _run(P, G, xg[:n].copy(), P.BVMV_F32_COMP))
         assert np.array_equal(yg[n:], _run(P, G2, xg[n:].copy(), P.BVMV_F32_COMP))
-        del grp, G2, G
+        # two personalized columns at once: each is its single run, bit for bit
+        V = np.stack([np.random.default_rng(seed + 3 + c).dirichlet(np.ones(n)) for c in range(2)]).astype(np.float32)
+        pk = torch.empty(2 * n, dtype=torch.float32, device=DEV)
+        resk = P.bvmv_pagerank(G, pk, teleport=torch.from_numpy(V.reshape(-1)).to(DEV), prec=P.BVMV_F32_COMP, k=2)
+        torch.cuda.synchronize()
+        pk = pk.cpu().numpy().reshape(2, n)
+        for c in range(2):
+            p1 = torch.empty(n, dtype=torch.float32, device=DEV)
+            ((it1, ok1, _),) = P.bvmv_pagerank(G, p1, teleport=torch.from_numpy(V[c].copy()).to(DEV),
+                                               prec=P.BVMV_F32_COMP)
+            torch.cuda.synchronize()
+            assert ok1 and resk[c][1] and resk[c][0] == it1
+            assert np.array_equal(pk[c], p1.cpu().numpy()), c
+        # learned restarts with a zero network: every restart is p_K itself
+        pp = torch.empty(n, dtype=torch.float64, device=DEV)
+        rp = P.bvmv_pagerank_detail(G, pp, prec=P.BVMV_F64)[0]
+        zero = P.bvmv_mlp_create(np.zeros(mlp.NPARAM))
+        pl = torch.empty(n, dtype=torch.float64, device=DEV)
+        rl = P.bvmv_pagerank_detail(G, pl, prec=P.BVMV_F64, mlp=zero)[0]
+        # (a probe exactly at the contraction bound, as on a cycle, may be rejected)
+        assert rl["converged"] and rl["products"] == rl["iters"] + rl["restarts_rejected"]
+        assert abs(rl["iters"] - rp["iters"]) <= 1
+        assert float(((pl - pp).abs() / pp).max()) < 1e-11
+        del grp, G2, G, zero
 
     check()
     assert count[0] == 40
