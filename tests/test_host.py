@@ -307,3 +307,30 @@ def test_layout_property_random_graphs(P):
         assert info["max_level"] <= max(enc_opts["R"], 0)
 
     check()
+
+
+def test_missing_library_fails_loudly():
+    """With the native library absent, every entry point raises instead of
+    computing anything, and the package never loads the oracle (there is no
+    CPU fallback).  Run in a child process so that this process keeps its
+    loaded library."""
+    import subprocess
+    import sys
+    code = "\n".join([
+        "import sys, numpy as np",
+        "import paper_1708_07271_amd as P",
+        "P.LIB_PATH = '/nonexistent/libbvmv.so'",
+        "calls = [lambda: P.load_library(), lambda: P.bvmv_load(np.zeros(64, np.uint8)),",
+        "         lambda: P.bvmv_decode(np.zeros(64, np.uint8)), lambda: P.bvmv_csr_create_host([0, 0], [])]",
+        "for f in calls:",
+        "    try:",
+        "        f()",
+        "    except ImportError as e:",
+        "        assert 'not built' in str(e), e",
+        "    else:",
+        "        raise SystemExit('an entry point ran without the library')",
+        "assert not any(m == 'oracle' or m.startswith('oracle.') for m in sys.modules), 'oracle imported'",
+        "print('ok')",
+    ])
+    r = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, timeout=300, cwd=ROOT)
+    assert r.returncode == 0 and r.stdout.strip().endswith("ok"), (r.stdout[-2000:], r.stderr[-2000:])
