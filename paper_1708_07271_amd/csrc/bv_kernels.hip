@@ -151,18 +151,6 @@ __device__ __forceinline__ uint64_t wave_excl_scan_u64(uint64_t v, uint64_t& tot
   return inc - v;
 }
 
-__device__ __forceinline__ double wave_excl_scan_f64(double v, double& total) {
-  const uint32_t lane = lane_id();
-  double inc = v;
-#pragma unroll
-  for (int d = 1; d < 64; d <<= 1) {
-    const double t = __shfl_up(inc, d, 64);
-    if (lane >= uint32_t(d)) inc += t;
-  }
-  total = __shfl(inc, 63, 64);
-  return inc - v;
-}
-
 // fixed shuffle tree, result broadcast to all lanes
 template <class M>
 __device__ __forceinline__ typename M::PAcc wave_reduce(typename M::PAcc a) {
@@ -232,29 +220,6 @@ __device__ __forceinline__ T* stage_range(const T* __restrict__ arr, uint64_t le
     }
   }
   return buf + shift;
-}
-
-// ------------------------------------------------------------- block helpers
-__device__ __forceinline__ uint64_t block_excl_scan_u64(uint64_t v, uint64_t* s_tmp, uint64_t& total) {
-  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-  uint64_t inc = v;
-#pragma unroll
-  for (int d = 1; d < 64; d <<= 1) {
-    const uint64_t t = __shfl_up(inc, d, 64);
-    if (lane >= d) inc += t;
-  }
-  if (lane == 63) s_tmp[wid] = inc;
-  __syncthreads();
-  uint64_t base = 0, tot = 0;
-#pragma unroll
-  for (int w = 0; w < kWaves; ++w) {
-    const uint64_t s = s_tmp[w];
-    if (w < wid) base += s;
-    tot += s;
-  }
-  __syncthreads();
-  total = tot;
-  return base + inc - v;
 }
 
 // q = floor(a / C) for an entry offset a of a flat pass (a < 64 C) and its
