@@ -3,7 +3,8 @@ scattered, run-like, copied and dense rows), random encoder settings and
 random tile / window / stage shapes within the load options' ranges.  On
 integer x every mode must give the oracle's sums exactly; on uniform x the
 FP64 path is within 1e-12 and the two-sum FP32 path within 1e-5 relative;
-a small multi-vector product must equal its single products; the degrees
+a small multi-vector product must equal its single products; the CSR
+baseline built from the host arrays gives the same exact sums; the degrees
 are exact; PageRank with a random teleport vector matches the oracle run
 for the same number of iterations within 1e-12; and a two-member group
 gives each member's solo product bit for bit; a two-column personalized
@@ -114,6 +115,21 @@ def test_random_graphs_and_layouts(P):
         Yh, Xh = Y.cpu().numpy(), X.cpu().numpy()
         for c in range(k):
             assert np.array_equal(Yh[c], product.matvec(g.rowptr, g.col, Xh[c])), c
+        # the CSR baseline built from the host arrays
+        C = P.bvmv_csr_create_host(g.rowptr, g.col)
+        for prec in (P.BVMV_F64, P.BVMV_F32, P.BVMV_F32_COMP):
+            xp = xi if prec == P.BVMV_F64 else xi.astype(np.float32)
+            xd = torch.from_numpy(np.ascontiguousarray(xp)).to(DEV)
+            yd = torch.empty_like(xd)
+            P.bvmv_csr_multiply(C, xd, yd, prec)
+            torch.cuda.synchronize()
+            assert np.array_equal(yd.cpu().numpy(), want), ("csr", prec)
+        xd = torch.from_numpy(x).to(DEV)
+        yd = torch.empty_like(xd)
+        P.bvmv_csr_multiply(C, xd, yd, P.BVMV_F64)
+        torch.cuda.synchronize()
+        assert _rel(yd.cpu().numpy(), product.matvec_exact(g.rowptr, g.col, x)) < 1e-12
+        del C
         deg = torch.empty(n, dtype=torch.int32, device=DEV)
         P.bvmv_degrees(G, deg)
         torch.cuda.synchronize()
