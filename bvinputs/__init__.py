@@ -247,6 +247,28 @@ def workload_graph(name: str, n: int | None = None) -> Graph:
     return social_graph(w["n"], w["mean"], w["max_deg"], w["exponent"], w["seed"])
 
 
+# ------------------------------------------------------- network parameters
+MLP_SHAPES = [("W1", (64, 12)), ("b1", (64,)), ("W2", (64, 64)), ("b2", (64,)), ("w3", (64,)), ("b3", (1,))]
+
+
+def mlp_init_params(seed: int) -> np.ndarray:
+    """Seeded starting parameters of the 12 -> 64 -> 64 -> 1 warm-restart
+    network, in the library's parameter order (W1 row-major (out, in), b1,
+    W2, b2, w3, b3): weights uniform on [-a, a] with a = sqrt(6 / (fan_in +
+    fan_out)) (Glorot) drawn from numpy's default_rng(seed) in that order,
+    biases zero, rounded to float32.  Returned as float32 (5057 values)."""
+    rng = np.random.default_rng(seed)
+    parts = []
+    for name, shape in MLP_SHAPES:
+        if name[0] == "b":
+            parts.append(np.zeros(int(np.prod(shape))))
+        else:
+            fo, fi = shape if len(shape) == 2 else (1, shape[0])
+            a = (6.0 / (fi + fo)) ** 0.5
+            parts.append(rng.uniform(-a, a, size=shape).reshape(-1))
+    return np.concatenate(parts).astype(np.float32)
+
+
 def ragged_sizes(count: int = 48, seed: int = 999, lo_exp: float = 4.0, hi_exp: float = 6.0):
     """Graph sizes log-uniform in [10^lo_exp, 10^hi_exp]."""
     u = np.random.default_rng(seed).random(count)

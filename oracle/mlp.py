@@ -93,7 +93,10 @@ def weights_bf16(theta):
 
 
 def init_params(seed):
-    """Uniform Glorot initialisation of the weights from numpy's default_rng(seed), zero biases."""
+    """Uniform Glorot initialisation of the weights from numpy's default_rng(seed), zero biases.
+    The tests' own copy of the recipe: the benchmark draws its starting
+    parameters from the seeded inputs module, and a pin checks that both
+    give the same values."""
     rng = np.random.default_rng(seed)
     p = {}
     for name, shape in SIZES:

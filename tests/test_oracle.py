@@ -316,6 +316,100 @@ def test_mlp_quantized_close_to_exact():
     assert np.linalg.norm(gq - ge) < 0.05 * np.linalg.norm(ge)
 
 
+def _bf16_spacing(a):
+    """Distance between consecutive BF16 values around |a| (8 significant bits)."""
+    return 2.0 ** (np.floor(np.log2(np.abs(a))) - 7)
+
+
+def test_mlp_inputs_enter_as_bf16():
+    # the first product takes bf(x): inputs that round to the same BF16 value
+    # give bit-identical outputs and gradients, while the unrounded network
+    # tells them apart
+    rng = np.random.default_rng(8)
+    theta = mlp.init_params(5) + rng.normal(0, 0.05, mlp.NPARAM)
+    X = mlp.bf16(rng.normal(0, 1.5, (64, mlp.NIN)))
+    assert np.all(X != 0)
+    Xp = X + 0.25 * _bf16_spacing(X) * rng.choice([-1.0, 1.0], X.shape)   # a quarter step: same BF16 value
+    t = rng.normal(0, 1, 64)
+    s0, _ = mlp.forward(theta, X)
+    s1, _ = mlp.forward(theta, Xp)
+    assert np.array_equal(s0, s1)
+    assert np.array_equal(mlp.grad(theta, X, t)[1], mlp.grad(theta, Xp, t)[1])
+    assert not np.array_equal(mlp.forward(theta, X, False)[0], mlp.forward(theta, Xp, False)[0])
+
+
+def test_mlp_weights_enter_as_bf16():
+    # the network uses BF16 copies of W1, W2 and w3: master weights moved
+    # within their BF16 cell give the same outputs; biases are used as given
+    rng = np.random.default_rng(9)
+    theta = mlp.init_params(7) + rng.normal(0, 0.05, mlp.NPARAM)
+    p = mlp.unpack(theta)
+    for k in mlp.WEIGHTS:
+        p[k] = mlp.bf16(p[k])
+        p[k][p[k] == 0] = 2.0 ** -20
+    q = {k: v.copy() for k, v in p.items()}
+    for k in mlp.WEIGHTS:
+        q[k] = p[k] + 0.25 * _bf16_spacing(p[k]) * rng.choice([-1.0, 1.0], p[k].shape)
+    X = rng.normal(0, 1.5, (32, mlp.NIN))
+    assert np.array_equal(mlp.forward(mlp.pack(p), X)[0], mlp.forward(mlp.pack(q), X)[0])
+    q["b2"] = p["b2"] + 0.25 * _bf16_spacing(p["b2"] + 1e-3)
+    assert not np.array_equal(mlp.forward(mlp.pack(p), X)[0], mlp.forward(mlp.pack(q), X)[0])
+
+
+def _saturated_theta(seed):
+    """A network whose first layer sits at z1 = 8 + (small input term): every
+    h1 = gelu(z1) lies in [7.98, 8.02] and rounds to the BF16 value 8.0
+    (spacing 1/32 below 8, 1/16 above)."""
+    rng = np.random.default_rng(seed)
+    p = mlp.unpack(mlp.init_params(seed) + rng.normal(0, 0.05, mlp.NPARAM))
+    p["W1"] = 2.0 ** -10 * np.where(rng.random((mlp.NH, mlp.NIN)) < 0.5, -1.0, 1.0)
+    p["b1"] = np.full(mlp.NH, 8.0)
+    return mlp.pack(p)
+
+
+def test_mlp_hidden_layer_enters_as_bf16():
+    # the second product takes bf(h1): with every h1 rounding to 8.0 the output
+    # is one value for all rows, although z1 and h1 differ from row to row
+    theta = _saturated_theta(10)
+    X = np.random.default_rng(11).uniform(-1, 1, (40, mlp.NIN))
+    s, c = mlp.forward(theta, X)
+    assert np.ptp(c["z1"]) > 1e-3
+    assert np.all(c["h1q"] == 8.0)
+    assert np.all(s == s[0])
+    assert np.ptp(mlp.forward(theta, X, False)[0]) > 1e-6
+
+
+def test_mlp_backward_operands_are_bf16():
+    # one row: the weight gradients are products of BF16-rounded deltas with
+    # the layer inputs, the bias gradients the unrounded deltas.  With h1q = 8
+    # (saturated first layer): dW2[i, j] = 8 bf(db2[i]).  With a one-hot input
+    # x = e_3: dW1[:, 3] = bf(db1) and the other columns are zero.
+    theta = _saturated_theta(12)
+    rng = np.random.default_rng(13)
+    x = rng.uniform(-1, 1, (1, mlp.NIN))
+    _, g = mlp.grad(theta, x, np.array([-3.0]))
+    d = mlp.unpack(g)
+    assert np.any(mlp.bf16(d["b2"]) != d["b2"])
+    assert np.array_equal(d["W2"], 8.0 * np.repeat(mlp.bf16(d["b2"])[:, None], mlp.NH, axis=1))
+    theta = mlp.init_params(14) + rng.normal(0, 0.05, mlp.NPARAM)
+    e3 = np.zeros((1, mlp.NIN))
+    e3[0, 3] = 1.0
+    _, g = mlp.grad(theta, e3, np.array([2.0]))
+    d = mlp.unpack(g)
+    assert np.any(mlp.bf16(d["b1"]) != d["b1"])
+    assert np.array_equal(d["W1"][:, 3], mlp.bf16(d["b1"]))
+    assert np.all(np.delete(d["W1"], 3, axis=1) == 0.0)
+
+
+def test_bvinputs_init_equals_oracle_init():
+    # the benchmark's seeded starting parameters (bvinputs) and the oracle's
+    # own copy of the same recipe agree value for value
+    for seed in (0, 4000):
+        a = B.mlp_init_params(seed).astype(np.float64)
+        b = mlp.init_params(seed)
+        assert a.shape == (mlp.NPARAM,) and np.array_equal(a, b)
+
+
 def test_adam_first_step_closed_form():
     # after one step mhat = g and vhat = g^2, so theta moves by lr g / (|g| + eps)
     g = np.array([0.3, -2.0, 1e-3, 0.0])

@@ -41,6 +41,10 @@ MLP_PINS = [
     (T.test_mlp_gradient_finite_differences, ()),
     (T.test_mlp_quantized_close_to_exact, ()),
     (T.test_adam_first_step_closed_form, ()),
+    (T.test_mlp_inputs_enter_as_bf16, ()),
+    (T.test_mlp_weights_enter_as_bf16, ()),
+    (T.test_mlp_hidden_layer_enters_as_bf16, ()),
+    (T.test_mlp_backward_operands_are_bf16, ()),
 ]
 FEATURE_PINS = [
     (T.test_row_stats_match_lists, ()),
@@ -125,6 +129,13 @@ MUTANTS = [
     ("backprop-weight-transposed", "oracle.mlp", "dh1 = dz2q @ p[\"W2\"]", "dh1 = dz2q @ p[\"W2\"].T",
      MLP_PINS),
     ("bias-grad-from-wrong-layer", "oracle.mlp", "g[\"b1\"] = dz1.sum(axis=0)", "g[\"b1\"] = dh1.sum(axis=0)",
+     MLP_PINS),
+    ("x-not-rounded", "oracle.mlp", "xq = q(X)", "xq = X", MLP_PINS),
+    ("h1-not-rounded", "oracle.mlp", "h1q = q(h1)", "h1q = h1", MLP_PINS),
+    ("dz2-not-rounded", "oracle.mlp", "dz2q = q(dz2)", "dz2q = dz2", MLP_PINS),
+    ("dz1-not-rounded", "oracle.mlp", "dz1q = q(dz1)", "dz1q = dz1", MLP_PINS),
+    ("w3-not-rounded", "oracle.mlp", 'WEIGHTS = ("W1", "W2", "w3")', 'WEIGHTS = ("W1", "W2")', MLP_PINS),
+    ("b2-grad-from-rounded-delta", "oracle.mlp", 'g["b2"] = dz2.sum(axis=0)', 'g["b2"] = dz2q.sum(axis=0)',
      MLP_PINS),
     # the network's inputs, target and restart vector
     ("trajectory-norm", "oracle.features", "delta = float(np.sum(np.abs(pK - pK1)))",
