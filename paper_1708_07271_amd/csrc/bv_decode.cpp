@@ -134,8 +134,14 @@ void decode_range(const StreamHeader& h, const uint8_t* padded, uint64_t lo, uin
       uint64_t p = 0;
       bool keep = true;
       for (uint64_t b = 0; b < nb; ++b) {
-        uint64_t ln = b == 0 ? in.gamma() : in.gamma() + 1;
-        if (!in.ok() || ln > rlen - p) { fail("copy blocks exceed the reference list", i); return; }
+        // a block's length is gamma (first block) or gamma + 1: bounded by
+        // what is left of the reference list before any arithmetic on it
+        const uint64_t code = in.gamma();
+        if (!in.ok() || code > rlen - p || (b > 0 && code == rlen - p)) {
+          fail("copy blocks exceed the reference list", i);
+          return;
+        }
+        const uint64_t ln = b == 0 ? code : code + 1;
         if (keep) copied.insert(copied.end(), rl + p, rl + p + ln);
         p += ln;
         keep = !keep;
@@ -153,11 +159,18 @@ void decode_range(const StreamHeader& h, const uint8_t* padded, uint64_t lo, uin
       const uint64_t nint = ne >= h.Lmin ? in.gamma() : 0;
       int64_t prev_last = 0;
       for (uint64_t k = 0; k < nint; ++k) {
-        int64_t s;
-        if (k == 0) s = int64_t(i) + nu_inv(in.gamma());
-        else s = prev_last + 2 + int64_t(in.gamma());
-        const uint64_t ln = in.gamma() + h.Lmin;
-        if (!in.ok() || s < 0 || uint64_t(s) + ln > h.n || extras.size() + ln > ne) {
+        // every decoded value is checked against n (or the entries left)
+        // before it enters any sum, so no arithmetic below can wrap
+        const uint64_t cs = in.gamma();
+        const uint64_t cl = in.gamma();
+        const uint64_t left = ne - extras.size();
+        if (!in.ok() || cs >= 2 * h.n || left < h.Lmin || cl > left - h.Lmin) {
+          fail("bad interval", i);
+          return;
+        }
+        const int64_t s = k == 0 ? int64_t(i) + nu_inv(cs) : prev_last + 2 + int64_t(cs);
+        const uint64_t ln = cl + h.Lmin;
+        if (s < 0 || uint64_t(s) + ln > h.n) {
           fail("bad interval", i);
           return;
         }
@@ -171,8 +184,10 @@ void decode_range(const StreamHeader& h, const uint8_t* padded, uint64_t lo, uin
       stats[li].nres = uint32_t(nres);
       int64_t prev = 0;
       for (uint64_t k = 0; k < nres; ++k) {
-        int64_t j = k == 0 ? int64_t(i) + nu_inv(in.zeta(h.zeta_k)) : prev + 1 + int64_t(in.zeta(h.zeta_k));
-        if (!in.ok() || j < 0 || uint64_t(j) >= h.n) { fail("bad residual", i); return; }
+        const uint64_t cz = in.zeta(h.zeta_k);
+        if (!in.ok() || cz >= 2 * h.n) { fail("bad residual", i); return; }
+        const int64_t j = k == 0 ? int64_t(i) + nu_inv(cz) : prev + 1 + int64_t(cz);
+        if (j < 0 || uint64_t(j) >= h.n) { fail("bad residual", i); return; }
         extras.push_back(uint32_t(j));
         prev = j;
       }

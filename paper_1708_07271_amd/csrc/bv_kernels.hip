@@ -28,6 +28,7 @@
 #include <type_traits>
 
 #include "kernels.hpp"
+#include "twosum.hpp"
 
 namespace bvmv {
 namespace {
@@ -37,20 +38,7 @@ constexpr int kWaves = kThreads / 64;
 static_assert(kWaves == kTilesPerBlock, "one tile per wavefront");
 
 // ------------------------------------------------------------ precision modes
-struct Pair {
-  float hi, lo;
-};
-
-// Knuth's TwoSum on the reuse chain: s + e == a + b exactly, then the pair is
-// renormalised.
-__device__ __forceinline__ Pair pair_add(Pair a, Pair b) {
-  const float s = a.hi + b.hi;
-  const float bp = s - a.hi;
-  float e = (a.hi - (s - bp)) + (b.hi - bp);
-  e += a.lo + b.lo;
-  const float hi = s + e;
-  return Pair{hi, e - (hi - s)};
-}
+// (Pair and pair_add, the TwoSum-compensated chain sums, are in twosum.hpp)
 
 // PAcc accumulates a row's partial sum; CAcc carries sums along reuse chains.
 struct MF64 {

@@ -7,6 +7,8 @@
 //     comparing with the plain row sums of the decoded lists;
 //   - decode truncated copies and copies with one flipped bit: each must
 //     either decode or fail with a message, never touch memory out of bounds.
+// A path given as reject:<file> is a hand-built hostile stream (decoded
+// values near 2^64): its decode must fail with a message.
 // Exit status 0 when every check holds.
 #include <cstdint>
 #include <cstdio>
@@ -84,9 +86,26 @@ static int check_file(const std::string& path) {
   return 0;
 }
 
+static int check_rejected(const std::string& path) {
+  std::ifstream f(path, std::ios::binary);
+  std::vector<uint8_t> bytes((std::istreambuf_iterator<char>(f)), std::istreambuf_iterator<char>());
+  for (int threads : {1, 2}) {
+    DecodedGraph d;
+    std::string err;
+    if (decode_stream(bytes.data(), bytes.size(), threads, d, err) == 0 || err.empty()) {
+      std::fprintf(stderr, "%s: hostile stream was not rejected\n", path.c_str());
+      return 1;
+    }
+  }
+  return 0;
+}
+
 int main(int argc, char** argv) {
   int bad = 0;
-  for (int i = 1; i < argc; ++i) bad |= check_file(argv[i]);
+  for (int i = 1; i < argc; ++i) {
+    const std::string a = argv[i];
+    bad |= a.rfind("reject:", 0) == 0 ? check_rejected(a.substr(7)) : check_file(a);
+  }
   if (!bad) std::printf("ok %d streams\n", argc - 1);
   return bad;
 }

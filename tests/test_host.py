@@ -156,6 +156,56 @@ def test_bench_refuses_several_gpus():
     assert "one GPU" in r.stderr and not r.stdout.strip()
 
 
+def _gamma_bits(x):
+    """Elias gamma of x + 1 (the format's gamma code of x)."""
+    b = (x + 1).bit_length() - 1
+    return "0" * b + format(x + 1, "b")
+
+
+def _zeta_bits(x, k):
+    """zeta_k of x + 1: unary bucket h, then the value's offset in the bucket
+    [2^(hk), 2^((h+1)k)) in minimal binary."""
+    v = x + 1
+    h = 0
+    while v >= 1 << ((h + 1) * k):
+        h += 1
+    left = 1 << (h * k)
+    zmax = (1 << ((h + 1) * k)) - left
+    z = v - left
+    s = (zmax - 1).bit_length()
+    thr = (1 << s) - zmax
+    return "0" * h + "1" + (format(z, "0%db" % (s - 1)) if z < thr else format(z + thr, "0%db" % s))
+
+
+def _hostile_bodies():
+    """Bodies of an 8-node stream (W = 0, L_min = 4, zeta_3) whose node 0
+    decodes a value near 2^64 where a length, a gap or a start is expected."""
+    huge = (1 << 64) - 2           # the largest gamma value
+    zhuge = (1 << 63) - 2           # a zeta_3 value in the last bucket
+    return [
+        # 10 entries, one interval of length L_min + huge (wraps to a small length unchecked)
+        _gamma_bits(10) + _gamma_bits(1) + _gamma_bits(0) + _gamma_bits(huge),
+        # one interval whose start offset is huge
+        _gamma_bits(10) + _gamma_bits(1) + _gamma_bits(huge) + _gamma_bits(0),
+        # two intervals, the second's gap huge
+        _gamma_bits(10) + _gamma_bits(2) + _gamma_bits(0) + _gamma_bits(0) + _gamma_bits(huge) + _gamma_bits(0),
+        # two residuals, the second's gap huge (prev + 1 + gap would overflow)
+        _gamma_bits(2) + _zeta_bits(0, 3) + _zeta_bits(zhuge, 3),
+        # a first residual at a huge signed offset
+        _gamma_bits(2) + _zeta_bits(zhuge, 3) + _zeta_bits(0, 3),
+    ]
+
+
+def test_zeta_bits_helper_decodes():
+    # the test's own encoder of hostile streams, checked against the oracle decoder's reader
+    from oracle import bvdecode
+    for x in (0, 1, 6, 7, 8, 100, 4095, 123456, (1 << 40) + 3):
+        bits = _zeta_bits(x, 3) + _gamma_bits(x)
+        br = bvdecode.BitReader(int(bits + "0" * (-len(bits) % 8), 2).to_bytes((len(bits) + 7) // 8, "big"),
+                                len(bits))
+        assert br.zeta(3) == x and br.gamma() == x
+
+
 def test_host_decode_and_layout_under_sanitizers(tmp_path):
     """The host decoder, layout builder and layout interpreter built with
     AddressSanitizer and UndefinedBehaviorSanitizer (g++, host code only) and
@@ -193,6 +243,10 @@ def test_host_decode_and_layout_under_sanitizers(tmp_path):
             f = tmp_path / ("g%d_w%d_r%d.bv" % (k, W, R))
             f.write_bytes(bytes(B.encode(g, W=W, R=R, stride=stride).data))
             files.append(str(f))
+    for k, bits in enumerate(_hostile_bodies()):
+        f = tmp_path / ("hostile%d.bv" % k)
+        f.write_bytes(bytes(pack_stream(8, 12, 0, 0, 4, 3, bits)))
+        files.append("reject:" + str(f))
     env = dict(os.environ, ASAN_OPTIONS="detect_leaks=1:abort_on_error=0:verify_asan_link_order=0",
                UBSAN_OPTIONS="halt_on_error=1:print_stacktrace=1")
     r = subprocess.run([exe] + files, capture_output=True, text=True, timeout=600, env=env)
@@ -334,3 +388,111 @@ def test_missing_library_fails_loudly():
     ])
     r = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, timeout=300, cwd=ROOT)
     assert r.returncode == 0 and r.stdout.strip().endswith("ok"), (r.stdout[-2000:], r.stderr[-2000:])
+
+
+def _twosum_lib(tmp_path):
+    import ctypes
+    import shutil
+    import subprocess
+    if shutil.which("g++") is None:
+        pytest.skip("no g++")
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    so = str(tmp_path / "twosum_host.so")
+    subprocess.run(["g++", "-std=c++17", "-O2", "-shared", "-fPIC", "-ffp-contract=off", "-fno-fast-math",
+                    "-msse2", "-mfpmath=sse", "-I", os.path.join(root, "paper_1708_07271_amd", "csrc"),
+                    os.path.join(root, "tests", "native", "twosum_host.cpp"), "-o", so], check=True, timeout=300)
+    lib = ctypes.CDLL(so)
+    return lib
+
+
+def _f32_cases(rng, n):
+    """Float pairs over many binades, with exact ties, heavy cancellation and
+    operands far apart in magnitude."""
+    e = rng.integers(-40, 40, size=(n, 2))
+    m = rng.random((n, 2)) + 0.5
+    v = (np.where(rng.random((n, 2)) < 0.5, -1.0, 1.0) * m * np.exp2(e)).astype(np.float32)
+    hard = np.array([[1.0, 2.0 ** -24], [1.0, 3 * 2.0 ** -25], [1.0, -1.0 + 2.0 ** -24], [3 * 2.0 ** 100, 2.0 ** -100],
+                     [-2.0 ** 30, 2.0 ** 30 + 1.0], [1e-38, -1e-38 * 0.75], [0.0, 0.0], [65504.0, 2.0 ** -14]],
+                    dtype=np.float32)
+    near = v[:, :1] * (1 + np.float32(2.0 ** -20) * rng.integers(-8, 8, size=(n, 1))).astype(np.float32)
+    return np.concatenate([v, hard, np.concatenate([v[:, :1], -near], axis=1)]).astype(np.float32)
+
+
+def test_two_sum_exact(tmp_path):
+    """O7: TwoSum as the device code computes it (twosum.hpp built for the
+    host): s is the rounded float sum and s + e equals a + b exactly, checked
+    in rational arithmetic."""
+    import ctypes
+    from fractions import Fraction
+    lib = _twosum_lib(tmp_path)
+    v = _f32_cases(np.random.default_rng(17), 3000)
+    a, b = np.ascontiguousarray(v[:, 0]), np.ascontiguousarray(v[:, 1])
+    s, e = np.empty_like(a), np.empty_like(a)
+    fp = ctypes.POINTER(ctypes.c_float)
+    lib.host_two_sum(a.ctypes.data_as(fp), b.ctypes.data_as(fp), s.ctypes.data_as(fp), e.ctypes.data_as(fp),
+                     len(a))
+    assert np.array_equal(s, a + b)             # numpy float32 addition rounds to nearest as well
+    for i in range(len(a)):
+        assert Fraction(float(s[i])) + Fraction(float(e[i])) == Fraction(float(a[i])) + Fraction(float(b[i])), i
+
+
+def test_pair_add_error_bound(tmp_path):
+    """pair_add on normalised pairs (|lo| <= ulp(hi)/2): the result is
+    normalised, and hi + lo is within 4 u^2 (|a| + |b|) of the exact sum of
+    the four parts (u = 2^-24), in rational arithmetic."""
+    import ctypes
+    from fractions import Fraction
+    lib = _twosum_lib(tmp_path)
+    rng = np.random.default_rng(18)
+    v = _f32_cases(rng, 2000)
+    hi = v.astype(np.float32)
+    lo = (hi.astype(np.float64) * (rng.random(hi.shape) - 0.5) * 2.0 ** -24).astype(np.float32)
+    lo = np.where((hi + lo) == hi, lo, np.float32(0))                     # keep the pairs normalised
+    ah, al, bh, bl = (np.ascontiguousarray(t) for t in (hi[:, 0], lo[:, 0], hi[:, 1], lo[:, 1]))
+    h, l = np.empty_like(ah), np.empty_like(ah)
+    fp = ctypes.POINTER(ctypes.c_float)
+    lib.host_pair_add(ah.ctypes.data_as(fp), al.ctypes.data_as(fp), bh.ctypes.data_as(fp), bl.ctypes.data_as(fp),
+                      h.ctypes.data_as(fp), l.ctypes.data_as(fp), len(ah))
+    assert np.array_equal(h + l, h)
+    u2 = Fraction(1, 2 ** 48)
+    for i in range(len(ah)):
+        exact = sum(Fraction(float(t[i])) for t in (ah, al, bh, bl))
+        err = abs(Fraction(float(h[i])) + Fraction(float(l[i])) - exact)
+        assert err <= 4 * u2 * (abs(Fraction(float(ah[i]))) + abs(Fraction(float(bh[i])))), i
+
+
+def test_kernel_index_replay(tmp_path):
+    """Every global index the tile kernel computes (stream rounds, row-end
+    counts, window loads, Z indices, gathered wide and long columns), replayed
+    on the host over every tile and lane of layouts in six shapes, stays
+    inside the device arrays (tests/native/index_replay.cpp): the bench's
+    2^20-node graph, the property-test families and crafted edge cases."""
+    import shutil
+    import subprocess
+    if shutil.which("g++") is None:
+        pytest.skip("no g++")
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    csrc = os.path.join(root, "paper_1708_07271_amd", "csrc")
+    exe = str(tmp_path / "index_replay")
+    subprocess.run(["g++", "-std=c++17", "-O2", "-D__HIP_PLATFORM_AMD__", "-I/opt/rocm/include", "-I", csrc,
+                    "-I", os.path.join(root, "include"), os.path.join(root, "tests", "native", "index_replay.cpp"),
+                    os.path.join(csrc, "bv_decode.cpp"), os.path.join(csrc, "bv_layout.cpp"), "-lpthread", "-o", exe],
+                   check=True, timeout=600)
+    rng = np.random.default_rng(21)
+    graphs = [B.workload_graph("web-n2p20-d20"), B.web_graph(5000, 15.0, 22), B.social_graph(4000, 30.0, 3000, 2.1, 23),
+              B.empty_graph(1), B.empty_graph(77), B.complete_graph(300), B.star_graph(5000, 17, "both")]
+    n = 3000
+    lists = [sorted(rng.choice(n, int(rng.integers(0, 60)), replace=False).tolist()) for _ in range(n)]
+    lists[n - 1] = list(range(n))
+    graphs.append(B.from_lists(lists))
+    files = []
+    for k, g in enumerate(graphs):
+        for W, R in ((7, 3), (1, 15), (15, 1)):
+            f = tmp_path / ("g%d_%d_%d.bv" % (k, W, R))
+            f.write_bytes(bytes(B.encode(g, W=W, R=R).data))
+            files.append(str(f))
+            if k == 0:
+                break
+    r = subprocess.run([exe] + files, capture_output=True, text=True, timeout=900)
+    assert r.returncode == 0, (r.stdout[-2000:], r.stderr[-3000:])
+    assert r.stdout.startswith("ok")
