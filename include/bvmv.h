@@ -95,15 +95,22 @@ int bvmv_load(const void* bitstream, size_t nbytes, const bvmv_load_opts* opts, 
 
 /* y = A x (Section "Our Approach": y_i = y_{r_i} + sum_j A'_ij x_j, plus
  * interval sums and residual entries).  x, y: device vectors of n elements
- * (double for BVMV_F64, float otherwise); x and y must not overlap.
- * Deterministic: the same inputs give bit-identical y. */
+ * (double for BVMV_F64, float otherwise); overlapping x and y give
+ * BVMV_EINVAL.  Deterministic: the same inputs give bit-identical y.
+ * Accuracy, per entry, relative to the exactly rounded sum: BVMV_F64 1e-12;
+ * BVMV_F32_COMP 1e-5 (the FP32 bar); BVMV_F32 is an uncompensated mode that
+ * does NOT meet 1e-5: its error grows with the reference-chain depth and the
+ * magnitude of the window's prefix sums (tested to 1e-3). */
 int bvmv_multiply(bvmv_graph* g, const void* x, void* y, int prec, void* stream);
 
-/* Y = A X for k right-hand sides at once: every tile of the layout is decoded
+/* Y = A X for k right-hand sides at once (the product of the Proposition of
+ * Section "Our Approach" applied to each column; Section "PageRank" needs one
+ * per personalized start vector p_0): every tile of the layout is decoded
  * once and multiplies the k columns one after another.  X, Y: column-major
  * n x k blocks with leading dimension ld >= n (elements).  1 <= k <= 64.
  * prec: BVMV_F32 or BVMV_F32_COMP (float) or BVMV_F64 (double).  Column c of
- * Y is bit-identical to bvmv_multiply of column c of X. */
+ * Y is bit-identical to bvmv_multiply of column c of X.  Overlapping blocks
+ * give BVMV_EINVAL. */
 int bvmv_multiply_batch(bvmv_graph* g, const void* X, void* Y, int k, int64_t ld, int prec, void* stream);
 
 typedef struct bvmv_mlp bvmv_mlp;  /* the warm-restart network (declared with its entry points below) */
@@ -112,7 +119,8 @@ typedef struct bvmv_mlp bvmv_mlp;  /* the warm-restart network (declared with it
  * paper's teleport probability a is 1 - beta).  Iteration stops at the first
  * t with ||p_t - p_{t-1}||_1 < tol (accumulated in double), or at max_iter. */
 typedef struct {
-  double damping;   /* 0 <= damping < 1 (0 = default 0.85 unless exact_zero_damping) */
+  double damping;   /* 0 <= damping < 1.  0 means the default 0.85 unless exact_zero_damping = 1,
+                       which takes damping = 0 literally (then p = teleport after one step) */
   double tol;       /* > 0 (0 = default 1e-6) */
   int max_iter;     /* > 0 (0 = default 1000) */
   int prec;         /* BVMV_F32_COMP (default), BVMV_F32 or BVMV_F64 */
@@ -146,8 +154,8 @@ typedef struct {
  * y = B z (the compressed product); p'_v = (1-beta) v_v + beta (y_v + delta v_v);
  * residual = ||p' - p||_1 (double).  Dangling mass goes to the teleport vector.
  * teleport: device n x k column-major (ld = n) of the prec's element type, each
- *   column a probability vector; NULL = uniform 1/n (k must then be 1, or the
- *   graph a group: each member graph gets its own uniform vector).
+ *   column a probability vector; NULL = uniform 1/n for every column (on a
+ *   group: each member graph gets its own uniform vector).
  * start: device n x k start vectors; NULL = the teleport vector.
  * p_out: device n x k result.  res: HOST array of k results (for a group:
  *   one per member graph).  k = number of personalized right-hand sides.

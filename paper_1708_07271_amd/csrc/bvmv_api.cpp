@@ -845,6 +845,14 @@ int bvmv_load(const void* bitstream, size_t nbytes, const bvmv_load_opts* opts, 
   return BVMV_OK;
 }
 
+namespace {
+// [a, a + na) and [b, b + nb) share a byte
+bool ranges_overlap(const void* a, size_t na, const void* b, size_t nb) {
+  const uintptr_t pa = reinterpret_cast<uintptr_t>(a), pb = reinterpret_cast<uintptr_t>(b);
+  return pa < pb + nb && pb < pa + na;
+}
+}  // namespace
+
 void bvmv_free(bvmv_graph* g) {
   if (!g) return;
   {
@@ -857,7 +865,8 @@ void bvmv_free(bvmv_graph* g) {
 int bvmv_multiply(bvmv_graph* g, const void* x, void* y, int prec, void* stream) {
   if (!g || !x || !y) return fail(BVMV_EINVAL, "null argument");
   if (prec < 0 || prec > 2) return fail(BVMV_EINVAL, "bad precision");
-  if (x == y) return fail(BVMV_EINVAL, "x and y must not overlap");
+  const size_t vbytes = size_t(g->n) * elem_size(prec);
+  if (ranges_overlap(x, vbytes, y, vbytes)) return fail(BVMV_EINVAL, "x and y must not overlap");
   DeviceGuard dg(g->device);
   HIP_TRY(launch_bv_multiply(g->L, prec, x, y, static_cast<hipStream_t>(stream)));
   return BVMV_OK;
@@ -866,7 +875,8 @@ int bvmv_multiply(bvmv_graph* g, const void* x, void* y, int prec, void* stream)
 int bvmv_multiply_batch(bvmv_graph* g, const void* X, void* Y, int k, int64_t ld, int prec, void* stream) {
   if (!g || !X || !Y) return fail(BVMV_EINVAL, "null argument");
   if (prec < 0 || prec > 2 || k < 1 || k > 64 || ld < g->n) return fail(BVMV_EINVAL, "bad batch arguments");
-  if (X == Y) return fail(BVMV_EINVAL, "X and Y must not overlap");
+  const size_t bbytes = (size_t(k - 1) * size_t(ld) + size_t(g->n)) * elem_size(prec);
+  if (ranges_overlap(X, bbytes, Y, bbytes)) return fail(BVMV_EINVAL, "X and Y must not overlap");
   DeviceGuard dg(g->device);
   HIP_TRY(launch_bv_multiply_cols(g->L, prec, X, Y, k, ld, static_cast<hipStream_t>(stream)));
   return BVMV_OK;
@@ -1132,6 +1142,8 @@ int bvmv_csr_create(const bvmv_graph* g, bvmv_csr** out) {
 int bvmv_csr_multiply(bvmv_csr* c, const void* x, void* y, int prec, void* stream) {
   if (!c || !x || !y) return fail(BVMV_EINVAL, "null argument");
   if (prec < 0 || prec > 2) return fail(BVMV_EINVAL, "bad precision");
+  const size_t vbytes = size_t(c->n) * elem_size(prec);
+  if (ranges_overlap(x, vbytes, y, vbytes)) return fail(BVMV_EINVAL, "x and y must not overlap");
   DeviceGuard dg(c->device);
   HIP_TRY(launch_csr_multiply(c->C, prec, x, y, static_cast<hipStream_t>(stream)));
   return BVMV_OK;

@@ -5,8 +5,9 @@
 //     hidden layers on MFMA (v_mfma_f32_32x32x8_bf16: BF16 operands, FP32
 //     accumulation), biases, GELU and the output layer in FP32;
 //   - deterministic reduction of per-wave gradient partials and Adam on FP32
-//     master parameters with BF16 weight copies;
-//   - the start vector p0 = exp(s) / sum exp(s).
+//     master parameters with BF16 weight copies.
+// The restart vector built from the network's output is written by
+// restart_vector_kernel in bv_kernels.hip.
 // The network's arithmetic is defined operand by operand in the CPU oracle
 // (BF16 rounding, round to nearest even, of every operand that enters a
 // matrix product; the output layer takes h2 unrounded).

@@ -9,6 +9,7 @@ import pytest
 
 import bvinputs as B
 from oracle import pagerank
+from tests import tolerances as TOL
 
 pytestmark = pytest.mark.gpu
 
@@ -23,6 +24,17 @@ def P():
     import paper_1708_07271_amd as mod
     mod.load_library()
     return mod
+
+
+def _rel(a, b):
+    """Largest per-entry relative error of a against the oracle's b; entries
+    where b is 0 must be exactly 0."""
+    a = np.asarray(a, dtype=np.float64)
+    b = np.asarray(b, dtype=np.float64)
+    d = np.abs(a - b)
+    z = b == 0
+    assert np.all(d[z] == 0), "nonzero result where the oracle gives 0"
+    return float(np.max(d[~z] / np.abs(b[~z]))) if np.any(~z) else 0.0
 
 
 def _in_links(g):
@@ -63,7 +75,7 @@ def test_closed_forms(P):
             assert np.max(np.abs(p[1:] - (1 - pc) / (n - 1))) < 1e-12
 
 
-@pytest.mark.parametrize("prec_name,tol", [("f64", 1e-12), ("f32c", 1e-5), ("f32", 1e-4)])
+@pytest.mark.parametrize("prec_name,tol", [("f64", TOL.F64), ("f32c", TOL.F32C), ("f32", TOL.F32_NAIVE)])
 def test_iteration_matched(P, prec_name, tol):
     prec = P.PREC_NAMES[prec_name]
     g = B.web_graph(40_000, 15.0, 77)          # rows read as in-link lists, as loaded
@@ -73,7 +85,7 @@ def test_iteration_matched(P, prec_name, tol):
     _, t_or, _, ok_or = pagerank.pagerank(g.rowptr, g.col, 0.85, tol=1e-6)
     assert ok_or and abs(it - t_or) <= 1
     p_ref = pagerank.pagerank(g.rowptr, g.col, 0.85, iters=it)[0]
-    assert np.max(np.abs(p - p_ref) / p_ref) < tol
+    assert _rel(p, p_ref) < tol
     assert abs(p.sum() - 1.0) < (1e-12 if prec == P.BVMV_F64 else 1e-5)
 
 
@@ -85,17 +97,46 @@ def test_personalized_start_and_limits(P):
     v[seeds] = 1.0 / 16
     p, ((it, ok, r),) = _pr(P, G, g.n, P.BVMV_F64, teleport=v)
     p_ref = pagerank.pagerank(g.rowptr, g.col, 0.85, teleport=v, iters=it)[0]
-    assert ok and np.max(np.abs(p - p_ref)) < 1e-12 * np.max(p_ref)
+    assert ok and _rel(p, p_ref) < TOL.F64
     # warm start from the converged vector: stops almost at once
     p2, ((it2, ok2, r2),) = _pr(P, G, g.n, P.BVMV_F64, teleport=v, start=p)
     assert ok2 and it2 <= 2
     # iteration limit: NOT_CONVERGED status, outputs still written
     p3, ((it3, ok3, r3),) = _pr(P, G, g.n, P.BVMV_F64, teleport=v, max_iter=3)
     assert not ok3 and it3 == 3
-    assert np.max(np.abs(p3 - pagerank.pagerank(g.rowptr, g.col, 0.85, teleport=v, iters=3)[0])) < 1e-15
+    assert _rel(p3, pagerank.pagerank(g.rowptr, g.col, 0.85, teleport=v, iters=3)[0]) < TOL.F64
     # beta = 0: p = v
     p4, _ = _pr(P, G, g.n, P.BVMV_F64, teleport=v, damping=0.0)
     assert np.max(np.abs(p4 - v)) < 1e-16
+
+
+@pytest.mark.parametrize("prec_name", ["f64", "f32c"])
+def test_fallback_check_keeps_better_start(P, prec_name):
+    """fallback_check: one probe iteration from `start` and one from the
+    teleport vector; `start` is kept only if its residual is the smaller.  A
+    start near the fixed point is kept (and converges at once); a start with
+    all mass on one node is rejected, and the run is then the plain run from
+    the teleport vector, bit for bit, probes not counted."""
+    prec = P.PREC_NAMES[prec_name]
+    dt = torch.float64 if prec == P.BVMV_F64 else torch.float32
+    g = B.web_graph(20_000, 12.0, 83)
+    G = P.bvmv_load(B.encode(g).data)
+    plain = torch.empty(g.n, dtype=dt, device=DEV)
+    (rp,) = P.bvmv_pagerank_detail(G, plain, prec=prec)
+    good = plain.clone()
+    out = torch.empty_like(plain)
+    (rg,) = P.bvmv_pagerank_detail(G, out, start=good, prec=prec, fallback_check=1)
+    torch.cuda.synchronize()
+    assert rg["used_start"] == 1 and rg["converged"] and rg["iters"] <= 2
+    bad = torch.zeros_like(plain)
+    bad[0] = 1.0
+    (rb,) = P.bvmv_pagerank_detail(G, out, start=bad, prec=prec, fallback_check=1)
+    torch.cuda.synchronize()
+    assert rb["used_start"] == 0 and rb["iters"] == rp["iters"] and rb["products"] == rp["products"]
+    assert torch.equal(out, plain)
+    # without the check the bad start is used as given
+    (rn,) = P.bvmv_pagerank_detail(G, out, start=bad, prec=prec)
+    assert rn["used_start"] == 1
 
 
 def _pr_k(P, G, n, k, prec, V=None, start=None, **kw):
@@ -112,7 +153,7 @@ def _pr_k(P, G, n, k, prec, V=None, start=None, **kw):
     return p.cpu().numpy().astype(np.float64).reshape(k, n).T, res
 
 
-@pytest.mark.parametrize("prec_name,tol", [("f64", 1e-12), ("f32c", 1e-5)])
+@pytest.mark.parametrize("prec_name,tol", [("f64", TOL.F64), ("f32c", TOL.F32C)])
 def test_batched_personalized(P, prec_name, tol):
     """k teleport sets in one launch sequence: each column is the oracle's
     personalized PageRank (iteration-matched), columns stop independently."""
@@ -130,7 +171,7 @@ def test_batched_personalized(P, prec_name, tol):
         _, t_or, _, ok_or = pagerank.pagerank(g.rowptr, g.col, 0.85, teleport=V[:, c], tol=1e-6)
         assert ok_or and abs(it - t_or) <= 1
         p_ref = pagerank.pagerank(g.rowptr, g.col, 0.85, teleport=V[:, c], iters=it)[0]
-        assert np.max(np.abs(p[:, c] - p_ref)) < tol * np.max(p_ref), c
+        assert _rel(p[:, c], p_ref) < tol, c
         assert abs(p[:, c].sum() - 1.0) < (1e-12 if prec == P.BVMV_F64 else 1e-5)
         iters.add(it)
     # deterministic
@@ -149,13 +190,13 @@ def test_batched_uniform_and_limits(P):
     for c in range(k):
         assert abs(res[c][0] - it1) <= 1 and res[c][1]
         ref = pagerank.pagerank(g.rowptr, g.col, 0.85, iters=res[c][0])[0]
-        assert np.max(np.abs(p[:, c] - ref)) < 1e-12 * np.max(ref)
+        assert _rel(p[:, c], ref) < TOL.F64
     V = B.teleport_sets(g.n, k, 16, seed=9).astype(np.float64)
     p3, res3 = _pr_k(P, G, g.n, k, P.BVMV_F64, V, max_iter=4)
     for c in range(k):
         assert res3[c][0] == 4 and not res3[c][1]
         ref = pagerank.pagerank(g.rowptr, g.col, 0.85, teleport=V[:, c], iters=4)[0]
-        assert np.max(np.abs(p3[:, c] - ref)) < 1e-15
+        assert _rel(p3[:, c], ref) < TOL.F64
     # warm start from the converged columns: done almost at once
     p4, _ = _pr_k(P, G, g.n, k, P.BVMV_F64, V)
     p5, res5 = _pr_k(P, G, g.n, k, P.BVMV_F64, V, start=p4)
@@ -204,7 +245,7 @@ def test_group_equals_solo(P):
         assert res[i][0] == it and res[i][1] == ok
         assert np.array_equal(pg[offs[i]:offs[i + 1]], ps)
         p_ref = pagerank.pagerank(g.rowptr, g.col, 0.85, iters=it)[0]
-        assert np.max(np.abs(ps - p_ref) / p_ref) < 1e-5
+        assert _rel(ps, p_ref) < TOL.F32C
 
 
 def test_csr_pagerank(P):
@@ -215,7 +256,7 @@ def test_csr_pagerank(P):
     it, ok, r = P.bvmv_csr_pagerank(C, p)
     torch.cuda.synchronize()
     p_ref = pagerank.pagerank(g.rowptr, g.col, 0.85, iters=it)[0]
-    assert ok and np.max(np.abs(p.cpu().numpy() - p_ref) / p_ref) < 1e-5
+    assert ok and _rel(p.cpu().numpy(), p_ref) < TOL.F32C
     pc, ((itc, okc, rc),) = _pr(P, G, g.n, P.BVMV_F32_COMP)
     assert abs(itc - it) <= 1
 
@@ -229,5 +270,5 @@ def test_full_size_pagerank_2p20(P):
     p_ref, t_or, _, _ = pagerank.pagerank(g.rowptr, g.col, 0.85, tol=1e-6)
     assert abs(it - t_or) <= 1
     p_ref = pagerank.pagerank(g.rowptr, g.col, 0.85, iters=it)[0]
-    assert np.max(np.abs(p - p_ref) / p_ref) < 1e-5
+    assert _rel(p, p_ref) < TOL.F32C
     assert abs(p.sum() - 1.0) < 1e-5

@@ -1,14 +1,16 @@
 """GPU parity of the compressed product, degrees, CSR baseline and batched
 products against the CPU oracle (same seeded inputs).
 
-Tolerances: FP64 path 1e-12 relative per entry; FP32 paths 1e-5 relative per
-entry against the float64 oracle on the same float32 inputs; integer-valued
-x makes every partial sum exact, so all modes must then be bit-exact."""
+Tolerances (tests/tolerances.py): FP64 path 1e-12 relative per entry; the
+two-sum FP32 path 1e-5 relative per entry against the float64 oracle on the
+same float32 inputs; the naive FP32 path 1e-3; integer-valued x makes every
+partial sum exact, so all modes must then be bit-exact."""
 import numpy as np
 import pytest
 
 import bvinputs as B
-from oracle import product
+from oracle import bvdecode, product
+from tests import tolerances as TOL
 
 pytestmark = pytest.mark.gpu
 
@@ -78,11 +80,11 @@ def test_product_parity_all_modes(P, graphs, lay):
         print("case", name, LAYOUTS[lay], flush=True)
         G = P.bvmv_load(enc.data, **LAYOUTS[lay])
         x = B.uniform_x(g.n, 101)
-        assert _rel(_mul(P, G, x, P.BVMV_F64), product.matvec(g.rowptr, g.col, x)) < 1e-12
+        assert _rel(_mul(P, G, x, P.BVMV_F64), product.matvec(g.rowptr, g.col, x)) < TOL.F64
         x32 = x.astype(np.float32)
         ref32 = product.matvec(g.rowptr, g.col, x32.astype(np.float64))
-        assert _rel(_mul(P, G, x32, P.BVMV_F32_COMP), ref32) < 1e-5
-        assert _rel(_mul(P, G, x32, P.BVMV_F32), ref32) < 1e-3
+        assert _rel(_mul(P, G, x32, P.BVMV_F32_COMP), ref32) < TOL.F32C
+        assert _rel(_mul(P, G, x32, P.BVMV_F32), ref32) < TOL.F32_NAIVE
         xi = B.integer_x(g.n, 5, 7)                 # partial sums < 2^24: exact in float32
         refi = product.matvec(g.rowptr, g.col, xi)
         for prec in (P.BVMV_F32, P.BVMV_F32_COMP):
@@ -121,9 +123,9 @@ def test_closed_forms_on_device(P):
     for g, _ in cases:
         G = P.bvmv_load(B.encode(g).data)
         y = _mul(P, G, x, P.BVMV_F64)
-        assert _rel(y, product.matvec_exact(g.rowptr, g.col, x)) < 1e-12
+        assert _rel(y, product.matvec_exact(g.rowptr, g.col, x)) < TOL.F64
     G = P.bvmv_load(B.encode(B.complete_graph(n)).data)
-    assert _rel(_mul(P, G, x, P.BVMV_F64), x.sum() - x) < 1e-12
+    assert _rel(_mul(P, G, x, P.BVMV_F64), x.sum() - x) < TOL.F64
 
 
 def test_edge_cases(P):
@@ -165,11 +167,11 @@ def test_entries_at_the_end_of_the_stream_array(P, lay):
     G = P.bvmv_load(B.encode(g).data, **LAYOUTS[lay])
     assert P.bvmv_get_info(G)["escapes"] > 0
     x = B.uniform_x(n, 77)
-    assert _rel(_mul(P, G, x, P.BVMV_F64), product.matvec(g.rowptr, g.col, x)) < 1e-12
+    assert _rel(_mul(P, G, x, P.BVMV_F64), product.matvec(g.rowptr, g.col, x)) < TOL.F64
     x32 = x.astype(np.float32)
     ref32 = product.matvec(g.rowptr, g.col, x32.astype(np.float64))
-    assert _rel(_mul(P, G, x32, P.BVMV_F32_COMP), ref32) < 1e-5
-    assert _rel(_mul(P, G, x32, P.BVMV_F32), ref32) < 1e-3
+    assert _rel(_mul(P, G, x32, P.BVMV_F32_COMP), ref32) < TOL.F32C
+    assert _rel(_mul(P, G, x32, P.BVMV_F32), ref32) < TOL.F32_NAIVE
     xi = B.integer_x(n, 5, 9)
     refi = product.matvec(g.rowptr, g.col, xi)
     for prec in (P.BVMV_F32, P.BVMV_F32_COMP):
@@ -206,8 +208,8 @@ def test_largest_layouts(P, graphs):
         for prec in (P.BVMV_F64, P.BVMV_F32, P.BVMV_F32_COMP):
             xp = xi if prec == P.BVMV_F64 else xi.astype(np.float32)
             assert np.array_equal(_mul(P, G, xp, prec), want_i), (rows, prec)
-        assert _rel(_mul(P, G, x, P.BVMV_F64), want) < 1e-12
-        assert _rel(_mul(P, G, x32, P.BVMV_F32_COMP), want32) < 1e-5
+        assert _rel(_mul(P, G, x, P.BVMV_F64), want) < TOL.F64
+        assert _rel(_mul(P, G, x32, P.BVMV_F32_COMP), want32) < TOL.F32C
 
 
 def test_csr_baseline(P, graphs):
@@ -215,10 +217,10 @@ def test_csr_baseline(P, graphs):
         G = P.bvmv_load(enc.data, keep_lists=1)
         C = P.bvmv_csr_create(G)
         x = B.uniform_x(g.n, 11)
-        assert _rel(_csr_mul(P, C, x, P.BVMV_F64), product.matvec(g.rowptr, g.col, x)) < 1e-12
+        assert _rel(_csr_mul(P, C, x, P.BVMV_F64), product.matvec(g.rowptr, g.col, x)) < TOL.F64
         x32 = x.astype(np.float32)
         ref32 = product.matvec(g.rowptr, g.col, x32.astype(np.float64))
-        assert _rel(_csr_mul(P, C, x32, P.BVMV_F32_COMP), ref32) < 1e-5
+        assert _rel(_csr_mul(P, C, x32, P.BVMV_F32_COMP), ref32) < TOL.F32C
         xi = B.integer_x(g.n, 12, 7).astype(np.float32)
         assert np.array_equal(_csr_mul(P, C, xi, P.BVMV_F32), product.matvec(g.rowptr, g.col, xi))
 
@@ -237,7 +239,7 @@ def test_batch_matches_oracle(P, graphs, k):
         torch.cuda.synchronize()
         Y = Yd.cpu().numpy().T
         for c in range(0, k, max(1, k // 4)):
-            assert _rel(Y[:, c], product.matvec(g.rowptr, g.col, X[:, c].astype(np.float64))) < 1e-5
+            assert _rel(Y[:, c], product.matvec(g.rowptr, g.col, X[:, c].astype(np.float64))) < TOL.F32C
         Xi = rng.integers(0, 8, size=(g.n, k)).astype(np.float32)
         Xd = torch.from_numpy(np.ascontiguousarray(Xi.T)).to(DEV)
         P.bvmv_multiply_batch(G, Xd, Yd, P.BVMV_F32)
@@ -249,7 +251,7 @@ def test_batch_matches_oracle(P, graphs, k):
         Yd64 = torch.empty_like(Xd64)
         P.bvmv_multiply_batch(G, Xd64, Yd64, P.BVMV_F64)
         torch.cuda.synchronize()
-        assert _rel(Yd64.cpu().numpy()[k - 1], product.matvec(g.rowptr, g.col, X[:, k - 1].astype(np.float64))) < 1e-12
+        assert _rel(Yd64.cpu().numpy()[k - 1], product.matvec(g.rowptr, g.col, X[:, k - 1].astype(np.float64))) < TOL.F64
 
 
 def test_batch_leading_dimension(P):
@@ -267,7 +269,7 @@ def test_batch_leading_dimension(P):
     Y = Yb.cpu().numpy()
     assert np.all(Y[:, g.n:] == -7.0)
     for c in range(k):
-        assert _rel(Y[c, :g.n], product.matvec(g.rowptr, g.col, X[c, :g.n].astype(np.float64))) < 1e-5
+        assert _rel(Y[c, :g.n], product.matvec(g.rowptr, g.col, X[c, :g.n].astype(np.float64))) < TOL.F32C
     # each column equals the single-vector product bit for bit
     y1 = torch.empty(g.n, device=DEV)
     P.bvmv_multiply(G, Xb[3, :g.n].contiguous(), y1, P.BVMV_F32_COMP)
@@ -306,7 +308,7 @@ def test_autotune_candidates_exact(P, graphs, cand):
         for prec in (P.BVMV_F32, P.BVMV_F32_COMP):
             assert np.array_equal(_mul(P, G, xi, prec), refi)
         x = B.uniform_x(g.n, 9)
-        assert _rel(_mul(P, G, x, P.BVMV_F64), product.matvec(g.rowptr, g.col, x)) < 1e-12
+        assert _rel(_mul(P, G, x, P.BVMV_F64), product.matvec(g.rowptr, g.col, x)) < TOL.F64
 
 
 def test_autotune_load(P):
@@ -323,7 +325,7 @@ def test_autotune_load(P):
     assert info2["window_cap"] == info["window_cap"]
     x = B.uniform_x(g.n, 72, np.float32)
     ref = product.matvec(g.rowptr, g.col, x.astype(np.float64))
-    assert _rel(_mul(P, G, x, P.BVMV_F32_COMP), ref) < 1e-5
+    assert _rel(_mul(P, G, x, P.BVMV_F32_COMP), ref) < TOL.F32C
     assert P.bvmv_get_info(P.bvmv_load(enc.data))["autotuned"] == 0
 
 
@@ -336,11 +338,92 @@ def test_full_size_web_2p20(P):
     x32 = B.uniform_x(g.n, 102, np.float32)
     y = _mul(P, G, x32, P.BVMV_F32_COMP)
     x64 = x32.astype(np.float64)
-    assert _rel(y, product.matvec(g.rowptr, g.col, x64)) < 1e-5
+    assert _rel(y, product.matvec(g.rowptr, g.col, x64)) < TOL.F32C
     rows = np.random.default_rng(0).choice(g.n, 2000, replace=False)
-    assert _rel(y[rows], product.matvec_rows(g.rowptr, g.col, x64, rows)) < 1e-5
+    assert _rel(y[rows], product.matvec_rows(g.rowptr, g.col, x64, rows)) < TOL.F32C
     xi = B.integer_x(g.n, 4, 7).astype(np.float32)
     assert np.array_equal(_mul(P, G, xi, P.BVMV_F32_COMP), product.matvec(g.rowptr, g.col, xi))
+
+
+@pytest.mark.slow
+def test_full_size_web_2p20_f64(P):
+    """n = 2^20, FP64 vectors in the bench's launch configuration: every row
+    within 1e-12 of the oracle, and sampled rows against correctly rounded
+    sums."""
+    g = B.workload_graph("web-n2p20-d20")
+    G = P.bvmv_load(B.encode(g).data)
+    x = B.uniform_x(g.n, 102)
+    y = _mul(P, G, x, P.BVMV_F64)
+    assert _rel(y, product.matvec(g.rowptr, g.col, x)) < TOL.F64
+    rows = np.random.default_rng(3).choice(g.n, 2000, replace=False)
+    assert _rel(y[rows], product.matvec_rows(g.rowptr, g.col, x, rows)) < TOL.F64
+
+
+def _chain_graph(nchains, base_size, seed):
+    """Chains of 16 rows (depths 0..15 with R = 15, W = 1).  Row 0 of a chain
+    holds a big column and `base_size` small ones; every later row drops one
+    entry of the row before it and adds one: at odd depths it drops the big
+    column and adds a tiny one, at even depths it drops a small column and
+    adds a new big one.  Big x lie in [4096, 8192), where a float's spacing is
+    2^-11, and tiny x in [2^-13, 2^-12), under half that spacing: a float sum
+    of a row's partial (+tiny - big) loses the tiny value, so the naive chain
+    misses one more of them at every odd depth.  Columns 0..nbig-1 are big,
+    then the tiny ones, then the small ones."""
+    rng = np.random.default_rng(seed)
+    nbig, ntiny = nchains * 8, nchains * 8
+    n = nbig + ntiny + max(nchains * 16, 8 * base_size)
+    lists = []
+    big, tiny = iter(range(nbig)), iter(range(nbig, nbig + ntiny))
+    small = np.arange(nbig + ntiny, n)
+    for c in range(nchains):
+        row = set(rng.choice(small, base_size, replace=False).tolist())
+        b = next(big)
+        row.add(b)
+        lists.append(sorted(row))
+        for d in range(1, 16):
+            if d % 2:
+                row.discard(b)
+                row.add(next(tiny))
+            else:
+                row.discard(max(row))               # a small column (the largest ids are small ones)
+                b = next(big)
+                row.add(b)
+            lists.append(sorted(row))
+    lists += [[] for _ in range(n - len(lists))]
+    g = B.from_lists(lists)
+    x = np.random.default_rng(seed + 1).random(n).astype(np.float32)
+    r = np.random.default_rng(seed + 2)
+    x[:nbig] = (4096.0 * (1.0 + r.random(nbig))).astype(np.float32)
+    x[nbig:nbig + ntiny] = (2.0 ** -13 * (1.0 + r.random(ntiny))).astype(np.float32)
+    return g, x
+
+
+def test_deep_chain_compensation(P):
+    """Reference chains 15 deep (R = 15): the naive FP32 error of the odd
+    (small-sum) rows grows with the chain depth, one swamped tiny value more
+    at every odd step, while the TwoSum-compensated chains stay within 1e-5
+    of the FP64 oracle at every depth; the FP64 path stays within 1e-12."""
+    g, x = _chain_graph(48, 24, 5)
+    enc = B.encode(g, W=1, R=15)
+    _, _, _, hdr, st = bvdecode.decode(enc.data, with_stats=True)
+    depth = st[:, 0]
+    assert depth.max() == 15
+    G = P.bvmv_load(enc.data)
+    assert G.info()["max_level"] == 15
+    ref = product.matvec(g.rowptr, g.col, x.astype(np.float64))
+    yc = _mul(P, G, x, P.BVMV_F32_COMP).astype(np.float64)
+    yn = _mul(P, G, x, P.BVMV_F32).astype(np.float64)
+    assert _rel(yc, ref) < TOL.F32C
+    assert _rel(_mul(P, G, x.astype(np.float64), P.BVMV_F64), ref) < TOL.F64
+    nz = ref != 0
+    en = np.zeros_like(ref)
+    en[nz] = np.abs(yn[nz] - ref[nz]) / np.abs(ref[nz])
+    by_depth = np.array([en[nz & (depth == d)].mean() for d in range(1, 16, 2)])
+    print("naive FP32 mean relative error at depths 1, 3, .., 15:", ["%.1e" % v for v in by_depth],
+          "compensated max %.2e" % _rel(yc, ref), flush=True)
+    # one more swamped tiny value per odd depth: the error grows with depth
+    assert by_depth[-1] > 2.5 * by_depth[0] and by_depth[-1] > 5 * TOL.F32C
+    assert np.polyfit(np.arange(1, 16, 2), by_depth, 1)[0] > 0
 
 
 @pytest.mark.slow
@@ -354,8 +437,8 @@ def test_full_size_social_4e6(P):
     x32 = B.uniform_x(g.n, 103, np.float32)
     rows = np.random.default_rng(1).choice(g.n, 3000, replace=False)
     ref = product.matvec_rows(g.rowptr, g.col, x32.astype(np.float64), rows)
-    assert _rel(_mul(P, G, x32, P.BVMV_F32_COMP)[rows], ref) < 1e-5
-    assert _rel(_mul(P, G, x32, P.BVMV_F32)[rows], ref) < 1e-3
+    assert _rel(_mul(P, G, x32, P.BVMV_F32_COMP)[rows], ref) < TOL.F32C
+    assert _rel(_mul(P, G, x32, P.BVMV_F32)[rows], ref) < TOL.F32_NAIVE
     xi = B.integer_x(g.n, 5, 7).astype(np.float32)
     assert np.array_equal(_mul(P, G, xi, P.BVMV_F32_COMP), product.matvec(g.rowptr, g.col, xi.astype(np.float64)))
 
@@ -377,4 +460,4 @@ def test_full_size_batch_8e6(P):
     Yr = Yd[:, torch.from_numpy(rows).to(DEV)].cpu().numpy().T
     for c in (0, 7, 31):
         ref = product.matvec_rows(g.rowptr, g.col, X[:, c].astype(np.float64), rows)
-        assert _rel(Yr[:, c], ref) < 1e-5, c
+        assert _rel(Yr[:, c], ref) < TOL.F32C, c

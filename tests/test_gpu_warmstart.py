@@ -90,16 +90,58 @@ def test_restart_sample_rejects_converged(P):
     with pytest.raises(P.BvmvError):
         P.bvmv_restart_sample(G, 5, F)
 
+def _forward_bound(theta, X):
+    """Per-row bound on |s_device - s_oracle| for the network's forward pass,
+    from the oracle's own intermediates, and the rows where a BF16 rounding
+    of h1 may go the other way on the device.
+
+    The device takes the same BF16 operands (x, W1, W2, w3 exactly as here),
+    forms the products exactly and sums them in FP32 (12 and 64 terms), and
+    evaluates GELU in FP32 with a hardware exponential and reciprocal.  An
+    FP32 sum of k terms errs by at most k u sum|terms| (u = 2^-24), GELU by a
+    few u relative, so, with S = 1 + sum_k |w3_k| (|h2_k| + 1.1 (sum_j
+    |W2_kj h1q_j| + |b2_k|)) the sum of magnitudes the output is built from,
+    |ds| <= 64 u S (1 + 1.1) + 12 u-terms < 1e-5 S, as long as every bf(h1)
+    is the oracle's.  h1 itself comes with an FP32 error below e_j = 2 (4 u
+    |h1_j| + |gelu'(z1_j)| 13 u (sum_i |W1_ji x_i| + |b1_j|)): twice the worst
+    case of its 13-term sum carried through GELU, plus GELU's own few
+    roundings; a value of h1 closer than e_j to a BF16 rounding boundary may round
+    the other way, which moves s by at most |ds/dh1q_j| times one BF16 step.
+    Returns (s, FP32 bound, bound with the flips, near-tie rows)."""
+    s, c = mlp.forward(theta, X)
+    p = c["p"]
+    u = 2.0 ** -24
+    z2_mag = np.abs(c["h1q"]) @ np.abs(p["W2"]).T + np.abs(p["b2"])
+    S = 1.0 + (np.abs(c["h2"]) + 1.1 * z2_mag) @ np.abs(p["w3"]) + abs(p["b3"][0])
+    bound = 4 * 64 * u * S
+    h1 = mlp.gelu(c["z1"])
+    z1_mag = np.abs(c["xq"]) @ np.abs(p["W1"]).T + np.abs(p["b1"])
+    e = 2.0 * (4 * u * np.abs(h1) + np.abs(mlp.gelu_grad(c["z1"])) * 13 * u * z1_mag)
+    near = (mlp.bf16(h1 + e) != c["h1q"]) | (mlp.bf16(h1 - e) != c["h1q"])
+    # ds/dh1q_j = sum_k w3_k gelu'(z2_k) W2_kj; one BF16 step of h1 at j
+    ds = (mlp.gelu_grad(c["z2"]) * p["w3"]) @ p["W2"]
+    step = 2.0 ** (np.floor(np.log2(np.maximum(np.abs(h1) + e, 1e-30))) - 7)
+    flip = np.sum(np.where(near, np.abs(ds) * step, 0.0), axis=1)
+    return s, bound, bound + flip, near.any(axis=1)
+
+
 @pytest.mark.parametrize("n", [32, 1000, 4099])
 def test_mlp_forward_matches_oracle(P, n):
     theta = _theta(11)
-    X = np.random.default_rng(n).normal(0, 1.5, (n, mlp.NIN))
+    X = np.random.default_rng(n).normal(0, 1.5, (n, mlp.NIN)).astype(np.float32)
     m = P.bvmv_mlp_create(theta)
     s = torch.empty(n, device=DEV)
     P.bvmv_mlp_forward(m, _dev(X), s)
     torch.cuda.synchronize()
-    so, _ = mlp.forward(theta, X.astype(np.float32), quantize=True)
+    so, b32, bound, near = _forward_bound(theta, X)
     sg = s.cpu().numpy().astype(np.float64)
+    err = np.abs(sg - so)
+    # every row within its bound: FP32 sums and GELU, plus one BF16 step for
+    # each h1 next to a rounding boundary; rows with no such h1 within the
+    # FP32 part alone; and a rounding that does go the other way is rare
+    assert np.all(err <= bound), (np.max(err / bound), int(np.argmax(err / bound)))
+    assert np.all(err[~near] <= b32[~near])
+    assert np.mean(err > b32) < 0.05
     assert np.max(np.abs(sg - so) / (1 + np.abs(so))) < 1e-3
     # deterministic
     s2 = torch.empty(n, device=DEV)
@@ -151,8 +193,8 @@ def test_adam_step_matches_oracle(P):
     # the BF16 copies follow the master weights: forward equals the oracle on them
     s = torch.empty(n, device=DEV)
     P.bvmv_mlp_forward(m, X, s)
-    so, _ = mlp.forward(th, X.cpu().numpy(), quantize=True)
-    assert np.max(np.abs(s.cpu().numpy() - so) / (1 + np.abs(so))) < 1e-3
+    so, _, bound, _ = _forward_bound(th, X.cpu().numpy())
+    assert np.all(np.abs(s.cpu().numpy().astype(np.float64) - so) <= bound)
 
 
 def _zero_theta():
