@@ -5,7 +5,12 @@ CSR adjacency lists), encodes them into the project's BV-style bitstream (the
 input format of ``bvmv_load``) and draws the vectors the workloads use.  Both
 sides decode the bitstream with decoders of their own.
 
-The native part (``gen.c``) is plain C built with gcc; see ``build()``.
+It also produces the input of the biclique product: a decomposition of the
+edges into bicliques plus residual edges, mined from a graph
+(``biclique_mine``, ``biclique.c``) or planted (``planted_bicliques``).
+
+The native part (``gen.c``, ``biclique.c``) is plain C built with gcc; see
+``build()``.
 """
 from __future__ import annotations
 
@@ -22,12 +27,13 @@ _lib = None
 
 
 def build(force: bool = True) -> str:
-    """Compile gen.c into libbvinputs.so (host C, gcc -O3, pthreads)."""
+    """Compile gen.c and biclique.c into libbvinputs.so (host C, gcc -O3,
+    pthreads)."""
     if force or not os.path.exists(_SO):
-        src = os.path.join(_HERE, "gen.c")
+        srcs = [os.path.join(_HERE, "gen.c"), os.path.join(_HERE, "biclique.c")]
         tmp = _SO + ".tmp%d" % os.getpid()
         subprocess.check_call(["gcc", "-O3", "-std=c11", "-fPIC", "-shared", "-pthread",
-                               "-Wall", "-Wno-unused-variable", src, "-o", tmp, "-lm"])
+                               "-Wall", "-Wno-unused-variable"] + srcs + ["-o", tmp, "-lm"])
         os.replace(tmp, _SO)
     return _SO
 
@@ -54,6 +60,11 @@ def _load():
                                ctypes.c_int, ctypes.c_int, ctypes.c_int64, ctypes.c_int,
                                P(P(ctypes.c_uint8)), P(ctypes.c_int64), ctypes.c_void_p]
     lib.bvi_encode.restype = ctypes.c_int
+    lib.bvi_biclique_mine.argtypes = [ctypes.c_int64, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int, ctypes.c_int,
+                                      ctypes.c_int64, ctypes.c_int, P(ctypes.c_int64),
+                                      P(P(ctypes.c_uint64)), P(P(ctypes.c_uint32)), P(P(ctypes.c_uint64)),
+                                      P(P(ctypes.c_uint32)), P(P(ctypes.c_uint64)), P(P(ctypes.c_uint32))]
+    lib.bvi_biclique_mine.restype = ctypes.c_int
     lib.bvi_free.argtypes = [ctypes.c_void_p]
     lib.bvi_free.restype = None
     _lib = lib
@@ -245,6 +256,106 @@ def workload_graph(name: str, n: int | None = None) -> Graph:
     if w["kind"] == "web":
         return web_graph(w["n"], w["mean"], w["seed"])
     return social_graph(w["n"], w["mean"], w["max_deg"], w["exponent"], w["seed"])
+
+
+# ----------------------------------------------------- biclique decomposition
+@dataclass
+class Bicliques:
+    """Edges of an n-node graph as bicliques plus residual edges (the input of
+    the biclique product).  Biclique r: every node of S_r =
+    sidx[sptr[r]:sptr[r+1]] points to every node of C_r =
+    cidx[cptr[r]:cptr[r+1]] (both ascending); residual edges as CSR (rptr
+    n+1, rcol ascending per row).  Every edge lies in exactly one biclique or
+    in the residual."""
+    n: int
+    sptr: np.ndarray
+    sidx: np.ndarray
+    cptr: np.ndarray
+    cidx: np.ndarray
+    rptr: np.ndarray
+    rcol: np.ndarray
+
+    @property
+    def nbic(self) -> int:
+        return int(self.sptr.shape[0] - 1)
+
+    def words(self) -> int:
+        """Stored ids: sum |S_r| + |C_r| over bicliques, plus residual edges."""
+        return int(self.sidx.size + self.cidx.size + self.rcol.size)
+
+    def biclique(self, r: int):
+        return (self.sidx[int(self.sptr[r]):int(self.sptr[r + 1])],
+                self.cidx[int(self.cptr[r]):int(self.cptr[r + 1])])
+
+
+def biclique_mine(g: Graph, window: int = 8, cmin: int = 2, block: int = 4096, nthreads: int = 8) -> Bicliques:
+    """Greedy biclique decomposition of g (see biclique.c): rows seed
+    bicliques grown from the next `window` rows while |S||C| - |S| - |C|
+    grows; independent blocks of `block` rows."""
+    lib = _load()
+    rowptr = np.ascontiguousarray(g.rowptr, dtype=np.uint64)
+    col = np.ascontiguousarray(g.col, dtype=np.uint32)
+    if col.size == 0:
+        col = np.zeros(1, dtype=np.uint32)
+    nb = ctypes.c_int64()
+    ptrs = [ctypes.POINTER(ctypes.c_uint64)(), ctypes.POINTER(ctypes.c_uint32)(),
+            ctypes.POINTER(ctypes.c_uint64)(), ctypes.POINTER(ctypes.c_uint32)(),
+            ctypes.POINTER(ctypes.c_uint64)(), ctypes.POINTER(ctypes.c_uint32)()]
+    rc = lib.bvi_biclique_mine(g.n, rowptr.ctypes.data, col.ctypes.data, window, cmin, block, nthreads,
+                               ctypes.byref(nb), *[ctypes.byref(p) for p in ptrs])
+    if rc != 0:
+        raise RuntimeError("bvi_biclique_mine failed (%d)" % rc)
+    sptr = _take(ptrs[0], nb.value + 1, np.uint64)
+    cptr = _take(ptrs[2], nb.value + 1, np.uint64)
+    rptr = _take(ptrs[4], g.n + 1, np.uint64)
+    return Bicliques(g.n, sptr, _take(ptrs[1], int(sptr[-1]), np.uint32), cptr,
+                     _take(ptrs[3], int(cptr[-1]), np.uint32), rptr, _take(ptrs[5], int(rptr[-1]), np.uint32))
+
+
+def planted_bicliques(n: int, nbic: int, s_range=(2, 8), c_range=(2, 16), res_mean: float = 3.0, seed: int = 0,
+                      spread: int = 4):
+    """A graph built from planted bicliques plus residual edges, and that
+    decomposition.  Biclique r: |S_r|, |C_r| uniform in the given ranges,
+    each set a sample of distinct ids from a range of `spread` times its size
+    at a uniform offset; a column that one of S_r's rows already points to
+    is dropped from C_r (the edges stay a partition), and a biclique left
+    with no column is dropped.  Residual: 1 + Poisson(res_mean - 1) targets
+    per node near it (geometric gaps, mean 8), edges already present
+    skipped.  For small n (Python loops).  Returns (Graph, Bicliques)."""
+    rng = np.random.default_rng(seed)
+    rows = [set() for _ in range(n)]
+    S_l, C_l = [], []
+    for _ in range(nbic):
+        s = int(rng.integers(s_range[0], s_range[1] + 1))
+        c = int(rng.integers(c_range[0], c_range[1] + 1))
+        s, c = min(s, n), min(c, n)
+        a = int(rng.integers(0, max(1, n - spread * s + 1)))
+        b = int(rng.integers(0, max(1, n - spread * c + 1)))
+        S = np.sort(rng.choice(np.arange(a, min(n, a + spread * s)), size=s, replace=False))
+        C = np.sort(rng.choice(np.arange(b, min(n, b + spread * c)), size=c, replace=False))
+        C = np.array([j for j in C if all(int(j) not in rows[int(i)] for i in S)], dtype=np.int64)
+        if C.size == 0:
+            continue
+        for i in S:
+            rows[int(i)].update(int(j) for j in C)
+        S_l.append(S)
+        C_l.append(C)
+    res = [[] for _ in range(n)]
+    for i in range(n):
+        k = 1 + int(rng.poisson(max(res_mean - 1.0, 0.0))) if res_mean > 0 else 0
+        j = i - 12 + int(rng.geometric(1.0 / 8.0))
+        for _ in range(k):
+            jj = j % n
+            if jj not in rows[i]:
+                rows[i].add(jj)
+                res[i].append(jj)
+            j += int(rng.geometric(1.0 / 8.0))
+    g = from_lists([sorted(r) for r in rows])
+    cnt = lambda L: np.concatenate([[0], np.cumsum([len(x) for x in L])]).astype(np.uint64)
+    cat = lambda L: (np.concatenate(L) if L else np.zeros(0)).astype(np.uint32)
+    res = [sorted(r) for r in res]
+    return g, Bicliques(n, cnt(S_l), cat(S_l), cnt(C_l), cat(C_l), cnt(res),
+                        cat([np.asarray(r, dtype=np.int64) for r in res]))
 
 
 # ------------------------------------------------------- network parameters
