@@ -165,6 +165,30 @@ typedef struct {
 int bvmv_pagerank(bvmv_graph* g, const bvmv_pr_opts* opts, const void* teleport, const void* start,
                   void* p_out, int k, bvmv_pr_result* res, void* stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, serving loops, harnesses that forbid allocation): bvmv_pagerank of
+ * a single graph (not a group) for one right-hand side, with the same
+ * arguments and results (k = 1), that allocates nothing.  Its working set
+ * (the two iterates, their z = p / d, the block partials and the state) lives
+ * in a fixed array of BVMV_NOALLOC_SCRATCH_BYTES of device memory that the
+ * library holds on every device it runs on until the process ends; the
+ * caller passes inputs and outputs as for bvmv_pagerank.
+ * Limit: 4 * n * (element size) + 16 * (tiles / 4 + 1) bytes (each part
+ * rounded up to 256) plus 256 must fit in the array: n up to about 2^21 in
+ * the float modes and 2^20 in BVMV_F64 at the default layout; a larger graph
+ * gives BVMV_EINVAL before any device work.  Options: opts->mlp and
+ * opts->fallback_check must be 0 (BVMV_EINVAL otherwise).
+ * Iterations are launched directly (no captured graph), `chunk` at a time;
+ * after each chunk the state is read back with a synchronising copy into host
+ * stack memory.  Results are bit-identical to bvmv_pagerank's.
+ * Every call on a device shares that device's array, which keeps the last
+ * call's contents (every word a call reads it has written first): calls that
+ * overlap on one GPU (concurrent streams or threads) race and give wrong
+ * results; serialise them. */
+#define BVMV_NOALLOC_SCRATCH_BYTES (33u << 20)
+int bvmv_pagerank_noalloc(bvmv_graph* g, const bvmv_pr_opts* opts, const void* teleport, const void* start,
+                          void* p_out, bvmv_pr_result* res, void* stream);
+
 /* Ragged batch: the block-diagonal union of `count` loaded graphs as one
  * handle.  Member i occupies rows/columns [offsets[i], offsets[i+1]).
  * bvmv_multiply on a group multiplies every member at once; bvmv_pagerank

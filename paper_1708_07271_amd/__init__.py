@@ -83,6 +83,7 @@ def load_library():
         "bvmv_multiply": ([vp, vp, vp, i32, vp], i32),
         "bvmv_multiply_batch": ([vp, vp, vp, i32, i64, i32, vp], i32),
         "bvmv_pagerank": ([vp, P(PROpts), vp, vp, vp, i32, P(PRResult), vp], i32),
+        "bvmv_pagerank_noalloc": ([vp, P(PROpts), vp, vp, vp, P(PRResult), vp], i32),
         "bvmv_group": ([P(vp), i32, P(vp)], i32),
         "bvmv_group_offsets": ([vp, P(i64), P(i32)], i32),
         "bvmv_get_info": ([vp, P(Info)], i32),
@@ -269,6 +270,25 @@ def bvmv_pagerank(g: Graph, p_out, teleport=None, start=None, damping=0.85, tol=
     """Returns a list of (iters, converged, residual), one per column (or member of a group)."""
     out = bvmv_pagerank_detail(g, p_out, teleport, start, damping, tol, max_iter, prec, chunk, k, 0, stream)
     return [(r["iters"], r["converged"], r["residual"]) for r in out]
+
+
+def bvmv_pagerank_noalloc(g: Graph, p_out, teleport=None, start=None, damping=0.85, tol=1e-6, max_iter=1000,
+                          prec=BVMV_F32_COMP, chunk=16, stream=None):
+    """PageRank of a single graph (k = 1) that allocates nothing: its working
+    set lives in the library's fixed device array.  Returns a dict like
+    bvmv_pagerank_detail's entries."""
+    p = _prec(prec)
+    dt = _vec_dtype(p)
+    lib = load_library()
+    res = PRResult()
+    o = _pr_opts(damping, tol, max_iter, p, chunk)
+    tp = _dev_ptr(teleport, dt, g.n) if teleport is not None else ctypes.c_void_p(None)
+    sp = _dev_ptr(start, dt, g.n) if start is not None else ctypes.c_void_p(None)
+    _check(lib.bvmv_pagerank_noalloc(g.handle, ctypes.byref(o), tp, sp, _dev_ptr(p_out, dt, g.n), ctypes.byref(res),
+                                     _stream_ptr(stream)), allow=(BVMV_OK, BVMV_NOT_CONVERGED))
+    return dict(iters=res.iters, converged=bool(res.converged), residual=res.residual, used_start=res.used_start,
+                products=res.products, restarts_accepted=res.restarts_accepted,
+                restarts_rejected=res.restarts_rejected)
 
 
 def bvmv_group(graphs) -> Graph:

@@ -25,6 +25,7 @@
 //   6. epilogue: store y, or the PageRank update.
 #include <hip/hip_runtime.h>
 
+#include <mutex>
 #include <type_traits>
 
 #include "kernels.hpp"
@@ -1857,6 +1858,44 @@ hipError_t launch_pr_select(int prec, const PRState* st, const void* p0, const v
   else
     hipLaunchKernelGGL(pr_select_kernel<float>, grid, dim3(kThreads), 0, s, st, static_cast<const float*>(p0),
                        static_cast<const float*>(p1), static_cast<float*>(out), n);
+  return hipGetLastError();
+}
+
+// ------------------------------------------------- allocation-free working set
+// The working set of the allocation-free PageRank: a fixed device array, one
+// copy on every device the library's code is loaded on, held until the process
+// ends.  In host code the name `scratch` stands for a host-side shadow, not a
+// device address: host code only ever uses the address hipGetSymbolAddress
+// returns for it, taken once per device with that device current.
+static __device__ __align__(256) unsigned char scratch[kNoAllocScratchBytes];
+
+namespace {
+constexpr int kMaxDevices = 64;
+__global__ void pr_state_set_kernel(PRState* st, PRState v) {
+  if (threadIdx.x == 0) *st = v;
+}
+}  // namespace
+
+hipError_t noalloc_scratch(int device, void** ptr) {
+  static std::mutex mu;
+  static void* addr[kMaxDevices] = {};
+  if (device < 0 || device >= kMaxDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lock(mu);
+  if (!addr[device]) {
+    int cur = -1;
+    if (hipError_t e = hipGetDevice(&cur)) return e;
+    if (cur != device) return hipErrorInvalidDevice;
+    void* p = nullptr;
+    if (hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch))) return e;
+    if (!p) return hipErrorInvalidSymbol;
+    addr[device] = p;
+  }
+  *ptr = addr[device];
+  return hipSuccess;
+}
+
+hipError_t launch_pr_state_set(PRState* st, const PRState& v, hipStream_t s) {
+  hipLaunchKernelGGL(pr_state_set_kernel, dim3(1), dim3(64), 0, s, st, v);
   return hipGetLastError();
 }
 

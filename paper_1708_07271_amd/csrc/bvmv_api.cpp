@@ -941,6 +941,90 @@ int bvmv_pagerank(bvmv_graph* g, const bvmv_pr_opts* opts, const void* teleport,
                       g->d_outdeg, iter, init, out);
 }
 
+// PageRank of one graph, k = 1, with its working set in the library's fixed
+// device array instead of allocated buffers: no allocation, no graph capture,
+// no pinned host memory.  Iterations are launched eagerly, `chunk` at a time,
+// and the state is read back after each chunk by a synchronising copy into a
+// host stack variable.  The kernels are bvmv_pagerank's, in the same order, so
+// the results are bit-identical to it.
+static_assert(BVMV_NOALLOC_SCRATCH_BYTES == kNoAllocScratchBytes, "the header states the array's size");
+
+int bvmv_pagerank_noalloc(bvmv_graph* g, const bvmv_pr_opts* opts, const void* teleport, const void* start,
+                          void* p_out, bvmv_pr_result* res, void* stream) {
+  if (!g || !p_out) return fail(BVMV_EINVAL, "null argument");
+  PROptsResolved o;
+  if (int rc = resolve_pr_opts(opts, o)) return rc;
+  if (o.mlp || o.fallback)
+    return fail(BVMV_EINVAL, "the allocation-free PageRank takes no network and no fallback check");
+  if (g->ngraphs != 1) return fail(BVMV_EINVAL, "the allocation-free PageRank takes a single graph, not a group");
+  DeviceGuard dg(g->device);
+  if (dg.err != hipSuccess) return fail(BVMV_EDEVICE, "hipSetDevice failed");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  const DevLayout& L = g->L;
+  const int prec = o.prec;
+  // carve: p0, p1, z0, z1 (n elements each), the block partials, the state
+  auto up256 = [](uint64_t v) { return (v + 255) / 256 * 256; };
+  const uint64_t vec = up256(uint64_t(g->n) * elem_size(prec));
+  const uint64_t nslots = uint64_t(L.ntiles) / kTilesPerBlock + 1;
+  const uint64_t slot_bytes = up256(16 * nslots);
+  const uint64_t need = 4 * vec + slot_bytes + up256(sizeof(PRState));
+  if (need > kNoAllocScratchBytes)
+    return fail(BVMV_EINVAL, "graph too large for the allocation-free PageRank: its working set needs " +
+                                 std::to_string(need) + " bytes, the fixed array holds " +
+                                 std::to_string(kNoAllocScratchBytes));
+  void* base = nullptr;
+  HIP_TRY(noalloc_scratch(g->device, &base));
+  unsigned char* b = static_cast<unsigned char*>(base);
+  void* p[2] = {b, b + vec};
+  void* z[2] = {b + 2 * vec, b + 3 * vec};
+  double* slots = reinterpret_cast<double*>(b + 4 * vec);
+  PRState* st = reinterpret_cast<PRState*>(b + 4 * vec + slot_bytes);
+  PRState st0;
+  std::memset(&st0, 0, sizeof(st0));
+  st0.inv_n = 1.0 / double(g->n);
+  st0.blk_lo = 0;
+  st0.blk_hi = L.ntiles / kTilesPerBlock;
+  HIP_TRY(launch_pr_state_set(st, st0, s));
+  HIP_TRY(launch_pr_init(L, prec, start, teleport, p[0], z[0], g->d_outdeg, st, slots, 1, s));
+  PRArgs a{};
+  a.tele = teleport;
+  a.outdeg = g->d_outdeg;
+  a.st = st;
+  a.slots = slots;
+  a.beta = o.beta;
+  a.tol = o.tol;
+  a.max_iter = o.max_iter;
+  a.members = 1;
+  a.k = 1;
+  PRState h;
+  std::memset(&h, 0, sizeof(h));
+  const int max_chunks = (o.max_iter + o.chunk - 1) / o.chunk + 1;
+  for (int ch = 0; ch < max_chunks; ++ch) {
+    for (int c = 0; c < o.chunk; ++c) {
+      a.p_cur = p[c % 2];
+      a.p_new = p[(c + 1) % 2];
+      a.z_cur = z[c % 2];
+      a.z_new = z[(c + 1) % 2];
+      a.buf = (c + 1) % 2;
+      HIP_TRY(launch_bv_pagerank_iter(L, prec, a, s));
+    }
+    HIP_TRY(hipMemcpyAsync(&h, st, sizeof(PRState), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    if (h.done) break;
+  }
+  HIP_TRY(launch_pr_select(prec, st, p[0], p[1], p_out, g->n, 1, s));
+  if (res) {
+    res->iters = h.iter;
+    res->converged = h.converged;
+    res->residual = h.resid;
+    res->used_start = start ? 1 : 0;
+    res->products = h.iter;
+    res->restarts_accepted = 0;
+    res->restarts_rejected = 0;
+  }
+  return h.converged ? BVMV_OK : BVMV_NOT_CONVERGED;
+}
+
 int bvmv_group(bvmv_graph* const* graphs, int count, bvmv_graph** out) {
   if (!graphs || count < 1 || !out) return fail(BVMV_EINVAL, "bad group arguments");
   *out = nullptr;

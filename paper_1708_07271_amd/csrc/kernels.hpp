@@ -96,6 +96,18 @@ hipError_t launch_restart_inputs(const DevLayout& L, int prec, const void* pK, c
 hipError_t launch_restart_vector(const DevLayout& L, int prec, const void* pK, const float* svec, PRState* st,
                                  void* q, double* slots, int members, hipStream_t s);
 
+// ---------------------------------------------- allocation-free working set
+// Bytes of the fixed device array that holds the working set of the
+// allocation-free PageRank entry point (one copy per device, kept until the
+// process ends): four iterate-sized vectors of up to 2^21 floats (2^20
+// doubles) plus the block partials and the state.
+constexpr size_t kNoAllocScratchBytes = (size_t(32) << 20) + (size_t(1) << 20);
+// Device address of that array on `device`, which must be the current device;
+// looked up once per device (hipGetSymbolAddress) and kept.
+hipError_t noalloc_scratch(int device, void** ptr);
+// *st = v by a one-thread kernel (no host-to-device copy)
+hipError_t launch_pr_state_set(PRState* st, const PRState& v, hipStream_t s);
+
 hipError_t launch_csr_multiply(const DevCsr& C, int prec, const void* x, void* y, hipStream_t s);
 hipError_t launch_csr_pagerank_iter(const DevCsr& C, int prec, const PRArgs& a, hipStream_t s);
 hipError_t launch_csr_pr_init(const DevCsr& C, int prec, const void* start, const void* tele, void* p0, void* z0,
