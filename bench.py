@@ -224,6 +224,110 @@ def bench_social(args, B, P, np, torch, dev):
     print(json.dumps(out), flush=True)
 
 
+def bench_formats(args, B, P, np, torch, dev):
+    """One product y = A x (FP32 x uniform[0,1), seed 102, two-sum mode) on
+    a workload in three formats on this GPU: the BV-style compressed layout,
+    the biclique decomposition mined from the same graph (Section "Final
+    Remarks"), and plain CSR.  Each launch is timed from HBM (after a 1 GiB
+    device write) and back to back (cache-warm); algorithmic bytes are each
+    layout's bytes plus 8 bytes per node (x read once, y written once)."""
+    wl = args.workload
+    t0 = time.perf_counter()
+    g = B.workload_graph(wl)
+    enc = B.encode(g)
+    G = P.bvmv_load(enc.data, keep_lists=1)
+    del enc
+    C = P.bvmv_csr_create(G)
+    t1 = time.perf_counter()
+    bic = B.biclique_mine(g)
+    t_mine = time.perf_counter() - t1
+    H = P.bvmv_biclique_load(bic)
+    log("formats %s: n=%d m=%d, bicliques %d (%.1fs mining), setup %.1fs" % (
+        wl, g.n, g.m, bic.nbic, t_mine, time.perf_counter() - t0))
+    x = torch.from_numpy(B.uniform_x(g.n, 102, np.float32)).to(dev)
+    y = torch.empty_like(x)
+    prec = P.BVMV_F32_COMP
+    flush = Flusher(torch, dev)
+    info, binfo = G.info(), H.info()
+    rows = {}
+    for name, fn, nbytes in (("bv", lambda: P.bvmv_multiply(G, x, y, prec), info["layout_bytes"]),
+                             ("biclique", lambda: P.bvmv_biclique_multiply(H, x, y, prec), binfo["layout_bytes"]),
+                             ("csr", lambda: P.bvmv_csr_multiply(C, x, y, prec), C.bytes())):
+        ms, _ = time_flushed(fn, args.steps, args.warmup, flush, torch)
+        warm = time_launches(fn, args.steps, args.warmup, torch)
+        alg = nbytes + 8 * g.n
+        rows[name] = {"layout_bytes": nbytes, "bytes_per_edge": nbytes / g.m, "ms": ms,
+                      "edges_per_s": g.m / (ms * 1e-3), "alg_GBs": alg / (ms * 1e-3) / 1e9,
+                      "frac_hbm": alg / (ms * 1e-3) / 1e9 / PEAK_HBM_GBS, "mall_warm_ms": warm}
+        log("%s: %.4f ms from HBM (%.0f GB/s), %.4f ms warm" % (name, ms, rows[name]["alg_GBs"], warm))
+    out = {"mode": "formats", "workload": wl, "n": g.n, "m": g.m, "dtype": "f32 two-sum compensated",
+           "timing": "each launch after a 1 GiB device write; mall_warm_ms back to back",
+           "bv_m_over_m_prime": g.m / max(info["m_prime"], 1),
+           "biclique": {"bicliques": bic.nbic, "s_ids": binfo["s_ids"], "c_ids": binfo["c_ids"],
+                        "residual": binfo["residual"], "words": binfo["words"],
+                        "m_over_words": g.m / max(binfo["words"], 1), "mining_seconds": t_mine},
+           **rows,
+           "speedup_bv_vs_csr": rows["csr"]["ms"] / rows["bv"]["ms"],
+           "speedup_biclique_vs_csr": rows["csr"]["ms"] / rows["biclique"]["ms"]}
+    print(json.dumps(out), flush=True)
+
+
+def bench_sweep(args, B, P, np, torch, dev):
+    """The paper's proposed improvements of the BV method (Section "Final
+    Remarks"): the reference window W (with chain bound R), and splitting
+    the matrix into column blocks compressed apart.  For each setting: bits
+    per edge of the stream, m / m', layout bytes, and one FP32 two-sum
+    product timed from HBM (after a 1 GiB device write) and cache-warm."""
+    wl = args.workload
+    t0 = time.perf_counter()
+    g = B.workload_graph(wl)
+    log("sweep %s: n=%d m=%d (%.1fs)" % (wl, g.n, g.m, time.perf_counter() - t0))
+    x = torch.from_numpy(B.uniform_x(g.n, 102, np.float32)).to(dev)
+    y = torch.empty_like(x)
+    prec = P.BVMV_F32_COMP
+    flush = Flusher(torch, dev)
+    steps, warmup = max(args.steps // 5, 20), max(args.warmup // 5, 5)
+
+    def timed(fn):
+        ms, _ = time_flushed(fn, steps, warmup, flush, torch)
+        return ms, time_launches(fn, steps, warmup, torch)
+
+    windows = []
+    for W, R in ((1, 1), (3, 3), (7, 3), (7, 7), (15, 3), (15, 15)):
+        enc = B.encode(g, W=W, R=R)
+        G = P.bvmv_load(enc.data)
+        info = G.info()
+        ms, warm = timed(lambda: P.bvmv_multiply(G, x, y, prec))
+        windows.append({"W": W, "R": R, "bits_per_edge": enc.data.size * 8.0 / g.m,
+                        "m_over_m_prime": g.m / max(info["m_prime"], 1), "layout_bytes": info["layout_bytes"],
+                        "escapes": info["escapes"], "ms": ms, "mall_warm_ms": warm,
+                        "edges_per_s": g.m / (ms * 1e-3)})
+        log("W=%d R=%d: %.3f bits/edge, m/m' %.3f, %.4f ms (warm %.4f)" % (
+            W, R, windows[-1]["bits_per_edge"], windows[-1]["m_over_m_prime"], ms, warm))
+        del G, enc
+    blocks = []
+    for nb in (1, 2, 4, 8):
+        bounds, parts = B.column_blocks(g, nb)
+        encs = [B.encode(p_) for p_ in parts]
+        Gs = [P.bvmv_load(e.data) for e in encs]
+        H = P.bvmv_colblocks_create(Gs)
+        infos = [G_.info() for G_ in Gs]
+        mp = sum(i["m_prime"] for i in infos)
+        lb = sum(i["layout_bytes"] for i in infos)
+        ms, warm = timed(lambda: P.bvmv_colblocks_multiply(H, x, y, prec))
+        blocks.append({"blocks": nb, "bits_per_edge": sum(e.data.size for e in encs) * 8.0 / g.m,
+                       "m_over_m_prime": g.m / max(mp, 1), "layout_bytes": lb,
+                       "escapes": sum(i["escapes"] for i in infos), "ms": ms, "mall_warm_ms": warm,
+                       "edges_per_s": g.m / (ms * 1e-3), "alg_GBs": (lb + 4 * g.n * (nb + 1)) / (ms * 1e-3) / 1e9})
+        log("%d column blocks: %.3f bits/edge, m/m' %.3f, layout %.1f MB, %.4f ms (warm %.4f)" % (
+            nb, blocks[-1]["bits_per_edge"], blocks[-1]["m_over_m_prime"], lb / 1e6, ms, warm))
+        del H, Gs, encs, parts
+    out = {"mode": "window-and-column-block-sweep", "workload": wl, "n": g.n, "m": g.m,
+           "dtype": "f32 two-sum compensated", "timing": "each launch after a 1 GiB device write",
+           "windows": windows, "column_blocks": blocks}
+    print(json.dumps(out), flush=True)
+
+
 def ragged_encs(B, np):
     """The 48 ragged web-like graphs: n_g = round(10^(4 + 2 u_g)), u_g uniform
     from seed 999, mean out-degree 20, graph seeds 1000 + g (bitstreams)."""
@@ -432,6 +536,11 @@ def main():
                     help="social-like workload (n = 4e6): FP32 error against the FP64 oracle, compressed vs CSR")
     ap.add_argument("--ragged", action="store_true",
                     help="ragged batch of 48 graphs: solo against grouped PageRank, fixed against autotuned layouts")
+    ap.add_argument("--formats", action="store_true",
+                    help="one product of --workload in three formats: BV compressed, mined bicliques, CSR "
+                         "(flushed and cache-warm)")
+    ap.add_argument("--sweep", action="store_true",
+                    help="reference window W (and chain bound R) sweep and column-block splitting of --workload")
     ap.add_argument("--warm-graphs", type=int, default=200)
     ap.add_argument("--warm-steps", type=int, default=3000)
     ap.add_argument("--warm-test-n", type=int, default=5_000_000)
@@ -471,6 +580,10 @@ def main():
         return bench_ragged(args, B, P, np, torch, dev)
     if args.social:
         return bench_social(args, B, P, np, torch, dev)
+    if args.formats:
+        return bench_formats(args, B, P, np, torch, dev)
+    if args.sweep:
+        return bench_sweep(args, B, P, np, torch, dev)
     t0 = time.perf_counter()
     g = B.workload_graph(args.workload)
     enc = B.encode(g)

@@ -258,6 +258,26 @@ def workload_graph(name: str, n: int | None = None) -> Graph:
     return social_graph(w["n"], w["mean"], w["max_deg"], w["exponent"], w["seed"])
 
 
+# ------------------------------------------------------------ column blocks
+def column_blocks(g: Graph, nblocks: int):
+    """Split g's columns into nblocks ranges of consecutive ids of (nearly)
+    equal width: block b keeps, in every row, the ids in [c_b, c_{b+1}),
+    c_b = floor(b n / nblocks).  Each block is an n-row graph with absolute
+    column ids (encode it like any graph).  Returns (bounds, [Graph])."""
+    n = g.n
+    bounds = [(b * n) // nblocks for b in range(nblocks + 1)]
+    col = np.asarray(g.col, dtype=np.int64)
+    rowid = np.repeat(np.arange(n, dtype=np.int64), np.diff(g.rowptr.astype(np.int64)))
+    out = []
+    for b in range(nblocks):
+        keep = (col >= bounds[b]) & (col < bounds[b + 1])
+        cnt = np.bincount(rowid[keep], minlength=n)
+        rp = np.zeros(n + 1, dtype=np.uint64)
+        np.cumsum(cnt, out=rp[1:])
+        out.append(Graph(rp, g.col[keep].copy()))
+    return bounds, out
+
+
 # ----------------------------------------------------- biclique decomposition
 @dataclass
 class Bicliques:

@@ -103,6 +103,23 @@ int bvmv_load(const void* bitstream, size_t nbytes, const bvmv_load_opts* opts, 
  * magnitude of the window's prefix sums (tested to 1e-3). */
 int bvmv_multiply(bvmv_graph* g, const void* x, void* y, int prec, void* stream);
 
+/* y = x A, the left product (Section "PageRank" multiplies the row vector
+ * p by M), computed on the loaded rows without the transposed graph: with
+ * R the references (R_ik = 1 iff r_i = k), A = (I - R)^{-1} A', so
+ * x A = c A' with c_k = x_k + the sum of c_i over the rows i that reference
+ * k (Proposition of Section "Our Approach", read backwards).  Per tile, c
+ * is resolved level by level from the deepest, A' is read column-wise
+ * (interval entries as a difference array over the window), and each tile
+ * writes its window's contribution; a second launch sums, for every column,
+ * the contributions of the tiles whose window covers it and the entries
+ * outside the windows, in a fixed order.  x, y: device vectors of n
+ * elements (double for BVMV_F64, float otherwise), not overlapping.
+ * Deterministic.  A single graph (not a group).  The first call builds the
+ * column-wise layout (host work and device allocations, kept with the
+ * graph); products on one graph must not overlap in time (they share its
+ * buffers). */
+int bvmv_multiply_left(bvmv_graph* g, const void* x, void* y, int prec, void* stream);
+
 /* Y = A X for k right-hand sides at once (the product of the Proposition of
  * Section "Our Approach" applied to each column; Section "PageRank" needs one
  * per personalized start vector p_0): every tile of the layout is decoded
@@ -249,6 +266,65 @@ int bvmv_csr_pagerank(bvmv_csr* c, const bvmv_pr_opts* opts, const void* telepor
 int64_t bvmv_csr_bytes(const bvmv_csr* c);
 void bvmv_csr_free(bvmv_csr* c);
 
+/* Column blocks (Section "Final Remarks": splitting the matrix into
+ * submatrices of consecutive columns, so that a row's reference need not
+ * match the whole row).  Each block A_b (rows restricted to a column range)
+ * is loaded as a graph of its own with bvmv_load: same n, its own references
+ * and tiles.  bvmv_colblocks_multiply computes y = sum_b A_b x: the first
+ * block stores y, each later one adds its rows' sums to y (in the vector
+ * type, after the block's own accumulation), in block order, so the result
+ * is deterministic.  The blocks stay owned by the caller and must outlive the
+ * handle.  BVMV_EINVAL for a null pointer, a group, or blocks of different n
+ * or device.  Only products are defined on the handle. */
+typedef struct bvmv_colblocks bvmv_colblocks;
+int bvmv_colblocks_create(bvmv_graph* const* blocks, int count, bvmv_colblocks** out);
+int bvmv_colblocks_multiply(bvmv_colblocks* c, const void* x, void* y, int prec, void* stream);
+void bvmv_colblocks_free(bvmv_colblocks* c);
+
+/* ---------------------------------------------------------------------------
+ * Biclique format (Section "Final Remarks", after Hernandez and Navarro's
+ * biclique extraction): the edges of G split into bicliques (S_r, C_r) --
+ * every node of S_r points to every node of C_r, |S_r| |C_r| edges stored as
+ * the |S_r| + |C_r| ids of the two sets -- plus residual edges.  The product
+ * takes c_r = sum_{j in C_r} x_j for every biclique, then
+ * y_i = sum_{r : i in S_r} c_r + sum_{j : (i, j) residual} x_j, in time
+ * proportional to the stored ids.
+ * ------------------------------------------------------------------------- */
+typedef struct bvmv_biclique bvmv_biclique;
+
+/* Build the device layout of a biclique decomposition of an n-node graph.
+ * All arrays are HOST arrays, copied (the caller keeps them):
+ *   sptr[nbic+1], sidx: S_r = sidx[sptr[r] .. sptr[r+1]);
+ *   cptr[nbic+1], cidx: C_r = cidx[cptr[r] .. cptr[r+1]);
+ *   rptr[n+1], rcol: residual edges (i, j), j in rcol[rptr[i] .. rptr[i+1]).
+ * Every set and residual row strictly increasing with ids below n; offsets
+ * start at 0 and do not decrease; empty sets are allowed.  The bicliques and
+ * the residual must partition the edges (no edge listed twice).
+ * Errors: BVMV_EINVAL (null pointers, n < 1, n + nbic >= 2^32 - 1, more than
+ * 2^32 - 1 stored ids or edges), BVMV_EFORMAT (unsorted or out-of-range
+ * ids, bad offsets, an edge listed twice), BVMV_ENOMEM, BVMV_EDEVICE.
+ * Synchronous.  The layout holds a device array of the nbic sums c_r, so
+ * products on one handle must not overlap in time (one stream at a time). */
+int bvmv_biclique_load(int64_t n, int64_t nbic, const uint64_t* sptr, const uint32_t* sidx, const uint64_t* cptr,
+                       const uint32_t* cidx, const uint64_t* rptr, const uint32_t* rcol, int device,
+                       bvmv_biclique** out);
+/* y = A x on the biclique layout (two launches on `stream`: the sums c_r,
+ * then the rows).  x, y: device vectors of n elements (double for BVMV_F64,
+ * float otherwise), not overlapping.  Row partials accumulate as in
+ * bvmv_multiply (double in BVMV_F64 and BVMV_F32_COMP); c_r is stored in the
+ * vector type.  Deterministic. */
+int bvmv_biclique_multiply(bvmv_biclique* b, const void* x, void* y, int prec, void* stream);
+typedef struct {
+  int64_t n, m;         /* nodes, edges of the graph the decomposition represents */
+  int64_t nbic;         /* bicliques */
+  int64_t s_ids, c_ids; /* stored ids: sum |S_r|, sum |C_r| */
+  int64_t residual;     /* residual edges */
+  int64_t words;        /* s_ids + c_ids + residual (the paper's compressed size in words) */
+  int64_t layout_bytes; /* device bytes of the two passes' ids, offsets and tiles */
+} bvmv_biclique_info;
+int bvmv_biclique_get_info(const bvmv_biclique* b, bvmv_biclique_info* out);
+void bvmv_biclique_free(bvmv_biclique* b);
+
 /* Host interpretation of the device layout that bvmv_load would build from
  * this bitstream and options, in double precision: y = A x with x and y HOST
  * arrays of n doubles.  A test aid for the layout builder (no device
@@ -258,6 +334,13 @@ void bvmv_csr_free(bvmv_csr* c);
  * inconsistent. */
 int bvmv_layout_selfcheck(const void* bitstream, size_t nbytes, const bvmv_load_opts* opts, const double* x,
                           double* y, int64_t* stats);
+
+/* Host interpretation of the left product's column-wise layout
+ * (bvmv_multiply_left), in double precision: y = x A with x and y HOST
+ * arrays of n doubles.  A test aid (no device needed); BVMV_EINVAL if the
+ * layout is inconsistent. */
+int bvmv_left_selfcheck(const void* bitstream, size_t nbytes, const bvmv_load_opts* opts, const double* x,
+                        double* y);
 
 /* ---------------------------------------------------------------------------
  * Learned PageRank warm restarts (not in the paper; its PageRank starts from

@@ -9,5 +9,7 @@ Modules:
   product   - y = A x (plain definition) and the paper's sequential reuse
               algorithm on the difference form (A', r)
   pagerank  - power method, Eq. (1) of the paper, and a dense solve
+  biclique  - the biclique format of Section "Final Remarks": the lists it
+              stands for, and the paper's two-step product
 """
-from . import bvdecode, pagerank, product  # noqa: F401
+from . import biclique, bvdecode, pagerank, product  # noqa: F401

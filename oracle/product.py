@@ -14,6 +14,10 @@ form (A', r) (Section "Our Approach", the three-step algorithm after the
 Proposition, with the fallback rule of Section "Experimental Evaluation"
 that keeps v_i whenever |v_i - v_{r_i}| >= |v_i|).  It serves as a second,
 independent route that pins the Proposition, not as the reference result.
+
+`left_matvec` is the left product y = x A of PageRank's p M (Section
+"PageRank"), by its definition; `left_reuse_product` reaches it through the
+same difference form, x A = x (I - R)^{-1} A'.
 """
 from __future__ import annotations
 
@@ -106,4 +110,49 @@ def reuse_product(r, plus, minus, x):
     for i in range(n):
         base = y[r[i]] if r[i] >= 0 else 0.0
         y[i] = base + math.fsum(x[plus[i]].tolist()) - math.fsum(x[minus[i]].tolist())
+    return y
+
+
+# ------------------------------------------------------------ left products
+# PageRank multiplies a row vector by the matrix (Section "PageRank", p M):
+# the left product y = x A, y_j = sum over the rows i that list j of x_i.
+
+def left_matvec(rowptr, col, x):
+    """y = x A in float64: each column's terms summed in ascending row order."""
+    n = len(rowptr) - 1
+    x = np.asarray(x, dtype=np.float64)
+    rows = np.repeat(np.arange(n, dtype=np.int64), np.diff(np.asarray(rowptr, dtype=np.int64)))
+    return np.bincount(np.asarray(col, dtype=np.int64), weights=x[rows], minlength=n).astype(np.float64)
+
+
+def left_matvec_exact(rowptr, col, x):
+    """y = x A, each column correctly rounded (math.fsum over its rows)."""
+    n = len(rowptr) - 1
+    x = np.asarray(x, dtype=np.float64)
+    terms = [[] for _ in range(n)]
+    for i in range(n):
+        for j in col[int(rowptr[i]):int(rowptr[i + 1])].tolist():
+            terms[j].append(x[i])
+    return np.array([math.fsum(t) for t in terms], dtype=np.float64)
+
+
+def left_reuse_product(r, plus, minus, x):
+    """x A through the difference form (A', r): row i of A is row i of A' plus
+    row r_i of A, so A = (I - R)^{-1} A' with R_ik = [r_i = k], and
+    x A = c A' with c = x (I - R)^{-1}, i.e. c_k = x_k + the sum of c_i over
+    the rows i that reference k; since r_i < i, c is final once taken from
+    the last row down.  Then y_j = sum_i c_i A'_ij: +c_i on the entries row i
+    adds, -c_i on the reference entries it drops."""
+    x = np.asarray(x, dtype=np.float64)
+    n = len(r)
+    c = x.copy()
+    for i in range(n - 1, -1, -1):
+        if r[i] >= 0:
+            c[r[i]] += c[i]
+    y = np.zeros(n, dtype=np.float64)
+    for i in range(n):
+        for j in plus[i]:
+            y[j] += c[i]
+        for j in minus[i]:
+            y[j] -= c[i]
     return y

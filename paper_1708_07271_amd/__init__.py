@@ -50,6 +50,11 @@ class PRResult(ctypes.Structure):
                 ("restarts_rejected", ctypes.c_int)]
 
 
+class BicliqueInfo(ctypes.Structure):
+    _fields_ = [(f, ctypes.c_int64) for f in ("n", "m", "nbic", "s_ids", "c_ids", "residual", "words",
+                                               "layout_bytes")]
+
+
 NFEAT = 12
 MLP_PARAMS = 5057
 
@@ -82,8 +87,16 @@ def load_library():
         "bvmv_load": ([vp, sz, P(LoadOpts), P(vp)], i32),
         "bvmv_multiply": ([vp, vp, vp, i32, vp], i32),
         "bvmv_multiply_batch": ([vp, vp, vp, i32, i64, i32, vp], i32),
+        "bvmv_multiply_left": ([vp, vp, vp, i32, vp], i32),
         "bvmv_pagerank": ([vp, P(PROpts), vp, vp, vp, i32, P(PRResult), vp], i32),
         "bvmv_pagerank_noalloc": ([vp, P(PROpts), vp, vp, vp, P(PRResult), vp], i32),
+        "bvmv_colblocks_create": ([P(vp), i32, P(vp)], i32),
+        "bvmv_colblocks_multiply": ([vp, vp, vp, i32, vp], i32),
+        "bvmv_colblocks_free": ([vp], None),
+        "bvmv_biclique_load": ([i64, i64, vp, vp, vp, vp, vp, vp, i32, P(vp)], i32),
+        "bvmv_biclique_multiply": ([vp, vp, vp, i32, vp], i32),
+        "bvmv_biclique_get_info": ([vp, P(BicliqueInfo)], i32),
+        "bvmv_biclique_free": ([vp], None),
         "bvmv_group": ([P(vp), i32, P(vp)], i32),
         "bvmv_group_offsets": ([vp, P(i64), P(i32)], i32),
         "bvmv_get_info": ([vp, P(Info)], i32),
@@ -98,6 +111,7 @@ def load_library():
         "bvmv_csr_free": ([vp], None),
         "bvmv_free": ([vp], None),
         "bvmv_layout_selfcheck": ([vp, sz, P(LoadOpts), vp, vp, vp], i32),
+        "bvmv_left_selfcheck": ([vp, sz, P(LoadOpts), vp, vp], i32),
         "bvmv_features": ([vp, vp, vp], i32),
         "bvmv_mlp_create": ([i32, vp, P(vp)], i32),
         "bvmv_mlp_params": ([vp, vp], i32),
@@ -215,6 +229,14 @@ def bvmv_multiply(g: Graph, x, y, prec=BVMV_F32_COMP, stream=None):
                                         _stream_ptr(stream)))
 
 
+def bvmv_multiply_left(g: Graph, x, y, prec=BVMV_F32_COMP, stream=None):
+    """y = x A (the left product) on the loaded rows."""
+    p = _prec(prec)
+    dt = _vec_dtype(p)
+    _check(load_library().bvmv_multiply_left(g.handle, _dev_ptr(x, dt, g.n), _dev_ptr(y, dt, g.n), p,
+                                             _stream_ptr(stream)))
+
+
 def bvmv_multiply_batch(g: Graph, X, Y, prec=BVMV_F32_COMP, stream=None):
     """X, Y: (k, n) device tensors, row c = right-hand side c (the column-major
     n x k blocks of the C interface).  Rows may be views into longer rows:
@@ -289,6 +311,80 @@ def bvmv_pagerank_noalloc(g: Graph, p_out, teleport=None, start=None, damping=0.
     return dict(iters=res.iters, converged=bool(res.converged), residual=res.residual, used_start=res.used_start,
                 products=res.products, restarts_accepted=res.restarts_accepted,
                 restarts_rejected=res.restarts_rejected)
+
+
+class ColBlocks:
+    """Handle of column blocks; keeps the member graphs alive."""
+
+    def __init__(self, handle, n, blocks):
+        self._h = handle
+        self.n = n
+        self.blocks = list(blocks)
+
+    @property
+    def handle(self):
+        return self._h
+
+    def __del__(self):
+        if getattr(self, "_h", None) and _lib is not None:
+            _lib.bvmv_colblocks_free(self._h)
+            self._h = None
+
+
+def bvmv_colblocks_create(blocks) -> ColBlocks:
+    arr = (ctypes.c_void_p * len(blocks))(*[b.handle.value for b in blocks])
+    h = ctypes.c_void_p()
+    _check(load_library().bvmv_colblocks_create(arr, len(blocks), ctypes.byref(h)))
+    return ColBlocks(h, blocks[0].n, blocks)
+
+
+def bvmv_colblocks_multiply(c: ColBlocks, x, y, prec=BVMV_F32_COMP, stream=None):
+    p = _prec(prec)
+    dt = _vec_dtype(p)
+    _check(load_library().bvmv_colblocks_multiply(c.handle, _dev_ptr(x, dt, c.n), _dev_ptr(y, dt, c.n), p,
+                                                  _stream_ptr(stream)))
+
+
+class Biclique:
+    """Handle of a biclique layout (freed with the object)."""
+
+    def __init__(self, handle, n):
+        self._h = handle
+        self.n = n
+
+    @property
+    def handle(self):
+        return self._h
+
+    def info(self):
+        i = BicliqueInfo()
+        _check(load_library().bvmv_biclique_get_info(self._h, ctypes.byref(i)))
+        return {f: getattr(i, f) for f, _ in BicliqueInfo._fields_}
+
+    def __del__(self):
+        if getattr(self, "_h", None) and _lib is not None:
+            _lib.bvmv_biclique_free(self._h)
+            self._h = None
+
+
+def bvmv_biclique_load(bic, device=0) -> Biclique:
+    """bic: a decomposition with fields n, sptr, sidx, cptr, cidx, rptr, rcol
+    (host arrays; e.g. bvinputs.Bicliques)."""
+    lib = load_library()
+    u64 = lambda a: np.ascontiguousarray(a, dtype=np.uint64)
+    u32 = lambda a: np.ascontiguousarray(a, dtype=np.uint32)
+    arrs = [u64(bic.sptr), u32(bic.sidx), u64(bic.cptr), u32(bic.cidx), u64(bic.rptr), u32(bic.rcol)]
+    ptrs = [a.ctypes.data if a.size else None for a in arrs]
+    h = ctypes.c_void_p()
+    _check(lib.bvmv_biclique_load(int(bic.n), int(arrs[0].size - 1), *ptrs, device, ctypes.byref(h)))
+    return Biclique(h, int(bic.n))
+
+
+def bvmv_biclique_multiply(b: Biclique, x, y, prec=BVMV_F32_COMP, stream=None):
+    p = _prec(prec)
+    dt = _vec_dtype(p)
+    _check(load_library().bvmv_biclique_multiply(b.handle, _dev_ptr(x, dt, b.n), _dev_ptr(y, dt, b.n), p,
+                                                 _stream_ptr(stream)))
 
 
 def bvmv_group(graphs) -> Graph:
@@ -391,6 +487,17 @@ def bvmv_layout_selfcheck(bitstream, x, tile_rows=0, window_cap=0, stage_bytes=0
     keys = ["ntiles", "units", "diff_rows", "direct_rows", "long_rows", "escapes", "layout_bytes", "m_prime",
             "max_level"]
     return y, dict(zip(keys, stats.tolist()))
+
+
+def bvmv_left_selfcheck(bitstream, x, tile_rows=0, window_cap=0, stage_bytes=0, long_row_bytes=0, interval_mode=0):
+    """Host interpretation of the left product's layout (test aid): y = x A in double."""
+    data = _as_u8(bitstream)
+    x = np.ascontiguousarray(x, dtype=np.float64)
+    y = np.zeros_like(x)
+    o = LoadOpts(0, tile_rows, window_cap, stage_bytes, long_row_bytes, interval_mode, 0, 0, 0, 0)
+    _check(load_library().bvmv_left_selfcheck(data.ctypes.data, data.size, ctypes.byref(o), x.ctypes.data,
+                                              y.ctypes.data))
+    return y
 
 
 def bvmv_version():

@@ -56,6 +56,7 @@ struct MF64 {
   __device__ static CAcc chain(PAcc a) { return a; }
   __device__ static CAcc comb(CAcc a, CAcc b) { return a + b; }
   __device__ static X out(CAcc a) { return a; }
+  __device__ static X add_out(X y, CAcc a) { return y + a; }
   __device__ static double to_d(CAcc a) { return a; }
 };
 // float everywhere: the naive mode (window values and prefix sums are read
@@ -74,6 +75,7 @@ struct MF32 {
   __device__ static CAcc chain(PAcc a) { return a; }
   __device__ static CAcc comb(CAcc a, CAcc b) { return a + b; }
   __device__ static X out(CAcc a) { return a; }
+  __device__ static X add_out(X y, CAcc a) { return y + a; }
   __device__ static double to_d(CAcc a) { return a; }
 };
 // float vectors; a row's partial in double (one add per entry), reuse chains
@@ -95,6 +97,7 @@ struct MF32C {
   }
   __device__ static CAcc comb(CAcc a, CAcc b) { return pair_add(a, b); }
   __device__ static X out(CAcc a) { return a.hi + a.lo; }
+  __device__ static X add_out(X y, CAcc a) { return float((double(y) + double(a.hi)) + double(a.lo)); }
   __device__ static double to_d(CAcc a) { return double(a.hi) + double(a.lo); }
 };
 // integer counting with x = 1: degrees by reuse
@@ -112,6 +115,7 @@ struct MINT {
   __device__ static CAcc chain(PAcc a) { return a; }
   __device__ static CAcc comb(CAcc a, CAcc b) { return a + b; }
   __device__ static X out(CAcc a) { return a; }
+  __device__ static X add_out(X y, CAcc a) { return y + a; }
   __device__ static double to_d(CAcc a) { return a; }
 };
 
@@ -524,7 +528,9 @@ struct TileCtx {
 // is the CSR kernel's one-call form.
 constexpr int kEpiRows = kTileRowsMax / 64;  // rows of a tile per lane
 
-template <class M>
+// y = the rows' sums, or with kAdd y += them (one product of a sum of
+// column blocks, taken in block order)
+template <class M, bool kAdd = false>
 struct EpiStore {
   typename M::X* y;
   struct State {};
@@ -533,13 +539,21 @@ struct EpiStore {
   __device__ Fetch fetch(const TileCtx&, int) const { return {}; }
   __device__ bool skip(const State&, int) const { return false; }
   __device__ bool all_done(const State&) const { return false; }
+  __device__ void store(const TileCtx& tc, const typename M::CAcc* s_y) const {
+    for (uint32_t r = lane_id(); r < tc.nrows; r += 64) {
+      if constexpr (kAdd)
+        y[tc.row0 + r] = M::add_out(y[tc.row0 + r], s_y[r]);
+      else
+        y[tc.row0 + r] = M::out(s_y[r]);
+    }
+  }
   __device__ void col(const TileCtx& tc, const typename M::CAcc* s_y, unsigned char*, int, State&,
                       const Fetch&) const {
-    for (uint32_t r = lane_id(); r < tc.nrows; r += 64) y[tc.row0 + r] = M::out(s_y[r]);
+    store(tc, s_y);
   }
   __device__ void finish(const State&, unsigned char*, size_t, uint32_t) const {}
   __device__ void operator()(const TileCtx& tc, const typename M::CAcc* s_y, unsigned char*, int) const {
-    for (uint32_t r = lane_id(); r < tc.nrows; r += 64) y[tc.row0 + r] = M::out(s_y[r]);
+    store(tc, s_y);
   }
 };
 
@@ -1479,6 +1493,10 @@ __global__ void __launch_bounds__(kThreads) csr_wave_kernel(DevCsr C, const type
   const uint32_t lane = lane_id();
   const uint32_t tile = blockIdx.x * kWaves + wave;
   const CsrTile td = C.tiles[tile];
+  // an id's value: x below nx, the second source at and above it
+  const X* __restrict__ aux = static_cast<const X*>(C.aux);
+  const uint32_t nx = C.nx;
+  auto gval = [&](uint32_t c) -> X { return c < nx ? x[c] : aux[c - nx]; };
   const bool is_long = td.nrows & 0x80000000u;
   const uint32_t nrows = td.nrows & 0x7FFFFFFFu;
   const CsrCarve<M> cv{C.wcap, C.ccap};
@@ -1501,7 +1519,7 @@ __global__ void __launch_bounds__(kThreads) csr_wave_kernel(DevCsr C, const type
       }
       X v[8];
 #pragma unroll
-      for (int j = 0; j < 8; ++j) v[j] = base + lane + 64u * j < td.ncols ? x[c[j]] : X(0);
+      for (int j = 0; j < 8; ++j) v[j] = base + lane + 64u * j < td.ncols ? gval(c[j]) : X(0);
 #pragma unroll
       for (int j = 0; j < 8; ++j)
         if (base + lane + 64u * j < td.ncols) M::padd(s, v[j]);
@@ -1542,7 +1560,7 @@ __global__ void __launch_bounds__(kThreads) csr_wave_kernel(DevCsr C, const type
         const int64_t d = int64_t(c) - win0;
         const bool inwin = uint64_t(d) < winlen;
         X v = s_x[inwin ? uint32_t(d) : 0u];
-        if (ok && !inwin) v = x[c];
+        if (ok && !inwin) v = gval(c);
         return ok ? v : X(0);
       });
       wave_sync();
@@ -1681,6 +1699,15 @@ hipError_t launch_bv_multiply(const DevLayout& L, int prec, const void* x, void*
     case 0: return launch_tile<MF64>(L, x, EpiStore<MF64>{static_cast<double*>(y)}, nullptr, s);
     case 1: return launch_tile<MF32>(L, x, EpiStore<MF32>{static_cast<float*>(y)}, nullptr, s);
     case 2: return launch_tile<MF32C>(L, x, EpiStore<MF32C>{static_cast<float*>(y)}, nullptr, s);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+hipError_t launch_bv_multiply_add(const DevLayout& L, int prec, const void* x, void* y, hipStream_t s) {
+  switch (prec) {
+    case 0: return launch_tile<MF64>(L, x, EpiStore<MF64, true>{static_cast<double*>(y)}, nullptr, s);
+    case 1: return launch_tile<MF32>(L, x, EpiStore<MF32, true>{static_cast<float*>(y)}, nullptr, s);
+    case 2: return launch_tile<MF32C>(L, x, EpiStore<MF32C, true>{static_cast<float*>(y)}, nullptr, s);
     default: return hipErrorInvalidValue;
   }
 }
@@ -1859,6 +1886,191 @@ hipError_t launch_pr_select(int prec, const PRState* st, const void* p0, const v
     hipLaunchKernelGGL(pr_select_kernel<float>, grid, dim3(kThreads), 0, s, st, static_cast<const float*>(p0),
                        static_cast<const float*>(p1), static_cast<float*>(out), n);
   return hipGetLastError();
+}
+
+// ------------------------------------------------------------ left product
+namespace {
+// LDS of one wave of the left tile kernel: c of up to 128 rows, their
+// reference gaps, and the group sums T over the window's Z indices
+template <class M>
+struct LeftCarve {
+  using PAcc = typename M::PAcc;
+  uint32_t WC;
+  __host__ __device__ static constexpr size_t c() { return 0; }
+  __host__ __device__ static constexpr size_t gap() { return 128 * sizeof(PAcc); }
+  __host__ __device__ static constexpr size_t T() { return align16(gap() + 128); }
+  __host__ __device__ size_t wave_bytes() const { return align16(T() + (2 * size_t(WC) + 2) * sizeof(PAcc)); }
+  __host__ __device__ size_t block_bytes() const { return kWaves * wave_bytes(); }
+};
+
+// One tile per wave: c = x (I - R)^{-1} on the tile's rows, the group sums
+// T[f] of its A' entries read column-wise, and its window contribution
+// out[j] = T[2j+2] + sum_{p <= j} T[2p+1], written to the tile's part slots.
+template <class M>
+__global__ void __launch_bounds__(kThreads) bv_left_tile_kernel(DevLayout L, DevLeft D,
+                                                                const typename M::X* __restrict__ x) {
+  using PAcc = typename M::PAcc;
+  extern __shared__ __align__(16) unsigned char smem[];
+  const uint32_t wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const uint32_t lane = lane_id();
+  const uint32_t t = blockIdx.x * kWaves + wave;
+  const TileDesc td = L.tiles[t];
+  const LeftTile lt = D.lt[t];
+  const LeftCarve<M> cv{L.wcap};
+  unsigned char* ws = smem + size_t(wave) * cv.wave_bytes();
+  PAcc* s_c = reinterpret_cast<PAcc*>(ws + cv.c());
+  uint8_t* s_g = reinterpret_cast<uint8_t*>(ws + cv.gap());
+  PAcc* T = reinterpret_cast<PAcc*>(ws + cv.T());
+  const uint32_t nrows = td.nrows;
+  // 1. c = x, then each row at level l - 1 adds its children (rows at level
+  //    l that reference it: row r + g with gap g), from the deepest level up
+  uint32_t lv[2];
+  uint32_t lvmax = 0;
+#pragma unroll
+  for (int q = 0; q < 2; ++q) {
+    const uint32_t r = lane + 64u * q;
+    lv[q] = 0;
+    if (r < nrows) {
+      const uint32_t inf = L.info[td.row0 + r];
+      s_c[r] = PAcc(x[td.row0 + r]);
+      s_g[r] = uint8_t(inf & 15u);
+      lv[q] = (inf >> 4) & 15u;
+      lvmax = max(lvmax, lv[q]);
+    } else {
+      s_g[r] = 0;
+    }
+  }
+  for (int d = 32; d >= 1; d >>= 1) lvmax = max(lvmax, uint32_t(__shfl_xor(int(lvmax), d, 64)));
+  const uint32_t Tlen = 2 * td.winlen + 2;
+  for (uint32_t k = lane; k < Tlen; k += 64) T[k] = PAcc(0);
+  wave_sync();
+  for (uint32_t l = lvmax; l >= 1; --l) {
+#pragma unroll
+    for (int q = 0; q < 2; ++q) {
+      const uint32_t r = lane + 64u * q;
+      if (r < nrows && lv[q] == l - 1) {
+        PAcc a = s_c[r];
+        for (uint32_t g = 1; g <= 15 && r + g < nrows; ++g)
+          if (s_g[r + g] == g) a += s_c[r + g];
+        s_c[r] = a;
+      }
+    }
+    wave_sync();
+  }
+  // 2. group sums: lane l takes whole groups [gs, ge) with entries [es, ee)
+  {
+    const uint32_t a = D.lanes[lt.lane0 + lane], b = D.lanes[lt.lane0 + lane + 1];
+    uint32_t g = a >> 16;
+    const uint32_t es = a & 0xFFFFu, ee = b & 0xFFFFu;
+    const uint16_t* ent = D.ent + lt.e0;
+    const uint16_t* grp = D.grp + lt.g0;
+    PAcc acc = PAcc(0);
+    for (uint32_t e = es; e < ee; e += 8) {
+      uint32_t w[8];
+#pragma unroll
+      for (int k = 0; k < 8; ++k) w[k] = e + k < ee ? uint32_t(ent[e + k]) : 0u;
+#pragma unroll
+      for (int k = 0; k < 8; ++k) {
+        if (e + k >= ee) break;
+        const PAcc v = s_c[w[k] & 127u];
+        acc += (w[k] & 0x8000u) ? -v : v;
+        if (w[k] & 0x4000u) {
+          T[grp[g]] = acc;
+          acc = PAcc(0);
+          ++g;
+        }
+      }
+    }
+  }
+  wave_sync();
+  // 3. out[j] = T[2j+2] + sum_{p <= j} T[2p+1]: lane chunks, a wave scan of
+  //    the chunks' sums of the prefix entries
+  {
+    // the prefix of the difference array as a double pair: its terms cancel
+    // (an interval adds at its start and subtracts at its end), so a plain
+    // running sum would leave absolute errors of the window's mass on small
+    // columns
+    const uint32_t n = td.winlen;
+    const uint32_t ch = (n + 63) / 64;
+    const uint32_t b = min(n, lane * ch), e = min(n, b + ch);
+    DPair tot{0.0, 0.0};
+    for (uint32_t j = b; j < e; ++j) tot = dpair_add(tot, DPair{double(T[2 * j + 1]), 0.0});
+    DPair inc = tot;
+    for (int d = 1; d < 64; d <<= 1) {
+      const DPair o{__shfl_up(inc.hi, d, 64), __shfl_up(inc.lo, d, 64)};
+      if (lane >= uint32_t(d)) inc = dpair_add(o, inc);
+    }
+    DPair run{__shfl_up(inc.hi, 1, 64), __shfl_up(inc.lo, 1, 64)};
+    if (lane == 0) run = DPair{0.0, 0.0};
+    PAcc* part = static_cast<PAcc*>(D.part) + lt.part0;
+    for (uint32_t j = b; j < e; ++j) {
+      run = dpair_add(run, DPair{double(T[2 * j + 1]), 0.0});
+      part[j] = PAcc((double(T[2 * j + 2]) + run.hi) + run.lo);
+    }
+  }
+  // 4. the rows' c for the escapes' gather
+  if (lt.esc) {
+    PAcc* cb = static_cast<PAcc*>(D.cbuf);
+    for (uint32_t r = lane; r < nrows; r += 64) cb[td.row0 + r] = s_c[r];
+  }
+}
+
+// y_j = the contributions of the tiles whose window covers j (in tile order)
+// + the escapes of column j (in row order); one wave per 64 columns.
+template <class M>
+__global__ void __launch_bounds__(kThreads) bv_left_gather_kernel(DevLayout L, DevLeft D, typename M::X* __restrict__ y) {
+  using PAcc = typename M::PAcc;
+  using X = typename M::X;
+  const uint32_t wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const uint32_t g = blockIdx.x * kWaves + wave;
+  if (uint64_t(g) * 64 >= D.n) return;
+  const uint32_t j = g * 64 + lane_id();
+  const PAcc* part = static_cast<const PAcc*>(D.part);
+  double acc = 0.0;
+  for (uint32_t k = D.cov_off[g]; k < D.cov_off[g + 1]; ++k) {
+    const uint32_t t = D.cov[k];
+    const uint32_t w0 = L.tiles[t].win0, wl = L.tiles[t].winlen, p0 = D.lt[t].part0;
+    const uint32_t d = j - w0;
+    if (j >= w0 && d < wl) acc += double(part[p0 + d]);
+  }
+  const PAcc* cb = static_cast<const PAcc*>(D.cbuf);
+  for (uint32_t k = D.esc_off[g]; k < D.esc_off[g + 1]; ++k) {
+    const LeftEscape e = D.esc[k];
+    if (e.col == j) {
+      const double v = double(cb[e.row & 0x7FFFFFFFu]);
+      acc += (e.row & 0x80000000u) ? -v : v;
+    }
+  }
+  if (j < D.n) y[j] = X(acc);
+}
+
+template <class M>
+hipError_t launch_left(const DevLayout& L, const DevLeft& D, const void* x, void* y, hipStream_t s) {
+  const size_t smem = LeftCarve<M>{L.wcap}.block_bytes();
+  auto k1 = bv_left_tile_kernel<M>;
+  if (hipError_t e = set_lds(reinterpret_cast<const void*>(k1), smem)) return e;
+  if (L.ntiles)
+    hipLaunchKernelGGL(k1, dim3(L.ntiles / kWaves), dim3(kThreads), smem, s, L, D,
+                       static_cast<const typename M::X*>(x));
+  if (hipError_t e = hipGetLastError()) return e;
+  const uint32_t groups = (D.n + 63) / 64;
+  hipLaunchKernelGGL(bv_left_gather_kernel<M>, dim3((groups + kWaves - 1) / kWaves), dim3(kThreads), 0, s, L, D,
+                     static_cast<typename M::X*>(y));
+  return hipGetLastError();
+}
+}  // namespace
+
+size_t bv_left_lds_bytes(const DevLayout& L, int prec) {
+  return prec == 1 ? LeftCarve<MF32>{L.wcap}.block_bytes() : LeftCarve<MF64>{L.wcap}.block_bytes();
+}
+
+hipError_t launch_bv_left(const DevLayout& L, const DevLeft& D, int prec, const void* x, void* y, hipStream_t s) {
+  switch (prec) {
+    case 0: return launch_left<MF64>(L, D, x, y, s);
+    case 1: return launch_left<MF32>(L, D, x, y, s);
+    case 2: return launch_left<MF32C>(L, D, x, y, s);
+    default: return hipErrorInvalidValue;
+  }
 }
 
 // ------------------------------------------------- allocation-free working set

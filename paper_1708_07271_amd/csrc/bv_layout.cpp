@@ -389,14 +389,16 @@ int build_layout(const DecodedGraph& g, const LayoutParams& prm, int nthreads, H
 }
 
 void build_csr_tiles(const uint64_t* rowptr, const uint32_t* col, int64_t n, int rows_cap, int col_cap,
-                     int long_cols, int window_cap, std::vector<CsrTile>& tiles) {
+                     int long_cols, int window_cap, std::vector<CsrTile>& tiles, uint64_t xlen) {
   tiles.clear();
   std::vector<uint32_t> pts;
+  const uint32_t wmax = uint32_t(std::min<uint64_t>(xlen, 0xFFFFFFFFull));
+  const uint32_t wpad = uint32_t(std::min<uint64_t>(uint64_t(n), wmax));  // window start of an empty tile
   int64_t i = 0;
   while (i < n) {
     const uint64_t d = rowptr[i + 1] - rowptr[i];
     if (d > uint64_t(long_cols)) {
-      tiles.push_back({uint32_t(i), 1u | 0x80000000u, uint32_t(rowptr[i]), uint32_t(d), uint32_t(i), 0, 0, 0});
+      tiles.push_back({uint32_t(i), 1u | 0x80000000u, uint32_t(rowptr[i]), uint32_t(d), 0, 0, 0, 0});
       ++i;
       continue;
     }
@@ -405,11 +407,135 @@ void build_csr_tiles(const uint64_t* rowptr, const uint32_t* col, int64_t n, int
            rowptr[i + 1] - rowptr[i0] <= uint64_t(col_cap))
       ++i;
     CsrTile t{uint32_t(i0), uint32_t(i - i0), uint32_t(rowptr[i0]), uint32_t(rowptr[i] - rowptr[i0]), 0, 0, 0, 0};
-    pts.assign(col + rowptr[i0], col + rowptr[i]);
-    best_window(pts, window_cap, uint32_t(i0), t.win0, t.winlen);
+    pts.clear();
+    for (uint64_t k = rowptr[i0]; k < rowptr[i]; ++k)
+      if (col[k] < wmax) pts.push_back(col[k]);
+    best_window(pts, window_cap, std::min(uint32_t(i0), wmax), t.win0, t.winlen);
     tiles.push_back(t);
   }
-  while (tiles.size() % kTilesPerBlock) tiles.push_back({uint32_t(n), 0, 0, 0, uint32_t(n), 0, 0, 0});
+  while (tiles.size() % kTilesPerBlock) tiles.push_back({uint32_t(n), 0, 0, 0, wpad, 0, 0, 0});
+}
+
+int build_left_layout(const HostLayout& hl, LeftLayout& out, std::string& err) {
+  out = LeftLayout();
+  const int64_t n = hl.n;
+  const size_t ng = size_t((n + 63) / 64);
+  struct Ent {
+    uint16_t f, row;
+    uint16_t neg;
+  };
+  std::vector<Ent> ents;
+  std::vector<std::vector<uint32_t>> cover(ng);
+  uint64_t part = 0;
+  for (size_t t = 0; t < hl.tiles.size(); ++t) {
+    const TileDesc& td = hl.tiles[t];
+    LeftTile lt{};
+    lt.e0 = uint32_t(out.entries.size());
+    lt.g0 = uint32_t(out.groups.size());
+    lt.lane0 = uint32_t(out.lanes.size());
+    lt.part0 = uint32_t(part);
+    if (td.nrows > 128) {
+      err = "left product: tile of more than 128 rows";
+      return -1;
+    }
+    const uint8_t* base = hl.data.data() + size_t(td.data16) * 16;
+    const uint16_t* s16 = reinterpret_cast<const uint16_t*>(base);
+    const uint32_t* w32 = reinterpret_cast<const uint32_t*>(base + align16u(td.n16 * 2u));
+    ents.clear();
+    uint64_t o16 = 0, ow = 0, ol = 0;
+    for (uint32_t r = 0; r < td.nrows; ++r) {
+      const uint32_t inf = hl.info[td.row0 + r];
+      const uint32_t ns = hl.ns[td.row0 + r];
+      const uint32_t grow = td.row0 + r;
+      if (inf & kInfoLong) {
+        const uint64_t len = uint64_t(info_nwide(inf)) | (uint64_t(ns) << 19);
+        for (uint64_t k = 0; k < len; ++k) {
+          const uint32_t w = hl.longs[td.long0 + ol + k];
+          const int64_t c = int64_t(td.win0) + int64_t(w & 0x7FFFFFFFu) - int64_t(kLongBias);
+          out.esc.push_back({uint32_t(c), grow | (w & 0x80000000u)});
+        }
+        ol += len;
+        lt.esc = 1;
+        continue;
+      }
+      for (uint32_t k = 0; k < ns; ++k) {
+        const uint32_t w = s16[o16 + k];
+        const uint16_t f = uint16_t(w & kS16Off);
+        // a column adds with its sign; a prefix entry with the opposite one
+        const bool neg = (f & 1) ? !(w & kS16Neg) : (w & kS16Neg) != 0;
+        ents.push_back({f, uint16_t(r), uint16_t(neg)});
+      }
+      o16 += ns;
+      for (uint32_t k = 0; k < info_nwide(inf); ++k) {
+        const uint32_t w = w32[ow + k];
+        const int64_t c = int64_t(td.win0) + int64_t(w & kWideOff) - int64_t(kWideBias);
+        out.esc.push_back({uint32_t(c), grow | ((w & kWideNeg) ? 0x80000000u : 0u)});
+        lt.esc = 1;
+      }
+      ow += info_nwide(inf);
+    }
+    std::stable_sort(ents.begin(), ents.end(), [](const Ent& a, const Ent& b) {
+      return a.f != b.f ? a.f < b.f : a.row < b.row;
+    });
+    // groups, and the lanes' runs of whole groups balanced on entries
+    const uint32_t E = uint32_t(ents.size());
+    std::vector<uint32_t> gstart;  // entry index of each group's first entry
+    for (uint32_t k = 0; k < E; ++k) {
+      const bool last = k + 1 == E || ents[k + 1].f != ents[k].f;
+      if (k == 0 || ents[k - 1].f != ents[k].f) {
+        gstart.push_back(k);
+        out.groups.push_back(ents[k].f);
+      }
+      out.entries.push_back(uint16_t(ents[k].row | (last ? 0x4000u : 0u) | (ents[k].neg ? 0x8000u : 0u)));
+    }
+    const uint32_t G = uint32_t(gstart.size());
+    if (G > 0xFFFF || E > 0xFFFF) {
+      err = "left product: tile stream too long";
+      return -1;
+    }
+    uint32_t gi = 0;
+    for (uint32_t l = 0; l <= 64; ++l) {
+      const uint64_t target = (uint64_t(E) * l + 63) / 64;
+      while (gi < G && gstart[gi] < target) ++gi;
+      const uint32_t es = gi < G ? gstart[gi] : E;
+      out.lanes.push_back((gi << 16) | es);
+    }
+    while (out.entries.size() % 8) out.entries.push_back(0);
+    while (out.groups.size() % 8) out.groups.push_back(0);
+    if (td.winlen) {
+      for (uint64_t g = td.win0 / 64; g <= (uint64_t(td.win0) + td.winlen - 1) / 64 && g < ng; ++g)
+        cover[g].push_back(uint32_t(t));
+      part += (td.winlen + 3u) & ~3u;
+    }
+    out.tiles.push_back(lt);
+  }
+  if (part >= (uint64_t(1) << 32) || out.entries.size() >= (uint64_t(1) << 32)) {
+    err = "left product layout exceeds 32-bit offsets";
+    return -1;
+  }
+  out.part_len = part;
+  std::sort(out.esc.begin(), out.esc.end(), [](const LeftEscape& a, const LeftEscape& b) {
+    return a.col != b.col ? a.col < b.col : (a.row & 0x7FFFFFFFu) < (b.row & 0x7FFFFFFFu);
+  });
+  out.esc_off.assign(ng + 1, 0);
+  for (const auto& e : out.esc) {
+    if (int64_t(e.col) >= n) {
+      err = "left product: escape column out of range";
+      return -1;
+    }
+    ++out.esc_off[e.col / 64 + 1];
+  }
+  for (size_t g = 0; g < ng; ++g) out.esc_off[g + 1] += out.esc_off[g];
+  out.cov_off.assign(ng + 1, 0);
+  for (size_t g = 0; g < ng; ++g) {
+    out.cov_off[g + 1] = out.cov_off[g] + uint32_t(cover[g].size());
+    out.cov.insert(out.cov.end(), cover[g].begin(), cover[g].end());
+  }
+  if (out.esc.empty()) out.esc.push_back({0, 0});
+  if (out.cov.empty()) out.cov.push_back(0);
+  if (out.groups.empty()) out.groups.push_back(0);
+  if (out.entries.empty()) out.entries.push_back(0);
+  return 0;
 }
 
 }  // namespace bvmv

@@ -110,13 +110,63 @@ inline uint32_t info_nwide(uint32_t inf) { return inf >> 13; }
 
 int build_layout(const DecodedGraph& g, const LayoutParams& prm, int nthreads, HostLayout& out, std::string& err);
 
+// ------------------------------------------------------------ left product
+// Layout of the left product y = x A on the same tiles (PageRank's p M,
+// Section "PageRank"), without the transposed graph: with R the tile's
+// references (R_ik = [r_i = k]), A = (I - R)^{-1} A', so x A = c A' with
+// c = x (I - R)^{-1}, c_k = x_k + the sum of c_i over the rows i that
+// reference k.  Per tile, A' is read column-wise: the tile's singles entries
+// sorted by their Z index f (then by row) form groups, one per distinct f;
+// a group's sum T[f] = sum of s * c_row over its entries, with s the entry's
+// sign for a column (f = 2j+2) and the opposite sign for a prefix entry
+// (f = 2p+1: an interval [a, b) of row i puts +c_i at P[a] and -c_i at P[b]
+// of a difference array).  The tile's window contribution is then
+// out[j] = T[2j+2] + sum_{p <= j} T[2p+1].  Entries outside the window (wide
+// entries, long rows) are escapes, summed per column from a global list.
+//   entries (u16): bits 0..6 tile row, bit 14 last entry of its group,
+//                  bit 15 subtract;
+//   groups  (u16): f of each group, ascending;
+//   lanes   (u32 x 65 per tile): (group start << 16) | entry start of lane l's
+//                  contiguous run of whole groups, balanced on entries.
+struct LeftTile {
+  uint32_t e0;      // first entry (u16 index into entries)
+  uint32_t g0;      // first group (index into groups)
+  uint32_t lane0;   // lane table at lanes[lane0 .. lane0 + 64]
+  uint32_t part0;   // the tile's window contribution at part[part0 .. part0 + winlen)
+  uint32_t esc;     // 1 if the tile has escapes (its rows' c go to the global c)
+  uint32_t pad0, pad1, pad2;
+};
+struct LeftEscape {
+  uint32_t col;     // target column
+  uint32_t row;     // bit 31 subtract, bits 0..30 global row
+};
+struct LeftLayout {
+  std::vector<LeftTile> tiles;     // one per layout tile
+  std::vector<uint16_t> entries;   // padded to 8 entries per tile
+  std::vector<uint16_t> groups;
+  std::vector<uint32_t> lanes;
+  std::vector<LeftEscape> esc;     // sorted by (col, row)
+  std::vector<uint32_t> esc_off;   // per 64-column group: escapes [esc_off[g], esc_off[g+1])
+  std::vector<uint32_t> cov_off;   // per 64-column group: covering tiles cov[cov_off[g] .. cov_off[g+1])
+  std::vector<uint32_t> cov;       // tile ids, ascending within a group
+  uint64_t part_len = 0;           // elements of the window contributions
+  int64_t bytes() const {
+    return int64_t(tiles.size() * sizeof(LeftTile) + entries.size() * 2 + groups.size() * 2 + lanes.size() * 4 +
+                   esc.size() * sizeof(LeftEscape) + esc_off.size() * 4 + cov_off.size() * 4 + cov.size() * 4);
+  }
+};
+int build_left_layout(const HostLayout& hl, LeftLayout& out, std::string& err);
+
 // Plain CSR tiles for the baseline: runs of rows whose column ids fit the
 // staging budget (with an x window chosen like the compressed tiles'), or a
 // single long row summed block-wide (bit 31 of nrows).
 struct CsrTile {
   uint32_t row0, nrows, c0, ncols, win0, winlen, pad0, pad1;
 };
+// Row tiles of a CSR matrix with n rows for the CSR tile kernel.  Windows
+// cover ids below xlen only (ids at or above it are not columns of x), and
+// every window lies inside [0, xlen).
 void build_csr_tiles(const uint64_t* rowptr, const uint32_t* col, int64_t n, int rows_cap, int col_cap,
-                     int long_cols, int window_cap, std::vector<CsrTile>& tiles);
+                     int long_cols, int window_cap, std::vector<CsrTile>& tiles, uint64_t xlen);
 
 }  // namespace bvmv

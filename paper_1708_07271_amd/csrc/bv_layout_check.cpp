@@ -11,6 +11,12 @@
 #include "../../include/bvmv.h"
 #include "bv_decode.hpp"
 #include "bv_layout.hpp"
+// the compensated pair arithmetic of twosum.hpp in this host-only file (no
+// HIP headers here): the device qualifiers are dropped
+#define __host__
+#define __device__
+#define __forceinline__ inline
+#include "twosum.hpp"
 
 using namespace bvmv;
 
@@ -130,6 +136,90 @@ extern "C" int bvmv_layout_selfcheck(const void* bitstream, size_t nbytes, const
     stats[6] = hl.bytes();
     stats[7] = hl.m_prime;
     stats[8] = hl.max_level;
+  }
+  return BVMV_OK;
+}
+
+// Host interpretation of the left product's layout, in double precision, as
+// the two device passes read it: c = x (I - R)^{-1} per tile from the deepest
+// level up, the column-wise group sums T[f], the window contributions
+// out[j] = T[2j+2] + sum_{p <= j} T[2p+1], then per column the covering
+// tiles' contributions and the escapes.  x and y are HOST arrays of n doubles.
+extern "C" int bvmv_left_selfcheck(const void* bitstream, size_t nbytes, const bvmv_load_opts* opts,
+                                   const double* x, double* y) {
+  if (!bitstream || !x || !y) return set_error(BVMV_EINVAL, "null argument");
+  DecodedGraph dg;
+  std::string err;
+  if (decode_stream(static_cast<const uint8_t*>(bitstream), nbytes, 4, dg, err)) return set_error(BVMV_EFORMAT, err);
+  LayoutParams prm;
+  if (opts) {
+    if (opts->tile_rows) prm.tile_rows = opts->tile_rows;
+    if (opts->window_cap) prm.window_cap = opts->window_cap;
+    if (opts->stage_bytes) prm.stage_bytes = opts->stage_bytes;
+    prm.long_row_bytes = opts->long_row_bytes ? opts->long_row_bytes : prm.stage_bytes / 2;
+    if (opts->interval_mode == 1) prm.min_interval = INT_MAX;
+  }
+  HostLayout hl;
+  if (build_layout(dg, prm, 4, hl, err)) return set_error(BVMV_EINVAL, err);
+  LeftLayout ll;
+  if (build_left_layout(hl, ll, err)) return set_error(BVMV_EINVAL, err);
+  const int64_t n = hl.n;
+  std::vector<double> part(ll.part_len, 0.0), cb(size_t(n), 0.0);
+  for (size_t t = 0; t < hl.tiles.size(); ++t) {
+    const TileDesc& td = hl.tiles[t];
+    const LeftTile& lt = ll.tiles[t];
+    std::vector<double> c(td.nrows), T(2 * size_t(td.winlen) + 2, 0.0);
+    int lvmax = 0;
+    for (uint32_t r = 0; r < td.nrows; ++r) {
+      c[r] = x[td.row0 + r];
+      lvmax = std::max<int>(lvmax, int(info_level(hl.info[td.row0 + r])));
+    }
+    for (int l = lvmax; l >= 1; --l)
+      for (uint32_t r = 0; r < td.nrows; ++r) {
+        if (int(info_level(hl.info[td.row0 + r])) != l - 1) continue;
+        for (uint32_t g = 1; g <= 15 && r + g < td.nrows; ++g)
+          if (info_g(hl.info[td.row0 + r + g]) == g) c[r] += c[r + g];
+      }
+    for (uint32_t l = 0; l < 64; ++l) {
+      const uint32_t a = ll.lanes[lt.lane0 + l], b = ll.lanes[lt.lane0 + l + 1];
+      uint32_t g = a >> 16;
+      double acc = 0.0;
+      for (uint32_t e = a & 0xFFFFu; e < (b & 0xFFFFu); ++e) {
+        const uint32_t w = ll.entries[lt.e0 + e];
+        if ((w & 127u) >= td.nrows) return set_error(BVMV_EINVAL, "left entry row outside the tile");
+        acc += (w & 0x8000u) ? -c[w & 127u] : c[w & 127u];
+        if (w & 0x4000u) {
+          const uint32_t f = ll.groups[lt.g0 + g];
+          if (f >= T.size()) return set_error(BVMV_EINVAL, "left group outside the window");
+          T[f] = acc;
+          acc = 0.0;
+          ++g;
+        }
+      }
+      if (acc != 0.0) return set_error(BVMV_EINVAL, "lane run ends inside a group");
+    }
+    DPair run{0.0, 0.0};
+    for (uint32_t j = 0; j < td.winlen; ++j) {
+      run = dpair_add(run, DPair{T[2 * size_t(j) + 1], 0.0});
+      part[lt.part0 + j] = (T[2 * size_t(j) + 2] + run.hi) + run.lo;
+    }
+    if (lt.esc)
+      for (uint32_t r = 0; r < td.nrows; ++r) cb[td.row0 + r] = c[r];
+  }
+  for (int64_t j = 0; j < n; ++j) {
+    const size_t g = size_t(j / 64);
+    double acc = 0.0;
+    for (uint32_t k = ll.cov_off[g]; k < ll.cov_off[g + 1]; ++k) {
+      const uint32_t t = ll.cov[k];
+      const TileDesc& td = hl.tiles[t];
+      if (j >= int64_t(td.win0) && j < int64_t(td.win0) + int64_t(td.winlen))
+        acc += part[ll.tiles[t].part0 + uint64_t(j - td.win0)];
+    }
+    for (uint32_t k = ll.esc_off[g]; k < ll.esc_off[g + 1]; ++k) {
+      const LeftEscape& e = ll.esc[k];
+      if (int64_t(e.col) == j) acc += (e.row & 0x80000000u) ? -cb[e.row & 0x7FFFFFFFu] : cb[e.row & 0x7FFFFFFFu];
+    }
+    y[j] = acc;
   }
   return BVMV_OK;
 }

@@ -2,6 +2,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <climits>
 #include <cmath>
 #include <cstring>
@@ -247,8 +248,20 @@ struct bvmv_graph {
   PRWork prb;  // k right-hand sides
   LearnWork lw;
   hipStream_t cap = nullptr;
+  // left product (built on first use)
+  bool left_ready = false;
+  int64_t left_bytes = 0;
+  DevLeft left{};
+  std::vector<void*> left_bufs;
 
+  void release_left() {
+    for (void* p : left_bufs) dev_free(p);
+    left_bufs.clear();
+    left = DevLeft{};
+    left_ready = false;
+  }
   void release_device() {
+    release_left();
     pr.release();
     prb.release();
     lw.release();
@@ -872,6 +885,62 @@ int bvmv_multiply(bvmv_graph* g, const void* x, void* y, int prec, void* stream)
   return BVMV_OK;
 }
 
+// y = x A on the tiles of the layout (built once per graph, on first use).
+int bvmv_multiply_left(bvmv_graph* g, const void* x, void* y, int prec, void* stream) {
+  if (!g || !x || !y) return fail(BVMV_EINVAL, "null argument");
+  if (prec < 0 || prec > 2) return fail(BVMV_EINVAL, "bad precision");
+  if (g->ngraphs != 1) return fail(BVMV_EINVAL, "the left product takes a single graph, not a group");
+  const size_t vbytes = size_t(g->n) * elem_size(prec);
+  if (ranges_overlap(x, vbytes, y, vbytes)) return fail(BVMV_EINVAL, "x and y must not overlap");
+  DeviceGuard dg(g->device);
+  if (!g->left_ready) {
+    LeftLayout ll;
+    std::string err;
+    if (build_left_layout(g->hl, ll, err)) return fail(BVMV_EINVAL, err);
+    if (int rc = check_lds(g->device, std::max(bv_left_lds_bytes(g->L, 0), bv_left_lds_bytes(g->L, 1)))) return rc;
+    DevLeft D;
+    auto up = [&](auto** dst, const auto& v) -> int {
+      if (int rc = dev_upload(dst, v.data(), v.size())) return rc;
+      g->left_bufs.push_back(*dst);
+      return BVMV_OK;
+    };
+    LeftTile* lt = nullptr;
+    uint16_t *ent = nullptr, *grp = nullptr;
+    uint32_t *lanes = nullptr, *eo = nullptr, *co = nullptr, *cov = nullptr;
+    LeftEscape* esc = nullptr;
+    if (up(&lt, ll.tiles) || up(&ent, ll.entries) || up(&grp, ll.groups) || up(&lanes, ll.lanes) ||
+        up(&esc, ll.esc) || up(&eo, ll.esc_off) || up(&co, ll.cov_off) || up(&cov, ll.cov)) {
+      g->release_left();
+      return BVMV_ENOMEM;
+    }
+    void *part = nullptr, *cb = nullptr;
+    if (hipMalloc(&part, std::max<uint64_t>(ll.part_len, 1) * 8) != hipSuccess) part = nullptr;
+    if (part) g->left_bufs.push_back(part);
+    if (hipMalloc(&cb, size_t(std::max<int64_t>(g->n, 1)) * 8) != hipSuccess) cb = nullptr;
+    if (cb) g->left_bufs.push_back(cb);
+    if (!part || !cb) {
+      g->release_left();
+      return fail(BVMV_ENOMEM, "hipMalloc of the left product's buffers failed");
+    }
+    D.lt = lt;
+    D.ent = ent;
+    D.grp = grp;
+    D.lanes = lanes;
+    D.part = part;
+    D.cbuf = cb;
+    D.esc = esc;
+    D.esc_off = eo;
+    D.cov_off = co;
+    D.cov = cov;
+    D.n = uint32_t(g->n);
+    g->left = D;
+    g->left_bytes = ll.bytes();
+    g->left_ready = true;
+  }
+  HIP_TRY(launch_bv_left(g->L, g->left, prec, x, y, static_cast<hipStream_t>(stream)));
+  return BVMV_OK;
+}
+
 int bvmv_multiply_batch(bvmv_graph* g, const void* X, void* Y, int k, int64_t ld, int prec, void* stream) {
   if (!g || !X || !Y) return fail(BVMV_EINVAL, "null argument");
   if (prec < 0 || prec > 2 || k < 1 || k > 64 || ld < g->n) return fail(BVMV_EINVAL, "bad batch arguments");
@@ -1175,7 +1244,7 @@ int bvmv_csr_create_host(int64_t n, const uint64_t* rowptr, const uint32_t* col,
   // the compressed layout's defaults: 64 rows per wave, 4 KB of staged ids,
   // rows over 2 KB summed by the whole wave, x windows up to 512 columns
   const int rcap = 64, ccap = 1024, long_cols = 512, wcap_max = 512;
-  build_csr_tiles(rowptr, col, n, rcap, ccap, long_cols, wcap_max, c->tiles);
+  build_csr_tiles(rowptr, col, n, rcap, ccap, long_cols, wcap_max, c->tiles, uint64_t(n));
   uint32_t wcap = 0;
   for (const auto& t : c->tiles) wcap = std::max(wcap, t.winlen);
   DeviceGuard dg(device);
@@ -1275,6 +1344,273 @@ void bvmv_csr_free(bvmv_csr* c) {
 }
 
 
+
+// --------------------------------------------------------- column blocks
+// A matrix split into submatrices of consecutive columns, each loaded as a
+// graph of its own (same n; its own references, so a row may match different
+// reference rows in different blocks): y = A_1 x + A_2 x + ..., the first
+// block storing y and the others adding to it, in block order.
+struct bvmv_colblocks {
+  int device = 0;
+  int64_t n = 0;
+  std::vector<bvmv_graph*> blocks;  // owned by the caller
+};
+
+int bvmv_colblocks_create(bvmv_graph* const* blocks, int count, bvmv_colblocks** out) {
+  if (!blocks || count < 1 || !out) return fail(BVMV_EINVAL, "bad column-block arguments");
+  *out = nullptr;
+  std::unique_ptr<bvmv_colblocks> c(new bvmv_colblocks());
+  c->device = blocks[0] ? blocks[0]->device : 0;
+  c->n = blocks[0] ? blocks[0]->n : 0;
+  for (int b = 0; b < count; ++b) {
+    const bvmv_graph* g = blocks[b];
+    if (!g || g->ngraphs != 1) return fail(BVMV_EINVAL, "column blocks must be loaded graphs");
+    if (g->n != c->n || g->device != c->device)
+      return fail(BVMV_EINVAL, "column blocks must share n and the device");
+    c->blocks.push_back(blocks[b]);
+  }
+  *out = c.release();
+  return BVMV_OK;
+}
+
+int bvmv_colblocks_multiply(bvmv_colblocks* c, const void* x, void* y, int prec, void* stream) {
+  if (!c || !x || !y) return fail(BVMV_EINVAL, "null argument");
+  if (prec < 0 || prec > 2) return fail(BVMV_EINVAL, "bad precision");
+  const size_t vbytes = size_t(c->n) * elem_size(prec);
+  if (ranges_overlap(x, vbytes, y, vbytes)) return fail(BVMV_EINVAL, "x and y must not overlap");
+  DeviceGuard dg(c->device);
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  for (size_t b = 0; b < c->blocks.size(); ++b) {
+    if (b == 0)
+      HIP_TRY(launch_bv_multiply(c->blocks[b]->L, prec, x, y, s));
+    else
+      HIP_TRY(launch_bv_multiply_add(c->blocks[b]->L, prec, x, y, s));
+  }
+  return BVMV_OK;
+}
+
+void bvmv_colblocks_free(bvmv_colblocks* c) { delete c; }
+
+// ------------------------------------------------------------ bicliques
+// The biclique format (Section "Final Remarks"): c_r = sum_{j in C_r} x_j for
+// every biclique, then y_i = sum_{r : i in S_r} c_r + sum_{j in Res_i} x_j.
+// Both passes run the CSR tile kernel: the first over the C lists (rows =
+// bicliques, ids = columns of x), the second over each node's residual
+// columns followed by its bicliques' ids n + r, which read the sums c.
+struct bvmv_biclique {
+  int device = 0;
+  int64_t n = 0, m = 0, nbic = 0, s_ids = 0, c_ids = 0, res = 0;
+  std::vector<CsrTile> t_sum, t_row;
+  CsrTile *d_tsum = nullptr, *d_trow = nullptr;
+  uint32_t *d_cptr = nullptr, *d_cidx = nullptr, *d_rptr = nullptr, *d_ridx = nullptr;
+  void* d_c = nullptr;  // the biclique sums, nbic elements of the precision's type
+  DevCsr Csum, Crow;
+  int64_t layout_bytes = 0;
+  void release() {
+    dev_free(d_tsum);
+    dev_free(d_trow);
+    dev_free(d_cptr);
+    dev_free(d_cidx);
+    dev_free(d_rptr);
+    dev_free(d_ridx);
+    dev_free(d_c);
+    d_tsum = d_trow = nullptr;
+    d_cptr = d_cidx = d_rptr = d_ridx = nullptr;
+    d_c = nullptr;
+  }
+};
+
+namespace {
+// offsets p[0..cnt] start at 0 and do not decrease
+bool offsets_ok(const uint64_t* p, int64_t cnt) {
+  if (p[0] != 0) return false;
+  for (int64_t i = 0; i < cnt; ++i)
+    if (p[i + 1] < p[i]) return false;
+  return true;
+}
+// ids a[0..len) strictly increasing and below n
+bool ids_ok(const uint32_t* a, uint64_t len, int64_t n) {
+  for (uint64_t k = 0; k < len; ++k)
+    if (int64_t(a[k]) >= n || (k && a[k] <= a[k - 1])) return false;
+  return true;
+}
+}  // namespace
+
+int bvmv_biclique_load(int64_t n, int64_t nbic, const uint64_t* sptr, const uint32_t* sidx, const uint64_t* cptr,
+                       const uint32_t* cidx, const uint64_t* rptr, const uint32_t* rcol, int device,
+                       bvmv_biclique** out) {
+  if (!out) return fail(BVMV_EINVAL, "null argument");
+  *out = nullptr;
+  if (n < 1 || nbic < 0 || !rptr || (nbic > 0 && (!sptr || !cptr)))
+    return fail(BVMV_EINVAL, "bad biclique arguments");
+  if (uint64_t(n) + uint64_t(nbic) >= 0xFFFFFFFFull) return fail(BVMV_EINVAL, "n + bicliques must be below 2^32 - 1");
+  static const uint64_t kZero = 0;
+  if (nbic == 0) sptr = cptr = &kZero;
+  if (!offsets_ok(sptr, nbic) || !offsets_ok(cptr, nbic) || !offsets_ok(rptr, n))
+    return fail(BVMV_EFORMAT, "offsets must start at 0 and not decrease");
+  const uint64_t ns = sptr[nbic], nc = cptr[nbic], nr = rptr[n];
+  if ((ns && !sidx) || (nc && !cidx) || (nr && !rcol)) return fail(BVMV_EINVAL, "bad biclique arguments");
+  for (int64_t r = 0; r < nbic; ++r)
+    if (!ids_ok(sidx + sptr[r], sptr[r + 1] - sptr[r], n) || !ids_ok(cidx + cptr[r], cptr[r + 1] - cptr[r], n))
+      return fail(BVMV_EFORMAT, "biclique " + std::to_string(r) + ": ids must be strictly increasing and below n");
+  for (int64_t i = 0; i < n; ++i)
+    if (!ids_ok(rcol + rptr[i], rptr[i + 1] - rptr[i], n))
+      return fail(BVMV_EFORMAT, "residual row " + std::to_string(i) + ": ids must be strictly increasing and below n");
+  // each node's bicliques (ascending r), by counting
+  std::vector<uint64_t> mp(size_t(n) + 1, 0);
+  for (uint64_t k = 0; k < ns; ++k) ++mp[size_t(sidx[k]) + 1];
+  for (int64_t i = 0; i < n; ++i) mp[size_t(i) + 1] += mp[size_t(i)];
+  std::vector<uint32_t> memb(ns ? ns : 1);
+  {
+    std::vector<uint64_t> pos(mp.begin(), mp.end() - 1);
+    for (int64_t r = 0; r < nbic; ++r)
+      for (uint64_t k = sptr[r]; k < sptr[r + 1]; ++k) memb[pos[sidx[k]]++] = uint32_t(r);
+  }
+  // the edges must be a partition: no (i, j) in two bicliques or in a biclique
+  // and the residual (rows checked in parallel blocks)
+  std::atomic<int64_t> dup_row{-1};
+  uint64_t m = nr;
+  for (int64_t r = 0; r < nbic; ++r) m += (sptr[r + 1] - sptr[r]) * (cptr[r + 1] - cptr[r]);
+  {
+    const int nt = default_threads(0);
+    std::atomic<int64_t> next{0};
+    const int64_t blk = 4096;
+    auto worker = [&] {
+      std::vector<uint32_t> row;
+      for (int64_t b = next.fetch_add(blk); b < n && dup_row.load() < 0; b = next.fetch_add(blk))
+        for (int64_t i = b; i < std::min(n, b + blk); ++i) {
+          row.assign(rcol + rptr[i], rcol + rptr[i + 1]);
+          for (uint64_t k = mp[size_t(i)]; k < mp[size_t(i) + 1]; ++k) {
+            const uint32_t r = memb[k];
+            row.insert(row.end(), cidx + cptr[r], cidx + cptr[r + 1]);
+          }
+          std::sort(row.begin(), row.end());
+          if (std::adjacent_find(row.begin(), row.end()) != row.end()) {
+            int64_t none = -1;
+            dup_row.compare_exchange_strong(none, i);
+            return;
+          }
+        }
+    };
+    std::vector<std::thread> th;
+    for (int t = 1; t < nt; ++t) th.emplace_back(worker);
+    worker();
+    for (auto& t : th) t.join();
+  }
+  if (dup_row.load() >= 0)
+    return fail(BVMV_EFORMAT, "row " + std::to_string(dup_row.load()) +
+                                  " lists an edge twice (the bicliques and residual must partition the edges)");
+  if (m >= (uint64_t(1) << 32) || ns + nr >= (uint64_t(1) << 32) || nc >= (uint64_t(1) << 32))
+    return fail(BVMV_EINVAL, "biclique format too large for 32-bit offsets");
+  std::unique_ptr<bvmv_biclique> b(new bvmv_biclique());
+  b->device = device;
+  b->n = n;
+  b->m = int64_t(m);
+  b->nbic = nbic;
+  b->s_ids = int64_t(ns);
+  b->c_ids = int64_t(nc);
+  b->res = int64_t(nr);
+  // second pass rows: residual columns, then n + r for the node's bicliques
+  std::vector<uint64_t> rp2(size_t(n) + 1, 0);
+  std::vector<uint32_t> ids2(ns + nr ? ns + nr : 1);
+  for (int64_t i = 0; i < n; ++i) {
+    uint64_t o = rp2[size_t(i)];
+    for (uint64_t k = rptr[i]; k < rptr[i + 1]; ++k) ids2[o++] = rcol[k];
+    for (uint64_t k = mp[size_t(i)]; k < mp[size_t(i) + 1]; ++k) ids2[o++] = uint32_t(n) + memb[k];
+    rp2[size_t(i) + 1] = o;
+  }
+  // the CSR baseline's tile shape: 64 rows, 1024 staged ids, rows over 512 ids
+  // summed by the whole wave, windows up to 512 columns
+  const int rcap = 64, ccap = 1024, long_cols = 512, wcap_max = 512;
+  if (nbic) build_csr_tiles(cptr, cidx, nbic, rcap, ccap, long_cols, wcap_max, b->t_sum, uint64_t(n));
+  build_csr_tiles(rp2.data(), ids2.data(), n, rcap, ccap, long_cols, wcap_max, b->t_row, uint64_t(n));
+  std::vector<uint32_t> cp32(size_t(nbic) + 1), rp32(size_t(n) + 1);
+  for (int64_t r = 0; r <= nbic; ++r) cp32[size_t(r)] = uint32_t(cptr[r]);
+  for (int64_t i = 0; i <= n; ++i) rp32[size_t(i)] = uint32_t(rp2[size_t(i)]);
+  DeviceGuard dg(device);
+  if (dg.err != hipSuccess) return fail(BVMV_EDEVICE, "hipSetDevice failed");
+  static const uint32_t kNoIds = 0;
+  if (dev_upload(&b->d_tsum, b->t_sum.data(), b->t_sum.size()) ||
+      dev_upload(&b->d_trow, b->t_row.data(), b->t_row.size()) ||
+      dev_upload(&b->d_cptr, cp32.data(), cp32.size()) ||
+      dev_upload(&b->d_cidx, nc ? cidx : &kNoIds, nc ? size_t(nc) : 1, 4) ||
+      dev_upload(&b->d_rptr, rp32.data(), rp32.size()) ||
+      dev_upload(&b->d_ridx, ids2.data(), size_t(ns + nr ? ns + nr : 1), 4)) {
+    b->release();
+    return BVMV_ENOMEM;
+  }
+  if (hipMalloc(&b->d_c, size_t(std::max<int64_t>(nbic, 1)) * 8) != hipSuccess) {
+    b->d_c = nullptr;
+    b->release();
+    return fail(BVMV_ENOMEM, "hipMalloc of the biclique sums failed");
+  }
+  auto setup = [&](DevCsr& C, const std::vector<CsrTile>& tiles, const CsrTile* dt, const uint32_t* drp,
+                   const uint32_t* dcol, uint64_t len) {
+    C.tiles = dt;
+    C.rowptr = drp;
+    C.col = dcol;
+    C.ntiles = uint32_t(tiles.size());
+    C.n = uint32_t(n);
+    C.col_len = len + 4;
+    uint32_t cmax = 0, wcap = 0;
+    for (const auto& t : tiles) {
+      if (!(t.nrows & 0x80000000u)) cmax = std::max(cmax, t.ncols);
+      wcap = std::max(wcap, t.winlen);
+    }
+    C.ccap = std::max<uint32_t>(64, (cmax + 63) / 64 * 64);
+    C.wcap = std::max<uint32_t>(64, (wcap + 63) / 64 * 64);
+  };
+  setup(b->Csum, b->t_sum, b->d_tsum, b->d_cptr, b->d_cidx, nc);
+  setup(b->Crow, b->t_row, b->d_trow, b->d_rptr, b->d_ridx, ns + nr);
+  b->Crow.nx = uint32_t(n);
+  size_t lds = 0;
+  for (int prec = 0; prec <= 2; ++prec)
+    lds = std::max({lds, csr_kernel_lds_bytes(b->Csum, prec), csr_kernel_lds_bytes(b->Crow, prec)});
+  if (int rc = check_lds(device, lds)) {
+    b->release();
+    return rc;
+  }
+  b->layout_bytes = int64_t((cp32.size() + rp32.size() + nc + ns + nr) * 4 +
+                            (b->t_sum.size() + b->t_row.size()) * sizeof(CsrTile));
+  *out = b.release();
+  return BVMV_OK;
+}
+
+int bvmv_biclique_multiply(bvmv_biclique* b, const void* x, void* y, int prec, void* stream) {
+  if (!b || !x || !y) return fail(BVMV_EINVAL, "null argument");
+  if (prec < 0 || prec > 2) return fail(BVMV_EINVAL, "bad precision");
+  const size_t vbytes = size_t(b->n) * elem_size(prec);
+  if (ranges_overlap(x, vbytes, y, vbytes)) return fail(BVMV_EINVAL, "x and y must not overlap");
+  DeviceGuard dg(b->device);
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  if (b->nbic) HIP_TRY(launch_csr_multiply(b->Csum, prec, x, b->d_c, s));
+  DevCsr C = b->Crow;
+  C.aux = b->d_c;
+  HIP_TRY(launch_csr_multiply(C, prec, x, y, s));
+  return BVMV_OK;
+}
+
+int bvmv_biclique_get_info(const bvmv_biclique* b, bvmv_biclique_info* out) {
+  if (!b || !out) return fail(BVMV_EINVAL, "null argument");
+  out->n = b->n;
+  out->m = b->m;
+  out->nbic = b->nbic;
+  out->s_ids = b->s_ids;
+  out->c_ids = b->c_ids;
+  out->residual = b->res;
+  out->words = b->s_ids + b->c_ids + b->res;
+  out->layout_bytes = b->layout_bytes;
+  return BVMV_OK;
+}
+
+void bvmv_biclique_free(bvmv_biclique* b) {
+  if (!b) return;
+  {
+    DeviceGuard dg(b->device);
+    b->release();
+  }
+  delete b;
+}
 
 int bvmv_features(bvmv_graph* g, float* F, void* stream) {
   if (!g || !F) return fail(BVMV_EINVAL, "null argument");

@@ -29,8 +29,13 @@ struct DevCsr {
   const uint32_t* col = nullptr;
   uint32_t ntiles = 0;               // a multiple of kTilesPerBlock
   uint32_t ccap = 1024, wcap = 512;
-  uint32_t n = 0;                    // rows = columns
+  uint32_t n = 0;                    // length of x (= rows, except for the biclique sums)
   uint64_t col_len = 0;              // readable elements of col (m plus padding to a 16-byte boundary)
+  // ids at or above nx read aux[id - nx] instead of x[id] (the biclique
+  // product's second pass: a row's bicliques are ids n + r of their sums);
+  // nx = 2^32 - 1 leaves every id to x
+  uint32_t nx = 0xFFFFFFFFu;
+  const void* aux = nullptr;         // the second source (X*), or nullptr
 };
 
 // LDS bytes per block of the single-vector kernels (0 if the mode is unknown);
@@ -69,6 +74,8 @@ struct PRArgs {
 };
 
 hipError_t launch_bv_multiply(const DevLayout& L, int prec, const void* x, void* y, hipStream_t s);
+// y += A x (column blocks after the first)
+hipError_t launch_bv_multiply_add(const DevLayout& L, int prec, const void* x, void* y, hipStream_t s);
 hipError_t launch_bv_degrees(const DevLayout& L, int32_t* deg, hipStream_t s);
 hipError_t launch_bv_pagerank_iter(const DevLayout& L, int prec, const PRArgs& a, hipStream_t s);
 // z = p / d, dangling mass and state reset for the start vector (tile grid)
@@ -95,6 +102,24 @@ hipError_t launch_restart_inputs(const DevLayout& L, int prec, const void* pK, c
 // member's sum of q ends in its state's delta field.
 hipError_t launch_restart_vector(const DevLayout& L, int prec, const void* pK, const float* svec, PRState* st,
                                  void* q, double* slots, int members, hipStream_t s);
+
+// ------------------------------------------------------------ left product
+struct DevLeft {
+  const LeftTile* lt = nullptr;
+  const uint16_t* ent = nullptr;
+  const uint16_t* grp = nullptr;
+  const uint32_t* lanes = nullptr;
+  void* part = nullptr;              // window contributions (row-sum type: double, or float for BVMV_F32)
+  void* cbuf = nullptr;              // c of the rows of tiles with escapes (same type)
+  const LeftEscape* esc = nullptr;
+  const uint32_t* esc_off = nullptr;
+  const uint32_t* cov_off = nullptr;
+  const uint32_t* cov = nullptr;
+  uint32_t n = 0;
+};
+// y = x A: the tiles' window contributions, then one gather per column
+hipError_t launch_bv_left(const DevLayout& L, const DevLeft& D, int prec, const void* x, void* y, hipStream_t s);
+size_t bv_left_lds_bytes(const DevLayout& L, int prec);
 
 // ---------------------------------------------- allocation-free working set
 // Bytes of the fixed device array that holds the working set of the

@@ -8,6 +8,10 @@
 // a renormalisation so that |lo| <= ulp(hi) / 2 (the fast two-sum step, valid
 // because |s| >= |e| after the first step).
 //
+// The same steps in double (DPair, dpair_add) carry the left product's
+// running window prefix, whose terms cancel (an interval adds at its start
+// and subtracts at its end).
+//
 // Used by device code (the tile kernel's reuse levels) and compiled as host
 // code by the exactness tests.
 #pragma once
@@ -18,9 +22,10 @@ struct Pair {
   float hi, lo;
 };
 
-__host__ __device__ __forceinline__ void two_sum(float a, float b, float& s, float& e) {
+template <class T>
+__host__ __device__ __forceinline__ void two_sum(T a, T b, T& s, T& e) {
   s = a + b;
-  const float bp = s - a;
+  const T bp = s - a;
   e = (a - (s - bp)) + (b - bp);
 }
 
@@ -30,6 +35,18 @@ __host__ __device__ __forceinline__ Pair pair_add(Pair a, Pair b) {
   e += a.lo + b.lo;
   const float hi = s + e;
   return Pair{hi, e - (hi - s)};
+}
+
+struct DPair {
+  double hi, lo;
+};
+
+__host__ __device__ __forceinline__ DPair dpair_add(DPair a, DPair b) {
+  double s, e;
+  two_sum(a.hi, b.hi, s, e);
+  e += a.lo + b.lo;
+  const double hi = s + e;
+  return DPair{hi, e - (hi - s)};
 }
 
 }  // namespace bvmv

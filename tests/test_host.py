@@ -496,3 +496,64 @@ def test_kernel_index_replay(tmp_path):
     r = subprocess.run([exe] + files, capture_output=True, text=True, timeout=900)
     assert r.returncode == 0, (r.stdout[-2000:], r.stderr[-3000:])
     assert r.stdout.startswith("ok")
+
+
+def test_biclique_load_rejects_bad_decompositions():
+    """bvmv_biclique_load validates on the host before any device work: an
+    edge listed twice, unsorted or out-of-range ids and bad offsets give
+    BVMV_EFORMAT; a null argument BVMV_EINVAL."""
+    import paper_1708_07271_amd as P
+    g, b = B.planted_bicliques(300, 30, seed=11)
+
+    def bad(**kw):
+        d = dict(n=b.n, sptr=b.sptr.copy(), sidx=b.sidx.copy(), cptr=b.cptr.copy(), cidx=b.cidx.copy(),
+                 rptr=b.rptr.copy(), rcol=b.rcol.copy())
+        d.update(kw)
+        with pytest.raises(P.BvmvError) as e:
+            P.bvmv_biclique_load(B.Bicliques(**d))
+        return e.value.code
+
+    S0, C0 = b.biclique(0)
+    # the residual repeats an edge of biclique 0
+    i, j = int(S0[0]), int(C0[0])
+    rows = [list(b.rcol[int(b.rptr[k]):int(b.rptr[k + 1])]) for k in range(b.n)]
+    rows[i] = sorted(set(rows[i]) | {j})
+    rp = np.concatenate([[0], np.cumsum([len(r) for r in rows])]).astype(np.uint64)
+    rc = np.asarray([v for r in rows for v in r], np.uint32)
+    assert bad(rptr=rp, rcol=rc) == P.BVMV_EFORMAT
+    cidx = b.cidx.copy()
+    cidx[int(b.cptr[0])] = b.n  # out of range
+    assert bad(cidx=cidx) == P.BVMV_EFORMAT
+    if C0.size >= 2:
+        cidx = b.cidx.copy()
+        a = int(b.cptr[0])
+        cidx[a], cidx[a + 1] = cidx[a + 1], cidx[a]  # unsorted
+        assert bad(cidx=cidx) == P.BVMV_EFORMAT
+    sptr = b.sptr.copy()
+    sptr[1] = sptr[2] + 1  # decreasing offsets
+    assert bad(sptr=sptr) == P.BVMV_EFORMAT
+
+
+@pytest.mark.parametrize("case", range(5))
+def test_left_layout_interpreter(case):
+    """The left product's column-wise layout, interpreted on the host as the
+    two device passes read it (bvmv_left_selfcheck): x A exactly for integer
+    x, and within the left product's tolerance (per entry 1e-12 relative plus
+    2^-48 of the largest entry: a column's terms cancel where a row skips an
+    entry of its reference row) for uniform x; on web-like and social-like
+    graphs, 128-row tiles with wide windows, intervals summed entry by entry,
+    and long rows (whose entries all leave the windows)."""
+    import paper_1708_07271_amd as P
+    from oracle import product
+    from tests import tolerances as TOL
+    g, kw = [(B.web_graph(20000, 15.0, 5), {}), (B.social_graph(20000, 40.0, 5000, 2.1, 6), {}),
+             (B.web_graph(5000, 12.0, 7), dict(tile_rows=128, window_cap=512)),
+             (B.web_graph(5000, 12.0, 8), dict(interval_mode=1)),
+             (B.web_graph(3000, 30.0, 9), dict(long_row_bytes=40))][case]
+    enc = B.encode(g)
+    xi = B.integer_x(g.n, 3, 1000)
+    assert np.array_equal(P.bvmv_left_selfcheck(enc.data, xi, **kw), product.left_matvec(g.rowptr, g.col, xi))
+    x = B.uniform_x(g.n, 4)
+    ratio, _ = TOL.within(P.bvmv_left_selfcheck(enc.data, x, **kw), product.left_matvec_exact(g.rowptr, g.col, x),
+                          TOL.F64, TOL.FLOOR["f64"])
+    assert ratio <= 1.0

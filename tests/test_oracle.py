@@ -587,3 +587,146 @@ def test_structural_depth_input_is_normalised():
         k = F[:, 2] * R
         assert np.allclose(k, np.round(k), atol=1e-12) and k.min() == 0.0 and k.max() == R
         assert np.array_equal(F[:, 2] == 0.0, refs == 0)
+
+
+# ------------------------------------------------------------ biclique format
+from oracle import biclique as bic  # noqa: E402
+
+
+def _one_biclique(n, S, C, res=None):
+    """A decomposition of one biclique S x C plus the given residual lists."""
+    res = res or [[] for _ in range(n)]
+    rp = np.zeros(n + 1, dtype=np.uint64)
+    rp[1:] = np.cumsum([len(r) for r in res])
+    cat = [j for r in res for j in sorted(r)]
+    return B.Bicliques(n, np.array([0, len(S)], np.uint64), np.asarray(S, np.uint32),
+                       np.array([0, len(C)], np.uint64), np.asarray(C, np.uint32), rp,
+                       np.asarray(cat, np.uint32))
+
+
+def test_biclique_closed_form_complete_bipartite():
+    """K_{|S|,|C|}: y_i = sum_{j in C} x_j for i in S and 0 elsewhere; with
+    residual edges added, each row also gains its residual targets' x."""
+    n = 40
+    S, C = [3, 4, 9, 20, 21], [0, 5, 6, 7, 30, 39]
+    x = B.integer_x(n, 1, 1000)
+    want = np.zeros(n)
+    want[S] = x[C].sum()
+    b = _one_biclique(n, S, C)
+    assert np.array_equal(bic.paper_product(b, x), want)
+    rp, col = bic.lists(b)
+    assert np.array_equal(product.matvec(rp, col, x), want)
+    res = [[] for _ in range(n)]
+    res[3], res[10], res[39] = [1, 2], [0], [38]
+    b2 = _one_biclique(n, S, C, res)
+    want2 = want.copy()
+    want2[3] += x[1] + x[2]
+    want2[10] += x[0]
+    want2[39] += x[38]
+    assert np.array_equal(bic.paper_product(b2, x), want2)
+    assert np.array_equal(product.matvec(*bic.lists(b2), x), want2)
+
+
+def test_biclique_dense_bruteforce_and_lists():
+    """A planted decomposition: its dense matrix is 0/1 (a partition of the
+    edges) and equals the generator's graph; the paper's two-step product and
+    the per-row sums over the written-out lists equal A @ x."""
+    for seed in (0, 1, 2):
+        g, b = B.planted_bicliques(300, 40, seed=seed)
+        A = bic.dense(b)
+        assert set(np.unique(A).tolist()) <= {0.0, 1.0}
+        rp, col = bic.lists(b)
+        assert np.array_equal(rp, g.rowptr) and np.array_equal(col, g.col)
+        Ag = np.zeros_like(A)
+        for i in range(g.n):
+            Ag[i, g.row(i).astype(np.int64)] = 1.0
+        assert np.array_equal(A, Ag)
+        x = B.uniform_x(g.n, 7 + seed)
+        ref = A @ x
+        for y in (bic.paper_product(b, x), product.matvec(rp, col, x)):
+            assert np.max(np.abs(y - ref) / np.maximum(np.abs(ref), 1e-300)) < 1e-14
+        xi = B.integer_x(g.n, 3, 1000)
+        assert np.array_equal(bic.paper_product(b, xi), A @ xi)
+
+
+def test_biclique_indicator_and_ones():
+    """x = 1 gives the out-degrees; x = e_j gives column j of A, exactly."""
+    g, b = B.planted_bicliques(200, 30, seed=5)
+    deg = np.diff(g.rowptr.astype(np.int64)).astype(np.float64)
+    assert np.array_equal(bic.paper_product(b, np.ones(g.n)), deg)
+    A = bic.dense(b)
+    for j in (0, 17, 199):
+        e = np.zeros(g.n)
+        e[j] = 1.0
+        assert np.array_equal(bic.paper_product(b, e), A[:, j])
+
+
+def test_biclique_miner_partitions_the_edges():
+    """The miner's decomposition of a web-like graph stands for exactly that
+    graph, every biclique is one (each of S_r's rows lists all of C_r), and
+    it stores fewer ids than edges."""
+    g = B.web_graph(5000, 12.0, 21)
+    b = B.biclique_mine(g)
+    rp, col = bic.lists(b)
+    assert np.array_equal(rp, g.rowptr) and np.array_equal(col, g.col)
+    for r in range(0, b.nbic, 97):
+        S, C = b.biclique(r)
+        assert S.size >= 2 and C.size >= 2
+        for i in S.tolist():
+            assert np.all(np.isin(C, g.row(i)))
+    assert b.words() < g.m
+    xi = B.integer_x(g.n, 4, 1000)
+    assert np.array_equal(bic.paper_product(b, xi), product.matvec(g.rowptr, g.col, xi))
+
+
+# --------------------------------------------------------------- left product
+def test_left_product_dense_and_closed_forms():
+    """y = x A against numpy's x @ A on the dense matrix; closed forms: the
+    complete graph gives sum(x) - x_j, the out-star (centre -> leaves) gives
+    x_c on every leaf and 0 at the centre, the in-star gives the leaves' sum
+    at the centre, the path i -> i+1 gives x_{j-1}; x = 1 gives the
+    in-degrees exactly."""
+    for seed in (0, 1):
+        g = B.web_graph(400, 8.0, 30 + seed)
+        A = np.zeros((g.n, g.n))
+        for i in range(g.n):
+            A[i, g.row(i).astype(np.int64)] = 1.0
+        x = B.uniform_x(g.n, 5 + seed)
+        ref = x @ A
+        for y in (product.left_matvec(g.rowptr, g.col, x), product.left_matvec_exact(g.rowptr, g.col, x)):
+            assert np.max(np.abs(y - ref) / np.maximum(np.abs(ref), 1e-300)) < 1e-14
+        indeg = np.bincount(g.col.astype(np.int64), minlength=g.n).astype(np.float64)
+        assert np.array_equal(product.left_matvec(g.rowptr, g.col, np.ones(g.n)), indeg)
+    n = 12
+    x = B.integer_x(n, 2, 1000)
+    g = B.complete_graph(n)
+    assert np.array_equal(product.left_matvec(g.rowptr, g.col, x), x.sum() - x)
+    g = B.star_graph(n, 0, "out")
+    want = np.full(n, x[0])
+    want[0] = 0.0
+    assert np.array_equal(product.left_matvec(g.rowptr, g.col, x), want)
+    g = B.star_graph(n, 0, "in")
+    want = np.zeros(n)
+    want[0] = x[1:].sum()
+    assert np.array_equal(product.left_matvec(g.rowptr, g.col, x), want)
+    g = B.path_graph(n)
+    want = np.concatenate([[0.0], x[:-1]])
+    assert np.array_equal(product.left_matvec(g.rowptr, g.col, x), want)
+
+
+def test_left_product_through_the_difference_form():
+    """x A = c A' with c = x (I - R)^{-1}: exact for integer x, within
+    rounding otherwise; equals x A of the transposed lists' product."""
+    g = B.web_graph(3000, 12.0, 33)
+    enc = B.encode(g)
+    rowptr, col, refs, _ = bvdecode.decode(enc.data)
+    r, plus, minus, _ = product.difference_form(rowptr, col, refs)
+    xi = B.integer_x(g.n, 3, 1000)
+    want = product.left_matvec(g.rowptr, g.col, xi)
+    assert np.array_equal(product.left_reuse_product(r, plus, minus, xi), want)
+    gt = g.transpose()
+    assert np.array_equal(product.matvec(gt.rowptr, gt.col, xi), want)
+    x = B.uniform_x(g.n, 4)
+    ex = product.left_matvec_exact(g.rowptr, g.col, x)
+    nz = ex != 0
+    assert np.max(np.abs(product.left_reuse_product(r, plus, minus, x)[nz] - ex[nz]) / ex[nz]) < 1e-12

@@ -21,6 +21,10 @@ PRODUCT_PINS = [
     (T.test_proposition_reuse_equals_plain, ()),
     (T.test_difference_form_rule, ()),
 ]
+LEFT_PINS = [
+    (T.test_left_product_dense_and_closed_forms, ()),
+    (T.test_left_product_through_the_difference_form, ()),
+]
 PAGERANK_PINS = [(T.test_pagerank_dense_solve, (s,)) for s in (0, 1, 2)] + [
     (T.test_pagerank_closed_forms, ()),
     (T.test_pagerank_degenerate, ()),
@@ -60,8 +64,35 @@ RESTART_PINS = [
     (T.test_restart_kept_only_under_the_contraction_bound, ()),
 ]
 
+BICLIQUE_PINS = [
+    (T.test_biclique_closed_form_complete_bipartite, ()),
+    (T.test_biclique_dense_bruteforce_and_lists, ()),
+    (T.test_biclique_indicator_and_ones, ()),
+    (T.test_biclique_miner_partitions_the_edges, ()),
+]
+
 # (id, oracle module, source text, mistaken text, pins)
 MUTANTS = [
+    # left product: x A by definition, and through c = x (I - R)^{-1}
+    ("left-product-not-transposed", "oracle.product",
+     "return np.bincount(np.asarray(col, dtype=np.int64), weights=x[rows], minlength=n).astype(np.float64)",
+     "return np.bincount(rows, weights=x[np.asarray(col, dtype=np.int64)], minlength=n).astype(np.float64)",
+     LEFT_PINS),
+    ("left-recurrence-forward-order", "oracle.product", "    for i in range(n - 1, -1, -1):\n        if r[i] >= 0:",
+     "    for i in range(n):\n        if r[i] >= 0:", LEFT_PINS),
+    ("left-recurrence-dropped", "oracle.product", "            c[r[i]] += c[i]", "            pass", LEFT_PINS),
+    ("left-minus-sign", "oracle.product", "            y[j] -= c[i]", "            y[j] += c[i]", LEFT_PINS),
+    # biclique format: c_r over C_r, added to the rows of S_r, plus residual edges
+    ("biclique-sum-over-S", "oracle.biclique", "C = b.cidx[int(b.cptr[r]):int(b.cptr[r + 1])].astype(np.int64)\n        c[r]",
+     "C = b.sidx[int(b.sptr[r]):int(b.sptr[r + 1])].astype(np.int64)\n        c[r]", BICLIQUE_PINS),
+    ("biclique-scatter-transposed", "oracle.biclique", "        y[S] += c[r]",
+     "        y[b.cidx[int(b.cptr[r]):int(b.cptr[r + 1])].astype(np.int64)] += c[r]", BICLIQUE_PINS),
+    ("biclique-residual-dropped", "oracle.biclique", "            y[i] += np.sum(x[R])", "            pass",
+     BICLIQUE_PINS),
+    ("biclique-lists-residual-dropped", "oracle.biclique",
+     "        rows[i].extend(b.rcol[int(b.rptr[i]):int(b.rptr[i + 1])].tolist())", "        pass", BICLIQUE_PINS),
+    ("biclique-scatter-set-not-added", "oracle.biclique", "        y[S] += c[r]", "        y[S] = c[r]",
+     BICLIQUE_PINS),
     # product: the definition y_i = sum of x over row i, and the reuse algorithm
     ("row-last-entry-dropped", "oracle.product", "y[i] = math.fsum(x[col[a:b]].tolist())",
      "y[i] = math.fsum(x[col[a:b - 1]].tolist())", PRODUCT_PINS),
