@@ -83,30 +83,31 @@ class Flusher:
 
 
 def time_flushed(fn, steps, warmup, flush, torch):
-    """ms per launch with cold caches: `steps` rounds of (flush, launch) and
-    `steps` rounds of the flush alone, each pair of sequences timed by HIP
-    events on the current stream; the launch time is the difference of the
-    two means, so neither event overhead nor the flush is counted.  Returns
-    (ms per launch, ms per flush)."""
+    """ms per launch with cold caches: `steps` rounds of (flush, launch), each
+    launch bracketed by its own pair of HIP events on the current stream (the
+    stream the library launches on), recorded after the flush; the mean of
+    the per-launch times.  Returns (ms per launch, ms per flush)."""
     for _ in range(warmup):
         flush()
         fn()
     torch.cuda.synchronize()
     s = torch.cuda.current_stream()
-    ev = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
-    ev[0].record(s)
-    for _ in range(steps):
+    e0 = [torch.cuda.Event(enable_timing=True) for _ in range(steps)]
+    e1 = [torch.cuda.Event(enable_timing=True) for _ in range(steps)]
+    f0 = torch.cuda.Event(enable_timing=True)
+    f1 = torch.cuda.Event(enable_timing=True)
+    for k in range(steps):
+        if k == 0:
+            f0.record(s)
         flush()
+        if k == 0:
+            f1.record(s)
+        e0[k].record(s)
         fn()
-    ev[1].record(s)
-    ev[2].record(s)
-    for _ in range(steps):
-        flush()
-    ev[3].record(s)
+        e1[k].record(s)
     torch.cuda.synchronize()
-    both = ev[0].elapsed_time(ev[1]) / steps
-    alone = ev[2].elapsed_time(ev[3]) / steps
-    return both - alone, alone
+    per = [a.elapsed_time(b) for a, b in zip(e0, e1)]
+    return sum(per) / len(per), f0.elapsed_time(f1)
 
 
 def cpu_baseline(g, x64, budget_s):
@@ -522,6 +523,9 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
     ap.add_argument("--only", choices=["bv", "csr", "all"], default="all",
                     help="restrict the timed kernels (profiling runs)")
+    ap.add_argument("--timing", choices=["both", "flushed", "warm"], default="both",
+                    help="time launches from HBM (after a 1 GiB write), back to back, or both (profiling runs "
+                         "take one, so that the profiler's per-kernel average is that figure)")
     ap.add_argument("--tile-rows", type=int, default=0)
     ap.add_argument("--window-cap", type=int, default=0)
     ap.add_argument("--stage-bytes", type=int, default=0)
@@ -604,14 +608,19 @@ def main():
 
     flush = Flusher(torch, dev)
     ms_bv = ms_csr = warm_bv = warm_csr = ms_flush = None
+    def both(fn):
+        ms = fl = warm = None
+        if args.timing in ("both", "flushed"):
+            ms, fl = time_flushed(fn, args.steps, args.warmup, flush, torch)
+        if args.timing in ("both", "warm"):
+            warm = time_launches(fn, args.steps, args.warmup, torch)
+        return ms if ms is not None else warm, fl, warm if warm is not None else ms
+
     if args.only in ("bv", "all"):
-        ms_bv, ms_flush = time_flushed(lambda: P.bvmv_multiply(G, x, y, prec), args.steps, args.warmup, flush, torch)
-        warm_bv = time_launches(lambda: P.bvmv_multiply(G, x, y, prec), args.steps, args.warmup, torch)
-        log("compressed product: %.4f ms from HBM (flush %.3f ms), %.4f ms cache-warm" % (ms_bv, ms_flush, warm_bv))
+        ms_bv, ms_flush, warm_bv = both(lambda: P.bvmv_multiply(G, x, y, prec))
+        log("compressed product: %.4f ms from HBM (flush %s ms), %.4f ms cache-warm" % (ms_bv, ms_flush, warm_bv))
     if args.only in ("csr", "all"):
-        ms_csr, ms_flush = time_flushed(lambda: P.bvmv_csr_multiply(C, x, y2, prec), args.steps, args.warmup, flush,
-                                        torch)
-        warm_csr = time_launches(lambda: P.bvmv_csr_multiply(C, x, y2, prec), args.steps, args.warmup, torch)
+        ms_csr, ms_flush, warm_csr = both(lambda: P.bvmv_csr_multiply(C, x, y2, prec))
         log("csr product: %.4f ms from HBM, %.4f ms cache-warm" % (ms_csr, warm_csr))
     del flush
     if ms_bv is None:
@@ -654,10 +663,13 @@ def main():
         "data": "synthetic",
         "config": {"workload": args.workload, "n": g.n, "m": g.m, "precision": "f32 two-sum compensated",
                    "x": "uniform[0,1) float32, seed 102",
-                   "timing": "each launch after a 1 GiB device write (L2 and MALL flushed): inputs read from HBM"},
+                   "timing": ("each launch after a 1 GiB device write (L2 and MALL flushed): inputs read from HBM; "
+                              "per-launch HIP events, mean" if args.timing != "warm" else
+                              "back-to-back launches (cache-warm)")},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": PEAK_HBM_GBS, "unit": "GB/s",
                      "frac": achieved / PEAK_HBM_GBS, "traffic": load_traffic("bv_wave_kernel", args.workload),
-                     "kernel": "bv_wave_kernel", "alg_bytes_per_launch": alg_bytes, "caches": "flushed"},
+                     "kernel": "bv_wave_kernel", "alg_bytes_per_launch": alg_bytes,
+                     "caches": "flushed" if args.timing != "warm" else "warm"},
         "mall_warm": {"ms": warm_bv, "edges_per_s": g.m / (warm_bv * 1e-3),
                       "achieved_GBs": alg_bytes / (warm_bv * 1e-3) / 1e9,
                       "frac": alg_bytes / (warm_bv * 1e-3) / 1e9 / PEAK_HBM_GBS,

@@ -39,7 +39,7 @@ def _left(P, G, x, prec):
 
 def _ok(y, ref, name):
     tol = TOL.F64 if name == "f64" else TOL.F32C if name == "f32c" else TOL.F32_NAIVE
-    ratio, rel_big = TOL.within(y, ref, tol, TOL.FLOOR["f64" if name == "f64" else "f32c"])
+    ratio, rel_big = TOL.within(y, ref, tol, TOL.FLOOR[name])
     print("left %s: ratio %.3g, relative error above the floor %.3g" % (name, ratio, rel_big), flush=True)
     return ratio <= 1.0
 

@@ -30,9 +30,10 @@ F32_NAIVE = 1e-3
 
 # units of max|p*|: 2^-48 is 16 double roundings of the largest entry (the
 # window prefixes and reference sums a row subtracts are sums of at most a
-# few hundred entries, all <= max|p*|); the float modes carry reuse chains as
-# TwoSum pairs of ~48 significant bits, and round the result to float
-FLOOR = {"f64": 2.0 ** -48, "f32c": 2.0 ** -40}
+# few hundred entries, all <= max|p*|); the two-sum mode carries reuse chains
+# as TwoSum pairs of ~48 significant bits and rounds the result to float;
+# the uncompensated float mode subtracts in float: 16 float roundings
+FLOOR = {"f64": 2.0 ** -48, "f32c": 2.0 ** -40, "f32": 2.0 ** -20}
 
 
 def within(p, p_ref, tol, floor):
