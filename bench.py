@@ -83,31 +83,42 @@ class Flusher:
 
 
 def time_flushed(fn, steps, warmup, flush, torch):
-    """ms per launch with cold caches: `steps` rounds of (flush, launch), each
-    launch bracketed by its own pair of HIP events on the current stream (the
-    stream the library launches on), recorded after the flush; the mean of
-    the per-launch times.  Returns (ms per launch, ms per flush)."""
+    """ms per launch with cold caches.  `steps` rounds of (flush, launch) and
+    `steps` rounds of the flush alone are each timed between two HIP events on
+    the current stream (the stream the library launches on); the launch time
+    is the difference of the two means, so neither the flush nor per-launch
+    event overhead is counted (this is the figure the profiler's per-kernel
+    average agrees with).  Also returns the mean of per-launch event pairs
+    recorded around each launch of a third sequence, which adds each event's
+    own overhead (reported beside).  Returns (ms per launch, ms per flush,
+    per-launch event ms)."""
     for _ in range(warmup):
         flush()
         fn()
     torch.cuda.synchronize()
     s = torch.cuda.current_stream()
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
+    ev[0].record(s)
+    for _ in range(steps):
+        flush()
+        fn()
+    ev[1].record(s)
+    ev[2].record(s)
+    for _ in range(steps):
+        flush()
+    ev[3].record(s)
     e0 = [torch.cuda.Event(enable_timing=True) for _ in range(steps)]
     e1 = [torch.cuda.Event(enable_timing=True) for _ in range(steps)]
-    f0 = torch.cuda.Event(enable_timing=True)
-    f1 = torch.cuda.Event(enable_timing=True)
     for k in range(steps):
-        if k == 0:
-            f0.record(s)
         flush()
-        if k == 0:
-            f1.record(s)
         e0[k].record(s)
         fn()
         e1[k].record(s)
     torch.cuda.synchronize()
+    both = ev[0].elapsed_time(ev[1]) / steps
+    alone = ev[2].elapsed_time(ev[3]) / steps
     per = [a.elapsed_time(b) for a, b in zip(e0, e1)]
-    return sum(per) / len(per), f0.elapsed_time(f1)
+    return both - alone, alone, sum(per) / len(per)
 
 
 def cpu_baseline(g, x64, budget_s):
@@ -254,7 +265,7 @@ def bench_formats(args, B, P, np, torch, dev):
     for name, fn, nbytes in (("bv", lambda: P.bvmv_multiply(G, x, y, prec), info["layout_bytes"]),
                              ("biclique", lambda: P.bvmv_biclique_multiply(H, x, y, prec), binfo["layout_bytes"]),
                              ("csr", lambda: P.bvmv_csr_multiply(C, x, y, prec), C.bytes())):
-        ms, _ = time_flushed(fn, args.steps, args.warmup, flush, torch)
+        ms, _, _ = time_flushed(fn, args.steps, args.warmup, flush, torch)
         warm = time_launches(fn, args.steps, args.warmup, torch)
         alg = nbytes + 8 * g.n
         rows[name] = {"layout_bytes": nbytes, "bytes_per_edge": nbytes / g.m, "ms": ms,
@@ -290,11 +301,11 @@ def bench_sweep(args, B, P, np, torch, dev):
     steps, warmup = max(args.steps // 5, 20), max(args.warmup // 5, 5)
 
     def timed(fn):
-        ms, _ = time_flushed(fn, steps, warmup, flush, torch)
+        ms, _, _ = time_flushed(fn, steps, warmup, flush, torch)
         return ms, time_launches(fn, steps, warmup, torch)
 
     windows = []
-    for W, R in ((1, 1), (3, 3), (7, 3), (7, 7), (15, 3), (15, 15)):
+    for W, R in (((1, 1), (3, 3), (7, 3), (7, 7), (15, 3), (15, 15)) if args.sweep_what != "blocks" else ()):
         enc = B.encode(g, W=W, R=R)
         G = P.bvmv_load(enc.data)
         info = G.info()
@@ -307,7 +318,7 @@ def bench_sweep(args, B, P, np, torch, dev):
             W, R, windows[-1]["bits_per_edge"], windows[-1]["m_over_m_prime"], ms, warm))
         del G, enc
     blocks = []
-    for nb in (1, 2, 4, 8):
+    for nb in ([int(v) for v in args.sweep_blocks.split(",")] if args.sweep_what != "windows" else []):
         bounds, parts = B.column_blocks(g, nb)
         encs = [B.encode(p_) for p_ in parts]
         Gs = [P.bvmv_load(e.data) for e in encs]
@@ -326,6 +337,98 @@ def bench_sweep(args, B, P, np, torch, dev):
     out = {"mode": "window-and-column-block-sweep", "workload": wl, "n": g.n, "m": g.m,
            "dtype": "f32 two-sum compensated", "timing": "each launch after a 1 GiB device write",
            "windows": windows, "column_blocks": blocks}
+    print(json.dumps(out), flush=True)
+
+
+def bench_structural_start(args, B, P, np, torch, dev):
+    """The first warm-start design, kept as a control: a start vector
+    predicted from structure alone.  The network (12 -> 64 -> 64 -> 1) sees
+    the 8 structural inputs (the trajectory inputs 8..11 held at 0) and is
+    trained on the target log(n p*) of the method's own FP64 PageRank (to
+    1e-12) of the same generated graphs as the learned restarts (n
+    log-uniform in [1e5, 1e6], mean degree 20, seeds 2000 + i); the start is
+    p0 = exp(s) / sum exp(s), kept only if its first step's residual beats the
+    uniform start's (the one-step fallback).  On the unseen n = 5e6 graph
+    (seed 3000) it is run beside the uniform start and an in-degree
+    proportional start (p0 = (indeg + 1) / sum, a non-learned control).
+    The start vectors are formed with torch here (a bench-side control, not a
+    library path); seconds are reported for PageRank alone and with the
+    inputs, the network and the start."""
+    rng = np.random.default_rng(2000)
+    sizes = np.round(10 ** rng.uniform(5, 6, args.warm_graphs)).astype(np.int64)
+    Fs, Ts = [], []
+    t0 = time.perf_counter()
+    for i, n in enumerate(sizes):
+        g = B.web_graph(int(n), 20.0, 2000 + i)
+        G = P.bvmv_load(B.encode(g).data)
+        ps = torch.empty(g.n, dtype=torch.float64, device=dev)
+        P.bvmv_pagerank(G, ps, tol=1e-12, max_iter=5000, prec=P.BVMV_F64)
+        F = torch.zeros(g.n, P.NFEAT, device=dev)
+        P.bvmv_features(G, F)
+        F[:, 8:] = 0.0
+        Fs.append(F)
+        Ts.append(torch.log(g.n * ps).float())
+        del G, g
+        if i % 20 == 0:
+            log("structural data: graph %d/%d (%.1fs)" % (i, len(sizes), time.perf_counter() - t0))
+    F = torch.cat(Fs)
+    T = torch.cat(Ts).contiguous()
+    del Fs, Ts
+    t_data = time.perf_counter() - t0
+    m = P.bvmv_mlp_create(B.mlp_init_params(4000))
+    loss = torch.empty(1, device=dev)
+    gen = torch.Generator(device=dev).manual_seed(4000)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    losses = []
+    for it in range(args.warm_steps):
+        lr = 3e-3 * (0.5 * (1 + math.cos(math.pi * it / args.warm_steps)) + 0.01)
+        idx = torch.randint(0, F.shape[0], (8192,), device=dev, generator=gen)
+        P.bvmv_mlp_train_step(m, F[idx].contiguous(), T[idx].contiguous(), lr, loss)
+        if it % max(1, args.warm_steps // 10) == 0 or it == args.warm_steps - 1:
+            losses.append(float(loss.item()))
+    torch.cuda.synchronize()
+    t_train = time.perf_counter() - t0
+    log("structural training: %d steps in %.2fs, loss %s" % (args.warm_steps, t_train, ["%.4f" % v for v in losses]))
+    del F, T
+    g = B.web_graph(args.warm_test_n, 20.0, 3000)
+    G = P.bvmv_load(B.encode(g).data)
+    n = g.n
+    p = torch.empty(n, device=dev)
+
+    def timed(fn):
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        r = fn()
+        torch.cuda.synchronize()
+        return r, time.perf_counter() - t
+
+    def learned_start():
+        Ft = torch.zeros(n, P.NFEAT, device=dev)
+        P.bvmv_features(G, Ft)
+        Ft[:, 8:] = 0.0
+        sv = torch.empty(n, device=dev)
+        P.bvmv_mlp_forward(m, Ft, sv)
+        return torch.softmax(sv, 0)
+
+    P.bvmv_pagerank(G, p)  # graph capture
+    p0_learned, t_start = timed(learned_start)
+    indeg = torch.from_numpy(np.bincount(g.col.astype(np.int64), minlength=n).astype(np.float32)).to(dev)
+    p0_degree = (indeg + 1.0) / float((indeg + 1.0).sum())
+    runs = {}
+    for name, start in (("uniform", None), ("structural_learned", p0_learned), ("indegree", p0_degree)):
+        ts = []
+        for _ in range(3):
+            (r,), t = timed(lambda: P.bvmv_pagerank_detail(G, p, start=start, fallback_check=1 if start is not None
+                                                             else 0))
+            ts.append(t)
+        runs[name] = dict(iters=r["iters"], used_start=r["used_start"], converged=bool(r["converged"]),
+                          seconds=float(np.median(ts)))
+        log("structural start %s: %s" % (name, runs[name]))
+    runs["structural_learned"]["seconds_with_start"] = runs["structural_learned"]["seconds"] + t_start
+    out = {"mode": "structural-start-control", "train_graphs": len(sizes), "train_nodes": int(sizes.sum()),
+           "train_steps": args.warm_steps, "train_seconds": t_train, "data_seconds": t_data, "loss_trace": losses,
+           "test_n": n, "test_m": g.m, "dtype": "f32 two-sum compensated", "start_seconds": t_start, **runs}
     print(json.dumps(out), flush=True)
 
 
@@ -545,6 +648,11 @@ def main():
                          "(flushed and cache-warm)")
     ap.add_argument("--sweep", action="store_true",
                     help="reference window W (and chain bound R) sweep and column-block splitting of --workload")
+    ap.add_argument("--sweep-what", choices=["both", "windows", "blocks"], default="both")
+    ap.add_argument("--sweep-blocks", default="1,2,4,8", help="column-block counts of --sweep")
+    ap.add_argument("--structural-start", action="store_true",
+                    help="control: a start vector predicted from structure alone (the first warm-start design) "
+                         "against the uniform and an in-degree start")
     ap.add_argument("--warm-graphs", type=int, default=200)
     ap.add_argument("--warm-steps", type=int, default=3000)
     ap.add_argument("--warm-test-n", type=int, default=5_000_000)
@@ -580,6 +688,8 @@ def main():
         return bench_batch(args, B, P, np, torch, dev)
     if args.warm_start:
         return bench_warm(args, B, P, np, torch, dev)
+    if args.structural_start:
+        return bench_structural_start(args, B, P, np, torch, dev)
     if args.ragged:
         return bench_ragged(args, B, P, np, torch, dev)
     if args.social:
@@ -608,19 +718,21 @@ def main():
 
     flush = Flusher(torch, dev)
     ms_bv = ms_csr = warm_bv = warm_csr = ms_flush = None
-    def both(fn):
+    per_launch = {}
+
+    def both(fn, name):
         ms = fl = warm = None
         if args.timing in ("both", "flushed"):
-            ms, fl = time_flushed(fn, args.steps, args.warmup, flush, torch)
+            ms, fl, per_launch[name] = time_flushed(fn, args.steps, args.warmup, flush, torch)
         if args.timing in ("both", "warm"):
             warm = time_launches(fn, args.steps, args.warmup, torch)
         return ms if ms is not None else warm, fl, warm if warm is not None else ms
 
     if args.only in ("bv", "all"):
-        ms_bv, ms_flush, warm_bv = both(lambda: P.bvmv_multiply(G, x, y, prec))
+        ms_bv, ms_flush, warm_bv = both(lambda: P.bvmv_multiply(G, x, y, prec), "bv")
         log("compressed product: %.4f ms from HBM (flush %s ms), %.4f ms cache-warm" % (ms_bv, ms_flush, warm_bv))
     if args.only in ("csr", "all"):
-        ms_csr, ms_flush, warm_csr = both(lambda: P.bvmv_csr_multiply(C, x, y2, prec))
+        ms_csr, ms_flush, warm_csr = both(lambda: P.bvmv_csr_multiply(C, x, y2, prec), "csr")
         log("csr product: %.4f ms from HBM, %.4f ms cache-warm" % (ms_csr, warm_csr))
     del flush
     if ms_bv is None:
@@ -664,8 +776,9 @@ def main():
         "config": {"workload": args.workload, "n": g.n, "m": g.m, "precision": "f32 two-sum compensated",
                    "x": "uniform[0,1) float32, seed 102",
                    "timing": ("each launch after a 1 GiB device write (L2 and MALL flushed): inputs read from HBM; "
-                              "per-launch HIP events, mean" if args.timing != "warm" else
-                              "back-to-back launches (cache-warm)")},
+                              "mean of (flush + launch) less mean of flush alone, HIP events on the library's "
+                              "stream" if args.timing != "warm" else "back-to-back launches (cache-warm)"),
+                   "per_launch_event_ms": per_launch.get("bv")},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": PEAK_HBM_GBS, "unit": "GB/s",
                      "frac": achieved / PEAK_HBM_GBS, "traffic": load_traffic("bv_wave_kernel", args.workload),
                      "kernel": "bv_wave_kernel", "alg_bytes_per_launch": alg_bytes,
