@@ -272,6 +272,19 @@ def bench_formats(args, B, P, np, torch, dev):
                       "edges_per_s": g.m / (ms * 1e-3), "alg_GBs": alg / (ms * 1e-3) / 1e9,
                       "frac_hbm": alg / (ms * 1e-3) / 1e9 / PEAK_HBM_GBS, "mall_warm_ms": warm}
         log("%s: %.4f ms from HBM (%.0f GB/s), %.4f ms warm" % (name, ms, rows[name]["alg_GBs"], warm))
+    # the left product y = x A: on the loaded rows (no transposed graph), and
+    # as the paper runs it, a right product with the transposed graph
+    Gt = P.bvmv_load(B.encode(g.transpose()).data)
+    tinfo = Gt.info()
+    P.bvmv_multiply_left(G, x, y, prec)  # builds the column-wise layout once
+    for name, fn, nbytes in (("left_on_rows", lambda: P.bvmv_multiply_left(G, x, y, prec), None),
+                             ("left_as_transposed", lambda: P.bvmv_multiply(Gt, x, y, prec), tinfo["layout_bytes"])):
+        ms, _, _ = time_flushed(fn, args.steps, args.warmup, flush, torch)
+        warm = time_launches(fn, args.steps, args.warmup, torch)
+        rows[name] = {"ms": ms, "edges_per_s": g.m / (ms * 1e-3), "mall_warm_ms": warm}
+        if nbytes is not None:
+            rows[name]["layout_bytes"] = nbytes
+        log("%s: %.4f ms from HBM, %.4f ms warm" % (name, ms, warm))
     out = {"mode": "formats", "workload": wl, "n": g.n, "m": g.m, "dtype": "f32 two-sum compensated",
            "timing": "each launch after a 1 GiB device write; mall_warm_ms back to back",
            "bv_m_over_m_prime": g.m / max(info["m_prime"], 1),
