@@ -25,6 +25,7 @@
 //   6. epilogue: store y, or the PageRank update.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <mutex>
 #include <type_traits>
 
@@ -918,7 +919,10 @@ __device__ __forceinline__ void issue_loads(const DevLayout& L, const TileDesc& 
                                             TileLoads<M, RPL, SV>& ld) {
   const uint32_t lane = lane_id(), r0 = lane * RPL;
   const uint32_t n16 = td.n16;
-  if (n16) {
+  // Every load is unconditional (a tile without singles reads its stream's
+  // first words, one without a window the value at win0, which is below n),
+  // so that no branch join waits for a load before the tile's data is used.
+  {
     const uint32_t* g16 = reinterpret_cast<const uint32_t*>(L.data + td.data16);
     const Chunk<2> ch(n16, flat_chunk<2>(n16));
     // the running-sum mode zeros the words past the lane's chunk before use;
@@ -934,8 +938,7 @@ __device__ __forceinline__ void issue_loads(const DevLayout& L, const TileDesc& 
     ld.inf[q] = L.info[r];
     ld.ns[q] = uint32_t(L.ns[r]);
   }
-  if constexpr (!M::kInt && !Src::kMulti)
-    if (td.winlen) load_window(src, td.win0, td.winlen, 0, ld.xs);
+  if constexpr (!M::kInt && !Src::kMulti) load_window(src, td.win0, max(td.winlen, 1u), 0, ld.xs);
 }
 
 // Stage a tile's x window of n values into the LDS array Z (doubles): Z[0] =
@@ -1027,6 +1030,10 @@ __device__ __forceinline__ void process_tile(const DevLayout& L, const TileDesc&
   const TileCtx tc{td.row0, td.nrows, td.graph, slot};
   auto S = epi.prepare(tc);
   if (epi.all_done(S)) return;  // every vector is done: the whole block returns
+  // the first vector's epilogue loads: with one vector they go out with the
+  // tile's own loads (with several, after the decode, to spare registers)
+  decltype(epi.fetch(tc, 0)) f_next;
+  if constexpr (!Src::kMulti) f_next = epi.fetch(tc, 0);
   const uint32_t lane = lane_id();
   const uint32_t nrows = td.nrows;
   const int64_t win0 = td.win0;
@@ -1091,9 +1098,10 @@ __device__ __forceinline__ void process_tile(const DevLayout& L, const TileDesc&
   wave_sync();
 
   X xs_next[SV];
-  auto f_next = epi.fetch(tc, 0);
-  if constexpr (Src::kMulti)
-    if (winlen) load_window(src, win0, winlen, 0, xs_next);
+  if constexpr (Src::kMulti) {
+    f_next = epi.fetch(tc, 0);
+    load_window(src, win0, max(winlen, 1u), 0, xs_next);
+  }
   for (int col = 0; col < src.count(); ++col) {
   const auto f_cur = f_next;
   const X* xcol = src.col(col);
@@ -1107,7 +1115,7 @@ __device__ __forceinline__ void process_tile(const DevLayout& L, const TileDesc&
       for (int j = 0; j < SV; ++j) xs[j] = xs_next[j];
       if (col + 1 < src.count()) {
         f_next = epi.fetch(tc, col + 1);
-        if (winlen) load_window(src, win0, winlen, col + 1, xs_next);
+        load_window(src, win0, max(winlen, 1u), col + 1, xs_next);
       }
       if (epi.skip(S, col)) continue;
       stage_regs<X, SV>(xs, [&](uint32_t j) { return xcol[win0 + j]; }, winlen, td.nint != 0, Z);

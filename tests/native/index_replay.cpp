@@ -6,8 +6,10 @@
 //     last) while r < the wave's largest dword count);
 //   - the clamped rounds and row-end counts of the other passes and of the
 //     wide entries;
-//   - row info / count loads, x-window loads, Z indices of the singles, and
-//     the columns the wide and long entries gather.
+//   - row info / count loads, x-window loads (every tile loads its first
+//     stream round and window values, also without singles or a window),
+//     Z indices of the singles, and the columns the wide and long entries
+//     gather.
 // Every stream dword index must lie below the device data array's size plus
 // its zero padding (kDataPadBytes), every gathered column below n, every Z
 // index inside the staged window.  Exit status 0 when all hold; built with g++
@@ -64,6 +66,22 @@ static void replay(const HostLayout& hl, int64_t n) {
     if (td.nrows && uint64_t(td.row0) + td.nrows > uint64_t(n)) bad("row", t, td.row0 + td.nrows, n);
     if (td.winlen && uint64_t(td.win0) + td.winlen > uint64_t(n)) bad("window end", t, td.win0 + td.winlen, n);
     const uint32_t n16 = td.n16, nwide = td.nwide;
+    // the tile's first loads are unconditional: the first stream round (also
+    // for a tile without singles) and the lanes' first window values, at
+    // win0 + min(b + j, max(winlen, 1) - 1) (also for a tile without a window)
+    {
+      const uint32_t C = flat_chunk(n16, 2);
+      for (uint32_t lane = 0; lane < 64; ++lane) {
+        const ChunkH ch(lane, n16, C, 2);
+        const uint64_t hi0 = base + std::min(ch.d0, ch.last) + kRoundW - 1;
+        if (hi0 >= data_dw) bad("unconditional first-round dword", t, hi0, data_dw);
+        const uint32_t wl = std::max(td.winlen, 1u), w = (wl + 63) / 64, b = std::min(wl, lane * w);
+        for (uint32_t j = 0; j < 16; ++j) {
+          const uint64_t col = uint64_t(td.win0) + std::min(b + j, wl - 1);
+          if (col >= uint64_t(n)) bad("window value column", t, col, n);
+        }
+      }
+    }
     if (n16) {
       const uint32_t C = flat_chunk(n16, 2);
       uint32_t ndmax = (std::min(C, n16) + 1) / 2;
