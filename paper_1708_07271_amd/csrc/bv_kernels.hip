@@ -504,13 +504,18 @@ struct WaveCarve {
   static constexpr size_t kSlot = sizeof(PAcc) > sizeof(CAcc) ? sizeof(PAcc) : sizeof(CAcc);
   __host__ __device__ static constexpr size_t seg() { return 0; }
   __host__ __device__ static constexpr size_t y() { return 0; }
-  // (kRows + 64 slots: the running-sum pass keeps one more slot per lane)
-  __host__ __device__ static constexpr size_t carry() { return align16((kRows + 64) * kSlot); }
+  // kRows + 64 slots: the running-sum pass keeps one more slot per lane.  A
+  // pass cut at row-end bits has at most one piece per row, so its 64 lane
+  // carries take the slots past the rows (the wide pass starts after the
+  // running sums are read).
+  __host__ __device__ static constexpr size_t carry() { return kRows * sizeof(PAcc); }
+  static_assert(kRows * sizeof(PAcc) + 64 * sizeof(PAcc) <= (kRows + 64) * kSlot, "carries inside the slots");
   // the window array Z, placed 8 bytes past a 16-byte boundary so that Z + 1
   // is 16-byte aligned
-  __host__ __device__ static constexpr size_t Z() { return carry() + align16(64 * sizeof(PAcc)) + 8; }
+  __host__ __device__ static constexpr size_t Z() { return align16((kRows + 64) * kSlot) + 8; }
   __host__ __device__ size_t wave_bytes() const { return align16(Z() + (M::kInt ? 0 : (2 * size_t(WC) + 2) * 8)); }
-  __host__ __device__ size_t block_bytes() const { return kWaves * wave_bytes() + 256; }
+  // the waves' regions, then the block's PageRank partials (two doubles a wave)
+  __host__ __device__ size_t block_bytes() const { return kWaves * wave_bytes() + kWaves * 16; }
 };
 
 struct TileCtx {
@@ -624,6 +629,7 @@ __global__ void __launch_bounds__(kThreads) pr_finish_kernel(PRState* st_all, co
   if (threadIdx.x == 0) {
     st->delta = D;
     if (with_resid) {
+      st->resid_prev = st->resid;
       st->resid = R;
       st->iter += 1;
       if (R < tol) {
@@ -636,6 +642,7 @@ __global__ void __launch_bounds__(kThreads) pr_finish_kernel(PRState* st_all, co
       }
     } else {
       st->resid = 0.0;
+      st->resid_prev = 0.0;
       st->iter = iter0;
       st->done = 0;
       st->converged = 0;

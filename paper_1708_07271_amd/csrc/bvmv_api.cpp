@@ -89,18 +89,24 @@ struct PRWork {
   double* slots = nullptr;
   PRState* h_st = nullptr;  // pinned
   int nst = 0;
-  hipGraphExec_t exec = nullptr;
-  hipGraph_t graph = nullptr;
-  // key of the captured graph
+  // captured runs of iterations, by length: the chunk and its halvings down to 2
+  static constexpr int kGraphs = 12;
+  hipGraphExec_t exec[kGraphs] = {};
+  hipGraph_t graph[kGraphs] = {};
+  int glen[kGraphs] = {};
+  // key of the captured graphs
   const void* key_tele = nullptr;
   double key_beta = -1, key_tol = -1;
   int key_max_iter = -1, key_chunk = -1;
 
   void drop_graph() {
-    if (exec) (void)hipGraphExecDestroy(exec);
-    if (graph) (void)hipGraphDestroy(graph);
-    exec = nullptr;
-    graph = nullptr;
+    for (int i = 0; i < kGraphs; ++i) {
+      if (exec[i]) (void)hipGraphExecDestroy(exec[i]);
+      if (graph[i]) (void)hipGraphDestroy(graph[i]);
+      exec[i] = nullptr;
+      graph[i] = nullptr;
+      glen[i] = 0;
+    }
     key_chunk = -1;
   }
   void release() {
@@ -335,7 +341,7 @@ int upload_layout(bvmv_graph* g) {
     sb = std::max(sb, tile_stage_bytes(t));
   }
   g->L.tcap = std::max<uint32_t>(64, (tcap + 63) / 64 * 64);
-  g->L.wcap = std::max<uint32_t>(64, (wcap + 63) / 64 * 64);
+  g->L.wcap = std::max<uint32_t>(64, (wcap + 3) / 4 * 4);
   g->L.sbytes = std::max<uint32_t>(256, (sb + 255) / 256 * 256);
   size_t need = 0;
   for (int prec = 0; prec <= 2; ++prec) need = std::max(need, bv_kernel_lds_bytes(g->L, prec));
@@ -372,19 +378,61 @@ int read_states(PRWork& w, int members, hipStream_t s) {
   return BVMV_OK;
 }
 
-// Replay a captured chunk of o.chunk iterations, starting from buffer 0,
-// until every member is done; the chunk is captured once and kept with the
-// working set while its key holds.
+// Iterations still to run after a replay: for each member not done, the
+// count at which its residual, contracting by the ratio of its last two
+// residuals, falls below tol (one more, and a whole chunk when the ratio is
+// not yet known or not below 1), at most its iterations left; the largest
+// over the members, rounded up to even.
+int planned_iterations(const PRState* sts, const PROptsResolved& o, int members) {
+  int plan = 0;
+  for (int gI = 0; gI < members; ++gI) {
+    const PRState& st = sts[gI];
+    if (st.done) continue;
+    int need = o.chunk;
+    if (st.resid > 0.0 && st.resid_prev > st.resid && st.resid >= o.tol) {
+      const double rate = st.resid / st.resid_prev;
+      const double it = std::ceil(std::log(o.tol / st.resid) / std::log(rate));
+      if (it >= 0.0 && it < 4.0 * o.chunk) need = int(it) + 1;
+    }
+    need = std::max(1, std::min(need, o.max_iter - st.iter));
+    plan = std::max(plan, need);
+  }
+  return std::max(2, (plan + 1) / 2 * 2);
+}
+
+// Run PageRank iterations as replays of captured runs of iterations, each
+// starting from buffer 0 (an even length) until every member is done: first
+// one chunk, then as many iterations as the members' residuals predict
+// (planned_iterations), as runs of the chunk's length and its halvings,
+// launched back to back before the states are read.  The runs are captured
+// once and kept with the working set while its key holds.
 template <class IterFn>
 int replay_until_done(PRWork& w, hipStream_t cap, const PROptsResolved& o, const void* tele, const int32_t* outdeg,
                       int members, int k, hipStream_t s, IterFn iter) {
-  const bool same = w.exec && w.key_tele == tele && w.key_beta == o.beta && w.key_tol == o.tol &&
+  const bool same = w.exec[0] && w.key_tele == tele && w.key_beta == o.beta && w.key_tol == o.tol &&
                     w.key_max_iter == o.max_iter && w.key_chunk == o.chunk;
   if (!same) {
     w.drop_graph();
+    w.key_tele = tele;
+    w.key_beta = o.beta;
+    w.key_tol = o.tol;
+    w.key_max_iter = o.max_iter;
+    w.key_chunk = o.chunk;
+  }
+  // the captured run of `len` iterations (captured on first use)
+  auto run_of = [&](int len, hipGraphExec_t* out) -> int {
+    int slot = -1;
+    for (int i = 0; i < PRWork::kGraphs; ++i) {
+      if (w.glen[i] == len && w.exec[i]) {
+        *out = w.exec[i];
+        return BVMV_OK;
+      }
+      if (slot < 0 && !w.exec[i]) slot = i;
+    }
+    if (slot < 0) return fail(BVMV_EDEVICE, "PageRank: no free graph slot");
     HIP_TRY(hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal));
     hipError_t ce = hipSuccess;
-    for (int c = 0; c < o.chunk && ce == hipSuccess; ++c) ce = iter(pr_args(w, o, tele, outdeg, members, k, c), cap);
+    for (int c = 0; c < len && ce == hipSuccess; ++c) ce = iter(pr_args(w, o, tele, outdeg, members, k, c), cap);
     hipGraph_t gr = nullptr;
     hipError_t ee = hipStreamEndCapture(cap, &gr);
     if (ce != hipSuccess) {
@@ -392,21 +440,32 @@ int replay_until_done(PRWork& w, hipStream_t cap, const PROptsResolved& o, const
       return fail(BVMV_EDEVICE, std::string("PageRank launch: ") + hipGetErrorString(ce));
     }
     if (ee != hipSuccess) return fail(BVMV_EDEVICE, std::string("hipStreamEndCapture: ") + hipGetErrorString(ee));
-    w.graph = gr;
-    HIP_TRY(hipGraphInstantiate(&w.exec, w.graph, nullptr, nullptr, 0));
-    w.key_tele = tele;
-    w.key_beta = o.beta;
-    w.key_tol = o.tol;
-    w.key_max_iter = o.max_iter;
-    w.key_chunk = o.chunk;
-  }
-  const int max_replays = (o.max_iter + o.chunk - 1) / o.chunk + 1;
-  for (int rep = 0; rep < max_replays; ++rep) {
-    HIP_TRY(hipGraphLaunch(w.exec, s));
+    w.graph[slot] = gr;
+    HIP_TRY(hipGraphInstantiate(&w.exec[slot], gr, nullptr, nullptr, 0));
+    w.glen[slot] = len;
+    *out = w.exec[slot];
+    return BVMV_OK;
+  };
+  // the chunk first: it also occupies slot 0, whose presence marks the key as captured
+  hipGraphExec_t first = nullptr;
+  if (int rc = run_of(o.chunk, &first)) return rc;
+  int plan = o.chunk;
+  for (int done_iters = 0; done_iters <= o.max_iter + o.chunk;) {
+    // plan as runs of the chunk's length and its even halvings
+    for (int left = plan; left > 0;) {
+      int len = o.chunk;
+      while (len > left && len > 2) len = std::max(2, (len / 2 + 1) / 2 * 2);
+      hipGraphExec_t ex = nullptr;
+      if (int rc = run_of(len, &ex)) return rc;
+      HIP_TRY(hipGraphLaunch(ex, s));
+      left -= len;
+      done_iters += len;
+    }
     if (int rc = read_states(w, members, s)) return rc;
     bool all = true;
     for (int gI = 0; gI < members; ++gI) all = all && w.h_st[gI].done;
     if (all) break;
+    plan = planned_iterations(w.h_st, o, members);
   }
   return BVMV_OK;
 }
@@ -1067,9 +1126,11 @@ int bvmv_pagerank_noalloc(bvmv_graph* g, const bvmv_pr_opts* opts, const void* t
   a.k = 1;
   PRState h;
   std::memset(&h, 0, sizeof(h));
-  const int max_chunks = (o.max_iter + o.chunk - 1) / o.chunk + 1;
-  for (int ch = 0; ch < max_chunks; ++ch) {
-    for (int c = 0; c < o.chunk; ++c) {
+  // a chunk, then as many iterations as the residuals predict (an even
+  // count, so every run starts from buffer 0)
+  int plan = o.chunk;
+  for (int done_iters = 0; done_iters <= o.max_iter + o.chunk; done_iters += plan) {
+    for (int c = 0; c < plan; ++c) {
       a.p_cur = p[c % 2];
       a.p_new = p[(c + 1) % 2];
       a.z_cur = z[c % 2];
@@ -1080,6 +1141,7 @@ int bvmv_pagerank_noalloc(bvmv_graph* g, const bvmv_pr_opts* opts, const void* t
     HIP_TRY(hipMemcpyAsync(&h, st, sizeof(PRState), hipMemcpyDeviceToHost, s));
     HIP_TRY(hipStreamSynchronize(s));
     if (h.done) break;
+    plan = planned_iterations(&h, o, 1);
   }
   HIP_TRY(launch_pr_select(prec, st, p[0], p[1], p_out, g->n, 1, s));
   if (res) {

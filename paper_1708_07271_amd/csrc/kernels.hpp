@@ -55,6 +55,7 @@ struct PRState {
   uint32_t blk_lo, blk_hi;    // block range of the member's partial slots
   uint32_t slot0;             // the member's first slot (slots slot0 + blk_lo .. slot0 + blk_hi - 1)
   uint32_t pad;
+  double resid_prev;          // the residual of the iteration before the last (0 before two iterations)
 };
 
 struct PRArgs {
