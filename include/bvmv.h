@@ -77,7 +77,8 @@ typedef struct {
                             each) and keep the fastest; the choice is remembered for the rest
                             of the process per size bucket (floor(log2 n), mean degree).  The
                             options' tile_rows, window_cap, stage_bytes, long_row_bytes are then
-                            ignored */
+                            ignored.  The decoded lists stay on the host (as with keep_lists,
+                            without the export), so that bvmv_group can lay the graph out again */
   int keep_lists;        /* 1 = keep the decoded lists on the host (export, CSR baseline) */
   int nthreads;          /* host decode / layout threads (0 = hardware concurrency, max 16) */
   uint64_t device_mem_budget;  /* bytes; 0 = unlimited.  Layout larger than this -> BVMV_ENOMEM */
@@ -210,7 +211,14 @@ int bvmv_pagerank_noalloc(bvmv_graph* g, const bvmv_pr_opts* opts, const void* t
  * handle.  Member i occupies rows/columns [offsets[i], offsets[i+1]).
  * bvmv_multiply on a group multiplies every member at once; bvmv_pagerank
  * runs every member's PageRank (own uniform teleport, own stopping test) in
- * one launch sequence.  The members stay valid and owned by the caller. */
+ * one launch sequence.  The members stay valid and owned by the caller.
+ * Members laid out differently (autotuned one by one, or loaded with other
+ * options) share one layout in the group when every member still holds its
+ * decoded lists (autotune or keep_lists): each of the members' layouts is
+ * timed over the whole group (FP32 two-sum product, 10 launches) and the
+ * fastest is used for all; a member's rows may then be summed in another
+ * order than in its own handle.  Otherwise the members' own layouts are
+ * joined as they are. */
 int bvmv_group(bvmv_graph* const* graphs, int count, bvmv_graph** out);
 /* offsets: HOST array of count+1 row offsets of a group's members. */
 int bvmv_group_offsets(const bvmv_graph* group, int64_t* offsets, int* count);
@@ -231,7 +239,9 @@ typedef struct {
   int max_level;            /* deepest reuse level in the layout (<= R) */
   int ngraphs;              /* 1, or the member count of a group */
   int autotuned;            /* 0: layout from the options; 1: chosen by timing candidate layouts at
-                               load; 2: the autotuner's earlier choice for this size bucket */
+                               load (for a group: one of its members' layouts, timed over the
+                               whole group); 2: the autotuner's earlier choice for this size
+                               bucket */
 } bvmv_info;
 int bvmv_get_info(const bvmv_graph* g, bvmv_info* out);
 

@@ -908,7 +908,9 @@ int bvmv_load(const void* bitstream, size_t nbytes, const bvmv_load_opts* opts, 
   }
   if (o.keep_lists) {
     g->lists_kept = true;
-  } else {
+  } else if (!o.autotune) {
+    // (an autotuned graph keeps its lists, so that a group of graphs tuned to
+    // different layouts can lay them all out with one layout)
     std::vector<uint32_t>().swap(g->dec.col);
     std::vector<uint64_t>().swap(g->dec.rowptr);
     std::vector<uint8_t>().swap(g->dec.refs);
@@ -1156,27 +1158,35 @@ int bvmv_pagerank_noalloc(bvmv_graph* g, const bvmv_pr_opts* opts, const void* t
   return h.converged ? BVMV_OK : BVMV_NOT_CONVERGED;
 }
 
-int bvmv_group(bvmv_graph* const* graphs, int count, bvmv_graph** out) {
-  if (!graphs || count < 1 || !out) return fail(BVMV_EINVAL, "bad group arguments");
-  *out = nullptr;
-  std::unique_ptr<bvmv_graph> g(new bvmv_graph());
+namespace {
+bool same_layout(const LayoutParams& a, const LayoutParams& b) {
+  return a.tile_rows == b.tile_rows && a.window_cap == b.window_cap && a.stage_bytes == b.stage_bytes &&
+         a.long_row_bytes == b.long_row_bytes && a.min_interval == b.min_interval;
+}
+
+// The members' layouts (`lay[i]` for member i) one after another as the
+// group's layout, with the members' rows, tiles and row statistics.
+int concat_group(bvmv_graph* g, bvmv_graph* const* graphs, int count, const HostLayout* const* lay) {
   g->device = graphs[0]->device;
   g->opts = graphs[0]->opts;
   g->interval_mode = graphs[0]->interval_mode;
   g->ngraphs = count;
+  g->n = g->m = g->m_prime = g->stream_bytes = 0;
   g->offsets.assign(1, 0);
   g->tile_offsets.assign(1, 0);
+  g->h_outdeg.clear();
+  g->dec.stats.clear();
   HostLayout& hl = g->hl;
-  hl.prm = graphs[0]->hl.prm;
+  hl = HostLayout();
+  hl.prm = lay[0]->prm;
   for (int i = 0; i < count; ++i) {
     const bvmv_graph* m = graphs[i];
-    if (!m || m->ngraphs != 1) return fail(BVMV_EINVAL, "group members must be loaded graphs");
-    if (m->device != g->device) return fail(BVMV_EINVAL, "group members must share the device");
+    const HostLayout& ml = *lay[i];
     const uint64_t rb = uint64_t(g->n), db = hl.data.size(), lb = hl.longs.size();
-    if (rb + uint64_t(m->n) >= (uint64_t(1) << 30) || (db + m->hl.data.size()) / 16 >= (uint64_t(1) << 32) ||
-        lb + m->hl.longs.size() >= (uint64_t(1) << 32))
+    if (rb + uint64_t(m->n) >= (uint64_t(1) << 30) || (db + ml.data.size()) / 16 >= (uint64_t(1) << 32) ||
+        lb + ml.longs.size() >= (uint64_t(1) << 32))
       return fail(BVMV_EINVAL, "group too large");
-    for (TileDesc td : m->hl.tiles) {
+    for (TileDesc td : ml.tiles) {
       td.row0 += uint32_t(rb);
       td.win0 += uint32_t(rb);
       td.data16 += uint32_t(db / 16);
@@ -1184,24 +1194,24 @@ int bvmv_group(bvmv_graph* const* graphs, int count, bvmv_graph** out) {
       td.graph = uint32_t(i);
       hl.tiles.push_back(td);
     }
-    hl.info.insert(hl.info.end(), m->hl.info.begin(), m->hl.info.end());
-    hl.ns.insert(hl.ns.end(), m->hl.ns.begin(), m->hl.ns.end());
-    hl.data.insert(hl.data.end(), m->hl.data.begin(), m->hl.data.end());
-    hl.longs.insert(hl.longs.end(), m->hl.longs.begin(), m->hl.longs.end());
-    hl.n_singles += m->hl.n_singles;
-    hl.n_wide += m->hl.n_wide;
-    hl.n_intervals += m->hl.n_intervals;
+    hl.info.insert(hl.info.end(), ml.info.begin(), ml.info.end());
+    hl.ns.insert(hl.ns.end(), ml.ns.begin(), ml.ns.end());
+    hl.data.insert(hl.data.end(), ml.data.begin(), ml.data.end());
+    hl.longs.insert(hl.longs.end(), ml.longs.begin(), ml.longs.end());
+    hl.n_singles += ml.n_singles;
+    hl.n_wide += ml.n_wide;
+    hl.n_intervals += ml.n_intervals;
     g->h_outdeg.insert(g->h_outdeg.end(), m->h_outdeg.begin(), m->h_outdeg.end());
-    hl.units += m->hl.units;
-    hl.diff_rows += m->hl.diff_rows;
-    hl.direct_rows += m->hl.direct_rows;
-    hl.long_rows += m->hl.long_rows;
-    hl.escapes += m->hl.escapes;
-    hl.m_prime += m->hl.m_prime;
-    hl.max_level = std::max(hl.max_level, m->hl.max_level);
+    hl.units += ml.units;
+    hl.diff_rows += ml.diff_rows;
+    hl.direct_rows += ml.direct_rows;
+    hl.long_rows += ml.long_rows;
+    hl.escapes += ml.escapes;
+    hl.m_prime += ml.m_prime;
+    hl.max_level = std::max(hl.max_level, ml.max_level);
     g->n += m->n;
     g->m += m->m;
-    g->m_prime += m->m_prime;
+    g->m_prime += ml.m_prime;
     g->stream_bytes += m->stream_bytes;
     g->offsets.push_back(g->n);
     g->tile_offsets.push_back(uint32_t(hl.tiles.size()));
@@ -1219,7 +1229,86 @@ int bvmv_group(bvmv_graph* const* graphs, int count, bvmv_graph** out) {
   g->R = graphs[0]->R;
   g->Lmin = graphs[0]->Lmin;
   g->zk = graphs[0]->zk;
-  DeviceGuard dg(g->device);
+  return BVMV_OK;
+}
+}  // namespace
+
+int bvmv_group(bvmv_graph* const* graphs, int count, bvmv_graph** out) {
+  if (!graphs || count < 1 || !out) return fail(BVMV_EINVAL, "bad group arguments");
+  *out = nullptr;
+  for (int i = 0; i < count; ++i) {
+    const bvmv_graph* m = graphs[i];
+    if (!m || m->ngraphs != 1) return fail(BVMV_EINVAL, "group members must be loaded graphs");
+    if (m->device != graphs[0]->device) return fail(BVMV_EINVAL, "group members must share the device");
+  }
+  std::unique_ptr<bvmv_graph> g(new bvmv_graph());
+  DeviceGuard dg(graphs[0]->device);
+  std::vector<const HostLayout*> lay(static_cast<size_t>(count));
+  for (int i = 0; i < count; ++i) lay[size_t(i)] = &graphs[i]->hl;
+  // Members laid out with different layouts (each tuned alone) would force
+  // the widest LDS carve and the two-rows-per-lane kernel on every block of
+  // the group.  When every member still has its lists (autotuned loads keep
+  // them), each of the members' layouts is timed over the whole group and
+  // the fastest is used for all of them.
+  std::vector<LayoutParams> classes;
+  bool relayable = true;
+  for (int i = 0; i < count; ++i) {
+    const bvmv_graph* m = graphs[i];
+    relayable = relayable && m->dec.col.size() == size_t(m->m) && m->dec.rowptr.size() == size_t(m->n) + 1;
+    bool seen = false;
+    for (const auto& c : classes) seen = seen || same_layout(c, m->hl.prm);
+    if (!seen) classes.push_back(m->hl.prm);
+  }
+  std::vector<HostLayout> own_lay;
+  if (classes.size() > 1 && relayable) {
+    const int nt = default_threads(0);
+    std::string err;
+    DevBuf<float> xb, yb;
+    int64_t ntot = 0;
+    for (int i = 0; i < count; ++i) ntot += graphs[i]->n;
+    if (xb.alloc(size_t(ntot)) || yb.alloc(size_t(ntot))) return fail(BVMV_ENOMEM, "group autotune vectors");
+    HIP_TRY(hipMemset(xb.p, 0, size_t(std::max<int64_t>(ntot, 1)) * sizeof(float)));
+    int best = -1;
+    float best_us = 0.0f;
+    for (size_t c = 0; c < classes.size(); ++c) {
+      std::vector<HostLayout> tl(static_cast<size_t>(count));
+      std::vector<const HostLayout*> tp(static_cast<size_t>(count));
+      bool ok = true;
+      for (int i = 0; i < count && ok; ++i) {
+        if (same_layout(graphs[i]->hl.prm, classes[c])) {
+          tp[size_t(i)] = &graphs[i]->hl;
+        } else {
+          ok = build_layout(graphs[i]->dec, classes[c], nt, tl[size_t(i)], err) == 0;
+          tp[size_t(i)] = &tl[size_t(i)];
+        }
+      }
+      if (!ok) continue;
+      bvmv_graph trial;
+      if (int rc = concat_group(&trial, graphs, count, tp.data())) return rc;
+      if (upload_layout(&trial) != BVMV_OK) {
+        trial.release_device();
+        continue;
+      }
+      float us = 0.0f;
+      const int rc = time_product(&trial, xb.p, yb.p, 10, &us);
+      trial.release_device();
+      if (rc) return rc;
+      if (best < 0 || us < best_us) {
+        best = int(c);
+        best_us = us;
+      }
+    }
+    if (best < 0) return fail(BVMV_EINVAL, "no member layout fits the group on the device");
+    own_lay.resize(static_cast<size_t>(count));
+    for (int i = 0; i < count; ++i) {
+      if (same_layout(graphs[i]->hl.prm, classes[size_t(best)])) continue;
+      if (build_layout(graphs[i]->dec, classes[size_t(best)], nt, own_lay[size_t(i)], err))
+        return fail(BVMV_EINVAL, err);
+      lay[size_t(i)] = &own_lay[size_t(i)];
+    }
+    g->autotuned = 1;
+  }
+  if (int rc = concat_group(g.get(), graphs, count, lay.data())) return rc;
   if (int rc = upload_layout(g.get())) {
     g->release_device();
     return rc;

@@ -292,6 +292,39 @@ def test_group_block_diagonal(P):
         assert np.array_equal(y[seg], _mul(P, Gs[i], x[seg], P.BVMV_F32_COMP))
 
 
+
+def test_group_of_mixed_layouts(P):
+    """Members laid out differently (as the autotuner may leave them): with
+    their lists kept, the group is laid out with one of the members' layouts,
+    the faster over the whole group; without lists the members' own layouts
+    are concatenated.  Either way every member's rows are exact on integer x
+    and within the tolerance on uniform x."""
+    sizes = [3000, 12_000, 700]
+    gs = [B.web_graph(n, 14.0, 80 + i) for i, n in enumerate(sizes)]
+    shapes = [dict(tile_rows=64, window_cap=256), dict(tile_rows=128, window_cap=768, stage_bytes=6144),
+              dict(tile_rows=32, window_cap=256, stage_bytes=2048)]
+    for keep in (1, 0):
+        Gs = [P.bvmv_load(B.encode(g).data, keep_lists=keep, **sh) for g, sh in zip(gs, shapes)]
+        grp = P.bvmv_group(Gs)
+        info = P.bvmv_get_info(grp)
+        print("group of mixed layouts, lists kept %d: tile rows %d, window %d, autotuned %d"
+              % (keep, info["tile_rows"], info["window_cap"], info["autotuned"]), flush=True)
+        if keep:
+            assert info["autotuned"] == 1
+            assert (info["tile_rows"], info["window_cap"]) in [(sh["tile_rows"], sh["window_cap"]) for sh in shapes]
+        else:
+            assert info["autotuned"] == 0
+        offs = P.bvmv_group_offsets(grp)
+        xi = B.integer_x(offs[-1], 4, 9).astype(np.float32)
+        x = B.uniform_x(offs[-1], 5, np.float32)
+        yi = _mul(P, grp, xi, P.BVMV_F32_COMP)
+        y = _mul(P, grp, x, P.BVMV_F32_COMP)
+        for i, g in enumerate(gs):
+            seg = slice(offs[i], offs[i + 1])
+            assert np.array_equal(yi[seg], product.matvec(g.rowptr, g.col, xi[seg].astype(np.float64)))
+            assert _rel(y[seg], product.matvec_exact(g.rowptr, g.col, x[seg].astype(np.float64))) < TOL.F32C
+
+
 # the autotuner's candidate layouts (tile rows, window columns, staged bytes)
 TUNE_CANDS = [(32, 256, 2048), (64, 256, 4096), (64, 384, 3072), (64, 512, 4096), (64, 768, 6144),
               (128, 768, 6144)]
