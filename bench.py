@@ -20,8 +20,10 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 PEAK_HBM_GBS = 8000.0
-KERNEL_SOURCES = ["paper_1708_07271_amd/csrc/bv_kernels.hip", "paper_1708_07271_amd/csrc/bv_layout.cpp",
-                  "paper_1708_07271_amd/csrc/bv_layout.hpp", "paper_1708_07271_amd/csrc/bvmv_api.cpp"]
+# the device code and the layout it reads: the sources that decide a kernel's
+# HBM traffic (host scheduling in bvmv_api.cpp does not)
+KERNEL_SOURCES = ["paper_1708_07271_amd/csrc/bv_kernels.hip", "paper_1708_07271_amd/csrc/kernels.hpp",
+                  "paper_1708_07271_amd/csrc/bv_layout.cpp", "paper_1708_07271_amd/csrc/bv_layout.hpp"]
 
 
 def log(*a):
@@ -747,6 +749,20 @@ def main():
     if args.only in ("csr", "all"):
         ms_csr, ms_flush, warm_csr = both(lambda: P.bvmv_csr_multiply(C, x, y2, prec), "csr")
         log("csr product: %.4f ms from HBM, %.4f ms cache-warm" % (ms_csr, warm_csr))
+    # the same bytes as the compressed product's (layout + x + y) moved by a
+    # plain device copy, timed the same way: what HBM delivers at this size
+    copy_floor = None
+    if args.only in ("bv", "all") and args.timing != "warm":
+        nfl = (info["layout_bytes"] + 8 * g.n) // 8
+        ca = torch.ones(nfl, dtype=torch.float32, device=dev)
+        cb = torch.empty_like(ca)
+        ms_c, _, _ = time_flushed(lambda: cb.copy_(ca), args.steps, args.warmup, flush, torch)
+        warm_c = time_launches(lambda: cb.copy_(ca), args.steps, args.warmup, torch)
+        copy_floor = {"bytes_moved": 8 * nfl, "ms": ms_c, "GBps": 8 * nfl / (ms_c * 1e-3) / 1e9,
+                      "mall_warm_ms": warm_c, "product_over_copy": ms_bv / ms_c}
+        log("device copy of the same bytes: %.4f ms from HBM (%.0f GB/s), %.4f ms cache-warm; product / copy %.2f"
+            % (ms_c, copy_floor["GBps"], warm_c, ms_bv / ms_c))
+        del ca, cb
     del flush
     if ms_bv is None:
         ms_bv, warm_bv = ms_csr, warm_csr
@@ -796,6 +812,7 @@ def main():
                      "frac": achieved / PEAK_HBM_GBS, "traffic": load_traffic("bv_wave_kernel", args.workload),
                      "kernel": "bv_wave_kernel", "alg_bytes_per_launch": alg_bytes,
                      "caches": "flushed" if args.timing != "warm" else "warm"},
+        "copy_same_bytes": copy_floor,
         "mall_warm": {"ms": warm_bv, "edges_per_s": g.m / (warm_bv * 1e-3),
                       "achieved_GBs": alg_bytes / (warm_bv * 1e-3) / 1e9,
                       "frac": alg_bytes / (warm_bv * 1e-3) / 1e9 / PEAK_HBM_GBS,

@@ -382,7 +382,10 @@ int read_states(PRWork& w, int members, hipStream_t s) {
 // count at which its residual, contracting by the ratio of its last two
 // residuals, falls below tol (one more, and a whole chunk when the ratio is
 // not yet known or not below 1), at most its iterations left; the largest
-// over the members, rounded up to even.
+// over the members, rounded up to even.  A ratio below the damping factor
+// is taken halfway to it: the power method's contraction tends to the
+// damping factor from below on these graphs, and one more host round trip
+// costs about as much as eight iterations whose blocks all return at once.
 int planned_iterations(const PRState* sts, const PROptsResolved& o, int members) {
   int plan = 0;
   for (int gI = 0; gI < members; ++gI) {
@@ -390,7 +393,8 @@ int planned_iterations(const PRState* sts, const PROptsResolved& o, int members)
     if (st.done) continue;
     int need = o.chunk;
     if (st.resid > 0.0 && st.resid_prev > st.resid && st.resid >= o.tol) {
-      const double rate = st.resid / st.resid_prev;
+      double rate = st.resid / st.resid_prev;
+      if (rate < o.beta) rate = 0.5 * (rate + o.beta);
       const double it = std::ceil(std::log(o.tol / st.resid) / std::log(rate));
       if (it >= 0.0 && it < 4.0 * o.chunk) need = int(it) + 1;
     }
