@@ -525,7 +525,8 @@ struct TileCtx {
 
 // ---------------------------------------------------------------- epilogues
 // Every wave of the block calls them (a wave may have no rows).  In the tile
-// kernel: prepare(tc) runs once per wave before the tile is decoded and
+// kernel: block_start(block, member, s_blk) runs first, with every thread of
+// the block (the fused PageRank's fold); prepare(tc) runs once per wave before the tile is decoded and
 // returns per-lane state; fetch(tc, c) issues vector c's global loads ahead
 // of their use (vector 0 with the tile's own loads, vector c + 1 while c is
 // summed); skip(st, c) passes over vector c and all_done(st) over the whole
@@ -539,6 +540,7 @@ constexpr int kEpiRows = kTileRowsMax / 64;  // rows of a tile per lane
 template <class M, bool kAdd = false>
 struct EpiStore {
   typename M::X* y;
+  __device__ void block_start(uint32_t, uint32_t, unsigned char*) const {}
   struct State {};
   struct Fetch {};
   __device__ State prepare(const TileCtx&) const { return {}; }
@@ -587,23 +589,32 @@ __device__ __forceinline__ void pr_block_partial(double rs, double dg, double* s
   }
 }
 
-// One block per member: the member's residual and dangling mass from its
-// blocks' slots, then the stopping test (with_resid = 1, after an iteration;
-// members already done were skipped by the iteration and are left alone) or
-// the start state (with_resid = 0, after pr_init_kernel), whose iteration
-// count is iter0 (nonzero when a run resumes from a restart vector).
-__global__ void __launch_bounds__(kThreads) pr_finish_kernel(PRState* st_all, const double* __restrict__ slots,
-                                                             int with_resid, double tol, int32_t max_iter,
-                                                             int32_t buf, int32_t iter0) {
-  __shared__ double2 s_red[kWaves];
-  PRState* st = st_all + blockIdx.x;
-  if (with_resid && st->done) return;
+__device__ __forceinline__ double readlane_f64(double v, int l) {
+  const uint64_t u = __double_as_longlong(v);
+  const uint32_t lo = __builtin_amdgcn_readlane(uint32_t(u), l), hi = __builtin_amdgcn_readlane(uint32_t(u >> 32), l);
+  return __longlong_as_double(int64_t((uint64_t(hi) << 32) | lo));
+}
+
+// The fold of one member's block partials (residual and dangling sums) in
+// one fixed order: 256 threads, thread t adding slots blk_lo + t, + 256, ...
+// in sequence, each wave's sums by the shuffle reduction, then the four
+// waves in order.  Every fold below gives the same two doubles bit for bit:
+// fold_block with a whole block, fold_wave with one wave taking the four
+// waves' threads in turn.
+struct Fold {
+  double R, D;
+};
+
+// (every thread of the block calls it; s_red: 4 double2 of LDS, free again
+// after the caller's next __syncthreads; kU loads in flight per thread, which
+// does not change the order of the sums)
+template <int kU = 16>
+__device__ __forceinline__ Fold fold_block(const PRState& st, const double* __restrict__ slots, double2* s_red) {
   // each thread's slots t, t + 256, ... in batches of kU loads in flight
-  constexpr int kU = 16;
-  const double2* sl = reinterpret_cast<const double2*>(slots) + st->slot0;
-  const uint32_t hi = st->blk_hi;
+  const double2* sl = reinterpret_cast<const double2*>(slots) + st.slot0;
+  const uint32_t hi = st.blk_hi;
   double R = 0.0, D = 0.0;
-  for (uint32_t b = st->blk_lo + threadIdx.x; b < hi; b += kThreads * kU) {
+  for (uint32_t b = st.blk_lo + threadIdx.x; b < hi; b += kThreads * kU) {
     double2 v[kU];
 #pragma unroll
     for (int u = 0; u < kU; ++u) {
@@ -620,41 +631,173 @@ __global__ void __launch_bounds__(kThreads) pr_finish_kernel(PRState* st_all, co
   D = wave_sum_f64(D);
   if (lane_id() == 0) s_red[threadIdx.x >> 6] = make_double2(R, D);
   __syncthreads();
-  R = s_red[0].x;
-  D = s_red[0].y;
+  Fold f{s_red[0].x, s_red[0].y};
   for (int w = 1; w < kWaves; ++w) {
-    R += s_red[w].x;
-    D += s_red[w].y;
+    f.R += s_red[w].x;
+    f.D += s_red[w].y;
+  }
+  return f;
+}
+
+// (the same sums from one wave; the zero terms fold_block adds past the
+// last slot leave its non-negative sums unchanged)
+__device__ __forceinline__ Fold fold_wave(const PRState& st, const double* __restrict__ slots) {
+  const double2* sl = reinterpret_cast<const double2*>(slots) + st.slot0;
+  const uint32_t hi = st.blk_hi;
+  Fold f{0.0, 0.0};
+  for (int w = 0; w < kWaves; ++w) {
+    double R = 0.0, D = 0.0;
+    for (uint32_t b = st.blk_lo + uint32_t(w) * 64u + lane_id(); b < hi; b += kThreads) {
+      const double2 v = sl[b];
+      R += v.x;
+      D += v.y;
+    }
+    R = wave_sum_f64(R);
+    D = wave_sum_f64(D);
+    if (w == 0) {
+      f = Fold{R, D};
+    } else {
+      f.R += R;
+      f.D += D;
+    }
+  }
+  return f;
+}
+
+// A member's state after a fold: after an iteration (with_resid = 1; the
+// folded iterate is in buffer buf) the stopping test, else the start state,
+// whose iteration count is iter0 (nonzero when a run resumes from a restart
+// vector).
+__device__ __forceinline__ void pr_apply(PRState& st, const Fold& f, int with_resid, double tol, int32_t max_iter,
+                                         int32_t buf, int32_t iter0) {
+  st.delta = f.D;
+  if (with_resid) {
+    st.resid_prev = st.resid;
+    st.resid = f.R;
+    st.iter += 1;
+    if (f.R < tol) {
+      st.done = 1;
+      st.converged = 1;
+      st.final_buf = buf;
+    } else if (st.iter >= max_iter) {
+      st.done = 1;
+      st.final_buf = buf;
+    }
+  } else {
+    st.resid = 0.0;
+    st.resid_prev = 0.0;
+    st.iter = iter0;
+    st.done = 0;
+    st.converged = 0;
+    st.final_buf = 0;
+    st.pending = 0;
+  }
+}
+
+// One block per member: the member's residual and dangling mass from its
+// blocks' slots, then the stopping test (with_resid = 1, after an iteration;
+// members already done were skipped by the iteration and are left alone) or
+// the start state (with_resid = 0, after pr_init_kernel).
+__global__ void __launch_bounds__(kThreads) pr_finish_kernel(PRState* st_all, const double* __restrict__ slots,
+                                                             int with_resid, double tol, int32_t max_iter,
+                                                             int32_t buf, int32_t iter0) {
+  __shared__ double2 s_red[kWaves];
+  PRState* st = st_all + blockIdx.x;
+  if (with_resid && st->done) return;
+  PRState F = *st;
+  const Fold f = fold_block(F, slots, s_red);
+  if (threadIdx.x == 0) {
+    pr_apply(F, f, with_resid, tol, max_iter, buf, iter0);
+    *st = F;
+  }
+}
+
+// The published value of a fused iteration (below): the dangling mass of
+// the iterate being multiplied, kPubDone once the member has converged, or
+// the not-yet-published pattern (a NaN).
+constexpr double kPubDone = -1.0;
+__device__ __forceinline__ double pub_load(const double* p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void pub_store(double* p, double v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ double pub_unset() { return __longlong_as_double(int64_t(-1)); }
+
+// After a run of fused iterations the last iterate's partials are still
+// unfolded (pending): one block per member folds them into the member's state
+// (the run has even length, so that iterate is in buffer 0 and its partials
+// in the slots of parity 0), and both published values are cleared for the
+// next run.  A member without blocks (no rows) folds zeros.
+__global__ void __launch_bounds__(kThreads) pr_flush_kernel(PRState* st_all, const double* __restrict__ slots,
+                                                            double tol, int32_t max_iter, double* pub) {
+  __shared__ double2 s_red[kWaves];
+  PRState* st = st_all + blockIdx.x;
+  PRState F = *st;
+  if (!F.done && (F.pending || F.blk_lo == F.blk_hi)) {
+    const Fold f = fold_block(F, slots, s_red);
+    if (threadIdx.x == 0) pr_apply(F, f, 1, tol, max_iter, 0, 0);
   }
   if (threadIdx.x == 0) {
-    st->delta = D;
-    if (with_resid) {
-      st->resid_prev = st->resid;
-      st->resid = R;
-      st->iter += 1;
-      if (R < tol) {
-        st->done = 1;
-        st->converged = 1;
-        st->final_buf = buf;
-      } else if (st->iter >= max_iter) {
-        st->done = 1;
-        st->final_buf = buf;
-      }
-    } else {
-      st->resid = 0.0;
-      st->resid_prev = 0.0;
-      st->iter = iter0;
-      st->done = 0;
-      st->converged = 0;
-      st->final_buf = 0;
-    }
+    F.pending = 0;
+    *st = F;
+    pub[2 * size_t(blockIdx.x)] = pub_unset();
+    pub[2 * size_t(blockIdx.x) + 1] = pub_unset();
   }
 }
 
 // PageRank update of Eq. (1), dangling mass sent to the teleport vector.
+// With a.fused the dangling mass of the iterate being multiplied comes from
+// the member's published value (block_start), not from its state.
+constexpr int kPubPolls = 48;  // polls of a published value before a wave folds itself
 template <class M>
 struct EpiPR {
   PRArgs a;
+  // parity of the iterate being multiplied
+  __device__ int32_t cur() const { return 1 - a.buf; }
+
+  // Fused iterations: the first block of each member folds the partials of
+  // the iterate being multiplied (if not folded yet), writes the member's
+  // next state and publishes the dangling mass, or kPubDone; every thread of
+  // every block calls it first (s_blk: 64 bytes of LDS).
+  __device__ void block_start(uint32_t block, uint32_t graph, unsigned char* s_blk) const {
+    if (!a.fused) return;
+    const PRState* st = a.st + graph;
+    if (block != st->blk_lo) return;  // (block-uniform)
+    PRState F = *st;
+    if (!F.done && F.pending) {
+      // (8 loads in flight per thread: the fold's registers stay below the tile's)
+      const Fold f = fold_block<8>(F, a.slots_prev, reinterpret_cast<double2*>(s_blk));
+      pr_apply(F, f, 1, a.tol, a.max_iter, cur(), 0);
+    }
+    if (threadIdx.x == 0) {
+      F.pending = F.done ? 0 : 1;
+      a.st_next[graph] = F;
+      pub_store(a.pub + 2 * size_t(graph) + (1 - cur()), pub_unset());
+      pub_store(a.pub + 2 * size_t(graph) + cur(), F.done ? kPubDone : F.delta);
+    }
+    __syncthreads();
+  }
+
+  // The dangling mass for this iteration (fused): the published value (a
+  // first read `early` taken with the tile's loads), or, when it is still
+  // unset after kPubPolls reads, the same fold done by this wave from the
+  // same state and partials.  kPubDone: the member has converged.
+  __device__ double resolve(uint32_t graph, double early) const {
+    const double* pp = a.pub + 2 * size_t(graph) + cur();
+    double v = readlane_f64(early, 0);
+    for (int k = 0; k < kPubPolls && __builtin_isnan(v); ++k) {
+      if (k) __builtin_amdgcn_s_sleep(8);
+      v = readlane_f64(pub_load(pp), 0);
+    }
+    if (__builtin_isnan(v)) {
+      PRState F = a.st[graph];
+      if (!F.done && F.pending) pr_apply(F, fold_wave(F, a.slots_prev), 1, a.tol, a.max_iter, cur(), 0);
+      v = F.done ? kPubDone : F.delta;
+    }
+    return v;
+  }
+
   __device__ void operator()(const TileCtx& tc, const typename M::CAcc* s_y, unsigned char* s_blk, int) const {
     using X = typename M::X;
     const X* p = static_cast<const X*>(a.p_cur);
@@ -662,7 +805,12 @@ struct EpiPR {
     X* zn = static_cast<X*>(a.z_new);
     const X* tele = static_cast<const X*>(a.tele);
     PRState* st = a.st + tc.graph;
-    const double delta = st->delta, inv_n = st->inv_n, beta = a.beta;
+    double delta = st->delta;
+    if (a.fused) {
+      delta = resolve(tc.graph, pub_load(a.pub + 2 * size_t(tc.graph) + cur()));
+      if (delta < 0.0) return;  // converged: every wave of the block returns
+    }
+    const double inv_n = st->inv_n, beta = a.beta;
     double rs = 0.0, dg = 0.0;
     for (uint32_t r = lane_id(); r < tc.nrows; r += 64) {
       const uint32_t v = tc.row0 + r;
@@ -680,11 +828,13 @@ struct EpiPR {
     pr_block_partial(rs, dg, a.slots, s_blk, tc.slot);
   }
   // the tile kernel's form: out-degrees, p and the teleport values are loaded
-  // with the tile's own loads (rows past the tile read element 0)
+  // with the tile's own loads (rows past the tile read element 0), and with
+  // fused iterations a first read of the published dangling mass
   using X = typename M::X;
   struct State {
     int32_t d[kEpiRows];
     double delta, inv_n;  // the member's dangling mass and 1/n
+    double pub0;
   };
   struct Fetch {
     X p[kEpiRows], t[kEpiRows];
@@ -694,6 +844,7 @@ struct EpiPR {
     const PRState* st = a.st + tc.graph;
     S.delta = st->delta;
     S.inv_n = st->inv_n;
+    S.pub0 = a.fused ? pub_load(a.pub + 2 * size_t(tc.graph) + cur()) : 0.0;
 #pragma unroll
     for (int q = 0; q < kEpiRows; ++q) {
       const uint32_t r = lane_id() + 64u * q;
@@ -720,7 +871,12 @@ struct EpiPR {
                       const Fetch& f) const {
     X* pn = static_cast<X*>(a.p_new) + tc.row0;
     X* zn = static_cast<X*>(a.z_new) + tc.row0;
-    const double delta = S.delta, inv_n = S.inv_n, beta = a.beta;
+    double delta = S.delta;
+    if (a.fused) {
+      delta = resolve(tc.graph, S.pub0);
+      if (delta < 0.0) return;  // converged: every wave of the block returns
+    }
+    const double inv_n = S.inv_n, beta = a.beta;
     double rs = 0.0, dg = 0.0;
 #pragma unroll
     for (int q = 0; q < kEpiRows; ++q) {
@@ -745,17 +901,12 @@ struct EpiPR {
 
 // Multi-vector epilogues (the same interface).
 
-__device__ __forceinline__ double readlane_f64(double v, int l) {
-  const uint64_t u = __double_as_longlong(v);
-  const uint32_t lo = __builtin_amdgcn_readlane(uint32_t(u), l), hi = __builtin_amdgcn_readlane(uint32_t(u >> 32), l);
-  return __longlong_as_double(int64_t((uint64_t(hi) << 32) | lo));
-}
-
 // Column c of a column-major block (leading dimension ld) for the tile's rows.
 template <class M>
 struct EpiStoreCols {
   typename M::X* y;
   int64_t ld;
+  __device__ void block_start(uint32_t, uint32_t, unsigned char*) const {}
   struct State {};
   struct Fetch {};
   __device__ State prepare(const TileCtx&) const { return {}; }
@@ -782,6 +933,7 @@ struct EpiPRCols {
   using X = typename M::X;
   PRArgs a;
   int64_t n;
+  __device__ void block_start(uint32_t, uint32_t, unsigned char*) const {}
   struct State {
     uint64_t done;  // bit c: column c is done
     double delta, inv_n, rs, dg;
@@ -1291,7 +1443,8 @@ __global__ void __launch_bounds__(kThreads) bv_wave_kernel(DevLayout L, Src src,
   unsigned char* ws = smem + size_t(wave) * cv.wave_bytes();
   unsigned char* s_blk = smem + size_t(kWaves) * cv.wave_bytes();
   const TileDesc td = L.tiles[blockIdx.x * kWaves + wave];
-  if (skip_done && skip_done[td.graph].done) return;  // a block holds one member's tiles
+  epi.block_start(blockIdx.x, td.graph, s_blk);        // (a block holds one member's tiles)
+  if (skip_done && skip_done[td.graph].done) return;
   TileLoads<M, RPL, SV> ld;
   issue_loads<M, RPL, SV>(L, td, src, ld);
   process_tile<M, RPL, SV>(L, td, ld, src, epi, blockIdx.x, ws, s_blk);
@@ -1503,6 +1656,8 @@ __global__ void __launch_bounds__(kThreads) csr_wave_kernel(DevCsr C, const type
   using PAcc = typename M::PAcc;
   using CAcc = typename M::CAcc;
   extern __shared__ __align__(16) unsigned char smem[];
+  const CsrCarve<M> cv0{C.wcap, C.ccap};
+  epi.block_start(blockIdx.x, 0u, smem + size_t(kWaves) * cv0.wave_bytes());
   if (skip_done && skip_done[0].done) return;
   const uint32_t wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const uint32_t lane = lane_id();
@@ -1745,7 +1900,15 @@ hipError_t launch_bv_pagerank_iter(const DevLayout& L, int prec, const PRArgs& a
     case 2: e = launch_tile<MF32C>(L, a.z_cur, EpiPR<MF32C>{a}, a.st, s); break;
     default: return hipErrorInvalidValue;
   }
-  return e != hipSuccess ? e : launch_pr_finish(a, s);
+  if (e != hipSuccess || a.fused) return e;
+  return launch_pr_finish(a, s);
+}
+
+hipError_t launch_pr_flush(PRState* st, const double* slots, double tol, int32_t max_iter, double* pub, int members,
+                           hipStream_t s) {
+  if (members <= 0) return hipSuccess;
+  hipLaunchKernelGGL(pr_flush_kernel, dim3(members), dim3(kThreads), 0, s, st, slots, tol, max_iter, pub);
+  return hipGetLastError();
 }
 
 hipError_t launch_pr_init(const DevLayout& L, int prec, const void* start, const void* tele, void* p0, void* z0,
@@ -1858,7 +2021,8 @@ hipError_t launch_csr_pagerank_iter(const DevCsr& C, int prec, const PRArgs& a, 
     case 2: e = launch_csr<MF32C>(C, a.z_cur, EpiPR<MF32C>{a}, a.st, s); break;
     default: return hipErrorInvalidValue;
   }
-  return e != hipSuccess ? e : launch_pr_finish(a, s);
+  if (e != hipSuccess || a.fused) return e;
+  return launch_pr_finish(a, s);
 }
 
 hipError_t launch_csr_pr_init(const DevCsr& C, int prec, const void* start, const void* tele, void* p0, void* z0,

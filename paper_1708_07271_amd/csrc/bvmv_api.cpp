@@ -85,10 +85,12 @@ struct PRWork {
   int64_t n = 0;
   void* p[2] = {nullptr, nullptr};
   void* z[2] = {nullptr, nullptr};
-  PRState* st = nullptr;
-  double* slots = nullptr;
+  PRState* st = nullptr;     // 2 x members: the states of parity 0 (read back by the host) and 1
+  double* slots = nullptr;   // 2 x nslots block slots of 2 doubles: parity 0, then 1
+  double* pub = nullptr;     // 2 doubles per member: the fused iterations' published values
   PRState* h_st = nullptr;  // pinned
   int nst = 0;
+  int64_t nslots = 0;
   // captured runs of iterations, by length: the chunk and its halvings down to 2
   static constexpr int kGraphs = 12;
   hipGraphExec_t exec[kGraphs] = {};
@@ -97,7 +99,7 @@ struct PRWork {
   // key of the captured graphs
   const void* key_tele = nullptr;
   double key_beta = -1, key_tol = -1;
-  int key_max_iter = -1, key_chunk = -1;
+  int key_max_iter = -1, key_chunk = -1, key_fused = -1;
 
   void drop_graph() {
     for (int i = 0; i < kGraphs; ++i) {
@@ -114,26 +116,31 @@ struct PRWork {
     for (int b = 0; b < 2; ++b) { dev_free(p[b]); dev_free(z[b]); p[b] = z[b] = nullptr; }
     dev_free(st);
     dev_free(slots);
+    dev_free(pub);
     if (h_st) (void)hipHostFree(h_st);
     st = nullptr;
     slots = nullptr;
+    pub = nullptr;
     h_st = nullptr;
     prec = -1;
   }
-  int ensure(int pr, int64_t nn, int members, int64_t ntiles) {
-    if (prec == pr && n == nn && nst == members && slots) return BVMV_OK;
+  int ensure(int pr, int64_t nn, int members, int64_t nsl) {
+    nsl = std::max<int64_t>(nsl, 1);
+    if (prec == pr && n == nn && nst == members && nslots == nsl && slots) return BVMV_OK;
     release();
     const size_t es = elem_size(pr);
     for (int b = 0; b < 2; ++b) {
       HIP_TRY(hipMalloc(&p[b], size_t(nn) * es));
       HIP_TRY(hipMalloc(&z[b], size_t(nn) * es));
     }
-    HIP_TRY(hipMalloc(reinterpret_cast<void**>(&st), sizeof(PRState) * size_t(members)));
-    HIP_TRY(hipMalloc(reinterpret_cast<void**>(&slots), sizeof(double) * 2 * size_t(std::max<int64_t>(ntiles, 1))));
+    HIP_TRY(hipMalloc(reinterpret_cast<void**>(&st), sizeof(PRState) * 2 * size_t(members)));
+    HIP_TRY(hipMalloc(reinterpret_cast<void**>(&slots), sizeof(double) * 4 * size_t(nsl)));
+    HIP_TRY(hipMalloc(reinterpret_cast<void**>(&pub), sizeof(double) * 2 * size_t(members)));
     HIP_TRY(hipHostMalloc(reinterpret_cast<void**>(&h_st), sizeof(PRState) * size_t(members), hipHostMallocDefault));
     prec = pr;
     n = nn;
     nst = members;
+    nslots = nsl;
     return BVMV_OK;
   }
 };
@@ -350,9 +357,10 @@ int upload_layout(bvmv_graph* g) {
   return BVMV_OK;
 }
 
-// Arguments of the iteration that reads buffer c % 2 and writes the other.
+// Arguments of the iteration that reads buffer c % 2 and writes the other;
+// fused: without a finish kernel, states and slots taken by parity (PRArgs).
 PRArgs pr_args(const PRWork& w, const PROptsResolved& o, const void* tele, const int32_t* outdeg, int members, int k,
-               int c) {
+               int c, bool fused) {
   PRArgs a{};
   a.p_cur = w.p[c % 2];
   a.p_new = w.p[(c + 1) % 2];
@@ -360,8 +368,17 @@ PRArgs pr_args(const PRWork& w, const PROptsResolved& o, const void* tele, const
   a.z_new = w.z[(c + 1) % 2];
   a.tele = tele;
   a.outdeg = outdeg;
-  a.st = w.st;
-  a.slots = w.slots;
+  a.fused = fused ? 1 : 0;
+  a.pub = w.pub;
+  if (fused) {
+    a.st = w.st + size_t(c % 2) * size_t(members);
+    a.st_next = w.st + size_t((c + 1) % 2) * size_t(members);
+    a.slots = w.slots + size_t((c + 1) % 2) * 2 * size_t(w.nslots);
+    a.slots_prev = w.slots + size_t(c % 2) * 2 * size_t(w.nslots);
+  } else {
+    a.st = w.st;
+    a.slots = w.slots;
+  }
   a.beta = o.beta;
   a.tol = o.tol;
   a.max_iter = o.max_iter;
@@ -372,6 +389,13 @@ PRArgs pr_args(const PRWork& w, const PROptsResolved& o, const void* tele, const
 }
 
 // Host copy of the members' states (synchronises s).
+// Fold a run of fused iterations' last partials into the states of parity 0
+// (no-op after iterations with a finish kernel) and clear the published values.
+int flush_states(PRWork& w, const PROptsResolved& o, int members, hipStream_t s) {
+  HIP_TRY(launch_pr_flush(w.st, w.slots, o.tol, o.max_iter, w.pub, members, s));
+  return BVMV_OK;
+}
+
 int read_states(PRWork& w, int members, hipStream_t s) {
   HIP_TRY(hipMemcpyAsync(w.h_st, w.st, sizeof(PRState) * size_t(members), hipMemcpyDeviceToHost, s));
   HIP_TRY(hipStreamSynchronize(s));
@@ -412,9 +436,9 @@ int planned_iterations(const PRState* sts, const PROptsResolved& o, int members)
 // once and kept with the working set while its key holds.
 template <class IterFn>
 int replay_until_done(PRWork& w, hipStream_t cap, const PROptsResolved& o, const void* tele, const int32_t* outdeg,
-                      int members, int k, hipStream_t s, IterFn iter) {
+                      int members, int k, hipStream_t s, IterFn iter, bool fused) {
   const bool same = w.exec[0] && w.key_tele == tele && w.key_beta == o.beta && w.key_tol == o.tol &&
-                    w.key_max_iter == o.max_iter && w.key_chunk == o.chunk;
+                    w.key_max_iter == o.max_iter && w.key_chunk == o.chunk && w.key_fused == int(fused);
   if (!same) {
     w.drop_graph();
     w.key_tele = tele;
@@ -422,6 +446,7 @@ int replay_until_done(PRWork& w, hipStream_t cap, const PROptsResolved& o, const
     w.key_tol = o.tol;
     w.key_max_iter = o.max_iter;
     w.key_chunk = o.chunk;
+    w.key_fused = int(fused);
   }
   // the captured run of `len` iterations (captured on first use)
   auto run_of = [&](int len, hipGraphExec_t* out) -> int {
@@ -436,7 +461,8 @@ int replay_until_done(PRWork& w, hipStream_t cap, const PROptsResolved& o, const
     if (slot < 0) return fail(BVMV_EDEVICE, "PageRank: no free graph slot");
     HIP_TRY(hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal));
     hipError_t ce = hipSuccess;
-    for (int c = 0; c < len && ce == hipSuccess; ++c) ce = iter(pr_args(w, o, tele, outdeg, members, k, c), cap);
+    for (int c = 0; c < len && ce == hipSuccess; ++c)
+      ce = iter(pr_args(w, o, tele, outdeg, members, k, c, fused), cap);
     hipGraph_t gr = nullptr;
     hipError_t ee = hipStreamEndCapture(cap, &gr);
     if (ce != hipSuccess) {
@@ -465,6 +491,7 @@ int replay_until_done(PRWork& w, hipStream_t cap, const PROptsResolved& o, const
       left -= len;
       done_iters += len;
     }
+    if (int rc = flush_states(w, o, members, s)) return rc;
     if (int rc = read_states(w, members, s)) return rc;
     bool all = true;
     for (int gI = 0; gI < members; ++gI) all = all && w.h_st[gI].done;
@@ -514,7 +541,8 @@ int run_pagerank(PRWork& w, hipStream_t cap, const PROptsResolved& o, int64_t n_
     std::memcpy(w.h_st, states.data(), sizeof(PRState) * size_t(members));
     HIP_TRY(hipMemcpyAsync(w.st, w.h_st, sizeof(PRState) * size_t(members), hipMemcpyHostToDevice, s));
     HIP_TRY(init(st0, tele, w.p[0], w.z[0], s));
-    return BVMV_OK;
+    // (clears the published values of fused iterations; nothing is pending)
+    return flush_states(w, o, members, s);
   };
   int used = start ? 1 : 0;
   if (o.fallback && start && members == 1 && k == 1) {
@@ -523,7 +551,7 @@ int run_pagerank(PRWork& w, hipStream_t cap, const PROptsResolved& o, int64_t n_
     double r[2] = {0.0, 0.0};
     for (int cand = 0; cand < 2; ++cand) {
       if (int rc = reset(cand == 0 ? start : nullptr)) return rc;
-      HIP_TRY(iter(pr_args(w, o, tele, outdeg, members, k, 0), s));
+      HIP_TRY(iter(pr_args(w, o, tele, outdeg, members, k, 0, false), s));
       if (int rc = read_states(w, 1, s)) return rc;
       r[cand] = w.h_st[0].resid;
     }
@@ -533,7 +561,8 @@ int run_pagerank(PRWork& w, hipStream_t cap, const PROptsResolved& o, int64_t n_
     }
   }
   if (int rc = reset(start)) return rc;
-  if (int rc = replay_until_done(w, cap, o, tele, outdeg, members, k, s, iter)) return rc;
+  // one right-hand side: fused iterations (no finish kernel between products)
+  if (int rc = replay_until_done(w, cap, o, tele, outdeg, members, k, s, iter, k == 1)) return rc;
   HIP_TRY(out(w, s));
   return fill_results(w, members, used, 0, 0, res);
 }
@@ -637,7 +666,7 @@ int run_phase(bvmv_graph* g, const PROptsResolved& o, int K, int& c, int& since,
   for (; since < K; ++since, ++c) {
     if (since == K - 2) HIP_TRY(hipMemcpyAsync(lw.t[0], w.p[(c + 1) % 2], bytes, hipMemcpyDeviceToDevice, s));
     if (since == K - 1) HIP_TRY(hipMemcpyAsync(lw.t[1], w.p[(c + 1) % 2], bytes, hipMemcpyDeviceToDevice, s));
-    HIP_TRY(launch_bv_pagerank_iter(g->L, o.prec, pr_args(w, o, nullptr, g->d_outdeg, g->ngraphs, 1, c), s));
+    HIP_TRY(launch_bv_pagerank_iter(g->L, o.prec, pr_args(w, o, nullptr, g->d_outdeg, g->ngraphs, 1, c, false), s));
   }
   return BVMV_OK;
 }
@@ -702,7 +731,7 @@ int run_learned(bvmv_graph* g, const PROptsResolved& o, const bvmv_mlp* m, void*
     HIP_TRY(hipMemcpyAsync(lw.t[1], w.p[c % 2], bytes, hipMemcpyDeviceToDevice, s));
     HIP_TRY(launch_pr_init(L, o.prec, lw.t[0], nullptr, w.p[0], w.z[0], g->d_outdeg, w.st, w.slots, M, s, 1,
                            at_k[0].iter));
-    HIP_TRY(launch_bv_pagerank_iter(L, o.prec, pr_args(w, o, nullptr, g->d_outdeg, M, 1, 0), s));
+    HIP_TRY(launch_bv_pagerank_iter(L, o.prec, pr_args(w, o, nullptr, g->d_outdeg, M, 1, 0, false), s));
     c = 1;
     if (int rc = read_states(w, M, s)) return rc;
     bool any_rejected = false;
@@ -730,13 +759,13 @@ int run_learned(bvmv_graph* g, const PROptsResolved& o, const bvmv_mlp* m, void*
   }
   if (!done && c % 2) {
     // the captured chunk starts from buffer 0
-    HIP_TRY(launch_bv_pagerank_iter(L, o.prec, pr_args(w, o, nullptr, g->d_outdeg, M, 1, c), s));
+    HIP_TRY(launch_bv_pagerank_iter(L, o.prec, pr_args(w, o, nullptr, g->d_outdeg, M, 1, c, false), s));
     if (int rc = read_states(w, M, s)) return rc;
     done = all_done();
   }
   if (!done) {
     auto iter = [&](const PRArgs& a, hipStream_t cs) { return launch_bv_pagerank_iter(L, o.prec, a, cs); };
-    if (int rc = replay_until_done(w, g->cap, o, nullptr, g->d_outdeg, M, 1, s, iter)) return rc;
+    if (int rc = replay_until_done(w, g->cap, o, nullptr, g->d_outdeg, M, 1, s, iter, false)) return rc;
   }
   HIP_TRY(copy_member_outputs(w, g->offsets, o.prec, p_out, s));
   return fill_results(w, M, 0, rejected.data(), accepted.data(), res);
@@ -1096,12 +1125,14 @@ int bvmv_pagerank_noalloc(bvmv_graph* g, const bvmv_pr_opts* opts, const void* t
   hipStream_t s = static_cast<hipStream_t>(stream);
   const DevLayout& L = g->L;
   const int prec = o.prec;
-  // carve: p0, p1, z0, z1 (n elements each), the block partials, the state
+  // carve: p0, p1, z0, z1 (n elements each), the block partials of both
+  // parities, the states of both parities, the two published values
   auto up256 = [](uint64_t v) { return (v + 255) / 256 * 256; };
   const uint64_t vec = up256(uint64_t(g->n) * elem_size(prec));
   const uint64_t nslots = uint64_t(L.ntiles) / kTilesPerBlock + 1;
   const uint64_t slot_bytes = up256(16 * nslots);
-  const uint64_t need = 4 * vec + slot_bytes + up256(sizeof(PRState));
+  const uint64_t st_bytes = up256(2 * sizeof(PRState));
+  const uint64_t need = 4 * vec + 2 * slot_bytes + st_bytes + 256;
   if (need > kNoAllocScratchBytes)
     return fail(BVMV_EINVAL, "graph too large for the allocation-free PageRank: its working set needs " +
                                  std::to_string(need) + " bytes, the fixed array holds " +
@@ -1111,8 +1142,9 @@ int bvmv_pagerank_noalloc(bvmv_graph* g, const bvmv_pr_opts* opts, const void* t
   unsigned char* b = static_cast<unsigned char*>(base);
   void* p[2] = {b, b + vec};
   void* z[2] = {b + 2 * vec, b + 3 * vec};
-  double* slots = reinterpret_cast<double*>(b + 4 * vec);
-  PRState* st = reinterpret_cast<PRState*>(b + 4 * vec + slot_bytes);
+  double* slots = reinterpret_cast<double*>(b + 4 * vec);  // parity 0, then parity 1 at slot_bytes
+  PRState* st = reinterpret_cast<PRState*>(b + 4 * vec + 2 * slot_bytes);  // parity 0, then 1
+  double* pub = reinterpret_cast<double*>(b + 4 * vec + 2 * slot_bytes + st_bytes);
   PRState st0;
   std::memset(&st0, 0, sizeof(st0));
   st0.inv_n = 1.0 / double(g->n);
@@ -1120,11 +1152,13 @@ int bvmv_pagerank_noalloc(bvmv_graph* g, const bvmv_pr_opts* opts, const void* t
   st0.blk_hi = L.ntiles / kTilesPerBlock;
   HIP_TRY(launch_pr_state_set(st, st0, s));
   HIP_TRY(launch_pr_init(L, prec, start, teleport, p[0], z[0], g->d_outdeg, st, slots, 1, s));
+  // (clears the published values; the start state has nothing pending)
+  HIP_TRY(launch_pr_flush(st, slots, o.tol, o.max_iter, pub, 1, s));
   PRArgs a{};
   a.tele = teleport;
   a.outdeg = g->d_outdeg;
-  a.st = st;
-  a.slots = slots;
+  a.fused = 1;
+  a.pub = pub;
   a.beta = o.beta;
   a.tol = o.tol;
   a.max_iter = o.max_iter;
@@ -1142,8 +1176,13 @@ int bvmv_pagerank_noalloc(bvmv_graph* g, const bvmv_pr_opts* opts, const void* t
       a.z_cur = z[c % 2];
       a.z_new = z[(c + 1) % 2];
       a.buf = (c + 1) % 2;
+      a.st = st + c % 2;
+      a.st_next = st + (c + 1) % 2;
+      a.slots = slots + size_t((c + 1) % 2) * (slot_bytes / 8);
+      a.slots_prev = slots + size_t(c % 2) * (slot_bytes / 8);
       HIP_TRY(launch_bv_pagerank_iter(L, prec, a, s));
     }
+    HIP_TRY(launch_pr_flush(st, slots, o.tol, o.max_iter, pub, 1, s));
     HIP_TRY(hipMemcpyAsync(&h, st, sizeof(PRState), hipMemcpyDeviceToHost, s));
     HIP_TRY(hipStreamSynchronize(s));
     if (h.done) break;

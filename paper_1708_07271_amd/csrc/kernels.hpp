@@ -54,7 +54,7 @@ struct PRState {
   int32_t final_buf; // buffer (0/1) holding the final iterate once done
   uint32_t blk_lo, blk_hi;    // block range of the member's partial slots
   uint32_t slot0;             // the member's first slot (slots slot0 + blk_lo .. slot0 + blk_hi - 1)
-  uint32_t pad;
+  int32_t pending;            // fused iterations: the iterate's partials are not folded in yet
   double resid_prev;          // the residual of the iteration before the last (0 before two iterations)
 };
 
@@ -72,6 +72,17 @@ struct PRArgs {
   int32_t buf;           // index of p_new's buffer (0/1)
   int32_t members;       // PRState entries (member graphs, or right-hand sides)
   int32_t k;             // right-hand sides (column-major p, z, teleport with leading dimension n)
+  // Fused iterations (one right-hand side): no finish kernel between
+  // products.  The iteration reading buffer c = 1 - buf reads the states st
+  // and the partials slots_prev of parity c (left by the iteration before),
+  // writes its partials to slots and, from the first block of each member,
+  // the member's next state to st_next; that block folds the pending partials
+  // and publishes the dangling mass in pub[2 member + c] for the member's
+  // other blocks.
+  int32_t fused;
+  PRState* st_next;
+  const double* slots_prev;
+  double* pub;           // 2 doubles per member
 };
 
 hipError_t launch_bv_multiply(const DevLayout& L, int prec, const void* x, void* y, hipStream_t s);
@@ -79,6 +90,9 @@ hipError_t launch_bv_multiply(const DevLayout& L, int prec, const void* x, void*
 hipError_t launch_bv_multiply_add(const DevLayout& L, int prec, const void* x, void* y, hipStream_t s);
 hipError_t launch_bv_degrees(const DevLayout& L, int32_t* deg, hipStream_t s);
 hipError_t launch_bv_pagerank_iter(const DevLayout& L, int prec, const PRArgs& a, hipStream_t s);
+// fold the last fused iteration's partials into the states (see PRArgs)
+hipError_t launch_pr_flush(PRState* st, const double* slots, double tol, int32_t max_iter, double* pub, int members,
+                           hipStream_t s);
 // z = p / d, dangling mass and state reset for the start vector (tile grid)
 // (normalize: p0 = start / the member's delta field; iter0: the states' iteration count)
 hipError_t launch_pr_init(const DevLayout& L, int prec, const void* start, const void* tele, void* p0, void* z0,
