@@ -749,7 +749,6 @@ __global__ void __launch_bounds__(kThreads) pr_flush_kernel(PRState* st_all, con
 // PageRank update of Eq. (1), dangling mass sent to the teleport vector.
 // With a.fused the dangling mass of the iterate being multiplied comes from
 // the member's published value (block_start), not from its state.
-constexpr int kPubPolls = 48;  // polls of a published value before a wave folds itself
 template <class M>
 struct EpiPR {
   PRArgs a;
@@ -781,12 +780,12 @@ struct EpiPR {
 
   // The dangling mass for this iteration (fused): the published value (a
   // first read `early` taken with the tile's loads), or, when it is still
-  // unset after kPubPolls reads, the same fold done by this wave from the
+  // unset after a.pub_polls reads, the same fold done by this wave from the
   // same state and partials.  kPubDone: the member has converged.
   __device__ double resolve(uint32_t graph, double early) const {
     const double* pp = a.pub + 2 * size_t(graph) + cur();
-    double v = readlane_f64(early, 0);
-    for (int k = 0; k < kPubPolls && __builtin_isnan(v); ++k) {
+    double v = a.pub_polls < 0 ? pub_unset() : readlane_f64(early, 0);
+    for (int k = 0; k < a.pub_polls && __builtin_isnan(v); ++k) {
       if (k) __builtin_amdgcn_s_sleep(8);
       v = readlane_f64(pub_load(pp), 0);
     }

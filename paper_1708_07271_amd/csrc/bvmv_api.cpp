@@ -5,6 +5,7 @@
 #include <atomic>
 #include <climits>
 #include <cmath>
+#include <cstdlib>
 #include <cstring>
 #include <map>
 #include <memory>
@@ -99,7 +100,7 @@ struct PRWork {
   // key of the captured graphs
   const void* key_tele = nullptr;
   double key_beta = -1, key_tol = -1;
-  int key_max_iter = -1, key_chunk = -1, key_fused = -1;
+  int key_max_iter = -1, key_chunk = -1, key_fused = -1, key_polls = -2;
 
   void drop_graph() {
     for (int i = 0; i < kGraphs; ++i) {
@@ -357,6 +358,16 @@ int upload_layout(bvmv_graph* g) {
   return BVMV_OK;
 }
 
+// Reads of an unset published value before a wave of a fused PageRank
+// iteration folds the partials itself: kPubPolls, or BVMV_FOLD_POLLS from the
+// environment (-1: every wave folds itself; a test of that path).
+int32_t fold_polls() {
+  const char* e = std::getenv("BVMV_FOLD_POLLS");
+  if (!e || !*e) return kPubPolls;
+  const long v = std::strtol(e, nullptr, 10);
+  return int32_t(std::max<long>(-1, std::min<long>(v, 1 << 20)));
+}
+
 // Arguments of the iteration that reads buffer c % 2 and writes the other;
 // fused: without a finish kernel, states and slots taken by parity (PRArgs).
 PRArgs pr_args(const PRWork& w, const PROptsResolved& o, const void* tele, const int32_t* outdeg, int members, int k,
@@ -370,6 +381,7 @@ PRArgs pr_args(const PRWork& w, const PROptsResolved& o, const void* tele, const
   a.outdeg = outdeg;
   a.fused = fused ? 1 : 0;
   a.pub = w.pub;
+  a.pub_polls = fold_polls();
   if (fused) {
     a.st = w.st + size_t(c % 2) * size_t(members);
     a.st_next = w.st + size_t((c + 1) % 2) * size_t(members);
@@ -438,7 +450,8 @@ template <class IterFn>
 int replay_until_done(PRWork& w, hipStream_t cap, const PROptsResolved& o, const void* tele, const int32_t* outdeg,
                       int members, int k, hipStream_t s, IterFn iter, bool fused) {
   const bool same = w.exec[0] && w.key_tele == tele && w.key_beta == o.beta && w.key_tol == o.tol &&
-                    w.key_max_iter == o.max_iter && w.key_chunk == o.chunk && w.key_fused == int(fused);
+                    w.key_max_iter == o.max_iter && w.key_chunk == o.chunk && w.key_fused == int(fused) &&
+                    w.key_polls == fold_polls();
   if (!same) {
     w.drop_graph();
     w.key_tele = tele;
@@ -447,6 +460,7 @@ int replay_until_done(PRWork& w, hipStream_t cap, const PROptsResolved& o, const
     w.key_max_iter = o.max_iter;
     w.key_chunk = o.chunk;
     w.key_fused = int(fused);
+    w.key_polls = fold_polls();
   }
   // the captured run of `len` iterations (captured on first use)
   auto run_of = [&](int len, hipGraphExec_t* out) -> int {
@@ -1159,6 +1173,7 @@ int bvmv_pagerank_noalloc(bvmv_graph* g, const bvmv_pr_opts* opts, const void* t
   a.outdeg = g->d_outdeg;
   a.fused = 1;
   a.pub = pub;
+  a.pub_polls = fold_polls();
   a.beta = o.beta;
   a.tol = o.tol;
   a.max_iter = o.max_iter;

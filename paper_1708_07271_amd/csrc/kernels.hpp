@@ -83,7 +83,11 @@ struct PRArgs {
   PRState* st_next;
   const double* slots_prev;
   double* pub;           // 2 doubles per member
+  // reads of an unset published value before a wave folds the partials
+  // itself; -1: every wave folds itself (a test of that path)
+  int32_t pub_polls;
 };
+constexpr int32_t kPubPolls = 48;
 
 hipError_t launch_bv_multiply(const DevLayout& L, int prec, const void* x, void* y, hipStream_t s);
 // y += A x (column blocks after the first)

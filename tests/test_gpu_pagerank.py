@@ -242,6 +242,43 @@ def test_edgeless_and_determinism(P):
     assert ra == rb and np.array_equal(a, b)
 
 
+
+def test_fused_iteration_own_fold(P, monkeypatch):
+    """Iterations without a finish kernel: the first block of each member
+    publishes the dangling mass; a wave that does not see it in time folds the
+    same partials itself.  Forcing every wave to fold itself
+    (BVMV_FOLD_POLLS=-1), or to fold whenever its first read finds nothing
+    (0), must give the same iterates bit for bit, for a single graph in both
+    precisions, a group and the CSR baseline."""
+    g = B.web_graph(40_000, 14.0, 91)
+    G = P.bvmv_load(B.encode(g).data, keep_lists=1)
+    C = P.bvmv_csr_create(G)
+    gs = [B.web_graph(n, 12.0, 300 + i) for i, n in enumerate((5000, 900, 17_000))]
+    grp = P.bvmv_group([P.bvmv_load(B.encode(h).data) for h in gs])
+    offs = P.bvmv_group_offsets(grp)
+
+    def runs():
+        out = []
+        for prec in (P.BVMV_F64, P.BVMV_F32_COMP):
+            out.append(_pr(P, G, g.n, prec))
+        out.append(_pr(P, grp, offs[-1], P.BVMV_F32_COMP))
+        p = torch.empty(g.n, dtype=torch.float32, device=DEV)
+        res = P.bvmv_csr_pagerank(C, p)
+        torch.cuda.synchronize()
+        out.append((p.cpu().numpy().astype(np.float64), res))
+        return out
+
+    base = runs()
+    for polls in ("-1", "0"):
+        monkeypatch.setenv("BVMV_FOLD_POLLS", polls)
+        other = runs()
+        for (a, ra), (b, rb) in zip(base, other):
+            assert ra == rb, polls
+            assert np.array_equal(a, b), polls
+    monkeypatch.delenv("BVMV_FOLD_POLLS")
+    p_ref = pagerank.pagerank(g.rowptr, g.col, 0.85, iters=base[1][1][0][0])[0]
+    assert _rel(base[1][0], p_ref) < TOL.F32C
+
 def test_group_equals_solo(P):
     sizes = [3000, 800, 12_000, 5000, 200]
     gs = [B.web_graph(n, 10.0 + i, 200 + i) for i, n in enumerate(sizes)]
