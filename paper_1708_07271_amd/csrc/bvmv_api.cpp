@@ -400,7 +400,6 @@ PRArgs pr_args(const PRWork& w, const PROptsResolved& o, const void* tele, const
   return a;
 }
 
-// Host copy of the members' states (synchronises s).
 // Fold a run of fused iterations' last partials into the states of parity 0
 // (no-op after iterations with a finish kernel) and clear the published values.
 int flush_states(PRWork& w, const PROptsResolved& o, int members, hipStream_t s) {
@@ -408,6 +407,7 @@ int flush_states(PRWork& w, const PROptsResolved& o, int members, hipStream_t s)
   return BVMV_OK;
 }
 
+// Host copy of the members' states (synchronises s).
 int read_states(PRWork& w, int members, hipStream_t s) {
   HIP_TRY(hipMemcpyAsync(w.h_st, w.st, sizeof(PRState) * size_t(members), hipMemcpyDeviceToHost, s));
   HIP_TRY(hipStreamSynchronize(s));
@@ -575,8 +575,12 @@ int run_pagerank(PRWork& w, hipStream_t cap, const PROptsResolved& o, int64_t n_
     }
   }
   if (int rc = reset(start)) return rc;
-  // one right-hand side: fused iterations (no finish kernel between products)
-  if (int rc = replay_until_done(w, cap, o, tele, outdeg, members, k, s, iter, k == 1)) return rc;
+  // one graph and one right-hand side: fused iterations (no finish kernel
+  // between products).  A group keeps its finish kernel: with many members
+  // the waves of each wait on that member's first block, and the group ran
+  // about 5% slower fused.
+  const bool fused = k == 1 && members == 1;
+  if (int rc = replay_until_done(w, cap, o, tele, outdeg, members, k, s, iter, fused)) return rc;
   HIP_TRY(out(w, s));
   return fill_results(w, members, used, 0, 0, res);
 }
@@ -672,16 +676,25 @@ int compute_structural(bvmv_graph* g, float* F, int64_t stride, hipStream_t s) {
 // iterate K - 2 into lw.t[1] just before the buffers they occupy are
 // overwritten, so that at the end p_K, p_{K-1}, p_{K-2}, p_{K-3} are in
 // w.p[c % 2], w.p[(c + 1) % 2], lw.t[1], lw.t[0].  Iterations of a member
-// already done are skipped by the kernels.
+// already done are skipped by the kernels.  The states start and end folded
+// in w.st (parity 0).  On a single graph, when the phase ends on an even c,
+// its iterations are fused (no finish kernel between products; the states
+// enter at parity c % 2 and the last partials are folded by the flush), else
+// each has its finish kernel, as run_pagerank does.
 int run_phase(bvmv_graph* g, const PROptsResolved& o, int K, int& c, int& since, hipStream_t s) {
   PRWork& w = g->pr;
   LearnWork& lw = g->lw;
+  const int M = g->ngraphs;
   const size_t bytes = size_t(g->n) * elem_size(o.prec);
+  const bool fused = M == 1 && since < K && (c + K - since) % 2 == 0;
+  if (fused && c % 2)
+    HIP_TRY(hipMemcpyAsync(w.st + M, w.st, sizeof(PRState) * size_t(M), hipMemcpyDeviceToDevice, s));
   for (; since < K; ++since, ++c) {
     if (since == K - 2) HIP_TRY(hipMemcpyAsync(lw.t[0], w.p[(c + 1) % 2], bytes, hipMemcpyDeviceToDevice, s));
     if (since == K - 1) HIP_TRY(hipMemcpyAsync(lw.t[1], w.p[(c + 1) % 2], bytes, hipMemcpyDeviceToDevice, s));
-    HIP_TRY(launch_bv_pagerank_iter(g->L, o.prec, pr_args(w, o, nullptr, g->d_outdeg, g->ngraphs, 1, c, false), s));
+    HIP_TRY(launch_bv_pagerank_iter(g->L, o.prec, pr_args(w, o, nullptr, g->d_outdeg, M, 1, c, fused), s));
   }
+  if (fused) return flush_states(w, o, M, s);
   return BVMV_OK;
 }
 
@@ -695,7 +708,8 @@ int start_learned(bvmv_graph* g, const PROptsResolved& o, hipStream_t s) {
   std::memcpy(w.h_st, states.data(), sizeof(PRState) * size_t(M));
   HIP_TRY(hipMemcpyAsync(w.st, w.h_st, sizeof(PRState) * size_t(M), hipMemcpyHostToDevice, s));
   HIP_TRY(launch_pr_init(g->L, o.prec, nullptr, nullptr, w.p[0], w.z[0], g->d_outdeg, w.st, w.slots, M, s));
-  return BVMV_OK;
+  // (clears the published values of fused iterations; nothing is pending)
+  return flush_states(w, o, M, s);
 }
 
 // PageRank with learned warm restarts (a single graph or a group, uniform
@@ -778,8 +792,11 @@ int run_learned(bvmv_graph* g, const PROptsResolved& o, const bvmv_mlp* m, void*
     done = all_done();
   }
   if (!done) {
+    // (fused on a single graph, as run_pagerank; the published values were
+    // cleared by the last flush, and the iterations since then had finish
+    // kernels and left them alone)
     auto iter = [&](const PRArgs& a, hipStream_t cs) { return launch_bv_pagerank_iter(L, o.prec, a, cs); };
-    if (int rc = replay_until_done(w, g->cap, o, nullptr, g->d_outdeg, M, 1, s, iter, false)) return rc;
+    if (int rc = replay_until_done(w, g->cap, o, nullptr, g->d_outdeg, M, 1, s, iter, M == 1)) return rc;
   }
   HIP_TRY(copy_member_outputs(w, g->offsets, o.prec, p_out, s));
   return fill_results(w, M, 0, rejected.data(), accepted.data(), res);

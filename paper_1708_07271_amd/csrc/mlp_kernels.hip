@@ -2,7 +2,7 @@
 //   - per-node structural features (12 per node) from degrees, the stream's
 //     row statistics and three products with the compressed graph;
 //   - the MLP 12 -> 64 -> 64 -> 1 with GELU: forward and backward of both
-//     hidden layers on MFMA (v_mfma_f32_32x32x8_bf16: BF16 operands, FP32
+//     hidden layers on MFMA (v_mfma_f32_32x32x16_bf16: BF16 operands, FP32
 //     accumulation), biases, GELU and the output layer in FP32;
 //   - deterministic reduction of per-wave gradient partials and Adam on FP32
 //     master parameters with BF16 weight copies.
@@ -21,6 +21,8 @@ namespace bvmv {
 namespace {
 
 typedef short s4 __attribute__((ext_vector_type(4)));
+typedef short s8 __attribute__((ext_vector_type(8)));
+typedef __bf16 bf8v __attribute__((ext_vector_type(8)));
 typedef float f16v __attribute__((ext_vector_type(16)));
 typedef float f2v __attribute__((ext_vector_type(2)));
 typedef __bf16 bf2v __attribute__((ext_vector_type(2)));
@@ -51,7 +53,15 @@ __device__ __forceinline__ float gelu_grad(float z) {
   return s + 1.702f * z * s * (1.0f - s);
 }
 
-__device__ __forceinline__ f16v mfma(s4 a, s4 b, f16v c) { return __builtin_amdgcn_mfma_f32_32x32x8bf16_1k(a, b, c, 0, 0, 0); }
+// One 32x32x16 product over two 8-wide K steps: D += A0 B0 + A1 B1.  A lane
+// holds 8 K positions of its A row and the same 8 of its B column, so pairing
+// the steps' operands the same way in A and B gives this sum whatever the
+// hardware's order of K within the instruction.
+__device__ __forceinline__ f16v mfma2(s4 a0, s4 a1, s4 b0, s4 b1, f16v c) {
+  const s8 a = __builtin_shufflevector(a0, a1, 0, 1, 2, 3, 4, 5, 6, 7);
+  const s8 b = __builtin_shufflevector(b0, b1, 0, 1, 2, 3, 4, 5, 6, 7);
+  return __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf8v, a), __builtin_bit_cast(bf8v, b), c, 0, 0, 0);
+}
 
 // four values rounded to BF16 (to nearest, ties to even: the same rounding
 // as bf16_bits for finite values), two per conversion instruction
@@ -68,13 +78,14 @@ __device__ __forceinline__ void wave_sync() {
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-// Layout of the 32x32x8 MFMA (64 lanes, h = lane / 32):
+// Operands are built in 8-wide K steps (64 lanes, h = lane / 32):
 //   A (32 x 8):  lane holds A[lane % 32][4h + e], e = 0..3;
 //   B (8 x 32):  lane holds B[4h + e][lane % 32];
-//   D (32 x 32): register v of a lane holds D[8 (v / 4) + 4h + v % 4][lane % 32].
-// So the D registers 4s .. 4s+3 of a lane are, for its column, the rows
-// 8s + 4h + e: exactly an A operand of a product whose K runs over those
-// rows (used for the weight gradients, K = nodes).
+//   D (32 x 32): register v of a lane holds D[8 (v / 4) + 4h + v % 4][lane % 32],
+// and two steps go to one 32x32x16 instruction (mfma2).  So the D registers
+// 4s .. 4s+3 of a lane are, for its column, the rows 8s + 4h + e: exactly an
+// A operand of a step whose K runs over those rows (used for the weight
+// gradients, K = nodes).
 __device__ __forceinline__ uint32_t drow(uint32_t v, uint32_t h) { return 8 * (v / 4) + 4 * h + (v % 4); }
 
 constexpr int kSStride = 68;   // bf16 per row of the per-wave transpose buffer (8-byte aligned rows)
@@ -154,8 +165,7 @@ __device__ __forceinline__ void forward_tile(const FeatIn& in, int64_t n, int64_
   // layer 1: z1 = W1 bf(x) + b1, h1 = gelu(z1)
 #pragma unroll
   for (int b = 0; b < 2; ++b) {
-    f16v d = mfma(a1[0], W.b1[b][0], zero);
-    d = mfma(a1[1], W.b1[b][1], d);
+    f16v d = mfma2(a1[0], a1[1], W.b1[b][0], W.b1[b][1], zero);
 #pragma unroll
     for (int v = 0; v < 16; ++v) d[v] += W.bias1[b];
     o.z1[b] = d;
@@ -180,8 +190,9 @@ __device__ __forceinline__ void forward_tile(const FeatIn& in, int64_t n, int64_
   for (int b = 0; b < 2; ++b) {
     f16v d = zero;
 #pragma unroll
-    for (int s = 0; s < 8; ++s)  // B[k][j] = W2[j][k], k = 8s + 4h + e, j = 32b + lane % 32
-      d = mfma(a2[s], *reinterpret_cast<const s4*>(&s_w2[(32 * b + c) * kSStride + 8 * s + 4 * h]), d);
+    for (int s = 0; s < 8; s += 2)  // B[k][j] = W2[j][k], k = 8s + 4h + e, j = 32b + lane % 32
+      d = mfma2(a2[s], a2[s + 1], *reinterpret_cast<const s4*>(&s_w2[(32 * b + c) * kSStride + 8 * s + 4 * h]),
+                *reinterpret_cast<const s4*>(&s_w2[(32 * b + c) * kSStride + 8 * s + 8 + 4 * h]), d);
 #pragma unroll
     for (int v = 0; v < 16; ++v) d[v] += W.bias2[b];
     o.z2[b] = d;
@@ -210,7 +221,10 @@ __device__ __forceinline__ void forward_tile(const FeatIn& in, int64_t n, int64_
 // no transpose through LDS.  Register v of block b holds unit 32b + drow(v, h);
 // the output layer sums the lane's 32 units and the other half's.  The
 // arithmetic is the node-major form's (the same operands and roundings).
-__global__ void __launch_bounds__(kThreads) mlp_forward_kernel(const float* __restrict__ theta,
+// The pass is bound by the GELUs' VALU issue, so it asks for at least five
+// waves per SIMD (the accumulators then stay in VGPRs: 77 registers, six
+// waves, no spills).
+__global__ void __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(5))) mlp_forward_kernel(const float* __restrict__ theta,
                                                                const uint16_t* __restrict__ wq, FeatIn in, int64_t n,
                                                                float* __restrict__ out) {
   __shared__ __align__(16) uint16_t s_w2[kNh * kSStride];
@@ -237,8 +251,7 @@ __global__ void __launch_bounds__(kThreads) mlp_forward_kernel(const float* __re
     s4 h1q[2][4];
 #pragma unroll
     for (int b = 0; b < 2; ++b) {
-      f16v d = mfma(W.b1[b][0], a1[0], zero);
-      d = mfma(W.b1[b][1], a1[1], d);
+      f16v d = mfma2(W.b1[b][0], W.b1[b][1], a1[0], a1[1], zero);
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
         const float4 bb = *reinterpret_cast<const float4*>(&s_c[z + 32 * b + 8 * q + 4 * h]);
@@ -252,9 +265,10 @@ __global__ void __launch_bounds__(kThreads) mlp_forward_kernel(const float* __re
     for (int b = 0; b < 2; ++b) {
       f16v d = zero;
 #pragma unroll
-      for (int s = 0; s < 8; ++s)  // A[j][k] = W2[j][k], j = 32b + lane % 32, k = 8s + 4h + e
-        d = mfma(*reinterpret_cast<const s4*>(&s_w2[z + (32 * b + c) * kSStride + 8 * s + 4 * h]), h1q[s / 4][s % 4],
-                 d);
+      for (int s = 0; s < 8; s += 2)  // A[j][k] = W2[j][k], j = 32b + lane % 32, k = 8s + 4h + e
+        d = mfma2(*reinterpret_cast<const s4*>(&s_w2[z + (32 * b + c) * kSStride + 8 * s + 4 * h]),
+                  *reinterpret_cast<const s4*>(&s_w2[z + (32 * b + c) * kSStride + 8 * s + 8 + 4 * h]),
+                  h1q[s / 4][s % 4], h1q[s / 4][s % 4 + 1], d);
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
         const float4 bb = *reinterpret_cast<const float4*>(&s_c[z + kNh + 32 * b + 8 * q + 4 * h]);
@@ -337,7 +351,7 @@ __global__ void __launch_bounds__(kThreads) mlp_backward_kernel(const float* __r
     for (int bk = 0; bk < 2; ++bk) {
       f16v gw = zero;
 #pragma unroll
-      for (int s = 0; s < 4; ++s) gw = mfma(dq[s], o.h1q[bk][s], gw);
+      for (int s = 0; s < 4; s += 2) gw = mfma2(dq[s], dq[s + 1], o.h1q[bk][s], o.h1q[bk][s + 1], gw);
 #pragma unroll
       for (int v = 0; v < 16; ++v) out[oW2 + (32 * bj + drow(v, h)) * kNh + 32 * bk + c] = gw[v];
     }
@@ -362,11 +376,13 @@ __global__ void __launch_bounds__(kThreads) mlp_backward_kernel(const float* __r
   for (int bk = 0; bk < 2; ++bk) {
     f16v d = zero;
 #pragma unroll
-    for (int s = 0; s < 8; ++s) {
-      s4 bw;
+    for (int s = 0; s < 8; s += 2) {
+      s4 bw[2];
 #pragma unroll
-      for (int e = 0; e < 4; ++e) bw[e] = short(s_w2[(8 * s + 4 * h + e) * kSStride + 32 * bk + c]);
-      d = mfma(a2[s], bw, d);
+      for (int u = 0; u < 2; ++u)
+#pragma unroll
+        for (int e = 0; e < 4; ++e) bw[u][e] = short(s_w2[(8 * (s + u) + 4 * h + e) * kSStride + 32 * bk + c]);
+      d = mfma2(a2[s], a2[s + 1], bw[0], bw[1], d);
     }
     s4 dq[4];
     float gb1 = 0.0f;
@@ -380,7 +396,7 @@ __global__ void __launch_bounds__(kThreads) mlp_backward_kernel(const float* __r
     if (h == 0) out[oB1 + 32 * bk + c] = gb1;
     f16v gw = zero;
 #pragma unroll
-    for (int s = 0; s < 4; ++s) gw = mfma(dq[s], bx[s], gw);
+    for (int s = 0; s < 4; s += 2) gw = mfma2(dq[s], dq[s + 1], bx[s], bx[s + 1], gw);
     if (c < uint32_t(kNin))
 #pragma unroll
       for (int v = 0; v < 16; ++v) out[oW1 + (32 * bk + drow(v, h)) * kNin + c] = gw[v];

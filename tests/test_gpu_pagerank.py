@@ -249,19 +249,17 @@ def test_fused_iteration_own_fold(P, monkeypatch):
     same partials itself.  Forcing every wave to fold itself
     (BVMV_FOLD_POLLS=-1), or to fold whenever its first read finds nothing
     (0), must give the same iterates bit for bit, for a single graph in both
-    precisions, a group and the CSR baseline."""
+    precisions and the CSR baseline.  (Groups keep a finish kernel per
+    iteration; test_group_equals_solo checks that both forms agree bit for
+    bit.)"""
     g = B.web_graph(40_000, 14.0, 91)
     G = P.bvmv_load(B.encode(g).data, keep_lists=1)
     C = P.bvmv_csr_create(G)
-    gs = [B.web_graph(n, 12.0, 300 + i) for i, n in enumerate((5000, 900, 17_000))]
-    grp = P.bvmv_group([P.bvmv_load(B.encode(h).data) for h in gs])
-    offs = P.bvmv_group_offsets(grp)
 
     def runs():
         out = []
         for prec in (P.BVMV_F64, P.BVMV_F32_COMP):
             out.append(_pr(P, G, g.n, prec))
-        out.append(_pr(P, grp, offs[-1], P.BVMV_F32_COMP))
         p = torch.empty(g.n, dtype=torch.float32, device=DEV)
         res = P.bvmv_csr_pagerank(C, p)
         torch.cuda.synchronize()
