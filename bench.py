@@ -638,6 +638,7 @@ def main():
     ap.add_argument("--workload", default="web-n2p20-d20")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU-baseline leg")
     ap.add_argument("--no-pagerank", action="store_true")
+    ap.add_argument("--pr-runs", type=int, default=20, help="timed PageRank runs (the median is reported)")
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
     ap.add_argument("--only", choices=["bv", "csr", "all"], default="all",
                     help="restrict the timed kernels (profiling runs)")
@@ -770,21 +771,28 @@ def main():
     pr = None
     if not args.no_pagerank and args.only == "all":
         p = torch.empty(g.n, dtype=torch.float32, device=dev)
-        P.bvmv_pagerank(G, p, prec=prec)          # warm (graph capture)
-        torch.cuda.synchronize()
-        t = time.perf_counter()
-        (it, ok, r), = P.bvmv_pagerank(G, p, prec=prec)
-        torch.cuda.synchronize()
-        pr_s = time.perf_counter() - t
-        P.bvmv_csr_pagerank(C, p, prec=prec)
-        torch.cuda.synchronize()
-        t = time.perf_counter()
-        it_c, ok_c, r_c = P.bvmv_csr_pagerank(C, p, prec=prec)
-        torch.cuda.synchronize()
-        pr_csr_s = time.perf_counter() - t
+
+        def pr_runs(fn, runs=args.pr_runs):
+            # one untimed run (graph capture), then the median of `runs` whole
+            # runs, each from the uniform start and bracketed by synchronisations
+            fn()
+            ts = []
+            for _ in range(runs):
+                torch.cuda.synchronize()
+                t = time.perf_counter()
+                res = fn()
+                torch.cuda.synchronize()
+                ts.append(time.perf_counter() - t)
+            return res, float(np.median(ts)), float(min(ts))
+
+        ((it, ok, r),), pr_s, pr_min = pr_runs(lambda: P.bvmv_pagerank(G, p, prec=prec))
+        (it_c, ok_c, r_c), pr_csr_s, pr_csr_min = pr_runs(lambda: P.bvmv_csr_pagerank(C, p, prec=prec))
         pr = {"seconds_to_1e-6": pr_s, "iterations": it, "converged": ok, "residual": r,
-              "csr_seconds_to_1e-6": pr_csr_s, "csr_iterations": it_c, "speedup_vs_csr": pr_csr_s / pr_s}
-        log("pagerank: %.4f s (%d it) vs csr %.4f s (%d it)" % (pr_s, it, pr_csr_s, it_c))
+              "csr_seconds_to_1e-6": pr_csr_s, "csr_iterations": it_c, "speedup_vs_csr": pr_csr_s / pr_s,
+              "runs": args.pr_runs, "statistic": "median of whole runs (min %.6f s, csr min %.6f s)" % (
+                  pr_min, pr_csr_min)}
+        log("pagerank: %.4f s (%d it, median of %d runs) vs csr %.4f s (%d it)" % (pr_s, it, args.pr_runs,
+                                                                                   pr_csr_s, it_c))
 
     alg_bytes = info["layout_bytes"] + 4 * g.n + 4 * g.n     # layout + read x once + write y once
     achieved = alg_bytes / (ms_bv * 1e-3) / 1e9
