@@ -52,7 +52,7 @@ def test_features_match_oracle(P):
     assert np.all(Fg[:, 8:] == 7.0)
 
 
-@pytest.mark.parametrize("prec,K", [(F64, 6), (F64, 10), (F32C, 10)])
+@pytest.mark.parametrize("prec,K", [(F64, 6), (F64, 7), (F64, 10), (F32C, 10)])
 def test_restart_sample_matches_oracle(P, prec, K):
     g = B.web_graph(30_000, 15.0, 32)
     enc = B.encode(g)
@@ -225,8 +225,12 @@ def test_learned_zero_network_follows_plain(P, prec):
     assert float(((pl.double() - pp.double()).abs() / pp.double()).max()) < tol
 
 
-@pytest.mark.parametrize("prec", [F64, F32C])
-def test_learned_rejected_restart_is_plain_run(P, prec):
+@pytest.mark.parametrize("prec,K", [(F64, 10), (F32C, 10), (F32C, 7)])
+def test_learned_rejected_restart_is_plain_run(P, prec, K):
+    """K = 10: the phase runs fused iterations (no finish kernel between
+    products); K = 7 ends on an odd iterate, so the phase has a finish kernel
+    per iteration and the rest is fused.  Either way the run is the plain
+    run bit for bit."""
     g = B.web_graph(40_000, 15.0, 52)
     G = P.bvmv_load(B.encode(g).data)
     dt = torch.float64 if prec == F64 else torch.float32
@@ -234,7 +238,7 @@ def test_learned_rejected_restart_is_plain_run(P, prec):
     rp = P.bvmv_pagerank_detail(G, pp, prec=prec)[0]
     m = P.bvmv_mlp_create(_const_theta(1e6))
     pl = torch.empty(g.n, dtype=dt, device=DEV)
-    rl = P.bvmv_pagerank_detail(G, pl, prec=prec, mlp=m)[0]
+    rl = P.bvmv_pagerank_detail(G, pl, prec=prec, mlp=m, restart_every=K)[0]
     # a wild correction fails the probe once; the run resumes from p_K itself
     assert rl["restarts_accepted"] == 0 and rl["restarts_rejected"] == 1
     assert rl["iters"] == rp["iters"] and rl["products"] == rp["iters"] + 1
