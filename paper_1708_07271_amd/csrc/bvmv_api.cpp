@@ -368,6 +368,20 @@ int32_t fold_polls() {
   return int32_t(std::max<long>(-1, std::min<long>(v, 1 << 20)));
 }
 
+// Whether PageRank iterations fold the previous partials inside the product
+// launch (fused) or in a finish kernel between launches.  Fused only for one
+// graph and one right-hand side, and up to kFusedMaxBlocks blocks: the fold
+// in the member's first block reads every block's partials, and past about
+// 12k blocks it outlasts the first round of tiles, so the other waves wait
+// on it.  Measured on web-like graphs, median of 40 runs: fused 4% faster at
+// 8k blocks and 2% at 11.7k, equal at 17.6k, 3% slower at 31k; the CSR
+// baseline's iteration 1% faster at 10.5k blocks, 2% slower at 15k and 52%
+// slower at 50k.  A group keeps its finish kernel: with many members the
+// waves of each wait on that member's first block (a 48-graph group ran
+// about 5% slower fused).
+constexpr int64_t kFusedMaxBlocks = 12288;
+bool use_fused(int members, int k, int64_t blocks) { return members == 1 && k == 1 && blocks <= kFusedMaxBlocks; }
+
 // Arguments of the iteration that reads buffer c % 2 and writes the other;
 // fused: without a finish kernel, states and slots taken by parity (PRArgs).
 PRArgs pr_args(const PRWork& w, const PROptsResolved& o, const void* tele, const int32_t* outdeg, int members, int k,
@@ -575,11 +589,8 @@ int run_pagerank(PRWork& w, hipStream_t cap, const PROptsResolved& o, int64_t n_
     }
   }
   if (int rc = reset(start)) return rc;
-  // one graph and one right-hand side: fused iterations (no finish kernel
-  // between products).  A group keeps its finish kernel: with many members
-  // the waves of each wait on that member's first block, and the group ran
-  // about 5% slower fused.
-  const bool fused = k == 1 && members == 1;
+  // (the slots are the blocks' partials plus one)
+  const bool fused = use_fused(members, k, nslots - 1);
   if (int rc = replay_until_done(w, cap, o, tele, outdeg, members, k, s, iter, fused)) return rc;
   HIP_TRY(out(w, s));
   return fill_results(w, members, used, 0, 0, res);
@@ -677,8 +688,9 @@ int compute_structural(bvmv_graph* g, float* F, int64_t stride, hipStream_t s) {
 // overwritten, so that at the end p_K, p_{K-1}, p_{K-2}, p_{K-3} are in
 // w.p[c % 2], w.p[(c + 1) % 2], lw.t[1], lw.t[0].  Iterations of a member
 // already done are skipped by the kernels.  The states start and end folded
-// in w.st (parity 0).  On a single graph, when the phase ends on an even c,
-// its iterations are fused (no finish kernel between products; the states
+// in w.st (parity 0).  Where run_pagerank would fuse (use_fused) and the
+// phase ends on an even c, its iterations are fused (no finish kernel
+// between products; the states
 // enter at parity c % 2 and the last partials are folded by the flush), else
 // each has its finish kernel, as run_pagerank does.
 int run_phase(bvmv_graph* g, const PROptsResolved& o, int K, int& c, int& since, hipStream_t s) {
@@ -686,7 +698,8 @@ int run_phase(bvmv_graph* g, const PROptsResolved& o, int K, int& c, int& since,
   LearnWork& lw = g->lw;
   const int M = g->ngraphs;
   const size_t bytes = size_t(g->n) * elem_size(o.prec);
-  const bool fused = M == 1 && since < K && (c + K - since) % 2 == 0;
+  const bool fused =
+      use_fused(M, 1, int64_t(g->L.ntiles) / kTilesPerBlock) && since < K && (c + K - since) % 2 == 0;
   if (fused && c % 2)
     HIP_TRY(hipMemcpyAsync(w.st + M, w.st, sizeof(PRState) * size_t(M), hipMemcpyDeviceToDevice, s));
   for (; since < K; ++since, ++c) {
@@ -792,11 +805,12 @@ int run_learned(bvmv_graph* g, const PROptsResolved& o, const bvmv_mlp* m, void*
     done = all_done();
   }
   if (!done) {
-    // (fused on a single graph, as run_pagerank; the published values were
+    // (fused where run_pagerank would fuse; the published values were
     // cleared by the last flush, and the iterations since then had finish
     // kernels and left them alone)
     auto iter = [&](const PRArgs& a, hipStream_t cs) { return launch_bv_pagerank_iter(L, o.prec, a, cs); };
-    if (int rc = replay_until_done(w, g->cap, o, nullptr, g->d_outdeg, M, 1, s, iter, M == 1)) return rc;
+    const bool fused = use_fused(M, 1, int64_t(L.ntiles) / kTilesPerBlock);
+    if (int rc = replay_until_done(w, g->cap, o, nullptr, g->d_outdeg, M, 1, s, iter, fused)) return rc;
   }
   HIP_TRY(copy_member_outputs(w, g->offsets, o.prec, p_out, s));
   return fill_results(w, M, 0, rejected.data(), accepted.data(), res);

@@ -307,6 +307,30 @@ def test_csr_pagerank(P):
 
 
 @pytest.mark.slow
+def test_full_size_pagerank_finish_kernel_path(P):
+    """More than 12,288 blocks of tiles (n = 3.3e6, about as many edges as
+    the 2^20 graph): each iteration's partials are folded by a finish kernel
+    between launches instead of inside the next launch, for the compressed
+    layout and for the CSR baseline.  Iteration-matched parity with the
+    oracle."""
+    g = B.web_graph(3_300_000, 6.0, 61)
+    G = P.bvmv_load(B.encode(g).data, keep_lists=1)
+    assert P.bvmv_get_info(G)["ntiles"] // 4 > 12288
+    p, ((it, ok, r),) = _pr(P, G, g.n, P.BVMV_F32_COMP)
+    assert ok
+    p_ref, t_or, _, _ = pagerank.pagerank(g.rowptr, g.col, 0.85, tol=1e-6)
+    assert abs(it - t_or) <= 1
+    p_ref = pagerank.pagerank(g.rowptr, g.col, 0.85, iters=it)[0]
+    assert _rel(p, p_ref) < TOL.F32C
+    C = P.bvmv_csr_create(G)
+    pc = torch.empty(g.n, dtype=torch.float32, device=DEV)
+    itc, okc, rc = P.bvmv_csr_pagerank(C, pc)
+    torch.cuda.synchronize()
+    assert okc and abs(itc - t_or) <= 1
+    pc_ref = p_ref if itc == it else pagerank.pagerank(g.rowptr, g.col, 0.85, iters=itc)[0]
+    assert _rel(pc.cpu().numpy(), pc_ref) < TOL.F32C
+
+
 def test_full_size_pagerank_2p20(P):
     g = B.workload_graph("web-n2p20-d20")
     G = P.bvmv_load(B.encode(g).data)
