@@ -1153,8 +1153,10 @@ int bvmv_pagerank(bvmv_graph* g, const bvmv_pr_opts* opts, const void* teleport,
 // device array instead of allocated buffers: no allocation, no graph capture,
 // no pinned host memory.  Iterations are launched eagerly, `chunk` at a time,
 // and the state is read back after each chunk by a synchronising copy into a
-// host stack variable.  The kernels are bvmv_pagerank's, in the same order, so
-// the results are bit-identical to it.
+// host stack variable.  The iterations are always fused (bvmv_pagerank fuses
+// them up to kFusedMaxBlocks blocks, and the array's limit keeps 64-row
+// layouts below that); the fold order is the same in both forms, so the
+// results are bit-identical to bvmv_pagerank's.
 static_assert(BVMV_NOALLOC_SCRATCH_BYTES == kNoAllocScratchBytes, "the header states the array's size");
 
 int bvmv_pagerank_noalloc(bvmv_graph* g, const bvmv_pr_opts* opts, const void* teleport, const void* start,
