@@ -1,6 +1,6 @@
 """The allocation-free PageRank entry point (bvmv_pagerank_noalloc), through
 the C ABI, against bvmv_pagerank on the same inputs: identical results (the
-same kernels in the same order) on two calls in a row, the second on a
+same kernels and fold order) on two calls in a row, the second on a
 smaller graph, for the double and the two-sum float modes, with a
 personalized teleport vector and a start vector too; a graph whose working
 set does not fit the fixed array is refused before any device work."""
@@ -56,6 +56,22 @@ def test_noalloc_equals_pagerank(P, prec_name):
         assert not ra["converged"] and ra["iters"] == 7 and rb == ra
         assert np.array_equal(a, b)
         del G
+
+
+def test_noalloc_equals_pagerank_past_the_fold_threshold(P):
+    """32-row tiles on n = 2e6: 15,625 blocks, past the 12,288 up to which
+    bvmv_pagerank folds each iteration's partials inside the next launch; it
+    then runs a finish kernel per iteration while the allocation-free call
+    stays fused.  The fold order is the same, so the results are identical."""
+    n = 2_000_000
+    print("noalloc f32c n=%d 32-row tiles" % n, flush=True)
+    g = B.web_graph(n, 6.0, 94)
+    G = P.bvmv_load(B.encode(g).data, tile_rows=32, stage_bytes=2048)
+    assert P.bvmv_get_info(G)["ntiles"] // 4 > 12288
+    a, ra, b, rb = _both(P, G, n, P.BVMV_F32_COMP)
+    assert ra["converged"] and rb == ra
+    assert np.array_equal(a, b)
+    del G
 
 
 def test_noalloc_limit(P):
