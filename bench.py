@@ -84,6 +84,20 @@ class Flusher:
         self.buf.fill_(self.k)
 
 
+class ReadFlusher:
+    """Reads a 1 GiB device buffer (a row-wise max into 1 MiB), so that the
+    caches hold clean unrelated lines: the next launch reads its inputs from
+    HBM without first writing back the dirty lines a write flush leaves."""
+
+    def __init__(self, torch, dev, nbytes=1 << 30):
+        self.torch = torch
+        self.buf = torch.ones(nbytes // 4, dtype=torch.int32, device=dev).view(-1, 1024)
+        self.out = torch.empty(self.buf.shape[0], dtype=torch.int32, device=dev)
+
+    def __call__(self):
+        self.torch.amax(self.buf, dim=1, out=self.out)
+
+
 def time_flushed(fn, steps, warmup, flush, torch):
     """ms per launch with cold caches.  `steps` rounds of (flush, launch) and
     `steps` rounds of the flush alone are each timed between two HIP events on
@@ -763,6 +777,18 @@ def main():
                       "mall_warm_ms": warm_c, "product_over_copy": ms_bv / ms_c}
         log("device copy of the same bytes: %.4f ms from HBM (%.0f GB/s), %.4f ms cache-warm; product / copy %.2f"
             % (ms_c, copy_floor["GBps"], warm_c, ms_bv / ms_c))
+        # the same product and copy after a read flush instead (reported beside
+        # the headline, which keeps the write flush)
+        rflush = ReadFlusher(torch, dev)
+        ms_rb, ms_rf, _ = time_flushed(lambda: P.bvmv_multiply(G, x, y, prec), args.steps, args.warmup, rflush, torch)
+        ms_rc, _, _ = time_flushed(lambda: cb.copy_(ca), args.steps, args.warmup, rflush, torch)
+        copy_floor["read_flush"] = {
+            "product_ms": ms_rb, "copy_ms": ms_rc, "flush_ms": ms_rf, "product_over_copy": ms_rb / ms_rc,
+            "achieved_GBs": (info["layout_bytes"] + 8 * g.n) / (ms_rb * 1e-3) / 1e9,
+            "note": "each launch after a 1 GiB read instead of a 1 GiB write: the caches hold clean lines, so the "
+                    "launch does not pay for writing back the flush's dirty lines"}
+        log("after a read flush: product %.4f ms, copy %.4f ms (flush %.3f ms)" % (ms_rb, ms_rc, ms_rf))
+        del rflush
         del ca, cb
     del flush
     if ms_bv is None:
