@@ -13,6 +13,7 @@ import hashlib
 import json
 import math
 import os
+import statistics
 import sys
 import time
 
@@ -96,6 +97,45 @@ class ReadFlusher:
 
     def __call__(self):
         self.torch.amax(self.buf, dim=1, out=self.out)
+
+
+def pr_median(fn, runs, torch):
+    """One untimed run (graph capture), then the median and minimum of
+    `runs` whole runs, each bracketed by device synchronisations."""
+    fn()
+    ts = []
+    for _ in range(runs):
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        res = fn()
+        torch.cuda.synchronize()
+        ts.append(time.perf_counter() - t)
+    return res, float(statistics.median(ts)), min(ts)
+
+
+def bench_pr_sizes(args, B, P, np, torch, dev):
+    """PageRank (FP32 two-sum, uniform teleport, L1 1e-6) of the workload's
+    recipe at several sizes, compressed and CSR, with the blocks of each
+    layout: where the fold inside the next launch and the finish kernel
+    cross over."""
+    rows = []
+    for n in [int(float(v)) for v in args.pagerank_sizes.split(",") if v]:
+        g = B.workload_graph(args.workload, n)
+        G = P.bvmv_load(B.encode(g).data, keep_lists=1)
+        C = P.bvmv_csr_create(G)
+        p = torch.empty(g.n, dtype=torch.float32, device=dev)
+        ((it, ok, _),), ms, mn = pr_median(lambda: P.bvmv_pagerank(G, p, prec=P.BVMV_F32_COMP), args.pr_runs, torch)
+        (itc, okc, _), msc, mnc = pr_median(lambda: P.bvmv_csr_pagerank(C, p, prec=P.BVMV_F32_COMP), args.pr_runs,
+                                           torch)
+        row = {"n": g.n, "m": g.m, "blocks": P.bvmv_get_info(G)["ntiles"] // 4, "iterations": it,
+               "converged": bool(ok), "ms": 1e3 * ms, "min_ms": 1e3 * mn, "csr_iterations": itc, "csr_ms": 1e3 * msc,
+               "csr_min_ms": 1e3 * mnc}
+        log("n %d: %d blocks, pagerank %.4f ms (%d it), csr %.4f ms (%d it)" % (g.n, row["blocks"], row["ms"], it,
+                                                                                row["csr_ms"], itc))
+        rows.append(row)
+        del G, C
+    print(json.dumps({"mode": "pagerank-sizes", "workload": args.workload, "runs": args.pr_runs,
+                      "fused": os.environ.get("BVMV_PR_FUSED", "auto"), "rows": rows}), flush=True)
 
 
 def time_flushed(fn, steps, warmup, flush, torch):
@@ -653,6 +693,9 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU-baseline leg")
     ap.add_argument("--no-pagerank", action="store_true")
     ap.add_argument("--pr-runs", type=int, default=20, help="timed PageRank runs (the median is reported)")
+    ap.add_argument("--pagerank-sizes", default="", metavar="N1,N2,...",
+                    help="only PageRank (median of --pr-runs whole runs) of --workload's recipe at each size n, "
+                         "compressed and CSR; BVMV_PR_FUSED=0/1 forces the finish-kernel or the fused form")
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
     ap.add_argument("--only", choices=["bv", "csr", "all"], default="all",
                     help="restrict the timed kernels (profiling runs)")
@@ -714,6 +757,8 @@ def main():
     import bvinputs as B
     import paper_1708_07271_amd as P
 
+    if args.pagerank_sizes:
+        return bench_pr_sizes(args, B, P, np, torch, dev)
     if args.batch:
         return bench_batch(args, B, P, np, torch, dev)
     if args.warm_start:
@@ -798,21 +843,10 @@ def main():
     if not args.no_pagerank and args.only == "all":
         p = torch.empty(g.n, dtype=torch.float32, device=dev)
 
-        def pr_runs(fn, runs=args.pr_runs):
-            # one untimed run (graph capture), then the median of `runs` whole
-            # runs, each from the uniform start and bracketed by synchronisations
-            fn()
-            ts = []
-            for _ in range(runs):
-                torch.cuda.synchronize()
-                t = time.perf_counter()
-                res = fn()
-                torch.cuda.synchronize()
-                ts.append(time.perf_counter() - t)
-            return res, float(np.median(ts)), float(min(ts))
-
-        ((it, ok, r),), pr_s, pr_min = pr_runs(lambda: P.bvmv_pagerank(G, p, prec=prec))
-        (it_c, ok_c, r_c), pr_csr_s, pr_csr_min = pr_runs(lambda: P.bvmv_csr_pagerank(C, p, prec=prec))
+        # each run from the uniform start
+        ((it, ok, r),), pr_s, pr_min = pr_median(lambda: P.bvmv_pagerank(G, p, prec=prec), args.pr_runs, torch)
+        (it_c, ok_c, r_c), pr_csr_s, pr_csr_min = pr_median(lambda: P.bvmv_csr_pagerank(C, p, prec=prec),
+                                                            args.pr_runs, torch)
         pr = {"seconds_to_1e-6": pr_s, "iterations": it, "converged": ok, "residual": r,
               "csr_seconds_to_1e-6": pr_csr_s, "csr_iterations": it_c, "speedup_vs_csr": pr_csr_s / pr_s,
               "runs": args.pr_runs, "statistic": "median of whole runs (min %.6f s, csr min %.6f s)" % (

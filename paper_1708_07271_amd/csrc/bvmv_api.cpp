@@ -380,7 +380,21 @@ int32_t fold_polls() {
 // waves of each wait on that member's first block (a 48-graph group ran
 // about 5% slower fused).
 constexpr int64_t kFusedMaxBlocks = 12288;
-bool use_fused(int members, int k, int64_t blocks) { return members == 1 && k == 1 && blocks <= kFusedMaxBlocks; }
+// BVMV_PR_FUSED from the environment: "0" never fuses, "1" fuses every run
+// with one right-hand side (groups and graphs past kFusedMaxBlocks too);
+// unset or anything else follows the rule above.  A knob for measuring and
+// testing both forms; the fold order, and so every result, is the same.
+int fused_mode() {
+  const char* e = std::getenv("BVMV_PR_FUSED");
+  if (e && e[0] == '0' && !e[1]) return 0;
+  if (e && e[0] == '1' && !e[1]) return 1;
+  return -1;
+}
+bool use_fused(int members, int k, int64_t blocks) {
+  const int m = fused_mode();
+  if (k != 1 || m == 0) return false;
+  return m == 1 || (members == 1 && blocks <= kFusedMaxBlocks);
+}
 
 // Arguments of the iteration that reads buffer c % 2 and writes the other;
 // fused: without a finish kernel, states and slots taken by parity (PRArgs).

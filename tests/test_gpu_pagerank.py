@@ -277,6 +277,38 @@ def test_fused_iteration_own_fold(P, monkeypatch):
     p_ref = pagerank.pagerank(g.rowptr, g.col, 0.85, iters=base[1][1][0][0])[0]
     assert _rel(base[1][0], p_ref) < TOL.F32C
 
+def test_fused_and_finish_forms_identical(P, monkeypatch):
+    """The fold inside the next launch (BVMV_PR_FUSED=1, also for a group)
+    and a finish kernel between launches (BVMV_PR_FUSED=0) give the same
+    iterates bit for bit: a single graph in both precisions, a group and the
+    CSR baseline."""
+    g = B.web_graph(40_000, 14.0, 97)
+    G = P.bvmv_load(B.encode(g).data, keep_lists=1)
+    C = P.bvmv_csr_create(G)
+    gs = [B.web_graph(n, 12.0, 310 + i) for i, n in enumerate((5000, 900, 17_000))]
+    grp = P.bvmv_group([P.bvmv_load(B.encode(h).data) for h in gs])
+    offs = P.bvmv_group_offsets(grp)
+
+    def runs():
+        out = [_pr(P, G, g.n, prec) for prec in (P.BVMV_F64, P.BVMV_F32_COMP)]
+        out.append(_pr(P, grp, offs[-1], P.BVMV_F32_COMP))
+        p = torch.empty(g.n, dtype=torch.float32, device=DEV)
+        res = P.bvmv_csr_pagerank(C, p)
+        torch.cuda.synchronize()
+        out.append((p.cpu().numpy().astype(np.float64), res))
+        return out
+
+    forms = {}
+    for mode in ("0", "1"):
+        monkeypatch.setenv("BVMV_PR_FUSED", mode)
+        forms[mode] = runs()
+    monkeypatch.delenv("BVMV_PR_FUSED")
+    for (a, ra), (b, rb) in zip(forms["0"], forms["1"]):
+        assert ra == rb
+        assert np.array_equal(a, b)
+    assert forms["1"][1][1][0][1]
+
+
 def test_group_equals_solo(P):
     sizes = [3000, 800, 12_000, 5000, 200]
     gs = [B.web_graph(n, 10.0 + i, 200 + i) for i, n in enumerate(sizes)]
