@@ -684,7 +684,8 @@ def bench_warm(args, B, P, np, torch, dev):
     print(json.dumps(out), flush=True)
 
 
-def main():
+def build_parser():
+    """The command line of bench.py (the profiles quote commands in it)."""
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=500)
@@ -731,7 +732,11 @@ def main():
     ap.add_argument("--warm-test-n", type=int, default=5_000_000)
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="only run torch copies of MIB MiB (the calibration kernel for HBM byte counters)")
-    args = ap.parse_args()
+    return ap
+
+
+def main():
+    args = build_parser().parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py runs on one GPU only: the compressed product and PageRank here are single-GPU "
               "kernels; independent graphs or right-hand sides would go one set per GPU", file=sys.stderr)
